@@ -1,0 +1,30 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
+
+
+_PH_CACHE = {}
+
+
+def cached_phantom(name, seed=0, **kw):
+    """Phantoms are deterministic per (name, seed, options); build each once per session."""
+    from phantom import make_phantom
+    key = (name, seed, tuple(sorted(kw.items())))
+    if key not in _PH_CACHE:
+        _PH_CACHE[key] = make_phantom(name, seed, **kw)
+    return _PH_CACHE[key]
+
+
+def oracle_problem(ph):
+    import oracle
+    return oracle.make_problem(ph.csr(), ph.rows_per_beam, ph.row_len, ph.vox_struct, ph.prescriptions)

@@ -1,0 +1,164 @@
+"""Pins for the restricted master (gradient projection, Section 2.3).
+
+* Exact line search against brute force: every breakpoint of the piecewise
+  quadratic phi(t) = F(d + t q) is sorted, phi' is evaluated at each, and the
+  root is interpolated inside the piece where phi' changes sign.
+* NNLS special case: with every voxel in one target whose under- and
+  over-dose thresholds and weights coincide, F is a scaled least-squares
+  objective ||D_K y - T||^2, so the converged master must agree with
+  scipy.optimize.nnls on the aperture dose matrix.
+* General master against scipy's L-BFGS-B with bounds y >= 0.
+* Invariants: F never increases from one step to the next, and the KKT
+  conditions hold at exit.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.optimize as so
+import scipy.sparse as sp
+
+import oracle
+from conftest import cached_phantom, oracle_problem
+from oracle.master import MasterState, kkt_residual, solve_master
+
+
+def _phi_prime(P, d, q, t):
+    return math.fsum((q * oracle.grad_objective(P, d + t * q)).tolist())
+
+
+def _brute_line_search(P, d, q, t_max):
+    nz = q != 0
+    bps = []
+    for T, wgt in ((P.t_under, P.a), (P.t_over, P.b)):
+        m = nz & (wgt > 0)
+        bps.append((T - d)[m] / q[m])
+    bps = np.concatenate(bps)
+    cand = np.unique(np.concatenate([[0.0], bps[(bps > 0) & (bps < t_max)]]))
+    ends = list(cand) + ([t_max] if math.isfinite(t_max) else [cand[-1] * 2 + 1.0])
+    for ta, tb in zip(ends[:-1], ends[1:]):
+        ga, gb = _phi_prime(P, d, q, ta), _phi_prime(P, d, q, tb)
+        if gb >= 0:
+            return ta - ga * (tb - ta) / (gb - ga)
+    if not math.isfinite(t_max):
+        # root beyond the last breakpoint: phi' is linear there
+        ta = ends[-1]
+        ga, gb = _phi_prime(P, d, q, ta), _phi_prime(P, d, q, ta + 1.0)
+        return ta - ga / (gb - ga)
+    return t_max
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_line_search_against_breakpoint_sort(seed):
+    ph = cached_phantom("mini")
+    P = oracle_problem(ph)
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0, 0.05, P.n_blt)
+    d = oracle.dose(P, x)
+    u = oracle.grad_objective(P, d)
+    # a descent direction in beamlet space
+    dx = -oracle.prices(P, u) * rng.uniform(0.5, 1.5, P.n_blt)
+    q = oracle.dose(P, dx)
+    assert _phi_prime(P, d, q, 0.0) < 0
+    t_max = math.inf if seed % 2 == 0 else float(rng.uniform(0.1, 2.0)) * 1e-3
+    t, evals = oracle.line_search(P, d, q, t_max)
+    ref = _brute_line_search(P, d, q, t_max)
+    assert abs(t - ref) <= 1e-9 * max(abs(ref), 1e-300), (t, ref, evals)
+    assert evals <= 20
+
+
+def test_line_search_blocking_step():
+    ph = cached_phantom("mini")
+    P = oracle_problem(ph)
+    rng = np.random.default_rng(11)
+    d = oracle.dose(P, rng.uniform(0, 0.02, P.n_blt))
+    q = oracle.dose(P, -oracle.prices(P, oracle.grad_objective(P, d)))
+    t_free, _ = oracle.line_search(P, d, q, math.inf)
+    t, _ = oracle.line_search(P, d, q, 0.5 * t_free)
+    assert t == 0.5 * t_free
+
+
+def _single_target_problem(ph):
+    """Every voxel that any beamlet reaches is one target, T- = T+ = 0.3, alpha = beta."""
+    reached = np.diff(ph.row_ptr) > 0
+    vs = np.where(reached, 0, -1).astype(np.int16)
+    pres = [dict(is_target=1, t_under=0.3, t_over=0.3, w_under=2.0, w_over=2.0)]
+    return oracle.make_problem(ph.csr(), ph.rows_per_beam, ph.row_len, vs, pres), reached
+
+
+def _pool(P, k, seed):
+    rng = np.random.default_rng(seed)
+    pool = []
+    for _ in range(k):
+        b = int(rng.integers(P.rows_per_beam.shape[0]))
+        r0, r1 = P.beam_row_range(b)
+        leaves = []
+        for r in range(r0, r1):
+            n = int(P.row_len[r])
+            L = int(rng.integers(0, n))
+            R = int(rng.integers(L + 1, n + 1))
+            leaves.append((L, R))
+        pool.append(oracle.Aperture(b, tuple(leaves)))
+    return pool
+
+
+def _dk(P, pool):
+    cols = []
+    for ap in pool:
+        x = np.zeros(P.n_blt)
+        x[ap.open_beamlets(P)] = 1.0
+        cols.append(oracle.dose(P, x))
+    return np.stack(cols, axis=1)
+
+
+def test_master_matches_nnls_special_case():
+    ph = cached_phantom("mini")
+    P, reached = _single_target_problem(ph)
+    pool = _pool(P, 5, 0)
+    st = MasterState.empty(P)
+    for ap in pool:
+        st.add(ap)
+    log = solve_master(P, st, tol=1e-13, max_steps=20000)
+    assert log["kkt"] <= 1e-13
+    DK = _dk(P, pool)[reached]
+    y_ref, _ = so.nnls(DK, np.full(DK.shape[0], 0.3), maxiter=10000)
+    F_ref = 2.0 / reached.sum() * float(np.sum((DK @ y_ref - 0.3) ** 2))
+    F = oracle.objective(P, st.d)
+    assert abs(F - F_ref) <= 1e-9 * F_ref
+    np.testing.assert_allclose(st.y, y_ref, rtol=1e-5, atol=1e-7)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_master_matches_lbfgsb(seed):
+    ph = cached_phantom("mini")
+    P = oracle_problem(ph)
+    pool = _pool(P, 6, seed)
+    st = MasterState.empty(P)
+    for ap in pool:
+        st.add(ap)
+    log = solve_master(P, st, tol=1e-12, max_steps=50000, track_F=True)
+    assert log["kkt"] <= 1e-12
+    DK = sp.csr_matrix(_dk(P, pool))
+
+    def fg(y):
+        z = DK @ y
+        return oracle.objective(P, z), DK.T @ oracle.grad_objective(P, z)
+
+    r = so.minimize(fg, np.full(len(pool), 0.01), jac=True, method="L-BFGS-B",
+                    bounds=[(0, None)] * len(pool),
+                    options=dict(ftol=1e-16, gtol=1e-14, maxiter=20000, maxcor=30))
+    F = oracle.objective(P, st.d)
+    assert F <= r.fun * (1 + 1e-9)
+    assert abs(F - r.fun) <= 1e-9 * r.fun
+    pi = oracle.grad_objective(P, st.d)
+    pi_ref = oracle.grad_objective(P, DK @ r.x)
+    assert np.max(np.abs(pi - pi_ref)) <= 1e-6 * np.max(np.abs(pi_ref))
+    # F never increases along the iteration
+    Fs = np.array(log["F_trace"])
+    assert np.all(np.diff(Fs) <= 1e-15 * Fs[0])
+    # KKT at exit
+    grad = oracle.aperture_gradient(P, pool, st.g)
+    assert np.all(st.y >= 0)
+    assert np.all(np.abs(grad[st.y > 0]) <= 1e-12)
+    assert np.all(grad[st.y == 0] >= -1e-12)
+    assert kkt_residual(st.y, grad) == log["kkt"]
