@@ -162,3 +162,43 @@ def test_master_matches_lbfgsb(seed):
     assert np.all(np.abs(grad[st.y > 0]) <= 1e-12)
     assert np.all(grad[st.y == 0] >= -1e-12)
     assert kkt_residual(st.y, grad) == log["kkt"]
+
+
+def test_line_search_pure_quadratic_clamps_to_t_max():
+    # every reached voxel in one target with T- = T+: phi is one quadratic with
+    # no breakpoints, so the line search must stop at t_max when t_max is short
+    ph = cached_phantom("mini")
+    P, reached = _single_target_problem(ph)
+    rng = np.random.default_rng(5)
+    d = oracle.dose(P, rng.uniform(0, 0.01, P.n_blt))
+    q = oracle.dose(P, -oracle.prices(P, oracle.grad_objective(P, d)))
+    t_free, ev = oracle.line_search(P, d, q, math.inf)
+    # exact minimiser of the quadratic: -phi'(0) / phi''
+    g0 = _phi_prime(P, d, q, 0.0)
+    curv = 2.0 * float(np.sum(q * q * P.a))      # one side active at a time, a = b
+    assert abs(t_free - (-g0 / curv)) <= 1e-12 * t_free
+    t, _ = oracle.line_search(P, d, q, 0.3 * t_free)
+    assert t == 0.3 * t_free
+
+
+def test_blocking_apertures_land_exactly_on_zero():
+    from oracle.master import master_step
+    ph = cached_phantom("mini")
+    P = oracle_problem(ph)
+    blocked = 0
+    for seed in range(6):
+        st = MasterState.empty(P)
+        for ap in _pool(P, 6, 100 + seed):
+            st.add(ap)
+        st.y = np.random.default_rng(seed).uniform(0.0, 0.05, 6)
+        st.refresh(P)
+        for _ in range(40):
+            y_before = st.y.copy()
+            rec = master_step(P, st)
+            if rec is None:
+                break
+            if rec["t"] == rec["t_max"]:
+                was_pos = y_before > 0
+                assert np.any(st.y[was_pos] == 0.0)
+                blocked += 1
+    assert blocked >= 3

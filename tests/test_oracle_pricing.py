@@ -158,3 +158,17 @@ def test_first_round_closed_form():
             assert (L, R) == (0, int(neg.max()) + 1)
     n_ptv = int(ptv.sum())
     assert abs(res["rc"] - (-2.0 / n_ptv) * max(totals)) <= 1e-12 * abs(res["rc"])
+
+
+def test_beam_tie_goes_to_lowest_index():
+    # both beams see the same prices: equal values, beam 0 wins, gap 0
+    P, g = _tiny_problem(3, 4, 5, False)
+    half = g.shape[0] // 2
+    g[half:] = g[:half]
+    res = oracle.price(P, g)
+    assert res["beam_values"][0] == res["beam_values"][1]
+    assert res["aperture"].beam == 0 and res["gap"] == 0.0
+    # make beam 1 strictly better by one unit on an open beamlet of its best row
+    g2 = g.copy()
+    g2[half + int(np.argmin(g[:half]))] -= 1.0
+    assert oracle.price(P, g2)["aperture"].beam == 1
