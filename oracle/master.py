@@ -142,6 +142,27 @@ def kkt_residual(y: np.ndarray, grad: np.ndarray) -> float:
     return float(np.max(np.abs(np.minimum(y, grad))))
 
 
+def _ratios(y: np.ndarray, p: np.ndarray) -> np.ndarray:
+    r = np.full(p.shape, math.inf)
+    neg = p < 0.0
+    r[neg] = y[neg] / (-p[neg])
+    return r
+
+
+def max_step(y: np.ndarray, p: np.ndarray) -> float:
+    """Longest step keeping y + t p >= 0: min over p_k < 0 of y_k / (-p_k)."""
+    return float(_ratios(y, p).min()) if p.size else math.inf
+
+
+def take_step(y: np.ndarray, p: np.ndarray, t: float) -> np.ndarray:
+    """y + t p, with the apertures that block at t = t_max set to exactly 0."""
+    r = _ratios(y, p)
+    out = y + t * p
+    if p.size and t == float(r.min()):
+        out[r == t] = 0.0
+    return np.maximum(out, 0.0)
+
+
 def master_step(P: Problem, st: MasterState) -> Optional[dict]:
     """One gradient-projection iteration in place.  Returns its record, or
     None when the projected direction is zero (an exact KKT point)."""
@@ -150,16 +171,10 @@ def master_step(P: Problem, st: MasterState) -> Optional[dict]:
     p[(st.y == 0.0) & (grad >= 0.0)] = 0.0
     if not np.any(p != 0.0):
         return None
-    neg = p < 0.0
-    ratios = np.full(p.shape, math.inf)
-    ratios[neg] = st.y[neg] / (-p[neg])
-    t_max = float(ratios.min())
+    t_max = max_step(st.y, p)
     q = dose(P, beamlet_intensity(P, st.pool, p))
     t, evals = line_search(P, st.d, q, t_max)
-    y = st.y + t * p
-    if t == t_max:
-        y[neg & (ratios == t_max)] = 0.0
-    st.y = np.maximum(y, 0.0)
+    st.y = take_step(st.y, p, t)
     st.d = st.d + t * q
     st.u = grad_objective(P, st.d)
     st.g = prices(P, st.u)

@@ -202,3 +202,39 @@ def test_blocking_apertures_land_exactly_on_zero():
                 assert np.any(st.y[was_pos] == 0.0)
                 blocked += 1
     assert blocked >= 3
+
+
+def test_take_step_blocking_exactly_zero():
+    from oracle.master import max_step, take_step
+    rng = np.random.default_rng(3)
+    residual_nonzero = 0
+    for _ in range(2000):
+        y = rng.uniform(0.0, 1.0, 4)
+        p = rng.normal(size=4)
+        if not np.any(p < 0):
+            continue
+        t = max_step(y, p)
+        k = int(np.argmin(np.where(p < 0, y / np.where(p < 0, -p, 1.0), np.inf)))
+        if y[k] + t * p[k] != 0.0:
+            residual_nonzero += 1          # plain arithmetic would miss zero here
+        out = take_step(y, p, t)
+        assert out[k] == 0.0 and np.all(out >= 0.0)
+        # a shorter step blocks nothing
+        assert np.all(take_step(y, p, 0.5 * t) > 0.0)
+    assert residual_nonzero > 0
+
+
+def test_line_search_returns_t_max_inside_first_piece():
+    # under-dose only, threshold far above any reachable dose: the first
+    # breakpoint lies far beyond the Newton point, which lies beyond t_max
+    ph = cached_phantom("mini")
+    reached = np.diff(ph.row_ptr) > 0
+    vs = np.where(reached, 0, -1).astype(np.int16)
+    pres = [dict(is_target=1, t_under=50.0, t_over=1e9, w_under=1.0, w_over=0.0)]
+    P = oracle.make_problem(ph.csr(), ph.rows_per_beam, ph.row_len, vs, pres)
+    d = np.zeros(P.n_vox)
+    q = oracle.dose(P, np.ones(P.n_blt))
+    t_free, ev = oracle.line_search(P, d, q, math.inf)
+    assert ev == 1
+    t, ev = oracle.line_search(P, d, q, 0.25 * t_free)
+    assert t == 0.25 * t_free and ev == 1
