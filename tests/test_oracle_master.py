@@ -225,16 +225,17 @@ def test_take_step_blocking_exactly_zero():
 
 
 def test_line_search_returns_t_max_inside_first_piece():
-    # under-dose only, threshold far above any reachable dose: the first
-    # breakpoint lies far beyond the Newton point, which lies beyond t_max
+    # under-dose only (T- = 50) and a uniform direction: phi is one quadratic
+    # up to t = 50, where every voxel reaches its threshold at once, so the
+    # first Newton point is the exact minimiser; a shorter t_max must win
     ph = cached_phantom("mini")
     reached = np.diff(ph.row_ptr) > 0
     vs = np.where(reached, 0, -1).astype(np.int16)
     pres = [dict(is_target=1, t_under=50.0, t_over=1e9, w_under=1.0, w_over=0.0)]
     P = oracle.make_problem(ph.csr(), ph.rows_per_beam, ph.row_len, vs, pres)
     d = np.zeros(P.n_vox)
-    q = oracle.dose(P, np.ones(P.n_blt))
+    q = reached.astype(float)
     t_free, ev = oracle.line_search(P, d, q, math.inf)
-    assert ev == 1
-    t, ev = oracle.line_search(P, d, q, 0.25 * t_free)
-    assert t == 0.25 * t_free and ev == 1
+    assert ev == 1 and abs(t_free - 50.0) < 1e-12
+    t, ev = oracle.line_search(P, d, q, 12.5)
+    assert t == 12.5 and ev == 1
