@@ -231,8 +231,11 @@ def test_line_search_returns_t_max_inside_first_piece():
     ph = cached_phantom("mini")
     reached = np.diff(ph.row_ptr) > 0
     vs = np.where(reached, 0, -1).astype(np.int16)
-    pres = [dict(is_target=1, t_under=50.0, t_over=1e9, w_under=1.0, w_over=0.0)]
+    # alpha = |v| makes every per-voxel weight exactly 1, so all sums are exact
+    pres = [dict(is_target=1, t_under=50.0, t_over=1e9, w_under=float(reached.sum()),
+                 w_over=0.0)]
     P = oracle.make_problem(ph.csr(), ph.rows_per_beam, ph.row_len, vs, pres)
+    assert np.all(P.a[reached] == 1.0)
     d = np.zeros(P.n_vox)
     q = reached.astype(float)
     t_free, ev = oracle.line_search(P, d, q, math.inf)
