@@ -1,0 +1,181 @@
+"""Benchmark: time-to-50-aperture plan on the prostate-shaped phantom (1 GPU).
+
+One "step" is one whole plan: dao_solve from an empty pool to 50 apertures
+(pricing, master, column generation) with the dose matrix resident on the
+device.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--config prostate] [--cpu-seconds S]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-50-aperture plan (s), plans/s + p50/p99; D·x, Dᵀg HBM GB/s vs peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(ph, gpu_steps_per_plan, rounds_per_plan, seconds):
+    """Time the FP64 oracle on the host on a bounded sample of the same plan.
+
+    Sample: the oracle's own column generation on the same phantom, run
+    round by round until `seconds` of CPU time are spent.  Its mean time per
+    master step and per pricing round are scaled to one whole plan with the
+    master step count the plan takes (the GPU runs the same algorithm).
+    """
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    from oracle.master import MasterState, solve_master
+
+    with threadpool_limits(limits=1):
+        P = oracle.make_problem(ph.csr(), ph.rows_per_beam, ph.row_len, ph.vox_struct, ph.prescriptions)
+        st = MasterState.empty(P)
+        t_price = t_master = 0.0
+        steps = rounds = 0
+        rc1 = None
+        t_all = time.perf_counter()
+        while time.perf_counter() - t_all < seconds and rounds < ph.n_apertures:
+            t0 = time.perf_counter()
+            pr = oracle.price(P, st.g)
+            t_price += time.perf_counter() - t0
+            rc1 = rc1 if rc1 is not None else pr["rc"]
+            st.add(pr["aperture"])
+            t0 = time.perf_counter()
+            budget = max(1, int(500))
+            m = solve_master(P, st, tol=1e-6 * abs(rc1), max_steps=budget)
+            t_master += time.perf_counter() - t0
+            steps += m["steps"]
+            rounds += 1
+            if m["steps"] and (time.perf_counter() - t_all) > seconds:
+                break
+    s_step = t_master / max(1, steps)
+    s_round = t_price / max(1, rounds)
+    plan_s = s_step * gpu_steps_per_plan + s_round * rounds_per_plan
+    return dict(value=1.0 / plan_s, unit="plans/s", cores=1, kind="oracle",
+                sample=(f"FP64 oracle column generation on the same phantom for {rounds} rounds "
+                        f"({steps} master steps, {t_master + t_price:.1f} s); {s_step * 1e3:.1f} ms per "
+                        f"master step and {s_round * 1e3:.1f} ms per pricing round scaled to the "
+                        f"{gpu_steps_per_plan} master steps and {rounds_per_plan} rounds of one plan"),
+                plan_seconds=plan_s)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="prostate")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--product-iters", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the plan is a single-GPU workload "
+              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1003_5402_amd as dao
+    from phantom import make_phantom
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a HIP device")
+    log(f"[bench] phantom {args.config} seed {args.seed}")
+    ph = make_phantom(args.config, args.seed)
+    stream = torch.cuda.current_stream().cuda_stream
+    t0 = time.perf_counter()
+    ctx = dao.DaoContext.from_phantom(ph, stream=stream)
+    create_s = time.perf_counter() - t0
+    info = ctx.info()
+    n_ap = ph.n_apertures
+    log(f"[bench] ctx ready in {create_s:.2f} s: {info}")
+
+    for w in range(args.warmup):
+        out = ctx.solve(n_ap)
+        log(f"[bench] warmup {w}: rounds {out['rounds']} steps {out['total_steps']} F {out['F']:.6e}")
+    torch.cuda.synchronize()
+    lat = []
+    outs = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        t0 = time.perf_counter()
+        out = ctx.solve(n_ap)
+        lat.append(time.perf_counter() - t0)
+        outs.append(out)
+        log(f"[bench] plan {k}: {lat[-1]:.4f} s rounds {out['rounds']} steps {out['total_steps']} "
+            f"ls {out['total_ls_evals']} F {out['F']:.8e}")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    lat = np.array(lat)
+
+    # product kernels, timed with HIP events on the context stream
+    us_dose = ctx.time_product(0, args.product_iters)
+    us_grad = ctx.time_product(1, args.product_iters)
+    gbs_dose = info["bytes_dose"] / (us_dose * 1e-6) / 1e9
+    gbs_grad = info["bytes_gradient"] / (us_grad * 1e-6) / 1e9
+    log(f"[bench] D x: {us_dose:.2f} us {gbs_dose:.0f} GB/s; D^T u: {us_grad:.2f} us {gbs_grad:.0f} GB/s")
+    if us_grad >= us_dose:
+        dom, us, byts, gbs = "transposed product g = D^T u (k_gradT)", us_grad, info["bytes_gradient"], gbs_grad
+    else:
+        dom, us, byts, gbs = "forward product d = D x (k_dose)", us_dose, info["bytes_dose"], gbs_dose
+
+    steps_per_plan = int(outs[-1]["total_steps"])
+    result = {
+        "metric": METRIC,
+        "value": args.steps / total,
+        "unit": "plans/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"prostate-shaped phantom {ph.shape[0]}x{ph.shape[1]}x{ph.shape[2]} voxels at 2.5 mm, "
+                         f"{ph.n_beams} beams, {ph.n_blt} beamlets, nnz {ph.nnz}, {n_ap}-aperture plan, "
+                         f"FP32 dose matrix"),
+            "phantom": args.config, "seed": args.seed, "apertures": n_ap,
+            "n_vox_nonempty": info["n_vox_nonempty"], "nnz": info["nnz"], "n_blt": info["n_blt"],
+        },
+        "plan_s_p50": float(np.percentile(lat, 50)),
+        "plan_s_p99": float(np.percentile(lat, 99)),
+        "plan_s_mean": float(lat.mean()),
+        "master_steps_per_plan": steps_per_plan,
+        "ls_evals_per_plan": int(outs[-1]["total_ls_evals"]),
+        "final_F": outs[-1]["F"],
+        "create_s": create_s,
+        "products": {
+            "dose_us": us_dose, "dose_bytes": info["bytes_dose"], "dose_GBs": gbs_dose,
+            "gradient_us": us_grad, "gradient_bytes": info["bytes_gradient"], "gradient_GBs": gbs_grad,
+            "note": "warm: the dose matrix fits in the 256 MB last-level cache",
+        },
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": byts,
+                     "us_per_launch": us},
+    }
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(ph, steps_per_plan, int(outs[-1]["rounds"]), args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

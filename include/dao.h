@@ -1,0 +1,225 @@
+/*
+ * dao.h -- C ABI of the MI355X (gfx950) column-generation direct aperture
+ * optimisation library.
+ *
+ * Model (Men, Jia & Jiang, "GPU-based ultra-fast direct aperture
+ * optimization for online adaptive radiation therapy"):
+ *   - Section 2.1, eq. 1 and eq. 2: voxel dose z_j = sum_k D_kj y_k with the
+ *     aperture coefficients D_kj = sum_{i in A_k} D_ij; eq. 7: beamlet
+ *     intensity x_i = sum_{k in K_i} y_k, so z = D x.
+ *   - Discussion, eq. 9 and eq. 10: per-structure one-sided quadratic
+ *     penalties (under-dose on targets, over-dose on every structure), each
+ *     weight divided by the structure's voxel count.
+ *   - eq. 6: min F(z) over y >= 0 with z defined by eq. 1.
+ *   - Section 2.2 and Section 2.3: column generation; the master is solved by
+ *     gradient projection, the pricing sub-problem (eq. 8) by a per-row
+ *     minimum-sum leaf interval and a per-beam argmin.
+ *
+ * Conventions shared by every call
+ *   - Voxels are numbered 0..n_vox-1 in the caller's order; beamlets
+ *     0..n_blt-1 beam by beam, then MLC row by row, then position within the
+ *     row (each row is a contiguous run of beamlet numbers).
+ *   - Leaf positions are row-local, 0-based, half-open [L, R); a closed row
+ *     is (0, 0).  An aperture is one beam plus one (L, R) pair per row of that
+ *     beam.
+ *   - "ctx type" is the storage/arithmetic type chosen at create time:
+ *     DAO_F64 -> double, DAO_F32 -> float.  Device vectors passed to
+ *     dao_dose / dao_gradient use the ctx type.  Objective values, reduced
+ *     costs, gaps, intensities y and the master's dose are always double.
+ *   - Device pointers are plain HIP device addresses (for example a torch
+ *     tensor's data_ptr()).  All device work is enqueued on the stream given
+ *     to dao_create; calls that return host values synchronise that stream.
+ *   - A context is not thread-safe; use one per plan and per host thread.
+ *   - Every call returns a dao_status.  On failure the context keeps a
+ *     message readable with dao_last_error(); dao_create failures are
+ *     described by dao_create_error() (thread-local).
+ */
+#ifndef DAO_H
+#define DAO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dao_ctx dao_ctx;
+
+typedef enum {
+    DAO_OK = 0,
+    DAO_EOPTIMAL = 1,   /* dao_solve stopped: no aperture prices below -tau */
+    DAO_ESTALLED = 2,   /* dao_solve stopped: pricing kept returning a pool member */
+    DAO_EINVAL = -1,    /* malformed argument; nothing was changed */
+    DAO_ENOMEM = -2,    /* device allocation failed or exceeded mem_cap_bytes */
+    DAO_EDEVICE = -3,   /* a HIP call failed */
+    DAO_ESTATE = -4     /* call not valid in the context's current state */
+} dao_status;
+
+typedef enum { DAO_F64 = 0, DAO_F32 = 1 } dao_dtype;
+
+/* Beamlet dose matrix D (eq. 2's D_ij): voxel-row CSR on the host.
+ * row_ptr[n_vox + 1] non-decreasing from 0 to nnz; col[nnz] strictly
+ * increasing inside each row, each in [0, n_blt); val[nnz] finite and >= 0.
+ * Limits: n_blt <= 65535 (columns are stored as 16-bit indices on the
+ * device), nnz < 2^31.  Values are rounded to the ctx type on upload. */
+typedef struct {
+    int64_t n_vox, n_blt, nnz;
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const double* val;
+} dao_matrix;
+
+/* Beam and MLC geometry (Section 2.3: rows of n beamlets per beam).
+ * rows_per_beam[n_beams] >= 1 each; row_len[sum rows_per_beam] in [1, 64];
+ * sum(row_len) must equal n_blt. */
+typedef struct {
+    int32_t n_beams;
+    const int32_t* rows_per_beam;
+    const int32_t* row_len;
+} dao_beams;
+
+/* Structure label of every voxel (eq. 9 and eq. 10's v_s): vox_struct[n_vox]
+ * in [-1, n_struct), -1 = in no structure.  n_struct <= 255. */
+typedef struct {
+    int32_t n_struct;
+    const int16_t* vox_struct;
+} dao_structures;
+
+/* One prescription per structure (eq. 9 and eq. 10): targets (is_target != 0)
+ * are penalised below t_under with weight w_under and above t_over with
+ * weight w_over; other structures only above t_over.  Weights are divided by
+ * the structure's voxel count on the device.  Requires finite values,
+ * w_under, w_over >= 0, and t_under <= t_over for targets. */
+typedef struct {
+    int32_t is_target;
+    double t_under, t_over, w_under, w_over;
+} dao_prescription;
+
+/* Options; fill with dao_default_options() and change what you need. */
+typedef struct {
+    int32_t dtype;          /* DAO_F64 or DAO_F32 (default DAO_F32) */
+    int32_t max_apertures;  /* pool capacity, 1..256 (default 64) */
+    double eps;             /* master stops at KKT residual <= eps * |rc_1| (1e-6) */
+    int32_t max_steps;      /* master steps per round (500) */
+    double tau_rel;         /* aperture enters iff rc < -tau_rel * |rc_1| (1e-10) */
+    int32_t max_tighten;    /* eps tightenings on a duplicate aperture (3) */
+    int32_t refresh_every;  /* recompute d = D(A y) every this many steps (50) */
+    int32_t ls_slots;       /* line-search launches per master cycle (2) */
+    int64_t mem_cap_bytes;  /* fail dao_create with DAO_ENOMEM above this device footprint; 0 = none */
+} dao_options;
+
+void dao_default_options(dao_options* opt);
+
+/* Validate the inputs, build the device layouts and upload them (one copy;
+ * the caller keeps ownership of every host array).  `stream` is a
+ * hipStream_t (NULL = default stream) on the current HIP device.  On
+ * success *out owns all device memory until dao_destroy.  Returns DAO_EINVAL
+ * for any malformed input before touching the device. */
+dao_status dao_create(const dao_matrix* D, const dao_beams* beams,
+                      const dao_structures* structs, const dao_prescription* presc,
+                      const dao_options* opt, void* stream, dao_ctx** out);
+void dao_destroy(dao_ctx* ctx);
+const char* dao_last_error(const dao_ctx* ctx);
+const char* dao_create_error(void);
+
+/* Sizes and device footprint. */
+typedef struct {
+    int64_t n_vox, n_vox_nonempty, n_blt, nnz, n_rows;
+    int32_t n_beams, max_rows_per_beam, dtype, n_slices;
+    int64_t sell_entries;     /* stored forward-layout entries incl. padding */
+    int64_t device_bytes;     /* device memory held by the context */
+    int64_t bytes_dose;       /* algorithmic HBM bytes of one forward product */
+    int64_t bytes_gradient;   /* algorithmic HBM bytes of one transposed product */
+} dao_info_t;
+dao_status dao_info(const dao_ctx* ctx, dao_info_t* out);
+
+/* d = D x (eq. 1 and eq. 2 with x from eq. 7).  x_dev: n_blt values, d_dev:
+ * n_vox values, both ctx type, caller-order, device.  Every d entry is
+ * written (voxels no beamlet reaches get 0). */
+dao_status dao_dose(dao_ctx* ctx, const void* x_dev, void* d_dev);
+
+/* g = D^T grad F(d) (eq. 8's w_i with pi = grad F) and F(d) over all voxels
+ * (eq. 9 and eq. 10).  d_dev: n_vox ctx-type values; g_dev: n_blt ctx-type
+ * values; *F receives the objective (double). */
+dao_status dao_gradient(dao_ctx* ctx, const void* d_dev, void* g_dev, double* F);
+
+/* Pricing sub-problem (eq. 8, Section 2.3) on prices g (n_blt doubles on the
+ * device): per row the minimum-sum leaf interval (ties: smallest right end,
+ * then smallest left end; a row with no negative interval stays closed),
+ * per-beam sums, argmin over beams (ties: lowest beam).  Outputs the beam,
+ * leaves[2 * rows of that beam] as (L, R) pairs, the reduced cost *rc (the
+ * beam value) and the decision gap *gap (distance to the runner-up beam or
+ * to the runner-up interval of any chosen row, whichever is smaller). */
+dao_status dao_price(dao_ctx* ctx, const double* g_dev, int32_t* beam, int16_t* leaves,
+                     double* rc, double* gap);
+
+/* Master state.  dao_reset empties the pool (y = 0, dose 0).
+ * dao_add_aperture appends an aperture with y = 0 (leaves as in dao_price;
+ * DAO_EINVAL for a malformed aperture, DAO_ESTATE when the pool is full). */
+dao_status dao_reset(dao_ctx* ctx);
+dao_status dao_add_aperture(dao_ctx* ctx, int32_t beam, const int16_t* leaves);
+
+/* One gradient-projection iteration of the restricted master (Section 2.3)
+ * over the current pool: gradient over the pool, projected direction,
+ * longest feasible step, exact line search, update.  Returns the objective
+ * after the step (*F), the KKT residual max_k |min(y_k, dF/dy_k)| after the
+ * step (*kkt) and the step length (*step, 0 if already at a KKT point). */
+dao_status dao_master_step(dao_ctx* ctx, double* F, double* kkt, double* step);
+
+/* Gradient projection until KKT residual <= tol or max_steps steps. */
+dao_status dao_master_solve(dao_ctx* ctx, double tol, int32_t max_steps,
+                            int32_t* steps, double* kkt, double* F);
+
+/* Prices at the current master point in FP64 and returns the entering
+ * aperture (same outputs as dao_price). */
+dao_status dao_price_current(dao_ctx* ctx, int32_t* beam, int16_t* leaves,
+                             double* rc, double* gap);
+
+/* Copy the pool (entry order) and intensities to the host.  beams[cap],
+ * leaves[cap * 2 * max_rows_per_beam] (row-major per aperture, unused rows
+ * left as is), y[cap]; *n receives the pool size.  Any pointer may be NULL. */
+dao_status dao_get_pool(dao_ctx* ctx, int32_t cap, int32_t* n, int32_t* beams,
+                        int16_t* leaves, double* y);
+
+/* Master dose (double, caller voxel order, n_vox values) into a device
+ * buffer, and the objective at it. */
+dao_status dao_get_dose(dao_ctx* ctx, double* d_dev, double* F);
+
+/* Mean device time, in microseconds, of `iters` back-to-back launches of one
+ * product kernel on the context stream, measured with HIP events: kernel 0
+ * is the forward product d = D x (Section 2.1, eq. 1, eq. 2, eq. 7; the
+ * kernel behind dao_dose), kernel 1 the transposed product g = D^T u (the
+ * w_i of eq. 8; the kernel behind dao_gradient).  Inputs are the master's
+ * current vectors, outputs go to context scratch memory.  For measurement
+ * only; the master state is left unchanged. */
+dao_status dao_time_product(dao_ctx* ctx, int32_t kernel, int32_t iters, double* us_per_launch);
+
+/* Per-round log and outcome of dao_solve.  The arrays are caller-owned with
+ * room for n_apertures entries each; any may be NULL. */
+typedef struct {
+    int32_t rounds;           /* apertures added */
+    int32_t stop;             /* DAO_OK (budget reached), DAO_EOPTIMAL or DAO_ESTALLED */
+    double F;                 /* final objective */
+    double rc1;               /* reduced cost of round 1 */
+    int64_t total_steps;      /* master steps over all rounds */
+    int64_t total_ls_evals;   /* line-search evaluations over all rounds */
+    int32_t* round_beam;
+    double* round_rc;
+    double* round_gap;
+    int32_t* round_steps;
+    double* round_kkt;
+    double* round_F;
+} dao_plan;
+
+/* Column generation (Section 2.2, Section 2.3) from an empty pool: round 1
+ * prices at zero dose; each round prices in FP64, stops when rc >= -tau
+ * (DAO_EOPTIMAL), tightens the master tolerance and re-solves when pricing
+ * returns a pool member (at most max_tighten times, then DAO_ESTALLED),
+ * otherwise adds the aperture and solves the master to
+ * eps * |rc_1| or max_steps.  Stops after n_apertures apertures. */
+dao_status dao_solve(dao_ctx* ctx, int32_t n_apertures, dao_plan* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DAO_H */

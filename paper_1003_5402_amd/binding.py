@@ -1,0 +1,281 @@
+"""ctypes declarations of include/dao.h and a small context wrapper."""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int16, c_int32, c_int64, c_void_p
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdao.so")
+
+DAO_OK, DAO_EOPTIMAL, DAO_ESTALLED = 0, 1, 2
+DAO_EINVAL, DAO_ENOMEM, DAO_EDEVICE, DAO_ESTATE = -1, -2, -3, -4
+DAO_F64, DAO_F32 = 0, 1
+_NAMES = {0: "DAO_OK", 1: "DAO_EOPTIMAL", 2: "DAO_ESTALLED", -1: "DAO_EINVAL", -2: "DAO_ENOMEM",
+          -3: "DAO_EDEVICE", -4: "DAO_ESTATE"}
+
+
+class DaoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class dao_matrix(ctypes.Structure):
+    _fields_ = [("n_vox", c_int64), ("n_blt", c_int64), ("nnz", c_int64),
+                ("row_ptr", POINTER(c_int64)), ("col", POINTER(c_int32)), ("val", POINTER(c_double))]
+
+
+class dao_beams(ctypes.Structure):
+    _fields_ = [("n_beams", c_int32), ("rows_per_beam", POINTER(c_int32)), ("row_len", POINTER(c_int32))]
+
+
+class dao_structures(ctypes.Structure):
+    _fields_ = [("n_struct", c_int32), ("vox_struct", POINTER(c_int16))]
+
+
+class dao_prescription(ctypes.Structure):
+    _fields_ = [("is_target", c_int32), ("t_under", c_double), ("t_over", c_double),
+                ("w_under", c_double), ("w_over", c_double)]
+
+
+class dao_options(ctypes.Structure):
+    _fields_ = [("dtype", c_int32), ("max_apertures", c_int32), ("eps", c_double),
+                ("max_steps", c_int32), ("tau_rel", c_double), ("max_tighten", c_int32),
+                ("refresh_every", c_int32), ("ls_slots", c_int32), ("mem_cap_bytes", c_int64)]
+
+
+class dao_info_t(ctypes.Structure):
+    _fields_ = [("n_vox", c_int64), ("n_vox_nonempty", c_int64), ("n_blt", c_int64), ("nnz", c_int64),
+                ("n_rows", c_int64), ("n_beams", c_int32), ("max_rows_per_beam", c_int32),
+                ("dtype", c_int32), ("n_slices", c_int32), ("sell_entries", c_int64),
+                ("device_bytes", c_int64), ("bytes_dose", c_int64), ("bytes_gradient", c_int64)]
+
+
+class dao_plan(ctypes.Structure):
+    _fields_ = [("rounds", c_int32), ("stop", c_int32), ("F", c_double), ("rc1", c_double),
+                ("total_steps", c_int64), ("total_ls_evals", c_int64),
+                ("round_beam", POINTER(c_int32)), ("round_rc", POINTER(c_double)),
+                ("round_gap", POINTER(c_double)), ("round_steps", POINTER(c_int32)),
+                ("round_kkt", POINTER(c_double)), ("round_F", POINTER(c_double))]
+
+
+# name -> (restype, argtypes); every symbol include/dao.h declares
+_SIGS = {
+    "dao_default_options": (None, [POINTER(dao_options)]),
+    "dao_create": (c_int32, [POINTER(dao_matrix), POINTER(dao_beams), POINTER(dao_structures),
+                             POINTER(dao_prescription), POINTER(dao_options), c_void_p, POINTER(c_void_p)]),
+    "dao_destroy": (None, [c_void_p]),
+    "dao_last_error": (c_char_p, [c_void_p]),
+    "dao_create_error": (c_char_p, []),
+    "dao_info": (c_int32, [c_void_p, POINTER(dao_info_t)]),
+    "dao_dose": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "dao_gradient": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(c_double)]),
+    "dao_price": (c_int32, [c_void_p, c_void_p, POINTER(c_int32), POINTER(c_int16),
+                            POINTER(c_double), POINTER(c_double)]),
+    "dao_reset": (c_int32, [c_void_p]),
+    "dao_add_aperture": (c_int32, [c_void_p, c_int32, POINTER(c_int16)]),
+    "dao_master_step": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
+    "dao_master_solve": (c_int32, [c_void_p, c_double, c_int32, POINTER(c_int32), POINTER(c_double),
+                                   POINTER(c_double)]),
+    "dao_price_current": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int16), POINTER(c_double),
+                                    POINTER(c_double)]),
+    "dao_get_pool": (c_int32, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_int16),
+                               POINTER(c_double)]),
+    "dao_get_dose": (c_int32, [c_void_p, c_void_p, POINTER(c_double)]),
+    "dao_solve": (c_int32, [c_void_p, c_int32, POINTER(dao_plan)]),
+    "dao_time_product": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double)]),
+}
+
+_lib = None
+
+
+def symbols():
+    return sorted(_SIGS)
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libdao.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with `python -m paper_1003_5402_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(POINTER(ctype))
+
+
+def _addr(v) -> int:
+    """Device address of a torch tensor (or an int address)."""
+    if isinstance(v, int):
+        return v
+    return int(v.data_ptr())
+
+
+class DaoContext:
+    """One plan's device state: dose matrix, structures, pool and master."""
+
+    def __init__(self, row_ptr, col, val, n_blt: int, rows_per_beam, row_len, vox_struct,
+                 prescriptions: Sequence[Dict], dtype: str = "f32", stream: int = 0, **opts):
+        lib = load_library()
+        self._lib = lib
+        self._keep = []
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        vl = np.ascontiguousarray(val, dtype=np.float64)
+        rpb = np.ascontiguousarray(rows_per_beam, dtype=np.int32)
+        rl = np.ascontiguousarray(row_len, dtype=np.int32)
+        vs = np.ascontiguousarray(vox_struct, dtype=np.int16)
+        self._keep += [rp, cl, vl, rpb, rl, vs]
+        M = dao_matrix(rp.shape[0] - 1, int(n_blt), cl.shape[0], _ptr(rp, c_int64), _ptr(cl, c_int32),
+                       _ptr(vl, c_double))
+        Bm = dao_beams(rpb.shape[0], _ptr(rpb, c_int32), _ptr(rl, c_int32))
+        S = dao_structures(len(prescriptions), _ptr(vs, c_int16))
+        PA = (dao_prescription * max(1, len(prescriptions)))()
+        for i, p in enumerate(prescriptions):
+            PA[i] = dao_prescription(int(p["is_target"]), p["t_under"], p["t_over"], p["w_under"], p["w_over"])
+        O = dao_options()
+        lib.dao_default_options(byref(O))
+        O.dtype = DAO_F64 if dtype == "f64" else DAO_F32
+        for k, v in opts.items():
+            setattr(O, k, v)
+        h = c_void_p()
+        st = lib.dao_create(byref(M), byref(Bm), byref(S), PA, byref(O), c_void_p(stream), byref(h))
+        if st != DAO_OK:
+            raise DaoError(st, lib.dao_create_error().decode())
+        self._h = h
+        self.dtype = dtype
+        self.n_vox = int(M.n_vox)
+        self.n_blt = int(n_blt)
+        self.rows_per_beam = rpb.copy()
+        self.max_rows_per_beam = int(rpb.max())
+        self.opts = O
+
+    @classmethod
+    def from_phantom(cls, ph, dtype: Optional[str] = None, stream: int = 0, **opts) -> "DaoContext":
+        return cls(ph.row_ptr, ph.col, ph.val, ph.n_blt, ph.rows_per_beam, ph.row_len, ph.vox_struct,
+                   ph.prescriptions, dtype=dtype or ph.dtype, stream=stream, **opts)
+
+    # -- helpers -------------------------------------------------------------
+    def _check(self, st):
+        if st < 0:
+            raise DaoError(st, self._lib.dao_last_error(self._h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.dao_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- calls -----------------------------------------------------------------
+    def info(self) -> Dict:
+        i = dao_info_t()
+        self._check(self._lib.dao_info(self._h, byref(i)))
+        return {f: getattr(i, f) for f, _ in dao_info_t._fields_}
+
+    def dose(self, x, d) -> None:
+        self._check(self._lib.dao_dose(self._h, c_void_p(_addr(x)), c_void_p(_addr(d))))
+
+    def gradient(self, d, g) -> float:
+        F = c_double()
+        self._check(self._lib.dao_gradient(self._h, c_void_p(_addr(d)), c_void_p(_addr(g)), byref(F)))
+        return F.value
+
+    def _price_out(self):
+        beam = c_int32()
+        lv = np.zeros(2 * self.max_rows_per_beam, dtype=np.int16)
+        rc, gap = c_double(), c_double()
+        return beam, lv, rc, gap
+
+    def _price_result(self, beam, lv, rc, gap):
+        nr = int(self.rows_per_beam[beam.value])
+        leaves = tuple((int(lv[2 * i]), int(lv[2 * i + 1])) for i in range(nr))
+        return dict(beam=beam.value, leaves=leaves, rc=rc.value, gap=gap.value)
+
+    def price(self, g64) -> Dict:
+        beam, lv, rc, gap = self._price_out()
+        self._check(self._lib.dao_price(self._h, c_void_p(_addr(g64)), byref(beam), _ptr(lv, c_int16),
+                                        byref(rc), byref(gap)))
+        return self._price_result(beam, lv, rc, gap)
+
+    def price_current(self) -> Dict:
+        beam, lv, rc, gap = self._price_out()
+        self._check(self._lib.dao_price_current(self._h, byref(beam), _ptr(lv, c_int16), byref(rc),
+                                                byref(gap)))
+        return self._price_result(beam, lv, rc, gap)
+
+    def reset(self) -> None:
+        self._check(self._lib.dao_reset(self._h))
+
+    def add_aperture(self, beam: int, leaves) -> None:
+        lv = np.zeros(2 * self.max_rows_per_beam, dtype=np.int16)
+        flat = np.asarray(leaves, dtype=np.int16).reshape(-1)
+        lv[:flat.shape[0]] = flat
+        self._check(self._lib.dao_add_aperture(self._h, int(beam), _ptr(lv, c_int16)))
+
+    def master_step(self):
+        F, kkt, step = c_double(), c_double(), c_double()
+        self._check(self._lib.dao_master_step(self._h, byref(F), byref(kkt), byref(step)))
+        return F.value, kkt.value, step.value
+
+    def master_solve(self, tol: float, max_steps: int):
+        steps, kkt, F = c_int32(), c_double(), c_double()
+        self._check(self._lib.dao_master_solve(self._h, float(tol), int(max_steps), byref(steps),
+                                               byref(kkt), byref(F)))
+        return steps.value, kkt.value, F.value
+
+    def get_pool(self, cap: int = 256):
+        n = c_int32()
+        beams = np.zeros(cap, dtype=np.int32)
+        lv = np.zeros(cap * 2 * self.max_rows_per_beam, dtype=np.int16)
+        y = np.zeros(cap, dtype=np.float64)
+        self._check(self._lib.dao_get_pool(self._h, cap, byref(n), _ptr(beams, c_int32), _ptr(lv, c_int16),
+                                           _ptr(y, c_double)))
+        k = min(n.value, cap)
+        lv = lv.reshape(cap, self.max_rows_per_beam, 2)
+        pool = []
+        for i in range(k):
+            nr = int(self.rows_per_beam[beams[i]])
+            pool.append((int(beams[i]), tuple((int(a), int(b)) for a, b in lv[i, :nr])))
+        return pool, y[:k].copy()
+
+    def get_dose(self, d64=None) -> float:
+        F = c_double()
+        self._check(self._lib.dao_get_dose(self._h, c_void_p(_addr(d64) if d64 is not None else 0),
+                                           byref(F)))
+        return F.value
+
+    def time_product(self, kernel: int, iters: int) -> float:
+        """Mean microseconds per launch of product kernel 0 (D x) or 1 (D^T u)."""
+        us = c_double()
+        self._check(self._lib.dao_time_product(self._h, int(kernel), int(iters), byref(us)))
+        return us.value
+
+    def solve(self, n_apertures: int) -> Dict:
+        n = max(1, int(n_apertures))
+        arr = dict(round_beam=np.zeros(n, np.int32), round_rc=np.zeros(n), round_gap=np.zeros(n),
+                   round_steps=np.zeros(n, np.int32), round_kkt=np.zeros(n), round_F=np.zeros(n))
+        P = dao_plan()
+        for k, a in arr.items():
+            setattr(P, k, _ptr(a, c_int32 if a.dtype == np.int32 else c_double))
+        st = self._check(self._lib.dao_solve(self._h, int(n_apertures), byref(P)))
+        r = P.rounds
+        return dict(status=st, rounds=r, stop=P.stop, F=P.F, rc1=P.rc1, total_steps=P.total_steps,
+                    total_ls_evals=P.total_ls_evals, **{k: v[:r].copy() for k, v in arr.items()})

@@ -1,0 +1,781 @@
+// C ABI of the DAO library (include/dao.h): context, device buffers, launch
+// sequences and the column-generation driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/dao.h"
+#include "dao_common.h"
+#include "kernels.h"
+#include "layout.h"
+
+using namespace dao;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr size_t STAGE_LIMIT = 48 * 1024;   // largest vector staged in LDS per block
+constexpr int SLICES_PER_BLOCK = 4;         // one slice per wavefront
+constexpr int ELEM_BLOCKS_MAX = 2048;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct dao_ctx {
+    dao_options opt{};
+    int dtype = DAO_F32;
+    size_t tsize = 4;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // sizes and host geometry
+    int64_t V = 0, N = 0, nnz = 0, Vnz = 0, Vpad = 0, nslices = 0;
+    int32_t B = 0, R = 0, maxRB = 0, ncls = 0;
+    uint32_t sell_entries = 0;
+    double F_const = 0.0;
+    std::vector<int32_t> rows_per_beam, row_len, beam_row0;
+
+    // device memory
+    std::vector<DevBuf> bufs;
+    int64_t device_bytes = 0;
+    uint32_t* slice_ptr = nullptr;
+    int32_t* slice_w = nullptr;
+    void* sell_val = nullptr;
+    uint16_t* sell_col = nullptr;
+    int32_t* perm = nullptr;
+    int32_t* csc_ptr = nullptr;
+    int32_t* csc_row = nullptr;
+    void* csc_val = nullptr;
+    uint8_t* cls_int = nullptr;
+    uint8_t* cls_ext = nullptr;
+    ObjClass* classes = nullptr;
+    int32_t *row_start_d = nullptr, *row_len_d = nullptr, *beam_row0_d = nullptr;
+    int32_t *blt_beam_d = nullptr, *blt_row_d = nullptr, *blt_pos_d = nullptr;
+    // master vectors
+    double* d = nullptr;       // [Vpad] master dose
+    void* q = nullptr;         // [Vpad] ctx type
+    void* u = nullptr;         // [Vpad] ctx type
+    double* u64 = nullptr;     // [Vpad]
+    void* ug = nullptr;        // [Vpad] scratch for dao_gradient
+    void* vscratch = nullptr;  // [V] ctx type, allocated on first product timing
+    void* g = nullptr;         // [N] ctx type
+    double* g64 = nullptr;     // [N]
+    void* dx = nullptr;        // [N] ctx type
+    double* x64 = nullptr;     // [N]
+    // pool
+    int K = 0;
+    int32_t* ap_beam = nullptr;
+    int16_t* ap_lv = nullptr;
+    double* y = nullptr;
+    double* p = nullptr;
+    double* gradk = nullptr;
+    std::vector<int32_t> pool_beam;
+    std::vector<int16_t> pool_lv;
+    // state and scratch
+    MasterState* ms = nullptr;
+    MasterState* ms_h = nullptr;      // pinned
+    PriceResult* pr = nullptr;
+    PriceResult* pr_h = nullptr;      // pinned
+    RowRec* rowrec = nullptr;
+    Rec* parts = nullptr;
+    int64_t nparts = 0;
+    uint32_t* counter = nullptr;
+    double* scalar = nullptr;
+    double* scalar_h = nullptr;       // pinned
+    int16_t* lv_stage_h = nullptr;    // pinned
+
+    ~dao_ctx() {
+        for (auto& b : bufs) if (b.p) (void)hipFree(b.p);
+        if (ms_h) (void)hipHostFree(ms_h);
+        if (pr_h) (void)hipHostFree(pr_h);
+        if (scalar_h) (void)hipHostFree(scalar_h);
+        if (lv_stage_h) (void)hipHostFree(lv_stage_h);
+    }
+
+    dao_status fail(dao_status s, std::string m) {
+        err = std::move(m);
+        return s;
+    }
+
+    int64_t elem_blocks(int64_t n) const {
+        return std::max<int64_t>(1, std::min<int64_t>(ELEM_BLOCKS_MAX, (n + BLOCK - 1) / BLOCK));
+    }
+    int64_t slice_blocks() const {
+        return std::max<int64_t>(1, (nslices + SLICES_PER_BLOCK - 1) / SLICES_PER_BLOCK);
+    }
+    bool stage_x() const { return size_t(N) * tsize <= STAGE_LIMIT; }
+    bool stage_x64() const { return size_t(N) * 8 <= STAGE_LIMIT; }
+};
+
+#define HIPCHK(ctx, call)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return (ctx)->fail(DAO_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCHCHK(ctx)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = hipGetLastError();                                                    \
+        if (e_ != hipSuccess)                                                                 \
+            return (ctx)->fail(DAO_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
+
+template <class P>
+dao_status dev_alloc(dao_ctx* c, P** out, size_t bytes) {
+    void* p = nullptr;
+    bytes = std::max<size_t>(bytes, 16);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return c->fail(DAO_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    c->bufs.push_back(DevBuf{p, bytes});
+    c->device_bytes += int64_t(bytes);
+    *out = static_cast<P*>(p);
+    return DAO_OK;
+}
+
+template <class P>
+dao_status upload(dao_ctx* c, P** out, const void* host, size_t bytes) {
+    dao_status s = dev_alloc(c, out, bytes);
+    if (s != DAO_OK) return s;
+    if (bytes) HIPCHK(c, hipMemcpyAsync(*out, host, bytes, hipMemcpyHostToDevice, c->stream));
+    return DAO_OK;
+}
+
+template <class T>
+std::vector<T> convert(const std::vector<double>& v) {
+    std::vector<T> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = T(v[i]);
+    return o;
+}
+
+// Device footprint predicted from the layout (checked against mem_cap before allocating).
+int64_t predicted_bytes(const HostLayout& L, size_t ts, int kmax) {
+    int64_t b = 0;
+    b += (L.nslices + 1) * 4 + L.nslices * 4 + int64_t(L.slice_ptr.back()) * (ts + 2) + L.Vpad * 4;
+    b += (L.N + 1) * 4 + L.nnz * (4 + ts);
+    b += L.Vpad + L.V + (L.n_struct + 1) * sizeof(ObjClass);
+    b += int64_t(L.R) * 8 + (L.B + 1) * 4 + L.N * 12;
+    b += L.Vpad * (8 + 3 * ts + 8) + L.N * (ts + 8 + ts + 8);
+    b += int64_t(kmax) * (4 + 2 * 2 * L.max_rows_per_beam + 24);
+    b += sizeof(MasterState) + sizeof(PriceResult) + L.R * sizeof(RowRec) + 8 * ELEM_BLOCKS_MAX * sizeof(Rec);
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+template <class T>
+SellView<T> sell_view(dao_ctx* c) {
+    return SellView<T>{c->slice_ptr, c->slice_w, static_cast<const T*>(c->sell_val), c->sell_col,
+                       c->nslices, SLICES_PER_BLOCK};
+}
+
+PoolView pool_view(dao_ctx* c) {
+    return PoolView{c->ap_beam, c->ap_lv, c->maxRB, c->blt_beam_d, c->blt_row_d, c->blt_pos_d,
+                    c->beam_row0_d, c->row_start_d, int32_t(c->N)};
+}
+
+template <class T>
+dao_status enqueue_cycle(dao_ctx* c) {
+    const PoolView P = pool_view(c);
+    const SellView<T> S = sell_view<T>(c);
+    const size_t cls_b = sizeof(ObjClass) * c->ncls;
+    k_dir<T><<<1, 1024, 0, c->stream>>>(P, static_cast<const T*>(c->g), c->y, c->p, c->gradk,
+                                        static_cast<T*>(c->dx), c->ms);
+    k_qstep<T><<<c->slice_blocks(), BLOCK, cls_b + (c->stage_x() ? c->N * sizeof(T) : 0), c->stream>>>(
+        S, static_cast<const T*>(c->dx), int(c->N), c->stage_x(), c->d, c->cls_int, c->classes, c->ncls,
+        static_cast<T*>(c->q), c->parts, c->ms, P, c->y, c->p, c->x64);
+    for (int i = 0; i < c->opt.ls_slots; ++i)
+        k_lseval<<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
+            c->d, c->q, sizeof(T) == 8, c->cls_int, c->Vpad, c->classes, c->ncls, c->parts, c->ms, P,
+            c->y, c->p, c->x64);
+    k_update<T><<<c->slice_blocks(), BLOCK, cls_b + (c->stage_x64() ? c->N * 8 : 0), c->stream>>>(
+        S, c->x64, int(c->N), c->stage_x64(), c->d, static_cast<const T*>(c->q), c->cls_int, c->classes,
+        c->ncls, static_cast<T*>(c->u), c->parts, c->ms);
+    k_gradT<T, T, T, T, true><<<c->N, BLOCK, 0, c->stream>>>(c->csc_ptr, c->csc_row,
+                                                             static_cast<const T*>(c->csc_val),
+                                                             static_cast<const T*>(c->u),
+                                                             static_cast<T*>(c->g), c->ms);
+    LAUNCHCHK(c);
+    return DAO_OK;
+}
+
+template <class T>
+dao_status run_master(dao_ctx* c, double tol, int max_steps) {
+    k_master_init<<<1, 1, 0, c->stream>>>(c->ms, c->K, tol, max_steps);
+    LAUNCHCHK(c);
+    // every cycle either finishes a step or advances a line search by
+    // ls_slots evaluations; bound the cycles so a stuck state cannot spin
+    const int64_t max_cycles =
+        int64_t(max_steps + 1) * (LS_MAX_ITER / std::max(1, c->opt.ls_slots) + 2) + 16;
+    int64_t cycles = 0;
+    int chunk = 2;
+    for (;;) {
+        for (int i = 0; i < chunk; ++i) {
+            dao_status s = enqueue_cycle<T>(c);
+            if (s != DAO_OK) return s;
+        }
+        cycles += chunk;
+        HIPCHK(c, hipMemcpyAsync(c->ms_h, c->ms, sizeof(MasterState), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->ms_h->done) break;
+        if (cycles > max_cycles) return c->fail(DAO_EDEVICE, "master state machine made no progress");
+        chunk = std::min(chunk * 2, 32);
+    }
+    return DAO_OK;
+}
+
+// u, u64 and F from the master dose; g (ctx type) from u.
+template <class T>
+dao_status refresh_gradient(dao_ctx* c) {
+    k_objective_int<T><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
+        c->d, c->cls_int, c->Vpad, c->classes, static_cast<T*>(c->u), c->u64, c->parts, c->ms);
+    k_gradT<T, T, T, T, false><<<c->N, BLOCK, 0, c->stream>>>(c->csc_ptr, c->csc_row,
+                                                              static_cast<const T*>(c->csc_val),
+                                                              static_cast<const T*>(c->u),
+                                                              static_cast<T*>(c->g), nullptr);
+    LAUNCHCHK(c);
+    return DAO_OK;
+}
+
+PriceGeom price_geom(dao_ctx* c) {
+    return PriceGeom{c->row_start_d, c->row_len_d, c->beam_row0_d, c->R, c->B};
+}
+
+dao_status price_on(dao_ctx* c, const double* g, int32_t* beam, int16_t* leaves, double* rc,
+                    double* gap) {
+    const int blocks = (c->R + BLOCK / WAVE - 1) / (BLOCK / WAVE);
+    k_price<<<blocks, BLOCK, 0, c->stream>>>(price_geom(c), g, c->rowrec, c->pr);
+    LAUNCHCHK(c);
+    HIPCHK(c, hipMemcpyAsync(c->pr_h, c->pr, sizeof(PriceResult), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (beam) *beam = c->pr_h->beam;
+    if (leaves) std::memcpy(leaves, c->pr_h->leaves, sizeof(int16_t) * 2 * c->pr_h->n_rows);
+    if (rc) *rc = c->pr_h->rc;
+    if (gap) *gap = c->pr_h->gap;
+    return DAO_OK;
+}
+
+// FP64 prices at the master's current dose (g64 = D^T grad F(d), FP64 sums).
+template <class T>
+dao_status price_current(dao_ctx* c, int32_t* beam, int16_t* leaves, double* rc, double* gap) {
+    k_objective_int<T><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
+        c->d, c->cls_int, c->Vpad, c->classes, static_cast<T*>(c->u), c->u64, c->parts, c->ms);
+    k_gradT<T, double, double, double, false><<<c->N, BLOCK, 0, c->stream>>>(
+        c->csc_ptr, c->csc_row, static_cast<const T*>(c->csc_val), c->u64, c->g64, nullptr);
+    LAUNCHCHK(c);
+    return price_on(c, c->g64, beam, leaves, rc, gap);
+}
+
+template <class T>
+dao_status reset_state(dao_ctx* c) {
+    const int64_t eb = c->elem_blocks(c->Vpad);
+    k_fill<double><<<eb, BLOCK, 0, c->stream>>>(c->d, c->Vpad, 0.0);
+    k_fill<double><<<1, BLOCK, 0, c->stream>>>(c->y, c->opt.max_apertures, 0.0);
+    LAUNCHCHK(c);
+    c->K = 0;
+    c->pool_beam.clear();
+    c->pool_lv.clear();
+    return refresh_gradient<T>(c);
+}
+
+dao_status check_aperture(dao_ctx* c, int32_t beam, const int16_t* leaves) {
+    if (beam < 0 || beam >= c->B) return c->fail(DAO_EINVAL, "aperture beam out of range");
+    if (!leaves) return c->fail(DAO_EINVAL, "null leaves");
+    for (int r = c->beam_row0[beam]; r < c->beam_row0[beam + 1]; ++r) {
+        const int lr = r - c->beam_row0[beam];
+        const int L = leaves[2 * lr], Rr = leaves[2 * lr + 1];
+        if (L < 0 || Rr > c->row_len[r] || L > Rr || (L == Rr && L != 0))
+            return c->fail(DAO_EINVAL, "malformed leaf pair in row " + std::to_string(lr));
+    }
+    return DAO_OK;
+}
+
+void mirror_add(dao_ctx* c, int32_t beam, const int16_t* leaves) {
+    c->pool_beam.push_back(beam);
+    const int nr = c->rows_per_beam[beam];
+    for (int i = 0; i < c->maxRB; ++i) {
+        c->pool_lv.push_back(i < nr ? leaves[2 * i] : int16_t(0));
+        c->pool_lv.push_back(i < nr ? leaves[2 * i + 1] : int16_t(0));
+    }
+}
+
+bool in_pool(dao_ctx* c, int32_t beam, const int16_t* leaves) {
+    const int nr = c->rows_per_beam[beam];
+    for (size_t k = 0; k < c->pool_beam.size(); ++k) {
+        if (c->pool_beam[k] != beam) continue;
+        const int16_t* lv = &c->pool_lv[k * 2 * c->maxRB];
+        if (std::equal(lv, lv + 2 * nr, leaves)) return true;
+    }
+    return false;
+}
+
+template <class T>
+dao_status create_typed(dao_ctx* c, const HostLayout& L) {
+    dao_status s;
+#define TRY(x)            \
+    do {                  \
+        s = (x);          \
+        if (s != DAO_OK) return s; \
+    } while (0)
+    const size_t ts = sizeof(T);
+    TRY(upload(c, &c->slice_ptr, L.slice_ptr.data(), L.slice_ptr.size() * 4));
+    TRY(upload(c, &c->slice_w, L.slice_w.data(), L.slice_w.size() * 4));
+    {
+        std::vector<T> v = convert<T>(L.sell_val);
+        TRY(upload(c, &c->sell_val, v.data(), v.size() * ts));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    TRY(upload(c, &c->sell_col, L.sell_col.data(), L.sell_col.size() * 2));
+    TRY(upload(c, &c->perm, L.perm.data(), L.perm.size() * 4));
+    TRY(upload(c, &c->csc_ptr, L.csc_ptr.data(), L.csc_ptr.size() * 4));
+    TRY(upload(c, &c->csc_row, L.csc_row.data(), L.csc_row.size() * 4));
+    {
+        std::vector<T> v = convert<T>(L.csc_val);
+        TRY(upload(c, &c->csc_val, v.data(), v.size() * ts));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    TRY(upload(c, &c->cls_int, L.cls_int.data(), L.cls_int.size()));
+    TRY(upload(c, &c->cls_ext, L.cls_ext.data(), L.cls_ext.size()));
+    TRY(upload(c, &c->classes, L.classes.data(), L.classes.size() * sizeof(ObjClass)));
+    TRY(upload(c, &c->row_start_d, L.row_start.data(), L.row_start.size() * 4));
+    TRY(upload(c, &c->row_len_d, L.row_len.data(), L.row_len.size() * 4));
+    TRY(upload(c, &c->beam_row0_d, L.beam_row0.data(), L.beam_row0.size() * 4));
+    TRY(upload(c, &c->blt_beam_d, L.blt_beam.data(), L.blt_beam.size() * 4));
+    TRY(upload(c, &c->blt_row_d, L.blt_row.data(), L.blt_row.size() * 4));
+    TRY(upload(c, &c->blt_pos_d, L.blt_pos.data(), L.blt_pos.size() * 4));
+    TRY(dev_alloc(c, &c->d, c->Vpad * 8));
+    TRY(dev_alloc(c, &c->q, c->Vpad * ts));
+    TRY(dev_alloc(c, &c->u, c->Vpad * ts));
+    TRY(dev_alloc(c, &c->u64, c->Vpad * 8));
+    TRY(dev_alloc(c, &c->ug, c->Vpad * ts));
+    TRY(dev_alloc(c, &c->g, c->N * ts));
+    TRY(dev_alloc(c, &c->g64, c->N * 8));
+    TRY(dev_alloc(c, &c->dx, c->N * ts));
+    TRY(dev_alloc(c, &c->x64, c->N * 8));
+    const int km = c->opt.max_apertures;
+    TRY(dev_alloc(c, &c->ap_beam, km * 4));
+    TRY(dev_alloc(c, &c->ap_lv, size_t(km) * c->maxRB * 2 * 2));
+    TRY(dev_alloc(c, &c->y, km * 8));
+    TRY(dev_alloc(c, &c->p, km * 8));
+    TRY(dev_alloc(c, &c->gradk, km * 8));
+    TRY(dev_alloc(c, &c->ms, sizeof(MasterState)));
+    TRY(dev_alloc(c, &c->pr, sizeof(PriceResult)));
+    TRY(dev_alloc(c, &c->rowrec, std::max<int64_t>(1, c->R) * sizeof(RowRec)));
+    c->nparts = std::max<int64_t>({c->slice_blocks(), c->elem_blocks(c->Vpad), c->elem_blocks(c->V)});
+    TRY(dev_alloc(c, &c->parts, c->nparts * sizeof(Rec)));
+    TRY(dev_alloc(c, &c->counter, 16));
+    TRY(dev_alloc(c, &c->scalar, 16));
+#undef TRY
+    HIPCHK(c, hipHostMalloc((void**)&c->ms_h, sizeof(MasterState), hipHostMallocDefault));
+    HIPCHK(c, hipHostMalloc((void**)&c->pr_h, sizeof(PriceResult), hipHostMallocDefault));
+    HIPCHK(c, hipHostMalloc((void**)&c->scalar_h, 16, hipHostMallocDefault));
+    HIPCHK(c, hipHostMalloc((void**)&c->lv_stage_h, size_t(c->maxRB) * 4 + 16, hipHostMallocDefault));
+    std::memset(c->ms_h, 0, sizeof(MasterState));
+    c->ms_h->done = 1;
+    c->ms_h->refresh_every = c->opt.refresh_every;
+    c->ms_h->F_const = c->F_const;
+    HIPCHK(c, hipMemcpyAsync(c->ms, c->ms_h, sizeof(MasterState), hipMemcpyHostToDevice, c->stream));
+    std::memset(c->pr_h, 0, sizeof(PriceResult));
+    HIPCHK(c, hipMemcpyAsync(c->pr, c->pr_h, sizeof(PriceResult), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->counter, 0, 16, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->ap_lv, 0, size_t(km) * c->maxRB * 4, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->ap_beam, 0, km * 4, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->p, 0, km * 8, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->q, 0, c->Vpad * ts, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->dx, 0, c->N * ts, c->stream));
+    s = reset_state<T>(c);
+    if (s != DAO_OK) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DAO_OK;
+}
+
+template <class T>
+dao_status dose_typed(dao_ctx* c, const void* x, void* d) {
+    k_fill<T><<<c->elem_blocks(c->V), BLOCK, 0, c->stream>>>(static_cast<T*>(d), c->V, T(0));
+    k_dose<T><<<c->slice_blocks(), BLOCK, c->stage_x() ? c->N * sizeof(T) : 0, c->stream>>>(
+        sell_view<T>(c), c->perm, static_cast<const T*>(x), int(c->N), c->stage_x(), static_cast<T*>(d));
+    LAUNCHCHK(c);
+    return DAO_OK;
+}
+
+template <class T>
+dao_status gradient_typed(dao_ctx* c, const void* d, void* g, double* F) {
+    const T* dd = static_cast<const T*>(d);
+    k_objective_ext<T><<<c->elem_blocks(c->V), BLOCK, 0, c->stream>>>(dd, c->cls_ext, c->V, c->classes,
+                                                                       c->parts, c->counter, c->scalar);
+    k_gather_grad<T><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(dd, c->perm, c->cls_int, c->Vpad,
+                                                                        c->classes, static_cast<T*>(c->ug));
+    k_gradT<T, T, T, T, false><<<c->N, BLOCK, 0, c->stream>>>(c->csc_ptr, c->csc_row,
+                                                              static_cast<const T*>(c->csc_val),
+                                                              static_cast<const T*>(c->ug), static_cast<T*>(g),
+                                                              nullptr);
+    LAUNCHCHK(c);
+    HIPCHK(c, hipMemcpyAsync(c->scalar_h, c->scalar, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (F) *F = c->scalar_h[0];
+    return DAO_OK;
+}
+
+// Mean device time of `iters` back-to-back launches of one product kernel,
+// measured with HIP events on the context stream.  Inputs are the master's
+// current vectors; outputs go to scratch buffers.
+template <class T>
+dao_status time_product_typed(dao_ctx* c, int kernel, int iters, double* us) {
+    if (!c->vscratch) {   // k_dose scatters to caller order: V entries
+        dao_status s = dev_alloc(c, &c->vscratch, size_t(c->V) * sizeof(T));
+        if (s != DAO_OK) return s;
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    auto launch = [&]() {
+        if (kernel == 0)
+            k_dose<T><<<c->slice_blocks(), BLOCK, c->stage_x() ? c->N * sizeof(T) : 0, c->stream>>>(
+                sell_view<T>(c), c->perm, static_cast<const T*>(c->dx), int(c->N), c->stage_x(),
+                static_cast<T*>(c->vscratch));
+        else
+            k_gradT<T, T, T, T, false><<<c->N, BLOCK, 0, c->stream>>>(
+                c->csc_ptr, c->csc_row, static_cast<const T*>(c->csc_val), static_cast<const T*>(c->u),
+                static_cast<T*>(c->dx), nullptr);
+    };
+    launch();
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int i = 0; i < iters; ++i) launch();
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    LAUNCHCHK(c);
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *us = 1e3 * double(ms) / iters;
+    return DAO_OK;
+}
+
+template <class T>
+dao_status master_solve_typed(dao_ctx* c, double tol, int max_steps, int32_t* steps, double* kkt,
+                              double* F) {
+    dao_status s = run_master<T>(c, tol, max_steps);
+    if (s != DAO_OK) return s;
+    if (steps) *steps = c->ms_h->steps;
+    if (kkt) *kkt = c->ms_h->kkt;
+    if (F) *F = c->ms_h->F;
+    return DAO_OK;
+}
+
+template <class T>
+dao_status solve_typed(dao_ctx* c, int32_t n_ap, dao_plan* out) {
+    dao_status s = reset_state<T>(c);
+    if (s != DAO_OK) return s;
+    double eps = c->opt.eps, rc1 = NAN;
+    int tighten = 0;
+    int32_t stop = DAO_OK;
+    int64_t steps0 = 0, ls0 = 0;
+    HIPCHK(c, hipMemcpyAsync(c->ms_h, c->ms, sizeof(MasterState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    steps0 = c->ms_h->total_steps;
+    ls0 = c->ms_h->total_ls;
+    std::vector<int16_t> lv(2 * c->maxRB);
+    int rounds = 0;
+    while (c->K < n_ap) {
+        int32_t beam;
+        double rc, gap;
+        s = (sizeof(T) == 8) ? price_on(c, static_cast<const double*>(c->g), &beam, lv.data(), &rc, &gap)
+                             : price_current<T>(c, &beam, lv.data(), &rc, &gap);
+        if (s != DAO_OK) return s;
+        if (std::isnan(rc1)) {
+            rc1 = rc;
+            if (!(rc1 < 0.0)) {
+                stop = DAO_EOPTIMAL;
+                break;
+            }
+        }
+        const double scale = std::fabs(rc1);
+        if (rc >= -c->opt.tau_rel * scale) {
+            stop = DAO_EOPTIMAL;
+            break;
+        }
+        if (in_pool(c, beam, lv.data())) {
+            if (tighten >= c->opt.max_tighten) {
+                stop = DAO_ESTALLED;
+                break;
+            }
+            ++tighten;
+            eps /= 10.0;
+            s = run_master<T>(c, eps * scale, c->opt.max_steps);
+            if (s != DAO_OK) return s;
+            continue;
+        }
+        if (c->K >= c->opt.max_apertures) return c->fail(DAO_ESTATE, "pool capacity reached");
+        k_add_from_price<<<1, 256, 0, c->stream>>>(c->pr, c->K, c->maxRB, c->ap_beam, c->ap_lv, c->y);
+        LAUNCHCHK(c);
+        mirror_add(c, beam, lv.data());
+        c->K += 1;
+        s = run_master<T>(c, eps * scale, c->opt.max_steps);
+        if (s != DAO_OK) return s;
+        if (out) {
+            if (out->round_beam) out->round_beam[rounds] = beam;
+            if (out->round_rc) out->round_rc[rounds] = rc;
+            if (out->round_gap) out->round_gap[rounds] = gap;
+            if (out->round_steps) out->round_steps[rounds] = c->ms_h->steps;
+            if (out->round_kkt) out->round_kkt[rounds] = c->ms_h->kkt;
+            if (out->round_F) out->round_F[rounds] = c->ms_h->F;
+        }
+        ++rounds;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->ms_h, c->ms, sizeof(MasterState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (out) {
+        out->rounds = rounds;
+        out->stop = stop;
+        out->F = c->ms_h->F;
+        out->rc1 = rc1;
+        out->total_steps = c->ms_h->total_steps - steps0;
+        out->total_ls_evals = c->ms_h->total_ls - ls0;
+    }
+    return DAO_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void dao_default_options(dao_options* o) {
+    if (!o) return;
+    o->dtype = DAO_F32;
+    o->max_apertures = 64;
+    o->eps = 1e-6;
+    o->max_steps = 500;
+    o->tau_rel = 1e-10;
+    o->max_tighten = 3;
+    o->refresh_every = 50;
+    o->ls_slots = 2;
+    o->mem_cap_bytes = 0;
+}
+
+const char* dao_create_error(void) { return g_create_error.c_str(); }
+
+const char* dao_last_error(const dao_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+dao_status dao_create(const dao_matrix* D, const dao_beams* beams, const dao_structures* structs,
+                      const dao_prescription* presc, const dao_options* opt_in, void* stream,
+                      dao_ctx** out) {
+    g_create_error.clear();
+    if (!out) {
+        g_create_error = "null output pointer";
+        return DAO_EINVAL;
+    }
+    *out = nullptr;
+    dao_options opt;
+    if (opt_in)
+        opt = *opt_in;
+    else
+        dao_default_options(&opt);
+    std::string err;
+    dao_status s = validate_inputs(D, beams, structs, presc, &opt, &err);
+    if (s != DAO_OK) {
+        g_create_error = err;
+        return s;
+    }
+    auto L = std::make_unique<HostLayout>();
+    build_layout(D, beams, structs, presc, L.get());
+    const size_t ts = opt.dtype == DAO_F64 ? 8 : 4;
+    const int64_t need = predicted_bytes(*L, ts, opt.max_apertures);
+    if (opt.mem_cap_bytes > 0 && need > opt.mem_cap_bytes) {
+        g_create_error = "device footprint " + std::to_string(need) + " B exceeds mem_cap_bytes";
+        return DAO_ENOMEM;
+    }
+    auto c = std::make_unique<dao_ctx>();
+    c->opt = opt;
+    c->dtype = opt.dtype;
+    c->tsize = ts;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->V = L->V;
+    c->N = L->N;
+    c->nnz = L->nnz;
+    c->Vnz = L->Vnz;
+    c->Vpad = std::max<int64_t>(L->Vpad, SLICE);
+    c->nslices = L->nslices;
+    c->B = L->B;
+    c->R = L->R;
+    c->maxRB = L->max_rows_per_beam;
+    c->ncls = L->n_struct + 1;
+    c->sell_entries = L->slice_ptr.back();
+    c->F_const = L->F_const;
+    c->rows_per_beam.assign(beams->rows_per_beam, beams->rows_per_beam + beams->n_beams);
+    c->row_len = L->row_len;
+    c->beam_row0 = L->beam_row0;
+    if (L->Vpad < c->Vpad) {   // no non-empty row at all: keep one padding slice
+        L->perm.resize(c->Vpad, -1);
+        L->cls_int.resize(c->Vpad, uint8_t(L->n_struct));
+    }
+    s = (c->dtype == DAO_F64) ? create_typed<double>(c.get(), *L) : create_typed<float>(c.get(), *L);
+    if (s != DAO_OK) {
+        g_create_error = c->err;
+        return s;
+    }
+    *out = c.release();
+    return DAO_OK;
+}
+
+void dao_destroy(dao_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+dao_status dao_info(const dao_ctx* c, dao_info_t* o) {
+    if (!c || !o) return DAO_EINVAL;
+    o->n_vox = c->V;
+    o->n_vox_nonempty = c->Vnz;
+    o->n_blt = c->N;
+    o->nnz = c->nnz;
+    o->n_rows = c->R;
+    o->n_beams = c->B;
+    o->max_rows_per_beam = c->maxRB;
+    o->dtype = c->dtype;
+    o->n_slices = int32_t(c->nslices);
+    o->sell_entries = c->sell_entries;
+    o->device_bytes = c->device_bytes;
+    const int64_t ts = int64_t(c->tsize);
+    // forward: every stored entry (value + 16-bit column) + slice headers +
+    // x once + d once (caller order)
+    o->bytes_dose = c->nnz * (ts + 2) + (c->nslices + 1) * 4 + c->nslices * 4 + c->N * ts + c->Vnz * (ts + 4);
+    // transpose: every entry (value + 32-bit row) + column pointers + u once + g once
+    o->bytes_gradient = c->nnz * (ts + 4) + (c->N + 1) * 4 + c->Vnz * ts + c->N * ts;
+    return DAO_OK;
+}
+
+dao_status dao_dose(dao_ctx* c, const void* x, void* d) {
+    if (!c) return DAO_EINVAL;
+    if (!x || !d) return c->fail(DAO_EINVAL, "null vector");
+    return c->dtype == DAO_F64 ? dose_typed<double>(c, x, d) : dose_typed<float>(c, x, d);
+}
+
+dao_status dao_gradient(dao_ctx* c, const void* d, void* g, double* F) {
+    if (!c) return DAO_EINVAL;
+    if (!d || !g) return c->fail(DAO_EINVAL, "null vector");
+    return c->dtype == DAO_F64 ? gradient_typed<double>(c, d, g, F) : gradient_typed<float>(c, d, g, F);
+}
+
+dao_status dao_price(dao_ctx* c, const double* g, int32_t* beam, int16_t* leaves, double* rc,
+                     double* gap) {
+    if (!c) return DAO_EINVAL;
+    if (!g) return c->fail(DAO_EINVAL, "null prices");
+    return price_on(c, g, beam, leaves, rc, gap);
+}
+
+dao_status dao_reset(dao_ctx* c) {
+    if (!c) return DAO_EINVAL;
+    dao_status s = c->dtype == DAO_F64 ? reset_state<double>(c) : reset_state<float>(c);
+    if (s != DAO_OK) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DAO_OK;
+}
+
+dao_status dao_add_aperture(dao_ctx* c, int32_t beam, const int16_t* leaves) {
+    if (!c) return DAO_EINVAL;
+    dao_status s = check_aperture(c, beam, leaves);
+    if (s != DAO_OK) return s;
+    if (c->K >= c->opt.max_apertures) return c->fail(DAO_ESTATE, "pool capacity reached");
+    const int nr = c->rows_per_beam[beam];
+    for (int i = 0; i < c->maxRB; ++i) {
+        c->lv_stage_h[2 * i] = i < nr ? leaves[2 * i] : int16_t(0);
+        c->lv_stage_h[2 * i + 1] = i < nr ? leaves[2 * i + 1] : int16_t(0);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->ap_lv + size_t(c->K) * c->maxRB * 2, c->lv_stage_h,
+                             size_t(c->maxRB) * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->ap_beam + c->K, &beam, 4, hipMemcpyHostToDevice, c->stream));
+    k_fill<double><<<1, 64, 0, c->stream>>>(c->y + c->K, 1, 0.0);
+    LAUNCHCHK(c);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    mirror_add(c, beam, leaves);
+    c->K += 1;
+    return DAO_OK;
+}
+
+dao_status dao_master_step(dao_ctx* c, double* F, double* kkt, double* step) {
+    if (!c) return DAO_EINVAL;
+    dao_status s = c->dtype == DAO_F64 ? run_master<double>(c, 0.0, 1) : run_master<float>(c, 0.0, 1);
+    if (s != DAO_OK) return s;
+    if (F) *F = c->ms_h->F;
+    if (kkt) *kkt = c->ms_h->kkt;
+    if (step) *step = c->ms_h->steps > 0 ? c->ms_h->last_step : 0.0;
+    return DAO_OK;
+}
+
+dao_status dao_master_solve(dao_ctx* c, double tol, int32_t max_steps, int32_t* steps, double* kkt,
+                            double* F) {
+    if (!c) return DAO_EINVAL;
+    if (!(tol >= 0) || max_steps < 0) return c->fail(DAO_EINVAL, "bad tolerance or step cap");
+    return c->dtype == DAO_F64 ? master_solve_typed<double>(c, tol, max_steps, steps, kkt, F)
+                               : master_solve_typed<float>(c, tol, max_steps, steps, kkt, F);
+}
+
+dao_status dao_price_current(dao_ctx* c, int32_t* beam, int16_t* leaves, double* rc, double* gap) {
+    if (!c) return DAO_EINVAL;
+    return c->dtype == DAO_F64 ? price_current<double>(c, beam, leaves, rc, gap)
+                               : price_current<float>(c, beam, leaves, rc, gap);
+}
+
+dao_status dao_get_pool(dao_ctx* c, int32_t cap, int32_t* n, int32_t* beams, int16_t* leaves, double* y) {
+    if (!c) return DAO_EINVAL;
+    if (n) *n = c->K;
+    const int m = std::min<int>(std::max(cap, 0), c->K);
+    if (beams) std::copy(c->pool_beam.begin(), c->pool_beam.begin() + m, beams);
+    if (leaves) std::copy(c->pool_lv.begin(), c->pool_lv.begin() + size_t(m) * 2 * c->maxRB, leaves);
+    if (y && m > 0) {
+        HIPCHK(c, hipMemcpyAsync(y, c->y, size_t(m) * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return DAO_OK;
+}
+
+dao_status dao_get_dose(dao_ctx* c, double* d_dev, double* F) {
+    if (!c) return DAO_EINVAL;
+    if (d_dev) {
+        k_fill<double><<<c->elem_blocks(c->V), BLOCK, 0, c->stream>>>(d_dev, c->V, 0.0);
+        k_scatter<double, double><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(c->d, c->perm, c->Vpad, d_dev);
+        LAUNCHCHK(c);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->ms_h, c->ms, sizeof(MasterState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (F) *F = c->ms_h->F;
+    return DAO_OK;
+}
+
+dao_status dao_time_product(dao_ctx* c, int32_t kernel, int32_t iters, double* us_per_launch) {
+    if (!c) return DAO_EINVAL;
+    if ((kernel != 0 && kernel != 1) || iters < 1 || !us_per_launch)
+        return c->fail(DAO_EINVAL, "kernel must be 0 or 1, iters >= 1");
+    return c->dtype == DAO_F64 ? time_product_typed<double>(c, kernel, iters, us_per_launch)
+                               : time_product_typed<float>(c, kernel, iters, us_per_launch);
+}
+
+dao_status dao_solve(dao_ctx* c, int32_t n_apertures, dao_plan* out) {
+    if (!c) return DAO_EINVAL;
+    if (n_apertures < 0 || n_apertures > c->opt.max_apertures)
+        return c->fail(DAO_EINVAL, "n_apertures must be in [0, max_apertures]");
+    dao_status s = c->dtype == DAO_F64 ? solve_typed<double>(c, n_apertures, out)
+                                       : solve_typed<float>(c, n_apertures, out);
+    if (s != DAO_OK) return s;
+    return out ? dao_status(out->stop) : DAO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Internal types shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <stdint.h>
+
+namespace dao {
+
+constexpr int WAVE = 64;              // CDNA wavefront width
+constexpr int SLICE = 64;             // rows per forward-layout slice (one per wavefront)
+constexpr int MAX_ROW_LEN = 64;       // one MLC row per wavefront in pricing
+constexpr int MAX_APERTURES = 256;
+constexpr int LS_MAX_ITER = 60;       // line-search evaluations per master step
+constexpr int BLOCK = 256;            // threads per block of the streaming kernels
+constexpr int NPART = 6;              // doubles per block in a reduction record
+
+// Per-structure objective coefficients (eq. 9 and eq. 10).  a and b are the
+// structure weights already divided by the structure size; the class index
+// n_struct (one past the last structure) is "no structure": all zero.
+struct ObjClass {
+    double a, t_under, b, t_over;
+};
+
+// Phases of one gradient-projection step (the master loop is a fixed
+// sequence of launches; each launch runs only in its phase).
+enum Phase : int {
+    PH_DIR = 0,   // gradient over the pool, projection, t_max, dx = A p
+    PH_Q = 1,     // q = D dx and the first line-search evaluation at t = 0
+    PH_LS = 2,    // further line-search evaluations
+    PH_UPD = 3,   // d += t q (or d = D(A y) on refresh steps), grad F, F
+    PH_TP = 4     // g = D^T grad F
+};
+
+// Device-resident master state.  Written only by single threads (a lone
+// block, or the last block of a launch) and read by every block at the start
+// of the next launch.
+struct MasterState {
+    int32_t phase;
+    int32_t done;          // 1: converged / cap reached / zero direction
+    int32_t steps;         // steps taken in the current master solve
+    int32_t max_steps;
+    int32_t K;             // pool size
+    int32_t ls_iter;       // evaluations in the current line search
+    int32_t hi_known;
+    int32_t refresh;       // current update recomputes d = D(A y)
+    int32_t refresh_every;
+    int32_t stop_reason;   // 0 running, 1 kkt, 2 cap, 3 zero direction
+    int64_t total_steps;
+    int64_t total_ls;
+    double tol;
+    double kkt;
+    double t;              // current trial / final step
+    double lo, hi;
+    double t_max;
+    double gphi0;          // <grad_y, p>
+    double F;              // objective at the current dose
+    double F_const;        // objective of voxels no beamlet reaches (dose 0)
+    double last_step;
+    uint32_t counter;      // last-block-done counter, reset by the last block
+    uint32_t pad;
+};
+
+// Pricing result written by the last block of the pricing launch.
+struct PriceResult {
+    int32_t beam;
+    int32_t n_rows;
+    double rc;
+    double gap;
+    uint32_t counter;
+    uint32_t pad;
+    int16_t leaves[2 * 1024];   // (L, R) per row of the chosen beam
+};
+
+}  // namespace dao

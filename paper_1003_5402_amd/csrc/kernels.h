@@ -1,0 +1,849 @@
+// gfx950 kernels of the DAO hot path.
+//
+// Layouts (built on the host, see layout.cpp):
+//   forward  : sliced ELL, 64 voxel rows per slice, entries of a slice stored
+//              column-major (entry k of the slice's lane-l row at
+//              slice_ptr[s] + 64 k + l) so a wavefront reads each k as one
+//              contiguous 64-lane load; 16-bit beamlet indices.
+//   transpose: beamlet-major copy (one run of (internal row, value) per
+//              beamlet), read by one workgroup per beamlet.
+//   vectors  : "internal" voxel vectors (d, q, u, class) follow the slice
+//              row order; rows past the last non-empty voxel are padding
+//              with class "none" and zero coefficients.
+//
+// Reductions are deterministic: every sum is taken in a fixed order
+// (per-lane sequential, then a fixed butterfly, then a fixed block order),
+// never with floating-point atomics.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "dao_common.h"
+
+namespace dao {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double grad_f(const ObjClass& c, double z) {
+    // dF/dz of eq. 9 + eq. 10 for one voxel
+    return -2.0 * c.a * fmax(0.0, c.t_under - z) + 2.0 * c.b * fmax(0.0, z - c.t_over);
+}
+
+__device__ __forceinline__ double obj_f(const ObjClass& c, double z) {
+    const double un = fmax(0.0, c.t_under - z);
+    const double ov = fmax(0.0, z - c.t_over);
+    return c.a * un * un + c.b * ov * ov;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, WAVE));
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, WAVE));
+    return v;
+}
+
+// Block-wide reduction record: (sum, sum, sum, min, max, sum) -- the line
+// search needs phi', the right and left slopes, the nearest breakpoints on
+// both sides; the last slot carries an objective partial.
+struct Rec {
+    double s0, s1, s2, mn, mx, s5;
+};
+
+__device__ __forceinline__ Rec rec_identity() {
+    return Rec{0.0, 0.0, 0.0, INFINITY, -INFINITY, 0.0};
+}
+
+// Reduce one Rec over the block (blockDim.x = BLOCK); result valid in thread 0.
+__device__ __forceinline__ Rec block_reduce(Rec r) {
+    __shared__ Rec s_w[BLOCK / WAVE];
+    r.s0 = wave_sum(r.s0);
+    r.s1 = wave_sum(r.s1);
+    r.s2 = wave_sum(r.s2);
+    r.mn = wave_min(r.mn);
+    r.mx = wave_max(r.mx);
+    r.s5 = wave_sum(r.s5);
+    const int w = threadIdx.x / WAVE;
+    if ((threadIdx.x % WAVE) == 0) s_w[w] = r;
+    __syncthreads();
+    Rec out = rec_identity();
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < BLOCK / WAVE; ++i) {
+            out.s0 += s_w[i].s0;
+            out.s1 += s_w[i].s1;
+            out.s2 += s_w[i].s2;
+            out.mn = fmin(out.mn, s_w[i].mn);
+            out.mx = fmax(out.mx, s_w[i].mx);
+            out.s5 += s_w[i].s5;
+        }
+    }
+    __syncthreads();
+    return out;
+}
+
+// Thread 0 of every block stores its record, then the last block to arrive
+// reduces all records in block order.  Returns true in every thread of the
+// last block, with the total in *total (valid in thread 0).
+__device__ __forceinline__ bool arrive_and_reduce(Rec mine, Rec* parts, uint32_t* counter,
+                                                  Rec* total) {
+    __shared__ int s_last;
+    if (threadIdx.x == 0) {
+        parts[blockIdx.x] = mine;
+        __threadfence();
+        const uint32_t prev = atomicAdd(counter, 1u);
+        s_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __threadfence();
+    // fixed-order reduction of gridDim.x records: each thread takes a
+    // contiguous run, then the block combines runs in order
+    Rec acc = rec_identity();
+    const int n = gridDim.x;
+    const int per = (n + BLOCK - 1) / BLOCK;
+    const int b0 = threadIdx.x * per;
+    const int b1 = min(n, b0 + per);
+    for (int b = b0; b < b1; ++b) {
+        const Rec p = parts[b];
+        acc.s0 += p.s0;
+        acc.s1 += p.s1;
+        acc.s2 += p.s2;
+        acc.mn = fmin(acc.mn, p.mn);
+        acc.mx = fmax(acc.mx, p.mx);
+        acc.s5 += p.s5;
+    }
+    const Rec t = block_reduce(acc);
+    if (threadIdx.x == 0) {
+        *total = t;
+        *counter = 0u;
+    }
+    __syncthreads();
+    return true;
+}
+
+// Contribution of one voxel to the line-search evaluation at step t:
+// phi'(t) = sum q_j dF/dz_j(d_j + t q_j); slopes of phi' just right / left of
+// t; nearest breakpoint above / below t (where d_j + t q_j meets a threshold).
+__device__ __forceinline__ void ls_voxel(const ObjClass& c, double d, double q, double t,
+                                         Rec& r) {
+    const double z = d + t * q;
+    r.s0 += q * grad_f(c, z);
+    const bool ua = c.a > 0.0, ob = c.b > 0.0;
+    const bool under_r = ua && ((z < c.t_under) || (z == c.t_under && q < 0.0));
+    const bool over_r = ob && ((z > c.t_over) || (z == c.t_over && q > 0.0));
+    const bool under_l = ua && ((z < c.t_under) || (z == c.t_under && q > 0.0));
+    const bool over_l = ob && ((z > c.t_over) || (z == c.t_over && q < 0.0));
+    const double q2 = q * q;
+    r.s1 += q2 * ((under_r ? c.a : 0.0) + (over_r ? c.b : 0.0));
+    r.s2 += q2 * ((under_l ? c.a : 0.0) + (over_l ? c.b : 0.0));
+    if (q != 0.0) {
+        if (ua) {
+            const double bp = (c.t_under - d) / q;
+            if (bp > t) r.mn = fmin(r.mn, bp);
+            if (bp < t) r.mx = fmax(r.mx, bp);
+        }
+        if (ob) {
+            const double bp = (c.t_over - d) / q;
+            if (bp > t) r.mn = fmin(r.mn, bp);
+            if (bp < t) r.mx = fmax(r.mx, bp);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// sliced-ELL row dot product: lane `lane` of a wavefront owns one row of the
+// slice starting at entry `base` with `w` entries per row.  Entries are
+// visited in the row's stored (ascending beamlet) order.
+// ---------------------------------------------------------------------------
+template <class T, class XT, class Acc>
+__device__ __forceinline__ Acc sell_dot(const T* __restrict__ val, const uint16_t* __restrict__ col,
+                                        uint32_t base, int w, int lane, const XT* __restrict__ xs) {
+    const T* v = val + base + lane;
+    const uint16_t* c = col + base + lane;
+    Acc acc = Acc(0);
+    int k = 0;
+    for (; k + 4 <= w; k += 4) {
+        const T v0 = v[0], v1 = v[SLICE], v2 = v[2 * SLICE], v3 = v[3 * SLICE];
+        const uint16_t c0 = c[0], c1 = c[SLICE], c2 = c[2 * SLICE], c3 = c[3 * SLICE];
+        acc += Acc(v0) * Acc(xs[c0]);
+        acc += Acc(v1) * Acc(xs[c1]);
+        acc += Acc(v2) * Acc(xs[c2]);
+        acc += Acc(v3) * Acc(xs[c3]);
+        v += 4 * SLICE;
+        c += 4 * SLICE;
+    }
+    for (; k < w; ++k) {
+        acc += Acc(v[0]) * Acc(xs[c[0]]);
+        v += SLICE;
+        c += SLICE;
+    }
+    return acc;
+}
+
+// Forward-layout device view.
+template <class T>
+struct SellView {
+    const uint32_t* slice_ptr;
+    const int32_t* slice_w;
+    const T* val;
+    const uint16_t* col;
+    int64_t nslices;
+    int spb;   // slices per block
+};
+
+// Stage an n-vector into LDS (or return the global pointer when not staged).
+template <class XT, class ST>
+__device__ __forceinline__ const XT* stage_vec(const ST* __restrict__ src, int n, XT* lds, bool stage) {
+    if (!stage) return reinterpret_cast<const XT*>(src);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = XT(src[i]);
+    __syncthreads();
+    return lds;
+}
+
+// ---------------------------------------------------------------------------
+// plain products (C-ABI dao_dose / dao_gradient and pricing at round ends)
+// ---------------------------------------------------------------------------
+
+// d_ext[perm[r]] = (D x)_r for every non-empty row; x staged in LDS.
+template <class T>
+__global__ void __launch_bounds__(BLOCK) k_dose(SellView<T> S, const int32_t* __restrict__ perm,
+                                                const T* __restrict__ x, int N, bool stage,
+                                                T* __restrict__ d_ext) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const T* xs = stage_vec<T, T>(x, N, reinterpret_cast<T*>(smem), stage);
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int64_t s0 = int64_t(blockIdx.x) * S.spb;
+    const int64_t s1 = min(S.nslices, s0 + S.spb);
+    for (int64_t s = s0 + wave; s < s1; s += BLOCK / WAVE) {
+        const T acc = sell_dot<T, T, T>(S.val, S.col, S.slice_ptr[s], S.slice_w[s], lane, xs);
+        const int32_t j = perm[s * SLICE + lane];
+        if (j >= 0) d_ext[j] = acc;
+    }
+}
+
+template <class T>
+__global__ void k_fill(T* __restrict__ p, int64_t n, T v) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+// out[perm[r]] = in[r] for internal rows (caller order), after a fill of out.
+template <class TI, class TO>
+__global__ void k_scatter(const TI* __restrict__ in, const int32_t* __restrict__ perm, int64_t n,
+                          TO* __restrict__ out) {
+    for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < n;
+         r += int64_t(gridDim.x) * blockDim.x) {
+        const int32_t j = perm[r];
+        if (j >= 0) out[j] = TO(in[r]);
+    }
+}
+
+// F over every caller voxel (eq. 9 + eq. 10), last block writes *F_out.
+template <class T>
+__global__ void __launch_bounds__(BLOCK) k_objective_ext(const T* __restrict__ d_ext,
+                                                         const uint8_t* __restrict__ cls, int64_t V,
+                                                         const ObjClass* __restrict__ classes,
+                                                         Rec* parts, uint32_t* counter,
+                                                         double* F_out) {
+    Rec r = rec_identity();
+    for (int64_t j = int64_t(blockIdx.x) * BLOCK + threadIdx.x; j < V; j += int64_t(gridDim.x) * BLOCK)
+        r.s5 += obj_f(classes[cls[j]], double(d_ext[j]));
+    Rec tot;
+    Rec mine = block_reduce(r);
+    if (arrive_and_reduce(mine, parts, counter, &tot) && threadIdx.x == 0) *F_out = tot.s5;
+}
+
+// u[r] = dF/dz at the caller's dose of internal row r (0 on padding rows).
+template <class T>
+__global__ void k_gather_grad(const T* __restrict__ d_ext, const int32_t* __restrict__ perm,
+                              const uint8_t* __restrict__ cls, int64_t Vpad,
+                              const ObjClass* __restrict__ classes, T* __restrict__ u) {
+    for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < Vpad;
+         r += int64_t(gridDim.x) * blockDim.x) {
+        const int32_t j = perm[r];
+        u[r] = j >= 0 ? T(grad_f(classes[cls[r]], double(d_ext[j]))) : T(0);
+    }
+}
+
+// u (ctx type) and optionally u64 (double) from the master dose d, plus
+// F = F_const + sum f_j; the last block stores F in ms->F.
+template <class T>
+__global__ void __launch_bounds__(BLOCK) k_objective_int(const double* __restrict__ d,
+                                                         const uint8_t* __restrict__ cls, int64_t Vpad,
+                                                         const ObjClass* __restrict__ classes,
+                                                         T* __restrict__ u, double* __restrict__ u64,
+                                                         Rec* parts, MasterState* ms) {
+    Rec r = rec_identity();
+    for (int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x; i < Vpad;
+         i += int64_t(gridDim.x) * BLOCK) {
+        const ObjClass c = classes[cls[i]];
+        const double z = d[i];
+        const double gz = grad_f(c, z);
+        u[i] = T(gz);
+        if (u64) u64[i] = gz;
+        r.s5 += obj_f(c, z);
+    }
+    Rec tot;
+    Rec mine = block_reduce(r);
+    if (arrive_and_reduce(mine, parts, &ms->counter, &tot) && threadIdx.x == 0)
+        ms->F = ms->F_const + tot.s5;
+}
+
+// g_i = sum over beamlet i's entries of val * u[row]; one block per beamlet.
+// GATED (the master's copy): runs only in PH_TP of an unfinished master
+// state and moves it to PH_DIR.
+template <class T, class UT, class Acc, class GT, bool GATED>
+__global__ void __launch_bounds__(BLOCK) k_gradT(const int32_t* __restrict__ cptr,
+                                                 const int32_t* __restrict__ crow,
+                                                 const T* __restrict__ cval, const UT* __restrict__ u,
+                                                 GT* __restrict__ g, MasterState* gate) {
+    if (GATED) {
+        __shared__ int s_skip;
+        if (threadIdx.x == 0) s_skip = (gate->done || gate->phase != PH_TP);
+        __syncthreads();
+        if (s_skip) return;
+    }
+    const int i = blockIdx.x;
+    const int e0 = cptr[i], e1 = cptr[i + 1];
+    Acc acc = Acc(0);
+    int e = e0 + threadIdx.x;
+    for (; e + 3 * BLOCK < e1; e += 4 * BLOCK) {
+        const int32_t r0 = crow[e], r1 = crow[e + BLOCK], r2 = crow[e + 2 * BLOCK], r3 = crow[e + 3 * BLOCK];
+        const T v0 = cval[e], v1 = cval[e + BLOCK], v2 = cval[e + 2 * BLOCK], v3 = cval[e + 3 * BLOCK];
+        acc += Acc(v0) * Acc(u[r0]);
+        acc += Acc(v1) * Acc(u[r1]);
+        acc += Acc(v2) * Acc(u[r2]);
+        acc += Acc(v3) * Acc(u[r3]);
+    }
+    for (; e < e1; e += BLOCK) acc += Acc(cval[e]) * Acc(u[crow[e]]);
+    acc = wave_sum(acc);
+    __shared__ Acc s_w[BLOCK / WAVE];
+    if ((threadIdx.x % WAVE) == 0) s_w[threadIdx.x / WAVE] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Acc t = Acc(0);
+        for (int w = 0; w < BLOCK / WAVE; ++w) t += s_w[w];
+        g[i] = GT(t);
+    }
+    if (GATED) {
+        __shared__ int s_last;
+        if (threadIdx.x == 0) {
+            __threadfence();
+            const uint32_t prev = atomicAdd(&gate->counter, 1u);
+            s_last = (prev == gridDim.x - 1);
+            if (s_last) {
+                gate->counter = 0u;
+                gate->phase = PH_DIR;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pricing: one wavefront per MLC row, last block picks the beam
+// ---------------------------------------------------------------------------
+struct RowRec {
+    double v;        // best value (0 when closed)
+    double second;   // best value among all other candidates
+    int32_t L, R;
+};
+
+struct PriceGeom {
+    const int32_t* row_start;
+    const int32_t* row_len;
+    const int32_t* beam_row0;
+    int32_t R, B;
+};
+
+__global__ void __launch_bounds__(BLOCK) k_price(PriceGeom G, const double* __restrict__ g,
+                                                 RowRec* __restrict__ rows, PriceResult* res) {
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int r = blockIdx.x * (BLOCK / WAVE) + wave;
+    if (r < G.R) {
+        const int n = G.row_len[r];
+        const double w = lane < n ? g[G.row_start[r] + lane] : 0.0;
+        // inclusive prefix sum: lane i holds S_{i+1} = w_0 + ... + w_i
+        double S1 = w;
+#pragma unroll
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const double o = __shfl_up(S1, off, WAVE);
+            if (lane >= off) S1 += o;
+        }
+        // exclusive: lane i holds S_i (S_0 = 0)
+        double S0 = __shfl_up(S1, 1, WAVE);
+        if (lane == 0) S0 = 0.0;
+        // running maximum of S_0..S_i with the earliest index on ties
+        double M = S0;
+        int Mi = lane;
+#pragma unroll
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const double om = __shfl_up(M, off, WAVE);
+            const int oi = __shfl_up(Mi, off, WAVE);
+            if (lane >= off && !(M > om)) {
+                M = om;
+                Mi = oi;
+            }
+        }
+        // best interval ending at right end i+1
+        const bool valid = lane < n;
+        const double c = valid ? S1 - M : INFINITY;
+        // argmin over right ends, smallest right end on ties
+        double bc = c;
+        int bi = lane;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double oc = __shfl_xor(bc, off, WAVE);
+            const int oi = __shfl_xor(bi, off, WAVE);
+            if (oc < bc || (oc == bc && oi < bi)) {
+                bc = oc;
+                bi = oi;
+            }
+        }
+        const bool open = bc < 0.0;
+        const int Lb = __shfl(Mi, bi, WAVE);
+        const int Rb = bi + 1;
+        double second;
+        if (!open) {
+            second = wave_min(c);                 // every interval is a candidate
+        } else {
+            const double other_r = wave_min(lane == bi ? INFINITY : c);
+            // runner-up left end for right end Rb: max S_l, l < Rb, l != Lb
+            const double Sl = (lane < Rb && lane != Lb) ? S0 : -INFINITY;
+            const double m2 = wave_max(Sl);
+            const double SR = __shfl(S1, bi, WAVE);
+            const double same_r = (m2 == -INFINITY) ? INFINITY : SR - m2;
+            second = fmin(0.0, fmin(other_r, same_r));
+        }
+        if (lane == 0) {
+            RowRec rr;
+            rr.v = open ? bc : 0.0;
+            rr.second = second;
+            rr.L = open ? Lb : 0;
+            rr.R = open ? Rb : 0;
+            rows[r] = rr;
+        }
+    }
+    // last block: per-beam sums, argmin, gap
+    __shared__ int s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t prev = atomicAdd(&res->counter, 1u);
+        s_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if (threadIdx.x == 0) {
+        int best = -1;
+        double bv = INFINITY, sv = INFINITY;
+        for (int b = 0; b < G.B; ++b) {
+            double s = 0.0;
+            for (int rr = G.beam_row0[b]; rr < G.beam_row0[b + 1]; ++rr) s += rows[rr].v;
+            if (best < 0 || s < bv) {
+                sv = bv;
+                bv = s;
+                best = b;
+            } else if (s < sv) {
+                sv = s;
+            }
+        }
+        double gap = sv - bv;
+        const int r0 = G.beam_row0[best], r1 = G.beam_row0[best + 1];
+        for (int rr = r0; rr < r1; ++rr) {
+            const RowRec x = rows[rr];
+            gap = fmin(gap, x.second - x.v);
+            res->leaves[2 * (rr - r0)] = int16_t(x.L);
+            res->leaves[2 * (rr - r0) + 1] = int16_t(x.R);
+        }
+        res->beam = best;
+        res->n_rows = r1 - r0;
+        res->rc = bv;
+        res->gap = gap;
+        res->counter = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// gradient projection master (device-resident state machine)
+// ---------------------------------------------------------------------------
+struct PoolView {
+    const int32_t* ap_beam;      // [Kmax]
+    const int16_t* ap_lv;        // [Kmax * maxRB * 2]
+    int32_t maxRB;
+    const int32_t* blt_beam;     // [N]
+    const int32_t* blt_row;      // [N]
+    const int32_t* blt_pos;      // [N]
+    const int32_t* beam_row0;    // [B + 1]
+    const int32_t* row_start;    // [R]
+    int32_t N;
+};
+
+// sum over the pool of v_k for apertures that open beamlet i (eq. 7), in
+// pool order
+__device__ __forceinline__ double pool_at_beamlet(const PoolView& P, int K, const double* v, int i) {
+    const int b = P.blt_beam[i];
+    const int lr = P.blt_row[i] - P.beam_row0[b];
+    const int pos = P.blt_pos[i];
+    double acc = 0.0;
+    for (int k = 0; k < K; ++k) {
+        if (P.ap_beam[k] != b) continue;
+        const int16_t* lv = P.ap_lv + (size_t(k) * P.maxRB + lr) * 2;
+        if (pos >= lv[0] && pos < lv[1]) acc += v[k];
+    }
+    return acc;
+}
+
+// x = A v for all beamlets (block-strided), stored as XT
+template <class XT>
+__device__ __forceinline__ void pool_to_beamlets(const PoolView& P, int K, const double* v, XT* x) {
+    for (int i = threadIdx.x; i < P.N; i += blockDim.x) x[i] = XT(pool_at_beamlet(P, K, v, i));
+}
+
+// Direction step (single block of 1024 threads): grad_y = A^T g, KKT test,
+// projected direction p, longest feasible step t_max, dx = A p.
+template <class T>
+__global__ void __launch_bounds__(1024) k_dir(PoolView P, const T* __restrict__ g,
+                                              double* __restrict__ y, double* __restrict__ p,
+                                              double* __restrict__ grad, T* __restrict__ dx,
+                                              MasterState* ms) {
+    __shared__ int s_skip, s_go;
+    __shared__ double s_grad[MAX_APERTURES];
+    __shared__ double s_p[MAX_APERTURES];
+    if (threadIdx.x == 0) s_skip = (ms->done || ms->phase != PH_DIR);
+    __syncthreads();
+    if (s_skip) return;
+    const int K = ms->K;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int nw = blockDim.x / WAVE;
+    for (int k = wave; k < K; k += nw) {
+        const int b = P.ap_beam[k];
+        const int r0 = P.beam_row0[b], nr = P.beam_row0[b + 1] - r0;
+        double acc = 0.0;
+        for (int lr = lane; lr < nr; lr += WAVE) {
+            const int16_t* lv = P.ap_lv + (size_t(k) * P.maxRB + lr) * 2;
+            const int base = P.row_start[r0 + lr];
+            double s = 0.0;
+            for (int pos = lv[0]; pos < lv[1]; ++pos) s += double(g[base + pos]);
+            acc += s;
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) s_grad[k] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double kkt = 0.0;
+        for (int k = 0; k < K; ++k) kkt = fmax(kkt, fabs(fmin(y[k], s_grad[k])));
+        ms->kkt = kkt;
+        int go = 1;
+        if (!(kkt > ms->tol)) {
+            ms->stop_reason = 1;
+            go = 0;
+        } else if (ms->steps >= ms->max_steps) {
+            ms->stop_reason = 2;
+            go = 0;
+        }
+        double tmax = INFINITY, gp = 0.0;
+        int any = 0;
+        if (go) {
+            for (int k = 0; k < K; ++k) {
+                double pk = -s_grad[k];
+                if (y[k] == 0.0 && s_grad[k] >= 0.0) pk = 0.0;
+                p[k] = pk;
+                s_p[k] = pk;
+                grad[k] = s_grad[k];
+                if (pk != 0.0) any = 1;
+                if (pk < 0.0) tmax = fmin(tmax, y[k] / (-pk));
+                gp += s_grad[k] * pk;
+            }
+            if (!any) {
+                ms->stop_reason = 3;
+                go = 0;
+            }
+        }
+        if (!go) {
+            ms->done = 1;
+        } else {
+            ms->t_max = tmax;
+            ms->gphi0 = gp;
+            ms->t = 0.0;
+            ms->lo = 0.0;
+            ms->hi = tmax;
+            ms->hi_known = 0;
+            ms->ls_iter = 0;
+        }
+        s_go = go;
+    }
+    __syncthreads();
+    if (!s_go) return;
+    pool_to_beamlets<T>(P, K, s_p, dx);
+    __syncthreads();
+    if (threadIdx.x == 0) ms->phase = PH_Q;
+}
+
+// Line-search decision after an evaluation at ms->t (thread 0 of the last
+// block).  Returns 1 when the step is final (ms->t holds it), 0 when ms->t
+// holds the next trial point.
+__device__ __forceinline__ int ls_decide(MasterState* ms, const Rec& e) {
+    const double t = ms->t, tmax = ms->t_max;
+    const double gphi = e.s0, s_r = 2.0 * e.s1, s_l = 2.0 * e.s2, nb = e.mn, pb = e.mx;
+    ms->ls_iter += 1;
+    ms->total_ls += 1;
+    int fin = 0;
+    double tf = 0.0, nxt = 0.0;
+    if (gphi == 0.0) {
+        fin = 1;
+        tf = t;
+    } else if (gphi < 0.0) {
+        if (t >= tmax) {
+            fin = 1;
+            tf = tmax;
+        } else {
+            ms->lo = t;
+            const double tn = s_r > 0.0 ? t - gphi / s_r : INFINITY;
+            if (tn <= nb) {
+                fin = 1;
+                tf = fmin(tn, tmax);
+            } else if (nb >= tmax) {
+                fin = 1;
+                tf = tmax;
+            } else {
+                if (tn < ms->hi)
+                    nxt = tn;
+                else if (!ms->hi_known)
+                    nxt = ms->hi;
+                else
+                    nxt = 0.5 * (ms->lo + ms->hi);
+                if (isinf(nxt)) nxt = nb;
+            }
+        }
+    } else {
+        ms->hi = t;
+        ms->hi_known = 1;
+        const double tn = s_l > 0.0 ? t - gphi / s_l : -INFINITY;
+        if (tn >= pb) {
+            fin = 1;
+            tf = fmax(tn, ms->lo);
+        } else {
+            nxt = tn > ms->lo ? tn : 0.5 * (ms->lo + ms->hi);
+        }
+    }
+    if (!fin && ms->ls_iter >= LS_MAX_ITER) {
+        fin = 1;
+        tf = ms->lo;
+    }
+    ms->t = fin ? tf : nxt;
+    return fin;
+}
+
+// Final step of a line search (all threads of the last block): y update with
+// exact zeros for blocking apertures, step count, refresh of x = A y.
+__device__ __forceinline__ void finish_step(const PoolView& P, MasterState* ms, double* y,
+                                            const double* p, double* x64, int fin) {
+    __shared__ int s_refresh;
+    __shared__ double s_y[MAX_APERTURES];
+    if (!fin) return;
+    const int K = ms->K;
+    const double t = ms->t, tmax = ms->t_max;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        const double pk = p[k];
+        const double ratio = pk < 0.0 ? y[k] / (-pk) : INFINITY;
+        double yn = y[k] + t * pk;
+        if (t == tmax && ratio == t) yn = 0.0;
+        yn = fmax(yn, 0.0);
+        y[k] = yn;
+        s_y[k] = yn;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ms->steps += 1;
+        ms->total_steps += 1;
+        ms->last_step = t;
+        ms->refresh = (ms->steps % ms->refresh_every) == 0;
+        s_refresh = ms->refresh;
+    }
+    __syncthreads();
+    if (s_refresh) pool_to_beamlets<double>(P, K, s_y, x64);
+    __syncthreads();
+    if (threadIdx.x == 0) ms->phase = PH_UPD;
+}
+
+// q = D dx and the line-search evaluation at t = 0.
+template <class T>
+__global__ void __launch_bounds__(BLOCK) k_qstep(SellView<T> S, const T* __restrict__ dx, int N,
+                                                 bool stage, const double* __restrict__ d,
+                                                 const uint8_t* __restrict__ cls,
+                                                 const ObjClass* __restrict__ classes, int ncls,
+                                                 T* __restrict__ q, Rec* parts, MasterState* ms,
+                                                 PoolView P, double* y, const double* p,
+                                                 double* x64) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_skip;
+    __shared__ double s_t;
+    if (threadIdx.x == 0) {
+        s_skip = (ms->done || ms->phase != PH_Q);
+        s_t = ms->t;
+    }
+    __syncthreads();
+    if (s_skip) return;
+    ObjClass* cl = reinterpret_cast<ObjClass*>(smem);
+    for (int i = threadIdx.x; i < ncls; i += blockDim.x) cl[i] = classes[i];
+    T* xs_l = reinterpret_cast<T*>(smem + sizeof(ObjClass) * ncls);
+    __syncthreads();
+    const T* xs = stage_vec<T, T>(dx, N, xs_l, stage);
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int64_t s0 = int64_t(blockIdx.x) * S.spb;
+    const int64_t s1 = min(S.nslices, s0 + S.spb);
+    Rec r = rec_identity();
+    const double t = s_t;
+    for (int64_t s = s0 + wave; s < s1; s += BLOCK / WAVE) {
+        const T acc = sell_dot<T, T, T>(S.val, S.col, S.slice_ptr[s], S.slice_w[s], lane, xs);
+        const int64_t row = s * SLICE + lane;
+        q[row] = acc;
+        ls_voxel(cl[cls[row]], d[row], double(acc), t, r);
+    }
+    Rec tot;
+    Rec mine = block_reduce(r);
+    if (!arrive_and_reduce(mine, parts, &ms->counter, &tot)) return;
+    __shared__ int s_fin;
+    if (threadIdx.x == 0) {
+        s_fin = ls_decide(ms, tot);
+        if (!s_fin) ms->phase = PH_LS;
+    }
+    __syncthreads();
+    finish_step(P, ms, y, p, x64, s_fin);
+}
+
+// Further line-search evaluations at ms->t.
+__global__ void __launch_bounds__(BLOCK) k_lseval(const double* __restrict__ d, const void* qv,
+                                                  int q_is_f64, const uint8_t* __restrict__ cls,
+                                                  int64_t Vpad, const ObjClass* __restrict__ classes,
+                                                  int ncls, Rec* parts, MasterState* ms, PoolView P,
+                                                  double* y, const double* p, double* x64) {
+    __shared__ int s_skip;
+    __shared__ double s_t;
+    __shared__ ObjClass cl[256];
+    if (threadIdx.x == 0) {
+        s_skip = (ms->done || ms->phase != PH_LS);
+        s_t = ms->t;
+    }
+    __syncthreads();
+    if (s_skip) return;
+    for (int i = threadIdx.x; i < ncls; i += blockDim.x) cl[i] = classes[i];
+    __syncthreads();
+    const double t = s_t;
+    Rec r = rec_identity();
+    if (q_is_f64) {
+        const double* q = static_cast<const double*>(qv);
+        for (int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x; i < Vpad; i += int64_t(gridDim.x) * BLOCK)
+            ls_voxel(cl[cls[i]], d[i], q[i], t, r);
+    } else {
+        const float* q = static_cast<const float*>(qv);
+        for (int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x; i < Vpad; i += int64_t(gridDim.x) * BLOCK)
+            ls_voxel(cl[cls[i]], d[i], double(q[i]), t, r);
+    }
+    Rec tot;
+    Rec mine = block_reduce(r);
+    if (!arrive_and_reduce(mine, parts, &ms->counter, &tot)) return;
+    __shared__ int s_fin;
+    if (threadIdx.x == 0) s_fin = ls_decide(ms, tot);
+    __syncthreads();
+    finish_step(P, ms, y, p, x64, s_fin);
+}
+
+// Update: d += t q (or d = D x64 on refresh steps), u = grad F(d), F.
+template <class T>
+__global__ void __launch_bounds__(BLOCK) k_update(SellView<T> S, const double* __restrict__ x64, int N,
+                                                  bool stage, double* __restrict__ d,
+                                                  const T* __restrict__ q,
+                                                  const uint8_t* __restrict__ cls,
+                                                  const ObjClass* __restrict__ classes, int ncls,
+                                                  T* __restrict__ u, Rec* parts, MasterState* ms) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_skip, s_refresh;
+    __shared__ double s_t;
+    if (threadIdx.x == 0) {
+        s_skip = (ms->done || ms->phase != PH_UPD);
+        s_refresh = ms->refresh;
+        s_t = ms->t;
+    }
+    __syncthreads();
+    if (s_skip) return;
+    ObjClass* cl = reinterpret_cast<ObjClass*>(smem);
+    for (int i = threadIdx.x; i < ncls; i += blockDim.x) cl[i] = classes[i];
+    double* xs_l = reinterpret_cast<double*>(smem + sizeof(ObjClass) * ncls);
+    __syncthreads();
+    const double* xs = s_refresh ? stage_vec<double, double>(x64, N, xs_l, stage) : nullptr;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int64_t s0 = int64_t(blockIdx.x) * S.spb;
+    const int64_t s1 = min(S.nslices, s0 + S.spb);
+    const double t = s_t;
+    Rec r = rec_identity();
+    for (int64_t s = s0 + wave; s < s1; s += BLOCK / WAVE) {
+        const int64_t row = s * SLICE + lane;
+        double dn;
+        if (s_refresh)
+            dn = sell_dot<T, double, double>(S.val, S.col, S.slice_ptr[s], S.slice_w[s], lane, xs);
+        else
+            dn = d[row] + t * double(q[row]);
+        d[row] = dn;
+        const ObjClass c = cl[cls[row]];
+        u[row] = T(grad_f(c, dn));
+        r.s5 += obj_f(c, dn);
+    }
+    Rec tot;
+    Rec mine = block_reduce(r);
+    if (!arrive_and_reduce(mine, parts, &ms->counter, &tot)) return;
+    if (threadIdx.x == 0) {
+        ms->F = ms->F_const + tot.s5;
+        ms->refresh = 0;
+        ms->phase = PH_TP;
+    }
+}
+
+// Reset the master state machine for a new solve over a pool of K.
+__global__ void k_master_init(MasterState* ms, int K, double tol, int max_steps) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ms->phase = PH_DIR;
+        ms->done = 0;
+        ms->steps = 0;
+        ms->max_steps = max_steps;
+        ms->K = K;
+        ms->tol = tol;
+        ms->stop_reason = 0;
+        ms->ls_iter = 0;
+        ms->refresh = 0;
+        ms->counter = 0u;
+    }
+}
+
+// Append the last pricing result to the pool as aperture k with y_k = 0.
+__global__ void k_add_from_price(const PriceResult* res, int k, int maxRB, int32_t* ap_beam,
+                                 int16_t* ap_lv, double* y) {
+    const int n = res->n_rows;
+    for (int i = threadIdx.x; i < maxRB; i += blockDim.x) {
+        ap_lv[(size_t(k) * maxRB + i) * 2] = i < n ? res->leaves[2 * i] : int16_t(0);
+        ap_lv[(size_t(k) * maxRB + i) * 2 + 1] = i < n ? res->leaves[2 * i + 1] : int16_t(0);
+    }
+    if (threadIdx.x == 0) {
+        ap_beam[k] = res->beam;
+        y[k] = 0.0;
+    }
+}
+
+}  // namespace dao

@@ -1,0 +1,235 @@
+// Host-side validation and layout construction (see layout.h).
+#include "layout.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <sstream>
+
+namespace dao {
+
+namespace {
+
+constexpr int64_t SORT_WINDOW = 1024;   // rows sorted by length within windows of this size
+
+template <class... A>
+std::string cat(A&&... a) {
+    std::ostringstream s;
+    (s << ... << a);
+    return s.str();
+}
+
+}  // namespace
+
+dao_status validate_inputs(const dao_matrix* D, const dao_beams* beams,
+                           const dao_structures* structs, const dao_prescription* presc,
+                           const dao_options* opt, std::string* err) {
+    auto fail = [&](std::string m) { *err = std::move(m); return DAO_EINVAL; };
+    if (!D || !beams || !structs || !opt || !err) return fail("null argument");
+    if (D->n_vox <= 0 || D->n_blt <= 0 || D->nnz < 0) return fail("n_vox and n_blt must be positive, nnz >= 0");
+    if (D->n_blt > 65535) return fail("n_blt above 65535 is not supported (16-bit column indices)");
+    if (D->nnz >= (int64_t(1) << 31)) return fail("nnz must be below 2^31");
+    if (D->n_vox >= (int64_t(1) << 31)) return fail("n_vox must be below 2^31");
+    if (!D->row_ptr || (D->nnz > 0 && (!D->col || !D->val))) return fail("null CSR array");
+    if (opt->dtype != DAO_F64 && opt->dtype != DAO_F32) return fail("dtype must be DAO_F64 or DAO_F32");
+    if (opt->max_apertures < 1 || opt->max_apertures > MAX_APERTURES) return fail("max_apertures must be in [1, 256]");
+    if (!(opt->eps > 0) || !std::isfinite(opt->eps)) return fail("eps must be positive");
+    if (opt->max_steps < 1) return fail("max_steps must be >= 1");
+    if (!(opt->tau_rel >= 0) || !std::isfinite(opt->tau_rel)) return fail("tau_rel must be >= 0");
+    if (opt->max_tighten < 0) return fail("max_tighten must be >= 0");
+    if (opt->refresh_every < 1) return fail("refresh_every must be >= 1");
+    if (opt->ls_slots < 1 || opt->ls_slots > 16) return fail("ls_slots must be in [1, 16]");
+    if (opt->mem_cap_bytes < 0) return fail("mem_cap_bytes must be >= 0");
+
+    const int64_t* rp = D->row_ptr;
+    if (rp[0] != 0) return fail("row_ptr[0] must be 0");
+    for (int64_t r = 0; r < D->n_vox; ++r) {
+        if (rp[r + 1] < rp[r]) return fail(cat("row_ptr decreases at row ", r));
+    }
+    if (rp[D->n_vox] != D->nnz) return fail("row_ptr[n_vox] must equal nnz");
+    for (int64_t r = 0; r < D->n_vox; ++r) {
+        int32_t prev = -1;
+        for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+            int32_t c = D->col[e];
+            if (c < 0 || c >= D->n_blt) return fail(cat("column index out of range at entry ", e));
+            if (c <= prev) return fail(cat("columns not strictly increasing in row ", r));
+            prev = c;
+            double v = D->val[e];
+            if (!std::isfinite(v) || v < 0) return fail(cat("non-finite or negative value at entry ", e));
+        }
+    }
+
+    if (beams->n_beams < 1 || !beams->rows_per_beam || !beams->row_len) return fail("beams: empty or null");
+    int64_t R = 0;
+    for (int b = 0; b < beams->n_beams; ++b) {
+        if (beams->rows_per_beam[b] < 1 || beams->rows_per_beam[b] > 1024)
+            return fail(cat("rows_per_beam[", b, "] must be in [1, 1024]"));
+        R += beams->rows_per_beam[b];
+    }
+    int64_t Nsum = 0;
+    for (int64_t r = 0; r < R; ++r) {
+        if (beams->row_len[r] < 1 || beams->row_len[r] > MAX_ROW_LEN)
+            return fail(cat("row_len[", r, "] must be in [1, 64]"));
+        Nsum += beams->row_len[r];
+    }
+    if (Nsum != D->n_blt) return fail("sum of row_len must equal n_blt");
+
+    if (structs->n_struct < 0 || structs->n_struct > 255) return fail("n_struct must be in [0, 255]");
+    if (structs->n_struct > 0 && !presc) return fail("null prescriptions");
+    if (!structs->vox_struct) return fail("null vox_struct");
+    for (int64_t j = 0; j < D->n_vox; ++j) {
+        int s = structs->vox_struct[j];
+        if (s < -1 || s >= structs->n_struct) return fail(cat("structure id out of range at voxel ", j));
+    }
+    for (int s = 0; s < structs->n_struct; ++s) {
+        const dao_prescription& p = presc[s];
+        if (!std::isfinite(p.t_under) || !std::isfinite(p.t_over) || !std::isfinite(p.w_under) ||
+            !std::isfinite(p.w_over))
+            return fail(cat("non-finite prescription for structure ", s));
+        if (p.w_under < 0 || p.w_over < 0) return fail(cat("negative weight for structure ", s));
+        if (p.is_target && p.t_under > p.t_over) return fail(cat("target ", s, " has t_under > t_over"));
+    }
+    return DAO_OK;
+}
+
+void build_layout(const dao_matrix* D, const dao_beams* beams, const dao_structures* structs,
+                  const dao_prescription* presc, HostLayout* L) {
+    const int64_t V = D->n_vox, N = D->n_blt;
+    const int64_t* rp = D->row_ptr;
+    L->V = V;
+    L->N = N;
+    L->nnz = D->nnz;
+    L->n_struct = structs->n_struct;
+
+    // --- objective classes (eq. 9 and eq. 10) ------------------------------
+    std::vector<int64_t> size(structs->n_struct, 0);
+    for (int64_t j = 0; j < V; ++j)
+        if (structs->vox_struct[j] >= 0) size[structs->vox_struct[j]]++;
+    L->classes.assign(structs->n_struct + 1, ObjClass{0, 0, 0, 0});
+    for (int s = 0; s < structs->n_struct; ++s) {
+        if (size[s] == 0) continue;
+        const dao_prescription& p = presc[s];
+        ObjClass c{0, 0, 0, 0};
+        if (p.is_target) {
+            c.a = p.w_under / double(size[s]);
+            c.t_under = p.t_under;
+        }
+        c.b = p.w_over / double(size[s]);
+        c.t_over = p.t_over;
+        L->classes[s] = c;
+    }
+    const uint8_t none = uint8_t(structs->n_struct);
+    L->cls_ext.resize(V);
+    for (int64_t j = 0; j < V; ++j)
+        L->cls_ext[j] = structs->vox_struct[j] < 0 ? none : uint8_t(structs->vox_struct[j]);
+
+    // --- internal row order: non-empty rows, sorted by length (descending)
+    //     inside windows so that slices carry little padding ---------------
+    std::vector<int32_t> rows;
+    rows.reserve(V);
+    for (int64_t j = 0; j < V; ++j)
+        if (rp[j + 1] > rp[j]) rows.push_back(int32_t(j));
+    L->Vnz = int64_t(rows.size());
+    for (size_t w0 = 0; w0 < rows.size(); w0 += SORT_WINDOW) {
+        size_t w1 = std::min(rows.size(), w0 + size_t(SORT_WINDOW));
+        std::stable_sort(rows.begin() + w0, rows.begin() + w1, [&](int32_t a, int32_t b) {
+            return (rp[a + 1] - rp[a]) > (rp[b + 1] - rp[b]);
+        });
+    }
+    L->nslices = (L->Vnz + SLICE - 1) / SLICE;
+    L->Vpad = L->nslices * SLICE;
+    L->perm.assign(L->Vpad, -1);
+    std::copy(rows.begin(), rows.end(), L->perm.begin());
+    std::vector<int32_t> inv(V, -1);
+    for (int64_t r = 0; r < L->Vnz; ++r) inv[L->perm[r]] = int32_t(r);
+
+    L->cls_int.assign(L->Vpad, none);
+    for (int64_t r = 0; r < L->Vnz; ++r) L->cls_int[r] = L->cls_ext[L->perm[r]];
+
+    // objective of voxels that no beamlet reaches (their dose is always 0)
+    {
+        double acc = 0.0;
+        for (int64_t j = 0; j < V; ++j) {
+            if (rp[j + 1] > rp[j]) continue;
+            const ObjClass& c = L->classes[L->cls_ext[j]];
+            double un = std::max(0.0, c.t_under);
+            double ov = std::max(0.0, -c.t_over);
+            acc += c.a * un * un + c.b * ov * ov;
+        }
+        L->F_const = acc;
+    }
+
+    // --- sliced ELL ------------------------------------------------------
+    L->slice_ptr.assign(L->nslices + 1, 0);
+    L->slice_w.assign(L->nslices, 0);
+    for (int64_t s = 0; s < L->nslices; ++s) {
+        int64_t w = 0;
+        for (int l = 0; l < SLICE; ++l) {
+            int32_t j = L->perm[s * SLICE + l];
+            if (j >= 0) w = std::max<int64_t>(w, rp[j + 1] - rp[j]);
+        }
+        L->slice_w[s] = int32_t(w);
+        L->slice_ptr[s + 1] = L->slice_ptr[s] + uint32_t(w * SLICE);
+    }
+    const uint32_t total = L->slice_ptr[L->nslices];
+    L->sell_col.assign(total, 0);
+    L->sell_val.assign(total, 0.0);
+    for (int64_t s = 0; s < L->nslices; ++s) {
+        for (int l = 0; l < SLICE; ++l) {
+            int32_t j = L->perm[s * SLICE + l];
+            if (j < 0) continue;
+            int64_t len = rp[j + 1] - rp[j];
+            for (int64_t k = 0; k < len; ++k) {
+                uint32_t e = L->slice_ptr[s] + uint32_t(k * SLICE + l);
+                L->sell_col[e] = uint16_t(D->col[rp[j] + k]);
+                L->sell_val[e] = D->val[rp[j] + k];
+            }
+        }
+    }
+
+    // --- beamlet-major copy over internal row numbers ----------------------
+    L->csc_ptr.assign(N + 1, 0);
+    for (int64_t e = 0; e < D->nnz; ++e) L->csc_ptr[D->col[e] + 1]++;
+    for (int64_t i = 0; i < N; ++i) L->csc_ptr[i + 1] += L->csc_ptr[i];
+    L->csc_row.assign(D->nnz, 0);
+    L->csc_val.assign(D->nnz, 0.0);
+    {
+        std::vector<int32_t> fill(L->csc_ptr.begin(), L->csc_ptr.end() - 1);
+        for (int64_t r = 0; r < L->Vnz; ++r) {          // internal order: rows ascending
+            int32_t j = L->perm[r];
+            for (int64_t e = rp[j]; e < rp[j + 1]; ++e) {
+                int32_t c = D->col[e];
+                L->csc_row[fill[c]] = int32_t(r);
+                L->csc_val[fill[c]] = D->val[e];
+                fill[c]++;
+            }
+        }
+    }
+
+    // --- MLC geometry -----------------------------------------------------
+    L->B = beams->n_beams;
+    L->beam_row0.assign(L->B + 1, 0);
+    for (int b = 0; b < L->B; ++b) {
+        L->beam_row0[b + 1] = L->beam_row0[b] + beams->rows_per_beam[b];
+        L->max_rows_per_beam = std::max(L->max_rows_per_beam, beams->rows_per_beam[b]);
+    }
+    L->R = L->beam_row0[L->B];
+    L->row_start.assign(L->R, 0);
+    L->row_len.assign(beams->row_len, beams->row_len + L->R);
+    L->blt_beam.assign(N, 0);
+    L->blt_row.assign(N, 0);
+    L->blt_pos.assign(N, 0);
+    int32_t i = 0;
+    for (int b = 0; b < L->B; ++b) {
+        for (int r = L->beam_row0[b]; r < L->beam_row0[b + 1]; ++r) {
+            L->row_start[r] = i;
+            for (int p = 0; p < L->row_len[r]; ++p, ++i) {
+                L->blt_beam[i] = b;
+                L->blt_row[i] = r;
+                L->blt_pos[i] = p;
+            }
+        }
+    }
+}
+
+}  // namespace dao

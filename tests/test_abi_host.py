@@ -1,0 +1,84 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+* libdao.so loads and exports every function include/dao.h declares, and the
+  binding declares exactly those;
+* dao_create rejects every malformed input with DAO_EINVAL before any device
+  call, and an over-cap footprint with DAO_ENOMEM.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1003_5402_amd as dao
+from conftest import ROOT, cached_phantom
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dao.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dao_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = dao.load_library()
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    assert names == dao.symbols()
+
+
+def test_library_links_hip_runtime():
+    # the product path is the HIP library itself: no Python fallback exists
+    import subprocess
+    out = subprocess.run(["ldd", dao.binding.LIB_PATH], capture_output=True, text=True).stdout
+    assert "amdhip64" in out
+
+
+def _args(ph):
+    return dict(row_ptr=ph.row_ptr.copy(), col=ph.col.copy(), val=ph.val.copy(), n_blt=ph.n_blt,
+                rows_per_beam=ph.rows_per_beam.copy(), row_len=ph.row_len.copy(),
+                vox_struct=ph.vox_struct.copy(), prescriptions=[dict(p) for p in ph.prescriptions])
+
+
+def _expect(status, **kw):
+    with pytest.raises(dao.DaoError) as e:
+        a = kw.pop("_a")
+        opts = kw.pop("_opts", {})
+        dao.DaoContext(**a, **opts)
+    assert e.value.status == status, str(e.value)
+    return str(e.value)
+
+
+def test_create_rejects_malformed_inputs():
+    ph = cached_phantom("mini")
+    cases = []
+    a = _args(ph); a["row_ptr"][10] = a["row_ptr"][9] - 1; cases.append(("decreases", a))
+    a = _args(ph); a["col"][3] = ph.n_blt; cases.append(("out of range", a))
+    r = int(np.flatnonzero(np.diff(ph.row_ptr) >= 2)[0])
+    a = _args(ph); e = a["row_ptr"][r]; a["col"][e + 1] = a["col"][e]
+    cases.append(("strictly increasing", a))
+    a = _args(ph); a["val"][7] = np.nan; cases.append(("non-finite", a))
+    a = _args(ph); a["val"][7] = -1.0; cases.append(("negative value", a))
+    a = _args(ph); a["row_len"][0] += 1; cases.append(("sum of row_len", a))
+    a = _args(ph); a["row_len"][0] = 65; a["row_len"][1] -= 61; cases.append(("row_len", a))
+    a = _args(ph); a["vox_struct"][4] = len(ph.prescriptions); cases.append(("structure id", a))
+    a = _args(ph); a["prescriptions"][1]["w_over"] = -0.5; cases.append(("negative weight", a))
+    a = _args(ph); a["prescriptions"][0]["t_under"] = 2.0; cases.append(("t_under > t_over", a))
+    a = _args(ph); a["rows_per_beam"][0] = 0; cases.append(("rows_per_beam", a))
+    a = _args(ph); a["n_blt"] = 70000; cases.append(("65535", a))
+    for needle, a in cases:
+        msg = _expect(dao.DAO_EINVAL, _a=a)
+        assert needle in msg, (needle, msg)
+    msg = _expect(dao.DAO_EINVAL, _a=_args(ph), _opts=dict(max_apertures=0))
+    assert "max_apertures" in msg
+    msg = _expect(dao.DAO_EINVAL, _a=_args(ph), _opts=dict(ls_slots=0))
+    assert "ls_slots" in msg
+
+
+def test_create_enforces_memory_cap():
+    ph = cached_phantom("mini")
+    msg = _expect(dao.DAO_ENOMEM, _a=_args(ph), _opts=dict(mem_cap_bytes=10000))
+    assert "exceeds mem_cap_bytes" in msg
