@@ -37,7 +37,7 @@ def contexts():
     out = {}
     yield out
     for c in out.values():
-        c.close()
+        c[2].close()
 
 
 def _get(contexts, name, dtype):
