@@ -372,21 +372,28 @@ struct PriceGeom {
 
 __global__ void __launch_bounds__(BLOCK) k_price(PriceGeom G, const double* __restrict__ g,
                                                  RowRec* __restrict__ rows, PriceResult* res) {
+    // prefix sums of each wave's row, accumulated sequentially so that a
+    // beamlet priced exactly 0 leaves the prefix exactly unchanged (exact
+    // ties such as leading or trailing zero-price beamlets stay ties)
+    __shared__ double s_S[BLOCK / WAVE][WAVE + 1];
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int r = blockIdx.x * (BLOCK / WAVE) + wave;
-    if (r < G.R) {
-        const int n = G.row_len[r];
-        const double w = lane < n ? g[G.row_start[r] + lane] : 0.0;
-        // inclusive prefix sum: lane i holds S_{i+1} = w_0 + ... + w_i
-        double S1 = w;
-#pragma unroll
-        for (int off = 1; off < WAVE; off <<= 1) {
-            const double o = __shfl_up(S1, off, WAVE);
-            if (lane >= off) S1 += o;
+    const bool have = r < G.R;
+    const int n = have ? G.row_len[r] : 0;
+    double* S = s_S[wave];
+    if (lane == 0) {
+        const double* w = have ? g + G.row_start[r] : g;
+        double acc = 0.0;
+        S[0] = 0.0;
+        for (int i = 0; i < WAVE; ++i) {
+            if (i < n) acc += w[i];
+            S[i + 1] = acc;
         }
-        // exclusive: lane i holds S_i (S_0 = 0)
-        double S0 = __shfl_up(S1, 1, WAVE);
-        if (lane == 0) S0 = 0.0;
+    }
+    __syncthreads();
+    if (have) {
+        const double S1 = S[lane + 1];   // S_{i+1} = w_0 + ... + w_i
+        const double S0 = S[lane];       // S_i
         // running maximum of S_0..S_i with the earliest index on ties
         double M = S0;
         int Mi = lane;

@@ -140,3 +140,18 @@ def test_products_are_deterministic(contexts, name, dtype):
     F1 = ctx.gradient(d1, g1)
     F2 = ctx.gradient(d1, g2)
     assert torch.equal(d1, d2) and torch.equal(g1, g2) and F1 == F2
+
+
+@pytest.mark.parametrize("name,dtype", CASES)
+def test_price_own_prices_at_zero_dose(contexts, name, dtype):
+    """Round 1 prices on the GPU's own FP64 prices.  Beamlets that reach no
+    target voxel are priced exactly 0, which makes exact ties between leaf
+    intervals with and without them; the row scan's rule (leading zeros in,
+    trailing zeros out) must resolve them as the oracle does."""
+    ph, P, ctx = _get(contexts, name, dtype)
+    ctx.reset()
+    got = ctx.price_current()
+    w = oracle.prices(P, oracle.grad_objective(P, np.zeros(P.n_vox)))
+    ref = oracle.price(P, w)
+    assert (got["beam"], got["leaves"]) == (ref["aperture"].beam, ref["aperture"].leaves)
+    assert abs(got["rc"] - ref["rc"]) <= 1e-12 * abs(ref["rc"])
