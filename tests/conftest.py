@@ -25,6 +25,14 @@ def cached_phantom(name, seed=0, **kw):
     return _PH_CACHE[key]
 
 
-def oracle_problem(ph):
+def oracle_problem(ph, dtype=None):
+    """Oracle problem on the phantom's data.  With dtype="f32" the dose
+    matrix is first rounded to FP32, which is what an FP32 context stores, so
+    both sides solve the same problem."""
+    import numpy as np
     import oracle
-    return oracle.make_problem(ph.csr(), ph.rows_per_beam, ph.row_len, ph.vox_struct, ph.prescriptions)
+    D = ph.csr()
+    if dtype == "f32":
+        D = D.copy()
+        D.data = D.data.astype(np.float32).astype(np.float64)
+    return oracle.make_problem(D, ph.rows_per_beam, ph.row_len, ph.vox_struct, ph.prescriptions)

@@ -45,7 +45,7 @@ def _get(contexts, name, dtype):
     if key not in contexts:
         ph = cached_phantom(name)
         print(f"[ctx] {name} {dtype}", flush=True)
-        contexts[key] = (ph, oracle_problem(ph), ctx_for(ph, dtype=dtype))
+        contexts[key] = (ph, oracle_problem(ph, dtype), ctx_for(ph, dtype=dtype))
     return contexts[key]
 
 

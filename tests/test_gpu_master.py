@@ -36,7 +36,7 @@ def _oracle_pool(P, n, seed=0):
                                                    ("tiny", "f32", 10, 1e-5)])
 def test_master_steps_parity(name, dtype, steps, tol):
     ph = cached_phantom(name)
-    P = oracle_problem(ph)
+    P = oracle_problem(ph, dtype)
     pool = _oracle_pool(P, 4)
     ctx = ctx_for(ph, dtype=dtype)
     try:
@@ -67,7 +67,7 @@ def test_master_steps_parity(name, dtype, steps, tol):
 def test_master_converged_parity(name, dtype, tol):
     torch = torch_cuda()
     ph = cached_phantom(name)
-    P = oracle_problem(ph)
+    P = oracle_problem(ph, dtype)
     pool = _oracle_pool(P, 5)
     st = MasterState.empty(P)
     for ap in pool:
