@@ -21,7 +21,6 @@ namespace {
 thread_local std::string g_create_error;
 
 constexpr size_t STAGE_LIMIT = 48 * 1024;   // largest vector staged in LDS per block
-constexpr int SLICES_PER_BLOCK = 4;         // one slice per wavefront
 constexpr int ELEM_BLOCKS_MAX = 2048;
 
 struct DevBuf {
@@ -88,8 +87,9 @@ struct dao_ctx {
     PriceResult* pr_h = nullptr;      // pinned
     RowRec* rowrec = nullptr;
     Rec* parts = nullptr;
+    Rec* upd_parts = nullptr;
     int64_t nparts = 0;
-    uint32_t* counter = nullptr;
+    Arrival* arr = nullptr;
     double* scalar = nullptr;
     double* scalar_h = nullptr;       // pinned
     int16_t* lv_stage_h = nullptr;    // pinned
@@ -110,11 +110,14 @@ struct dao_ctx {
     int64_t elem_blocks(int64_t n) const {
         return std::max<int64_t>(1, std::min<int64_t>(ELEM_BLOCKS_MAX, (n + BLOCK - 1) / BLOCK));
     }
-    int64_t slice_blocks() const {
-        return std::max<int64_t>(1, (nslices + SLICES_PER_BLOCK - 1) / SLICES_PER_BLOCK);
-    }
+    int64_t slab_blocks() const { return std::max<int64_t>(1, (nslices + SPB - 1) / SPB); }
+    int64_t price_blocks() const { return std::max<int64_t>(1, (R + BLOCK / WAVE - 1) / (BLOCK / WAVE)); }
     bool stage_x() const { return size_t(N) * tsize <= STAGE_LIMIT; }
     bool stage_x64() const { return size_t(N) * 8 <= STAGE_LIMIT; }
+    size_t dir_lds() const {
+        return ((size_t(N) * tsize + 15) & ~size_t(15)) + size_t(opt.max_apertures) * maxRB * 4;
+    }
+    bool stage_dir() const { return dir_lds() <= STAGE_LIMIT; }
 };
 
 #define HIPCHK(ctx, call)                                                                    \
@@ -169,7 +172,8 @@ int64_t predicted_bytes(const HostLayout& L, size_t ts, int kmax) {
     b += int64_t(L.R) * 8 + (L.B + 1) * 4 + L.N * 12;
     b += L.Vpad * (8 + 3 * ts + 8) + L.N * (ts + 8 + ts + 8);
     b += int64_t(kmax) * (4 + 2 * 2 * L.max_rows_per_beam + 24);
-    b += sizeof(MasterState) + sizeof(PriceResult) + L.R * sizeof(RowRec) + 8 * ELEM_BLOCKS_MAX * sizeof(Rec);
+    b += sizeof(MasterState) + sizeof(PriceResult) + L.R * sizeof(RowRec) + 2 * ELEM_BLOCKS_MAX * sizeof(Rec) +
+         sizeof(Arrival);
     return b;
 }
 
@@ -179,7 +183,7 @@ int64_t predicted_bytes(const HostLayout& L, size_t ts, int kmax) {
 template <class T>
 SellView<T> sell_view(dao_ctx* c) {
     return SellView<T>{c->slice_ptr, c->slice_w, static_cast<const T*>(c->sell_val), c->sell_col,
-                       c->nslices, SLICES_PER_BLOCK};
+                       c->nslices};
 }
 
 PoolView pool_view(dao_ctx* c) {
@@ -192,18 +196,20 @@ dao_status enqueue_cycle(dao_ctx* c) {
     const PoolView P = pool_view(c);
     const SellView<T> S = sell_view<T>(c);
     const size_t cls_b = sizeof(ObjClass) * c->ncls;
-    k_dir<T><<<1, 1024, 0, c->stream>>>(P, static_cast<const T*>(c->g), c->y, c->p, c->gradk,
-                                        static_cast<T*>(c->dx), c->ms);
-    k_qstep<T><<<c->slice_blocks(), BLOCK, cls_b + (c->stage_x() ? c->N * sizeof(T) : 0), c->stream>>>(
-        S, static_cast<const T*>(c->dx), int(c->N), c->stage_x(), c->d, c->cls_int, c->classes, c->ncls,
-        static_cast<T*>(c->q), c->parts, c->ms, P, c->y, c->p, c->x64);
+    const int nupd = int(c->slab_blocks());
+    k_dir<T><<<1, 1024, c->stage_dir() ? c->dir_lds() : 0, c->stream>>>(
+        P, static_cast<const T*>(c->g), c->y, c->p, c->gradk, static_cast<T*>(c->dx), c->ms, c->upd_parts,
+        nupd, c->stage_dir());
+    k_qstep<T><<<c->slab_blocks(), SLAB_THREADS, cls_b + (c->stage_x() ? c->N * sizeof(T) : 0), c->stream>>>(
+        S, c->Vpad, static_cast<const T*>(c->dx), int(c->N), c->stage_x(), c->d, c->cls_int, c->classes,
+        c->ncls, static_cast<T*>(c->q), c->parts, c->arr, c->ms, P, c->y, c->p, c->x64);
     for (int i = 0; i < c->opt.ls_slots; ++i)
         k_lseval<<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
-            c->d, c->q, sizeof(T) == 8, c->cls_int, c->Vpad, c->classes, c->ncls, c->parts, c->ms, P,
+            c->d, c->q, sizeof(T) == 8, c->cls_int, c->Vpad, c->classes, c->ncls, c->parts, c->arr, c->ms, P,
             c->y, c->p, c->x64);
-    k_update<T><<<c->slice_blocks(), BLOCK, cls_b + (c->stage_x64() ? c->N * 8 : 0), c->stream>>>(
-        S, c->x64, int(c->N), c->stage_x64(), c->d, static_cast<const T*>(c->q), c->cls_int, c->classes,
-        c->ncls, static_cast<T*>(c->u), c->parts, c->ms);
+    k_update<T><<<c->slab_blocks(), SLAB_THREADS, cls_b + (c->stage_x64() ? c->N * 8 : 0), c->stream>>>(
+        S, c->Vpad, c->x64, int(c->N), c->stage_x64(), c->d, static_cast<const T*>(c->q), c->cls_int,
+        c->classes, c->ncls, static_cast<T*>(c->u), c->upd_parts, c->ms);
     k_gradT<T, T, T, T, true><<<c->N, BLOCK, 0, c->stream>>>(c->csc_ptr, c->csc_row,
                                                              static_cast<const T*>(c->csc_val),
                                                              static_cast<const T*>(c->u),
@@ -241,7 +247,7 @@ dao_status run_master(dao_ctx* c, double tol, int max_steps) {
 template <class T>
 dao_status refresh_gradient(dao_ctx* c) {
     k_objective_int<T><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
-        c->d, c->cls_int, c->Vpad, c->classes, static_cast<T*>(c->u), c->u64, c->parts, c->ms);
+        c->d, c->cls_int, c->Vpad, c->classes, static_cast<T*>(c->u), c->u64, c->parts, c->arr, c->ms);
     k_gradT<T, T, T, T, false><<<c->N, BLOCK, 0, c->stream>>>(c->csc_ptr, c->csc_row,
                                                               static_cast<const T*>(c->csc_val),
                                                               static_cast<const T*>(c->u),
@@ -256,8 +262,7 @@ PriceGeom price_geom(dao_ctx* c) {
 
 dao_status price_on(dao_ctx* c, const double* g, int32_t* beam, int16_t* leaves, double* rc,
                     double* gap) {
-    const int blocks = (c->R + BLOCK / WAVE - 1) / (BLOCK / WAVE);
-    k_price<<<blocks, BLOCK, 0, c->stream>>>(price_geom(c), g, c->rowrec, c->pr);
+    k_price<<<c->price_blocks(), BLOCK, 0, c->stream>>>(price_geom(c), g, c->rowrec, c->pr, c->arr);
     LAUNCHCHK(c);
     HIPCHK(c, hipMemcpyAsync(c->pr_h, c->pr, sizeof(PriceResult), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -272,7 +277,7 @@ dao_status price_on(dao_ctx* c, const double* g, int32_t* beam, int16_t* leaves,
 template <class T>
 dao_status price_current(dao_ctx* c, int32_t* beam, int16_t* leaves, double* rc, double* gap) {
     k_objective_int<T><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
-        c->d, c->cls_int, c->Vpad, c->classes, static_cast<T*>(c->u), c->u64, c->parts, c->ms);
+        c->d, c->cls_int, c->Vpad, c->classes, static_cast<T*>(c->u), c->u64, c->parts, c->arr, c->ms);
     k_gradT<T, double, double, double, false><<<c->N, BLOCK, 0, c->stream>>>(
         c->csc_ptr, c->csc_row, static_cast<const T*>(c->csc_val), c->u64, c->g64, nullptr);
     LAUNCHCHK(c);
@@ -374,9 +379,10 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     TRY(dev_alloc(c, &c->ms, sizeof(MasterState)));
     TRY(dev_alloc(c, &c->pr, sizeof(PriceResult)));
     TRY(dev_alloc(c, &c->rowrec, std::max<int64_t>(1, c->R) * sizeof(RowRec)));
-    c->nparts = std::max<int64_t>({c->slice_blocks(), c->elem_blocks(c->Vpad), c->elem_blocks(c->V)});
+    c->nparts = std::max<int64_t>({c->slab_blocks(), c->elem_blocks(c->Vpad), c->elem_blocks(c->V)});
     TRY(dev_alloc(c, &c->parts, c->nparts * sizeof(Rec)));
-    TRY(dev_alloc(c, &c->counter, 16));
+    TRY(dev_alloc(c, &c->upd_parts, c->slab_blocks() * sizeof(Rec)));
+    TRY(dev_alloc(c, &c->arr, sizeof(Arrival)));
     TRY(dev_alloc(c, &c->scalar, 16));
 #undef TRY
     HIPCHK(c, hipHostMalloc((void**)&c->ms_h, sizeof(MasterState), hipHostMallocDefault));
@@ -390,7 +396,7 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     HIPCHK(c, hipMemcpyAsync(c->ms, c->ms_h, sizeof(MasterState), hipMemcpyHostToDevice, c->stream));
     std::memset(c->pr_h, 0, sizeof(PriceResult));
     HIPCHK(c, hipMemcpyAsync(c->pr, c->pr_h, sizeof(PriceResult), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemsetAsync(c->counter, 0, 16, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->arr, 0, sizeof(Arrival), c->stream));
     HIPCHK(c, hipMemsetAsync(c->ap_lv, 0, size_t(km) * c->maxRB * 4, c->stream));
     HIPCHK(c, hipMemsetAsync(c->ap_beam, 0, km * 4, c->stream));
     HIPCHK(c, hipMemsetAsync(c->p, 0, km * 8, c->stream));
@@ -405,8 +411,8 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
 template <class T>
 dao_status dose_typed(dao_ctx* c, const void* x, void* d) {
     k_fill<T><<<c->elem_blocks(c->V), BLOCK, 0, c->stream>>>(static_cast<T*>(d), c->V, T(0));
-    k_dose<T><<<c->slice_blocks(), BLOCK, c->stage_x() ? c->N * sizeof(T) : 0, c->stream>>>(
-        sell_view<T>(c), c->perm, static_cast<const T*>(x), int(c->N), c->stage_x(), static_cast<T*>(d));
+    k_dose<T><<<c->slab_blocks(), SLAB_THREADS, c->stage_x() ? c->N * sizeof(T) : 0, c->stream>>>(
+        sell_view<T>(c), c->perm, c->Vpad, static_cast<const T*>(x), int(c->N), c->stage_x(), static_cast<T*>(d));
     LAUNCHCHK(c);
     return DAO_OK;
 }
@@ -415,7 +421,7 @@ template <class T>
 dao_status gradient_typed(dao_ctx* c, const void* d, void* g, double* F) {
     const T* dd = static_cast<const T*>(d);
     k_objective_ext<T><<<c->elem_blocks(c->V), BLOCK, 0, c->stream>>>(dd, c->cls_ext, c->V, c->classes,
-                                                                       c->parts, c->counter, c->scalar);
+                                                                       c->parts, c->arr, c->scalar);
     k_gather_grad<T><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(dd, c->perm, c->cls_int, c->Vpad,
                                                                         c->classes, static_cast<T*>(c->ug));
     k_gradT<T, T, T, T, false><<<c->N, BLOCK, 0, c->stream>>>(c->csc_ptr, c->csc_row,
@@ -443,8 +449,8 @@ dao_status time_product_typed(dao_ctx* c, int kernel, int iters, double* us) {
     HIPCHK(c, hipEventCreate(&e1));
     auto launch = [&]() {
         if (kernel == 0)
-            k_dose<T><<<c->slice_blocks(), BLOCK, c->stage_x() ? c->N * sizeof(T) : 0, c->stream>>>(
-                sell_view<T>(c), c->perm, static_cast<const T*>(c->dx), int(c->N), c->stage_x(),
+            k_dose<T><<<c->slab_blocks(), SLAB_THREADS, c->stage_x() ? c->N * sizeof(T) : 0, c->stream>>>(
+                sell_view<T>(c), c->perm, c->Vpad, static_cast<const T*>(c->dx), int(c->N), c->stage_x(),
                 static_cast<T*>(c->vscratch));
         else
             k_gradT<T, T, T, T, false><<<c->N, BLOCK, 0, c->stream>>>(

@@ -4,7 +4,10 @@
 //   forward  : sliced ELL, 64 voxel rows per slice, entries of a slice stored
 //              column-major (entry k of the slice's lane-l row at
 //              slice_ptr[s] + 64 k + l) so a wavefront reads each k as one
-//              contiguous 64-lane load; 16-bit beamlet indices.
+//              contiguous 64-lane load; 16-bit beamlet indices.  A workgroup
+//              ("slab") owns 4 slices = 256 rows; each slice's entries are
+//              split into 4 contiguous k-ranges, one wavefront each, so 16
+//              wavefronts stream one slab.
 //   transpose: beamlet-major copy (one run of (internal row, value) per
 //              beamlet), read by one workgroup per beamlet.
 //   vectors  : "internal" voxel vectors (d, q, u, class) follow the slice
@@ -13,7 +16,9 @@
 //
 // Reductions are deterministic: every sum is taken in a fixed order
 // (per-lane sequential, then a fixed butterfly, then a fixed block order),
-// never with floating-point atomics.
+// never with floating-point atomics.  Grid-wide results are combined by the
+// last workgroup to arrive (integer arrival counters only); no launch ever
+// waits on another workgroup.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,6 +28,21 @@
 #include "dao_common.h"
 
 namespace dao {
+
+constexpr int KSPLIT = 4;                          // wavefronts per slice
+constexpr int SPB = 4;                             // slices per slab
+constexpr int SLAB = SPB * SLICE;                  // rows per slab
+constexpr int SLAB_THREADS = SPB * KSPLIT * WAVE;  // 1024
+constexpr int NSLOT = 8;                           // arrival counters
+constexpr int SLOT_STRIDE = 32;                    // 128 B between counters
+
+// Arrival counters of the last-workgroup pattern.  Workgroups hash onto
+// NSLOT counters (one cache line each) so that arrivals of different
+// workgroups do not serialise on one address; the last arrival of every
+// counter then arrives at a top-level counter.
+struct Arrival {
+    uint32_t c[(NSLOT + 1) * SLOT_STRIDE];
+};
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -57,9 +77,9 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Block-wide reduction record: (sum, sum, sum, min, max, sum) -- the line
-// search needs phi', the right and left slopes, the nearest breakpoints on
-// both sides; the last slot carries an objective partial.
+// Reduction record: (sum, sum, sum, min, max, sum).  The line search needs
+// phi', the slopes of phi' right and left of t and the nearest breakpoints
+// on both sides; the last slot carries an objective partial.
 struct Rec {
     double s0, s1, s2, mn, mx, s5;
 };
@@ -68,78 +88,83 @@ __device__ __forceinline__ Rec rec_identity() {
     return Rec{0.0, 0.0, 0.0, INFINITY, -INFINITY, 0.0};
 }
 
-// Reduce one Rec over the block (blockDim.x = BLOCK); result valid in thread 0.
+__device__ __forceinline__ void rec_add(Rec& a, const Rec& b) {
+    a.s0 += b.s0;
+    a.s1 += b.s1;
+    a.s2 += b.s2;
+    a.mn = fmin(a.mn, b.mn);
+    a.mx = fmax(a.mx, b.mx);
+    a.s5 += b.s5;
+}
+
+// Reduce one Rec over the block (up to 1024 threads); valid in thread 0.
 __device__ __forceinline__ Rec block_reduce(Rec r) {
-    __shared__ Rec s_w[BLOCK / WAVE];
+    __shared__ Rec s_w[1024 / WAVE];
     r.s0 = wave_sum(r.s0);
     r.s1 = wave_sum(r.s1);
     r.s2 = wave_sum(r.s2);
     r.mn = wave_min(r.mn);
     r.mx = wave_max(r.mx);
     r.s5 = wave_sum(r.s5);
-    const int w = threadIdx.x / WAVE;
-    if ((threadIdx.x % WAVE) == 0) s_w[w] = r;
+    const int nw = blockDim.x / WAVE;
+    if ((threadIdx.x % WAVE) == 0) s_w[threadIdx.x / WAVE] = r;
     __syncthreads();
     Rec out = rec_identity();
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < BLOCK / WAVE; ++i) {
-            out.s0 += s_w[i].s0;
-            out.s1 += s_w[i].s1;
-            out.s2 += s_w[i].s2;
-            out.mn = fmin(out.mn, s_w[i].mn);
-            out.mx = fmax(out.mx, s_w[i].mx);
-            out.s5 += s_w[i].s5;
-        }
-    }
+    if (threadIdx.x == 0)
+        for (int i = 0; i < nw; ++i) rec_add(out, s_w[i]);
     __syncthreads();
     return out;
 }
 
-// Thread 0 of every block stores its record, then the last block to arrive
+// Called by thread 0 of every workgroup after it published its results:
+// true in exactly one workgroup, the last to arrive, which may then read
+// every other workgroup's results.  Counters are reset for the next launch.
+__device__ __forceinline__ bool arrive_last(Arrival* A) {
+    const uint32_t nb = gridDim.x;
+    const uint32_t slot = blockIdx.x % NSLOT;
+    const uint32_t expect = (nb - slot + NSLOT - 1) / NSLOT;   // workgroups on this counter
+    __threadfence();
+    const uint32_t prev = atomicAdd(&A->c[slot * SLOT_STRIDE], 1u);
+    if (prev + 1 != expect) return false;
+    atomicExch(&A->c[slot * SLOT_STRIDE], 0u);
+    __threadfence();
+    const uint32_t nslots = nb < NSLOT ? nb : NSLOT;
+    const uint32_t p2 = atomicAdd(&A->c[NSLOT * SLOT_STRIDE], 1u);
+    if (p2 + 1 != nslots) return false;
+    atomicExch(&A->c[NSLOT * SLOT_STRIDE], 0u);
+    __threadfence();
+    return true;
+}
+
+// Thread 0 of every block stores its record; the last block to arrive
 // reduces all records in block order.  Returns true in every thread of the
 // last block, with the total in *total (valid in thread 0).
-__device__ __forceinline__ bool arrive_and_reduce(Rec mine, Rec* parts, uint32_t* counter,
-                                                  Rec* total) {
+__device__ __forceinline__ bool arrive_and_reduce(Rec mine, Rec* parts, Arrival* A, Rec* total) {
     __shared__ int s_last;
     if (threadIdx.x == 0) {
         parts[blockIdx.x] = mine;
-        __threadfence();
-        const uint32_t prev = atomicAdd(counter, 1u);
-        s_last = (prev == gridDim.x - 1);
+        s_last = arrive_last(A);
     }
     __syncthreads();
     if (!s_last) return false;
     __threadfence();
-    // fixed-order reduction of gridDim.x records: each thread takes a
-    // contiguous run, then the block combines runs in order
+    // fixed-order reduction: each thread a contiguous run, then the block
     Rec acc = rec_identity();
     const int n = gridDim.x;
-    const int per = (n + BLOCK - 1) / BLOCK;
+    const int per = (n + blockDim.x - 1) / blockDim.x;
     const int b0 = threadIdx.x * per;
     const int b1 = min(n, b0 + per);
-    for (int b = b0; b < b1; ++b) {
-        const Rec p = parts[b];
-        acc.s0 += p.s0;
-        acc.s1 += p.s1;
-        acc.s2 += p.s2;
-        acc.mn = fmin(acc.mn, p.mn);
-        acc.mx = fmax(acc.mx, p.mx);
-        acc.s5 += p.s5;
-    }
+    for (int b = b0; b < b1; ++b) rec_add(acc, parts[b]);
     const Rec t = block_reduce(acc);
-    if (threadIdx.x == 0) {
-        *total = t;
-        *counter = 0u;
-    }
+    if (threadIdx.x == 0) *total = t;
     __syncthreads();
     return true;
 }
 
 // Contribution of one voxel to the line-search evaluation at step t:
 // phi'(t) = sum q_j dF/dz_j(d_j + t q_j); slopes of phi' just right / left of
-// t; nearest breakpoint above / below t (where d_j + t q_j meets a threshold).
-__device__ __forceinline__ void ls_voxel(const ObjClass& c, double d, double q, double t,
-                                         Rec& r) {
+// t (without the factor 2); nearest breakpoint above / below t.
+__device__ __forceinline__ void ls_voxel(const ObjClass& c, double d, double q, double t, Rec& r) {
     const double z = d + t * q;
     r.s0 += q * grad_f(c, z);
     const bool ua = c.a > 0.0, ob = c.b > 0.0;
@@ -165,18 +190,28 @@ __device__ __forceinline__ void ls_voxel(const ObjClass& c, double d, double q, 
 }
 
 // ---------------------------------------------------------------------------
-// sliced-ELL row dot product: lane `lane` of a wavefront owns one row of the
-// slice starting at entry `base` with `w` entries per row.  Entries are
-// visited in the row's stored (ascending beamlet) order.
+// forward products over slabs
 // ---------------------------------------------------------------------------
+template <class T>
+struct SellView {
+    const uint32_t* slice_ptr;
+    const int32_t* slice_w;
+    const T* val;
+    const uint16_t* col;
+    int64_t nslices;
+};
+
+// Lane `lane` of a wavefront: entries k0..k1-1 of its row in the slice that
+// starts at entry `base`, visited in stored (ascending beamlet) order.
 template <class T, class XT, class Acc>
 __device__ __forceinline__ Acc sell_dot(const T* __restrict__ val, const uint16_t* __restrict__ col,
-                                        uint32_t base, int w, int lane, const XT* __restrict__ xs) {
-    const T* v = val + base + lane;
-    const uint16_t* c = col + base + lane;
+                                        uint32_t base, int k0, int k1, int lane,
+                                        const XT* __restrict__ xs) {
+    const T* v = val + base + uint32_t(k0) * SLICE + lane;
+    const uint16_t* c = col + base + uint32_t(k0) * SLICE + lane;
     Acc acc = Acc(0);
-    int k = 0;
-    for (; k + 4 <= w; k += 4) {
+    int k = k0;
+    for (; k + 4 <= k1; k += 4) {
         const T v0 = v[0], v1 = v[SLICE], v2 = v[2 * SLICE], v3 = v[3 * SLICE];
         const uint16_t c0 = c[0], c1 = c[SLICE], c2 = c[2 * SLICE], c3 = c[3 * SLICE];
         acc += Acc(v0) * Acc(xs[c0]);
@@ -186,7 +221,7 @@ __device__ __forceinline__ Acc sell_dot(const T* __restrict__ val, const uint16_
         v += 4 * SLICE;
         c += 4 * SLICE;
     }
-    for (; k < w; ++k) {
+    for (; k < k1; ++k) {
         acc += Acc(v[0]) * Acc(xs[c[0]]);
         v += SLICE;
         c += SLICE;
@@ -194,16 +229,31 @@ __device__ __forceinline__ Acc sell_dot(const T* __restrict__ val, const uint16_
     return acc;
 }
 
-// Forward-layout device view.
-template <class T>
-struct SellView {
-    const uint32_t* slice_ptr;
-    const int32_t* slice_w;
-    const T* val;
-    const uint16_t* col;
-    int64_t nslices;
-    int spb;   // slices per block
-};
+// Row sums of this workgroup's slab (SLAB_THREADS threads).  Wavefront w
+// takes slice w / KSPLIT of the slab and the (w % KSPLIT)-th quarter of its
+// entries; partials meet in s_part and are added in k order.  Returns the
+// row sum in threads t < SLAB (row blockIdx.x * SLAB + t).
+template <class T, class XT, class Acc>
+__device__ __forceinline__ Acc slab_rows(const SellView<T>& S, const XT* __restrict__ xs, Acc* s_part) {
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int j = wave / KSPLIT, kp = wave % KSPLIT;
+    const int64_t s = int64_t(blockIdx.x) * SPB + j;
+    Acc acc = Acc(0);
+    if (s < S.nslices) {
+        const int w = S.slice_w[s];
+        const int kc = (w + KSPLIT - 1) / KSPLIT;
+        const int k0 = min(w, kp * kc), k1 = min(w, k0 + kc);
+        acc = sell_dot<T, XT, Acc>(S.val, S.col, S.slice_ptr[s], k0, k1, lane, xs);
+    }
+    s_part[kp * SLAB + j * SLICE + lane] = acc;
+    __syncthreads();
+    Acc sum = Acc(0);
+    if (threadIdx.x < SLAB) {
+#pragma unroll
+        for (int q = 0; q < KSPLIT; ++q) sum += s_part[q * SLAB + threadIdx.x];
+    }
+    return sum;
+}
 
 // Stage an n-vector into LDS (or return the global pointer when not staged).
 template <class XT, class ST>
@@ -215,23 +265,22 @@ __device__ __forceinline__ const XT* stage_vec(const ST* __restrict__ src, int n
 }
 
 // ---------------------------------------------------------------------------
-// plain products (C-ABI dao_dose / dao_gradient and pricing at round ends)
+// plain products and objective (C-ABI calls, round ends)
 // ---------------------------------------------------------------------------
 
-// d_ext[perm[r]] = (D x)_r for every non-empty row; x staged in LDS.
+// d_ext[perm[r]] = (D x)_r for every row of the slab; x staged in LDS.
 template <class T>
-__global__ void __launch_bounds__(BLOCK) k_dose(SellView<T> S, const int32_t* __restrict__ perm,
-                                                const T* __restrict__ x, int N, bool stage,
-                                                T* __restrict__ d_ext) {
+__global__ void __launch_bounds__(SLAB_THREADS) k_dose(SellView<T> S, const int32_t* __restrict__ perm,
+                                                       int64_t Vpad, const T* __restrict__ x, int N,
+                                                       bool stage, T* __restrict__ d_ext) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ T s_part[KSPLIT * SLAB];
     const T* xs = stage_vec<T, T>(x, N, reinterpret_cast<T*>(smem), stage);
-    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int64_t s0 = int64_t(blockIdx.x) * S.spb;
-    const int64_t s1 = min(S.nslices, s0 + S.spb);
-    for (int64_t s = s0 + wave; s < s1; s += BLOCK / WAVE) {
-        const T acc = sell_dot<T, T, T>(S.val, S.col, S.slice_ptr[s], S.slice_w[s], lane, xs);
-        const int32_t j = perm[s * SLICE + lane];
-        if (j >= 0) d_ext[j] = acc;
+    const T sum = slab_rows<T, T, T>(S, xs, s_part);
+    const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
+    if (threadIdx.x < SLAB && row < Vpad) {
+        const int32_t j = perm[row];
+        if (j >= 0) d_ext[j] = sum;
     }
 }
 
@@ -253,19 +302,18 @@ __global__ void k_scatter(const TI* __restrict__ in, const int32_t* __restrict__
     }
 }
 
-// F over every caller voxel (eq. 9 + eq. 10), last block writes *F_out.
+// F over every caller voxel (eq. 9 + eq. 10); the last block writes *F_out.
 template <class T>
 __global__ void __launch_bounds__(BLOCK) k_objective_ext(const T* __restrict__ d_ext,
                                                          const uint8_t* __restrict__ cls, int64_t V,
                                                          const ObjClass* __restrict__ classes,
-                                                         Rec* parts, uint32_t* counter,
-                                                         double* F_out) {
+                                                         Rec* parts, Arrival* arr, double* F_out) {
     Rec r = rec_identity();
     for (int64_t j = int64_t(blockIdx.x) * BLOCK + threadIdx.x; j < V; j += int64_t(gridDim.x) * BLOCK)
         r.s5 += obj_f(classes[cls[j]], double(d_ext[j]));
     Rec tot;
-    Rec mine = block_reduce(r);
-    if (arrive_and_reduce(mine, parts, counter, &tot) && threadIdx.x == 0) *F_out = tot.s5;
+    const Rec mine = block_reduce(r);
+    if (arrive_and_reduce(mine, parts, arr, &tot) && threadIdx.x == 0) *F_out = tot.s5;
 }
 
 // u[r] = dF/dz at the caller's dose of internal row r (0 on padding rows).
@@ -287,7 +335,7 @@ __global__ void __launch_bounds__(BLOCK) k_objective_int(const double* __restric
                                                          const uint8_t* __restrict__ cls, int64_t Vpad,
                                                          const ObjClass* __restrict__ classes,
                                                          T* __restrict__ u, double* __restrict__ u64,
-                                                         Rec* parts, MasterState* ms) {
+                                                         Rec* parts, Arrival* arr, MasterState* ms) {
     Rec r = rec_identity();
     for (int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x; i < Vpad;
          i += int64_t(gridDim.x) * BLOCK) {
@@ -299,22 +347,21 @@ __global__ void __launch_bounds__(BLOCK) k_objective_int(const double* __restric
         r.s5 += obj_f(c, z);
     }
     Rec tot;
-    Rec mine = block_reduce(r);
-    if (arrive_and_reduce(mine, parts, &ms->counter, &tot) && threadIdx.x == 0)
-        ms->F = ms->F_const + tot.s5;
+    const Rec mine = block_reduce(r);
+    if (arrive_and_reduce(mine, parts, arr, &tot) && threadIdx.x == 0) ms->F = ms->F_const + tot.s5;
 }
 
 // g_i = sum over beamlet i's entries of val * u[row]; one block per beamlet.
-// GATED (the master's copy): runs only in PH_TP of an unfinished master
-// state and moves it to PH_DIR.
+// GATED (the master's copy) runs only while a finished line search awaits
+// its update (phase PH_UPD of an unfinished master), like k_update.
 template <class T, class UT, class Acc, class GT, bool GATED>
 __global__ void __launch_bounds__(BLOCK) k_gradT(const int32_t* __restrict__ cptr,
                                                  const int32_t* __restrict__ crow,
                                                  const T* __restrict__ cval, const UT* __restrict__ u,
-                                                 GT* __restrict__ g, MasterState* gate) {
+                                                 GT* __restrict__ g, const MasterState* gate) {
     if (GATED) {
         __shared__ int s_skip;
-        if (threadIdx.x == 0) s_skip = (gate->done || gate->phase != PH_TP);
+        if (threadIdx.x == 0) s_skip = (gate->done || gate->phase != PH_UPD);
         __syncthreads();
         if (s_skip) return;
     }
@@ -340,18 +387,6 @@ __global__ void __launch_bounds__(BLOCK) k_gradT(const int32_t* __restrict__ cpt
         for (int w = 0; w < BLOCK / WAVE; ++w) t += s_w[w];
         g[i] = GT(t);
     }
-    if (GATED) {
-        __shared__ int s_last;
-        if (threadIdx.x == 0) {
-            __threadfence();
-            const uint32_t prev = atomicAdd(&gate->counter, 1u);
-            s_last = (prev == gridDim.x - 1);
-            if (s_last) {
-                gate->counter = 0u;
-                gate->phase = PH_DIR;
-            }
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -371,7 +406,8 @@ struct PriceGeom {
 };
 
 __global__ void __launch_bounds__(BLOCK) k_price(PriceGeom G, const double* __restrict__ g,
-                                                 RowRec* __restrict__ rows, PriceResult* res) {
+                                                 RowRec* __restrict__ rows, PriceResult* res,
+                                                 Arrival* arr) {
     // prefix sums of each wave's row, accumulated sequentially so that a
     // beamlet priced exactly 0 leaves the prefix exactly unchanged (exact
     // ties such as leading or trailing zero-price beamlets stay ties)
@@ -448,11 +484,7 @@ __global__ void __launch_bounds__(BLOCK) k_price(PriceGeom G, const double* __re
     // last block: per-beam sums, argmin, gap
     __shared__ int s_last;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t prev = atomicAdd(&res->counter, 1u);
-        s_last = (prev == gridDim.x - 1);
-    }
+    if (threadIdx.x == 0) s_last = arrive_last(arr);
     __syncthreads();
     if (!s_last) return;
     __threadfence();
@@ -482,12 +514,19 @@ __global__ void __launch_bounds__(BLOCK) k_price(PriceGeom G, const double* __re
         res->n_rows = r1 - r0;
         res->rc = bv;
         res->gap = gap;
-        res->counter = 0u;
     }
 }
 
 // ---------------------------------------------------------------------------
 // gradient projection master (device-resident state machine)
+//
+// One step is the launch sequence
+//   k_dir -> k_qstep -> k_lseval x slots -> k_update -> k_gradT.
+// k_dir runs in PH_DIR (start of a solve) and PH_UPD (after an update); it
+// sums the update's objective partials, tests KKT and builds the direction
+// (-> PH_Q).  k_qstep and k_lseval evaluate the line search and decide in
+// their last workgroup (-> PH_LS or, once final, PH_UPD).  k_update and
+// k_gradT run in PH_UPD and leave the phase to the next k_dir.
 // ---------------------------------------------------------------------------
 struct PoolView {
     const int32_t* ap_beam;      // [Kmax]
@@ -502,51 +541,81 @@ struct PoolView {
 };
 
 // sum over the pool of v_k for apertures that open beamlet i (eq. 7), in
-// pool order
-__device__ __forceinline__ double pool_at_beamlet(const PoolView& P, int K, const double* v, int i) {
+// pool order; `beam` and `lv` may point to LDS copies of the pool
+__device__ __forceinline__ double pool_at_beamlet(const PoolView& P, int K, const int32_t* beam,
+                                                  const int16_t* lv, const double* v, int i) {
     const int b = P.blt_beam[i];
     const int lr = P.blt_row[i] - P.beam_row0[b];
     const int pos = P.blt_pos[i];
     double acc = 0.0;
     for (int k = 0; k < K; ++k) {
-        if (P.ap_beam[k] != b) continue;
-        const int16_t* lv = P.ap_lv + (size_t(k) * P.maxRB + lr) * 2;
-        if (pos >= lv[0] && pos < lv[1]) acc += v[k];
+        if (beam[k] != b) continue;
+        const int16_t* l = lv + (size_t(k) * P.maxRB + lr) * 2;
+        if (pos >= l[0] && pos < l[1]) acc += v[k];
     }
     return acc;
 }
 
-// x = A v for all beamlets (block-strided), stored as XT
-template <class XT>
-__device__ __forceinline__ void pool_to_beamlets(const PoolView& P, int K, const double* v, XT* x) {
-    for (int i = threadIdx.x; i < P.N; i += blockDim.x) x[i] = XT(pool_at_beamlet(P, K, v, i));
-}
-
-// Direction step (single block of 1024 threads): grad_y = A^T g, KKT test,
-// projected direction p, longest feasible step t_max, dx = A p.
+// Direction step (single block of 1024 threads): objective of the last
+// update, grad_y = A^T g, KKT test, projected direction p, longest feasible
+// step t_max, dx = A p.  The pool and g are staged in LDS when they fit.
 template <class T>
 __global__ void __launch_bounds__(1024) k_dir(PoolView P, const T* __restrict__ g,
                                               double* __restrict__ y, double* __restrict__ p,
                                               double* __restrict__ grad, T* __restrict__ dx,
-                                              MasterState* ms) {
-    __shared__ int s_skip, s_go;
+                                              MasterState* ms, const Rec* __restrict__ upd_parts,
+                                              int n_upd, bool stage) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_skip, s_go, s_upd, s_K;
     __shared__ double s_grad[MAX_APERTURES];
     __shared__ double s_p[MAX_APERTURES];
-    if (threadIdx.x == 0) s_skip = (ms->done || ms->phase != PH_DIR);
+    __shared__ double s_y[MAX_APERTURES];
+    __shared__ int32_t s_beam[MAX_APERTURES];
+    if (threadIdx.x == 0) {
+        s_skip = ms->done || !(ms->phase == PH_DIR || ms->phase == PH_UPD);
+        s_upd = ms->phase == PH_UPD;
+        s_K = ms->K;
+    }
     __syncthreads();
     if (s_skip) return;
-    const int K = ms->K;
+    const int K = s_K;
+    // objective after the update (fixed-order sum of the update's partials)
+    if (s_upd) {
+        Rec acc = rec_identity();
+        const int per = (n_upd + blockDim.x - 1) / blockDim.x;
+        const int b0 = threadIdx.x * per, b1 = min(n_upd, b0 + per);
+        for (int b = b0; b < b1; ++b) acc.s5 += upd_parts[b].s5;
+        const Rec t = block_reduce(acc);
+        if (threadIdx.x == 0) ms->F = ms->F_const + t.s5;
+    }
+    // stage g and the pool
+    T* gs_l = reinterpret_cast<T*>(smem);
+    int16_t* lv_l = reinterpret_cast<int16_t*>(smem + ((size_t(P.N) * sizeof(T) + 15) & ~size_t(15)));
+    const T* gs = g;
+    const int16_t* lvs = P.ap_lv;
+    if (stage) {
+        for (int i = threadIdx.x; i < P.N; i += blockDim.x) gs_l[i] = g[i];
+        const int nlv = K * P.maxRB * 2;
+        for (int i = threadIdx.x; i < nlv; i += blockDim.x) lv_l[i] = P.ap_lv[i];
+        gs = gs_l;
+        lvs = lv_l;
+    }
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        s_beam[k] = P.ap_beam[k];
+        s_y[k] = y[k];
+    }
+    __syncthreads();
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int nw = blockDim.x / WAVE;
     for (int k = wave; k < K; k += nw) {
-        const int b = P.ap_beam[k];
+        const int b = s_beam[k];
         const int r0 = P.beam_row0[b], nr = P.beam_row0[b + 1] - r0;
         double acc = 0.0;
         for (int lr = lane; lr < nr; lr += WAVE) {
-            const int16_t* lv = P.ap_lv + (size_t(k) * P.maxRB + lr) * 2;
+            const int16_t* l = lvs + (size_t(k) * P.maxRB + lr) * 2;
             const int base = P.row_start[r0 + lr];
             double s = 0.0;
-            for (int pos = lv[0]; pos < lv[1]; ++pos) s += double(g[base + pos]);
+            for (int pos = l[0]; pos < l[1]; ++pos) s += double(gs[base + pos]);
             acc += s;
         }
         acc = wave_sum(acc);
@@ -555,7 +624,7 @@ __global__ void __launch_bounds__(1024) k_dir(PoolView P, const T* __restrict__ 
     __syncthreads();
     if (threadIdx.x == 0) {
         double kkt = 0.0;
-        for (int k = 0; k < K; ++k) kkt = fmax(kkt, fabs(fmin(y[k], s_grad[k])));
+        for (int k = 0; k < K; ++k) kkt = fmax(kkt, fabs(fmin(s_y[k], s_grad[k])));
         ms->kkt = kkt;
         int go = 1;
         if (!(kkt > ms->tol)) {
@@ -570,12 +639,12 @@ __global__ void __launch_bounds__(1024) k_dir(PoolView P, const T* __restrict__ 
         if (go) {
             for (int k = 0; k < K; ++k) {
                 double pk = -s_grad[k];
-                if (y[k] == 0.0 && s_grad[k] >= 0.0) pk = 0.0;
+                if (s_y[k] == 0.0 && s_grad[k] >= 0.0) pk = 0.0;
                 p[k] = pk;
                 s_p[k] = pk;
                 grad[k] = s_grad[k];
                 if (pk != 0.0) any = 1;
-                if (pk < 0.0) tmax = fmin(tmax, y[k] / (-pk));
+                if (pk < 0.0) tmax = fmin(tmax, s_y[k] / (-pk));
                 gp += s_grad[k] * pk;
             }
             if (!any) {
@@ -585,6 +654,7 @@ __global__ void __launch_bounds__(1024) k_dir(PoolView P, const T* __restrict__ 
         }
         if (!go) {
             ms->done = 1;
+            ms->phase = PH_DIR;
         } else {
             ms->t_max = tmax;
             ms->gphi0 = gp;
@@ -598,7 +668,7 @@ __global__ void __launch_bounds__(1024) k_dir(PoolView P, const T* __restrict__ 
     }
     __syncthreads();
     if (!s_go) return;
-    pool_to_beamlets<T>(P, K, s_p, dx);
+    for (int i = threadIdx.x; i < P.N; i += blockDim.x) dx[i] = T(pool_at_beamlet(P, K, s_beam, lvs, s_p, i));
     __syncthreads();
     if (threadIdx.x == 0) ms->phase = PH_Q;
 }
@@ -685,23 +755,26 @@ __device__ __forceinline__ void finish_step(const PoolView& P, MasterState* ms, 
         s_refresh = ms->refresh;
     }
     __syncthreads();
-    if (s_refresh) pool_to_beamlets<double>(P, K, s_y, x64);
+    if (s_refresh)
+        for (int i = threadIdx.x; i < P.N; i += blockDim.x)
+            x64[i] = pool_at_beamlet(P, K, P.ap_beam, P.ap_lv, s_y, i);
     __syncthreads();
     if (threadIdx.x == 0) ms->phase = PH_UPD;
 }
 
-// q = D dx and the line-search evaluation at t = 0.
+// q = D dx and the line-search evaluation at t = 0 (slab layout).
 template <class T>
-__global__ void __launch_bounds__(BLOCK) k_qstep(SellView<T> S, const T* __restrict__ dx, int N,
-                                                 bool stage, const double* __restrict__ d,
-                                                 const uint8_t* __restrict__ cls,
-                                                 const ObjClass* __restrict__ classes, int ncls,
-                                                 T* __restrict__ q, Rec* parts, MasterState* ms,
-                                                 PoolView P, double* y, const double* p,
-                                                 double* x64) {
+__global__ void __launch_bounds__(SLAB_THREADS) k_qstep(SellView<T> S, int64_t Vpad, const T* __restrict__ dx,
+                                                        int N, bool stage, const double* __restrict__ d,
+                                                        const uint8_t* __restrict__ cls,
+                                                        const ObjClass* __restrict__ classes, int ncls,
+                                                        T* __restrict__ q, Rec* parts, Arrival* arr,
+                                                        MasterState* ms, PoolView P, double* y,
+                                                        const double* p, double* x64) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_skip;
     __shared__ double s_t;
+    __shared__ T s_part[KSPLIT * SLAB];
     if (threadIdx.x == 0) {
         s_skip = (ms->done || ms->phase != PH_Q);
         s_t = ms->t;
@@ -713,20 +786,16 @@ __global__ void __launch_bounds__(BLOCK) k_qstep(SellView<T> S, const T* __restr
     T* xs_l = reinterpret_cast<T*>(smem + sizeof(ObjClass) * ncls);
     __syncthreads();
     const T* xs = stage_vec<T, T>(dx, N, xs_l, stage);
-    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int64_t s0 = int64_t(blockIdx.x) * S.spb;
-    const int64_t s1 = min(S.nslices, s0 + S.spb);
+    const T sum = slab_rows<T, T, T>(S, xs, s_part);
     Rec r = rec_identity();
-    const double t = s_t;
-    for (int64_t s = s0 + wave; s < s1; s += BLOCK / WAVE) {
-        const T acc = sell_dot<T, T, T>(S.val, S.col, S.slice_ptr[s], S.slice_w[s], lane, xs);
-        const int64_t row = s * SLICE + lane;
-        q[row] = acc;
-        ls_voxel(cl[cls[row]], d[row], double(acc), t, r);
+    const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
+    if (threadIdx.x < SLAB && row < Vpad) {
+        q[row] = sum;
+        ls_voxel(cl[cls[row]], d[row], double(sum), s_t, r);
     }
     Rec tot;
-    Rec mine = block_reduce(r);
-    if (!arrive_and_reduce(mine, parts, &ms->counter, &tot)) return;
+    const Rec mine = block_reduce(r);
+    if (!arrive_and_reduce(mine, parts, arr, &tot)) return;
     __shared__ int s_fin;
     if (threadIdx.x == 0) {
         s_fin = ls_decide(ms, tot);
@@ -740,8 +809,8 @@ __global__ void __launch_bounds__(BLOCK) k_qstep(SellView<T> S, const T* __restr
 __global__ void __launch_bounds__(BLOCK) k_lseval(const double* __restrict__ d, const void* qv,
                                                   int q_is_f64, const uint8_t* __restrict__ cls,
                                                   int64_t Vpad, const ObjClass* __restrict__ classes,
-                                                  int ncls, Rec* parts, MasterState* ms, PoolView P,
-                                                  double* y, const double* p, double* x64) {
+                                                  int ncls, Rec* parts, Arrival* arr, MasterState* ms,
+                                                  PoolView P, double* y, const double* p, double* x64) {
     __shared__ int s_skip;
     __shared__ double s_t;
     __shared__ ObjClass cl[256];
@@ -765,25 +834,28 @@ __global__ void __launch_bounds__(BLOCK) k_lseval(const double* __restrict__ d, 
             ls_voxel(cl[cls[i]], d[i], double(q[i]), t, r);
     }
     Rec tot;
-    Rec mine = block_reduce(r);
-    if (!arrive_and_reduce(mine, parts, &ms->counter, &tot)) return;
+    const Rec mine = block_reduce(r);
+    if (!arrive_and_reduce(mine, parts, arr, &tot)) return;
     __shared__ int s_fin;
     if (threadIdx.x == 0) s_fin = ls_decide(ms, tot);
     __syncthreads();
     finish_step(P, ms, y, p, x64, s_fin);
 }
 
-// Update: d += t q (or d = D x64 on refresh steps), u = grad F(d), F.
+// Update (slab layout): d += t q (or d = D x64 on refresh steps),
+// u = grad F(d), per-block objective partials for the next k_dir.
 template <class T>
-__global__ void __launch_bounds__(BLOCK) k_update(SellView<T> S, const double* __restrict__ x64, int N,
-                                                  bool stage, double* __restrict__ d,
-                                                  const T* __restrict__ q,
-                                                  const uint8_t* __restrict__ cls,
-                                                  const ObjClass* __restrict__ classes, int ncls,
-                                                  T* __restrict__ u, Rec* parts, MasterState* ms) {
+__global__ void __launch_bounds__(SLAB_THREADS) k_update(SellView<T> S, int64_t Vpad,
+                                                         const double* __restrict__ x64, int N, bool stage,
+                                                         double* __restrict__ d, const T* __restrict__ q,
+                                                         const uint8_t* __restrict__ cls,
+                                                         const ObjClass* __restrict__ classes, int ncls,
+                                                         T* __restrict__ u, Rec* upd_parts,
+                                                         const MasterState* ms) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_skip, s_refresh;
     __shared__ double s_t;
+    __shared__ double s_part[KSPLIT * SLAB];
     if (threadIdx.x == 0) {
         s_skip = (ms->done || ms->phase != PH_UPD);
         s_refresh = ms->refresh;
@@ -795,32 +867,22 @@ __global__ void __launch_bounds__(BLOCK) k_update(SellView<T> S, const double* _
     for (int i = threadIdx.x; i < ncls; i += blockDim.x) cl[i] = classes[i];
     double* xs_l = reinterpret_cast<double*>(smem + sizeof(ObjClass) * ncls);
     __syncthreads();
-    const double* xs = s_refresh ? stage_vec<double, double>(x64, N, xs_l, stage) : nullptr;
-    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int64_t s0 = int64_t(blockIdx.x) * S.spb;
-    const int64_t s1 = min(S.nslices, s0 + S.spb);
-    const double t = s_t;
+    double dn = 0.0;
+    if (s_refresh) {
+        const double* xs = stage_vec<double, double>(x64, N, xs_l, stage);
+        dn = slab_rows<T, double, double>(S, xs, s_part);
+    }
     Rec r = rec_identity();
-    for (int64_t s = s0 + wave; s < s1; s += BLOCK / WAVE) {
-        const int64_t row = s * SLICE + lane;
-        double dn;
-        if (s_refresh)
-            dn = sell_dot<T, double, double>(S.val, S.col, S.slice_ptr[s], S.slice_w[s], lane, xs);
-        else
-            dn = d[row] + t * double(q[row]);
+    const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
+    if (threadIdx.x < SLAB && row < Vpad) {
+        if (!s_refresh) dn = d[row] + s_t * double(q[row]);
         d[row] = dn;
         const ObjClass c = cl[cls[row]];
         u[row] = T(grad_f(c, dn));
-        r.s5 += obj_f(c, dn);
+        r.s5 = obj_f(c, dn);
     }
-    Rec tot;
-    Rec mine = block_reduce(r);
-    if (!arrive_and_reduce(mine, parts, &ms->counter, &tot)) return;
-    if (threadIdx.x == 0) {
-        ms->F = ms->F_const + tot.s5;
-        ms->refresh = 0;
-        ms->phase = PH_TP;
-    }
+    const Rec mine = block_reduce(r);
+    if (threadIdx.x == 0) upd_parts[blockIdx.x] = mine;
 }
 
 // Reset the master state machine for a new solve over a pool of K.
@@ -835,7 +897,6 @@ __global__ void k_master_init(MasterState* ms, int K, double tol, int max_steps)
         ms->stop_reason = 0;
         ms->ls_iter = 0;
         ms->refresh = 0;
-        ms->counter = 0u;
     }
 }
 
