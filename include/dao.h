@@ -106,7 +106,17 @@ typedef struct {
     int32_t refresh_every;  /* recompute d = D(A y) every this many steps (50) */
     int32_t ls_slots;       /* line-search launches per master cycle (2) */
     int64_t mem_cap_bytes;  /* fail dao_create with DAO_ENOMEM above this device footprint; 0 = none */
+    int32_t master;         /* DAO_MASTER_APERTURE (default) or DAO_MASTER_BEAMLET, see below */
 } dao_options;
+
+/* How the restricted master evaluates its two products per step.
+ * DAO_MASTER_APERTURE keeps the aperture dose matrix D_K (eq. 1 and eq. 2:
+ * D_kj = sum_{i in A_k} D_ij) on the device, one column per pool aperture,
+ * appended when the aperture enters; each step streams it twice
+ * (q = D_K p, dF/dy = D_K^T grad F).  Needs max_apertures <= 64.
+ * DAO_MASTER_BEAMLET evaluates the same products through the beamlet
+ * matrix and the pool map: q = D (A p), dF/dy = A^T (D^T grad F) (eq. 7). */
+enum { DAO_MASTER_APERTURE = 0, DAO_MASTER_BEAMLET = 1 };
 
 void dao_default_options(dao_options* opt);
 

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdao.so")
 DAO_OK, DAO_EOPTIMAL, DAO_ESTALLED = 0, 1, 2
 DAO_EINVAL, DAO_ENOMEM, DAO_EDEVICE, DAO_ESTATE = -1, -2, -3, -4
 DAO_F64, DAO_F32 = 0, 1
+DAO_MASTER_APERTURE, DAO_MASTER_BEAMLET = 0, 1
 _NAMES = {0: "DAO_OK", 1: "DAO_EOPTIMAL", 2: "DAO_ESTALLED", -1: "DAO_EINVAL", -2: "DAO_ENOMEM",
           -3: "DAO_EDEVICE", -4: "DAO_ESTATE"}
 
@@ -44,7 +45,8 @@ class dao_prescription(ctypes.Structure):
 class dao_options(ctypes.Structure):
     _fields_ = [("dtype", c_int32), ("max_apertures", c_int32), ("eps", c_double),
                 ("max_steps", c_int32), ("tau_rel", c_double), ("max_tighten", c_int32),
-                ("refresh_every", c_int32), ("ls_slots", c_int32), ("mem_cap_bytes", c_int64)]
+                ("refresh_every", c_int32), ("ls_slots", c_int32), ("mem_cap_bytes", c_int64),
+                ("master", c_int32)]
 
 
 class dao_info_t(ctypes.Structure):

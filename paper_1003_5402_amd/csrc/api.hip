@@ -12,6 +12,7 @@
 #include "../../include/dao.h"
 #include "dao_common.h"
 #include "kernels.h"
+#include "kernels_ap.h"
 #include "layout.h"
 
 using namespace dao;
@@ -67,6 +68,9 @@ struct dao_ctx {
     double* u64 = nullptr;     // [Vpad]
     void* ug = nullptr;        // [Vpad] scratch for dao_gradient
     void* vscratch = nullptr;  // [V] ctx type, allocated on first product timing
+    void* dk = nullptr;        // [Vpad * KS] ctx type: aperture dose matrix (aperture master)
+    void* ind = nullptr;       // [N] ctx type: 0/1 beamlet indicator of one aperture
+    double* parts2 = nullptr;  // [ap_blocks * (KS + 1)] update records of the aperture master
     void* g = nullptr;         // [N] ctx type
     double* g64 = nullptr;     // [N]
     void* dx = nullptr;        // [N] ctx type
@@ -111,6 +115,8 @@ struct dao_ctx {
         return std::max<int64_t>(1, std::min<int64_t>(ELEM_BLOCKS_MAX, (n + BLOCK - 1) / BLOCK));
     }
     int64_t slab_blocks() const { return std::max<int64_t>(1, (nslices + SPB - 1) / SPB); }
+    int64_t ap_blocks() const { return std::max<int64_t>(1, std::min<int64_t>(512, (Vpad + 255) / 256)); }
+    bool ap_master() const { return opt.master == DAO_MASTER_APERTURE; }
     int64_t price_blocks() const { return std::max<int64_t>(1, (R + BLOCK / WAVE - 1) / (BLOCK / WAVE)); }
     bool stage_x() const { return size_t(N) * tsize <= STAGE_LIMIT; }
     bool stage_x64() const { return size_t(N) * 8 <= STAGE_LIMIT; }
@@ -172,6 +178,7 @@ int64_t predicted_bytes(const HostLayout& L, size_t ts, int kmax) {
     b += int64_t(L.R) * 8 + (L.B + 1) * 4 + L.N * 12;
     b += L.Vpad * (8 + 3 * ts + 8) + L.N * (ts + 8 + ts + 8);
     b += int64_t(kmax) * (4 + 2 * 2 * L.max_rows_per_beam + 24);
+    b += int64_t(L.Vpad) * KS * ts + L.N * ts + 512 * (KS + 1) * 8;
     b += sizeof(MasterState) + sizeof(PriceResult) + L.R * sizeof(RowRec) + 2 * ELEM_BLOCKS_MAX * sizeof(Rec) +
          sizeof(Arrival);
     return b;
@@ -219,8 +226,40 @@ dao_status enqueue_cycle(dao_ctx* c) {
 }
 
 template <class T>
+dao_status enqueue_cycle_ap(dao_ctx* c) {
+    const int nb = int(c->ap_blocks());
+    const T* dk = static_cast<const T*>(c->dk);
+    k_upd_ap<T><<<nb, BLOCK, 0, c->stream>>>(dk, c->Vpad, c->d, static_cast<const T*>(c->q), c->cls_int,
+                                              c->classes, c->ncls, c->y, c->parts2, c->ms);
+    k_dir_ap<<<1, 1024, 0, c->stream>>>(c->parts2, nb, c->y, c->p, c->gradk, c->ms);
+    k_qstep_ap<T><<<nb, BLOCK, 0, c->stream>>>(dk, c->Vpad, c->d, c->cls_int, c->classes, c->ncls,
+                                                static_cast<T*>(c->q), c->parts, c->arr, c->ms, c->y, c->p);
+    for (int i = 0; i < c->opt.ls_slots; ++i)
+        k_lseval_ap<T><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
+            c->d, static_cast<const T*>(c->q), c->cls_int, c->Vpad, c->classes, c->ncls, c->parts, c->arr,
+            c->ms, c->y, c->p);
+    LAUNCHCHK(c);
+    return DAO_OK;
+}
+
+// Column k of the aperture dose matrix: D times the 0/1 indicator of aperture k.
+template <class T>
+dao_status build_dk_column(dao_ctx* c, int k) {
+    if (!c->ap_master()) return DAO_OK;
+    k_ap_indicator<T><<<(c->N + BLOCK - 1) / BLOCK, BLOCK, 0, c->stream>>>(pool_view(c), k, static_cast<T*>(c->ind));
+    k_dk_column<T><<<c->slab_blocks(), SLAB_THREADS, c->stage_x() ? c->N * sizeof(T) : 0, c->stream>>>(
+        sell_view<T>(c), c->Vpad, static_cast<const T*>(c->ind), int(c->N), c->stage_x(), k,
+        static_cast<T*>(c->dk));
+    LAUNCHCHK(c);
+    return DAO_OK;
+}
+
+template <class T>
 dao_status run_master(dao_ctx* c, double tol, int max_steps) {
-    k_master_init<<<1, 1, 0, c->stream>>>(c->ms, c->K, tol, max_steps);
+    if (c->ap_master())
+        k_master_init_ap<<<1, 1, 0, c->stream>>>(c->ms, c->K, tol, max_steps);
+    else
+        k_master_init<<<1, 1, 0, c->stream>>>(c->ms, c->K, tol, max_steps);
     LAUNCHCHK(c);
     // every cycle either finishes a step or advances a line search by
     // ls_slots evaluations; bound the cycles so a stuck state cannot spin
@@ -230,7 +269,7 @@ dao_status run_master(dao_ctx* c, double tol, int max_steps) {
     int chunk = 2;
     for (;;) {
         for (int i = 0; i < chunk; ++i) {
-            dao_status s = enqueue_cycle<T>(c);
+            dao_status s = c->ap_master() ? enqueue_cycle_ap<T>(c) : enqueue_cycle<T>(c);
             if (s != DAO_OK) return s;
         }
         cycles += chunk;
@@ -383,6 +422,11 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     TRY(dev_alloc(c, &c->parts, c->nparts * sizeof(Rec)));
     TRY(dev_alloc(c, &c->upd_parts, c->slab_blocks() * sizeof(Rec)));
     TRY(dev_alloc(c, &c->arr, sizeof(Arrival)));
+    if (c->ap_master()) {
+        TRY(dev_alloc(c, &c->dk, size_t(c->Vpad) * KS * ts));
+        TRY(dev_alloc(c, &c->ind, c->N * ts));
+        TRY(dev_alloc(c, &c->parts2, c->ap_blocks() * (KS + 1) * sizeof(double)));
+    }
     TRY(dev_alloc(c, &c->scalar, 16));
 #undef TRY
     HIPCHK(c, hipHostMalloc((void**)&c->ms_h, sizeof(MasterState), hipHostMallocDefault));
@@ -397,6 +441,7 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     std::memset(c->pr_h, 0, sizeof(PriceResult));
     HIPCHK(c, hipMemcpyAsync(c->pr, c->pr_h, sizeof(PriceResult), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemsetAsync(c->arr, 0, sizeof(Arrival), c->stream));
+    if (c->ap_master()) HIPCHK(c, hipMemsetAsync(c->dk, 0, size_t(c->Vpad) * KS * ts, c->stream));
     HIPCHK(c, hipMemsetAsync(c->ap_lv, 0, size_t(km) * c->maxRB * 4, c->stream));
     HIPCHK(c, hipMemsetAsync(c->ap_beam, 0, km * 4, c->stream));
     HIPCHK(c, hipMemsetAsync(c->p, 0, km * 8, c->stream));
@@ -499,8 +544,7 @@ dao_status solve_typed(dao_ctx* c, int32_t n_ap, dao_plan* out) {
     while (c->K < n_ap) {
         int32_t beam;
         double rc, gap;
-        s = (sizeof(T) == 8) ? price_on(c, static_cast<const double*>(c->g), &beam, lv.data(), &rc, &gap)
-                             : price_current<T>(c, &beam, lv.data(), &rc, &gap);
+        s = price_current<T>(c, &beam, lv.data(), &rc, &gap);
         if (s != DAO_OK) return s;
         if (std::isnan(rc1)) {
             rc1 = rc;
@@ -528,6 +572,8 @@ dao_status solve_typed(dao_ctx* c, int32_t n_ap, dao_plan* out) {
         if (c->K >= c->opt.max_apertures) return c->fail(DAO_ESTATE, "pool capacity reached");
         k_add_from_price<<<1, 256, 0, c->stream>>>(c->pr, c->K, c->maxRB, c->ap_beam, c->ap_lv, c->y);
         LAUNCHCHK(c);
+        s = build_dk_column<T>(c, c->K);
+        if (s != DAO_OK) return s;
         mirror_add(c, beam, lv.data());
         c->K += 1;
         s = run_master<T>(c, eps * scale, c->opt.max_steps);
@@ -573,6 +619,7 @@ void dao_default_options(dao_options* o) {
     o->refresh_every = 50;
     o->ls_slots = 2;
     o->mem_cap_bytes = 0;
+    o->master = DAO_MASTER_APERTURE;
 }
 
 const char* dao_create_error(void) { return g_create_error.c_str(); }
@@ -710,6 +757,8 @@ dao_status dao_add_aperture(dao_ctx* c, int32_t beam, const int16_t* leaves) {
     HIPCHK(c, hipMemcpyAsync(c->ap_beam + c->K, &beam, 4, hipMemcpyHostToDevice, c->stream));
     k_fill<double><<<1, 64, 0, c->stream>>>(c->y + c->K, 1, 0.0);
     LAUNCHCHK(c);
+    s = c->dtype == DAO_F64 ? build_dk_column<double>(c, c->K) : build_dk_column<float>(c, c->K);
+    if (s != DAO_OK) return s;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     mirror_add(c, beam, leaves);
     c->K += 1;

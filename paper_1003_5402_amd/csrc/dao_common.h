@@ -9,6 +9,7 @@ constexpr int WAVE = 64;              // CDNA wavefront width
 constexpr int SLICE = 64;             // rows per forward-layout slice (one per wavefront)
 constexpr int MAX_ROW_LEN = 64;       // one MLC row per wavefront in pricing
 constexpr int MAX_APERTURES = 256;
+constexpr int KS = 64;                // aperture slots per row of the aperture dose matrix
 constexpr int LS_MAX_ITER = 60;       // line-search evaluations per master step
 constexpr int BLOCK = 256;            // threads per block of the streaming kernels
 constexpr int NPART = 6;              // doubles per block in a reduction record
@@ -41,7 +42,7 @@ struct MasterState {
     int32_t K;             // pool size
     int32_t ls_iter;       // evaluations in the current line search
     int32_t hi_known;
-    int32_t refresh;       // current update recomputes d = D(A y)
+    int32_t refresh;       // update mode: 0 d += t q, 1 d = D(A y), 2 keep d (refresh u, F only)
     int32_t refresh_every;
     int32_t stop_reason;   // 0 running, 1 kkt, 2 cap, 3 zero direction
     int64_t total_steps;
@@ -55,8 +56,8 @@ struct MasterState {
     double F;              // objective at the current dose
     double F_const;        // objective of voxels no beamlet reaches (dose 0)
     double last_step;
-    uint32_t counter;      // last-block-done counter, reset by the last block
-    uint32_t pad;
+    int32_t pad0;
+    int32_t pad1;
 };
 
 // Pricing result written by the last block of the pricing launch.
@@ -65,8 +66,6 @@ struct PriceResult {
     int32_t n_rows;
     double rc;
     double gap;
-    uint32_t counter;
-    uint32_t pad;
     int16_t leaves[2 * 1024];   // (L, R) per row of the chosen beam
 };
 

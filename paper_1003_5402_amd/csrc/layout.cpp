@@ -40,6 +40,10 @@ dao_status validate_inputs(const dao_matrix* D, const dao_beams* beams,
     if (opt->refresh_every < 1) return fail("refresh_every must be >= 1");
     if (opt->ls_slots < 1 || opt->ls_slots > 16) return fail("ls_slots must be in [1, 16]");
     if (opt->mem_cap_bytes < 0) return fail("mem_cap_bytes must be >= 0");
+    if (opt->master != DAO_MASTER_APERTURE && opt->master != DAO_MASTER_BEAMLET)
+        return fail("master must be DAO_MASTER_APERTURE or DAO_MASTER_BEAMLET");
+    if (opt->master == DAO_MASTER_APERTURE && opt->max_apertures > KS)
+        return fail("the aperture-matrix master holds at most 64 apertures (max_apertures)");
 
     const int64_t* rp = D->row_ptr;
     if (rp[0] != 0) return fail("row_ptr[0] must be 0");

@@ -25,6 +25,10 @@ from oracle.master import MasterState, kkt_residual, master_step, solve_master
 
 pytestmark = pytest.mark.gpu
 
+# both ways the master evaluates its products: aperture dose matrix (0) and
+# beamlet matrix with the pool map (1)
+MASTERS = pytest.mark.parametrize("master", [0, 1])
+
 
 def _oracle_pool(P, n, seed=0):
     """First n apertures of an oracle solve (a realistic pool)."""
@@ -32,13 +36,14 @@ def _oracle_pool(P, n, seed=0):
     return res["pool"]
 
 
+@MASTERS
 @pytest.mark.parametrize("name,dtype,steps,tol", [("mini", "f64", 30, 1e-9), ("tiny", "f64", 20, 1e-9),
                                                    ("tiny", "f32", 10, 1e-5)])
-def test_master_steps_parity(name, dtype, steps, tol):
+def test_master_steps_parity(name, dtype, steps, tol, master):
     ph = cached_phantom(name)
     P = oracle_problem(ph, dtype)
     pool = _oracle_pool(P, 4)
-    ctx = ctx_for(ph, dtype=dtype)
+    ctx = ctx_for(ph, dtype=dtype, master=master)
     try:
         ctx.reset()
         st = MasterState.empty(P)
@@ -63,8 +68,9 @@ def test_master_steps_parity(name, dtype, steps, tol):
         ctx.close()
 
 
+@MASTERS
 @pytest.mark.parametrize("name,dtype,tol", [("mini", "f64", 1e-9), ("tiny", "f64", 1e-9), ("tiny", "f32", 1e-5)])
-def test_master_converged_parity(name, dtype, tol):
+def test_master_converged_parity(name, dtype, tol, master):
     torch = torch_cuda()
     ph = cached_phantom(name)
     P = oracle_problem(ph, dtype)
@@ -74,7 +80,7 @@ def test_master_converged_parity(name, dtype, tol):
         st.add(ap)
     ktol = 1e-9 if dtype == "f64" else 1e-6
     log = solve_master(P, st, tol=ktol, max_steps=20000)
-    ctx = ctx_for(ph, dtype=dtype)
+    ctx = ctx_for(ph, dtype=dtype, master=master)
     try:
         ctx.reset()
         for ap in pool:
@@ -92,12 +98,18 @@ def test_master_converged_parity(name, dtype, tol):
         ctx.close()
 
 
-def test_solve_tiny_f64_free_running():
+_TINY_REF = {}
+
+
+@MASTERS
+def test_solve_tiny_f64_free_running(master):
     torch = torch_cuda()
     ph = cached_phantom("tiny")
     P = oracle_problem(ph)
-    ref = oracle.solve(P, ph.n_apertures, eps=1e-6)
-    ctx = ctx_for(ph, dtype="f64")
+    if "ref" not in _TINY_REF:
+        _TINY_REF["ref"] = oracle.solve(P, ph.n_apertures, eps=1e-6)
+    ref = _TINY_REF["ref"]
+    ctx = ctx_for(ph, dtype="f64", master=master)
     try:
         out = ctx.solve(ph.n_apertures)
         pool, y = ctx.get_pool()
@@ -118,10 +130,11 @@ def test_solve_tiny_f64_free_running():
         ctx.close()
 
 
-def test_prostate_f32_teacher_forced_rounds():
+@MASTERS
+def test_prostate_f32_teacher_forced_rounds(master):
     ph = cached_phantom("prostate")
     P = oracle_problem(ph)
-    ctx = ctx_for(ph, dtype="f32")
+    ctx = ctx_for(ph, dtype="f32", master=master)
     rounds = 3
     try:
         ctx.reset()
