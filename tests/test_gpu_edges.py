@@ -1,0 +1,101 @@
+"""GPU edge cases and reproducibility of the C ABI.
+
+* a whole solve is bitwise reproducible (fixed-order reductions only);
+* malformed apertures are rejected with DAO_EINVAL, a full pool with
+  DAO_ESTATE, and neither changes the pool;
+* an empty pool is already optimal for the master (no step);
+* an aperture with every row closed adds a zero dose column, and the master
+  leaves it at y = 0 (its gradient is exactly 0);
+* a plan whose prescription asks for no dose stops at once as optimal.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1003_5402_amd as dao
+from conftest import cached_phantom, oracle_problem
+from gpu_util import ctx_for, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("master", [0, 1])
+def test_solve_bitwise_reproducible(master):
+    ph = cached_phantom("tiny")
+    ctx = ctx_for(ph, dtype="f32", master=master)
+    try:
+        a = ctx.solve(6)
+        pa, ya = ctx.get_pool()
+        b = ctx.solve(6)
+        pb, yb = ctx.get_pool()
+        assert pa == pb and np.array_equal(ya, yb)
+        assert a["F"] == b["F"] and np.array_equal(a["round_steps"], b["round_steps"])
+    finally:
+        ctx.close()
+
+
+def test_aperture_validation_and_capacity():
+    ph = cached_phantom("mini")
+    ctx = ctx_for(ph, dtype="f64", max_apertures=2)
+    try:
+        ctx.reset()
+        nr = int(ph.rows_per_beam[0])
+        bad = [
+            (5, [(0, 1)] * nr),                      # beam out of range
+            (0, [(0, 5)] + [(0, 1)] * (nr - 1)),     # R beyond the row
+            (0, [(2, 1)] + [(0, 1)] * (nr - 1)),     # L > R
+            (0, [(1, 1)] + [(0, 1)] * (nr - 1)),     # empty but not (0, 0)
+            (0, [(-1, 2)] + [(0, 1)] * (nr - 1)),    # negative leaf
+        ]
+        for beam, lv in bad:
+            with pytest.raises(dao.DaoError) as e:
+                ctx.add_aperture(beam, lv)
+            assert e.value.status == dao.DAO_EINVAL
+        assert ctx.get_pool()[0] == []
+        ctx.add_aperture(0, [(0, 1)] * nr)
+        ctx.add_aperture(1, [(0, 2)] * int(ph.rows_per_beam[1]))
+        with pytest.raises(dao.DaoError) as e:
+            ctx.add_aperture(0, [(0, 3)] * nr)
+        assert e.value.status == dao.DAO_ESTATE
+        assert len(ctx.get_pool()[0]) == 2
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("master", [0, 1])
+def test_empty_pool_and_closed_aperture(master):
+    ph = cached_phantom("mini")
+    P = oracle_problem(ph)
+    ctx = ctx_for(ph, dtype="f64", master=master)
+    try:
+        ctx.reset()
+        F, kkt, t = ctx.master_step()
+        assert t == 0.0 and kkt == 0.0
+        assert abs(F - oracle.objective(P, np.zeros(P.n_vox))) <= 1e-14
+        nr = int(ph.rows_per_beam[0])
+        ctx.add_aperture(0, [(0, 0)] * nr)           # every row closed: zero dose
+        ctx.add_aperture(1, [(0, 4)] * int(ph.rows_per_beam[1]))
+        steps, kkt, F = ctx.master_solve(1e-12, 5000)
+        pool, y = ctx.get_pool()
+        assert y[0] == 0.0 and y[1] > 0.0
+        st = oracle.MasterState.empty(P)
+        for b, lv in pool:
+            st.add(oracle.Aperture(b, lv))
+        oracle.solve_master(P, st, 1e-12, 5000)
+        assert abs(F - oracle.objective(P, st.d)) <= 1e-9 * F
+    finally:
+        ctx.close()
+
+
+def test_nothing_to_deliver_is_optimal():
+    ph = cached_phantom("mini")
+    pres = [dict(p) for p in ph.prescriptions]
+    pres[0].update(t_under=0.0, w_under=0.0)
+    torch = torch_cuda()
+    ctx = dao.DaoContext(ph.row_ptr, ph.col, ph.val, ph.n_blt, ph.rows_per_beam, ph.row_len, ph.vox_struct,
+                         pres, dtype="f64", stream=torch.cuda.current_stream().cuda_stream)
+    try:
+        out = ctx.solve(5)
+        assert out["rounds"] == 0 and out["stop"] == dao.DAO_EOPTIMAL
+    finally:
+        ctx.close()

@@ -21,7 +21,7 @@ from gpu_util import ctx_for, dev, relerr, tdtype, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
-CASES = [("mini", "f64"), ("tiny", "f64"), ("tiny", "f32"), ("prostate", "f32")]
+CASES = [("mini", "f64"), ("tiny", "f64"), ("tiny", "f32"), ("prostate", "f32"), ("headneck", "f32")]
 
 
 def _tol(dtype):
