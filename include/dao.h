@@ -204,6 +204,22 @@ dao_status dao_get_dose(dao_ctx* ctx, double* d_dev, double* F);
  * only; the master state is left unchanged. */
 dao_status dao_time_product(dao_ctx* ctx, int32_t kernel, int32_t iters, double* us_per_launch);
 
+/* Launch-level measurement of one kernel of the aperture-matrix master
+ * (Section 2.3's master, evaluated as in DAO_MASTER_APERTURE): after
+ * dao_profile_start(ctx, kernel) every launch of that kernel is bracketed by
+ * HIP events on the context stream, and the kernel accumulates its
+ * algorithmic bytes on the device (launches that find nothing to do add
+ * none).  kernel: 0 update pass (apply step, grad F, F, grad_y partials),
+ * 1 q pass (q = D_K p with the line-search evaluation at 0), 2 line-search
+ * pass, 3 direction.  dao_profile_stop synchronises and returns the number
+ * of launches, how many did work, their summed event time (us) and summed
+ * algorithmic bytes, then disables the events.  DAO_ESTATE for the beamlet
+ * master or a stop without a start.  For measurement runs only: the events
+ * add a little host and queue overhead. */
+dao_status dao_profile_start(dao_ctx* ctx, int32_t kernel);
+dao_status dao_profile_stop(dao_ctx* ctx, int64_t* launches, int64_t* working_launches,
+                            double* total_us, double* total_bytes);
+
 /* Per-round log and outcome of dao_solve.  The arrays are caller-owned with
  * room for n_apertures entries each; any may be NULL. */
 typedef struct {

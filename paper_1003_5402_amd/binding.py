@@ -89,6 +89,9 @@ _SIGS = {
     "dao_get_dose": (c_int32, [c_void_p, c_void_p, POINTER(c_double)]),
     "dao_solve": (c_int32, [c_void_p, c_int32, POINTER(dao_plan)]),
     "dao_time_product": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double)]),
+    "dao_profile_start": (c_int32, [c_void_p, c_int32]),
+    "dao_profile_stop": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_double),
+                                   POINTER(c_double)]),
 }
 
 _lib = None
@@ -269,6 +272,14 @@ class DaoContext:
         us = c_double()
         self._check(self._lib.dao_time_product(self._h, int(kernel), int(iters), byref(us)))
         return us.value
+
+    def profile_start(self, kernel: int) -> None:
+        self._check(self._lib.dao_profile_start(self._h, int(kernel)))
+
+    def profile_stop(self) -> Dict:
+        n, w, us, b = c_int64(), c_int64(), c_double(), c_double()
+        self._check(self._lib.dao_profile_stop(self._h, byref(n), byref(w), byref(us), byref(b)))
+        return dict(launches=n.value, working_launches=w.value, total_us=us.value, total_bytes=b.value)
 
     def solve(self, n_apertures: int) -> Dict:
         n = max(1, int(n_apertures))

@@ -71,6 +71,11 @@ struct dao_ctx {
     void* dk = nullptr;        // [Vpad * KS] ctx type: aperture dose matrix (aperture master)
     void* ind = nullptr;       // [N] ctx type: 0/1 beamlet indicator of one aperture
     double* parts2 = nullptr;  // [ap_blocks * (KS + 1)] update records of the aperture master
+    ProfCounters* pc = nullptr;
+    ProfCounters* pc_h = nullptr;      // pinned
+    int prof_kernel = -1;              // aperture-master kernel timed with events (-1: none)
+    std::vector<hipEvent_t> prof_events;
+    size_t prof_used = 0;
     void* g = nullptr;         // [N] ctx type
     double* g64 = nullptr;     // [N]
     void* dx = nullptr;        // [N] ctx type
@@ -104,6 +109,8 @@ struct dao_ctx {
         if (pr_h) (void)hipHostFree(pr_h);
         if (scalar_h) (void)hipHostFree(scalar_h);
         if (lv_stage_h) (void)hipHostFree(lv_stage_h);
+        if (pc_h) (void)hipHostFree(pc_h);
+        for (auto e : prof_events) (void)hipEventDestroy(e);
     }
 
     dao_status fail(dao_status s, std::string m) {
@@ -225,19 +232,49 @@ dao_status enqueue_cycle(dao_ctx* c) {
     return DAO_OK;
 }
 
+// Event pair around one launch of the profiled kernel (when enabled).
+dao_status prof_mark(dao_ctx* c, int kernel, bool before) {
+    if (c->prof_kernel != kernel) return DAO_OK;
+    if (c->prof_used == c->prof_events.size()) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        c->prof_events.push_back(e);
+    }
+    (void)before;
+    HIPCHK(c, hipEventRecord(c->prof_events[c->prof_used++], c->stream));
+    return DAO_OK;
+}
+
 template <class T>
 dao_status enqueue_cycle_ap(dao_ctx* c) {
     const int nb = int(c->ap_blocks());
     const T* dk = static_cast<const T*>(c->dk);
+    dao_status s;
+#define MARK(k, b)                      \
+    do {                                \
+        s = prof_mark(c, k, b);         \
+        if (s != DAO_OK) return s;      \
+    } while (0)
+    MARK(0, true);
     k_upd_ap<T><<<nb, BLOCK, 0, c->stream>>>(dk, c->Vpad, c->d, static_cast<const T*>(c->q), c->cls_int,
-                                              c->classes, c->ncls, c->y, c->parts2, c->ms);
-    k_dir_ap<<<1, 1024, 0, c->stream>>>(c->parts2, nb, c->y, c->p, c->gradk, c->ms);
+                                              c->classes, c->ncls, c->y, c->parts2, c->ms, c->pc, c->Vnz);
+    MARK(0, false);
+    MARK(3, true);
+    k_dir_ap<<<1, 1024, 0, c->stream>>>(c->parts2, nb, c->y, c->p, c->gradk, c->ms, c->pc);
+    MARK(3, false);
+    MARK(1, true);
     k_qstep_ap<T><<<nb, BLOCK, 0, c->stream>>>(dk, c->Vpad, c->d, c->cls_int, c->classes, c->ncls,
-                                                static_cast<T*>(c->q), c->parts, c->arr, c->ms, c->y, c->p);
-    for (int i = 0; i < c->opt.ls_slots; ++i)
+                                                static_cast<T*>(c->q), c->parts, c->arr, c->ms, c->y, c->p,
+                                                c->pc, c->Vnz);
+    MARK(1, false);
+    for (int i = 0; i < c->opt.ls_slots; ++i) {
+        MARK(2, true);
         k_lseval_ap<T><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
             c->d, static_cast<const T*>(c->q), c->cls_int, c->Vpad, c->classes, c->ncls, c->parts, c->arr,
-            c->ms, c->y, c->p);
+            c->ms, c->y, c->p, c->pc, c->Vnz);
+        MARK(2, false);
+    }
+#undef MARK
     LAUNCHCHK(c);
     return DAO_OK;
 }
@@ -422,6 +459,7 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     TRY(dev_alloc(c, &c->parts, c->nparts * sizeof(Rec)));
     TRY(dev_alloc(c, &c->upd_parts, c->slab_blocks() * sizeof(Rec)));
     TRY(dev_alloc(c, &c->arr, sizeof(Arrival)));
+    TRY(dev_alloc(c, &c->pc, sizeof(ProfCounters)));
     if (c->ap_master()) {
         TRY(dev_alloc(c, &c->dk, size_t(c->Vpad) * KS * ts));
         TRY(dev_alloc(c, &c->ind, c->N * ts));
@@ -433,6 +471,8 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     HIPCHK(c, hipHostMalloc((void**)&c->pr_h, sizeof(PriceResult), hipHostMallocDefault));
     HIPCHK(c, hipHostMalloc((void**)&c->scalar_h, 16, hipHostMallocDefault));
     HIPCHK(c, hipHostMalloc((void**)&c->lv_stage_h, size_t(c->maxRB) * 4 + 16, hipHostMallocDefault));
+    HIPCHK(c, hipHostMalloc((void**)&c->pc_h, sizeof(ProfCounters), hipHostMallocDefault));
+    HIPCHK(c, hipMemsetAsync(c->pc, 0, sizeof(ProfCounters), c->stream));
     std::memset(c->ms_h, 0, sizeof(MasterState));
     c->ms_h->done = 1;
     c->ms_h->refresh_every = c->opt.refresh_every;
@@ -821,6 +861,41 @@ dao_status dao_time_product(dao_ctx* c, int32_t kernel, int32_t iters, double* u
         return c->fail(DAO_EINVAL, "kernel must be 0 or 1, iters >= 1");
     return c->dtype == DAO_F64 ? time_product_typed<double>(c, kernel, iters, us_per_launch)
                                : time_product_typed<float>(c, kernel, iters, us_per_launch);
+}
+
+dao_status dao_profile_start(dao_ctx* c, int32_t kernel) {
+    if (!c) return DAO_EINVAL;
+    if (kernel < 0 || kernel > 3) return c->fail(DAO_EINVAL, "kernel must be in [0, 3]");
+    if (!c->ap_master()) return c->fail(DAO_ESTATE, "profiling covers the aperture-matrix master");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemsetAsync(c->pc, 0, sizeof(ProfCounters), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->prof_kernel = kernel;
+    c->prof_used = 0;
+    return DAO_OK;
+}
+
+dao_status dao_profile_stop(dao_ctx* c, int64_t* launches, int64_t* working_launches, double* total_us,
+                            double* total_bytes) {
+    if (!c) return DAO_EINVAL;
+    const int k = c->prof_kernel;
+    if (k < 0) return c->fail(DAO_ESTATE, "profiling was not started");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double us = 0.0;
+    for (size_t i = 0; i + 1 < c->prof_used; i += 2) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->prof_events[i], c->prof_events[i + 1]));
+        us += 1e3 * double(ms);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->pc_h, c->pc, sizeof(ProfCounters), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (launches) *launches = int64_t(c->prof_used / 2);
+    if (working_launches) *working_launches = int64_t(c->pc_h->real[k]);
+    if (total_us) *total_us = us;
+    if (total_bytes) *total_bytes = c->pc_h->bytes[k];
+    c->prof_kernel = -1;
+    c->prof_used = 0;
+    return DAO_OK;
 }
 
 dao_status dao_solve(dao_ctx* c, int32_t n_apertures, dao_plan* out) {

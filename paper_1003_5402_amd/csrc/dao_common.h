@@ -60,6 +60,14 @@ struct MasterState {
     int32_t pad1;
 };
 
+// Work counters of the aperture master's kernels, kept by workgroup 0 of
+// every launch that does work: launches that ran and their algorithmic
+// bytes.  Index: 0 update pass, 1 q pass, 2 line-search pass, 3 direction.
+struct ProfCounters {
+    double bytes[4];
+    uint64_t real[4];
+};
+
 // Pricing result written by the last block of the pricing launch.
 struct PriceResult {
     int32_t beam;

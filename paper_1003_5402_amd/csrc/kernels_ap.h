@@ -107,7 +107,7 @@ __global__ void __launch_bounds__(BLOCK) k_upd_ap(const T* __restrict__ dk, int6
                                                   const uint8_t* __restrict__ cls,
                                                   const ObjClass* __restrict__ classes, int ncls,
                                                   const double* __restrict__ y, double* __restrict__ parts2,
-                                                  const MasterState* ms) {
+                                                  const MasterState* ms, ProfCounters* pc, int64_t Vnz) {
     using G = DKG<T>;
     using V = typename Vec16<T>::type;
     __shared__ int s_skip, s_mode, s_K;
@@ -130,6 +130,13 @@ __global__ void __launch_bounds__(BLOCK) k_upd_ap(const T* __restrict__ dk, int6
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int rg = lane / G::LPR, c = lane % G::LPR;
     const int nc = (K + G::EPL - 1) / G::EPL;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // D_K prefix + class + d read (unless recomputed) + q read (mode 0) + d write (modes 0, 1)
+        const double per_row = 16.0 * nc + 1.0 + (mode != 1 ? 8.0 : 0.0) + (mode == 0 ? double(sizeof(T)) : 0.0) +
+                               (mode != 2 ? 8.0 : 0.0);
+        pc->bytes[0] += per_row * double(Vnz) + double(gridDim.x) * (KS + 1) * 8.0;
+        pc->real[0] += 1;
+    }
     double yv[G::EPL];
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
@@ -193,7 +200,7 @@ __global__ void __launch_bounds__(BLOCK) k_upd_ap(const T* __restrict__ dk, int6
 // longest feasible step.
 __global__ void __launch_bounds__(1024) k_dir_ap(const double* __restrict__ parts2, int nblk,
                                                  const double* __restrict__ y, double* __restrict__ p,
-                                                 double* __restrict__ grad, MasterState* ms) {
+                                                 double* __restrict__ grad, MasterState* ms, ProfCounters* pc) {
     constexpr int SPLIT = 16;   // threads per record column
     __shared__ int s_skip, s_K;
     __shared__ double s_part[KS + 1][SPLIT];
@@ -205,6 +212,10 @@ __global__ void __launch_bounds__(1024) k_dir_ap(const double* __restrict__ part
     __syncthreads();
     if (s_skip) return;
     const int K = s_K;
+    if (threadIdx.x == 0) {
+        pc->bytes[3] += double(nblk) * (K + 1) * 8.0;
+        pc->real[3] += 1;
+    }
     // column j of the records (0: objective, 1 + k: aperture k), summed over
     // workgroups: SPLIT contiguous runs, then the runs in order
     for (int idx = threadIdx.x; idx < (K + 1) * SPLIT; idx += blockDim.x) {
@@ -297,7 +308,8 @@ __global__ void __launch_bounds__(BLOCK) k_qstep_ap(const T* __restrict__ dk, in
                                                     const uint8_t* __restrict__ cls,
                                                     const ObjClass* __restrict__ classes, int ncls,
                                                     T* __restrict__ q, Rec* parts, Arrival* arr,
-                                                    MasterState* ms, double* y, const double* p) {
+                                                    MasterState* ms, double* y, const double* p,
+                                                    ProfCounters* pc, int64_t Vnz) {
     using G = DKG<T>;
     using V = typename Vec16<T>::type;
     __shared__ int s_skip, s_K;
@@ -317,6 +329,11 @@ __global__ void __launch_bounds__(BLOCK) k_qstep_ap(const T* __restrict__ dk, in
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int rg = lane / G::LPR, c = lane % G::LPR;
     const int nc = (K + G::EPL - 1) / G::EPL;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // D_K prefix + d + class read, q write
+        pc->bytes[1] += (16.0 * nc + 8.0 + 1.0 + double(sizeof(T))) * double(Vnz);
+        pc->real[1] += 1;
+    }
     double pv[G::EPL];
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
@@ -359,7 +376,7 @@ __global__ void __launch_bounds__(BLOCK) k_lseval_ap(const double* __restrict__ 
                                                      const uint8_t* __restrict__ cls, int64_t Vpad,
                                                      const ObjClass* __restrict__ classes, int ncls,
                                                      Rec* parts, Arrival* arr, MasterState* ms, double* y,
-                                                     const double* p) {
+                                                     const double* p, ProfCounters* pc, int64_t Vnz) {
     __shared__ int s_skip;
     __shared__ double s_t;
     __shared__ ObjClass cl[256];
@@ -371,6 +388,10 @@ __global__ void __launch_bounds__(BLOCK) k_lseval_ap(const double* __restrict__ 
     if (s_skip) return;
     for (int i = threadIdx.x; i < ncls; i += blockDim.x) cl[i] = classes[i];
     __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        pc->bytes[2] += (8.0 + double(sizeof(T)) + 1.0) * double(Vnz);
+        pc->real[2] += 1;
+    }
     const double t = s_t;
     Rec r = rec_identity();
     for (int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x; i < Vpad; i += int64_t(gridDim.x) * BLOCK)
