@@ -74,6 +74,7 @@ struct dao_ctx {
     ProfCounters* pc = nullptr;
     ProfCounters* pc_h = nullptr;      // pinned
     int prof_kernel = -1;              // aperture-master kernel timed with events (-1: none)
+    int last_steps = 0;                // steps of the previous master solve (chunk size guess)
     std::vector<hipEvent_t> prof_events;
     size_t prof_used = 0;
     void* g = nullptr;         // [N] ctx type
@@ -303,7 +304,9 @@ dao_status run_master(dao_ctx* c, double tol, int max_steps) {
     const int64_t max_cycles =
         int64_t(max_steps + 1) * (LS_MAX_ITER / std::max(1, c->opt.ls_slots) + 2) + 16;
     int64_t cycles = 0;
-    int chunk = 2;
+    // the previous solve's step count predicts this one (rounds of one plan
+    // grow slowly); after that first guess, grow geometrically
+    int chunk = std::max(2, std::min(max_steps + 1, int(0.9 * c->last_steps)));
     for (;;) {
         for (int i = 0; i < chunk; ++i) {
             dao_status s = c->ap_master() ? enqueue_cycle_ap<T>(c) : enqueue_cycle<T>(c);
@@ -314,8 +317,9 @@ dao_status run_master(dao_ctx* c, double tol, int max_steps) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
         if (c->ms_h->done) break;
         if (cycles > max_cycles) return c->fail(DAO_EDEVICE, "master state machine made no progress");
-        chunk = std::min(chunk * 2, 32);
+        chunk = std::max(4, std::min(32, (max_steps - c->ms_h->steps) / 4 + 4));
     }
+    c->last_steps = c->ms_h->steps;
     return DAO_OK;
 }
 
