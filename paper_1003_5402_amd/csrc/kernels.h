@@ -161,6 +161,24 @@ __device__ __forceinline__ bool arrive_and_reduce(Rec mine, Rec* parts, Arrival*
     return true;
 }
 
+// The device-resident master state is read and written through an LDS copy:
+// one parallel load and one parallel store per launch instead of a chain of
+// dependent single-field accesses (each of which may cross XCDs).
+constexpr int MS_WORDS = int(sizeof(MasterState) / 8);
+static_assert(sizeof(MasterState) % 8 == 0, "state is copied in 8-byte words");
+
+__device__ __forceinline__ void ms_load(MasterState& s, const MasterState* g) {
+    if (threadIdx.x < MS_WORDS)
+        reinterpret_cast<uint64_t*>(&s)[threadIdx.x] = reinterpret_cast<const uint64_t*>(g)[threadIdx.x];
+    __syncthreads();
+}
+
+__device__ __forceinline__ void ms_store(MasterState* g, const MasterState& s) {
+    __syncthreads();
+    if (threadIdx.x < MS_WORDS)
+        reinterpret_cast<uint64_t*>(g)[threadIdx.x] = reinterpret_cast<const uint64_t*>(&s)[threadIdx.x];
+}
+
 // Contribution of one voxel to the line-search evaluation at step t:
 // phi'(t) = sum q_j dF/dz_j(d_j + t q_j); slopes of phi' just right / left of
 // t (without the factor 2); nearest breakpoint above / below t.
@@ -571,10 +589,12 @@ __global__ void __launch_bounds__(1024) k_dir(PoolView P, const T* __restrict__ 
     __shared__ double s_p[MAX_APERTURES];
     __shared__ double s_y[MAX_APERTURES];
     __shared__ int32_t s_beam[MAX_APERTURES];
+    __shared__ MasterState s_ms;
+    ms_load(s_ms, ms);
     if (threadIdx.x == 0) {
-        s_skip = ms->done || !(ms->phase == PH_DIR || ms->phase == PH_UPD);
-        s_upd = ms->phase == PH_UPD;
-        s_K = ms->K;
+        s_skip = s_ms.done || !(s_ms.phase == PH_DIR || s_ms.phase == PH_UPD);
+        s_upd = s_ms.phase == PH_UPD;
+        s_K = s_ms.K;
     }
     __syncthreads();
     if (s_skip) return;
@@ -586,7 +606,7 @@ __global__ void __launch_bounds__(1024) k_dir(PoolView P, const T* __restrict__ 
         const int b0 = threadIdx.x * per, b1 = min(n_upd, b0 + per);
         for (int b = b0; b < b1; ++b) acc.s5 += upd_parts[b].s5;
         const Rec t = block_reduce(acc);
-        if (threadIdx.x == 0) ms->F = ms->F_const + t.s5;
+        if (threadIdx.x == 0) s_ms.F = s_ms.F_const + t.s5;
     }
     // stage g and the pool
     T* gs_l = reinterpret_cast<T*>(smem);
@@ -625,13 +645,13 @@ __global__ void __launch_bounds__(1024) k_dir(PoolView P, const T* __restrict__ 
     if (threadIdx.x == 0) {
         double kkt = 0.0;
         for (int k = 0; k < K; ++k) kkt = fmax(kkt, fabs(fmin(s_y[k], s_grad[k])));
-        ms->kkt = kkt;
+        s_ms.kkt = kkt;
         int go = 1;
-        if (!(kkt > ms->tol)) {
-            ms->stop_reason = 1;
+        if (!(kkt > s_ms.tol)) {
+            s_ms.stop_reason = 1;
             go = 0;
-        } else if (ms->steps >= ms->max_steps) {
-            ms->stop_reason = 2;
+        } else if (s_ms.steps >= s_ms.max_steps) {
+            s_ms.stop_reason = 2;
             go = 0;
         }
         double tmax = INFINITY, gp = 0.0;
@@ -648,39 +668,41 @@ __global__ void __launch_bounds__(1024) k_dir(PoolView P, const T* __restrict__ 
                 gp += s_grad[k] * pk;
             }
             if (!any) {
-                ms->stop_reason = 3;
+                s_ms.stop_reason = 3;
                 go = 0;
             }
         }
         if (!go) {
-            ms->done = 1;
-            ms->phase = PH_DIR;
+            s_ms.done = 1;
+            s_ms.phase = PH_DIR;
         } else {
-            ms->t_max = tmax;
-            ms->gphi0 = gp;
-            ms->t = 0.0;
-            ms->lo = 0.0;
-            ms->hi = tmax;
-            ms->hi_known = 0;
-            ms->ls_iter = 0;
+            s_ms.t_max = tmax;
+            s_ms.gphi0 = gp;
+            s_ms.t = 0.0;
+            s_ms.lo = 0.0;
+            s_ms.hi = tmax;
+            s_ms.hi_known = 0;
+            s_ms.ls_iter = 0;
         }
         s_go = go;
     }
     __syncthreads();
-    if (!s_go) return;
-    for (int i = threadIdx.x; i < P.N; i += blockDim.x) dx[i] = T(pool_at_beamlet(P, K, s_beam, lvs, s_p, i));
-    __syncthreads();
-    if (threadIdx.x == 0) ms->phase = PH_Q;
+    if (s_go) {
+        for (int i = threadIdx.x; i < P.N; i += blockDim.x) dx[i] = T(pool_at_beamlet(P, K, s_beam, lvs, s_p, i));
+        __syncthreads();
+        if (threadIdx.x == 0) s_ms.phase = PH_Q;
+    }
+    ms_store(ms, s_ms);
 }
 
-// Line-search decision after an evaluation at ms->t (thread 0 of the last
-// block).  Returns 1 when the step is final (ms->t holds it), 0 when ms->t
-// holds the next trial point.
-__device__ __forceinline__ int ls_decide(MasterState* ms, const Rec& e) {
-    const double t = ms->t, tmax = ms->t_max;
+// Line-search decision after an evaluation at m.t (thread 0 of the last
+// block, on the LDS copy of the state).  Returns 1 when the step is final
+// (m.t holds it), 0 when m.t holds the next trial point.
+__device__ __forceinline__ int ls_decide(MasterState& m, const Rec& e) {
+    const double t = m.t, tmax = m.t_max;
     const double gphi = e.s0, s_r = 2.0 * e.s1, s_l = 2.0 * e.s2, nb = e.mn, pb = e.mx;
-    ms->ls_iter += 1;
-    ms->total_ls += 1;
+    m.ls_iter += 1;
+    m.total_ls += 1;
     int fin = 0;
     double tf = 0.0, nxt = 0.0;
     if (gphi == 0.0) {
@@ -691,7 +713,7 @@ __device__ __forceinline__ int ls_decide(MasterState* ms, const Rec& e) {
             fin = 1;
             tf = tmax;
         } else {
-            ms->lo = t;
+            m.lo = t;
             const double tn = s_r > 0.0 ? t - gphi / s_r : INFINITY;
             if (tn <= nb) {
                 fin = 1;
@@ -700,43 +722,43 @@ __device__ __forceinline__ int ls_decide(MasterState* ms, const Rec& e) {
                 fin = 1;
                 tf = tmax;
             } else {
-                if (tn < ms->hi)
+                if (tn < m.hi)
                     nxt = tn;
-                else if (!ms->hi_known)
-                    nxt = ms->hi;
+                else if (!m.hi_known)
+                    nxt = m.hi;
                 else
-                    nxt = 0.5 * (ms->lo + ms->hi);
+                    nxt = 0.5 * (m.lo + m.hi);
                 if (isinf(nxt)) nxt = nb;
             }
         }
     } else {
-        ms->hi = t;
-        ms->hi_known = 1;
+        m.hi = t;
+        m.hi_known = 1;
         const double tn = s_l > 0.0 ? t - gphi / s_l : -INFINITY;
         if (tn >= pb) {
             fin = 1;
-            tf = fmax(tn, ms->lo);
+            tf = fmax(tn, m.lo);
         } else {
-            nxt = tn > ms->lo ? tn : 0.5 * (ms->lo + ms->hi);
+            nxt = tn > m.lo ? tn : 0.5 * (m.lo + m.hi);
         }
     }
-    if (!fin && ms->ls_iter >= LS_MAX_ITER) {
+    if (!fin && m.ls_iter >= LS_MAX_ITER) {
         fin = 1;
-        tf = ms->lo;
+        tf = m.lo;
     }
-    ms->t = fin ? tf : nxt;
+    m.t = fin ? tf : nxt;
     return fin;
 }
 
 // Final step of a line search (all threads of the last block): y update with
 // exact zeros for blocking apertures, step count, refresh of x = A y.
-__device__ __forceinline__ void finish_step(const PoolView& P, MasterState* ms, double* y,
+__device__ __forceinline__ void finish_step(const PoolView& P, MasterState& m, double* y,
                                             const double* p, double* x64, int fin) {
     __shared__ int s_refresh;
     __shared__ double s_y[MAX_APERTURES];
     if (!fin) return;
-    const int K = ms->K;
-    const double t = ms->t, tmax = ms->t_max;
+    const int K = m.K;
+    const double t = m.t, tmax = m.t_max;
     for (int k = threadIdx.x; k < K; k += blockDim.x) {
         const double pk = p[k];
         const double ratio = pk < 0.0 ? y[k] / (-pk) : INFINITY;
@@ -748,18 +770,18 @@ __device__ __forceinline__ void finish_step(const PoolView& P, MasterState* ms, 
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        ms->steps += 1;
-        ms->total_steps += 1;
-        ms->last_step = t;
-        ms->refresh = (ms->steps % ms->refresh_every) == 0;
-        s_refresh = ms->refresh;
+        m.steps += 1;
+        m.total_steps += 1;
+        m.last_step = t;
+        m.refresh = (m.steps % m.refresh_every) == 0;
+        s_refresh = m.refresh;
     }
     __syncthreads();
     if (s_refresh)
         for (int i = threadIdx.x; i < P.N; i += blockDim.x)
             x64[i] = pool_at_beamlet(P, K, P.ap_beam, P.ap_lv, s_y, i);
     __syncthreads();
-    if (threadIdx.x == 0) ms->phase = PH_UPD;
+    if (threadIdx.x == 0) m.phase = PH_UPD;
 }
 
 // q = D dx and the line-search evaluation at t = 0 (slab layout).
@@ -796,13 +818,16 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_qstep(SellView<T> S, int64_t V
     Rec tot;
     const Rec mine = block_reduce(r);
     if (!arrive_and_reduce(mine, parts, arr, &tot)) return;
+    __shared__ MasterState s_ms;
     __shared__ int s_fin;
+    ms_load(s_ms, ms);
     if (threadIdx.x == 0) {
-        s_fin = ls_decide(ms, tot);
-        if (!s_fin) ms->phase = PH_LS;
+        s_fin = ls_decide(s_ms, tot);
+        if (!s_fin) s_ms.phase = PH_LS;
     }
     __syncthreads();
-    finish_step(P, ms, y, p, x64, s_fin);
+    finish_step(P, s_ms, y, p, x64, s_fin);
+    ms_store(ms, s_ms);
 }
 
 // Further line-search evaluations at ms->t.
@@ -836,10 +861,13 @@ __global__ void __launch_bounds__(BLOCK) k_lseval(const double* __restrict__ d, 
     Rec tot;
     const Rec mine = block_reduce(r);
     if (!arrive_and_reduce(mine, parts, arr, &tot)) return;
+    __shared__ MasterState s_ms;
     __shared__ int s_fin;
-    if (threadIdx.x == 0) s_fin = ls_decide(ms, tot);
+    ms_load(s_ms, ms);
+    if (threadIdx.x == 0) s_fin = ls_decide(s_ms, tot);
     __syncthreads();
-    finish_step(P, ms, y, p, x64, s_fin);
+    finish_step(P, s_ms, y, p, x64, s_fin);
+    ms_store(ms, s_ms);
 }
 
 // Update (slab layout): d += t q (or d = D x64 on refresh steps),

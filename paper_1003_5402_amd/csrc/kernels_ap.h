@@ -62,6 +62,15 @@ __device__ __forceinline__ double2 vzero<double2>() {
     return make_double2(0.0, 0.0);
 }
 
+// Order LDS traffic between lanes of one wavefront (used inside loops whose
+// trip count differs between the wavefronts of a workgroup, where a
+// workgroup barrier would be wrong).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Sum over the LPR lanes of one row (aligned lane groups); all get the sum.
 template <int LPR>
 __device__ __forceinline__ double group_sum(double v) {
@@ -99,6 +108,18 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_dk_column(SellView<T> S, int64
     if (threadIdx.x < SLAB && row < Vpad) dk[row * KS + k] = T(sum);
 }
 
+// Rows are processed in batches of BATCH = ITERS * RPW consecutive rows per
+// wavefront.  Each lane first issues all ITERS of its 16-byte D_K loads for
+// the batch (lane group rg holds rows rg, rg + RPW, ...; lane c of the group
+// holds aperture slots c*EPL .. c*EPL+EPL-1), then the batch is handled one
+// row per lane for the per-voxel work (coalesced d, q and class access, all
+// lanes active), with row results exchanged through LDS.
+template <class T>
+struct Batch {
+    static constexpr int ITERS = 16;
+    static constexpr int ROWS = ITERS * DKG<T>::RPW;   // 64 (FP32) or 32 (FP64)
+};
+
 // Update pass (PH_UPD).  Record of workgroup b in parts2[b * (KS + 1)]:
 // [objective partial, grad_y partial for apertures 0..KS-1].
 template <class T>
@@ -110,11 +131,14 @@ __global__ void __launch_bounds__(BLOCK) k_upd_ap(const T* __restrict__ dk, int6
                                                   const MasterState* ms, ProfCounters* pc, int64_t Vnz) {
     using G = DKG<T>;
     using V = typename Vec16<T>::type;
+    constexpr int IT = Batch<T>::ITERS, ROWS = Batch<T>::ROWS;
+    constexpr int NW = BLOCK / WAVE;
     __shared__ int s_skip, s_mode, s_K;
     __shared__ double s_t;
     __shared__ ObjClass cl[256];
-    __shared__ double s_acc[BLOCK / WAVE][KS];
-    __shared__ double s_F[BLOCK / WAVE];
+    __shared__ double s_acc[NW][KS];
+    __shared__ double s_F[NW];
+    __shared__ double s_u[NW][ROWS];
     if (threadIdx.x == 0) {
         s_skip = (ms->done || ms->phase != PH_UPD);
         s_mode = ms->refresh;
@@ -147,30 +171,52 @@ __global__ void __launch_bounds__(BLOCK) k_upd_ap(const T* __restrict__ dk, int6
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) acc[e] = 0.0;
     double Fp = 0.0;
-    const int64_t nw = int64_t(gridDim.x) * (BLOCK / WAVE);
-    const int64_t gw = int64_t(blockIdx.x) * (BLOCK / WAVE) + wave;
-    for (int64_t row0 = gw * G::RPW; row0 < Vpad; row0 += nw * G::RPW) {
-        const int64_t row = row0 + rg;
-        V v = vzero<V>();
-        if (c < nc) v = reinterpret_cast<const V*>(dk + row * KS)[c];
-        double dn;
-        if (mode == 1) {
-            double part = 0.0;
+    double* su = s_u[wave];
+    const int64_t nw = int64_t(gridDim.x) * NW;
+    for (int64_t base = (int64_t(blockIdx.x) * NW + wave) * ROWS; base < Vpad; base += nw * ROWS) {
+        // 1. all D_K loads of the batch
+        V v[IT];
 #pragma unroll
-            for (int e = 0; e < G::EPL; ++e) part += vget(v, e) * yv[e];
-            dn = group_sum<G::LPR>(part);
-        } else {
-            dn = d[row];
-            if (mode == 0) dn = dn + t * double(q[row]);
+        for (int it = 0; it < IT; ++it) {
+            v[it] = vzero<V>();
+            if (c < nc) v[it] = reinterpret_cast<const V*>(dk + (base + it * G::RPW + rg) * KS)[c];
         }
-        const ObjClass cc = cl[cls[row]];
-        const double u = grad_f(cc, dn);
-        if (c == 0) {
+        // 2. refresh: d = D_K y for the batch's rows
+        if (mode == 1) {
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                double part = 0.0;
+#pragma unroll
+                for (int e = 0; e < G::EPL; ++e) part += vget(v[it], e) * yv[e];
+                part = group_sum<G::LPR>(part);
+                if (c == 0) su[it * G::RPW + rg] = part;
+            }
+        }
+        wave_sync();
+        // 3. one row per lane: new dose, dF/dz, objective
+        if (lane < ROWS) {
+            const int64_t row = base + lane;
+            double dn;
+            if (mode == 1) {
+                dn = su[lane];
+            } else {
+                dn = d[row];
+                if (mode == 0) dn = dn + t * double(q[row]);
+            }
+            const ObjClass cc = cl[cls[row]];
             if (mode != 2) d[row] = dn;
             Fp += obj_f(cc, dn);
+            su[lane] = grad_f(cc, dn);
         }
+        wave_sync();
+        // 4. grad_y partials: u_row * D_K[row][k]
 #pragma unroll
-        for (int e = 0; e < G::EPL; ++e) acc[e] += u * vget(v, e);
+        for (int it = 0; it < IT; ++it) {
+            const double u = su[it * G::RPW + rg];
+#pragma unroll
+            for (int e = 0; e < G::EPL; ++e) acc[e] += u * vget(v[it], e);
+        }
+        wave_sync();   // su is rewritten by the next batch
     }
     // lanes holding the same aperture slots: combine the wave's row groups
 #pragma unroll
@@ -185,33 +231,32 @@ __global__ void __launch_bounds__(BLOCK) k_upd_ap(const T* __restrict__ dk, int6
     __syncthreads();
     double* rec = parts2 + size_t(blockIdx.x) * (KS + 1);
     if (threadIdx.x < KS) {
-        double s = 0.0;
-        for (int w = 0; w < BLOCK / WAVE; ++w) s += s_acc[w][threadIdx.x];
-        rec[1 + threadIdx.x] = s;
+        double sacc = 0.0;
+        for (int w = 0; w < NW; ++w) sacc += s_acc[w][threadIdx.x];
+        rec[1 + threadIdx.x] = sacc;
     } else if (threadIdx.x == KS) {
-        double s = 0.0;
-        for (int w = 0; w < BLOCK / WAVE; ++w) s += s_F[w];
-        rec[0] = s;
+        double sacc = 0.0;
+        for (int w = 0; w < NW; ++w) sacc += s_F[w];
+        rec[0] = sacc;
     }
 }
 
 // Direction step (single block, 1024 threads, PH_UPD): F and grad_y from
 // the update's partials (fixed order), KKT test, projected direction,
-// longest feasible step.
+// longest feasible step.  One wavefront handles the (at most 64) apertures.
 __global__ void __launch_bounds__(1024) k_dir_ap(const double* __restrict__ parts2, int nblk,
                                                  const double* __restrict__ y, double* __restrict__ p,
                                                  double* __restrict__ grad, MasterState* ms, ProfCounters* pc) {
     constexpr int SPLIT = 16;   // threads per record column
-    __shared__ int s_skip, s_K;
+    __shared__ MasterState s_ms;
+    __shared__ int s_skip;
     __shared__ double s_part[KS + 1][SPLIT];
     __shared__ double s_red[KS + 1];
-    if (threadIdx.x == 0) {
-        s_skip = ms->done || ms->phase != PH_UPD;
-        s_K = ms->K;
-    }
+    ms_load(s_ms, ms);
+    if (threadIdx.x == 0) s_skip = s_ms.done || s_ms.phase != PH_UPD;
     __syncthreads();
     if (s_skip) return;
-    const int K = s_K;
+    const int K = s_ms.K;
     if (threadIdx.x == 0) {
         pc->bytes[3] += double(nblk) * (K + 1) * 8.0;
         pc->real[3] += 1;
@@ -222,68 +267,70 @@ __global__ void __launch_bounds__(1024) k_dir_ap(const double* __restrict__ part
         const int j = idx / SPLIT, part = idx % SPLIT;
         const int per = (nblk + SPLIT - 1) / SPLIT;
         const int b0 = part * per, b1 = min(nblk, b0 + per);
-        double s = 0.0;
-        for (int b = b0; b < b1; ++b) s += parts2[size_t(b) * (KS + 1) + j];
-        s_part[j][part] = s;
+        double sacc = 0.0;
+        for (int b = b0; b < b1; ++b) sacc += parts2[size_t(b) * (KS + 1) + j];
+        s_part[j][part] = sacc;
     }
     __syncthreads();
     if (threadIdx.x <= K) {
-        double s = 0.0;
-        for (int q = 0; q < SPLIT; ++q) s += s_part[threadIdx.x][q];
-        s_red[threadIdx.x] = s;
+        double sacc = 0.0;
+        for (int qq = 0; qq < SPLIT; ++qq) sacc += s_part[threadIdx.x][qq];
+        s_red[threadIdx.x] = sacc;
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    ms->F = ms->F_const + s_red[0];
-    double kkt = 0.0;
-    for (int k = 0; k < K; ++k) kkt = fmax(kkt, fabs(fmin(y[k], s_red[1 + k])));
-    ms->kkt = kkt;
-    int go = 1;
-    if (!(kkt > ms->tol)) {
-        ms->stop_reason = 1;
-        go = 0;
-    } else if (ms->steps >= ms->max_steps) {
-        ms->stop_reason = 2;
-        go = 0;
-    }
-    double tmax = INFINITY, gp = 0.0;
-    int any = 0;
-    if (go) {
-        for (int k = 0; k < K; ++k) {
-            const double gk = s_red[1 + k];
-            double pk = -gk;
-            if (y[k] == 0.0 && gk >= 0.0) pk = 0.0;
+    if (threadIdx.x < WAVE) {
+        const int k = threadIdx.x;
+        const bool in = k < K;
+        const double yk = in ? y[k] : 0.0;
+        const double gk = in ? s_red[1 + k] : 0.0;
+        double pk = -gk;
+        if (!in || (yk == 0.0 && gk >= 0.0)) pk = 0.0;
+        const double kkt = wave_max(in ? fabs(fmin(yk, gk)) : 0.0);
+        const double tmax = wave_min(pk < 0.0 ? yk / (-pk) : INFINITY);
+        const double gp = wave_sum(gk * pk);
+        const bool any = __any(pk != 0.0);
+        if (in) {
             p[k] = pk;
             grad[k] = gk;
-            if (pk != 0.0) any = 1;
-            if (pk < 0.0) tmax = fmin(tmax, y[k] / (-pk));
-            gp += gk * pk;
         }
-        if (!any) {
-            ms->stop_reason = 3;
-            go = 0;
+        if (k == 0) {
+            s_ms.F = s_ms.F_const + s_red[0];
+            s_ms.kkt = kkt;
+            int go = 1;
+            if (!(kkt > s_ms.tol)) {
+                s_ms.stop_reason = 1;
+                go = 0;
+            } else if (s_ms.steps >= s_ms.max_steps) {
+                s_ms.stop_reason = 2;
+                go = 0;
+            } else if (!any) {
+                s_ms.stop_reason = 3;
+                go = 0;
+            }
+            if (!go) {
+                s_ms.done = 1;
+            } else {
+                s_ms.t_max = tmax;
+                s_ms.gphi0 = gp;
+                s_ms.t = 0.0;
+                s_ms.lo = 0.0;
+                s_ms.hi = tmax;
+                s_ms.hi_known = 0;
+                s_ms.ls_iter = 0;
+                s_ms.phase = PH_Q;
+            }
         }
     }
-    if (!go) {
-        ms->done = 1;
-        return;
-    }
-    ms->t_max = tmax;
-    ms->gphi0 = gp;
-    ms->t = 0.0;
-    ms->lo = 0.0;
-    ms->hi = tmax;
-    ms->hi_known = 0;
-    ms->ls_iter = 0;
-    ms->phase = PH_Q;
+    ms_store(ms, s_ms);
 }
 
-// Final step of a line search in the aperture master (last block): y
-// update with exact zeros for blocking apertures, step count, update mode.
-__device__ __forceinline__ void finish_step_ap(MasterState* ms, double* y, const double* p, int fin) {
+// Final step of a line search in the aperture master (last block, on the
+// LDS copy of the state): y update with exact zeros for blocking apertures,
+// step count, update mode.
+__device__ __forceinline__ void finish_step_ap(MasterState& m, double* y, const double* p, int fin) {
     if (!fin) return;
-    const int K = ms->K;
-    const double t = ms->t, tmax = ms->t_max;
+    const int K = m.K;
+    const double t = m.t, tmax = m.t_max;
     for (int k = threadIdx.x; k < K; k += blockDim.x) {
         const double pk = p[k];
         const double ratio = pk < 0.0 ? y[k] / (-pk) : INFINITY;
@@ -293,11 +340,11 @@ __device__ __forceinline__ void finish_step_ap(MasterState* ms, double* y, const
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        ms->steps += 1;
-        ms->total_steps += 1;
-        ms->last_step = t;
-        ms->refresh = (ms->steps % ms->refresh_every) == 0 ? 1 : 0;
-        ms->phase = PH_UPD;
+        m.steps += 1;
+        m.total_steps += 1;
+        m.last_step = t;
+        m.refresh = (m.steps % m.refresh_every) == 0 ? 1 : 0;
+        m.phase = PH_UPD;
     }
 }
 
@@ -312,9 +359,12 @@ __global__ void __launch_bounds__(BLOCK) k_qstep_ap(const T* __restrict__ dk, in
                                                     ProfCounters* pc, int64_t Vnz) {
     using G = DKG<T>;
     using V = typename Vec16<T>::type;
+    constexpr int IT = Batch<T>::ITERS, ROWS = Batch<T>::ROWS;
+    constexpr int NW = BLOCK / WAVE;
     __shared__ int s_skip, s_K;
     __shared__ double s_t;
     __shared__ ObjClass cl[256];
+    __shared__ double s_q[NW][ROWS];
     if (threadIdx.x == 0) {
         s_skip = (ms->done || ms->phase != PH_Q);
         s_K = ms->K;
@@ -341,32 +391,45 @@ __global__ void __launch_bounds__(BLOCK) k_qstep_ap(const T* __restrict__ dk, in
         pv[e] = k < K ? p[k] : 0.0;
     }
     Rec r = rec_identity();
-    const int64_t nw = int64_t(gridDim.x) * (BLOCK / WAVE);
-    const int64_t gw = int64_t(blockIdx.x) * (BLOCK / WAVE) + wave;
-    for (int64_t row0 = gw * G::RPW; row0 < Vpad; row0 += nw * G::RPW) {
-        const int64_t row = row0 + rg;
-        V v = vzero<V>();
-        if (c < nc) v = reinterpret_cast<const V*>(dk + row * KS)[c];
-        double part = 0.0;
+    double* sq = s_q[wave];
+    const int64_t nw = int64_t(gridDim.x) * NW;
+    for (int64_t base = (int64_t(blockIdx.x) * NW + wave) * ROWS; base < Vpad; base += nw * ROWS) {
+        V v[IT];
 #pragma unroll
-        for (int e = 0; e < G::EPL; ++e) part += vget(v, e) * pv[e];
-        const double qd = group_sum<G::LPR>(part);
-        if (c == 0) {
-            const T qt = T(qd);   // the line search and the update use the stored value
+        for (int it = 0; it < IT; ++it) {
+            v[it] = vzero<V>();
+            if (c < nc) v[it] = reinterpret_cast<const V*>(dk + (base + it * G::RPW + rg) * KS)[c];
+        }
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            double part = 0.0;
+#pragma unroll
+            for (int e = 0; e < G::EPL; ++e) part += vget(v[it], e) * pv[e];
+            part = group_sum<G::LPR>(part);
+            if (c == 0) sq[it * G::RPW + rg] = part;
+        }
+        wave_sync();
+        if (lane < ROWS) {
+            const int64_t row = base + lane;
+            const T qt = T(sq[lane]);   // the line search and the update use the stored value
             q[row] = qt;
             ls_voxel(cl[cls[row]], d[row], double(qt), t, r);
         }
+        wave_sync();   // sq is rewritten by the next batch
     }
     Rec tot;
     const Rec mine = block_reduce(r);
     if (!arrive_and_reduce(mine, parts, arr, &tot)) return;
+    __shared__ MasterState s_ms;
     __shared__ int s_fin;
+    ms_load(s_ms, ms);
     if (threadIdx.x == 0) {
-        s_fin = ls_decide(ms, tot);
-        if (!s_fin) ms->phase = PH_LS;
+        s_fin = ls_decide(s_ms, tot);
+        if (!s_fin) s_ms.phase = PH_LS;
     }
     __syncthreads();
-    finish_step_ap(ms, y, p, s_fin);
+    finish_step_ap(s_ms, y, p, s_fin);
+    ms_store(ms, s_ms);
 }
 
 // Line-search evaluations of the aperture master (PH_LS); same evaluation
@@ -399,10 +462,13 @@ __global__ void __launch_bounds__(BLOCK) k_lseval_ap(const double* __restrict__ 
     Rec tot;
     const Rec mine = block_reduce(r);
     if (!arrive_and_reduce(mine, parts, arr, &tot)) return;
+    __shared__ MasterState s_ms;
     __shared__ int s_fin;
-    if (threadIdx.x == 0) s_fin = ls_decide(ms, tot);
+    ms_load(s_ms, ms);
+    if (threadIdx.x == 0) s_fin = ls_decide(s_ms, tot);
     __syncthreads();
-    finish_step_ap(ms, y, p, s_fin);
+    finish_step_ap(s_ms, y, p, s_fin);
+    ms_store(ms, s_ms);
 }
 
 // Reset for a solve of the aperture master: the first update pass keeps d
