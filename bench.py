@@ -127,7 +127,13 @@ def main():
     # device.  Plans are deterministic, so each instrumented plan repeats
     # exactly the launches of a timed plan.
     kernels = {}
-    for kid, kname in [(0, "k_upd_ap"), (1, "k_qstep_ap"), (2, "k_lseval_ap"), (3, "k_dir_ap")]:
+    try:
+        ctx.profile_start(4)
+        ctx.profile_stop()
+        plist = [(4, "k_master_coop")]
+    except dao.DaoError:
+        plist = [(0, "k_upd_ap"), (1, "k_qstep_ap"), (2, "k_lseval_ap"), (3, "k_dir_ap")]
+    for kid, kname in plist:
         ctx.profile_start(kid)
         ctx.solve(n_ap)
         r = ctx.profile_stop()

@@ -107,6 +107,9 @@ typedef struct {
     int32_t ls_slots;       /* line-search launches per master cycle (2) */
     int64_t mem_cap_bytes;  /* fail dao_create with DAO_ENOMEM above this device footprint; 0 = none */
     int32_t master;         /* DAO_MASTER_APERTURE (default) or DAO_MASTER_BEAMLET, see below */
+    int32_t persistent;     /* aperture master: 1 (default) runs each master solve as one
+                               cooperative launch when the device supports it; 0 launches
+                               each phase of each step separately */
 } dao_options;
 
 /* How the restricted master evaluates its two products per step.
@@ -211,7 +214,8 @@ dao_status dao_time_product(dao_ctx* ctx, int32_t kernel, int32_t iters, double*
  * algorithmic bytes on the device (launches that find nothing to do add
  * none).  kernel: 0 update pass (apply step, grad F, F, grad_y partials),
  * 1 q pass (q = D_K p with the line-search evaluation at 0), 2 line-search
- * pass, 3 direction.  dao_profile_stop synchronises and returns the number
+ * pass, 3 direction, 4 the persistent master (one launch per master solve;
+ * its bytes are the sum over its update, q and line-search passes).  dao_profile_stop synchronises and returns the number
  * of launches, how many did work, their summed event time (us) and summed
  * algorithmic bytes, then disables the events.  DAO_ESTATE for the beamlet
  * master or a stop without a start.  For measurement runs only: the events

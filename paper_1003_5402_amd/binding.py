@@ -46,7 +46,7 @@ class dao_options(ctypes.Structure):
     _fields_ = [("dtype", c_int32), ("max_apertures", c_int32), ("eps", c_double),
                 ("max_steps", c_int32), ("tau_rel", c_double), ("max_tighten", c_int32),
                 ("refresh_every", c_int32), ("ls_slots", c_int32), ("mem_cap_bytes", c_int64),
-                ("master", c_int32)]
+                ("master", c_int32), ("persistent", c_int32)]
 
 
 class dao_info_t(ctypes.Structure):

@@ -13,6 +13,7 @@
 #include "dao_common.h"
 #include "kernels.h"
 #include "kernels_ap.h"
+#include "kernels_coop.h"
 #include "layout.h"
 
 using namespace dao;
@@ -72,6 +73,9 @@ struct dao_ctx {
     void* ind = nullptr;       // [N] ctx type: 0/1 beamlet indicator of one aperture
     double* parts2 = nullptr;  // [ap_blocks * (KS + 1)] update records of the aperture master
     ProfCounters* pc = nullptr;
+    CoopSync* coop = nullptr;          // grid-reduction scratch of the persistent master
+    double* coop_recs = nullptr;       // [coop_grid * RECW]
+    int coop_grid = 0;                 // co-resident workgroups (0: persistent master unavailable)
     ProfCounters* pc_h = nullptr;      // pinned
     int prof_kernel = -1;              // aperture-master kernel timed with events (-1: none)
     int last_steps = 0;                // steps of the previous master solve (chunk size guess)
@@ -125,6 +129,7 @@ struct dao_ctx {
     int64_t slab_blocks() const { return std::max<int64_t>(1, (nslices + SPB - 1) / SPB); }
     int64_t ap_blocks() const { return std::max<int64_t>(1, std::min<int64_t>(512, (Vpad + 255) / 256)); }
     bool ap_master() const { return opt.master == DAO_MASTER_APERTURE; }
+    bool coop_master() const { return ap_master() && opt.persistent && coop_grid > 0; }
     int64_t price_blocks() const { return std::max<int64_t>(1, (R + BLOCK / WAVE - 1) / (BLOCK / WAVE)); }
     bool stage_x() const { return size_t(N) * tsize <= STAGE_LIMIT; }
     bool stage_x64() const { return size_t(N) * 8 <= STAGE_LIMIT; }
@@ -292,8 +297,37 @@ dao_status build_dk_column(dao_ctx* c, int k) {
     return DAO_OK;
 }
 
+// One cooperative launch runs the whole master solve.
+template <class T>
+dao_status run_master_coop(dao_ctx* c, double tol, int max_steps) {
+    k_master_init_ap<<<1, 1, 0, c->stream>>>(c->ms, c->K, tol, max_steps);
+    LAUNCHCHK(c);
+    HIPCHK(c, hipMemsetAsync(c->coop, 0, sizeof(CoopSync), c->stream));
+    CoopArgs<T> A{static_cast<const T*>(c->dk), c->Vpad, c->Vnz, c->d, static_cast<T*>(c->q), c->cls_int,
+                  c->classes, c->ncls, c->y, c->p, c->gradk, c->ms, c->coop_recs, c->coop, c->pc};
+    void* args[] = {&A};
+    const bool prof = c->prof_kernel == 4;
+    if (prof) {
+        dao_status s = prof_mark(c, 4, true);
+        if (s != DAO_OK) return s;
+    }
+    HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T>), dim3(c->coop_grid),
+                                         dim3(BLOCK), args, 0, c->stream));
+    if (prof) {
+        dao_status s = prof_mark(c, 4, false);
+        if (s != DAO_OK) return s;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->ms_h, c->ms, sizeof(MasterState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->ms_h->stop_reason == 4 || !c->ms_h->done)
+        return c->fail(DAO_EDEVICE, "persistent master: grid reduction timed out");
+    c->last_steps = c->ms_h->steps;
+    return DAO_OK;
+}
+
 template <class T>
 dao_status run_master(dao_ctx* c, double tol, int max_steps) {
+    if (c->coop_master()) return run_master_coop<T>(c, tol, max_steps);
     if (c->ap_master())
         k_master_init_ap<<<1, 1, 0, c->stream>>>(c->ms, c->K, tol, max_steps);
     else
@@ -464,6 +498,19 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     TRY(dev_alloc(c, &c->upd_parts, c->slab_blocks() * sizeof(Rec)));
     TRY(dev_alloc(c, &c->arr, sizeof(Arrival)));
     TRY(dev_alloc(c, &c->pc, sizeof(ProfCounters)));
+    if (c->ap_master() && c->opt.persistent) {
+        int dev = 0, coop = 0, ncu = 0, occ = 0;
+        HIPCHK(c, hipGetDevice(&dev));
+        HIPCHK(c, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+        HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(&k_master_coop<T>),
+                                                               BLOCK, 0));
+        if (coop && occ > 0 && ncu > 0) {
+            c->coop_grid = ncu;   // one co-resident workgroup per compute unit
+            TRY(dev_alloc(c, &c->coop, sizeof(CoopSync)));
+            TRY(dev_alloc(c, &c->coop_recs, size_t(c->coop_grid) * RECW * sizeof(double)));
+        }
+    }
     if (c->ap_master()) {
         TRY(dev_alloc(c, &c->dk, size_t(c->Vpad) * KS * ts));
         TRY(dev_alloc(c, &c->ind, c->N * ts));
@@ -664,6 +711,7 @@ void dao_default_options(dao_options* o) {
     o->ls_slots = 2;
     o->mem_cap_bytes = 0;
     o->master = DAO_MASTER_APERTURE;
+    o->persistent = 1;
 }
 
 const char* dao_create_error(void) { return g_create_error.c_str(); }
@@ -869,7 +917,9 @@ dao_status dao_time_product(dao_ctx* c, int32_t kernel, int32_t iters, double* u
 
 dao_status dao_profile_start(dao_ctx* c, int32_t kernel) {
     if (!c) return DAO_EINVAL;
-    if (kernel < 0 || kernel > 3) return c->fail(DAO_EINVAL, "kernel must be in [0, 3]");
+    if (kernel < 0 || kernel > 4) return c->fail(DAO_EINVAL, "kernel must be in [0, 4]");
+    if (kernel == 4 && !c->coop_master()) return c->fail(DAO_ESTATE, "the persistent master is not in use");
+    if (kernel < 4 && c->coop_master()) return c->fail(DAO_ESTATE, "the per-phase kernels are not in use");
     if (!c->ap_master()) return c->fail(DAO_ESTATE, "profiling covers the aperture-matrix master");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemsetAsync(c->pc, 0, sizeof(ProfCounters), c->stream));
@@ -894,9 +944,10 @@ dao_status dao_profile_stop(dao_ctx* c, int64_t* launches, int64_t* working_laun
     HIPCHK(c, hipMemcpyAsync(c->pc_h, c->pc, sizeof(ProfCounters), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (launches) *launches = int64_t(c->prof_used / 2);
-    if (working_launches) *working_launches = int64_t(c->pc_h->real[k]);
+    if (working_launches) *working_launches = k == 4 ? int64_t(c->prof_used / 2) : int64_t(c->pc_h->real[k]);
     if (total_us) *total_us = us;
-    if (total_bytes) *total_bytes = c->pc_h->bytes[k];
+    if (total_bytes)
+        *total_bytes = k == 4 ? c->pc_h->bytes[0] + c->pc_h->bytes[1] + c->pc_h->bytes[2] : c->pc_h->bytes[k];
     c->prof_kernel = -1;
     c->prof_used = 0;
     return DAO_OK;

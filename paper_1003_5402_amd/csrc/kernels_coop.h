@@ -1,0 +1,434 @@
+// Persistent cooperative master over the aperture dose matrix (gfx950).
+//
+// One cooperative launch runs a whole master solve (Section 2.3's gradient
+// projection, same step rule and line search as the per-phase kernels of
+// kernels_ap.h).  The grid is co-resident (cooperative launch), each
+// workgroup owns a fixed contiguous range of voxel rows for the whole solve,
+// so the per-voxel vectors d and q are only ever touched by their owner and
+// need no cross-workgroup coherence.  The only data that crosses
+// workgroups are the small reduction records (objective, grad_y, line-search
+// sums), moved with agent-scope atomic loads and stores (coherent across
+// XCDs without writing back or invalidating caches).  Every workgroup then
+// takes the same decisions from the same broadcast totals, so the direction,
+// the line-search trial points and the intensities y are computed
+// redundantly (and identically) in every workgroup instead of being
+// broadcast.
+//
+// Grid-wide reduction: each workgroup publishes its record, arrives at one of
+// NSLOT counters; the last arrival of a counter sums that counter's records
+// (workgroups slot, slot + NSLOT, ... in order), the last counter sums the
+// counter totals in order and bumps a generation number that the other
+// workgroups wait for.  The order of every sum is fixed, so results do not
+// depend on arrival order.  Waits are bounded: a workgroup that waits too
+// long raises an abort flag that every waiter checks, so the grid always
+// drains.
+#pragma once
+
+#include "kernels_ap.h"
+
+namespace dao {
+
+constexpr int RECW = KS + 8;               // doubles per reduction record
+constexpr long SPIN_LIMIT = 4000000L;      // ~1 s of waiting before the grid aborts
+
+struct CoopSync {
+    uint32_t cnt[(NSLOT + 1) * SLOT_STRIDE];
+    uint32_t gen[SLOT_STRIDE];
+    uint32_t abort_flag[SLOT_STRIDE];
+    double slot_rec[NSLOT][RECW];
+    double final_rec[RECW];
+};
+
+__device__ __forceinline__ double aload(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void astore(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t aload_u(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Combine of one record field: sums, except the line-search record's
+// nearest-breakpoint fields (3: minimum, 4: maximum).
+template <bool LS>
+__device__ __forceinline__ double rec_comb(int i, double a, double b) {
+    if (LS && i == 3) return fmin(a, b);
+    if (LS && i == 4) return fmax(a, b);
+    return a + b;
+}
+template <bool LS>
+__device__ __forceinline__ double rec_init(int i) {
+    if (LS && i == 3) return INFINITY;
+    if (LS && i == 4) return -INFINITY;
+    return 0.0;
+}
+
+// Grid-wide fixed-order reduction of W-double records (all threads of every
+// workgroup call it).  mine: this workgroup's record (LDS); total: result
+// (LDS, every workgroup).  Returns false when the grid aborted.
+template <bool LS>
+__device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W, double* total,
+                            uint32_t& gen) {
+    __shared__ int s_flag;
+    const uint32_t nb = gridDim.x, b = blockIdx.x, slot = b % NSLOT;
+    for (int i = threadIdx.x; i < W; i += blockDim.x) astore(&recs[size_t(b) * RECW + i], mine[i]);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t expect = (nb - slot + NSLOT - 1) / NSLOT;
+        const uint32_t prev =
+            __hip_atomic_fetch_add(&S->cnt[slot * SLOT_STRIDE], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_flag = (prev + 1 == expect);
+    }
+    __syncthreads();
+    if (s_flag) {
+        // last of its counter: the counter's records in workgroup order
+        for (int i = threadIdx.x; i < W; i += blockDim.x) {
+            double acc = rec_init<LS>(i);
+            for (uint32_t bb = slot; bb < nb; bb += NSLOT) acc = rec_comb<LS>(i, acc, aload(&recs[size_t(bb) * RECW + i]));
+            astore(&S->slot_rec[slot][i], acc);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __hip_atomic_exchange(&S->cnt[slot * SLOT_STRIDE], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t ns = nb < NSLOT ? nb : NSLOT;
+            const uint32_t p2 =
+                __hip_atomic_fetch_add(&S->cnt[NSLOT * SLOT_STRIDE], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_flag = (p2 + 1 == ns);
+        }
+        __syncthreads();
+        if (s_flag) {
+            // last counter: counter totals in counter order, then release
+            const uint32_t ns = nb < NSLOT ? nb : NSLOT;
+            for (int i = threadIdx.x; i < W; i += blockDim.x) {
+                double acc = rec_init<LS>(i);
+                for (uint32_t s = 0; s < ns; ++s) acc = rec_comb<LS>(i, acc, aload(&S->slot_rec[s][i]));
+                astore(&S->final_rec[i], acc);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                __hip_atomic_exchange(&S->cnt[NSLOT * SLOT_STRIDE], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_s_waitcnt(0);
+                __hip_atomic_fetch_add(&S->gen[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        long spins = 0;
+        int ok = 1;
+        while (aload_u(&S->gen[0]) == gen) {
+            __builtin_amdgcn_s_sleep(1);
+            if (aload_u(&S->abort_flag[0])) {
+                ok = 0;
+                break;
+            }
+            if (++spins > SPIN_LIMIT) {
+                __hip_atomic_store(&S->abort_flag[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+        }
+        s_flag = ok;
+    }
+    __syncthreads();
+    gen += 1;
+    if (!s_flag) return false;
+    for (int i = threadIdx.x; i < W; i += blockDim.x) total[i] = aload(&S->final_rec[i]);
+    __syncthreads();
+    return true;
+}
+
+template <class T>
+struct CoopArgs {
+    const T* dk;
+    int64_t Vpad, Vnz;
+    double* d;
+    T* q;
+    const uint8_t* cls;
+    const ObjClass* classes;
+    int ncls;
+    double* y;          // in: current intensities; out: final intensities (workgroup 0)
+    double* p;          // out: last direction (workgroup 0)
+    double* grad;       // out: last grad_y (workgroup 0)
+    MasterState* ms;    // in: state set by k_master_init_ap; out: final state (workgroup 0)
+    double* recs;       // [gridDim.x * RECW]
+    CoopSync* sync;
+    ProfCounters* pc;
+};
+
+template <class T>
+__global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
+    using G = DKG<T>;
+    using V = typename Vec16<T>::type;
+    constexpr int IT = Batch<T>::ITERS, ROWS = Batch<T>::ROWS;
+    constexpr int NW = BLOCK / WAVE;
+    __shared__ MasterState s_ms;
+    __shared__ ObjClass cl[256];
+    __shared__ double s_y[KS], s_p[KS], s_g[KS];
+    __shared__ double s_rec[RECW], s_tot[RECW];
+    __shared__ double s_acc[NW][KS];
+    __shared__ double s_wr[NW][8];
+    __shared__ double s_u[NW][ROWS];
+    __shared__ uint32_t s_gen;
+    __shared__ int s_go, s_fin;
+
+    ms_load(s_ms, A.ms);
+    for (int i = threadIdx.x; i < A.ncls; i += blockDim.x) cl[i] = A.classes[i];
+    const int K = s_ms.K;
+    for (int k = threadIdx.x; k < KS; k += blockDim.x) {
+        s_y[k] = k < K ? A.y[k] : 0.0;
+        s_p[k] = 0.0;
+        s_g[k] = 0.0;
+    }
+    if (threadIdx.x == 0) s_gen = aload_u(&A.sync->gen[0]);
+    __syncthreads();
+    uint32_t gen = s_gen;
+
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    const int rg = lane / G::LPR, c = lane % G::LPR;
+    const int nc = (K + G::EPL - 1) / G::EPL;
+    // this workgroup's batches of ROWS rows
+    const int64_t nbat = A.Vpad / ROWS;
+    const int64_t per = (nbat + gridDim.x - 1) / gridDim.x;
+    const int64_t bat0 = min(nbat, int64_t(blockIdx.x) * per), bat1 = min(nbat, bat0 + per);
+    bool alive = true;
+    int mode = s_ms.refresh;   // first update keeps d (2) unless told otherwise
+
+    while (alive) {
+        // ---------------- update pass: apply the step, dF/dz, F, grad_y partials
+        {
+            const double t = s_ms.t;
+            double yv[G::EPL], acc[G::EPL];
+#pragma unroll
+            for (int e = 0; e < G::EPL; ++e) {
+                const int k = c * G::EPL + e;
+                yv[e] = (mode == 1 && k < K) ? s_y[k] : 0.0;
+                acc[e] = 0.0;
+            }
+            double Fp = 0.0;
+            double* su = s_u[wave];
+            for (int64_t bt = bat0 + wave; bt < bat1; bt += NW) {
+                const int64_t base = bt * ROWS;
+                V v[IT];
+#pragma unroll
+                for (int it = 0; it < IT; ++it) {
+                    v[it] = vzero<V>();
+                    if (c < nc) v[it] = reinterpret_cast<const V*>(A.dk + (base + it * G::RPW + rg) * KS)[c];
+                }
+                if (mode == 1) {
+#pragma unroll
+                    for (int it = 0; it < IT; ++it) {
+                        double part = 0.0;
+#pragma unroll
+                        for (int e = 0; e < G::EPL; ++e) part += vget(v[it], e) * yv[e];
+                        part = group_sum<G::LPR>(part);
+                        if (c == 0) su[it * G::RPW + rg] = part;
+                    }
+                }
+                wave_sync();
+                if (lane < ROWS) {
+                    const int64_t row = base + lane;
+                    double dn;
+                    if (mode == 1) {
+                        dn = su[lane];
+                    } else {
+                        dn = A.d[row];
+                        if (mode == 0) dn = dn + t * double(A.q[row]);
+                    }
+                    const ObjClass cc = cl[A.cls[row]];
+                    if (mode != 2) A.d[row] = dn;
+                    Fp += obj_f(cc, dn);
+                    su[lane] = grad_f(cc, dn);
+                }
+                wave_sync();
+#pragma unroll
+                for (int it = 0; it < IT; ++it) {
+                    const double u = su[it * G::RPW + rg];
+#pragma unroll
+                    for (int e = 0; e < G::EPL; ++e) acc[e] += u * vget(v[it], e);
+                }
+                wave_sync();
+            }
+#pragma unroll
+            for (int off = G::LPR; off < WAVE; off <<= 1)
+#pragma unroll
+                for (int e = 0; e < G::EPL; ++e) acc[e] += __shfl_xor(acc[e], off, WAVE);
+            if (rg == 0)
+#pragma unroll
+                for (int e = 0; e < G::EPL; ++e) s_acc[wave][c * G::EPL + e] = acc[e];
+            Fp = wave_sum(Fp);
+            if (lane == 0) s_wr[wave][0] = Fp;
+            __syncthreads();
+            if (threadIdx.x < K) {
+                double sacc = 0.0;
+                for (int w = 0; w < NW; ++w) sacc += s_acc[w][threadIdx.x];
+                s_rec[1 + threadIdx.x] = sacc;
+            } else if (threadIdx.x == KS) {
+                double sacc = 0.0;
+                for (int w = 0; w < NW; ++w) sacc += s_wr[w][0];
+                s_rec[0] = sacc;
+            }
+            __syncthreads();
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                const double per_row = 16.0 * nc + 1.0 + (mode != 1 ? 8.0 : 0.0) +
+                                       (mode == 0 ? double(sizeof(T)) : 0.0) + (mode != 2 ? 8.0 : 0.0);
+                A.pc->bytes[0] += per_row * double(A.Vnz);
+                A.pc->real[0] += 1;
+            }
+            if (!grid_reduce<false>(A.sync, A.recs, s_rec, K + 1, s_tot, gen)) {
+                alive = false;
+                break;
+            }
+        }
+        // ---------------- direction (identical in every workgroup)
+        if (threadIdx.x < WAVE) {
+            const int k = threadIdx.x;
+            const bool in = k < K;
+            const double yk = s_y[k];
+            const double gk = in ? s_tot[1 + k] : 0.0;
+            double pk = -gk;
+            if (!in || (yk == 0.0 && gk >= 0.0)) pk = 0.0;
+            const double kkt = wave_max(in ? fabs(fmin(yk, gk)) : 0.0);
+            const double tmax = wave_min(pk < 0.0 ? yk / (-pk) : INFINITY);
+            const double gp = wave_sum(gk * pk);
+            const bool any = __any(pk != 0.0);
+            s_p[k] = pk;
+            s_g[k] = gk;
+            if (k == 0) {
+                s_ms.F = s_ms.F_const + s_tot[0];
+                s_ms.kkt = kkt;
+                int go = 1;
+                if (!(kkt > s_ms.tol)) {
+                    s_ms.stop_reason = 1;
+                    go = 0;
+                } else if (s_ms.steps >= s_ms.max_steps) {
+                    s_ms.stop_reason = 2;
+                    go = 0;
+                } else if (!any) {
+                    s_ms.stop_reason = 3;
+                    go = 0;
+                }
+                if (!go) {
+                    s_ms.done = 1;
+                } else {
+                    s_ms.t_max = tmax;
+                    s_ms.gphi0 = gp;
+                    s_ms.t = 0.0;
+                    s_ms.lo = 0.0;
+                    s_ms.hi = tmax;
+                    s_ms.hi_known = 0;
+                    s_ms.ls_iter = 0;
+                }
+                s_go = go;
+            }
+        }
+        __syncthreads();
+        if (!s_go) break;
+        // ---------------- line search: first evaluation computes q = D_K p
+        bool first = true;
+        for (;;) {
+            const double t = s_ms.t;
+            Rec r = rec_identity();
+            double pv[G::EPL];
+#pragma unroll
+            for (int e = 0; e < G::EPL; ++e) pv[e] = s_p[c * G::EPL + e];
+            double* sq = s_u[wave];
+            for (int64_t bt = bat0 + wave; bt < bat1; bt += NW) {
+                const int64_t base = bt * ROWS;
+                if (first) {
+                    V v[IT];
+#pragma unroll
+                    for (int it = 0; it < IT; ++it) {
+                        v[it] = vzero<V>();
+                        if (c < nc) v[it] = reinterpret_cast<const V*>(A.dk + (base + it * G::RPW + rg) * KS)[c];
+                    }
+#pragma unroll
+                    for (int it = 0; it < IT; ++it) {
+                        double part = 0.0;
+#pragma unroll
+                        for (int e = 0; e < G::EPL; ++e) part += vget(v[it], e) * pv[e];
+                        part = group_sum<G::LPR>(part);
+                        if (c == 0) sq[it * G::RPW + rg] = part;
+                    }
+                    wave_sync();
+                }
+                if (lane < ROWS) {
+                    const int64_t row = base + lane;
+                    T qt;
+                    if (first) {
+                        qt = T(sq[lane]);   // the line search and the update use the stored value
+                        A.q[row] = qt;
+                    } else {
+                        qt = A.q[row];
+                    }
+                    ls_voxel(cl[A.cls[row]], A.d[row], double(qt), t, r);
+                }
+                wave_sync();
+            }
+            const Rec br = block_reduce(r);
+            if (threadIdx.x == 0) {
+                s_rec[0] = br.s0;
+                s_rec[1] = br.s1;
+                s_rec[2] = br.s2;
+                s_rec[3] = br.mn;
+                s_rec[4] = br.mx;
+                s_rec[5] = br.s5;
+            }
+            __syncthreads();
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                const int kk = first ? 1 : 2;
+                A.pc->bytes[kk] += (first ? (16.0 * nc + 8.0 + 1.0 + double(sizeof(T)))
+                                          : (8.0 + double(sizeof(T)) + 1.0)) * double(A.Vnz);
+                A.pc->real[kk] += 1;
+            }
+            if (!grid_reduce<true>(A.sync, A.recs, s_rec, 6, s_tot, gen)) {
+                alive = false;
+                break;
+            }
+            if (threadIdx.x == 0) {
+                const Rec tot{s_tot[0], s_tot[1], s_tot[2], s_tot[3], s_tot[4], s_tot[5]};
+                s_fin = ls_decide(s_ms, tot);
+            }
+            __syncthreads();
+            first = false;
+            if (s_fin) break;
+        }
+        if (!alive) break;
+        // ---------------- step: y update, counters, next update mode
+        {
+            const double t = s_ms.t, tmax = s_ms.t_max;
+            if (threadIdx.x < K) {
+                const int k = threadIdx.x;
+                const double pk = s_p[k];
+                const double ratio = pk < 0.0 ? s_y[k] / (-pk) : INFINITY;
+                double yn = s_y[k] + t * pk;
+                if (t == tmax && ratio == t) yn = 0.0;
+                s_y[k] = fmax(yn, 0.0);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                s_ms.steps += 1;
+                s_ms.total_steps += 1;
+                s_ms.last_step = t;
+                s_ms.refresh = (s_ms.steps % s_ms.refresh_every) == 0 ? 1 : 0;
+            }
+            __syncthreads();
+            mode = s_ms.refresh;
+        }
+    }
+    // workgroup 0 publishes the final state
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < K) {
+            A.y[threadIdx.x] = s_y[threadIdx.x];
+            A.p[threadIdx.x] = s_p[threadIdx.x];
+            A.grad[threadIdx.x] = s_g[threadIdx.x];
+        }
+        if (threadIdx.x == 0 && !alive) s_ms.stop_reason = 4;
+        ms_store(A.ms, s_ms);
+    }
+}
+
+}  // namespace dao

@@ -19,10 +19,14 @@ from gpu_util import ctx_for, torch_cuda
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("master", [0, 1])
+MASTER_OPTS = {"ap-persistent": dict(master=0, persistent=1), "ap-launches": dict(master=0, persistent=0),
+               "beamlet": dict(master=1)}
+
+
+@pytest.mark.parametrize("master", list(MASTER_OPTS))
 def test_solve_bitwise_reproducible(master):
     ph = cached_phantom("tiny")
-    ctx = ctx_for(ph, dtype="f32", master=master)
+    ctx = ctx_for(ph, dtype="f32", **MASTER_OPTS[master])
     try:
         a = ctx.solve(6)
         pa, ya = ctx.get_pool()
@@ -62,11 +66,11 @@ def test_aperture_validation_and_capacity():
         ctx.close()
 
 
-@pytest.mark.parametrize("master", [0, 1])
+@pytest.mark.parametrize("master", list(MASTER_OPTS))
 def test_empty_pool_and_closed_aperture(master):
     ph = cached_phantom("mini")
     P = oracle_problem(ph)
-    ctx = ctx_for(ph, dtype="f64", master=master)
+    ctx = ctx_for(ph, dtype="f64", **MASTER_OPTS[master])
     try:
         ctx.reset()
         F, kkt, t = ctx.master_step()
@@ -99,3 +103,23 @@ def test_nothing_to_deliver_is_optimal():
         assert out["rounds"] == 0 and out["stop"] == dao.DAO_EOPTIMAL
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("name,dtype", [("tiny", "f64"), ("tiny", "f32")])
+def test_persistent_and_per_phase_masters_agree(name, dtype):
+    """The persistent launch runs the same arithmetic as the per-phase
+    kernels: identical pools and intensities, objectives equal to rounding."""
+    ph = cached_phantom(name)
+    a = ctx_for(ph, dtype=dtype, master=0, persistent=1)
+    b = ctx_for(ph, dtype=dtype, master=0, persistent=0)
+    try:
+        ra, rb = a.solve(6), b.solve(6)
+        pa, ya = a.get_pool()
+        pb, yb = b.get_pool()
+        assert pa == pb
+        np.testing.assert_allclose(ya, yb, rtol=1e-9, atol=1e-12)
+        assert abs(ra["F"] - rb["F"]) <= 1e-12 * rb["F"]
+        assert np.array_equal(ra["round_steps"], rb["round_steps"])
+    finally:
+        a.close()
+        b.close()

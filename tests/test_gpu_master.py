@@ -25,9 +25,12 @@ from oracle.master import MasterState, kkt_residual, master_step, solve_master
 
 pytestmark = pytest.mark.gpu
 
-# both ways the master evaluates its products: aperture dose matrix (0) and
-# beamlet matrix with the pool map (1)
-MASTERS = pytest.mark.parametrize("master", [0, 1])
+# the ways the master can run: aperture dose matrix as one persistent
+# cooperative launch per solve, aperture dose matrix with one launch per
+# phase, beamlet matrix with the pool map
+MASTER_OPTS = {"ap-persistent": dict(master=0, persistent=1), "ap-launches": dict(master=0, persistent=0),
+               "beamlet": dict(master=1)}
+MASTERS = pytest.mark.parametrize("master", list(MASTER_OPTS))
 
 
 def _oracle_pool(P, n, seed=0):
@@ -43,7 +46,7 @@ def test_master_steps_parity(name, dtype, steps, tol, master):
     ph = cached_phantom(name)
     P = oracle_problem(ph, dtype)
     pool = _oracle_pool(P, 4)
-    ctx = ctx_for(ph, dtype=dtype, master=master)
+    ctx = ctx_for(ph, dtype=dtype, **MASTER_OPTS[master])
     try:
         ctx.reset()
         st = MasterState.empty(P)
@@ -80,7 +83,7 @@ def test_master_converged_parity(name, dtype, tol, master):
         st.add(ap)
     ktol = 1e-9 if dtype == "f64" else 1e-6
     log = solve_master(P, st, tol=ktol, max_steps=20000)
-    ctx = ctx_for(ph, dtype=dtype, master=master)
+    ctx = ctx_for(ph, dtype=dtype, **MASTER_OPTS[master])
     try:
         ctx.reset()
         for ap in pool:
@@ -109,7 +112,7 @@ def test_solve_tiny_f64_free_running(master):
     if "ref" not in _TINY_REF:
         _TINY_REF["ref"] = oracle.solve(P, ph.n_apertures, eps=1e-6)
     ref = _TINY_REF["ref"]
-    ctx = ctx_for(ph, dtype="f64", master=master)
+    ctx = ctx_for(ph, dtype="f64", **MASTER_OPTS[master])
     try:
         out = ctx.solve(ph.n_apertures)
         pool, y = ctx.get_pool()
@@ -134,7 +137,7 @@ def test_solve_tiny_f64_free_running(master):
 def test_prostate_f32_teacher_forced_rounds(master):
     ph = cached_phantom("prostate")
     P = oracle_problem(ph)
-    ctx = ctx_for(ph, dtype="f32", master=master)
+    ctx = ctx_for(ph, dtype="f32", **MASTER_OPTS[master])
     rounds = 3
     try:
         ctx.reset()
