@@ -64,6 +64,39 @@ __device__ __forceinline__ double rec_init(int i) {
     return 0.0;
 }
 
+// Fixed-order combine of `count` records (record m at base + (first + m*step)
+// * RECW) into out[0..W) (LDS).  Columns are split into up to 4 contiguous
+// parts of records whose loads are issued 8 at a time; parts are combined
+// in order.  Called by all threads of a workgroup.
+template <bool LS>
+__device__ __forceinline__ void combine_records(const double* base, uint32_t first, uint32_t step, uint32_t count,
+                                                int W, double* out, double* scratch) {
+    const int nparts = max(1, min(4, int(blockDim.x) / max(W, 1)));
+    const uint32_t per = (count + nparts - 1) / nparts;
+    for (int tt = threadIdx.x; tt < W * nparts; tt += blockDim.x) {
+        const int i = tt % W, j = tt / W;
+        const uint32_t m0 = min(count, j * per), m1 = min(count, m0 + per);
+        double acc = rec_init<LS>(i);
+        uint32_t m = m0;
+        for (; m + 8 <= m1; m += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = aload(base + size_t(first + (m + u) * step) * RECW + i);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc = rec_comb<LS>(i, acc, v[u]);
+        }
+        for (; m < m1; ++m) acc = rec_comb<LS>(i, acc, aload(base + size_t(first + m * step) * RECW + i));
+        scratch[j * RECW + i] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < W; i += blockDim.x) {
+        double acc = rec_init<LS>(i);
+        for (int j = 0; j < nparts; ++j) acc = rec_comb<LS>(i, acc, scratch[j * RECW + i]);
+        out[i] = acc;
+    }
+    __syncthreads();
+}
+
 // Grid-wide fixed-order reduction of W-double records (all threads of every
 // workgroup call it).  mine: this workgroup's record (LDS); total: result
 // (LDS, every workgroup).  Returns false when the grid aborted.
@@ -71,6 +104,7 @@ template <bool LS>
 __device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W, double* total,
                             uint32_t& gen) {
     __shared__ int s_flag;
+    __shared__ double s_scr[4 * RECW], s_sum[RECW];
     const uint32_t nb = gridDim.x, b = blockIdx.x, slot = b % NSLOT;
     for (int i = threadIdx.x; i < W; i += blockDim.x) astore(&recs[size_t(b) * RECW + i], mine[i]);
     __builtin_amdgcn_s_waitcnt(0);
@@ -84,11 +118,9 @@ __device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W
     __syncthreads();
     if (s_flag) {
         // last of its counter: the counter's records in workgroup order
-        for (int i = threadIdx.x; i < W; i += blockDim.x) {
-            double acc = rec_init<LS>(i);
-            for (uint32_t bb = slot; bb < nb; bb += NSLOT) acc = rec_comb<LS>(i, acc, aload(&recs[size_t(bb) * RECW + i]));
-            astore(&S->slot_rec[slot][i], acc);
-        }
+        const uint32_t cnt = (nb - slot + NSLOT - 1) / NSLOT;
+        combine_records<LS>(recs, slot, NSLOT, cnt, W, s_sum, s_scr);
+        for (int i = threadIdx.x; i < W; i += blockDim.x) astore(&S->slot_rec[slot][i], s_sum[i]);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -102,11 +134,8 @@ __device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W
         if (s_flag) {
             // last counter: counter totals in counter order, then release
             const uint32_t ns = nb < NSLOT ? nb : NSLOT;
-            for (int i = threadIdx.x; i < W; i += blockDim.x) {
-                double acc = rec_init<LS>(i);
-                for (uint32_t s = 0; s < ns; ++s) acc = rec_comb<LS>(i, acc, aload(&S->slot_rec[s][i]));
-                astore(&S->final_rec[i], acc);
-            }
+            combine_records<LS>(&S->slot_rec[0][0], 0, 1, ns, W, s_sum, s_scr);
+            for (int i = threadIdx.x; i < W; i += blockDim.x) astore(&S->final_rec[i], s_sum[i]);
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             if (threadIdx.x == 0) {
