@@ -107,9 +107,12 @@ typedef struct {
     int32_t ls_slots;       /* line-search launches per master cycle (2) */
     int64_t mem_cap_bytes;  /* fail dao_create with DAO_ENOMEM above this device footprint; 0 = none */
     int32_t master;         /* DAO_MASTER_APERTURE (default) or DAO_MASTER_BEAMLET, see below */
-    int32_t persistent;     /* aperture master: 1 (default) runs each master solve as one
-                               cooperative launch when the device supports it; 0 launches
-                               each phase of each step separately */
+    int32_t persistent;     /* aperture master: 2 (default) runs each master solve as one
+                               cooperative launch when the device supports it, each
+                               workgroup holding its rows of D_K, d and q in LDS when they
+                               fit (else as 1); 1 is that launch streaming D_K from device
+                               memory on every pass; 0 launches each phase of each step
+                               separately */
 } dao_options;
 
 /* How the restricted master evaluates its two products per step.

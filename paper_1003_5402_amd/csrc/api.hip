@@ -76,6 +76,7 @@ struct dao_ctx {
     CoopSync* coop = nullptr;          // grid-reduction scratch of the persistent master
     double* coop_recs = nullptr;       // [coop_grid * RECW]
     int coop_grid = 0;                 // co-resident workgroups (0: persistent master unavailable)
+    int coop_lds_max = 0;              // dynamic LDS the on-chip variant may use (0: never)
     ProfCounters* pc_h = nullptr;      // pinned
     int prof_kernel = -1;              // aperture-master kernel timed with events (-1: none)
     int last_steps = 0;                // steps of the previous master solve (chunk size guess)
@@ -311,8 +312,16 @@ dao_status run_master_coop(dao_ctx* c, double tol, int max_steps) {
         dao_status s = prof_mark(c, 4, true);
         if (s != DAO_OK) return s;
     }
-    HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T>), dim3(c->coop_grid),
-                                         dim3(BLOCK), args, 0, c->stream));
+    // LDS-resident variant when the workgroup's slice fits on chip
+    const int nc = (c->K + DKG<T>::EPL - 1) / DKG<T>::EPL;
+    const int64_t rows = coop_batches_per_group<T>(c->Vpad, c->coop_grid) * Batch<T>::ROWS;
+    const size_t lds = coop_lds_bytes<T>(rows, nc);
+    if (c->opt.persistent == 2 && c->coop_lds_max > 0 && lds <= size_t(c->coop_lds_max))
+        HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T, true>),
+                                             dim3(c->coop_grid), dim3(BLOCK), args, lds, c->stream));
+    else
+        HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T, false>),
+                                             dim3(c->coop_grid), dim3(BLOCK), args, 0, c->stream));
     if (prof) {
         dao_status s = prof_mark(c, 4, false);
         if (s != DAO_OK) return s;
@@ -503,10 +512,25 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
         HIPCHK(c, hipGetDevice(&dev));
         HIPCHK(c, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
         HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-        HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(&k_master_coop<T>),
-                                                               BLOCK, 0));
+        HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &occ, reinterpret_cast<const void*>(&k_master_coop<T, false>), BLOCK, 0));
         if (coop && occ > 0 && ncu > 0) {
             c->coop_grid = ncu;   // one co-resident workgroup per compute unit
+            // on-chip variant: as much dynamic LDS as the device grants one
+            // workgroup beyond the kernel's static LDS, if one per CU still fits
+            int lds_max = 0;
+            HIPCHK(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+            const int want = lds_max - 24 * 1024;
+            if (want > 0 &&
+                hipFuncSetAttribute(reinterpret_cast<const void*>(&k_master_coop<T, true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, want) == hipSuccess) {
+                int occ2 = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &occ2, reinterpret_cast<const void*>(&k_master_coop<T, true>), BLOCK, want) == hipSuccess &&
+                    occ2 >= 1)
+                    c->coop_lds_max = want;
+            }
+            (void)hipGetLastError();
             TRY(dev_alloc(c, &c->coop, sizeof(CoopSync)));
             TRY(dev_alloc(c, &c->coop_recs, size_t(c->coop_grid) * RECW * sizeof(double)));
         }
@@ -711,7 +735,7 @@ void dao_default_options(dao_options* o) {
     o->ls_slots = 2;
     o->mem_cap_bytes = 0;
     o->master = DAO_MASTER_APERTURE;
-    o->persistent = 1;
+    o->persistent = 2;
 }
 
 const char* dao_create_error(void) { return g_create_error.c_str(); }

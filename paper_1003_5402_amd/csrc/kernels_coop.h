@@ -188,12 +188,30 @@ struct CoopArgs {
     ProfCounters* pc;
 };
 
+// Rows of workgroup b: batches [bat0, bat1) of ROWS rows (contiguous).
 template <class T>
+__host__ __device__ inline int64_t coop_batches_per_group(int64_t Vpad, int grid) {
+    const int64_t nbat = Vpad / Batch<T>::ROWS;
+    return (nbat + grid - 1) / grid;
+}
+
+// Dynamic LDS of the LDS-resident variant: the workgroup's D_K rows (nc
+// 16-byte vectors each), then d (double), q (T), class (uint8).
+template <class T>
+__host__ __device__ inline size_t coop_lds_bytes(int64_t rows, int nc) {
+    return size_t(rows) * nc * 16 + size_t(rows) * (8 + sizeof(T) + 1) + 64;
+}
+
+// LDSRES: the workgroup copies its rows of D_K, d, q and the classes into
+// LDS once per solve and every pass reads on-chip memory; d is written back
+// at the end.  Otherwise the passes stream them from global memory.
+template <class T, bool LDSRES>
 __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
     using G = DKG<T>;
     using V = typename Vec16<T>::type;
     constexpr int IT = Batch<T>::ITERS, ROWS = Batch<T>::ROWS;
     constexpr int NW = BLOCK / WAVE;
+    extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ MasterState s_ms;
     __shared__ ObjClass cl[256];
     __shared__ double s_y[KS], s_p[KS], s_g[KS];
@@ -221,8 +239,32 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
     const int nc = (K + G::EPL - 1) / G::EPL;
     // this workgroup's batches of ROWS rows
     const int64_t nbat = A.Vpad / ROWS;
-    const int64_t per = (nbat + gridDim.x - 1) / gridDim.x;
+    const int64_t per = coop_batches_per_group<T>(A.Vpad, gridDim.x);
     const int64_t bat0 = min(nbat, int64_t(blockIdx.x) * per), bat1 = min(nbat, bat0 + per);
+    const int64_t r0 = bat0 * ROWS, nrows = (bat1 - bat0) * ROWS;
+    // on-chip copies (LDSRES)
+    V* dkl = reinterpret_cast<V*>(dyn);
+    double* dl = reinterpret_cast<double*>(dyn + size_t(nrows) * nc * 16);
+    T* ql = reinterpret_cast<T*>(dyn + size_t(nrows) * nc * 16 + size_t(nrows) * 8);
+    uint8_t* cll = reinterpret_cast<uint8_t*>(dyn + size_t(nrows) * nc * 16 + size_t(nrows) * (8 + sizeof(T)));
+    if (LDSRES) {
+        for (int64_t idx = threadIdx.x; idx < nrows * nc; idx += blockDim.x) {
+            const int64_t rr = idx / nc;
+            dkl[idx] = reinterpret_cast<const V*>(A.dk + (r0 + rr) * KS)[idx - rr * nc];
+        }
+        for (int64_t rr = threadIdx.x; rr < nrows; rr += blockDim.x) {
+            dl[rr] = A.d[r0 + rr];
+            ql[rr] = T(0);
+            cll[rr] = A.cls[r0 + rr];
+        }
+        __syncthreads();
+    }
+    auto dk_vec = [&](int64_t row) -> V {
+        return LDSRES ? dkl[(row - r0) * nc + c] : reinterpret_cast<const V*>(A.dk + row * KS)[c];
+    };
+    auto d_at = [&](int64_t row) -> double& { return LDSRES ? dl[row - r0] : A.d[row]; };
+    auto q_at = [&](int64_t row) -> T& { return LDSRES ? ql[row - r0] : A.q[row]; };
+    auto cls_at = [&](int64_t row) -> uint8_t { return LDSRES ? cll[row - r0] : A.cls[row]; };
     bool alive = true;
     int mode = s_ms.refresh;   // first update keeps d (2) unless told otherwise
 
@@ -245,7 +287,7 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
 #pragma unroll
                 for (int it = 0; it < IT; ++it) {
                     v[it] = vzero<V>();
-                    if (c < nc) v[it] = reinterpret_cast<const V*>(A.dk + (base + it * G::RPW + rg) * KS)[c];
+                    if (c < nc) v[it] = dk_vec(base + it * G::RPW + rg);
                 }
                 if (mode == 1) {
 #pragma unroll
@@ -264,11 +306,11 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
                     if (mode == 1) {
                         dn = su[lane];
                     } else {
-                        dn = A.d[row];
-                        if (mode == 0) dn = dn + t * double(A.q[row]);
+                        dn = d_at(row);
+                        if (mode == 0) dn = dn + t * double(q_at(row));
                     }
-                    const ObjClass cc = cl[A.cls[row]];
-                    if (mode != 2) A.d[row] = dn;
+                    const ObjClass cc = cl[cls_at(row)];
+                    if (mode != 2) d_at(row) = dn;
                     Fp += obj_f(cc, dn);
                     su[lane] = grad_f(cc, dn);
                 }
@@ -372,7 +414,7 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
 #pragma unroll
                     for (int it = 0; it < IT; ++it) {
                         v[it] = vzero<V>();
-                        if (c < nc) v[it] = reinterpret_cast<const V*>(A.dk + (base + it * G::RPW + rg) * KS)[c];
+                        if (c < nc) v[it] = dk_vec(base + it * G::RPW + rg);
                     }
 #pragma unroll
                     for (int it = 0; it < IT; ++it) {
@@ -389,11 +431,11 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
                     T qt;
                     if (first) {
                         qt = T(sq[lane]);   // the line search and the update use the stored value
-                        A.q[row] = qt;
+                        q_at(row) = qt;
                     } else {
-                        qt = A.q[row];
+                        qt = q_at(row);
                     }
-                    ls_voxel(cl[A.cls[row]], A.d[row], double(qt), t, r);
+                    ls_voxel(cl[cls_at(row)], d_at(row), double(qt), t, r);
                 }
                 wave_sync();
             }
@@ -447,6 +489,10 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
             __syncthreads();
             mode = s_ms.refresh;
         }
+    }
+    if (LDSRES) {
+        __syncthreads();
+        for (int64_t rr = threadIdx.x; rr < nrows; rr += blockDim.x) A.d[r0 + rr] = dl[rr];
     }
     // workgroup 0 publishes the final state
     if (blockIdx.x == 0) {

@@ -42,7 +42,7 @@ dao_status validate_inputs(const dao_matrix* D, const dao_beams* beams,
     if (opt->mem_cap_bytes < 0) return fail("mem_cap_bytes must be >= 0");
     if (opt->master != DAO_MASTER_APERTURE && opt->master != DAO_MASTER_BEAMLET)
         return fail("master must be DAO_MASTER_APERTURE or DAO_MASTER_BEAMLET");
-    if (opt->persistent != 0 && opt->persistent != 1) return fail("persistent must be 0 or 1");
+    if (opt->persistent < 0 || opt->persistent > 2) return fail("persistent must be 0, 1 or 2");
     if (opt->master == DAO_MASTER_APERTURE && opt->max_apertures > KS)
         return fail("the aperture-matrix master holds at most 64 apertures (max_apertures)");
 

@@ -76,6 +76,8 @@ def test_create_rejects_malformed_inputs():
     assert "max_apertures" in msg
     msg = _expect(dao.DAO_EINVAL, _a=_args(ph), _opts=dict(ls_slots=0))
     assert "ls_slots" in msg
+    msg = _expect(dao.DAO_EINVAL, _a=_args(ph), _opts=dict(persistent=3))
+    assert "persistent" in msg
 
 
 def test_create_enforces_memory_cap():

@@ -19,7 +19,8 @@ from gpu_util import ctx_for, torch_cuda
 pytestmark = pytest.mark.gpu
 
 
-MASTER_OPTS = {"ap-persistent": dict(master=0, persistent=1), "ap-launches": dict(master=0, persistent=0),
+MASTER_OPTS = {"ap-persistent": dict(master=0, persistent=2), "ap-stream": dict(master=0, persistent=1),
+               "ap-launches": dict(master=0, persistent=0),
                "beamlet": dict(master=1)}
 
 
@@ -105,12 +106,14 @@ def test_nothing_to_deliver_is_optimal():
         ctx.close()
 
 
+@pytest.mark.parametrize("persistent", [2, 1])
 @pytest.mark.parametrize("name,dtype", [("tiny", "f64"), ("tiny", "f32")])
-def test_persistent_and_per_phase_masters_agree(name, dtype):
-    """The persistent launch runs the same arithmetic as the per-phase
-    kernels: identical pools and intensities, objectives equal to rounding."""
+def test_persistent_and_per_phase_masters_agree(name, dtype, persistent):
+    """The persistent launch (rows on chip or streamed) runs the same
+    arithmetic as the per-phase kernels: identical pools and intensities,
+    objectives equal to rounding."""
     ph = cached_phantom(name)
-    a = ctx_for(ph, dtype=dtype, master=0, persistent=1)
+    a = ctx_for(ph, dtype=dtype, master=0, persistent=persistent)
     b = ctx_for(ph, dtype=dtype, master=0, persistent=0)
     try:
         ra, rb = a.solve(6), b.solve(6)

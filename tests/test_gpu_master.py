@@ -26,9 +26,11 @@ from oracle.master import MasterState, kkt_residual, master_step, solve_master
 pytestmark = pytest.mark.gpu
 
 # the ways the master can run: aperture dose matrix as one persistent
-# cooperative launch per solve, aperture dose matrix with one launch per
-# phase, beamlet matrix with the pool map
-MASTER_OPTS = {"ap-persistent": dict(master=0, persistent=1), "ap-launches": dict(master=0, persistent=0),
+# cooperative launch per solve (rows held in LDS, or streamed from device
+# memory), aperture dose matrix with one launch per phase, beamlet matrix
+# with the pool map
+MASTER_OPTS = {"ap-persistent": dict(master=0, persistent=2), "ap-stream": dict(master=0, persistent=1),
+               "ap-launches": dict(master=0, persistent=0),
                "beamlet": dict(master=1)}
 MASTERS = pytest.mark.parametrize("master", list(MASTER_OPTS))
 
