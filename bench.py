@@ -151,6 +151,16 @@ def main():
     gbs_dose = info["bytes_dose"] / (us_dose * 1e-6) / 1e9
     gbs_grad = info["bytes_gradient"] / (us_grad * 1e-6) / 1e9
     log(f"[bench] D x: {us_dose:.2f} us {gbs_dose:.0f} GB/s; D^T u: {us_grad:.2f} us {gbs_grad:.0f} GB/s")
+    # cold: a 1 GiB write (4x the last-level cache) before every timed launch
+    scrub = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    cold_iters = max(1, args.product_iters // 10)
+    us_dose_c = ctx.time_product_cold(0, cold_iters, scrub)
+    us_grad_c = ctx.time_product_cold(1, cold_iters, scrub)
+    del scrub
+    gbs_dose_c = info["bytes_dose"] / (us_dose_c * 1e-6) / 1e9
+    gbs_grad_c = info["bytes_gradient"] / (us_grad_c * 1e-6) / 1e9
+    log(f"[bench] cold D x: {us_dose_c:.2f} us {gbs_dose_c:.0f} GB/s; "
+        f"cold D^T u: {us_grad_c:.2f} us {gbs_grad_c:.0f} GB/s")
 
     steps_per_plan = int(outs[-1]["total_steps"])
     result = {
@@ -183,7 +193,11 @@ def main():
         "products": {
             "dose_us": us_dose, "dose_bytes": info["bytes_dose"], "dose_GBs": gbs_dose,
             "gradient_us": us_grad, "gradient_bytes": info["bytes_gradient"], "gradient_GBs": gbs_grad,
-            "note": "D x = k_dose, D^T u = k_gradT, timed standalone; warm (D fits the 256 MB last-level cache)",
+            "dose_cold_us": us_dose_c, "dose_cold_GBs": gbs_dose_c,
+            "gradient_cold_us": us_grad_c, "gradient_cold_GBs": gbs_grad_c,
+            "dose_frac_cold": gbs_dose_c / HBM_PEAK_GBS, "gradient_frac_cold": gbs_grad_c / HBM_PEAK_GBS,
+            "note": ("D x = k_dose, D^T u = k_gradT, timed standalone: warm back-to-back (D fits the 256 MB "
+                     "last-level cache) and cold (1 GiB scrub write before each timed launch)"),
         },
         "master_kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk_["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",

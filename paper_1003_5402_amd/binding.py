@@ -89,6 +89,7 @@ _SIGS = {
     "dao_get_dose": (c_int32, [c_void_p, c_void_p, POINTER(c_double)]),
     "dao_solve": (c_int32, [c_void_p, c_int32, POINTER(dao_plan)]),
     "dao_time_product": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double)]),
+    "dao_time_product_cold": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_int64, POINTER(c_double)]),
     "dao_profile_start": (c_int32, [c_void_p, c_int32]),
     "dao_profile_stop": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_double),
                                    POINTER(c_double)]),
@@ -271,6 +272,15 @@ class DaoContext:
         """Mean microseconds per launch of product kernel 0 (D x) or 1 (D^T u)."""
         us = c_double()
         self._check(self._lib.dao_time_product(self._h, int(kernel), int(iters), byref(us)))
+        return us.value
+
+    def time_product_cold(self, kernel: int, iters: int, scrub) -> float:
+        """As time_product, with a write of the device tensor `scrub` (its
+        whole size) before every timed launch to evict the caches."""
+        us = c_double()
+        nbytes = scrub.numel() * scrub.element_size()
+        self._check(self._lib.dao_time_product_cold(self._h, int(kernel), int(iters), c_void_p(_addr(scrub)),
+                                                    c_int64(nbytes), byref(us)))
         return us.value
 
     def profile_start(self, kernel: int) -> None:

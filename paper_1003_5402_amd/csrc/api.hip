@@ -599,7 +599,7 @@ dao_status gradient_typed(dao_ctx* c, const void* d, void* g, double* F) {
 // measured with HIP events on the context stream.  Inputs are the master's
 // current vectors; outputs go to scratch buffers.
 template <class T>
-dao_status time_product_typed(dao_ctx* c, int kernel, int iters, double* us) {
+dao_status time_product_typed(dao_ctx* c, int kernel, int iters, double* us, bool warm = true) {
     if (!c->vscratch) {   // k_dose scatters to caller order: V entries
         dao_status s = dev_alloc(c, &c->vscratch, size_t(c->V) * sizeof(T));
         if (s != DAO_OK) return s;
@@ -617,7 +617,7 @@ dao_status time_product_typed(dao_ctx* c, int kernel, int iters, double* us) {
                 c->csc_ptr, c->csc_row, static_cast<const T*>(c->csc_val), static_cast<const T*>(c->u),
                 static_cast<T*>(c->dx), nullptr);
     };
-    launch();
+    if (warm) launch();
     HIPCHK(c, hipEventRecord(e0, c->stream));
     for (int i = 0; i < iters; ++i) launch();
     HIPCHK(c, hipEventRecord(e1, c->stream));
@@ -628,6 +628,29 @@ dao_status time_product_typed(dao_ctx* c, int kernel, int iters, double* us) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     *us = 1e3 * double(ms) / iters;
+    return DAO_OK;
+}
+
+__global__ void k_scrub(uint4* __restrict__ p, int64_t n, uint32_t v) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+        p[i] = make_uint4(v, v + 1, v + 2, v + 3);
+}
+
+// Cold-cache timing: scrub, then one timed product, per iteration.
+template <class T>
+dao_status time_product_cold_typed(dao_ctx* c, int kernel, int iters, void* scrub, int64_t scrub_bytes,
+                                   double* us) {
+    double tot = 0.0;
+    for (int i = 0; i < iters; ++i) {
+        k_scrub<<<2048, BLOCK, 0, c->stream>>>(static_cast<uint4*>(scrub), scrub_bytes / 16, uint32_t(i));
+        LAUNCHCHK(c);
+        double one = 0.0;
+        dao_status s = time_product_typed<T>(c, kernel, 1, &one, false);
+        if (s != DAO_OK) return s;
+        tot += one;
+    }
+    *us = tot / iters;
     return DAO_OK;
 }
 
@@ -937,6 +960,17 @@ dao_status dao_time_product(dao_ctx* c, int32_t kernel, int32_t iters, double* u
         return c->fail(DAO_EINVAL, "kernel must be 0 or 1, iters >= 1");
     return c->dtype == DAO_F64 ? time_product_typed<double>(c, kernel, iters, us_per_launch)
                                : time_product_typed<float>(c, kernel, iters, us_per_launch);
+}
+
+dao_status dao_time_product_cold(dao_ctx* c, int32_t kernel, int32_t iters, void* scrub, int64_t scrub_bytes,
+                                 double* us_per_launch) {
+    if (!c) return DAO_EINVAL;
+    if ((kernel != 0 && kernel != 1) || iters < 1 || !us_per_launch)
+        return c->fail(DAO_EINVAL, "kernel must be 0 or 1, iters >= 1");
+    if (!scrub || scrub_bytes < (int64_t(1) << 20) || scrub_bytes % 16 != 0)
+        return c->fail(DAO_EINVAL, "scrub must be a device buffer of >= 1 MiB, a multiple of 16 bytes");
+    return c->dtype == DAO_F64 ? time_product_cold_typed<double>(c, kernel, iters, scrub, scrub_bytes, us_per_launch)
+                               : time_product_cold_typed<float>(c, kernel, iters, scrub, scrub_bytes, us_per_launch);
 }
 
 dao_status dao_profile_start(dao_ctx* c, int32_t kernel) {
