@@ -16,6 +16,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# device sources of the master kernels; HBM traffic figures taken with
+# rocprofv3 counters stay valid while these are unchanged
+KERNEL_SOURCES = ["dao_common.h", "kernels.h", "kernels_ap.h", "kernels_coop.h"]
+COPY_CALIB_BYTES = 512 << 20   # each of read and write of the calibration copy
+
 METRIC = "time-to-50-aperture plan (s), plans/s + p50/p99; D·x, Dᵀg HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
 
@@ -70,6 +75,54 @@ def cpu_baseline(ph, gpu_steps_per_plan, rounds_per_plan, seconds):
                 plan_seconds=plan_s)
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1003_5402_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, config):
+    """HBM bytes per launch of `kernel` from its committed counter summary
+    (profiles/<kernel>_<config>_traffic.md: "key: value" lines), or None when
+    there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{config}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip().strip("-* `")] = v.strip().strip("`")
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def pmc_workload(ctx, n_ap, torch):
+    """Short run for counter collection: one plan, then a plain device copy
+    of COPY_CALIB_BYTES (read and write) that calibrates FETCH_SIZE and
+    WRITE_SIZE against a known byte count."""
+    out = ctx.solve(n_ap)
+    log(f"[bench] pmc plan: rounds {out['rounds']} steps {out['total_steps']}")
+    n = COPY_CALIB_BYTES // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    log(f"[bench] pmc calibration: 3 copies of {COPY_CALIB_BYTES} bytes (torch.mul by 1.0)")
+    print(json.dumps({"pmc_workload": True, "source_sha256": kernel_source_hash(),
+                      "copy_bytes": COPY_CALIB_BYTES}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +133,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--product-iters", type=int, default=200)
+    ap.add_argument("--pmc-workload", action="store_true",
+                    help="one plan plus a calibration copy, for rocprofv3 --pmc runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the plan is a single-GPU workload "
@@ -103,6 +158,10 @@ def main():
     info = ctx.info()
     n_ap = ph.n_apertures
     log(f"[bench] ctx ready in {create_s:.2f} s: {info}")
+    if args.pmc_workload:
+        pmc_workload(ctx, n_ap, torch)
+        ctx.close()
+        return
 
     for w in range(args.warmup):
         out = ctx.solve(n_ap)
@@ -144,6 +203,7 @@ def main():
             f"{r['total_us'] / 1e3:.1f} ms, avg {r['avg_us']:.2f} us, {r['GBs']:.0f} GB/s")
     dom = max(kernels, key=lambda k: kernels[k]["total_us"])
     dk_ = kernels[dom]
+    traffic = measured_traffic(dom, args.config)
 
     # the plain products (the kernels behind dao_dose / dao_gradient)
     us_dose = ctx.time_product(0, args.product_iters)
@@ -201,7 +261,7 @@ def main():
         },
         "master_kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk_["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dk_["GBs"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": dk_["GBs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": dk_["total_bytes"] / max(1, dk_["launches"]),
                      "us_per_launch": dk_["avg_us"], "launches_per_plan": dk_["launches"]},
     }
