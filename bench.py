@@ -246,6 +246,8 @@ def main():
         "plan_s_p50": float(np.percentile(lat, 50)),
         "plan_s_p99": float(np.percentile(lat, 99)),
         "plan_s_mean": float(lat.mean()),
+        "plan_split_s": {"pricing": float(np.mean([o["price_s"] for o in outs])),
+                         "columns_and_master": float(np.mean([o["master_s"] for o in outs]))},
         "master_steps_per_plan": steps_per_plan,
         "ls_evals_per_plan": int(outs[-1]["total_ls_evals"]),
         "final_F": outs[-1]["F"],

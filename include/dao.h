@@ -251,6 +251,8 @@ typedef struct {
     int32_t* round_steps;
     double* round_kkt;
     double* round_F;
+    double price_s;           /* host wall-clock seconds in pricing (incl. the gradient refresh) */
+    double master_s;          /* host wall-clock seconds in column building and master solves */
 } dao_plan;
 
 /* Column generation (Section 2.2, Section 2.3) from an empty pool: round 1

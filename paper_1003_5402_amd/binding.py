@@ -61,7 +61,8 @@ class dao_plan(ctypes.Structure):
                 ("total_steps", c_int64), ("total_ls_evals", c_int64),
                 ("round_beam", POINTER(c_int32)), ("round_rc", POINTER(c_double)),
                 ("round_gap", POINTER(c_double)), ("round_steps", POINTER(c_int32)),
-                ("round_kkt", POINTER(c_double)), ("round_F", POINTER(c_double))]
+                ("round_kkt", POINTER(c_double)), ("round_F", POINTER(c_double)),
+                ("price_s", c_double), ("master_s", c_double)]
 
 
 # name -> (restype, argtypes); every symbol include/dao.h declares
@@ -301,4 +302,5 @@ class DaoContext:
         st = self._check(self._lib.dao_solve(self._h, int(n_apertures), byref(P)))
         r = P.rounds
         return dict(status=st, rounds=r, stop=P.stop, F=P.F, rc1=P.rc1, total_steps=P.total_steps,
-                    total_ls_evals=P.total_ls_evals, **{k: v[:r].copy() for k, v in arr.items()})
+                    total_ls_evals=P.total_ls_evals, price_s=P.price_s, master_s=P.master_s,
+                    **{k: v[:r].copy() for k, v in arr.items()})

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -679,11 +680,17 @@ dao_status solve_typed(dao_ctx* c, int32_t n_ap, dao_plan* out) {
     ls0 = c->ms_h->total_ls;
     std::vector<int16_t> lv(2 * c->maxRB);
     int rounds = 0;
+    using clk = std::chrono::steady_clock;
+    double t_price = 0.0, t_master = 0.0;
+    auto since = [](clk::time_point t0) { return std::chrono::duration<double>(clk::now() - t0).count(); };
     while (c->K < n_ap) {
         int32_t beam;
         double rc, gap;
+        const auto tp = clk::now();
         s = price_current<T>(c, &beam, lv.data(), &rc, &gap);
         if (s != DAO_OK) return s;
+        t_price += since(tp);
+        const auto tm = clk::now();
         if (std::isnan(rc1)) {
             rc1 = rc;
             if (!(rc1 < 0.0)) {
@@ -705,6 +712,7 @@ dao_status solve_typed(dao_ctx* c, int32_t n_ap, dao_plan* out) {
             eps /= 10.0;
             s = run_master<T>(c, eps * scale, c->opt.max_steps);
             if (s != DAO_OK) return s;
+            t_master += since(tm);
             continue;
         }
         if (c->K >= c->opt.max_apertures) return c->fail(DAO_ESTATE, "pool capacity reached");
@@ -716,6 +724,7 @@ dao_status solve_typed(dao_ctx* c, int32_t n_ap, dao_plan* out) {
         c->K += 1;
         s = run_master<T>(c, eps * scale, c->opt.max_steps);
         if (s != DAO_OK) return s;
+        t_master += since(tm);
         if (out) {
             if (out->round_beam) out->round_beam[rounds] = beam;
             if (out->round_rc) out->round_rc[rounds] = rc;
@@ -735,6 +744,8 @@ dao_status solve_typed(dao_ctx* c, int32_t n_ap, dao_plan* out) {
         out->rc1 = rc1;
         out->total_steps = c->ms_h->total_steps - steps0;
         out->total_ls_evals = c->ms_h->total_ls - ls0;
+        out->price_s = t_price;
+        out->master_s = t_master;
     }
     return DAO_OK;
 }
