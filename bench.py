@@ -198,6 +198,9 @@ def main():
         r = ctx.profile_stop()
         r["avg_us"] = r["total_us"] / max(1, r["launches"])
         r["GBs"] = r["total_bytes"] / max(r["total_us"], 1e-9) / 1e3
+        if kid == 4:
+            r["phases_us"] = ctx.profile_phases()
+            log(f"[bench] {kname} phases (us per plan): {r['phases_us']}")
         kernels[kname] = r
         log(f"[bench] {kname}: {r['launches']} launches ({r['working_launches']} working), "
             f"{r['total_us'] / 1e3:.1f} ms, avg {r['avg_us']:.2f} us, {r['GBs']:.0f} GB/s")

@@ -236,6 +236,14 @@ dao_status dao_profile_start(dao_ctx* ctx, int32_t kernel);
 dao_status dao_profile_stop(dao_ctx* ctx, int64_t* launches, int64_t* working_launches,
                             double* total_us, double* total_bytes);
 
+/* Split of the persistent master's time in the last profiling window of
+ * kernel 4, as seen by its workgroup 0 (device wall clock), into us[6]:
+ * update passes, their grid reductions, direction, line-search passes,
+ * their grid reductions, line-search decisions and y updates.  Zeros when
+ * the last window was another kernel's.  Reductions include waiting for the
+ * slowest workgroup. */
+dao_status dao_profile_phases(dao_ctx* ctx, double* us);
+
 /* Per-round log and outcome of dao_solve.  The arrays are caller-owned with
  * room for n_apertures entries each; any may be NULL. */
 typedef struct {

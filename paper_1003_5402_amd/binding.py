@@ -90,6 +90,7 @@ _SIGS = {
     "dao_get_dose": (c_int32, [c_void_p, c_void_p, POINTER(c_double)]),
     "dao_solve": (c_int32, [c_void_p, c_int32, POINTER(dao_plan)]),
     "dao_time_product": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double)]),
+    "dao_profile_phases": (c_int32, [c_void_p, POINTER(c_double)]),
     "dao_time_product_cold": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_int64, POINTER(c_double)]),
     "dao_profile_start": (c_int32, [c_void_p, c_int32]),
     "dao_profile_stop": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_double),
@@ -283,6 +284,13 @@ class DaoContext:
         self._check(self._lib.dao_time_product_cold(self._h, int(kernel), int(iters), c_void_p(_addr(scrub)),
                                                     c_int64(nbytes), byref(us)))
         return us.value
+
+    def profile_phases(self) -> Dict:
+        """Persistent master: microseconds per phase in the last profiling window."""
+        us = (c_double * 6)()
+        self._check(self._lib.dao_profile_phases(self._h, us))
+        names = ["update", "update_reduce", "direction", "ls_pass", "ls_reduce", "decide_step"]
+        return {n: float(us[i]) for i, n in enumerate(names)}
 
     def profile_start(self, kernel: int) -> None:
         self._check(self._lib.dao_profile_start(self._h, int(kernel)))

@@ -75,11 +75,13 @@ struct dao_ctx {
     double* parts2 = nullptr;  // [ap_blocks * (KS + 1)] update records of the aperture master
     ProfCounters* pc = nullptr;
     CoopSync* coop = nullptr;          // grid-reduction scratch of the persistent master
-    double* coop_recs = nullptr;       // [coop_grid * RECW]
+    double* coop_recs = nullptr;       // [2][coop_grid][RECW]
     int coop_grid = 0;                 // co-resident workgroups (0: persistent master unavailable)
     int coop_lds_max = 0;              // dynamic LDS the on-chip variant may use (0: never)
     ProfCounters* pc_h = nullptr;      // pinned
     int prof_kernel = -1;              // aperture-master kernel timed with events (-1: none)
+    double prof_phase_us[PROF_PHASES] = {};   // persistent master split of the last window
+    int device = 0;                    // HIP device of the context
     int last_steps = 0;                // steps of the previous master solve (chunk size guess)
     std::vector<hipEvent_t> prof_events;
     size_t prof_used = 0;
@@ -306,7 +308,8 @@ dao_status run_master_coop(dao_ctx* c, double tol, int max_steps) {
     LAUNCHCHK(c);
     HIPCHK(c, hipMemsetAsync(c->coop, 0, sizeof(CoopSync), c->stream));
     CoopArgs<T> A{static_cast<const T*>(c->dk), c->Vpad, c->Vnz, c->d, static_cast<T*>(c->q), c->cls_int,
-                  c->classes, c->ncls, c->y, c->p, c->gradk, c->ms, c->coop_recs, c->coop, c->pc};
+                  c->classes, c->ncls, c->y, c->p, c->gradk, c->ms, c->coop_recs, c->coop, c->pc,
+                  c->prof_kernel == 4 ? 1 : 0};
     void* args[] = {&A};
     const bool prof = c->prof_kernel == 4;
     if (prof) {
@@ -511,12 +514,13 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     if (c->ap_master() && c->opt.persistent) {
         int dev = 0, coop = 0, ncu = 0, occ = 0;
         HIPCHK(c, hipGetDevice(&dev));
+        c->device = dev;
         HIPCHK(c, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
         HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
         HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(
                       &occ, reinterpret_cast<const void*>(&k_master_coop<T, false>), BLOCK, 0));
         if (coop && occ > 0 && ncu > 0) {
-            c->coop_grid = ncu;   // one co-resident workgroup per compute unit
+            c->coop_grid = std::min(ncu, MAX_COOP_GRID);   // one co-resident workgroup per compute unit
             // on-chip variant: as much dynamic LDS as the device grants one
             // workgroup beyond the kernel's static LDS, if one per CU still fits
             int lds_max = 0;
@@ -533,7 +537,7 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
             }
             (void)hipGetLastError();
             TRY(dev_alloc(c, &c->coop, sizeof(CoopSync)));
-            TRY(dev_alloc(c, &c->coop_recs, size_t(c->coop_grid) * RECW * sizeof(double)));
+            TRY(dev_alloc(c, &c->coop_recs, 2 * size_t(c->coop_grid) * RECW * sizeof(double)));
         }
     }
     if (c->ap_master()) {
@@ -984,6 +988,12 @@ dao_status dao_time_product_cold(dao_ctx* c, int32_t kernel, int32_t iters, void
                                : time_product_cold_typed<float>(c, kernel, iters, scrub, scrub_bytes, us_per_launch);
 }
 
+dao_status dao_profile_phases(dao_ctx* c, double* us) {
+    if (!c || !us) return DAO_EINVAL;
+    for (int i = 0; i < PROF_PHASES; ++i) us[i] = c->prof_phase_us[i];
+    return DAO_OK;
+}
+
 dao_status dao_profile_start(dao_ctx* c, int32_t kernel) {
     if (!c) return DAO_EINVAL;
     if (kernel < 0 || kernel > 4) return c->fail(DAO_EINVAL, "kernel must be in [0, 4]");
@@ -1012,6 +1022,12 @@ dao_status dao_profile_stop(dao_ctx* c, int64_t* launches, int64_t* working_laun
     }
     HIPCHK(c, hipMemcpyAsync(c->pc_h, c->pc, sizeof(ProfCounters), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (k == 4) {
+        int rate_khz = 0;
+        HIPCHK(c, hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device));
+        for (int i = 0; i < PROF_PHASES; ++i)
+            c->prof_phase_us[i] = rate_khz > 0 ? 1e3 * double(c->pc_h->ticks[i]) / rate_khz : 0.0;
+    }
     if (launches) *launches = int64_t(c->prof_used / 2);
     if (working_launches) *working_launches = k == 4 ? int64_t(c->prof_used / 2) : int64_t(c->pc_h->real[k]);
     if (total_us) *total_us = us;

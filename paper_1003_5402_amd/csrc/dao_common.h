@@ -63,9 +63,12 @@ struct MasterState {
 // Work counters of the aperture master's kernels, kept by workgroup 0 of
 // every launch that does work: launches that ran and their algorithmic
 // bytes.  Index: 0 update pass, 1 q pass, 2 line-search pass, 3 direction.
+// The persistent master also splits workgroup 0's time into phases.
+constexpr int PROF_PHASES = 6;
 struct ProfCounters {
     double bytes[4];
     uint64_t real[4];
+    uint64_t ticks[PROF_PHASES];   // persistent master: wall-clock ticks per phase (workgroup 0)
 };
 
 // Pricing result written by the last block of the pricing launch.

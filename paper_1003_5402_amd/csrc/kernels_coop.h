@@ -14,14 +14,16 @@
 // redundantly (and identically) in every workgroup instead of being
 // broadcast.
 //
-// Grid-wide reduction: each workgroup publishes its record, arrives at one of
-// NSLOT counters; the last arrival of a counter sums that counter's records
-// (workgroups slot, slot + NSLOT, ... in order), the last counter sums the
-// counter totals in order and bumps a generation number that the other
-// workgroups wait for.  The order of every sum is fixed, so results do not
-// depend on arrival order.  Waits are bounded: a workgroup that waits too
-// long raises an abort flag that every waiter checks, so the grid always
-// drains.
+// Grid-wide reduction: each workgroup publishes its record in one of two
+// alternating buffers, waits for the data stores to complete, then raises its
+// own flag to the reduction's sequence number.  Every workgroup polls all
+// flags (one per thread) and then sums all records itself in workgroup order,
+// so the order of every sum is fixed and identical everywhere, and no
+// workgroup has to wait for a combining workgroup.  Two buffers suffice: a
+// workgroup can only write a buffer again after every workgroup has raised
+// its flag for the reduction in between, which each does only after it has
+// finished reading.  Waits are bounded: a workgroup that waits too long
+// raises an abort flag that every waiter checks, so the grid always drains.
 #pragma once
 
 #include "kernels_ap.h"
@@ -29,14 +31,12 @@
 namespace dao {
 
 constexpr int RECW = KS + 8;               // doubles per reduction record
+constexpr int MAX_COOP_GRID = 1024;        // workgroups of one persistent launch
 constexpr long SPIN_LIMIT = 4000000L;      // ~1 s of waiting before the grid aborts
 
 struct CoopSync {
-    uint32_t cnt[(NSLOT + 1) * SLOT_STRIDE];
-    uint32_t gen[SLOT_STRIDE];
     uint32_t abort_flag[SLOT_STRIDE];
-    double slot_rec[NSLOT][RECW];
-    double final_rec[RECW];
+    uint32_t flag[MAX_COOP_GRID * SLOT_STRIDE];   // one 128-byte line per workgroup
 };
 
 __device__ __forceinline__ double aload(const double* p) {
@@ -64,109 +64,86 @@ __device__ __forceinline__ double rec_init(int i) {
     return 0.0;
 }
 
-// Fixed-order combine of `count` records (record m at base + (first + m*step)
-// * RECW) into out[0..W) (LDS).  Columns are split into up to 4 contiguous
-// parts of records whose loads are issued 8 at a time; parts are combined
-// in order.  Called by all threads of a workgroup.
+// Fixed-order combine of `count` records (record m at base + m * RECW) into
+// out[0..W) (LDS).  Thread t takes field t % W of part t / W, a contiguous
+// run of records whose loads it issues up to 32 at a time (one workgroup per
+// CU leaves room for the registers); parts are then combined in order.
+// scratch: BLOCK doubles of LDS.  Called by all threads of a workgroup.
 template <bool LS>
-__device__ __forceinline__ void combine_records(const double* base, uint32_t first, uint32_t step, uint32_t count,
-                                                int W, double* out, double* scratch) {
-    const int nparts = max(1, min(4, int(blockDim.x) / max(W, 1)));
+__device__ __forceinline__ void combine_records(const double* base, uint32_t count, int W, double* out,
+                                                double* scratch) {
+    const int nparts = max(1, int(blockDim.x) / max(W, 1));
     const uint32_t per = (count + nparts - 1) / nparts;
-    for (int tt = threadIdx.x; tt < W * nparts; tt += blockDim.x) {
-        const int i = tt % W, j = tt / W;
+    if (int(threadIdx.x) < W * nparts) {
+        const int i = threadIdx.x % W, j = threadIdx.x / W;
         const uint32_t m0 = min(count, j * per), m1 = min(count, m0 + per);
         double acc = rec_init<LS>(i);
         uint32_t m = m0;
+        for (; m + 32 <= m1; m += 32) {
+            double v[32];
+#pragma unroll
+            for (int u = 0; u < 32; ++u) v[u] = aload(base + size_t(m + u) * RECW + i);
+#pragma unroll
+            for (int u = 0; u < 32; ++u) acc = rec_comb<LS>(i, acc, v[u]);
+        }
         for (; m + 8 <= m1; m += 8) {
             double v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = aload(base + size_t(first + (m + u) * step) * RECW + i);
+            for (int u = 0; u < 8; ++u) v[u] = aload(base + size_t(m + u) * RECW + i);
 #pragma unroll
             for (int u = 0; u < 8; ++u) acc = rec_comb<LS>(i, acc, v[u]);
         }
-        for (; m < m1; ++m) acc = rec_comb<LS>(i, acc, aload(base + size_t(first + m * step) * RECW + i));
-        scratch[j * RECW + i] = acc;
+        for (; m < m1; ++m) acc = rec_comb<LS>(i, acc, aload(base + size_t(m) * RECW + i));
+        scratch[j * W + i] = acc;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < W; i += blockDim.x) {
         double acc = rec_init<LS>(i);
-        for (int j = 0; j < nparts; ++j) acc = rec_comb<LS>(i, acc, scratch[j * RECW + i]);
+        for (int j = 0; j < nparts; ++j) acc = rec_comb<LS>(i, acc, scratch[j * W + i]);
         out[i] = acc;
     }
     __syncthreads();
 }
 
 // Grid-wide fixed-order reduction of W-double records (all threads of every
-// workgroup call it).  mine: this workgroup's record (LDS); total: result
-// (LDS, every workgroup).  Returns false when the grid aborted.
+// workgroup call it).  recs: two buffers of gridDim.x records; mine: this
+// workgroup's record (LDS); total: result (LDS, every workgroup); seq: this
+// workgroup's count of reductions so far.  Returns false when the grid
+// aborted.
 template <bool LS>
 __device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W, double* total,
-                            uint32_t& gen) {
-    __shared__ int s_flag;
-    __shared__ double s_scr[4 * RECW], s_sum[RECW];
-    const uint32_t nb = gridDim.x, b = blockIdx.x, slot = b % NSLOT;
-    for (int i = threadIdx.x; i < W; i += blockDim.x) astore(&recs[size_t(b) * RECW + i], mine[i]);
+                            uint32_t& seq) {
+    __shared__ int s_ok;
+    __shared__ double s_scr[BLOCK];
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    seq += 1;
+    double* buf = recs + size_t(seq & 1u) * nb * RECW;
+    for (int i = threadIdx.x; i < W; i += blockDim.x) astore(&buf[size_t(b) * RECW + i], mine[i]);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t expect = (nb - slot + NSLOT - 1) / NSLOT;
-        const uint32_t prev =
-            __hip_atomic_fetch_add(&S->cnt[slot * SLOT_STRIDE], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_flag = (prev + 1 == expect);
+        __hip_atomic_store(&S->flag[b * SLOT_STRIDE], seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_ok = 1;
     }
     __syncthreads();
-    if (s_flag) {
-        // last of its counter: the counter's records in workgroup order
-        const uint32_t cnt = (nb - slot + NSLOT - 1) / NSLOT;
-        combine_records<LS>(recs, slot, NSLOT, cnt, W, s_sum, s_scr);
-        for (int i = threadIdx.x; i < W; i += blockDim.x) astore(&S->slot_rec[slot][i], s_sum[i]);
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __hip_atomic_exchange(&S->cnt[slot * SLOT_STRIDE], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t ns = nb < NSLOT ? nb : NSLOT;
-            const uint32_t p2 =
-                __hip_atomic_fetch_add(&S->cnt[NSLOT * SLOT_STRIDE], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_flag = (p2 + 1 == ns);
-        }
-        __syncthreads();
-        if (s_flag) {
-            // last counter: counter totals in counter order, then release
-            const uint32_t ns = nb < NSLOT ? nb : NSLOT;
-            combine_records<LS>(&S->slot_rec[0][0], 0, 1, ns, W, s_sum, s_scr);
-            for (int i = threadIdx.x; i < W; i += blockDim.x) astore(&S->final_rec[i], s_sum[i]);
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                __hip_atomic_exchange(&S->cnt[NSLOT * SLOT_STRIDE], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __builtin_amdgcn_s_waitcnt(0);
-                __hip_atomic_fetch_add(&S->gen[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-    }
-    if (threadIdx.x == 0) {
+    for (uint32_t w = threadIdx.x; w < nb; w += blockDim.x) {
         long spins = 0;
-        int ok = 1;
-        while (aload_u(&S->gen[0]) == gen) {
+        while (aload_u(&S->flag[w * SLOT_STRIDE]) < seq) {
             __builtin_amdgcn_s_sleep(1);
             if (aload_u(&S->abort_flag[0])) {
-                ok = 0;
+                s_ok = 0;
                 break;
             }
             if (++spins > SPIN_LIMIT) {
                 __hip_atomic_store(&S->abort_flag[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
+                s_ok = 0;
                 break;
             }
         }
-        s_flag = ok;
     }
     __syncthreads();
-    gen += 1;
-    if (!s_flag) return false;
-    for (int i = threadIdx.x; i < W; i += blockDim.x) total[i] = aload(&S->final_rec[i]);
-    __syncthreads();
+    if (!s_ok) return false;
+    combine_records<LS>(buf, nb, W, total, s_scr);
     return true;
 }
 
@@ -183,9 +160,10 @@ struct CoopArgs {
     double* p;          // out: last direction (workgroup 0)
     double* grad;       // out: last grad_y (workgroup 0)
     MasterState* ms;    // in: state set by k_master_init_ap; out: final state (workgroup 0)
-    double* recs;       // [gridDim.x * RECW]
+    double* recs;       // [2][gridDim.x][RECW]
     CoopSync* sync;
     ProfCounters* pc;
+    int timing;         // workgroup 0 accumulates per-phase wall-clock ticks in pc->ticks
 };
 
 // Rows of workgroup b: batches [bat0, bat1) of ROWS rows (contiguous).
@@ -219,7 +197,6 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
     __shared__ double s_acc[NW][KS];
     __shared__ double s_wr[NW][8];
     __shared__ double s_u[NW][ROWS];
-    __shared__ uint32_t s_gen;
     __shared__ int s_go, s_fin;
 
     ms_load(s_ms, A.ms);
@@ -230,9 +207,8 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
         s_p[k] = 0.0;
         s_g[k] = 0.0;
     }
-    if (threadIdx.x == 0) s_gen = aload_u(&A.sync->gen[0]);
     __syncthreads();
-    uint32_t gen = s_gen;
+    uint32_t seq = 0;   // grid reductions so far (the flags start at 0 every launch)
 
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int rg = lane / G::LPR, c = lane % G::LPR;
@@ -267,6 +243,21 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
     auto cls_at = [&](int64_t row) -> uint8_t { return LDSRES ? cll[row - r0] : A.cls[row]; };
     bool alive = true;
     int mode = s_ms.refresh;   // first update keeps d (2) unless told otherwise
+    // phase timing (workgroup 0, thread 0): 0 update pass, 1 its reduction,
+    // 2 direction, 3 line-search passes, 4 their reductions, 5 decisions + step
+    __shared__ uint64_t s_tk[PROF_PHASES], s_t0;
+    const bool timer = A.timing && blockIdx.x == 0 && threadIdx.x == 0;
+    if (timer) {
+        for (int i = 0; i < PROF_PHASES; ++i) s_tk[i] = 0;
+        s_t0 = wall_clock64();
+    }
+    auto tick = [&](int ph) {
+        if (timer) {
+            const uint64_t now = wall_clock64();
+            s_tk[ph] += now - s_t0;
+            s_t0 = now;
+        }
+    };
 
     while (alive) {
         // ---------------- update pass: apply the step, dF/dz, F, grad_y partials
@@ -349,10 +340,12 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
                 A.pc->bytes[0] += per_row * double(A.Vnz);
                 A.pc->real[0] += 1;
             }
-            if (!grid_reduce<false>(A.sync, A.recs, s_rec, K + 1, s_tot, gen)) {
+            tick(0);
+            if (!grid_reduce<false>(A.sync, A.recs, s_rec, K + 1, s_tot, seq)) {
                 alive = false;
                 break;
             }
+            tick(1);
         }
         // ---------------- direction (identical in every workgroup)
         if (threadIdx.x < WAVE) {
@@ -397,6 +390,7 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
             }
         }
         __syncthreads();
+        tick(2);
         if (!s_go) break;
         // ---------------- line search: first evaluation computes q = D_K p
         bool first = true;
@@ -455,10 +449,12 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
                                           : (8.0 + double(sizeof(T)) + 1.0)) * double(A.Vnz);
                 A.pc->real[kk] += 1;
             }
-            if (!grid_reduce<true>(A.sync, A.recs, s_rec, 6, s_tot, gen)) {
+            tick(3);
+            if (!grid_reduce<true>(A.sync, A.recs, s_rec, 6, s_tot, seq)) {
                 alive = false;
                 break;
             }
+            tick(4);
             if (threadIdx.x == 0) {
                 const Rec tot{s_tot[0], s_tot[1], s_tot[2], s_tot[3], s_tot[4], s_tot[5]};
                 s_fin = ls_decide(s_ms, tot);
@@ -488,12 +484,15 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
             }
             __syncthreads();
             mode = s_ms.refresh;
+            tick(5);
         }
     }
     if (LDSRES) {
         __syncthreads();
         for (int64_t rr = threadIdx.x; rr < nrows; rr += blockDim.x) A.d[r0 + rr] = dl[rr];
     }
+    if (timer)
+        for (int i = 0; i < PROF_PHASES; ++i) A.pc->ticks[i] += s_tk[i];
     // workgroup 0 publishes the final state
     if (blockIdx.x == 0) {
         if (threadIdx.x < K) {
