@@ -182,7 +182,16 @@ __device__ __forceinline__ void ms_store(MasterState* g, const MasterState& s) {
 // Contribution of one voxel to the line-search evaluation at step t:
 // phi'(t) = sum q_j dF/dz_j(d_j + t q_j); slopes of phi' just right / left of
 // t (without the factor 2); nearest breakpoint above / below t.
-__device__ __forceinline__ void ls_voxel(const ObjClass& c, double d, double q, double t, Rec& r) {
+// Breakpoints of voxel z(t) = d + t q against its thresholds (NaN when the
+// term is absent or q = 0, so they never count).  They do not depend on t.
+__device__ __forceinline__ void ls_breakpoints(const ObjClass& c, double d, double q, double& bu, double& bo) {
+    bu = (c.a > 0.0 && q != 0.0) ? (c.t_under - d) / q : NAN;
+    bo = (c.b > 0.0 && q != 0.0) ? (c.t_over - d) / q : NAN;
+}
+
+// Line-search sums of one voxel at t, with its breakpoints given.
+__device__ __forceinline__ void ls_voxel_bp(const ObjClass& c, double d, double q, double bu, double bo, double t,
+                                            Rec& r) {
     const double z = d + t * q;
     r.s0 += q * grad_f(c, z);
     const bool ua = c.a > 0.0, ob = c.b > 0.0;
@@ -193,18 +202,17 @@ __device__ __forceinline__ void ls_voxel(const ObjClass& c, double d, double q, 
     const double q2 = q * q;
     r.s1 += q2 * ((under_r ? c.a : 0.0) + (over_r ? c.b : 0.0));
     r.s2 += q2 * ((under_l ? c.a : 0.0) + (over_l ? c.b : 0.0));
-    if (q != 0.0) {
-        if (ua) {
-            const double bp = (c.t_under - d) / q;
-            if (bp > t) r.mn = fmin(r.mn, bp);
-            if (bp < t) r.mx = fmax(r.mx, bp);
-        }
-        if (ob) {
-            const double bp = (c.t_over - d) / q;
-            if (bp > t) r.mn = fmin(r.mn, bp);
-            if (bp < t) r.mx = fmax(r.mx, bp);
-        }
-    }
+    // comparisons with NaN are false: absent breakpoints never count
+    if (bu > t) r.mn = fmin(r.mn, bu);
+    if (bu < t) r.mx = fmax(r.mx, bu);
+    if (bo > t) r.mn = fmin(r.mn, bo);
+    if (bo < t) r.mx = fmax(r.mx, bo);
+}
+
+__device__ __forceinline__ void ls_voxel(const ObjClass& c, double d, double q, double t, Rec& r) {
+    double bu, bo;
+    ls_breakpoints(c, d, q, bu, bo);
+    ls_voxel_bp(c, d, q, bu, bo, t, r);
 }
 
 // ---------------------------------------------------------------------------

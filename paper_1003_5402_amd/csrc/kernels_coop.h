@@ -17,9 +17,9 @@
 // Grid-wide reduction: each workgroup publishes its record in one of two
 // alternating buffers, waits for the data stores to complete, then raises its
 // own flag to the reduction's sequence number.  Every workgroup polls all
-// flags (one per thread) and then sums all records itself in workgroup order,
-// so the order of every sum is fixed and identical everywhere, and no
-// workgroup has to wait for a combining workgroup.  Two buffers suffice: a
+// flags (one per thread) and then sums all records itself in a fixed order,
+// identical everywhere, so no workgroup has to wait for a combining
+// workgroup.  Two buffers suffice: a
 // workgroup can only write a buffer again after every workgroup has raised
 // its flag for the reduction in between, which each does only after it has
 // finished reading.  Waits are bounded: a workgroup that waits too long
@@ -64,61 +64,59 @@ __device__ __forceinline__ double rec_init(int i) {
     return 0.0;
 }
 
-// Fixed-order combine of `count` records (record m at base + m * RECW) into
-// out[0..W) (LDS).  Thread t takes field t % W of part t / W, a contiguous
-// run of records whose loads it issues up to 32 at a time (one workgroup per
-// CU leaves room for the registers); parts are then combined in order.
-// scratch: BLOCK doubles of LDS.  Called by all threads of a workgroup.
+// Fixed-order combine of nb records of W doubles stored field-major (field i
+// of workgroup b at buf[i * nb + b]) into out[0..W) (LDS).  Each wavefront
+// takes groups of 8 fields; lane l reduces records l, l + 64, ... of each
+// field in that order, with all its loads of a pass in flight together
+// (coalesced across lanes), then the lanes combine by a butterfly, whose
+// result is the same in every lane and every workgroup.
 template <bool LS>
-__device__ __forceinline__ void combine_records(const double* base, uint32_t count, int W, double* out,
-                                                double* scratch) {
-    const int nparts = max(1, int(blockDim.x) / max(W, 1));
-    const uint32_t per = (count + nparts - 1) / nparts;
-    if (int(threadIdx.x) < W * nparts) {
-        const int i = threadIdx.x % W, j = threadIdx.x / W;
-        const uint32_t m0 = min(count, j * per), m1 = min(count, m0 + per);
-        double acc = rec_init<LS>(i);
-        uint32_t m = m0;
-        for (; m + 32 <= m1; m += 32) {
-            double v[32];
+__device__ __forceinline__ void combine_fields(const double* buf, uint32_t nb, int W, double* out) {
+    constexpr int GF = 8, L = 4;
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    for (int f0 = wave * GF; f0 < W; f0 += nw * GF) {
+        double acc[GF];
 #pragma unroll
-            for (int u = 0; u < 32; ++u) v[u] = aload(base + size_t(m + u) * RECW + i);
+        for (int g = 0; g < GF; ++g) acc[g] = rec_init<LS>(f0 + g);
+        for (uint32_t q0 = 0; q0 < nb; q0 += L * WAVE) {
+            double v[GF][L];
 #pragma unroll
-            for (int u = 0; u < 32; ++u) acc = rec_comb<LS>(i, acc, v[u]);
+            for (int g = 0; g < GF; ++g)
+#pragma unroll
+                for (int u = 0; u < L; ++u) {
+                    const uint32_t rec = q0 + u * WAVE + lane;
+                    v[g][u] = (f0 + g < W && rec < nb) ? aload(buf + size_t(f0 + g) * nb + rec) : rec_init<LS>(f0 + g);
+                }
+#pragma unroll
+            for (int g = 0; g < GF; ++g)
+#pragma unroll
+                for (int u = 0; u < L; ++u) acc[g] = rec_comb<LS>(f0 + g, acc[g], v[g][u]);
         }
-        for (; m + 8 <= m1; m += 8) {
-            double v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = aload(base + size_t(m + u) * RECW + i);
+        for (int off = WAVE / 2; off > 0; off >>= 1)
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc = rec_comb<LS>(i, acc, v[u]);
-        }
-        for (; m < m1; ++m) acc = rec_comb<LS>(i, acc, aload(base + size_t(m) * RECW + i));
-        scratch[j * W + i] = acc;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < W; i += blockDim.x) {
-        double acc = rec_init<LS>(i);
-        for (int j = 0; j < nparts; ++j) acc = rec_comb<LS>(i, acc, scratch[j * W + i]);
-        out[i] = acc;
+            for (int g = 0; g < GF; ++g) acc[g] = rec_comb<LS>(f0 + g, acc[g], __shfl_xor(acc[g], off, WAVE));
+        if (lane == 0)
+#pragma unroll
+            for (int g = 0; g < GF; ++g)
+                if (f0 + g < W) out[f0 + g] = acc[g];
     }
     __syncthreads();
 }
 
 // Grid-wide fixed-order reduction of W-double records (all threads of every
-// workgroup call it).  recs: two buffers of gridDim.x records; mine: this
-// workgroup's record (LDS); total: result (LDS, every workgroup); seq: this
-// workgroup's count of reductions so far.  Returns false when the grid
-// aborted.
+// workgroup call it).  recs: two field-major buffers of gridDim.x records;
+// mine: this workgroup's record (LDS); total: result (LDS, every workgroup);
+// seq: this workgroup's count of reductions so far.  Returns false when the
+// grid aborted.
 template <bool LS>
 __device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W, double* total,
                             uint32_t& seq) {
     __shared__ int s_ok;
-    __shared__ double s_scr[BLOCK];
     const uint32_t nb = gridDim.x, b = blockIdx.x;
     seq += 1;
     double* buf = recs + size_t(seq & 1u) * nb * RECW;
-    for (int i = threadIdx.x; i < W; i += blockDim.x) astore(&buf[size_t(b) * RECW + i], mine[i]);
+    for (int i = threadIdx.x; i < W; i += blockDim.x) astore(&buf[size_t(i) * nb + b], mine[i]);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -143,7 +141,7 @@ __device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W
     }
     __syncthreads();
     if (!s_ok) return false;
-    combine_records<LS>(buf, nb, W, total, s_scr);
+    combine_fields<LS>(buf, nb, W, total);
     return true;
 }
 
@@ -174,10 +172,11 @@ __host__ __device__ inline int64_t coop_batches_per_group(int64_t Vpad, int grid
 }
 
 // Dynamic LDS of the LDS-resident variant: the workgroup's D_K rows (nc
-// 16-byte vectors each), then d (double), q (T), class (uint8).
+// 16-byte vectors each), then d, the two breakpoints (double), q (T), class
+// (uint8).
 template <class T>
 __host__ __device__ inline size_t coop_lds_bytes(int64_t rows, int nc) {
-    return size_t(rows) * nc * 16 + size_t(rows) * (8 + sizeof(T) + 1) + 64;
+    return size_t(rows) * nc * 16 + size_t(rows) * (3 * 8 + sizeof(T) + 1) + 64;
 }
 
 // LDSRES: the workgroup copies its rows of D_K, d, q and the classes into
@@ -221,8 +220,10 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
     // on-chip copies (LDSRES)
     V* dkl = reinterpret_cast<V*>(dyn);
     double* dl = reinterpret_cast<double*>(dyn + size_t(nrows) * nc * 16);
-    T* ql = reinterpret_cast<T*>(dyn + size_t(nrows) * nc * 16 + size_t(nrows) * 8);
-    uint8_t* cll = reinterpret_cast<uint8_t*>(dyn + size_t(nrows) * nc * 16 + size_t(nrows) * (8 + sizeof(T)));
+    double* bul = dl + nrows;   // breakpoints of the current direction
+    double* bol = bul + nrows;
+    T* ql = reinterpret_cast<T*>(bol + nrows);
+    uint8_t* cll = reinterpret_cast<uint8_t*>(ql + nrows);
     if (LDSRES) {
         for (int64_t idx = threadIdx.x; idx < nrows * nc; idx += blockDim.x) {
             const int64_t rr = idx / nc;
@@ -403,7 +404,7 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
             double* sq = s_u[wave];
             for (int64_t bt = bat0 + wave; bt < bat1; bt += NW) {
                 const int64_t base = bt * ROWS;
-                if (first) {
+                if (first && !LDSRES) {
                     V v[IT];
 #pragma unroll
                     for (int it = 0; it < IT; ++it) {
@@ -422,14 +423,49 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
                 }
                 if (lane < ROWS) {
                     const int64_t row = base + lane;
-                    T qt;
-                    if (first) {
-                        qt = T(sq[lane]);   // the line search and the update use the stored value
-                        q_at(row) = qt;
+                    if (LDSRES) {
+                        // one row per lane, straight from LDS: the per-slot
+                        // partials are combined in the order of the lane
+                        // butterfly above, so q is the same to the bit
+                        const int64_t rr = row - r0;
+                        const ObjClass cc = cl[cll[rr]];
+                        const double dv = dl[rr];
+                        T qt;
+                        if (first) {
+                            const V* rp = dkl + rr * nc;
+                            double pc[G::LPR];
+#pragma unroll
+                            for (int j = 0; j < G::LPR; ++j) {
+                                const V v = j < nc ? rp[j] : vzero<V>();
+                                double part = 0.0;
+#pragma unroll
+                                for (int e = 0; e < G::EPL; ++e) part += vget(v, e) * s_p[j * G::EPL + e];
+                                pc[j] = part;
+                            }
+#pragma unroll
+                            for (int off = G::LPR / 2; off > 0; off >>= 1)
+#pragma unroll
+                                for (int j = 0; j < off; ++j) pc[j] = pc[j] + pc[j + off];
+                            qt = T(pc[0]);
+                            ql[rr] = qt;
+                            double bu, bo;
+                            ls_breakpoints(cc, dv, double(qt), bu, bo);
+                            bul[rr] = bu;
+                            bol[rr] = bo;
+                        } else {
+                            qt = ql[rr];
+                        }
+                        ls_voxel_bp(cc, dv, double(qt), bul[rr], bol[rr], t, r);
                     } else {
-                        qt = q_at(row);
+                        T qt;
+                        if (first) {
+                            qt = T(sq[lane]);   // the line search and the update use the stored value
+                            q_at(row) = qt;
+                        } else {
+                            qt = q_at(row);
+                        }
+                        ls_voxel(cl[cls_at(row)], d_at(row), double(qt), t, r);
                     }
-                    ls_voxel(cl[cls_at(row)], d_at(row), double(qt), t, r);
                 }
                 wave_sync();
             }
