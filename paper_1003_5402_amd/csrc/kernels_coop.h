@@ -64,42 +64,107 @@ __device__ __forceinline__ double rec_init(int i) {
     return 0.0;
 }
 
+// Wavefront reductions through DPP lane moves (no LDS round trip).  The
+// order is fixed: xor 1, xor 2 inside quads, half-row mirror, row mirror,
+// then the row broadcasts; lane 63 ends with the total, which is then read
+// into every lane.  Call with all 64 lanes active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v, double ident) {
+    const long long b = __double_as_longlong(v), id = __double_as_longlong(ident);
+    const int lo = __builtin_amdgcn_update_dpp(int(id), int(b), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(int(id >> 32), int(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ __forceinline__ double lane63(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(int(b), 63), hi = __builtin_amdgcn_readlane(int(b >> 32), 63);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+// op: 0 sum, 1 min, 2 max
+template <int OP>
+__device__ __forceinline__ double dpp_comb(double a, double b) {
+    return OP == 0 ? a + b : OP == 1 ? fmin(a, b) : fmax(a, b);
+}
+template <int OP>
+__device__ __forceinline__ double wave_reduce_dpp(double v) {
+    const double id = OP == 0 ? 0.0 : OP == 1 ? INFINITY : -INFINITY;
+    v = dpp_comb<OP>(v, dpp_move<0xB1, 0xF>(v, id));    // quad_perm [1,0,3,2]
+    v = dpp_comb<OP>(v, dpp_move<0x4E, 0xF>(v, id));    // quad_perm [2,3,0,1]
+    v = dpp_comb<OP>(v, dpp_move<0x141, 0xF>(v, id));   // row_half_mirror
+    v = dpp_comb<OP>(v, dpp_move<0x140, 0xF>(v, id));   // row_mirror
+    v = dpp_comb<OP>(v, dpp_move<0x142, 0xA>(v, id));   // row_bcast15 into rows 1, 3
+    v = dpp_comb<OP>(v, dpp_move<0x143, 0xC>(v, id));   // row_bcast31 into rows 2, 3
+    return lane63(v);
+}
+__device__ __forceinline__ double field_reduce_dpp(bool ls, int f, double v) {
+    if (ls && f == 3) return wave_reduce_dpp<1>(v);
+    if (ls && f == 4) return wave_reduce_dpp<2>(v);
+    return wave_reduce_dpp<0>(v);
+}
+
+// Line-search record of a workgroup (fields as Rec: s0, s1, s2, mn, mx, s5)
+// into out[0..6) (LDS), waves combined in order.  All threads call it.
+__device__ __forceinline__ void block_rec_dpp(const Rec& r, double* out) {
+    __shared__ double s_w[BLOCK / WAVE][6];
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    const double v0 = wave_reduce_dpp<0>(r.s0), v1 = wave_reduce_dpp<0>(r.s1), v2 = wave_reduce_dpp<0>(r.s2);
+    const double v3 = wave_reduce_dpp<1>(r.mn), v4 = wave_reduce_dpp<2>(r.mx), v5 = wave_reduce_dpp<0>(r.s5);
+    if (lane == 0) {
+        s_w[wave][0] = v0;
+        s_w[wave][1] = v1;
+        s_w[wave][2] = v2;
+        s_w[wave][3] = v3;
+        s_w[wave][4] = v4;
+        s_w[wave][5] = v5;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int f = threadIdx.x;
+        double acc = s_w[0][f];
+        for (int w = 1; w < int(blockDim.x) / WAVE; ++w)
+            acc = f == 3 ? fmin(acc, s_w[w][f]) : f == 4 ? fmax(acc, s_w[w][f]) : acc + s_w[w][f];
+        out[f] = acc;
+    }
+    __syncthreads();
+}
+
 // Fixed-order combine of nb records of W doubles stored field-major (field i
-// of workgroup b at buf[i * nb + b]) into out[0..W) (LDS).  Each wavefront
-// takes groups of 8 fields; lane l reduces records l, l + 64, ... of each
-// field in that order, with all its loads of a pass in flight together
-// (coalesced across lanes), then the lanes combine by a butterfly, whose
-// result is the same in every lane and every workgroup.
+// of workgroup b at buf[i * nb + b]) into out[0..W) (LDS).  Wavefront w takes
+// fields w, w + nw, ...; lane l reduces records l, l + 64, ... of each field
+// in that order, all its loads of a pass in flight together (coalesced
+// across lanes); the lanes then combine by wave_reduce_dpp.  Every workgroup
+// runs the same code on the same data, so all get the same bits.
+// Needs W <= 17 * wavefronts.
 template <bool LS>
 __device__ __forceinline__ void combine_fields(const double* buf, uint32_t nb, int W, double* out) {
-    constexpr int GF = 8, L = 4;
+    constexpr int FMAX = 17, L = 4;
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
-    for (int f0 = wave * GF; f0 < W; f0 += nw * GF) {
-        double acc[GF];
+    const int nf = wave < W ? (W - wave + nw - 1) / nw : 0;
+    double acc[FMAX];
 #pragma unroll
-        for (int g = 0; g < GF; ++g) acc[g] = rec_init<LS>(f0 + g);
-        for (uint32_t q0 = 0; q0 < nb; q0 += L * WAVE) {
-            double v[GF][L];
+    for (int i = 0; i < FMAX; ++i) acc[i] = rec_init<LS>(wave + nw * i);
+    for (uint32_t q0 = 0; q0 < nb; q0 += L * WAVE) {
+        double v[FMAX][L];
 #pragma unroll
-            for (int g = 0; g < GF; ++g)
+        for (int i = 0; i < FMAX; ++i)
 #pragma unroll
-                for (int u = 0; u < L; ++u) {
-                    const uint32_t rec = q0 + u * WAVE + lane;
-                    v[g][u] = (f0 + g < W && rec < nb) ? aload(buf + size_t(f0 + g) * nb + rec) : rec_init<LS>(f0 + g);
-                }
+            for (int u = 0; u < L; ++u) {
+                const int f = wave + nw * i;
+                const uint32_t rec = q0 + u * WAVE + lane;
+                v[i][u] = (i < nf && rec < nb) ? aload(buf + size_t(f) * nb + rec) : rec_init<LS>(f);
+            }
 #pragma unroll
-            for (int g = 0; g < GF; ++g)
+        for (int i = 0; i < FMAX; ++i)
 #pragma unroll
-                for (int u = 0; u < L; ++u) acc[g] = rec_comb<LS>(f0 + g, acc[g], v[g][u]);
+            for (int u = 0; u < L; ++u) acc[i] = rec_comb<LS>(wave + nw * i, acc[i], v[i][u]);
+    }
+#pragma unroll
+    for (int i = 0; i < FMAX; ++i) {
+        if (i < nf) {
+            const int f = wave + nw * i;
+            const double tot = field_reduce_dpp(LS, f, acc[i]);
+            if (lane == 0) out[f] = tot;
         }
-#pragma unroll
-        for (int off = WAVE / 2; off > 0; off >>= 1)
-#pragma unroll
-            for (int g = 0; g < GF; ++g) acc[g] = rec_comb<LS>(f0 + g, acc[g], __shfl_xor(acc[g], off, WAVE));
-        if (lane == 0)
-#pragma unroll
-            for (int g = 0; g < GF; ++g)
-                if (f0 + g < W) out[f0 + g] = acc[g];
     }
     __syncthreads();
 }
@@ -322,7 +387,7 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
             if (rg == 0)
 #pragma unroll
                 for (int e = 0; e < G::EPL; ++e) s_acc[wave][c * G::EPL + e] = acc[e];
-            Fp = wave_sum(Fp);
+            Fp = wave_reduce_dpp<0>(Fp);
             if (lane == 0) s_wr[wave][0] = Fp;
             __syncthreads();
             if (threadIdx.x < K) {
@@ -402,61 +467,62 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
 #pragma unroll
             for (int e = 0; e < G::EPL; ++e) pv[e] = s_p[c * G::EPL + e];
             double* sq = s_u[wave];
-            for (int64_t bt = bat0 + wave; bt < bat1; bt += NW) {
-                const int64_t base = bt * ROWS;
-                if (first && !LDSRES) {
-                    V v[IT];
+            if (LDSRES) {
+                // one row per thread, straight from LDS; q's per-slot partials
+                // are combined in the order of the lane butterfly of the
+                // streaming form below, so q is the same to the bit
+                for (int64_t rr = threadIdx.x; rr < nrows; rr += BLOCK) {
+                    const ObjClass cc = cl[cll[rr]];
+                    const double dv = dl[rr];
+                    T qt;
+                    if (first) {
+                        const V* rp = dkl + rr * nc;
+                        double pc[G::LPR];
 #pragma unroll
-                    for (int it = 0; it < IT; ++it) {
-                        v[it] = vzero<V>();
-                        if (c < nc) v[it] = dk_vec(base + it * G::RPW + rg);
-                    }
+                        for (int j = 0; j < G::LPR; ++j) {
+                            const V v = j < nc ? rp[j] : vzero<V>();
+                            double part = 0.0;
 #pragma unroll
-                    for (int it = 0; it < IT; ++it) {
-                        double part = 0.0;
-#pragma unroll
-                        for (int e = 0; e < G::EPL; ++e) part += vget(v[it], e) * pv[e];
-                        part = group_sum<G::LPR>(part);
-                        if (c == 0) sq[it * G::RPW + rg] = part;
-                    }
-                    wave_sync();
-                }
-                if (lane < ROWS) {
-                    const int64_t row = base + lane;
-                    if (LDSRES) {
-                        // one row per lane, straight from LDS: the per-slot
-                        // partials are combined in the order of the lane
-                        // butterfly above, so q is the same to the bit
-                        const int64_t rr = row - r0;
-                        const ObjClass cc = cl[cll[rr]];
-                        const double dv = dl[rr];
-                        T qt;
-                        if (first) {
-                            const V* rp = dkl + rr * nc;
-                            double pc[G::LPR];
-#pragma unroll
-                            for (int j = 0; j < G::LPR; ++j) {
-                                const V v = j < nc ? rp[j] : vzero<V>();
-                                double part = 0.0;
-#pragma unroll
-                                for (int e = 0; e < G::EPL; ++e) part += vget(v, e) * s_p[j * G::EPL + e];
-                                pc[j] = part;
-                            }
-#pragma unroll
-                            for (int off = G::LPR / 2; off > 0; off >>= 1)
-#pragma unroll
-                                for (int j = 0; j < off; ++j) pc[j] = pc[j] + pc[j + off];
-                            qt = T(pc[0]);
-                            ql[rr] = qt;
-                            double bu, bo;
-                            ls_breakpoints(cc, dv, double(qt), bu, bo);
-                            bul[rr] = bu;
-                            bol[rr] = bo;
-                        } else {
-                            qt = ql[rr];
+                            for (int e = 0; e < G::EPL; ++e) part += vget(v, e) * s_p[j * G::EPL + e];
+                            pc[j] = part;
                         }
-                        ls_voxel_bp(cc, dv, double(qt), bul[rr], bol[rr], t, r);
+#pragma unroll
+                        for (int off = G::LPR / 2; off > 0; off >>= 1)
+#pragma unroll
+                            for (int j = 0; j < off; ++j) pc[j] = pc[j] + pc[j + off];
+                        qt = T(pc[0]);   // the line search and the update use the stored value
+                        ql[rr] = qt;
+                        double bu, bo;
+                        ls_breakpoints(cc, dv, double(qt), bu, bo);
+                        bul[rr] = bu;
+                        bol[rr] = bo;
                     } else {
+                        qt = ql[rr];
+                    }
+                    ls_voxel_bp(cc, dv, double(qt), bul[rr], bol[rr], t, r);
+                }
+            } else {
+                for (int64_t bt = bat0 + wave; bt < bat1; bt += NW) {
+                    const int64_t base = bt * ROWS;
+                    if (first) {
+                        V v[IT];
+#pragma unroll
+                        for (int it = 0; it < IT; ++it) {
+                            v[it] = vzero<V>();
+                            if (c < nc) v[it] = dk_vec(base + it * G::RPW + rg);
+                        }
+#pragma unroll
+                        for (int it = 0; it < IT; ++it) {
+                            double part = 0.0;
+#pragma unroll
+                            for (int e = 0; e < G::EPL; ++e) part += vget(v[it], e) * pv[e];
+                            part = group_sum<G::LPR>(part);
+                            if (c == 0) sq[it * G::RPW + rg] = part;
+                        }
+                        wave_sync();
+                    }
+                    if (lane < ROWS) {
+                        const int64_t row = base + lane;
                         T qt;
                         if (first) {
                             qt = T(sq[lane]);   // the line search and the update use the stored value
@@ -466,19 +532,10 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
                         }
                         ls_voxel(cl[cls_at(row)], d_at(row), double(qt), t, r);
                     }
+                    wave_sync();
                 }
-                wave_sync();
             }
-            const Rec br = block_reduce(r);
-            if (threadIdx.x == 0) {
-                s_rec[0] = br.s0;
-                s_rec[1] = br.s1;
-                s_rec[2] = br.s2;
-                s_rec[3] = br.mn;
-                s_rec[4] = br.mx;
-                s_rec[5] = br.s5;
-            }
-            __syncthreads();
+            block_rec_dpp(r, s_rec);
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 const int kk = first ? 1 : 2;
                 A.pc->bytes[kk] += (first ? (16.0 * nc + 8.0 + 1.0 + double(sizeof(T)))
