@@ -134,10 +134,10 @@ __device__ __forceinline__ void block_rec_dpp(const Rec& r, double* out) {
 // in that order, all its loads of a pass in flight together (coalesced
 // across lanes); the lanes then combine by wave_reduce_dpp.  Every workgroup
 // runs the same code on the same data, so all get the same bits.
-// Needs W <= 17 * wavefronts.
-template <bool LS>
+// Needs W <= FMAX * wavefronts.
+template <bool LS, int FMAX>
 __device__ __forceinline__ void combine_fields(const double* buf, uint32_t nb, int W, double* out) {
-    constexpr int FMAX = 17, L = 4;
+    constexpr int L = 4;
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
     const int nf = wave < W ? (W - wave + nw - 1) / nw : 0;
     double acc[FMAX];
@@ -151,7 +151,9 @@ __device__ __forceinline__ void combine_fields(const double* buf, uint32_t nb, i
             for (int u = 0; u < L; ++u) {
                 const int f = wave + nw * i;
                 const uint32_t rec = q0 + u * WAVE + lane;
-                v[i][u] = (i < nf && rec < nb) ? aload(buf + size_t(f) * nb + rec) : rec_init<LS>(f);
+                // always load a valid address (no branch per load), keep the value only when it counts
+                const double x = aload(buf + size_t(i < nf ? f : 0) * nb + (rec < nb ? rec : 0));
+                v[i][u] = (i < nf && rec < nb) ? x : rec_init<LS>(f);
             }
 #pragma unroll
         for (int i = 0; i < FMAX; ++i)
@@ -206,7 +208,7 @@ __device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W
     }
     __syncthreads();
     if (!s_ok) return false;
-    combine_fields<LS>(buf, nb, W, total);
+    combine_fields<LS, LS ? 2 : 17>(buf, nb, W, total);
     return true;
 }
 
