@@ -237,9 +237,10 @@ dao_status dao_profile_stop(dao_ctx* ctx, int64_t* launches, int64_t* working_la
                             double* total_us, double* total_bytes);
 
 /* Split of the persistent master's time in the last profiling window of
- * kernel 4, as seen by its workgroup 0 (device wall clock), into us[6]:
- * update passes, their grid reductions, direction, line-search passes,
- * their grid reductions, line-search decisions and y updates.  Zeros when
+ * kernel 4, as seen by its workgroup 0 (device wall clock), into us[7]:
+ * update passes, their grid reductions, direction, first line-search passes
+ * (q = D_K p), line-search grid reductions, final decisions and y updates,
+ * later line-search passes (with the decision before each).  Zeros when
  * the last window was another kernel's.  Reductions include waiting for the
  * slowest workgroup. */
 dao_status dao_profile_phases(dao_ctx* ctx, double* us);

@@ -287,9 +287,10 @@ class DaoContext:
 
     def profile_phases(self) -> Dict:
         """Persistent master: microseconds per phase in the last profiling window."""
-        us = (c_double * 6)()
+        us = (c_double * 7)()
         self._check(self._lib.dao_profile_phases(self._h, us))
-        names = ["update", "update_reduce", "direction", "ls_pass", "ls_reduce", "decide_step"]
+        names = ["update", "update_reduce", "direction", "ls_first_pass", "ls_reduce", "decide_step",
+                 "ls_later_passes"]
         return {n: float(us[i]) for i, n in enumerate(names)}
 
     def profile_start(self, kernel: int) -> None:

@@ -64,7 +64,7 @@ struct MasterState {
 // every launch that does work: launches that ran and their algorithmic
 // bytes.  Index: 0 update pass, 1 q pass, 2 line-search pass, 3 direction.
 // The persistent master also splits workgroup 0's time into phases.
-constexpr int PROF_PHASES = 6;
+constexpr int PROF_PHASES = 7;
 struct ProfCounters {
     double bytes[4];
     uint64_t real[4];

@@ -151,9 +151,7 @@ __device__ __forceinline__ void combine_fields(const double* buf, uint32_t nb, i
             for (int u = 0; u < L; ++u) {
                 const int f = wave + nw * i;
                 const uint32_t rec = q0 + u * WAVE + lane;
-                // always load a valid address (no branch per load), keep the value only when it counts
-                const double x = aload(buf + size_t(i < nf ? f : 0) * nb + (rec < nb ? rec : 0));
-                v[i][u] = (i < nf && rec < nb) ? x : rec_init<LS>(f);
+                v[i][u] = (i < nf && rec < nb) ? aload(buf + size_t(f) * nb + rec) : rec_init<LS>(f);
             }
 #pragma unroll
         for (int i = 0; i < FMAX; ++i)
@@ -312,7 +310,9 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
     bool alive = true;
     int mode = s_ms.refresh;   // first update keeps d (2) unless told otherwise
     // phase timing (workgroup 0, thread 0): 0 update pass, 1 its reduction,
-    // 2 direction, 3 line-search passes, 4 their reductions, 5 decisions + step
+    // 2 direction, 3 first line-search pass (q), 4 line-search reductions,
+    // 5 final decision + step, 6 later line-search passes (with the decision
+    // that asked for them)
     __shared__ uint64_t s_tk[PROF_PHASES], s_t0;
     const bool timer = A.timing && blockIdx.x == 0 && threadIdx.x == 0;
     if (timer) {
@@ -544,7 +544,7 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
                                           : (8.0 + double(sizeof(T)) + 1.0)) * double(A.Vnz);
                 A.pc->real[kk] += 1;
             }
-            tick(3);
+            tick(first ? 3 : 6);
             if (!grid_reduce<true>(A.sync, A.recs, s_rec, 6, s_tot, seq)) {
                 alive = false;
                 break;
