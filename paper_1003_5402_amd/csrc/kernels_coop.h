@@ -17,9 +17,9 @@
 // Grid-wide reduction without flags: records live in three rotating buffers
 // whose slots are reset to an "empty" bit pattern (all ones, a NaN that
 // arithmetic on finite data never produces).  A workgroup stores its record
-// with agent-scope atomic stores and goes straight on to read every record,
-// reloading any field that is still empty, so the data is its own arrival
-// signal.  Right after a reduction a workgroup resets its own slot in the
+// with agent-scope atomic stores and goes straight on to read every record:
+// it waits for field 0 of each record, then loads whole records, reloading
+// any field that is still empty, so the data is its own arrival signal.  Right after a reduction a workgroup resets its own slot in the
 // buffer that the reduction after next will use (every workgroup has
 // finished reading it by then), and it waits for that reset to complete
 // before it stores its next record, so anyone who sees the next record also
@@ -159,6 +159,24 @@ __device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W
     const int f = lane % W, g = lane / W;
     const uint32_t per_w = (nb + nw - 1) / nw;
     const uint32_t r0 = min(nb, uint32_t(wave) * per_w), r1 = min(nb, r0 + per_w);
+    // first wait (one load per lane and record) until field 0 of each of
+    // this wavefront's records has arrived; only then read whole records, so
+    // the polling traffic stays one load per record
+    for (uint32_t rq = r0 + lane; rq < r1; rq += WAVE) {
+        long spins = 0;
+        while (rec_empty(aload(&buf[size_t(rq) * RECW]))) {
+            __builtin_amdgcn_s_sleep(1);
+            if (aload_u(&S->abort_flag[0])) {
+                s_ok = 0;
+                break;
+            }
+            if (++spins > SPIN_LIMIT) {
+                __hip_atomic_store(&S->abort_flag[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_ok = 0;
+                break;
+            }
+        }
+    }
     double acc = rec_init<LS>(f);
     if (g < G) {
         for (uint32_t rb = r0 + g; rb < r1; rb += uint32_t(NL * G)) {
