@@ -75,7 +75,7 @@ struct dao_ctx {
     double* parts2 = nullptr;  // [ap_blocks * (KS + 1)] update records of the aperture master
     ProfCounters* pc = nullptr;
     CoopSync* coop = nullptr;          // grid-reduction scratch of the persistent master
-    double* coop_recs = nullptr;       // [REC_BUFS][coop_grid][RECW]
+    double* coop_recs = nullptr;       // [2][coop_grid][RECW]
     int coop_grid = 0;                 // co-resident workgroups (0: persistent master unavailable)
     int coop_lds_max = 0;              // dynamic LDS the on-chip variant may use (0: never)
     ProfCounters* pc_h = nullptr;      // pinned
@@ -307,9 +307,6 @@ dao_status run_master_coop(dao_ctx* c, double tol, int max_steps) {
     k_master_init_ap<<<1, 1, 0, c->stream>>>(c->ms, c->K, tol, max_steps);
     LAUNCHCHK(c);
     HIPCHK(c, hipMemsetAsync(c->coop, 0, sizeof(CoopSync), c->stream));
-    // every record slot starts empty (all-ones bytes)
-    HIPCHK(c, hipMemsetAsync(c->coop_recs, 0xFF, size_t(REC_BUFS) * c->coop_grid * RECW * sizeof(double),
-                             c->stream));
     CoopArgs<T> A{static_cast<const T*>(c->dk), c->Vpad, c->Vnz, c->d, static_cast<T*>(c->q), c->cls_int,
                   c->classes, c->ncls, c->y, c->p, c->gradk, c->ms, c->coop_recs, c->coop, c->pc,
                   c->prof_kernel == 4 ? 1 : 0};
@@ -540,7 +537,7 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
             }
             (void)hipGetLastError();
             TRY(dev_alloc(c, &c->coop, sizeof(CoopSync)));
-            TRY(dev_alloc(c, &c->coop_recs, size_t(REC_BUFS) * c->coop_grid * RECW * sizeof(double)));
+            TRY(dev_alloc(c, &c->coop_recs, 2 * size_t(c->coop_grid) * RECW * sizeof(double)));
         }
     }
     if (c->ap_master()) {

@@ -14,19 +14,16 @@
 // redundantly (and identically) in every workgroup instead of being
 // broadcast.
 //
-// Grid-wide reduction without flags: records live in three rotating buffers
-// whose slots are reset to an "empty" bit pattern (all ones, a NaN that
-// arithmetic on finite data never produces).  A workgroup stores its record
-// with agent-scope atomic stores and goes straight on to read every record:
-// it waits for field 0 of each record, then loads whole records, reloading
-// any field that is still empty, so the data is its own arrival signal.  Right after a reduction a workgroup resets its own slot in the
-// buffer that the reduction after next will use (every workgroup has
-// finished reading it by then), and it waits for that reset to complete
-// before it stores its next record, so anyone who sees the next record also
-// sees the reset.  Every workgroup sums all records itself in one fixed
-// order, so all hold the same bits.  Waits are bounded: a workgroup that
-// waits too long raises an abort flag that every waiter checks, so the grid
-// always drains.
+// Grid-wide reduction: each workgroup publishes its record in one of two
+// alternating buffers, waits for the data stores to complete, then raises its
+// own flag to the reduction's sequence number.  Every workgroup polls all
+// flags (one per thread) and then sums all records itself in a fixed order,
+// identical everywhere, so no workgroup has to wait for a combining
+// workgroup.  Two buffers suffice: a
+// workgroup can only write a buffer again after every workgroup has raised
+// its flag for the reduction in between, which each does only after it has
+// finished reading.  Waits are bounded: a workgroup that waits too long
+// raises an abort flag that every waiter checks, so the grid always drains.
 #pragma once
 
 #include "kernels_ap.h"
@@ -37,14 +34,10 @@ constexpr int RECW = KS + 8;               // doubles per reduction record
 constexpr int MAX_COOP_GRID = 1024;        // workgroups of one persistent launch
 constexpr long SPIN_LIMIT = 4000000L;      // ~1 s of waiting before the grid aborts
 
-constexpr int REC_BUFS = 3;                // rotating record buffers
-
 struct CoopSync {
     uint32_t abort_flag[SLOT_STRIDE];
+    uint32_t flag[MAX_COOP_GRID * SLOT_STRIDE];   // one 128-byte line per workgroup
 };
-
-__device__ __forceinline__ bool rec_empty(double v) { return __double_as_longlong(v) == -1LL; }
-__device__ __forceinline__ double rec_empty_value() { return __longlong_as_double(-1LL); }
 
 __device__ __forceinline__ double aload(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -103,6 +96,12 @@ __device__ __forceinline__ double wave_reduce_dpp(double v) {
     v = dpp_comb<OP>(v, dpp_move<0x143, 0xC>(v, id));   // row_bcast31 into rows 2, 3
     return lane63(v);
 }
+__device__ __forceinline__ double field_reduce_dpp(bool ls, int f, double v) {
+    if (ls && f == 3) return wave_reduce_dpp<1>(v);
+    if (ls && f == 4) return wave_reduce_dpp<2>(v);
+    return wave_reduce_dpp<0>(v);
+}
+
 // Line-search record of a workgroup (fields as Rec: s0, s1, s2, mn, mx, s5)
 // into out[0..6) (LDS), waves combined in order.  All threads call it.
 __device__ __forceinline__ void block_rec_dpp(const Rec& r, double* out) {
@@ -129,42 +128,70 @@ __device__ __forceinline__ void block_rec_dpp(const Rec& r, double* out) {
     __syncthreads();
 }
 
-// Grid-wide fixed-order reduction of W-double records (all threads of every
-// workgroup call it).  recs: REC_BUFS record-major buffers of gridDim.x
-// records of RECW doubles, every slot empty at launch; mine: this
-// workgroup's record (LDS); total: result (LDS, every workgroup); seq: this
-// workgroup's count of reductions so far.  Wavefront w reads records
-// [w nb/4, (w+1) nb/4); lane l takes field l % W of every (64 / W)-th of
-// them (all its loads of a chunk in flight, coalesced along the fields);
-// partials are then combined in (wavefront, group) order.  NL: loads per
-// lane and chunk.  Returns false when the grid aborted.
-template <bool LS, int NL>
-__device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W, double* total,
-                            uint32_t& seq, int reset_w) {
-    __shared__ int s_ok;
-    __shared__ double s_part[BLOCK];
-    const uint32_t nb = gridDim.x, b = blockIdx.x;
-    double* buf = recs + size_t(seq % REC_BUFS) * nb * RECW;
-    double* later = recs + size_t((seq + 2) % REC_BUFS) * nb * RECW;   // used by the reduction after next
-    seq += 1;
-    // the reset of this slot issued after the previous reduction is complete
-    // in every thread before any field of the new record can be seen
-    __builtin_amdgcn_s_waitcnt(0);
-    if (threadIdx.x == 0) s_ok = 1;
-    __syncthreads();
-    for (int i = threadIdx.x; i < W; i += blockDim.x) astore(&buf[size_t(b) * RECW + i], mine[i]);
-
+// Fixed-order combine of nb records of W doubles stored field-major (field i
+// of workgroup b at buf[i * nb + b]) into out[0..W) (LDS).  Wavefront w takes
+// fields w, w + nw, ...; lane l reduces records l, l + 64, ... of each field
+// in that order, all its loads of a pass in flight together (coalesced
+// across lanes); the lanes then combine by wave_reduce_dpp.  Every workgroup
+// runs the same code on the same data, so all get the same bits.
+// Needs W <= FMAX * wavefronts.
+template <bool LS, int FMAX>
+__device__ __forceinline__ void combine_fields(const double* buf, uint32_t nb, int W, double* out) {
+    constexpr int L = 4;
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
-    const int G = max(1, WAVE / W);
-    const int f = lane % W, g = lane / W;
-    const uint32_t per_w = (nb + nw - 1) / nw;
-    const uint32_t r0 = min(nb, uint32_t(wave) * per_w), r1 = min(nb, r0 + per_w);
-    // first wait (one load per lane and record) until field 0 of each of
-    // this wavefront's records has arrived; only then read whole records, so
-    // the polling traffic stays one load per record
-    for (uint32_t rq = r0 + lane; rq < r1; rq += WAVE) {
+    const int nf = wave < W ? (W - wave + nw - 1) / nw : 0;
+    double acc[FMAX];
+#pragma unroll
+    for (int i = 0; i < FMAX; ++i) acc[i] = rec_init<LS>(wave + nw * i);
+    for (uint32_t q0 = 0; q0 < nb; q0 += L * WAVE) {
+        double v[FMAX][L];
+#pragma unroll
+        for (int i = 0; i < FMAX; ++i)
+#pragma unroll
+            for (int u = 0; u < L; ++u) {
+                const int f = wave + nw * i;
+                const uint32_t rec = q0 + u * WAVE + lane;
+                v[i][u] = (i < nf && rec < nb) ? aload(buf + size_t(f) * nb + rec) : rec_init<LS>(f);
+            }
+#pragma unroll
+        for (int i = 0; i < FMAX; ++i)
+#pragma unroll
+            for (int u = 0; u < L; ++u) acc[i] = rec_comb<LS>(wave + nw * i, acc[i], v[i][u]);
+    }
+#pragma unroll
+    for (int i = 0; i < FMAX; ++i) {
+        if (i < nf) {
+            const int f = wave + nw * i;
+            const double tot = field_reduce_dpp(LS, f, acc[i]);
+            if (lane == 0) out[f] = tot;
+        }
+    }
+    __syncthreads();
+}
+
+// Grid-wide fixed-order reduction of W-double records (all threads of every
+// workgroup call it).  recs: two field-major buffers of gridDim.x records;
+// mine: this workgroup's record (LDS); total: result (LDS, every workgroup);
+// seq: this workgroup's count of reductions so far.  Returns false when the
+// grid aborted.
+template <bool LS>
+__device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W, double* total,
+                            uint32_t& seq) {
+    __shared__ int s_ok;
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    seq += 1;
+    double* buf = recs + size_t(seq & 1u) * nb * RECW;
+    for (int i = threadIdx.x; i < W; i += blockDim.x) astore(&buf[size_t(i) * nb + b], mine[i]);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&S->flag[b * SLOT_STRIDE], seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_ok = 1;
+    }
+    __syncthreads();
+    for (uint32_t w = threadIdx.x; w < nb; w += blockDim.x) {
         long spins = 0;
-        while (rec_empty(aload(&buf[size_t(rq) * RECW]))) {
+        while (aload_u(&S->flag[w * SLOT_STRIDE]) < seq) {
             __builtin_amdgcn_s_sleep(1);
             if (aload_u(&S->abort_flag[0])) {
                 s_ok = 0;
@@ -177,56 +204,9 @@ __device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W
             }
         }
     }
-    double acc = rec_init<LS>(f);
-    if (g < G) {
-        for (uint32_t rb = r0 + g; rb < r1; rb += uint32_t(NL * G)) {
-            double v[NL];
-#pragma unroll
-            for (int k = 0; k < NL; ++k) {
-                const uint32_t r = rb + uint32_t(k * G);
-                v[k] = r < r1 ? aload(&buf[size_t(r) * RECW + f]) : rec_init<LS>(f);
-            }
-            // wait until every field of the chunk has arrived: reload the
-            // empty ones after a short sleep (bounded)
-            for (long spins = 0;; ++spins) {
-                bool missing = false;
-#pragma unroll
-                for (int k = 0; k < NL; ++k) missing |= rb + uint32_t(k * G) < r1 && rec_empty(v[k]);
-                if (!missing) break;
-                __builtin_amdgcn_s_sleep(1);
-                if (aload_u(&S->abort_flag[0])) {
-                    s_ok = 0;
-                    break;
-                }
-                if (spins > SPIN_LIMIT) {
-                    __hip_atomic_store(&S->abort_flag[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    s_ok = 0;
-                    break;
-                }
-#pragma unroll
-                for (int k = 0; k < NL; ++k) {
-                    const uint32_t r = rb + uint32_t(k * G);
-                    if (r < r1 && rec_empty(v[k])) v[k] = aload(&buf[size_t(r) * RECW + f]);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < NL; ++k) acc = rec_comb<LS>(f, acc, v[k]);
-        }
-        s_part[wave * WAVE + lane] = acc;
-    }
     __syncthreads();
     if (!s_ok) return false;
-    if (int(threadIdx.x) < W) {
-        const int fi = threadIdx.x;
-        double t = rec_init<LS>(fi);
-        for (int w = 0; w < nw; ++w)
-            for (int gg = 0; gg < G; ++gg) t = rec_comb<LS>(fi, t, s_part[w * WAVE + gg * W + fi]);
-        total[fi] = t;
-    }
-    // every workgroup has finished reading `later` (it last served the
-    // reduction before this one): empty this workgroup's slot there
-    for (int i = threadIdx.x; i < reset_w; i += blockDim.x) astore(&later[size_t(b) * RECW + i], rec_empty_value());
-    __syncthreads();
+    combine_fields<LS, LS ? 2 : 17>(buf, nb, W, total);
     return true;
 }
 
@@ -243,7 +223,7 @@ struct CoopArgs {
     double* p;          // out: last direction (workgroup 0)
     double* grad;       // out: last grad_y (workgroup 0)
     MasterState* ms;    // in: state set by k_master_init_ap; out: final state (workgroup 0)
-    double* recs;       // [REC_BUFS][gridDim.x][RECW], every field empty (all ones) at launch
+    double* recs;       // [2][gridDim.x][RECW]
     CoopSync* sync;
     ProfCounters* pc;
     int timing;         // workgroup 0 accumulates per-phase wall-clock ticks in pc->ticks
@@ -429,7 +409,7 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
                 A.pc->real[0] += 1;
             }
             tick(0);
-            if (!grid_reduce<false, 32>(A.sync, A.recs, s_rec, K + 1, s_tot, seq, max(K + 1, 6))) {
+            if (!grid_reduce<false>(A.sync, A.recs, s_rec, K + 1, s_tot, seq)) {
                 alive = false;
                 break;
             }
@@ -568,7 +548,7 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
                 A.pc->real[kk] += 1;
             }
             tick(first ? 3 : 6);
-            if (!grid_reduce<true, 8>(A.sync, A.recs, s_rec, 6, s_tot, seq, max(K + 1, 6))) {
+            if (!grid_reduce<true>(A.sync, A.recs, s_rec, 6, s_tot, seq)) {
                 alive = false;
                 break;
             }
