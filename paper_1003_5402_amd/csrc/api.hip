@@ -322,10 +322,10 @@ dao_status run_master_coop(dao_ctx* c, double tol, int max_steps) {
     const size_t lds = coop_lds_bytes<T>(rows, nc);
     if (c->opt.persistent == 2 && c->coop_lds_max > 0 && lds <= size_t(c->coop_lds_max))
         HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T, true>),
-                                             dim3(c->coop_grid), dim3(BLOCK), args, lds, c->stream));
+                                             dim3(c->coop_grid), dim3(COOP_THREADS), args, lds, c->stream));
     else
         HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T, false>),
-                                             dim3(c->coop_grid), dim3(BLOCK), args, 0, c->stream));
+                                             dim3(c->coop_grid), dim3(COOP_THREADS), args, 0, c->stream));
     if (prof) {
         dao_status s = prof_mark(c, 4, false);
         if (s != DAO_OK) return s;
@@ -518,7 +518,7 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
         HIPCHK(c, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
         HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
         HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                      &occ, reinterpret_cast<const void*>(&k_master_coop<T, false>), BLOCK, 0));
+                      &occ, reinterpret_cast<const void*>(&k_master_coop<T, false>), COOP_THREADS, 0));
         if (coop && occ > 0 && ncu > 0) {
             c->coop_grid = std::min(ncu, MAX_COOP_GRID);   // one co-resident workgroup per compute unit
             // on-chip variant: as much dynamic LDS as the device grants one
@@ -531,7 +531,8 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
                                     hipFuncAttributeMaxDynamicSharedMemorySize, want) == hipSuccess) {
                 int occ2 = 0;
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                        &occ2, reinterpret_cast<const void*>(&k_master_coop<T, true>), BLOCK, want) == hipSuccess &&
+                        &occ2, reinterpret_cast<const void*>(&k_master_coop<T, true>), COOP_THREADS, want) ==
+                        hipSuccess &&
                     occ2 >= 1)
                     c->coop_lds_max = want;
             }

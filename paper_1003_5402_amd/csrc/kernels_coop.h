@@ -30,6 +30,7 @@
 
 namespace dao {
 
+constexpr int COOP_THREADS = 512;          // threads per workgroup: 8 wavefronts, 2 per SIMD
 constexpr int RECW = KS + 8;               // doubles per reduction record
 constexpr int MAX_COOP_GRID = 1024;        // workgroups of one persistent launch
 constexpr long SPIN_LIMIT = 4000000L;      // ~1 s of waiting before the grid aborts
@@ -105,7 +106,7 @@ __device__ __forceinline__ double field_reduce_dpp(bool ls, int f, double v) {
 // Line-search record of a workgroup (fields as Rec: s0, s1, s2, mn, mx, s5)
 // into out[0..6) (LDS), waves combined in order.  All threads call it.
 __device__ __forceinline__ void block_rec_dpp(const Rec& r, double* out) {
-    __shared__ double s_w[BLOCK / WAVE][6];
+    __shared__ double s_w[1024 / WAVE][6];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const double v0 = wave_reduce_dpp<0>(r.s0), v1 = wave_reduce_dpp<0>(r.s1), v2 = wave_reduce_dpp<0>(r.s2);
     const double v3 = wave_reduce_dpp<1>(r.mn), v4 = wave_reduce_dpp<2>(r.mx), v5 = wave_reduce_dpp<0>(r.s5);
@@ -206,7 +207,8 @@ __device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W
     }
     __syncthreads();
     if (!s_ok) return false;
-    combine_fields<LS, LS ? 2 : 17>(buf, nb, W, total);
+    combine_fields<LS, LS ? (6 + COOP_THREADS / WAVE - 1) / (COOP_THREADS / WAVE)
+                             : (KS + 1 + COOP_THREADS / WAVE - 1) / (COOP_THREADS / WAVE)>(buf, nb, W, total);
     return true;
 }
 
@@ -248,11 +250,11 @@ __host__ __device__ inline size_t coop_lds_bytes(int64_t rows, int nc) {
 // LDS once per solve and every pass reads on-chip memory; d is written back
 // at the end.  Otherwise the passes stream them from global memory.
 template <class T, bool LDSRES>
-__global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
+__global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
     using G = DKG<T>;
     using V = typename Vec16<T>::type;
     constexpr int IT = Batch<T>::ITERS, ROWS = Batch<T>::ROWS;
-    constexpr int NW = BLOCK / WAVE;
+    constexpr int NW = COOP_THREADS / WAVE;
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ MasterState s_ms;
     __shared__ ObjClass cl[256];
@@ -343,10 +345,23 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
             for (int64_t bt = bat0 + wave; bt < bat1; bt += NW) {
                 const int64_t base = bt * ROWS;
                 V v[IT];
+                if (LDSRES) {
+                    // running LDS offset, opaque to the compiler so it adds one
+                    // stride per load instead of keeping IT addresses live
+                    uint32_t off = uint32_t(((base - r0 + rg) * nc + c) * 16);
+                    const uint32_t stride = uint32_t(G::RPW * nc * 16);
 #pragma unroll
-                for (int it = 0; it < IT; ++it) {
-                    v[it] = vzero<V>();
-                    if (c < nc) v[it] = dk_vec(base + it * G::RPW + rg);
+                    for (int it = 0; it < IT; ++it) {
+                        asm volatile("" : "+v"(off));
+                        v[it] = c < nc ? *reinterpret_cast<const V*>(dyn + off) : vzero<V>();
+                        off += stride;
+                    }
+                } else {
+#pragma unroll
+                    for (int it = 0; it < IT; ++it) {
+                        v[it] = vzero<V>();
+                        if (c < nc) v[it] = dk_vec(base + it * G::RPW + rg);
+                    }
                 }
                 if (mode == 1) {
 #pragma unroll
@@ -474,25 +489,30 @@ __global__ void __launch_bounds__(BLOCK) k_master_coop(CoopArgs<T> A) {
                 // are combined in the order of the lane butterfly of the
                 // streaming form below, so q is the same up to the sign of an
                 // exact zero
-                for (int64_t rr = threadIdx.x; rr < nrows; rr += BLOCK) {
+                for (int64_t rr = threadIdx.x; rr < nrows; rr += blockDim.x) {
                     const ObjClass cc = cl[cll[rr]];
                     const double dv = dl[rr];
                     T qt;
                     if (first) {
                         const V* rp = dkl + rr * nc;
-                        double pc[G::LPR];
-#pragma unroll
-                        for (int j = 0; j < G::LPR; ++j) {
-                            double part = 0.0;   // slots past the pool add exact zeros
+                        // partial of slot vector j (slots past the pool add exact zeros)
+                        auto part_of = [&](int j) {
+                            double part = 0.0;
                             if (j < nc) {
                                 const V v = rp[j];
 #pragma unroll
                                 for (int e = 0; e < G::EPL; ++e) part += vget(v, e) * s_p[j * G::EPL + e];
                             }
-                            pc[j] = part;
-                        }
+                            return part;
+                        };
+                        // first butterfly level pairs j with j + LPR/2; only the
+                        // LPR/2 pair sums stay live
+                        constexpr int H = G::LPR / 2;
+                        double pc[H];
 #pragma unroll
-                        for (int off = G::LPR / 2; off > 0; off >>= 1)
+                        for (int j = 0; j < H; ++j) pc[j] = part_of(j) + part_of(j + H);
+#pragma unroll
+                        for (int off = H / 2; off > 0; off >>= 1)
 #pragma unroll
                             for (int j = 0; j < off; ++j) pc[j] = pc[j] + pc[j + off];
                         qt = T(pc[0]);   // the line search and the update use the stored value
