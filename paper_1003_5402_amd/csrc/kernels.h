@@ -703,10 +703,11 @@ __global__ void __launch_bounds__(1024) k_dir(PoolView P, const T* __restrict__ 
     ms_store(ms, s_ms);
 }
 
-// Line-search decision after an evaluation at m.t (thread 0 of the last
-// block, on the LDS copy of the state).  Returns 1 when the step is final
-// (m.t holds it), 0 when m.t holds the next trial point.
-__device__ __forceinline__ int ls_decide(MasterState& m, const Rec& e) {
+// Line-search decision after an evaluation at m.t (on the MasterState or on
+// any state with the same line-search fields).  Returns 1 when the step is
+// final (m.t holds it), 0 when m.t holds the next trial point.
+template <class S>
+__device__ __forceinline__ int ls_decide(S& m, const Rec& e) {
     const double t = m.t, tmax = m.t_max;
     const double gphi = e.s0, s_r = 2.0 * e.s1, s_l = 2.0 * e.s2, nb = e.mn, pb = e.mx;
     m.ls_iter += 1;

@@ -212,6 +212,14 @@ __device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W
     return true;
 }
 
+// Line-search state kept in registers by every thread (the fields
+// ls_decide uses).
+struct LsRegs {
+    double t, t_max, lo, hi;
+    int hi_known, ls_iter;
+    int64_t total_ls;
+};
+
 template <class T>
 struct CoopArgs {
     const T* dk;
@@ -263,7 +271,7 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
     __shared__ double s_acc[NW][KS];
     __shared__ double s_wr[NW][8];
     __shared__ double s_u[NW][ROWS];
-    __shared__ int s_go, s_fin;
+    __shared__ int s_go;
 
     ms_load(s_ms, A.ms);
     for (int i = threadIdx.x; i < A.ncls; i += blockDim.x) cl[i] = A.classes[i];
@@ -311,6 +319,11 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
     auto cls_at = [&](int64_t row) -> uint8_t { return LDSRES ? cll[row - r0] : A.cls[row]; };
     bool alive = true;
     int mode = s_ms.refresh;   // first update keeps d (2) unless told otherwise
+    // every thread takes the same line-search decisions and step counts from
+    // the same totals, in registers; thread 0 mirrors them into s_ms
+    LsRegs ls{0.0, 0.0, 0.0, 0.0, 0, 0, s_ms.total_ls};
+    int steps = s_ms.steps;
+    const int refresh_every = s_ms.refresh_every;
     // phase timing (workgroup 0, thread 0): 0 update pass, 1 its reduction,
     // 2 direction, 3 first line-search pass (q), 4 line-search reductions,
     // 5 final decision + step, 6 later line-search passes (with the decision
@@ -332,7 +345,7 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
     while (alive) {
         // ---------------- update pass: apply the step, dF/dz, F, grad_y partials
         {
-            const double t = s_ms.t;
+            const double t = ls.t;
             double yv[G::EPL], acc[G::EPL];
 #pragma unroll
             for (int e = 0; e < G::EPL; ++e) {
@@ -451,7 +464,7 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
                 if (!(kkt > s_ms.tol)) {
                     s_ms.stop_reason = 1;
                     go = 0;
-                } else if (s_ms.steps >= s_ms.max_steps) {
+                } else if (steps >= s_ms.max_steps) {
                     s_ms.stop_reason = 2;
                     go = 0;
                 } else if (!any) {
@@ -475,10 +488,16 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
         __syncthreads();
         tick(2);
         if (!s_go) break;
+        ls.t = 0.0;
+        ls.t_max = s_ms.t_max;
+        ls.lo = 0.0;
+        ls.hi = ls.t_max;
+        ls.hi_known = 0;
+        ls.ls_iter = 0;
         // ---------------- line search: first evaluation computes q = D_K p
         bool first = true;
         for (;;) {
-            const double t = s_ms.t;
+            const double t = ls.t;
             Rec r = rec_identity();
             double pv[G::EPL];
 #pragma unroll
@@ -573,18 +592,15 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
                 break;
             }
             tick(4);
-            if (threadIdx.x == 0) {
-                const Rec tot{s_tot[0], s_tot[1], s_tot[2], s_tot[3], s_tot[4], s_tot[5]};
-                s_fin = ls_decide(s_ms, tot);
-            }
-            __syncthreads();
+            const Rec tot{s_tot[0], s_tot[1], s_tot[2], s_tot[3], s_tot[4], s_tot[5]};
+            const int fin = ls_decide(ls, tot);
             first = false;
-            if (s_fin) break;
+            if (fin) break;
         }
         if (!alive) break;
         // ---------------- step: y update, counters, next update mode
         {
-            const double t = s_ms.t, tmax = s_ms.t_max;
+            const double t = ls.t, tmax = ls.t_max;
             if (threadIdx.x < K) {
                 const int k = threadIdx.x;
                 const double pk = s_p[k];
@@ -593,15 +609,22 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
                 if (t == tmax && ratio == t) yn = 0.0;
                 s_y[k] = fmax(yn, 0.0);
             }
-            __syncthreads();
+            steps += 1;
+            mode = (steps % refresh_every) == 0 ? 1 : 0;
             if (threadIdx.x == 0) {
-                s_ms.steps += 1;
+                s_ms.steps = steps;
                 s_ms.total_steps += 1;
                 s_ms.last_step = t;
-                s_ms.refresh = (s_ms.steps % s_ms.refresh_every) == 0 ? 1 : 0;
+                s_ms.refresh = mode;
+                s_ms.t = t;
+                s_ms.t_max = tmax;
+                s_ms.lo = ls.lo;
+                s_ms.hi = ls.hi;
+                s_ms.hi_known = ls.hi_known;
+                s_ms.ls_iter = ls.ls_iter;
+                s_ms.total_ls = ls.total_ls;
             }
-            __syncthreads();
-            mode = s_ms.refresh;
+            __syncthreads();   // y visible to the next update pass
             tick(5);
         }
     }
