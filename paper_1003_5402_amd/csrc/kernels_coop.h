@@ -319,6 +319,14 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
     auto cls_at = [&](int64_t row) -> uint8_t { return LDSRES ? cll[row - r0] : A.cls[row]; };
     bool alive = true;
     int mode = s_ms.refresh;   // first update keeps d (2) unless told otherwise
+    // work counters of workgroup 0 (update, q and line-search passes), kept in
+    // LDS and added to the device counters once at the end
+    __shared__ double cnt_bytes[3];
+    __shared__ uint64_t cnt_real[3];
+    if (threadIdx.x < 3) {
+        cnt_bytes[threadIdx.x] = 0.0;
+        cnt_real[threadIdx.x] = 0;
+    }
     // every thread takes the same line-search decisions and step counts from
     // the same totals, in registers; thread 0 mirrors them into s_ms
     LsRegs ls{0.0, 0.0, 0.0, 0.0, 0, 0, s_ms.total_ls};
@@ -433,8 +441,8 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 const double per_row = 16.0 * nc + 1.0 + (mode != 1 ? 8.0 : 0.0) +
                                        (mode == 0 ? double(sizeof(T)) : 0.0) + (mode != 2 ? 8.0 : 0.0);
-                A.pc->bytes[0] += per_row * double(A.Vnz);
-                A.pc->real[0] += 1;
+                cnt_bytes[0] += per_row * double(A.Vnz);
+                cnt_real[0] += 1;
             }
             tick(0);
             if (!grid_reduce<false>(A.sync, A.recs, s_rec, K + 1, s_tot, seq)) {
@@ -582,9 +590,9 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
             block_rec_dpp(r, s_rec);
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 const int kk = first ? 1 : 2;
-                A.pc->bytes[kk] += (first ? (16.0 * nc + 8.0 + 1.0 + double(sizeof(T)))
+                cnt_bytes[kk] += (first ? (16.0 * nc + 8.0 + 1.0 + double(sizeof(T)))
                                           : (8.0 + double(sizeof(T)) + 1.0)) * double(A.Vnz);
-                A.pc->real[kk] += 1;
+                cnt_real[kk] += 1;
             }
             tick(first ? 3 : 6);
             if (!grid_reduce<true>(A.sync, A.recs, s_rec, 6, s_tot, seq)) {
@@ -634,6 +642,11 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
     }
     if (timer)
         for (int i = 0; i < PROF_PHASES; ++i) A.pc->ticks[i] += s_tk[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (int i = 0; i < 3; ++i) {
+            A.pc->bytes[i] += cnt_bytes[i];
+            A.pc->real[i] += cnt_real[i];
+        }
     // workgroup 0 publishes the final state
     if (blockIdx.x == 0) {
         if (threadIdx.x < K) {
