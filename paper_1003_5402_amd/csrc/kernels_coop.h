@@ -103,8 +103,32 @@ __device__ __forceinline__ double field_reduce_dpp(bool ls, int f, double v) {
     return wave_reduce_dpp<0>(v);
 }
 
+// Fixed-order combine of the 8 wavefronts' partials part[w * stride + f]
+// (f < nf) into out[f] (LDS): lane group f of 8 lanes holds the 8 partials
+// of field f and combines them by three DPP moves inside the group (quad
+// swaps, then half-row mirror).  With ls, fields 3 and 4 are a minimum and
+// a maximum, the others sums.  Needs 8 wavefronts; all threads call it.
+__device__ __forceinline__ void combine_waves8(const double* part, int stride, int nf, bool ls, double* out) {
+    const int t = threadIdx.x, wave = t / WAVE;
+    if (wave < (nf * 8 + WAVE - 1) / WAVE) {   // whole wavefronts take part in the moves
+        const int f = t / 8, w = t % 8;
+        const int op = (ls && f == 3) ? 1 : (ls && f == 4) ? 2 : 0;
+        const double id = op == 0 ? 0.0 : op == 1 ? INFINITY : -INFINITY;
+        double x = f < nf ? part[w * stride + f] : id;
+        double m = dpp_move<0xB1, 0xF>(x, id);    // quad_perm [1,0,3,2]
+        x = op == 0 ? x + m : op == 1 ? fmin(x, m) : fmax(x, m);
+        m = dpp_move<0x4E, 0xF>(x, id);           // quad_perm [2,3,0,1]
+        x = op == 0 ? x + m : op == 1 ? fmin(x, m) : fmax(x, m);
+        m = dpp_move<0x141, 0xF>(x, id);          // row_half_mirror
+        x = op == 0 ? x + m : op == 1 ? fmin(x, m) : fmax(x, m);
+        if (w == 0 && f < nf) out[f] = x;
+    }
+    __syncthreads();
+}
+
 // Line-search record of a workgroup (fields as Rec: s0, s1, s2, mn, mx, s5)
-// into out[0..6) (LDS), waves combined in order.  All threads call it.
+// into out[0..6) (LDS), waves combined in a fixed order.  Needs 8
+// wavefronts; all threads call it.
 __device__ __forceinline__ void block_rec_dpp(const Rec& r, double* out) {
     __shared__ double s_w[1024 / WAVE][6];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
@@ -119,14 +143,7 @@ __device__ __forceinline__ void block_rec_dpp(const Rec& r, double* out) {
         s_w[wave][5] = v5;
     }
     __syncthreads();
-    if (threadIdx.x < 6) {
-        const int f = threadIdx.x;
-        double acc = s_w[0][f];
-        for (int w = 1; w < int(blockDim.x) / WAVE; ++w)
-            acc = f == 3 ? fmin(acc, s_w[w][f]) : f == 4 ? fmax(acc, s_w[w][f]) : acc + s_w[w][f];
-        out[f] = acc;
-    }
-    __syncthreads();
+    combine_waves8(&s_w[0][0], 6, 6, true, out);
 }
 
 // Fixed-order combine of nb records of W doubles stored field-major (field i
@@ -268,8 +285,8 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
     __shared__ ObjClass cl[256];
     __shared__ double s_y[KS], s_p[KS], s_g[KS];
     __shared__ double s_rec[RECW], s_tot[RECW];
-    __shared__ double s_acc[NW][KS];
-    __shared__ double s_wr[NW][8];
+    static_assert(NW == 8, "the wavefront combines assume 8 wavefronts");
+    __shared__ double s_acc[NW][RECW];   // per wavefront: objective, then grad_y
     __shared__ double s_u[NW][ROWS];
     __shared__ int s_go;
 
@@ -424,20 +441,11 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
                 for (int e = 0; e < G::EPL; ++e) acc[e] += __shfl_xor(acc[e], off, WAVE);
             if (rg == 0)
 #pragma unroll
-                for (int e = 0; e < G::EPL; ++e) s_acc[wave][c * G::EPL + e] = acc[e];
+                for (int e = 0; e < G::EPL; ++e) s_acc[wave][1 + c * G::EPL + e] = acc[e];
             Fp = wave_reduce_dpp<0>(Fp);
-            if (lane == 0) s_wr[wave][0] = Fp;
+            if (lane == 0) s_acc[wave][0] = Fp;
             __syncthreads();
-            if (threadIdx.x < K) {
-                double sacc = 0.0;
-                for (int w = 0; w < NW; ++w) sacc += s_acc[w][threadIdx.x];
-                s_rec[1 + threadIdx.x] = sacc;
-            } else if (threadIdx.x == KS) {
-                double sacc = 0.0;
-                for (int w = 0; w < NW; ++w) sacc += s_wr[w][0];
-                s_rec[0] = sacc;
-            }
-            __syncthreads();
+            combine_waves8(&s_acc[0][0], RECW, K + 1, false, s_rec);
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 const double per_row = 16.0 * nc + 1.0 + (mode != 1 ? 8.0 : 0.0) +
                                        (mode == 0 ? double(sizeof(T)) : 0.0) + (mode != 2 ? 8.0 : 0.0);
