@@ -467,9 +467,9 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
             const double gk = in ? s_tot[1 + k] : 0.0;
             double pk = -gk;
             if (!in || (yk == 0.0 && gk >= 0.0)) pk = 0.0;
-            const double kkt = wave_max(in ? fabs(fmin(yk, gk)) : 0.0);
-            const double tmax = wave_min(pk < 0.0 ? yk / (-pk) : INFINITY);
-            const double gp = wave_sum(gk * pk);
+            const double kkt = wave_reduce_dpp<2>(in ? fabs(fmin(yk, gk)) : 0.0);
+            const double tmax = wave_reduce_dpp<1>(pk < 0.0 ? yk / (-pk) : INFINITY);
+            const double gp = wave_reduce_dpp<0>(gk * pk);
             const bool any = __any(pk != 0.0);
             s_p[k] = pk;
             s_g[k] = gk;
