@@ -199,42 +199,28 @@ __device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W
     const uint32_t nb = gridDim.x, b = blockIdx.x;
     seq += 1;
     double* buf = recs + size_t(seq & 1u) * nb * RECW;
-    if (threadIdx.x < WAVE) {
-        // wavefront 0 publishes the record, waits for its own stores and
-        // raises the flag (no workgroup barrier needed in between) ...
-        for (int i = threadIdx.x; i < W; i += WAVE) astore(&buf[size_t(i) * nb + b], mine[i]);
-        __builtin_amdgcn_s_waitcnt(0);
-        if (threadIdx.x == 0)
-            __hip_atomic_store(&S->flag[b * SLOT_STRIDE], seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // ... then waits for every workgroup's flag, all of its lane's flags
-        // loaded together on each round
-        int ok = 1;
-        for (long spins = 0;; ++spins) {
-            int waiting = 0;
-            for (uint32_t w0 = threadIdx.x; w0 < nb; w0 += 4 * WAVE) {
-                uint32_t fl[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t w = w0 + uint32_t(j * WAVE);
-                    fl[j] = w < nb ? aload_u(&S->flag[w * SLOT_STRIDE]) : seq;
-                }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) waiting += fl[j] < seq;
-            }
-            if (!waiting) break;
+    for (int i = threadIdx.x; i < W; i += blockDim.x) astore(&buf[size_t(i) * nb + b], mine[i]);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&S->flag[b * SLOT_STRIDE], seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_ok = 1;
+    }
+    __syncthreads();
+    for (uint32_t w = threadIdx.x; w < nb; w += blockDim.x) {
+        long spins = 0;
+        while (aload_u(&S->flag[w * SLOT_STRIDE]) < seq) {
             __builtin_amdgcn_s_sleep(1);
             if (aload_u(&S->abort_flag[0])) {
-                ok = 0;
+                s_ok = 0;
                 break;
             }
-            if (spins > SPIN_LIMIT) {
+            if (++spins > SPIN_LIMIT) {
                 __hip_atomic_store(&S->abort_flag[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
+                s_ok = 0;
                 break;
             }
         }
-        const int bad = __any(!ok);
-        if (threadIdx.x == 0) s_ok = !bad;
     }
     __syncthreads();
     if (!s_ok) return false;
