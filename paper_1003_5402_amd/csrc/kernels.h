@@ -228,14 +228,14 @@ struct SellView {
 };
 
 // Lane `lane` of a wavefront: entries k0..k1-1 of its row in the slice that
-// starts at entry `base`, visited in stored (ascending beamlet) order and
-// added to acc.
+// starts at entry `base`, visited in stored (ascending beamlet) order.
 template <class T, class XT, class Acc>
 __device__ __forceinline__ Acc sell_dot(const T* __restrict__ val, const uint16_t* __restrict__ col,
                                         uint32_t base, int k0, int k1, int lane,
-                                        const XT* __restrict__ xs, Acc acc = Acc(0)) {
+                                        const XT* __restrict__ xs) {
     const T* v = val + base + uint32_t(k0) * SLICE + lane;
     const uint16_t* c = col + base + uint32_t(k0) * SLICE + lane;
+    Acc acc = Acc(0);
     int k = k0;
     for (; k + 4 <= k1; k += 4) {
         const T v0 = v[0], v1 = v[SLICE], v2 = v[2 * SLICE], v3 = v[3 * SLICE];
@@ -255,54 +255,22 @@ __device__ __forceinline__ Acc sell_dot(const T* __restrict__ val, const uint16_
     return acc;
 }
 
-// Stage an n-vector into LDS (or return the global pointer when not staged).
-template <class XT, class ST>
-__device__ __forceinline__ const XT* stage_vec(const ST* __restrict__ src, int n, XT* lds, bool stage) {
-    if (!stage) return reinterpret_cast<const XT*>(src);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = XT(src[i]);
-    __syncthreads();
-    return lds;
-}
-
-// Row sums of this workgroup's slab (SLAB_THREADS threads) for x = src
-// (staged into LDS when `stage`).  Wavefront w takes slice w / KSPLIT of the
-// slab and the (w % KSPLIT)-th quarter of its entries; each lane first issues
-// the loads of up to PF of its entries, so they are in flight while x is
-// staged, then adds the products in stored order; partials meet in s_part
-// and are added in k order.  Returns the row sum in threads t < SLAB (row
-// blockIdx.x * SLAB + t).
-template <class T, class XT, class Acc, class ST>
-__device__ __forceinline__ Acc slab_product(const SellView<T>& S, const ST* __restrict__ src, int N, XT* lds,
-                                            bool stage, Acc* s_part) {
-    constexpr int PF = 16;
+// Row sums of this workgroup's slab (SLAB_THREADS threads).  Wavefront w
+// takes slice w / KSPLIT of the slab and the (w % KSPLIT)-th quarter of its
+// entries; partials meet in s_part and are added in k order.  Returns the
+// row sum in threads t < SLAB (row blockIdx.x * SLAB + t).
+template <class T, class XT, class Acc>
+__device__ __forceinline__ Acc slab_rows(const SellView<T>& S, const XT* __restrict__ xs, Acc* s_part) {
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int j = wave / KSPLIT, kp = wave % KSPLIT;
     const int64_t s = int64_t(blockIdx.x) * SPB + j;
-    int k0 = 0, k1 = 0;
-    uint32_t base = 0;
+    Acc acc = Acc(0);
     if (s < S.nslices) {
         const int w = S.slice_w[s];
         const int kc = (w + KSPLIT - 1) / KSPLIT;
-        k0 = min(w, kp * kc);
-        k1 = min(w, k0 + kc);
-        base = S.slice_ptr[s];
+        const int k0 = min(w, kp * kc), k1 = min(w, k0 + kc);
+        acc = sell_dot<T, XT, Acc>(S.val, S.col, S.slice_ptr[s], k0, k1, lane, xs);
     }
-    const T* vp = S.val + base + uint32_t(k0) * SLICE + lane;
-    const uint16_t* cp = S.col + base + uint32_t(k0) * SLICE + lane;
-    T v[PF];
-    uint16_t c[PF];
-#pragma unroll
-    for (int u = 0; u < PF; ++u) {
-        const bool in = k0 + u < k1;
-        v[u] = in ? vp[u * SLICE] : T(0);
-        c[u] = in ? cp[u * SLICE] : uint16_t(0);
-    }
-    const XT* xs = stage_vec<XT, ST>(src, N, lds, stage);
-    Acc acc = Acc(0);
-#pragma unroll
-    for (int u = 0; u < PF; ++u)
-        if (k0 + u < k1) acc += Acc(v[u]) * Acc(xs[c[u]]);
-    if (k1 - k0 > PF) acc = sell_dot<T, XT, Acc>(S.val, S.col, base, k0 + PF, k1, lane, xs, acc);
     s_part[kp * SLAB + j * SLICE + lane] = acc;
     __syncthreads();
     Acc sum = Acc(0);
@@ -311,6 +279,15 @@ __device__ __forceinline__ Acc slab_product(const SellView<T>& S, const ST* __re
         for (int q = 0; q < KSPLIT; ++q) sum += s_part[q * SLAB + threadIdx.x];
     }
     return sum;
+}
+
+// Stage an n-vector into LDS (or return the global pointer when not staged).
+template <class XT, class ST>
+__device__ __forceinline__ const XT* stage_vec(const ST* __restrict__ src, int n, XT* lds, bool stage) {
+    if (!stage) return reinterpret_cast<const XT*>(src);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = XT(src[i]);
+    __syncthreads();
+    return lds;
 }
 
 // ---------------------------------------------------------------------------
@@ -324,7 +301,8 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_dose(SellView<T> S, const int3
                                                        bool stage, T* __restrict__ d_ext) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ T s_part[KSPLIT * SLAB];
-    const T sum = slab_product<T, T, T, T>(S, x, N, reinterpret_cast<T*>(smem), stage, s_part);
+    const T* xs = stage_vec<T, T>(x, N, reinterpret_cast<T*>(smem), stage);
+    const T sum = slab_rows<T, T, T>(S, xs, s_part);
     const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
     if (threadIdx.x < SLAB && row < Vpad) {
         const int32_t j = perm[row];
@@ -416,25 +394,16 @@ __global__ void __launch_bounds__(BLOCK) k_gradT(const int32_t* __restrict__ cpt
     const int i = blockIdx.x;
     const int e0 = cptr[i], e1 = cptr[i + 1];
     Acc acc = Acc(0);
-    // PF entries per thread in flight: their row numbers and values, then the
-    // PF gathers of u, then the products in entry order
-    constexpr int PF = 16;
-    for (int e = e0 + threadIdx.x; e < e1; e += PF * BLOCK) {
-        int32_t r[PF];
-        T v[PF];
-#pragma unroll
-        for (int q = 0; q < PF; ++q) {
-            const bool in = e + q * BLOCK < e1;
-            r[q] = in ? crow[e + q * BLOCK] : 0;
-            v[q] = in ? cval[e + q * BLOCK] : T(0);
-        }
-        UT g[PF];
-#pragma unroll
-        for (int q = 0; q < PF; ++q) g[q] = e + q * BLOCK < e1 ? u[r[q]] : UT(0);
-#pragma unroll
-        for (int q = 0; q < PF; ++q)
-            if (e + q * BLOCK < e1) acc += Acc(v[q]) * Acc(g[q]);
+    int e = e0 + threadIdx.x;
+    for (; e + 3 * BLOCK < e1; e += 4 * BLOCK) {
+        const int32_t r0 = crow[e], r1 = crow[e + BLOCK], r2 = crow[e + 2 * BLOCK], r3 = crow[e + 3 * BLOCK];
+        const T v0 = cval[e], v1 = cval[e + BLOCK], v2 = cval[e + 2 * BLOCK], v3 = cval[e + 3 * BLOCK];
+        acc += Acc(v0) * Acc(u[r0]);
+        acc += Acc(v1) * Acc(u[r1]);
+        acc += Acc(v2) * Acc(u[r2]);
+        acc += Acc(v3) * Acc(u[r3]);
     }
+    for (; e < e1; e += BLOCK) acc += Acc(cval[e]) * Acc(u[crow[e]]);
     acc = wave_sum(acc);
     __shared__ Acc s_w[BLOCK / WAVE];
     if ((threadIdx.x % WAVE) == 0) s_w[threadIdx.x / WAVE] = acc;
@@ -847,7 +816,8 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_qstep(SellView<T> S, int64_t V
     for (int i = threadIdx.x; i < ncls; i += blockDim.x) cl[i] = classes[i];
     T* xs_l = reinterpret_cast<T*>(smem + sizeof(ObjClass) * ncls);
     __syncthreads();
-    const T sum = slab_product<T, T, T, T>(S, dx, N, xs_l, stage, s_part);
+    const T* xs = stage_vec<T, T>(dx, N, xs_l, stage);
+    const T sum = slab_rows<T, T, T>(S, xs, s_part);
     Rec r = rec_identity();
     const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
     if (threadIdx.x < SLAB && row < Vpad) {
@@ -936,7 +906,8 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_update(SellView<T> S, int64_t 
     __syncthreads();
     double dn = 0.0;
     if (s_refresh) {
-        dn = slab_product<T, double, double, double>(S, x64, N, xs_l, stage, s_part);
+        const double* xs = stage_vec<double, double>(x64, N, xs_l, stage);
+        dn = slab_rows<T, double, double>(S, xs, s_part);
     }
     Rec r = rec_identity();
     const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;

@@ -102,7 +102,8 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_dk_column(SellView<T> S, int64
                                                             int k, T* __restrict__ dk) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double s_part[KSPLIT * SLAB];
-    const double sum = slab_product<T, T, double, T>(S, ind, N, reinterpret_cast<T*>(smem), stage, s_part);
+    const T* xs = stage_vec<T, T>(ind, N, reinterpret_cast<T*>(smem), stage);
+    const double sum = slab_rows<T, T, double>(S, xs, s_part);
     const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
     if (threadIdx.x < SLAB && row < Vpad) dk[row * KS + k] = T(sum);
 }
