@@ -225,6 +225,37 @@ def main():
     log(f"[bench] cold D x: {us_dose_c:.2f} us {gbs_dose_c:.0f} GB/s; "
         f"cold D^T u: {us_grad_c:.2f} us {gbs_grad_c:.0f} GB/s")
 
+    # 16-bit storage of D (FP16 / BF16 value per beamlet scale, optional FP16
+    # residual): product throughput and one plan each, on the same phantom
+    reduced = {}
+    scrub = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    for fname, fmt in (("f16", dao.DAO_DFMT_F16), ("bf16", dao.DAO_DFMT_BF16)):
+        for res in (0, 1):
+            rc = dao.DaoContext.from_phantom(ph, dtype="f32", stream=stream, d_format=fmt, d_residual=res)
+            ri = rc.info()
+            ud, ug = rc.time_product(0, args.product_iters), rc.time_product(1, args.product_iters)
+            udc, ugc = rc.time_product_cold(0, cold_iters, scrub), rc.time_product_cold(1, cold_iters, scrub)
+            rc.solve(n_ap)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ro = rc.solve(n_ap)
+            torch.cuda.synchronize()
+            pt = time.perf_counter() - t0
+            key = f"{fname}{'+lo' if res else ''}"
+            reduced[key] = {
+                "dose_us": ud, "dose_bytes": ri["bytes_dose"], "dose_GBs": ri["bytes_dose"] / (ud * 1e-6) / 1e9,
+                "gradient_us": ug, "gradient_bytes": ri["bytes_gradient"],
+                "gradient_GBs": ri["bytes_gradient"] / (ug * 1e-6) / 1e9,
+                "dose_cold_us": udc, "gradient_cold_us": ugc,
+                "dose_speedup_vs_f32": us_dose / ud, "gradient_speedup_vs_f32": us_grad / ug,
+                "plan_s": pt, "plan_F": ro["F"], "plan_F_rel_vs_f32": (ro["F"] - outs[-1]["F"]) / outs[-1]["F"],
+                "device_bytes": ri["device_bytes"],
+            }
+            log(f"[bench] D {key}: D x {ud:.2f} us ({reduced[key]['dose_GBs']:.0f} GB/s), D^T u {ug:.2f} us "
+                f"({reduced[key]['gradient_GBs']:.0f} GB/s), plan {pt:.4f} s F {ro['F']:.8e}")
+            rc.close()
+    del scrub
+
     steps_per_plan = int(outs[-1]["total_steps"])
     result = {
         "metric": METRIC,
@@ -265,6 +296,7 @@ def main():
                      "last-level cache) and cold (1 GiB scrub write before each timed launch)"),
         },
         "master_kernels": kernels,
+        "d_16bit": reduced,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk_["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dk_["GBs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": dk_["total_bytes"] / max(1, dk_["launches"]),

@@ -107,6 +107,11 @@ typedef struct {
     int32_t ls_slots;       /* line-search launches per master cycle (2) */
     int64_t mem_cap_bytes;  /* fail dao_create with DAO_ENOMEM above this device footprint; 0 = none */
     int32_t master;         /* DAO_MASTER_APERTURE (default) or DAO_MASTER_BEAMLET, see below */
+    int32_t d_format;       /* storage of D's values: DAO_DFMT_NATIVE (default: the ctx
+                               dtype) or, for DAO_F32 with the aperture master,
+                               DAO_DFMT_F16 / DAO_DFMT_BF16, see below */
+    int32_t d_residual;     /* with a 16-bit d_format: 1 also stores the FP16 residual and
+                               uses it in every product; 0 (default) the 16-bit values only */
     int32_t persistent;     /* aperture master: 2 (default) runs each master solve as one
                                cooperative launch when the device supports it, each
                                workgroup holding its rows of D_K, d and q in LDS when they
@@ -123,6 +128,22 @@ typedef struct {
  * DAO_MASTER_BEAMLET evaluates the same products through the beamlet
  * matrix and the pool map: q = D (A p), dF/dy = A^T (D^T grad F) (eq. 7). */
 enum { DAO_MASTER_APERTURE = 0, DAO_MASTER_BEAMLET = 1 };
+
+/* Reduced-precision storage of D (products accumulate in FP32; the
+ * objective total, line search, convergence and reduced-cost tests stay
+ * FP64).  Each beamlet column i gets an FP32 scale s_i = max_j D_ij (1 for
+ * an empty column); each entry stores hi = RNE(D_ij / s_i) in FP16 or BF16
+ * and, with d_residual, lo = RNE_FP16(D_ij / s_i - hi), so that
+ * D_ij ~= s_i (hi + lo).  The scale is applied to x before the forward
+ * product and to each column sum of the transposed product.  Needs
+ * n_blt * 4 bytes of x to fit the on-chip staging (n_blt <= 12288). */
+enum { DAO_DFMT_NATIVE = 0, DAO_DFMT_F16 = 1, DAO_DFMT_BF16 = 2 };
+
+/* The host encoder of that storage, for inspection and tests: for each of
+ * n ratios r[i] (finite, >= 0) writes hi[i] (the 16-bit pattern of
+ * RNE(r) in d_format) and, if lo is not NULL, lo[i] (the FP16 pattern of
+ * RNE(r - hi)).  DAO_EINVAL for a native or unknown format or a bad r. */
+dao_status dao_encode_values(int32_t d_format, int64_t n, const double* r, uint16_t* hi, uint16_t* lo);
 
 void dao_default_options(dao_options* opt);
 
@@ -144,6 +165,8 @@ typedef struct {
     int32_t n_beams, max_rows_per_beam, dtype, n_slices;
     int64_t sell_entries;     /* stored forward-layout entries incl. padding */
     int64_t device_bytes;     /* device memory held by the context */
+    int32_t d_format;         /* storage of D's values (DAO_DFMT_*) */
+    int32_t d_residual;       /* 1 when the FP16 residual is stored and used */
     int64_t bytes_dose;       /* algorithmic HBM bytes of one forward product */
     int64_t bytes_gradient;   /* algorithmic HBM bytes of one transposed product */
 } dao_info_t;

@@ -14,6 +14,7 @@ DAO_OK, DAO_EOPTIMAL, DAO_ESTALLED = 0, 1, 2
 DAO_EINVAL, DAO_ENOMEM, DAO_EDEVICE, DAO_ESTATE = -1, -2, -3, -4
 DAO_F64, DAO_F32 = 0, 1
 DAO_MASTER_APERTURE, DAO_MASTER_BEAMLET = 0, 1
+DAO_DFMT_NATIVE, DAO_DFMT_F16, DAO_DFMT_BF16 = 0, 1, 2
 _NAMES = {0: "DAO_OK", 1: "DAO_EOPTIMAL", 2: "DAO_ESTALLED", -1: "DAO_EINVAL", -2: "DAO_ENOMEM",
           -3: "DAO_EDEVICE", -4: "DAO_ESTATE"}
 
@@ -46,14 +47,16 @@ class dao_options(ctypes.Structure):
     _fields_ = [("dtype", c_int32), ("max_apertures", c_int32), ("eps", c_double),
                 ("max_steps", c_int32), ("tau_rel", c_double), ("max_tighten", c_int32),
                 ("refresh_every", c_int32), ("ls_slots", c_int32), ("mem_cap_bytes", c_int64),
-                ("master", c_int32), ("persistent", c_int32)]
+                ("master", c_int32), ("d_format", c_int32), ("d_residual", c_int32),
+                ("persistent", c_int32)]
 
 
 class dao_info_t(ctypes.Structure):
     _fields_ = [("n_vox", c_int64), ("n_vox_nonempty", c_int64), ("n_blt", c_int64), ("nnz", c_int64),
                 ("n_rows", c_int64), ("n_beams", c_int32), ("max_rows_per_beam", c_int32),
                 ("dtype", c_int32), ("n_slices", c_int32), ("sell_entries", c_int64),
-                ("device_bytes", c_int64), ("bytes_dose", c_int64), ("bytes_gradient", c_int64)]
+                ("device_bytes", c_int64), ("d_format", c_int32), ("d_residual", c_int32),
+                ("bytes_dose", c_int64), ("bytes_gradient", c_int64)]
 
 
 class dao_plan(ctypes.Structure):
@@ -91,6 +94,8 @@ _SIGS = {
     "dao_solve": (c_int32, [c_void_p, c_int32, POINTER(dao_plan)]),
     "dao_time_product": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double)]),
     "dao_profile_phases": (c_int32, [c_void_p, POINTER(c_double)]),
+    "dao_encode_values": (c_int32, [c_int32, c_int64, POINTER(c_double), POINTER(ctypes.c_uint16),
+                                    POINTER(ctypes.c_uint16)]),
     "dao_time_product_cold": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_int64, POINTER(c_double)]),
     "dao_profile_start": (c_int32, [c_void_p, c_int32]),
     "dao_profile_stop": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_double),
@@ -122,6 +127,20 @@ def load_library(path: str = LIB_PATH):
 
 def _ptr(a, ctype):
     return a.ctypes.data_as(POINTER(ctype))
+
+
+def encode_values(d_format: int, r, residual: bool = True):
+    """The library's host encoder of 16-bit D storage: (hi, lo) uint16 patterns
+    of the ratios r (lo None without residual)."""
+    lib = load_library()
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    hi = np.zeros(r.shape, dtype=np.uint16)
+    lo = np.zeros(r.shape, dtype=np.uint16) if residual else None
+    st = lib.dao_encode_values(int(d_format), r.size, _ptr(r, c_double), _ptr(hi, ctypes.c_uint16),
+                               _ptr(lo, ctypes.c_uint16) if lo is not None else None)
+    if st != DAO_OK:
+        raise DaoError(st, "dao_encode_values rejected its arguments")
+    return hi, lo
 
 
 def _addr(v) -> int:
@@ -156,7 +175,10 @@ class DaoContext:
         O = dao_options()
         lib.dao_default_options(byref(O))
         O.dtype = DAO_F64 if dtype == "f64" else DAO_F32
+        names = {f for f, _ in dao_options._fields_}
         for k, v in opts.items():
+            if k not in names:
+                raise TypeError(f"unknown option {k!r}")
             setattr(O, k, v)
         h = c_void_p()
         st = lib.dao_create(byref(M), byref(Bm), byref(S), PA, byref(O), c_void_p(stream), byref(h))

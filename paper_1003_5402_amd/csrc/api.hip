@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <type_traits>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -58,6 +59,9 @@ struct dao_ctx {
     int32_t* csc_ptr = nullptr;
     int32_t* csc_row = nullptr;
     void* csc_val = nullptr;
+    void* sell_lo = nullptr;           // FP16 residuals of the 16-bit formats (with d_residual)
+    void* csc_lo = nullptr;
+    float* col_scale = nullptr;        // per-beamlet scale of the 16-bit formats
     uint8_t* cls_int = nullptr;
     uint8_t* cls_ext = nullptr;
     ObjClass* classes = nullptr;
@@ -187,10 +191,11 @@ std::vector<T> convert(const std::vector<double>& v) {
 }
 
 // Device footprint predicted from the layout (checked against mem_cap before allocating).
-int64_t predicted_bytes(const HostLayout& L, size_t ts, int kmax) {
+int64_t predicted_bytes(const HostLayout& L, size_t ts, int kmax, const dao_options& opt) {
+    const int64_t vs = opt.d_format != DAO_DFMT_NATIVE ? 2 + (opt.d_residual ? 2 : 0) : int64_t(ts);
     int64_t b = 0;
-    b += (L.nslices + 1) * 4 + L.nslices * 4 + int64_t(L.slice_ptr.back()) * (ts + 2) + L.Vpad * 4;
-    b += (L.N + 1) * 4 + L.nnz * (4 + ts);
+    b += (L.nslices + 1) * 4 + L.nslices * 4 + int64_t(L.slice_ptr.back()) * (vs + 2) + L.Vpad * 4;
+    b += (L.N + 1) * 4 + L.nnz * (4 + vs) + (opt.d_format != DAO_DFMT_NATIVE ? L.N * 4 : 0);
     b += L.Vpad + L.V + (L.n_struct + 1) * sizeof(ObjClass);
     b += int64_t(L.R) * 8 + (L.B + 1) * 4 + L.N * 12;
     b += L.Vpad * (8 + 3 * ts + 8) + L.N * (ts + 8 + ts + 8);
@@ -207,7 +212,58 @@ int64_t predicted_bytes(const HostLayout& L, size_t ts, int kmax) {
 template <class T>
 SellView<T> sell_view(dao_ctx* c) {
     return SellView<T>{c->slice_ptr, c->slice_w, static_cast<const T*>(c->sell_val), c->sell_col,
-                       c->nslices};
+                       c->nslices, static_cast<const __half*>(c->sell_lo)};
+}
+
+// Calls f(ValueTag<VT, LO>{}) with the device type of D's stored values and
+// whether the FP16 residual is used (16-bit formats exist for FP32 only).
+template <class V, bool L>
+struct ValueTag {
+    using VT = V;
+    static constexpr bool LO = L;
+};
+template <class T, class F>
+void with_values(const dao_ctx* c, F&& f) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (c->opt.d_format == DAO_DFMT_F16) {
+            if (c->opt.d_residual)
+                f(ValueTag<__half, true>{});
+            else
+                f(ValueTag<__half, false>{});
+            return;
+        }
+        if (c->opt.d_format == DAO_DFMT_BF16) {
+            if (c->opt.d_residual)
+                f(ValueTag<__hip_bfloat16, true>{});
+            else
+                f(ValueTag<__hip_bfloat16, false>{});
+            return;
+        }
+    }
+    f(ValueTag<T, false>{});
+}
+
+// d_out (T, caller order) = D x (x: T, caller order) through k_dose.
+template <class T>
+void launch_dose(dao_ctx* c, const T* x, T* d_out) {
+    with_values<T>(c, [&](auto tag) {
+        using VT = typename decltype(tag)::VT;
+        constexpr bool LO = decltype(tag)::LO;
+        k_dose<T, VT, LO><<<c->slab_blocks(), SLAB_THREADS, c->stage_x() ? c->N * sizeof(T) : 0, c->stream>>>(
+            sell_view<VT>(c), c->perm, c->Vpad, x, int(c->N), c->stage_x(), c->col_scale, d_out);
+    });
+}
+
+// g = D^T u (internal row order in, beamlet order out) through k_gradT.
+template <class T, class UT, class Acc, class GT>
+void launch_gradT(dao_ctx* c, const UT* u, GT* g) {
+    with_values<T>(c, [&](auto tag) {
+        using VT = typename decltype(tag)::VT;
+        constexpr bool LO = decltype(tag)::LO;
+        k_gradT<VT, UT, Acc, GT, false, LO><<<c->N, BLOCK, 0, c->stream>>>(
+            c->csc_ptr, c->csc_row, static_cast<const VT*>(c->csc_val), static_cast<const __half*>(c->csc_lo), u,
+            g, nullptr, c->col_scale);
+    });
 }
 
 PoolView pool_view(dao_ctx* c) {
@@ -235,9 +291,9 @@ dao_status enqueue_cycle(dao_ctx* c) {
         S, c->Vpad, c->x64, int(c->N), c->stage_x64(), c->d, static_cast<const T*>(c->q), c->cls_int,
         c->classes, c->ncls, static_cast<T*>(c->u), c->upd_parts, c->ms);
     k_gradT<T, T, T, T, true><<<c->N, BLOCK, 0, c->stream>>>(c->csc_ptr, c->csc_row,
-                                                             static_cast<const T*>(c->csc_val),
+                                                             static_cast<const T*>(c->csc_val), nullptr,
                                                              static_cast<const T*>(c->u),
-                                                             static_cast<T*>(c->g), c->ms);
+                                                             static_cast<T*>(c->g), c->ms, nullptr);
     LAUNCHCHK(c);
     return DAO_OK;
 }
@@ -294,9 +350,13 @@ template <class T>
 dao_status build_dk_column(dao_ctx* c, int k) {
     if (!c->ap_master()) return DAO_OK;
     k_ap_indicator<T><<<(c->N + BLOCK - 1) / BLOCK, BLOCK, 0, c->stream>>>(pool_view(c), k, static_cast<T*>(c->ind));
-    k_dk_column<T><<<c->slab_blocks(), SLAB_THREADS, c->stage_x() ? c->N * sizeof(T) : 0, c->stream>>>(
-        sell_view<T>(c), c->Vpad, static_cast<const T*>(c->ind), int(c->N), c->stage_x(), k,
-        static_cast<T*>(c->dk));
+    with_values<T>(c, [&](auto tag) {
+        using VT = typename decltype(tag)::VT;
+        constexpr bool LO = decltype(tag)::LO;
+        k_dk_column<T, VT, LO><<<c->slab_blocks(), SLAB_THREADS, c->stage_x() ? c->N * sizeof(T) : 0, c->stream>>>(
+            sell_view<VT>(c), c->Vpad, static_cast<const T*>(c->ind), int(c->N), c->stage_x(), c->col_scale, k,
+            static_cast<T*>(c->dk));
+    });
     LAUNCHCHK(c);
     return DAO_OK;
 }
@@ -375,10 +435,7 @@ template <class T>
 dao_status refresh_gradient(dao_ctx* c) {
     k_objective_int<T><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
         c->d, c->cls_int, c->Vpad, c->classes, static_cast<T*>(c->u), c->u64, c->parts, c->arr, c->ms);
-    k_gradT<T, T, T, T, false><<<c->N, BLOCK, 0, c->stream>>>(c->csc_ptr, c->csc_row,
-                                                              static_cast<const T*>(c->csc_val),
-                                                              static_cast<const T*>(c->u),
-                                                              static_cast<T*>(c->g), nullptr);
+    launch_gradT<T, T, T, T>(c, static_cast<const T*>(c->u), static_cast<T*>(c->g));
     LAUNCHCHK(c);
     return DAO_OK;
 }
@@ -405,8 +462,7 @@ template <class T>
 dao_status price_current(dao_ctx* c, int32_t* beam, int16_t* leaves, double* rc, double* gap) {
     k_objective_int<T><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
         c->d, c->cls_int, c->Vpad, c->classes, static_cast<T*>(c->u), c->u64, c->parts, c->arr, c->ms);
-    k_gradT<T, double, double, double, false><<<c->N, BLOCK, 0, c->stream>>>(
-        c->csc_ptr, c->csc_row, static_cast<const T*>(c->csc_val), c->u64, c->g64, nullptr);
+    launch_gradT<T, double, double, double>(c, c->u64, c->g64);
     LAUNCHCHK(c);
     return price_on(c, c->g64, beam, leaves, rc, gap);
 }
@@ -465,18 +521,38 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     const size_t ts = sizeof(T);
     TRY(upload(c, &c->slice_ptr, L.slice_ptr.data(), L.slice_ptr.size() * 4));
     TRY(upload(c, &c->slice_w, L.slice_w.data(), L.slice_w.size() * 4));
-    {
+    const int fmt = c->opt.d_format;
+    if (fmt == DAO_DFMT_NATIVE) {
         std::vector<T> v = convert<T>(L.sell_val);
         TRY(upload(c, &c->sell_val, v.data(), v.size() * ts));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        // 16-bit value / per-beamlet scale (+ FP16 residual)
+        const bool res = c->opt.d_residual != 0;
+        std::vector<uint16_t> hi(L.sell_val.size()), lo(res ? L.sell_val.size() : 0);
+        for (size_t e = 0; e < hi.size(); ++e)
+            encode_value(fmt, L.sell_val[e] / double(L.col_scale[L.sell_col[e]]), &hi[e], res ? &lo[e] : nullptr);
+        TRY(upload(c, &c->sell_val, hi.data(), hi.size() * 2));
+        if (res) TRY(upload(c, &c->sell_lo, lo.data(), lo.size() * 2));
+        TRY(upload(c, &c->col_scale, L.col_scale.data(), L.col_scale.size() * 4));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     TRY(upload(c, &c->sell_col, L.sell_col.data(), L.sell_col.size() * 2));
     TRY(upload(c, &c->perm, L.perm.data(), L.perm.size() * 4));
     TRY(upload(c, &c->csc_ptr, L.csc_ptr.data(), L.csc_ptr.size() * 4));
     TRY(upload(c, &c->csc_row, L.csc_row.data(), L.csc_row.size() * 4));
-    {
+    if (fmt == DAO_DFMT_NATIVE) {
         std::vector<T> v = convert<T>(L.csc_val);
         TRY(upload(c, &c->csc_val, v.data(), v.size() * ts));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        const bool res = c->opt.d_residual != 0;
+        std::vector<uint16_t> hi(L.csc_val.size()), lo(res ? L.csc_val.size() : 0);
+        for (int64_t i = 0; i < L.N; ++i)
+            for (int32_t e = L.csc_ptr[i]; e < L.csc_ptr[i + 1]; ++e)
+                encode_value(fmt, L.csc_val[e] / double(L.col_scale[i]), &hi[e], res ? &lo[e] : nullptr);
+        TRY(upload(c, &c->csc_val, hi.data(), hi.size() * 2));
+        if (res) TRY(upload(c, &c->csc_lo, lo.data(), lo.size() * 2));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     TRY(upload(c, &c->cls_int, L.cls_int.data(), L.cls_int.size()));
@@ -577,8 +653,7 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
 template <class T>
 dao_status dose_typed(dao_ctx* c, const void* x, void* d) {
     k_fill<T><<<c->elem_blocks(c->V), BLOCK, 0, c->stream>>>(static_cast<T*>(d), c->V, T(0));
-    k_dose<T><<<c->slab_blocks(), SLAB_THREADS, c->stage_x() ? c->N * sizeof(T) : 0, c->stream>>>(
-        sell_view<T>(c), c->perm, c->Vpad, static_cast<const T*>(x), int(c->N), c->stage_x(), static_cast<T*>(d));
+    launch_dose<T>(c, static_cast<const T*>(x), static_cast<T*>(d));
     LAUNCHCHK(c);
     return DAO_OK;
 }
@@ -590,10 +665,7 @@ dao_status gradient_typed(dao_ctx* c, const void* d, void* g, double* F) {
                                                                        c->parts, c->arr, c->scalar);
     k_gather_grad<T><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(dd, c->perm, c->cls_int, c->Vpad,
                                                                         c->classes, static_cast<T*>(c->ug));
-    k_gradT<T, T, T, T, false><<<c->N, BLOCK, 0, c->stream>>>(c->csc_ptr, c->csc_row,
-                                                              static_cast<const T*>(c->csc_val),
-                                                              static_cast<const T*>(c->ug), static_cast<T*>(g),
-                                                              nullptr);
+    launch_gradT<T, T, T, T>(c, static_cast<const T*>(c->ug), static_cast<T*>(g));
     LAUNCHCHK(c);
     HIPCHK(c, hipMemcpyAsync(c->scalar_h, c->scalar, 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -615,13 +687,9 @@ dao_status time_product_typed(dao_ctx* c, int kernel, int iters, double* us, boo
     HIPCHK(c, hipEventCreate(&e1));
     auto launch = [&]() {
         if (kernel == 0)
-            k_dose<T><<<c->slab_blocks(), SLAB_THREADS, c->stage_x() ? c->N * sizeof(T) : 0, c->stream>>>(
-                sell_view<T>(c), c->perm, c->Vpad, static_cast<const T*>(c->dx), int(c->N), c->stage_x(),
-                static_cast<T*>(c->vscratch));
+            launch_dose<T>(c, static_cast<const T*>(c->dx), static_cast<T*>(c->vscratch));
         else
-            k_gradT<T, T, T, T, false><<<c->N, BLOCK, 0, c->stream>>>(
-                c->csc_ptr, c->csc_row, static_cast<const T*>(c->csc_val), static_cast<const T*>(c->u),
-                static_cast<T*>(c->dx), nullptr);
+            launch_gradT<T, T, T, T>(c, static_cast<const T*>(c->u), static_cast<T*>(c->dx));
     };
     if (warm) launch();
     HIPCHK(c, hipEventRecord(e0, c->stream));
@@ -774,6 +842,8 @@ void dao_default_options(dao_options* o) {
     o->ls_slots = 2;
     o->mem_cap_bytes = 0;
     o->master = DAO_MASTER_APERTURE;
+    o->d_format = DAO_DFMT_NATIVE;
+    o->d_residual = 0;
     o->persistent = 2;
 }
 
@@ -804,7 +874,7 @@ dao_status dao_create(const dao_matrix* D, const dao_beams* beams, const dao_str
     auto L = std::make_unique<HostLayout>();
     build_layout(D, beams, structs, presc, L.get());
     const size_t ts = opt.dtype == DAO_F64 ? 8 : 4;
-    const int64_t need = predicted_bytes(*L, ts, opt.max_apertures);
+    const int64_t need = predicted_bytes(*L, ts, opt.max_apertures, opt);
     if (opt.mem_cap_bytes > 0 && need > opt.mem_cap_bytes) {
         g_create_error = "device footprint " + std::to_string(need) + " B exceeds mem_cap_bytes";
         return DAO_ENOMEM;
@@ -862,11 +932,18 @@ dao_status dao_info(const dao_ctx* c, dao_info_t* o) {
     o->sell_entries = c->sell_entries;
     o->device_bytes = c->device_bytes;
     const int64_t ts = int64_t(c->tsize);
-    // forward: every stored entry (value + 16-bit column) + slice headers +
-    // x once + d once (caller order)
-    o->bytes_dose = c->nnz * (ts + 2) + (c->nslices + 1) * 4 + c->nslices * 4 + c->N * ts + c->Vnz * (ts + 4);
-    // transpose: every entry (value + 32-bit row) + column pointers + u once + g once
-    o->bytes_gradient = c->nnz * (ts + 4) + (c->N + 1) * 4 + c->Vnz * ts + c->N * ts;
+    o->d_format = c->opt.d_format;
+    o->d_residual = c->opt.d_residual;
+    // stored bytes per value: the ctx type, or 16 bits (+ 16 for the residual)
+    const bool narrow = c->opt.d_format != DAO_DFMT_NATIVE;
+    const int64_t vs = narrow ? 2 + (c->opt.d_residual ? 2 : 0) : ts;
+    const int64_t sc = narrow ? c->N * 4 : 0;   // per-beamlet scales
+    // forward: every entry (value + 16-bit column) + slice headers + x once +
+    // scales + d once (caller order)
+    o->bytes_dose = c->nnz * (vs + 2) + (c->nslices + 1) * 4 + c->nslices * 4 + c->N * ts + sc + c->Vnz * (ts + 4);
+    // transpose: every entry (value + 32-bit row) + column pointers + u once +
+    // scales + g once
+    o->bytes_gradient = c->nnz * (vs + 4) + (c->N + 1) * 4 + c->Vnz * ts + sc + c->N * ts;
     return DAO_OK;
 }
 
@@ -976,6 +1053,15 @@ dao_status dao_time_product(dao_ctx* c, int32_t kernel, int32_t iters, double* u
         return c->fail(DAO_EINVAL, "kernel must be 0 or 1, iters >= 1");
     return c->dtype == DAO_F64 ? time_product_typed<double>(c, kernel, iters, us_per_launch)
                                : time_product_typed<float>(c, kernel, iters, us_per_launch);
+}
+
+dao_status dao_encode_values(int32_t d_format, int64_t n, const double* r, uint16_t* hi, uint16_t* lo) {
+    if (d_format != DAO_DFMT_F16 && d_format != DAO_DFMT_BF16) return DAO_EINVAL;
+    if (n < 0 || (n > 0 && (!r || !hi))) return DAO_EINVAL;
+    for (int64_t i = 0; i < n; ++i)
+        if (!(r[i] >= 0.0) || !std::isfinite(r[i])) return DAO_EINVAL;
+    for (int64_t i = 0; i < n; ++i) encode_value(d_format, r[i], &hi[i], lo ? &lo[i] : nullptr);
+    return DAO_OK;
 }
 
 dao_status dao_time_product_cold(dao_ctx* c, int32_t kernel, int32_t iters, void* scrub, int64_t scrub_bytes,

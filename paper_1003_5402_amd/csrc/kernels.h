@@ -21,6 +21,8 @@
 // waits on another workgroup.
 #pragma once
 
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -218,6 +220,21 @@ __device__ __forceinline__ void ls_voxel(const ObjClass& c, double d, double q, 
 // ---------------------------------------------------------------------------
 // forward products over slabs
 // ---------------------------------------------------------------------------
+// Stored value of D: the context type, or a 16-bit pattern scaled per
+// beamlet (FP16 / BF16, optionally with an FP16 residual).
+__device__ __forceinline__ float dval(float v) { return v; }
+__device__ __forceinline__ double dval(double v) { return v; }
+__device__ __forceinline__ float dval(__half v) { return __half2float(v); }
+__device__ __forceinline__ float dval(__hip_bfloat16 v) { return __bfloat162float(v); }
+// hi + lo of a split value: exact in FP32 (lo is below hi's last bit)
+template <class VT, bool LO>
+__device__ __forceinline__ auto dval2(VT hi, const __half* lo_p) {
+    if constexpr (LO)
+        return dval(hi) + __half2float(*lo_p);
+    else
+        return dval(hi);
+}
+
 template <class T>
 struct SellView {
     const uint32_t* slice_ptr;
@@ -225,32 +242,37 @@ struct SellView {
     const T* val;
     const uint16_t* col;
     int64_t nslices;
+    const __half* lo;   // FP16 residuals (same positions as val), or null
 };
 
 // Lane `lane` of a wavefront: entries k0..k1-1 of its row in the slice that
 // starts at entry `base`, visited in stored (ascending beamlet) order.
-template <class T, class XT, class Acc>
-__device__ __forceinline__ Acc sell_dot(const T* __restrict__ val, const uint16_t* __restrict__ col,
-                                        uint32_t base, int k0, int k1, int lane,
-                                        const XT* __restrict__ xs) {
-    const T* v = val + base + uint32_t(k0) * SLICE + lane;
-    const uint16_t* c = col + base + uint32_t(k0) * SLICE + lane;
+template <class T, class XT, class Acc, bool LO = false>
+__device__ __forceinline__ Acc sell_dot(const T* __restrict__ val, const __half* __restrict__ lo,
+                                        const uint16_t* __restrict__ col, uint32_t base, int k0, int k1,
+                                        int lane, const XT* __restrict__ xs) {
+    const size_t o = base + uint32_t(k0) * SLICE + lane;
+    const T* v = val + o;
+    const __half* l = LO ? lo + o : nullptr;
+    const uint16_t* c = col + o;
     Acc acc = Acc(0);
     int k = k0;
     for (; k + 4 <= k1; k += 4) {
         const T v0 = v[0], v1 = v[SLICE], v2 = v[2 * SLICE], v3 = v[3 * SLICE];
         const uint16_t c0 = c[0], c1 = c[SLICE], c2 = c[2 * SLICE], c3 = c[3 * SLICE];
-        acc += Acc(v0) * Acc(xs[c0]);
-        acc += Acc(v1) * Acc(xs[c1]);
-        acc += Acc(v2) * Acc(xs[c2]);
-        acc += Acc(v3) * Acc(xs[c3]);
+        acc += Acc(dval2<T, LO>(v0, l)) * Acc(xs[c0]);
+        acc += Acc(dval2<T, LO>(v1, l + SLICE)) * Acc(xs[c1]);
+        acc += Acc(dval2<T, LO>(v2, l + 2 * SLICE)) * Acc(xs[c2]);
+        acc += Acc(dval2<T, LO>(v3, l + 3 * SLICE)) * Acc(xs[c3]);
         v += 4 * SLICE;
         c += 4 * SLICE;
+        if (LO) l += 4 * SLICE;
     }
     for (; k < k1; ++k) {
-        acc += Acc(v[0]) * Acc(xs[c[0]]);
+        acc += Acc(dval2<T, LO>(v[0], l)) * Acc(xs[c[0]]);
         v += SLICE;
         c += SLICE;
+        if (LO) l += SLICE;
     }
     return acc;
 }
@@ -259,7 +281,7 @@ __device__ __forceinline__ Acc sell_dot(const T* __restrict__ val, const uint16_
 // takes slice w / KSPLIT of the slab and the (w % KSPLIT)-th quarter of its
 // entries; partials meet in s_part and are added in k order.  Returns the
 // row sum in threads t < SLAB (row blockIdx.x * SLAB + t).
-template <class T, class XT, class Acc>
+template <class T, class XT, class Acc, bool LO = false>
 __device__ __forceinline__ Acc slab_rows(const SellView<T>& S, const XT* __restrict__ xs, Acc* s_part) {
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int j = wave / KSPLIT, kp = wave % KSPLIT;
@@ -269,7 +291,7 @@ __device__ __forceinline__ Acc slab_rows(const SellView<T>& S, const XT* __restr
         const int w = S.slice_w[s];
         const int kc = (w + KSPLIT - 1) / KSPLIT;
         const int k0 = min(w, kp * kc), k1 = min(w, k0 + kc);
-        acc = sell_dot<T, XT, Acc>(S.val, S.col, S.slice_ptr[s], k0, k1, lane, xs);
+        acc = sell_dot<T, XT, Acc, LO>(S.val, S.lo, S.col, S.slice_ptr[s], k0, k1, lane, xs);
     }
     s_part[kp * SLAB + j * SLICE + lane] = acc;
     __syncthreads();
@@ -281,11 +303,17 @@ __device__ __forceinline__ Acc slab_rows(const SellView<T>& S, const XT* __restr
     return sum;
 }
 
-// Stage an n-vector into LDS (or return the global pointer when not staged).
+// Stage an n-vector into LDS (or return the global pointer when not staged),
+// multiplied by the per-beamlet scale when one is given (16-bit formats,
+// which are always staged).
 template <class XT, class ST>
-__device__ __forceinline__ const XT* stage_vec(const ST* __restrict__ src, int n, XT* lds, bool stage) {
+__device__ __forceinline__ const XT* stage_vec(const ST* __restrict__ src, int n, XT* lds, bool stage,
+                                               const float* __restrict__ scale = nullptr) {
     if (!stage) return reinterpret_cast<const XT*>(src);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = XT(src[i]);
+    if (scale)
+        for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = XT(src[i]) * XT(scale[i]);
+    else
+        for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = XT(src[i]);
     __syncthreads();
     return lds;
 }
@@ -294,15 +322,17 @@ __device__ __forceinline__ const XT* stage_vec(const ST* __restrict__ src, int n
 // plain products and objective (C-ABI calls, round ends)
 // ---------------------------------------------------------------------------
 
-// d_ext[perm[r]] = (D x)_r for every row of the slab; x staged in LDS.
-template <class T>
-__global__ void __launch_bounds__(SLAB_THREADS) k_dose(SellView<T> S, const int32_t* __restrict__ perm,
+// d_ext[perm[r]] = (D x)_r for every row of the slab; x staged in LDS
+// (times the per-beamlet scale of a 16-bit value format).
+template <class T, class VT = T, bool LO = false>
+__global__ void __launch_bounds__(SLAB_THREADS) k_dose(SellView<VT> S, const int32_t* __restrict__ perm,
                                                        int64_t Vpad, const T* __restrict__ x, int N,
-                                                       bool stage, T* __restrict__ d_ext) {
+                                                       bool stage, const float* __restrict__ scale,
+                                                       T* __restrict__ d_ext) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ T s_part[KSPLIT * SLAB];
-    const T* xs = stage_vec<T, T>(x, N, reinterpret_cast<T*>(smem), stage);
-    const T sum = slab_rows<T, T, T>(S, xs, s_part);
+    const T* xs = stage_vec<T, T>(x, N, reinterpret_cast<T*>(smem), stage, scale);
+    const T sum = slab_rows<VT, T, T, LO>(S, xs, s_part);
     const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
     if (threadIdx.x < SLAB && row < Vpad) {
         const int32_t j = perm[row];
@@ -379,12 +409,14 @@ __global__ void __launch_bounds__(BLOCK) k_objective_int(const double* __restric
 
 // g_i = sum over beamlet i's entries of val * u[row]; one block per beamlet.
 // GATED (the master's copy) runs only while a finished line search awaits
-// its update (phase PH_UPD of an unfinished master), like k_update.
-template <class T, class UT, class Acc, class GT, bool GATED>
+// its update (phase PH_UPD of an unfinished master), like k_update.  With a
+// 16-bit value format the column sum is multiplied by the beamlet's scale.
+template <class T, class UT, class Acc, class GT, bool GATED, bool LO = false>
 __global__ void __launch_bounds__(BLOCK) k_gradT(const int32_t* __restrict__ cptr,
                                                  const int32_t* __restrict__ crow,
-                                                 const T* __restrict__ cval, const UT* __restrict__ u,
-                                                 GT* __restrict__ g, const MasterState* gate) {
+                                                 const T* __restrict__ cval, const __half* __restrict__ clo,
+                                                 const UT* __restrict__ u, GT* __restrict__ g,
+                                                 const MasterState* gate, const float* __restrict__ scale) {
     if (GATED) {
         __shared__ int s_skip;
         if (threadIdx.x == 0) s_skip = (gate->done || gate->phase != PH_UPD);
@@ -398,12 +430,12 @@ __global__ void __launch_bounds__(BLOCK) k_gradT(const int32_t* __restrict__ cpt
     for (; e + 3 * BLOCK < e1; e += 4 * BLOCK) {
         const int32_t r0 = crow[e], r1 = crow[e + BLOCK], r2 = crow[e + 2 * BLOCK], r3 = crow[e + 3 * BLOCK];
         const T v0 = cval[e], v1 = cval[e + BLOCK], v2 = cval[e + 2 * BLOCK], v3 = cval[e + 3 * BLOCK];
-        acc += Acc(v0) * Acc(u[r0]);
-        acc += Acc(v1) * Acc(u[r1]);
-        acc += Acc(v2) * Acc(u[r2]);
-        acc += Acc(v3) * Acc(u[r3]);
+        acc += Acc(dval2<T, LO>(v0, clo + e)) * Acc(u[r0]);
+        acc += Acc(dval2<T, LO>(v1, clo + e + BLOCK)) * Acc(u[r1]);
+        acc += Acc(dval2<T, LO>(v2, clo + e + 2 * BLOCK)) * Acc(u[r2]);
+        acc += Acc(dval2<T, LO>(v3, clo + e + 3 * BLOCK)) * Acc(u[r3]);
     }
-    for (; e < e1; e += BLOCK) acc += Acc(cval[e]) * Acc(u[crow[e]]);
+    for (; e < e1; e += BLOCK) acc += Acc(dval2<T, LO>(cval[e], clo + e)) * Acc(u[crow[e]]);
     acc = wave_sum(acc);
     __shared__ Acc s_w[BLOCK / WAVE];
     if ((threadIdx.x % WAVE) == 0) s_w[threadIdx.x / WAVE] = acc;
@@ -411,7 +443,7 @@ __global__ void __launch_bounds__(BLOCK) k_gradT(const int32_t* __restrict__ cpt
     if (threadIdx.x == 0) {
         Acc t = Acc(0);
         for (int w = 0; w < BLOCK / WAVE; ++w) t += s_w[w];
-        g[i] = GT(t);
+        g[i] = GT(scale ? t * Acc(scale[i]) : t);
     }
 }
 

@@ -96,14 +96,15 @@ __global__ void k_ap_indicator(PoolView P, int k, T* __restrict__ ind) {
 }
 
 // Column k of D_K: dk[row * KS + k] = (D ind)_row, FP64 sums rounded to T.
-template <class T>
-__global__ void __launch_bounds__(SLAB_THREADS) k_dk_column(SellView<T> S, int64_t Vpad,
+template <class T, class VT = T, bool LO = false>
+__global__ void __launch_bounds__(SLAB_THREADS) k_dk_column(SellView<VT> S, int64_t Vpad,
                                                             const T* __restrict__ ind, int N, bool stage,
-                                                            int k, T* __restrict__ dk) {
+                                                            const float* __restrict__ scale, int k,
+                                                            T* __restrict__ dk) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double s_part[KSPLIT * SLAB];
-    const T* xs = stage_vec<T, T>(ind, N, reinterpret_cast<T*>(smem), stage);
-    const double sum = slab_rows<T, T, double>(S, xs, s_part);
+    const T* xs = stage_vec<T, T>(ind, N, reinterpret_cast<T*>(smem), stage, scale);
+    const double sum = slab_rows<VT, T, double, LO>(S, xs, s_part);
     const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
     if (threadIdx.x < SLAB && row < Vpad) dk[row * KS + k] = T(sum);
 }

@@ -21,6 +21,63 @@ std::string cat(A&&... a) {
 
 }  // namespace
 
+namespace {
+// r = a * 2^E with a in [1, 2): E of |r| > 0
+int exp2_of(double a) {
+    int e = 0;
+    std::frexp(a, &e);   // a = m 2^e, m in [0.5, 1)
+    return e - 1;
+}
+// RNE of |r| to a binary format with `mant` stored mantissa bits, exponent
+// bias `bias` and `ebits` exponent bits; returns the magnitude bits.
+uint16_t enc_mag(double a, int mant, int bias, int ebits) {
+    const int emax_field = (1 << ebits) - 1;   // all ones: infinity
+    if (a == 0.0) return 0;
+    if (std::isinf(a)) return uint16_t(emax_field << mant);
+    int E = exp2_of(a);
+    if (E >= 1 - bias) {   // normal range
+        double q = std::nearbyint(std::ldexp(a, mant - E));
+        if (q >= std::ldexp(1.0, mant + 1)) {   // rounded up to the next binade
+            E += 1;
+            q = double(1 << mant);
+        }
+        if (E + bias >= emax_field) return uint16_t(emax_field << mant);
+        return uint16_t(((E + bias) << mant) | (int(q) - (1 << mant)));
+    }
+    // subnormal: units of 2^(1 - bias - mant); 2^mant units is the smallest normal
+    const double q = std::nearbyint(std::ldexp(a, bias - 1 + mant));
+    return uint16_t(q);
+}
+double dec_mag(uint16_t h, int mant, int bias, int ebits) {
+    const int ef = (h >> mant) & ((1 << ebits) - 1), m = h & ((1 << mant) - 1);
+    if (ef == (1 << ebits) - 1) return m ? NAN : INFINITY;
+    if (ef == 0) return std::ldexp(double(m), 1 - bias - mant);
+    return std::ldexp(double((1 << mant) + m), ef - bias - mant);
+}
+}  // namespace
+
+uint16_t enc_f16(double r) {
+    const uint16_t s = std::signbit(r) ? 0x8000 : 0;
+    return uint16_t(s | enc_mag(std::fabs(r), 10, 15, 5));
+}
+uint16_t enc_bf16(double r) {
+    const uint16_t s = std::signbit(r) ? 0x8000 : 0;
+    return uint16_t(s | enc_mag(std::fabs(r), 7, 127, 8));
+}
+double dec_f16(uint16_t h) {
+    const double v = dec_mag(uint16_t(h & 0x7FFF), 10, 15, 5);
+    return (h & 0x8000) ? -v : v;
+}
+double dec_bf16(uint16_t h) {
+    const double v = dec_mag(uint16_t(h & 0x7FFF), 7, 127, 8);
+    return (h & 0x8000) ? -v : v;
+}
+void encode_value(int fmt, double r, uint16_t* hi, uint16_t* lo) {
+    const uint16_t h = fmt == DAO_DFMT_BF16 ? enc_bf16(r) : enc_f16(r);
+    *hi = h;
+    if (lo) *lo = enc_f16(r - (fmt == DAO_DFMT_BF16 ? dec_bf16(h) : dec_f16(h)));
+}
+
 dao_status validate_inputs(const dao_matrix* D, const dao_beams* beams,
                            const dao_structures* structs, const dao_prescription* presc,
                            const dao_options* opt, std::string* err) {
@@ -43,6 +100,16 @@ dao_status validate_inputs(const dao_matrix* D, const dao_beams* beams,
     if (opt->master != DAO_MASTER_APERTURE && opt->master != DAO_MASTER_BEAMLET)
         return fail("master must be DAO_MASTER_APERTURE or DAO_MASTER_BEAMLET");
     if (opt->persistent < 0 || opt->persistent > 2) return fail("persistent must be 0, 1 or 2");
+    if (opt->d_format < DAO_DFMT_NATIVE || opt->d_format > DAO_DFMT_BF16)
+        return fail("d_format must be DAO_DFMT_NATIVE, DAO_DFMT_F16 or DAO_DFMT_BF16");
+    if (opt->d_residual != 0 && opt->d_residual != 1) return fail("d_residual must be 0 or 1");
+    if (opt->d_format != DAO_DFMT_NATIVE) {
+        if (opt->dtype != DAO_F32) return fail("a 16-bit d_format needs dtype DAO_F32");
+        if (opt->master != DAO_MASTER_APERTURE) return fail("a 16-bit d_format needs the aperture-matrix master");
+        if (D->n_blt > 12288) return fail("a 16-bit d_format needs n_blt <= 12288 (x staged on chip)");
+    } else if (opt->d_residual) {
+        return fail("d_residual needs a 16-bit d_format");
+    }
     if (opt->master == DAO_MASTER_APERTURE && opt->max_apertures > KS)
         return fail("the aperture-matrix master holds at most 64 apertures (max_apertures)");
 
@@ -209,6 +276,14 @@ void build_layout(const dao_matrix* D, const dao_beams* beams, const dao_structu
                 fill[c]++;
             }
         }
+    }
+
+    // per-beamlet scale of the 16-bit value formats: the column maximum
+    L->col_scale.assign(N, 1.0f);
+    for (int64_t i = 0; i < N; ++i) {
+        double mx = 0.0;
+        for (int32_t e = L->csc_ptr[i]; e < L->csc_ptr[i + 1]; ++e) mx = std::max(mx, L->csc_val[e]);
+        if (mx > 0.0) L->col_scale[i] = float(mx);
     }
 
     // --- MLC geometry -----------------------------------------------------

@@ -31,6 +31,7 @@ struct HostLayout {
     std::vector<int32_t> csc_ptr;     // [N + 1]
     std::vector<int32_t> csc_row;     // [nnz]
     std::vector<double> csc_val;      // [nnz]
+    std::vector<float> col_scale;     // [N] per-beamlet scale of the 16-bit formats (max of the column)
 
     // objective classes
     std::vector<uint8_t> cls_int;     // [Vpad] class of each internal row
@@ -46,6 +47,15 @@ struct HostLayout {
     std::vector<int32_t> blt_row;     // [N] global row of each beamlet
     std::vector<int32_t> blt_pos;     // [N] position within the row
 };
+
+// Round-to-nearest-even encoders of the 16-bit value formats (sign kept,
+// overflow to infinity, subnormals exact) and their exact decoders.
+uint16_t enc_f16(double r);
+uint16_t enc_bf16(double r);
+double dec_f16(uint16_t h);
+double dec_bf16(uint16_t h);
+// hi in `fmt` (DAO_DFMT_F16 / DAO_DFMT_BF16) and the FP16 residual lo.
+void encode_value(int fmt, double r, uint16_t* hi, uint16_t* lo);
 
 // Check every input (returns DAO_EINVAL with a message on the first problem).
 dao_status validate_inputs(const dao_matrix* D, const dao_beams* beams,

@@ -78,6 +78,11 @@ def test_create_rejects_malformed_inputs():
     assert "ls_slots" in msg
     msg = _expect(dao.DAO_EINVAL, _a=_args(ph), _opts=dict(persistent=3))
     assert "persistent" in msg
+    for opts, needle in [(dict(d_format=3), "d_format"), (dict(d_residual=1), "d_residual"),
+                         (dict(d_format=1, d_residual=2), "d_residual"),
+                         (dict(d_format=1, dtype="f64"), "DAO_F32"), (dict(d_format=2, master=1), "aperture")]:
+        msg = _expect(dao.DAO_EINVAL, _a=_args(ph), _opts=opts)
+        assert needle in msg, (opts, msg)
 
 
 def test_create_enforces_memory_cap():

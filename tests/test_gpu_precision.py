@@ -1,0 +1,116 @@
+"""GPU parity of the 16-bit storage of D: FP16 or BF16 values over a
+per-beamlet FP32 scale, with or without the FP16 residual.
+
+Two FP64 oracle references:
+* the quantized matrix s_i (hi + lo) that the device multiplies with, built
+  independently in tests/quant.py (numpy rounding).  The products must match
+  it to the FP32 bar (1e-5 of the max norm), which checks the kernels, the
+  scale handling and the residual path.
+* the original D.  Per entry, the stored value is within 2^-12 (FP16) or
+  2^-9 (BF16) of D_ij relative to its column maximum, and within ~2^-23 with
+  the residual; with non-negative terms the max-norm error of a product is
+  at most that bound.  The bars below are those bounds rounded up.
+The converged master on the same pool is compared the same two ways, plus
+the plan metrics PTV D95 and OAR Dmax against the FP64 master on the
+original D.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1003_5402_amd as dao
+from conftest import cached_phantom, oracle_problem
+from gpu_util import ctx_for, dev, relerr, torch_cuda
+from oracle.master import MasterState, solve_master
+from oracle.metrics import d95, dmax
+from quant import quantized
+
+pytestmark = pytest.mark.gpu
+
+FMT = {"f16": dao.DAO_DFMT_F16, "bf16": dao.DAO_DFMT_BF16}
+FORMATS = [("f16", 0), ("f16", 1), ("bf16", 0), ("bf16", 1)]
+# max-norm relative error against the original D
+BOUND = {("f16", 0): 3e-4, ("bf16", 0): 2e-3, ("f16", 1): 1e-5, ("bf16", 1): 1e-5}
+
+
+def _problems(ph, fmt, res):
+    import oracle as o
+    P = oracle_problem(ph)            # original D, FP64
+    Dq = quantized(ph.csr(), fmt, res)
+    Pq = o.make_problem(Dq, ph.rows_per_beam, ph.row_len, ph.vox_struct, ph.prescriptions)
+    return P, Pq
+
+
+@pytest.mark.parametrize("name", ["tiny", "prostate"])
+@pytest.mark.parametrize("fmt,res", FORMATS)
+def test_products_with_16bit_storage(name, fmt, res):
+    torch = torch_cuda()
+    ph = cached_phantom(name)
+    P, Pq = _problems(ph, fmt, res)
+    print(f"[precision] {name} {fmt} residual={res}", flush=True)
+    ctx = ctx_for(ph, dtype="f32", d_format=FMT[fmt], d_residual=res)
+    try:
+        info = ctx.info()
+        assert info["d_format"] == FMT[fmt] and info["d_residual"] == res
+        rng = np.random.default_rng(11)
+        for trial in range(2):
+            x = rng.uniform(0.0, 0.05, ph.n_blt).astype(np.float32).astype(np.float64)
+            d = torch.full((ph.n_vox,), float("nan"), dtype=torch.float32, device="cuda:0")
+            ctx.dose(dev(x, torch.float32), d)
+            torch.cuda.synchronize()
+            got = d.double().cpu().numpy()
+            assert relerr(got, oracle.dose(Pq, x)) <= 1e-5, trial
+            assert relerr(got, oracle.dose(P, x)) <= BOUND[(fmt, res)], (trial, relerr(got, oracle.dose(P, x)))
+            z = oracle.dose(P, x).astype(np.float32).astype(np.float64)
+            g = torch.full((ph.n_blt,), float("nan"), dtype=torch.float32, device="cuda:0")
+            F = ctx.gradient(dev(z, torch.float32), g)
+            torch.cuda.synchronize()
+            gg = g.double().cpu().numpy()
+            assert relerr(gg, oracle.prices(Pq, oracle.grad_objective(Pq, z))) <= 1e-5, trial
+            assert relerr(gg, oracle.prices(P, oracle.grad_objective(P, z))) <= BOUND[(fmt, res)], trial
+            assert abs(F - oracle.objective(P, z)) <= 1e-12 * oracle.objective(P, z)
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("fmt,res", FORMATS)
+def test_converged_master_with_16bit_storage(fmt, res):
+    """Same pool (the oracle's first five apertures on the original D): the
+    GPU master matches the FP64 master on the quantized D to the FP32 bars
+    (F 1e-5, dose 1e-4) and the FP64 master on the original D to the format's
+    bound (F, dose, PTV D95, OAR Dmax)."""
+    torch = torch_cuda()
+    ph = cached_phantom("tiny")
+    P, Pq = _problems(ph, fmt, res)
+    pool = oracle.solve(P, 5, eps=1e-4, max_steps=60)["pool"]
+    refs = {}
+    for key, PP in (("q", Pq), ("d", P)):
+        st = MasterState.empty(PP)
+        for ap in pool:
+            st.add(ap)
+        solve_master(PP, st, tol=1e-7, max_steps=20000)
+        refs[key] = (oracle.objective(PP, st.d), st.d)
+    ctx = ctx_for(ph, dtype="f32", d_format=FMT[fmt], d_residual=res)
+    try:
+        ctx.reset()
+        for ap in pool:
+            ctx.add_aperture(ap.beam, ap.leaves)
+        steps, kkt, F = ctx.master_solve(1e-7, 20000)
+        d = torch.empty(ph.n_vox, dtype=torch.float64, device="cuda:0")
+        ctx.get_dose(d)
+        z = d.cpu().numpy()
+        Fq, zq = refs["q"]
+        F0, z0 = refs["d"]
+        assert abs(F - Fq) <= 1e-5 * Fq, (F, Fq)
+        assert relerr(z, zq) <= 1e-4
+        bound = max(BOUND[(fmt, res)], 1e-4)
+        errs = dict(F=abs(F - F0) / F0, dose=relerr(z, z0))
+        ptv = np.asarray(ph.vox_struct) == 0
+        oar = np.asarray(ph.vox_struct) == 1
+        errs["D95"] = abs(d95(z, ptv) - d95(z0, ptv)) / d95(z0, ptv)
+        errs["Dmax"] = abs(dmax(z, oar) - dmax(z0, oar)) / dmax(z0, oar)
+        print(f"[precision] {fmt} residual={res} errors vs FP64 on the original D: {errs}", flush=True)
+        for k, v in errs.items():
+            assert v <= 10 * bound, (k, v)
+    finally:
+        ctx.close()
