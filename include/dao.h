@@ -295,6 +295,18 @@ typedef struct {
  * eps * |rc_1| or max_steps.  Stops after n_apertures apertures. */
 dao_status dao_solve(dao_ctx* ctx, int32_t n_apertures, dao_plan* out);
 
+/* Several independent solves advanced together (the serving form): each
+ * round prices every live solve and adds its column, then one cooperative
+ * launch runs all their master solves, the grid's workgroups shared out in
+ * proportion to their voxel rows; a solve leaves when it stops.  Every solve
+ * follows exactly dao_solve's rules, so each plan is the one dao_solve gives
+ * (up to the order of floating-point sums, which depends on how many
+ * workgroups a solve gets).  Contexts must be distinct and share the dtype;
+ * the shared launch needs the persistent aperture master on one stream
+ * (otherwise the master solves run one after another).  plans[i] receives
+ * solve i's log (may be NULL); the return is DAO_OK or the first error. */
+dao_status dao_solve_batch(dao_ctx* const* ctxs, int32_t n, const int32_t* n_apertures, dao_plan* plans);
+
 #ifdef __cplusplus
 }
 #endif

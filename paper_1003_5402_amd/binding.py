@@ -92,6 +92,7 @@ _SIGS = {
                                POINTER(c_double)]),
     "dao_get_dose": (c_int32, [c_void_p, c_void_p, POINTER(c_double)]),
     "dao_solve": (c_int32, [c_void_p, c_int32, POINTER(dao_plan)]),
+    "dao_solve_batch": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_int32), POINTER(dao_plan)]),
     "dao_time_product": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double)]),
     "dao_profile_phases": (c_int32, [c_void_p, POINTER(c_double)]),
     "dao_encode_values": (c_int32, [c_int32, c_int64, POINTER(c_double), POINTER(ctypes.c_uint16),
@@ -148,6 +149,41 @@ def _addr(v) -> int:
     if isinstance(v, int):
         return v
     return int(v.data_ptr())
+
+
+def _plan_arrays(n):
+    n = max(1, int(n))
+    arr = dict(round_beam=np.zeros(n, np.int32), round_rc=np.zeros(n), round_gap=np.zeros(n),
+               round_steps=np.zeros(n, np.int32), round_kkt=np.zeros(n), round_F=np.zeros(n))
+    P = dao_plan()
+    for k, a in arr.items():
+        setattr(P, k, _ptr(a, c_int32 if a.dtype == np.int32 else c_double))
+    return P, arr
+
+
+def _plan_dict(P, arr, st):
+    r = P.rounds
+    return dict(status=st, rounds=r, stop=P.stop, F=P.F, rc1=P.rc1, total_steps=P.total_steps,
+                total_ls_evals=P.total_ls_evals, price_s=P.price_s, master_s=P.master_s,
+                **{k: v[:r].copy() for k, v in arr.items()})
+
+
+def solve_batch(ctxs, n_apertures) -> list:
+    """dao_solve_batch over DaoContexts: one plan dict per context."""
+    lib = load_library()
+    n = len(ctxs)
+    H = (c_void_p * n)(*[c._h for c in ctxs])
+    na = np.ascontiguousarray(n_apertures, dtype=np.int32)
+    plans = (dao_plan * n)()
+    keep = []
+    for i in range(n):
+        P, arr = _plan_arrays(na[i])
+        plans[i] = P
+        keep.append(arr)
+    st = lib.dao_solve_batch(H, n, _ptr(na, c_int32), plans)
+    if st < 0:
+        raise DaoError(st, lib.dao_last_error(ctxs[0]._h).decode())
+    return [_plan_dict(plans[i], keep[i], int(plans[i].stop)) for i in range(n)]
 
 
 class DaoContext:

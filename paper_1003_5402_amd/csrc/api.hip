@@ -25,6 +25,7 @@ namespace {
 thread_local std::string g_create_error;
 
 constexpr size_t STAGE_LIMIT = 48 * 1024;   // largest vector staged in LDS per block
+constexpr int MAX_BATCH = 64;                // solves of one batched master launch
 constexpr int ELEM_BLOCKS_MAX = 2048;
 
 struct DevBuf {
@@ -82,6 +83,10 @@ struct dao_ctx {
     double* coop_recs = nullptr;       // [2][coop_grid][RECW]
     int coop_grid = 0;                 // co-resident workgroups (0: persistent master unavailable)
     int coop_lds_max = 0;              // dynamic LDS the on-chip variant may use (0: never)
+    void* batch_args = nullptr;        // [MAX_BATCH] CoopArgs of a batched master launch
+    int32_t* batch_gstart = nullptr;   // [MAX_BATCH + 1] first workgroup of each solve
+    void* batch_host = nullptr;        // pinned staging of both
+    bool batch_ok = false;             // the batched master launch is available
     ProfCounters* pc_h = nullptr;      // pinned
     int prof_kernel = -1;              // aperture-master kernel timed with events (-1: none)
     double prof_phase_us[PROF_PHASES] = {};   // persistent master split of the last window
@@ -123,6 +128,7 @@ struct dao_ctx {
         if (scalar_h) (void)hipHostFree(scalar_h);
         if (lv_stage_h) (void)hipHostFree(lv_stage_h);
         if (pc_h) (void)hipHostFree(pc_h);
+        if (batch_host) (void)hipHostFree(batch_host);
         for (auto e : prof_events) (void)hipEventDestroy(e);
     }
 
@@ -613,6 +619,21 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
                     c->coop_lds_max = want;
             }
             (void)hipGetLastError();
+            // the batched launch: same resources, both variants
+            int occ3 = 0, occ4 = 0;
+            c->batch_ok =
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &occ3, reinterpret_cast<const void*>(&k_master_batch<T, false>), COOP_THREADS, 0) == hipSuccess &&
+                occ3 >= 1;
+            if (c->batch_ok && c->coop_lds_max > 0 &&
+                !(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_master_batch<T, true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, c->coop_lds_max) == hipSuccess &&
+                  hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &occ4, reinterpret_cast<const void*>(&k_master_batch<T, true>), COOP_THREADS,
+                      c->coop_lds_max) == hipSuccess &&
+                  occ4 >= 1))
+                c->batch_ok = false;
+            (void)hipGetLastError();
             TRY(dev_alloc(c, &c->coop, sizeof(CoopSync)));
             TRY(dev_alloc(c, &c->coop_recs, 2 * size_t(c->coop_grid) * RECW * sizeof(double)));
         }
@@ -739,86 +760,264 @@ dao_status master_solve_typed(dao_ctx* c, double tol, int max_steps, int32_t* st
     return DAO_OK;
 }
 
-template <class T>
-dao_status solve_typed(dao_ctx* c, int32_t n_ap, dao_plan* out) {
-    dao_status s = reset_state<T>(c);
-    if (s != DAO_OK) return s;
-    double eps = c->opt.eps, rc1 = NAN;
-    int tighten = 0;
+// One column-generation solve, split into the steps around its master
+// solves so that several solves can share one master launch per round.
+using clk = std::chrono::steady_clock;
+inline double since(clk::time_point t0) { return std::chrono::duration<double>(clk::now() - t0).count(); }
+
+struct PlanRun {
+    dao_ctx* c = nullptr;
+    int32_t n_ap = 0;
+    dao_plan* out = nullptr;
+    double eps = 0.0, rc1 = NAN, tol = 0.0;
+    int tighten = 0, rounds = 0;
     int32_t stop = DAO_OK;
     int64_t steps0 = 0, ls0 = 0;
-    HIPCHK(c, hipMemcpyAsync(c->ms_h, c->ms, sizeof(MasterState), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    steps0 = c->ms_h->total_steps;
-    ls0 = c->ms_h->total_ls;
-    std::vector<int16_t> lv(2 * c->maxRB);
-    int rounds = 0;
-    using clk = std::chrono::steady_clock;
     double t_price = 0.0, t_master = 0.0;
-    auto since = [](clk::time_point t0) { return std::chrono::duration<double>(clk::now() - t0).count(); };
-    while (c->K < n_ap) {
-        int32_t beam;
-        double rc, gap;
-        const auto tp = clk::now();
-        s = price_current<T>(c, &beam, lv.data(), &rc, &gap);
-        if (s != DAO_OK) return s;
-        t_price += since(tp);
-        const auto tm = clk::now();
-        if (std::isnan(rc1)) {
-            rc1 = rc;
-            if (!(rc1 < 0.0)) {
-                stop = DAO_EOPTIMAL;
-                break;
-            }
-        }
-        const double scale = std::fabs(rc1);
-        if (rc >= -c->opt.tau_rel * scale) {
-            stop = DAO_EOPTIMAL;
-            break;
-        }
-        if (in_pool(c, beam, lv.data())) {
-            if (tighten >= c->opt.max_tighten) {
-                stop = DAO_ESTALLED;
-                break;
-            }
-            ++tighten;
-            eps /= 10.0;
-            s = run_master<T>(c, eps * scale, c->opt.max_steps);
-            if (s != DAO_OK) return s;
-            t_master += since(tm);
-            continue;
-        }
-        if (c->K >= c->opt.max_apertures) return c->fail(DAO_ESTATE, "pool capacity reached");
-        k_add_from_price<<<1, 256, 0, c->stream>>>(c->pr, c->K, c->maxRB, c->ap_beam, c->ap_lv, c->y);
-        LAUNCHCHK(c);
-        s = build_dk_column<T>(c, c->K);
-        if (s != DAO_OK) return s;
-        mirror_add(c, beam, lv.data());
-        c->K += 1;
-        s = run_master<T>(c, eps * scale, c->opt.max_steps);
-        if (s != DAO_OK) return s;
-        t_master += since(tm);
-        if (out) {
-            if (out->round_beam) out->round_beam[rounds] = beam;
-            if (out->round_rc) out->round_rc[rounds] = rc;
-            if (out->round_gap) out->round_gap[rounds] = gap;
-            if (out->round_steps) out->round_steps[rounds] = c->ms_h->steps;
-            if (out->round_kkt) out->round_kkt[rounds] = c->ms_h->kkt;
-            if (out->round_F) out->round_F[rounds] = c->ms_h->F;
-        }
-        ++rounds;
-    }
+    bool finished = false, added = false;
+    int32_t beam = 0;
+    double rc = 0.0, gap = 0.0;
+    std::vector<int16_t> lv;
+    clk::time_point tm;
+};
+
+template <class T>
+dao_status plan_start(PlanRun& r) {
+    dao_ctx* c = r.c;
+    dao_status s = reset_state<T>(c);
+    if (s != DAO_OK) return s;
+    r.eps = c->opt.eps;
     HIPCHK(c, hipMemcpyAsync(c->ms_h, c->ms, sizeof(MasterState), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (out) {
-        out->rounds = rounds;
-        out->stop = stop;
+    r.steps0 = c->ms_h->total_steps;
+    r.ls0 = c->ms_h->total_ls;
+    r.lv.assign(2 * c->maxRB, 0);
+    return DAO_OK;
+}
+
+// Pricing, entry test and column of the next round.  Either finishes the
+// solve (r.finished) or leaves a master solve to run to r.tol.
+template <class T>
+dao_status plan_round_begin(PlanRun& r) {
+    dao_ctx* c = r.c;
+    r.added = false;
+    if (c->K >= r.n_ap) {
+        r.finished = true;
+        return DAO_OK;
+    }
+    const auto tp = clk::now();
+    dao_status s = price_current<T>(c, &r.beam, r.lv.data(), &r.rc, &r.gap);
+    if (s != DAO_OK) return s;
+    r.t_price += since(tp);
+    r.tm = clk::now();
+    if (std::isnan(r.rc1)) {
+        r.rc1 = r.rc;
+        if (!(r.rc1 < 0.0)) {
+            r.stop = DAO_EOPTIMAL;
+            r.finished = true;
+            return DAO_OK;
+        }
+    }
+    const double scale = std::fabs(r.rc1);
+    if (r.rc >= -c->opt.tau_rel * scale) {
+        r.stop = DAO_EOPTIMAL;
+        r.finished = true;
+        return DAO_OK;
+    }
+    if (in_pool(c, r.beam, r.lv.data())) {
+        if (r.tighten >= c->opt.max_tighten) {
+            r.stop = DAO_ESTALLED;
+            r.finished = true;
+            return DAO_OK;
+        }
+        ++r.tighten;
+        r.eps /= 10.0;
+        r.tol = r.eps * scale;   // re-solve the same pool more tightly
+        return DAO_OK;
+    }
+    if (c->K >= c->opt.max_apertures) return c->fail(DAO_ESTATE, "pool capacity reached");
+    k_add_from_price<<<1, 256, 0, c->stream>>>(c->pr, c->K, c->maxRB, c->ap_beam, c->ap_lv, c->y);
+    LAUNCHCHK(c);
+    s = build_dk_column<T>(c, c->K);
+    if (s != DAO_OK) return s;
+    mirror_add(c, r.beam, r.lv.data());
+    c->K += 1;
+    r.added = true;
+    r.tol = r.eps * scale;
+    return DAO_OK;
+}
+
+// After the round's master solve (c->ms_h holds its final state).
+void plan_round_end(PlanRun& r) {
+    dao_ctx* c = r.c;
+    r.t_master += since(r.tm);
+    if (!r.added) return;
+    if (dao_plan* out = r.out) {
+        if (out->round_beam) out->round_beam[r.rounds] = r.beam;
+        if (out->round_rc) out->round_rc[r.rounds] = r.rc;
+        if (out->round_gap) out->round_gap[r.rounds] = r.gap;
+        if (out->round_steps) out->round_steps[r.rounds] = c->ms_h->steps;
+        if (out->round_kkt) out->round_kkt[r.rounds] = c->ms_h->kkt;
+        if (out->round_F) out->round_F[r.rounds] = c->ms_h->F;
+    }
+    ++r.rounds;
+}
+
+dao_status plan_finish(PlanRun& r) {
+    dao_ctx* c = r.c;
+    HIPCHK(c, hipMemcpyAsync(c->ms_h, c->ms, sizeof(MasterState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (dao_plan* out = r.out) {
+        out->rounds = r.rounds;
+        out->stop = r.stop;
         out->F = c->ms_h->F;
-        out->rc1 = rc1;
-        out->total_steps = c->ms_h->total_steps - steps0;
-        out->total_ls_evals = c->ms_h->total_ls - ls0;
-        out->price_s = t_price;
-        out->master_s = t_master;
+        out->rc1 = r.rc1;
+        out->total_steps = c->ms_h->total_steps - r.steps0;
+        out->total_ls_evals = c->ms_h->total_ls - r.ls0;
+        out->price_s = r.t_price;
+        out->master_s = r.t_master;
+    }
+    return DAO_OK;
+}
+
+template <class T>
+dao_status solve_typed(dao_ctx* c, int32_t n_ap, dao_plan* out) {
+    PlanRun r;
+    r.c = c;
+    r.n_ap = n_ap;
+    r.out = out;
+    dao_status s = plan_start<T>(r);
+    if (s != DAO_OK) return s;
+    for (;;) {
+        s = plan_round_begin<T>(r);
+        if (s != DAO_OK) return s;
+        if (r.finished) break;
+        s = run_master<T>(c, r.tol, c->opt.max_steps);
+        if (s != DAO_OK) return s;
+        plan_round_end(r);
+    }
+    return plan_finish(r);
+}
+
+// The round's master solves of several contexts in one cooperative launch of
+// k_master_batch (when all use the persistent master on one stream; else one
+// after another).  Workgroups are shared out in proportion to the solves'
+// voxel rows, at least one each.
+template <class T>
+dao_status run_master_batch(std::vector<PlanRun*>& live) {
+    dao_ctx* c0 = live[0]->c;
+    bool together = live.size() > 1 && int(live.size()) <= std::min(MAX_BATCH, c0->coop_grid);
+    for (PlanRun* r : live)
+        together = together && r->c->coop_master() && r->c->batch_ok && r->c->stream == c0->stream &&
+                   r->c->coop_grid == c0->coop_grid && r->c->prof_kernel < 0;
+    if (!together) {
+        for (PlanRun* r : live) {
+            dao_status s = run_master<T>(r->c, r->tol, r->c->opt.max_steps);
+            if (s != DAO_OK) return s;
+        }
+        return DAO_OK;
+    }
+    const int n = int(live.size()), G = c0->coop_grid;
+    if (!c0->batch_args) {
+        dao_status s = dev_alloc(c0, &c0->batch_args, size_t(MAX_BATCH) * sizeof(CoopArgs<double>));
+        if (s != DAO_OK) return s;
+        s = dev_alloc(c0, &c0->batch_gstart, size_t(MAX_BATCH + 1) * sizeof(int32_t));
+        if (s != DAO_OK) return s;
+        HIPCHK(c0, hipHostMalloc(&c0->batch_host, size_t(MAX_BATCH) * sizeof(CoopArgs<double>) +
+                                                    size_t(MAX_BATCH + 1) * sizeof(int32_t), hipHostMallocDefault));
+    }
+    // workgroups in proportion to the rows
+    double tot = 0.0;
+    for (PlanRun* r : live) tot += double(r->c->Vpad);
+    std::vector<int> g(n);
+    int used = 0;
+    for (int i = 0; i < n; ++i) {
+        g[i] = std::max(1, int(double(G) * double(live[i]->c->Vpad) / tot));
+        used += g[i];
+    }
+    while (used > G)   // take back from the largest shares
+        for (int i = 0; i < n && used > G; ++i)
+            if (g[i] > 1 && g[i] == *std::max_element(g.begin(), g.end())) {
+                --g[i];
+                --used;
+            }
+    for (int i = 0; used < G; i = (i + 1) % n) {   // hand out what is left
+        ++g[i];
+        ++used;
+    }
+    auto* hargs = reinterpret_cast<CoopArgs<T>*>(c0->batch_host);
+    auto* hstart = reinterpret_cast<int32_t*>(static_cast<char*>(c0->batch_host) +
+                                              size_t(MAX_BATCH) * sizeof(CoopArgs<double>));
+    size_t lds = 0;
+    bool fits = c0->opt.persistent == 2 && c0->coop_lds_max > 0;
+    hstart[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        dao_ctx* c = live[i]->c;
+        k_master_init_ap<<<1, 1, 0, c->stream>>>(c->ms, c->K, live[i]->tol, c->opt.max_steps);
+        LAUNCHCHK(c);
+        HIPCHK(c, hipMemsetAsync(c->coop, 0, sizeof(CoopSync), c->stream));
+        hargs[i] = CoopArgs<T>{static_cast<const T*>(c->dk), c->Vpad, c->Vnz, c->d, static_cast<T*>(c->q), c->cls_int,
+                               c->classes, c->ncls, c->y, c->p, c->gradk, c->ms, c->coop_recs, c->coop, c->pc, 0};
+        hstart[i + 1] = hstart[i] + g[i];
+        const int nc = (c->K + DKG<T>::EPL - 1) / DKG<T>::EPL;
+        const size_t li = coop_lds_bytes<T>(coop_batches_per_group<T>(c->Vpad, g[i]) * Batch<T>::ROWS, nc);
+        lds = std::max(lds, li);
+        fits = fits && c->opt.persistent == 2 && li <= size_t(c0->coop_lds_max);
+    }
+    HIPCHK(c0, hipMemcpyAsync(c0->batch_args, hargs, size_t(n) * sizeof(CoopArgs<T>), hipMemcpyHostToDevice,
+                              c0->stream));
+    HIPCHK(c0, hipMemcpyAsync(c0->batch_gstart, hstart, size_t(n + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
+                              c0->stream));
+    const CoopArgs<T>* dargs = static_cast<const CoopArgs<T>*>(c0->batch_args);
+    const int32_t* dstart = c0->batch_gstart;
+    int nn = n;
+    void* kargs[] = {&dargs, &dstart, &nn};
+    if (fits)
+        HIPCHK(c0, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_batch<T, true>), dim3(G),
+                                              dim3(COOP_THREADS), kargs, lds, c0->stream));
+    else
+        HIPCHK(c0, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_batch<T, false>), dim3(G),
+                                              dim3(COOP_THREADS), kargs, 0, c0->stream));
+    for (PlanRun* r : live)
+        HIPCHK(r->c, hipMemcpyAsync(r->c->ms_h, r->c->ms, sizeof(MasterState), hipMemcpyDeviceToHost, r->c->stream));
+    HIPCHK(c0, hipStreamSynchronize(c0->stream));
+    for (PlanRun* r : live) {
+        if (r->c->ms_h->stop_reason == 4 || !r->c->ms_h->done)
+            return r->c->fail(DAO_EDEVICE, "batched persistent master: grid reduction timed out");
+        r->c->last_steps = r->c->ms_h->steps;
+    }
+    return DAO_OK;
+}
+
+// Several solves advanced round by round together: each round prices every
+// live solve, adds its column, then runs all their master solves in one
+// launch.  A solve leaves the batch when it finishes.
+template <class T>
+dao_status solve_batch_typed(dao_ctx* const* ctxs, int n, const int32_t* n_ap, dao_plan* outs) {
+    std::vector<PlanRun> runs(n);
+    for (int i = 0; i < n; ++i) {
+        runs[i].c = ctxs[i];
+        runs[i].n_ap = n_ap[i];
+        runs[i].out = outs ? &outs[i] : nullptr;
+        dao_status s = plan_start<T>(runs[i]);
+        if (s != DAO_OK) return s;
+    }
+    for (;;) {
+        std::vector<PlanRun*> live;
+        for (PlanRun& r : runs) {
+            if (r.finished) continue;
+            dao_status s = plan_round_begin<T>(r);
+            if (s != DAO_OK) return s;
+            if (!r.finished) live.push_back(&r);
+        }
+        if (live.empty()) break;
+        dao_status s = run_master_batch<T>(live);
+        if (s != DAO_OK) return s;
+        for (PlanRun* r : live) plan_round_end(*r);
+    }
+    for (PlanRun& r : runs) {
+        dao_status s = plan_finish(r);
+        if (s != DAO_OK) return s;
     }
     return DAO_OK;
 }
@@ -1123,6 +1322,20 @@ dao_status dao_profile_stop(dao_ctx* c, int64_t* launches, int64_t* working_laun
     c->prof_kernel = -1;
     c->prof_used = 0;
     return DAO_OK;
+}
+
+dao_status dao_solve_batch(dao_ctx* const* ctxs, int32_t n, const int32_t* n_apertures, dao_plan* plans) {
+    if (!ctxs || !n_apertures || n < 1 || n > MAX_BATCH) return DAO_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) return DAO_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return ctxs[i]->fail(DAO_EINVAL, "a context appears twice in the batch");
+        if (ctxs[i]->dtype != ctxs[0]->dtype) return ctxs[i]->fail(DAO_EINVAL, "contexts of one batch share the dtype");
+        if (n_apertures[i] < 0 || n_apertures[i] > ctxs[i]->opt.max_apertures)
+            return ctxs[i]->fail(DAO_EINVAL, "n_apertures must be in [0, max_apertures]");
+    }
+    return ctxs[0]->dtype == DAO_F64 ? solve_batch_typed<double>(ctxs, n, n_apertures, plans)
+                                     : solve_batch_typed<float>(ctxs, n, n_apertures, plans);
 }
 
 dao_status dao_solve(dao_ctx* c, int32_t n_apertures, dao_plan* out) {

@@ -187,16 +187,16 @@ __device__ __forceinline__ void combine_fields(const double* buf, uint32_t nb, i
     __syncthreads();
 }
 
-// Grid-wide fixed-order reduction of W-double records (all threads of every
-// workgroup call it).  recs: two field-major buffers of gridDim.x records;
+// Grid-wide fixed-order reduction of W-double records over the nb workgroups
+// of one solve (all their threads call it; b is this workgroup's index among
+// them).  recs: two field-major buffers of nb records;
 // mine: this workgroup's record (LDS); total: result (LDS, every workgroup);
 // seq: this workgroup's count of reductions so far.  Returns false when the
 // grid aborted.
 template <bool LS>
 __device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W, double* total,
-                            uint32_t& seq) {
+                            uint32_t& seq, uint32_t b, uint32_t nb) {
     __shared__ int s_ok;
-    const uint32_t nb = gridDim.x, b = blockIdx.x;
     seq += 1;
     double* buf = recs + size_t(seq & 1u) * nb * RECW;
     for (int i = threadIdx.x; i < W; i += blockDim.x) astore(&buf[size_t(i) * nb + b], mine[i]);
@@ -250,7 +250,7 @@ struct CoopArgs {
     double* p;          // out: last direction (workgroup 0)
     double* grad;       // out: last grad_y (workgroup 0)
     MasterState* ms;    // in: state set by k_master_init_ap; out: final state (workgroup 0)
-    double* recs;       // [2][gridDim.x][RECW]
+    double* recs;       // [2][workgroups of the solve][RECW]
     CoopSync* sync;
     ProfCounters* pc;
     int timing;         // workgroup 0 accumulates per-phase wall-clock ticks in pc->ticks
@@ -275,7 +275,7 @@ __host__ __device__ inline size_t coop_lds_bytes(int64_t rows, int nc) {
 // LDS once per solve and every pass reads on-chip memory; d is written back
 // at the end.  Otherwise the passes stream them from global memory.
 template <class T, bool LDSRES>
-__global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
+__device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t gb, const uint32_t gn) {
     using G = DKG<T>;
     using V = typename Vec16<T>::type;
     constexpr int IT = Batch<T>::ITERS, ROWS = Batch<T>::ROWS;
@@ -306,8 +306,8 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
     const int nc = (K + G::EPL - 1) / G::EPL;
     // this workgroup's batches of ROWS rows
     const int64_t nbat = A.Vpad / ROWS;
-    const int64_t per = coop_batches_per_group<T>(A.Vpad, gridDim.x);
-    const int64_t bat0 = min(nbat, int64_t(blockIdx.x) * per), bat1 = min(nbat, bat0 + per);
+    const int64_t per = coop_batches_per_group<T>(A.Vpad, gn);
+    const int64_t bat0 = min(nbat, int64_t(gb) * per), bat1 = min(nbat, bat0 + per);
     const int64_t r0 = bat0 * ROWS, nrows = (bat1 - bat0) * ROWS;
     // on-chip copies (LDSRES)
     V* dkl = reinterpret_cast<V*>(dyn);
@@ -354,7 +354,7 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
     // 5 final decision + step, 6 later line-search passes (with the decision
     // that asked for them)
     __shared__ uint64_t s_tk[PROF_PHASES], s_t0;
-    const bool timer = A.timing && blockIdx.x == 0 && threadIdx.x == 0;
+    const bool timer = A.timing && gb == 0 && threadIdx.x == 0;
     if (timer) {
         for (int i = 0; i < PROF_PHASES; ++i) s_tk[i] = 0;
         s_t0 = wall_clock64();
@@ -446,14 +446,14 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
             if (lane == 0) s_acc[wave][0] = Fp;
             __syncthreads();
             combine_waves8(&s_acc[0][0], RECW, K + 1, false, s_rec);
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (gb == 0 && threadIdx.x == 0) {
                 const double per_row = 16.0 * nc + 1.0 + (mode != 1 ? 8.0 : 0.0) +
                                        (mode == 0 ? double(sizeof(T)) : 0.0) + (mode != 2 ? 8.0 : 0.0);
                 cnt_bytes[0] += per_row * double(A.Vnz);
                 cnt_real[0] += 1;
             }
             tick(0);
-            if (!grid_reduce<false>(A.sync, A.recs, s_rec, K + 1, s_tot, seq)) {
+            if (!grid_reduce<false>(A.sync, A.recs, s_rec, K + 1, s_tot, seq, gb, gn)) {
                 alive = false;
                 break;
             }
@@ -596,14 +596,14 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
                 }
             }
             block_rec_dpp(r, s_rec);
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (gb == 0 && threadIdx.x == 0) {
                 const int kk = first ? 1 : 2;
                 cnt_bytes[kk] += (first ? (16.0 * nc + 8.0 + 1.0 + double(sizeof(T)))
                                           : (8.0 + double(sizeof(T)) + 1.0)) * double(A.Vnz);
                 cnt_real[kk] += 1;
             }
             tick(first ? 3 : 6);
-            if (!grid_reduce<true>(A.sync, A.recs, s_rec, 6, s_tot, seq)) {
+            if (!grid_reduce<true>(A.sync, A.recs, s_rec, 6, s_tot, seq, gb, gn)) {
                 alive = false;
                 break;
             }
@@ -650,13 +650,13 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
     }
     if (timer)
         for (int i = 0; i < PROF_PHASES; ++i) A.pc->ticks[i] += s_tk[i];
-    if (blockIdx.x == 0 && threadIdx.x == 0)
+    if (gb == 0 && threadIdx.x == 0)
         for (int i = 0; i < 3; ++i) {
             A.pc->bytes[i] += cnt_bytes[i];
             A.pc->real[i] += cnt_real[i];
         }
     // workgroup 0 publishes the final state
-    if (blockIdx.x == 0) {
+    if (gb == 0) {
         if (threadIdx.x < K) {
             A.y[threadIdx.x] = s_y[threadIdx.x];
             A.p[threadIdx.x] = s_p[threadIdx.x];
@@ -665,6 +665,33 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
         if (threadIdx.x == 0 && !alive) s_ms.stop_reason = 4;
         ms_store(A.ms, s_ms);
     }
+}
+
+// One master solve per launch: every workgroup of the grid works on it.
+template <class T, bool LDSRES>
+__global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
+    master_body<T, LDSRES>(A, blockIdx.x, gridDim.x);
+}
+
+// Several master solves in one cooperative launch: solve i gets workgroups
+// [gstart[i], gstart[i + 1]) and runs exactly as k_master_coop would on a grid
+// of that size; solves never wait for each other, and the launch ends when
+// the last one has converged.
+template <class T, bool LDSRES>
+__global__ void __launch_bounds__(COOP_THREADS) k_master_batch(const CoopArgs<T>* __restrict__ args,
+                                                               const int32_t* __restrict__ gstart, int nsolves) {
+    __shared__ int s_i;
+    if (threadIdx.x == 0) {
+        int i = 0;
+        while (i + 1 < nsolves && int(blockIdx.x) >= gstart[i + 1]) ++i;
+        s_i = i;
+    }
+    __syncthreads();
+    const int i = s_i;
+    const uint32_t g0 = uint32_t(gstart[i]), g1 = uint32_t(gstart[i + 1]);
+    if (blockIdx.x >= g1) return;   // workgroups past the last solve (none when the host fills the grid)
+    const CoopArgs<T> A = args[i];
+    master_body<T, LDSRES>(A, blockIdx.x - g0, g1 - g0);
 }
 
 }  // namespace dao
