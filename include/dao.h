@@ -307,6 +307,42 @@ dao_status dao_solve(dao_ctx* ctx, int32_t n_apertures, dao_plan* out);
  * solve i's log (may be NULL); the return is DAO_OK or the first error. */
 dao_status dao_solve_batch(dao_ctx* const* ctxs, int32_t n, const int32_t* n_apertures, dao_plan* plans);
 
+/* Serving loop (continuous batching).  Requests are queued in arrival order;
+ * each dao_server_step admits queued requests while fewer than max_live
+ * solves are live and their contexts fit under hbm_cap_bytes (0: no cap; a
+ * context is created at admission with the remaining room as its
+ * mem_cap_bytes, so the oldest request waits until enough memory is freed,
+ * or fails with DAO_ENOMEM if it cannot fit even alone), then advances every
+ * live solve by one column-generation round, their master solves sharing one
+ * launch as in dao_solve_batch.  A solve that stops is retired at once: its
+ * context (dose matrix, dose, master state) is destroyed and its result is
+ * kept for dao_server_poll.  Each result is the plan dao_solve gives for the
+ * same request up to the order of floating-point sums.  The host arrays of
+ * a request must stay valid until its ticket is admitted.  All work runs on
+ * `stream`.  Not thread-safe. */
+typedef struct dao_server dao_server;
+typedef struct {
+    int32_t max_live;        /* solves advanced together, 1..64 */
+    int64_t hbm_cap_bytes;   /* device bytes of the live contexts; 0 = no cap */
+} dao_server_options;
+dao_status dao_server_create(const dao_server_options* opt, void* stream, dao_server** out);
+void dao_server_destroy(dao_server* srv);
+/* Queue one request (dao_solve of n_apertures on these inputs and options,
+ * NULL options = defaults); *ticket identifies it. */
+dao_status dao_server_submit(dao_server* srv, const dao_matrix* D, const dao_beams* beams,
+                             const dao_structures* structs, const dao_prescription* presc,
+                             const dao_options* opt, int32_t n_apertures, int64_t* ticket);
+/* Admit, then one round of every live solve.  *n_live: live solves after the
+ * step; *n_done: solves retired in it.  A device error ends every live solve
+ * with that error and is returned. */
+dao_status dao_server_step(dao_server* srv, int32_t* n_live, int32_t* n_done);
+/* *state: 0 queued, 1 live, 2 done.  When done, fills *out (arrays as in
+ * dao_solve, may be NULL), forgets the ticket and returns the solve's status
+ * (DAO_OK, DAO_EOPTIMAL, DAO_ESTALLED or an error).  DAO_EINVAL for an unknown
+ * or already collected ticket. */
+dao_status dao_server_poll(dao_server* srv, int64_t ticket, int32_t* state, dao_plan* out);
+dao_status dao_server_info(const dao_server* srv, int32_t* queued, int32_t* live, int64_t* used_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,6 +59,10 @@ class dao_info_t(ctypes.Structure):
                 ("bytes_dose", c_int64), ("bytes_gradient", c_int64)]
 
 
+class dao_server_options(ctypes.Structure):
+    _fields_ = [("max_live", c_int32), ("hbm_cap_bytes", c_int64)]
+
+
 class dao_plan(ctypes.Structure):
     _fields_ = [("rounds", c_int32), ("stop", c_int32), ("F", c_double), ("rc1", c_double),
                 ("total_steps", c_int64), ("total_ls_evals", c_int64),
@@ -93,6 +97,13 @@ _SIGS = {
     "dao_get_dose": (c_int32, [c_void_p, c_void_p, POINTER(c_double)]),
     "dao_solve": (c_int32, [c_void_p, c_int32, POINTER(dao_plan)]),
     "dao_solve_batch": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_int32), POINTER(dao_plan)]),
+    "dao_server_create": (c_int32, [c_void_p, c_void_p, POINTER(c_void_p)]),
+    "dao_server_destroy": (None, [c_void_p]),
+    "dao_server_submit": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
+                                    POINTER(c_int64)]),
+    "dao_server_step": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    "dao_server_poll": (c_int32, [c_void_p, c_int64, POINTER(c_int32), POINTER(dao_plan)]),
+    "dao_server_info": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int64)]),
     "dao_time_product": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double)]),
     "dao_profile_phases": (c_int32, [c_void_p, POINTER(c_double)]),
     "dao_encode_values": (c_int32, [c_int32, c_int64, POINTER(c_double), POINTER(ctypes.c_uint16),
@@ -371,3 +382,88 @@ class DaoContext:
         return dict(status=st, rounds=r, stop=P.stop, F=P.F, rc1=P.rc1, total_steps=P.total_steps,
                     total_ls_evals=P.total_ls_evals, price_s=P.price_s, master_s=P.master_s,
                     **{k: v[:r].copy() for k, v in arr.items()})
+
+
+class Server:
+    """The library's serving loop (dao_server_*): queue requests, step rounds,
+    poll results.  Keeps each request's host arrays alive until it is done."""
+
+    def __init__(self, max_live: int = 8, hbm_cap_bytes: int = 0, stream: int = 0):
+        self._lib = load_library()
+        o = dao_server_options(int(max_live), int(hbm_cap_bytes))
+        h = c_void_p()
+        st = self._lib.dao_server_create(byref(o), c_void_p(stream), byref(h))
+        if st != DAO_OK:
+            raise DaoError(st, "dao_server_create rejected its options")
+        self._h = h
+        self._keep = {}
+        self._n_ap = {}
+
+    def submit(self, ph, n_apertures: int, dtype: Optional[str] = None, **opts) -> int:
+        rp = np.ascontiguousarray(ph.row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(ph.col, dtype=np.int32)
+        vl = np.ascontiguousarray(ph.val, dtype=np.float64)
+        rpb = np.ascontiguousarray(ph.rows_per_beam, dtype=np.int32)
+        rl = np.ascontiguousarray(ph.row_len, dtype=np.int32)
+        vs = np.ascontiguousarray(ph.vox_struct, dtype=np.int16)
+        M = dao_matrix(rp.shape[0] - 1, int(ph.n_blt), cl.shape[0], _ptr(rp, c_int64), _ptr(cl, c_int32),
+                       _ptr(vl, c_double))
+        Bm = dao_beams(rpb.shape[0], _ptr(rpb, c_int32), _ptr(rl, c_int32))
+        S = dao_structures(len(ph.prescriptions), _ptr(vs, c_int16))
+        PA = (dao_prescription * max(1, len(ph.prescriptions)))()
+        for i, p in enumerate(ph.prescriptions):
+            PA[i] = dao_prescription(int(p["is_target"]), p["t_under"], p["t_over"], p["w_under"], p["w_over"])
+        O = dao_options()
+        self._lib.dao_default_options(byref(O))
+        O.dtype = DAO_F64 if (dtype or ph.dtype) == "f64" else DAO_F32
+        names = {f for f, _ in dao_options._fields_}
+        for k, v in opts.items():
+            if k not in names:
+                raise TypeError(f"unknown option {k!r}")
+            setattr(O, k, v)
+        t = c_int64()
+        st = self._lib.dao_server_submit(self._h, byref(M), byref(Bm), byref(S), PA, byref(O), int(n_apertures),
+                                         byref(t))
+        if st != DAO_OK:
+            raise DaoError(st, "dao_server_submit rejected the request")
+        self._keep[t.value] = (rp, cl, vl, rpb, rl, vs, M, Bm, S, PA, O)
+        self._n_ap[t.value] = int(n_apertures)
+        return t.value
+
+    def step(self):
+        nl, nd = c_int32(), c_int32()
+        st = self._lib.dao_server_step(self._h, byref(nl), byref(nd))
+        if st < 0:
+            raise DaoError(st, "dao_server_step failed")
+        return nl.value, nd.value
+
+    def poll(self, ticket: int):
+        """(state, plan dict or None): state 0 queued, 1 live, 2 done."""
+        P, arr = _plan_arrays(self._n_ap.get(ticket, 1))
+        state = c_int32()
+        st = self._lib.dao_server_poll(self._h, int(ticket), byref(state), byref(P))
+        if state.value != 2:
+            if st < 0:
+                raise DaoError(st, "unknown ticket")
+            return state.value, None
+        self._keep.pop(ticket, None)
+        self._n_ap.pop(ticket, None)
+        return 2, _plan_dict(P, arr, int(st))
+
+    def info(self):
+        q, l, u = c_int32(), c_int32(), c_int64()
+        self._lib.dao_server_info(self._h, byref(q), byref(l), byref(u))
+        return dict(queued=q.value, live=l.value, used_bytes=u.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.dao_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

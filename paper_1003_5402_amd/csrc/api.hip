@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <deque>
+#include <map>
 #include <type_traits>
 #include <cmath>
 #include <cstring>
@@ -1349,3 +1351,236 @@ dao_status dao_solve(dao_ctx* c, int32_t n_apertures, dao_plan* out) {
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Serving loop: continuous batching of solves under a device-memory cap
+// ===========================================================================
+struct dao_server {
+    hipStream_t stream = nullptr;
+    int max_live = 8;
+    int64_t cap = 0;     // 0: no cap
+    int64_t used = 0;    // device bytes of the live contexts
+    struct Req {
+        const dao_matrix* D;
+        const dao_beams* B;
+        const dao_structures* S;
+        const dao_prescription* P;
+        dao_options opt;
+        int32_t n_ap;
+        int64_t ticket;
+    };
+    struct Result {
+        dao_status status = DAO_OK;
+        dao_plan plan{};
+        std::vector<int32_t> beam, steps;
+        std::vector<double> rc, gap, kkt, F;
+        std::string error;
+    };
+    struct Live {
+        dao_ctx* c = nullptr;
+        PlanRun run;
+        int64_t ticket = 0;
+        int64_t bytes = 0;
+    };
+    std::deque<Req> queue;
+    std::vector<std::unique_ptr<Live>> live;
+    std::map<int64_t, Result> done;
+    std::map<int64_t, Result> running;   // results being filled by live solves
+    int64_t next_ticket = 0;
+    std::string error;
+};
+
+namespace {
+
+void server_retire(dao_server* sv, size_t i, dao_status st, const char* why) {
+    dao_server::Live& L = *sv->live[i];
+    auto it = sv->running.find(L.ticket);
+    dao_server::Result r = std::move(it->second);
+    sv->running.erase(it);
+    r.status = st == DAO_OK ? dao_status(L.run.stop) : st;
+    if (why) r.error = why;
+    // the arrays moved with the result: point the summary at them again
+    r.plan.round_beam = r.beam.data();
+    r.plan.round_steps = r.steps.data();
+    r.plan.round_rc = r.rc.data();
+    r.plan.round_gap = r.gap.data();
+    r.plan.round_kkt = r.kkt.data();
+    r.plan.round_F = r.F.data();
+    sv->done[L.ticket] = std::move(r);
+    sv->used -= L.bytes;
+    dao_destroy(L.c);
+    sv->live.erase(sv->live.begin() + long(i));
+}
+
+// Admit queued requests (first come, first served) while slots and memory allow.
+void server_admit(dao_server* sv) {
+    while (!sv->queue.empty() && int(sv->live.size()) < sv->max_live) {
+        dao_server::Req q = sv->queue.front();
+        dao_options o = q.opt;
+        if (sv->cap > 0) {
+            const int64_t room = sv->cap - sv->used;
+            if (room <= 0) break;
+            o.mem_cap_bytes = o.mem_cap_bytes > 0 ? std::min(o.mem_cap_bytes, room) : room;
+        }
+        dao_ctx* c = nullptr;
+        const dao_status st = dao_create(q.D, q.B, q.S, q.P, &o, sv->stream, &c);
+        if (st == DAO_ENOMEM && !sv->live.empty()) break;   // wait for memory to free up
+        sv->queue.pop_front();
+        dao_server::Result r;
+        if (st != DAO_OK) {
+            r.status = st;
+            r.error = dao_create_error();
+            sv->done[q.ticket] = std::move(r);
+            continue;
+        }
+        const int n = std::max(1, int(q.n_ap));
+        r.beam.assign(n, 0);
+        r.steps.assign(n, 0);
+        r.rc.assign(n, 0.0);
+        r.gap.assign(n, 0.0);
+        r.kkt.assign(n, 0.0);
+        r.F.assign(n, 0.0);
+        sv->running[q.ticket] = std::move(r);
+        dao_server::Result& rr = sv->running[q.ticket];
+        rr.plan.round_beam = rr.beam.data();
+        rr.plan.round_steps = rr.steps.data();
+        rr.plan.round_rc = rr.rc.data();
+        rr.plan.round_gap = rr.gap.data();
+        rr.plan.round_kkt = rr.kkt.data();
+        rr.plan.round_F = rr.F.data();
+        auto L = std::make_unique<dao_server::Live>();
+        L->c = c;
+        L->ticket = q.ticket;
+        L->bytes = c->device_bytes;
+        L->run.c = c;
+        L->run.n_ap = std::min(q.n_ap, c->opt.max_apertures);
+        L->run.out = &rr.plan;
+        const dao_status s2 = c->dtype == DAO_F64 ? plan_start<double>(L->run) : plan_start<float>(L->run);
+        sv->used += L->bytes;
+        sv->live.push_back(std::move(L));
+        if (s2 != DAO_OK) server_retire(sv, sv->live.size() - 1, s2, c->err.c_str());
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+dao_status dao_server_create(const dao_server_options* o, void* stream, dao_server** out) {
+    if (!out || !o || o->max_live < 1 || o->max_live > MAX_BATCH || o->hbm_cap_bytes < 0) return DAO_EINVAL;
+    auto* sv = new dao_server();
+    sv->stream = static_cast<hipStream_t>(stream);
+    sv->max_live = o->max_live;
+    sv->cap = o->hbm_cap_bytes;
+    *out = sv;
+    return DAO_OK;
+}
+
+void dao_server_destroy(dao_server* sv) {
+    if (!sv) return;
+    while (!sv->live.empty()) server_retire(sv, sv->live.size() - 1, DAO_ESTATE, "server destroyed");
+    delete sv;
+}
+
+dao_status dao_server_submit(dao_server* sv, const dao_matrix* D, const dao_beams* beams, const dao_structures* structs,
+                             const dao_prescription* presc, const dao_options* opt, int32_t n_apertures,
+                             int64_t* ticket) {
+    if (!sv || !D || !beams || !structs || !ticket || n_apertures < 0) return DAO_EINVAL;
+    dao_server::Req q{D, beams, structs, presc, {}, n_apertures, sv->next_ticket++};
+    if (opt)
+        q.opt = *opt;
+    else
+        dao_default_options(&q.opt);
+    sv->queue.push_back(q);
+    *ticket = q.ticket;
+    return DAO_OK;
+}
+
+dao_status dao_server_step(dao_server* sv, int32_t* n_live, int32_t* n_done) {
+    if (!sv) return DAO_EINVAL;
+    server_admit(sv);
+    int finished = 0;
+    // round begin for every live solve
+    std::vector<PlanRun*> need32, need64;
+    for (size_t i = 0; i < sv->live.size();) {
+        dao_server::Live& L = *sv->live[i];
+        const dao_status s = L.c->dtype == DAO_F64 ? plan_round_begin<double>(L.run) : plan_round_begin<float>(L.run);
+        if (s != DAO_OK) {
+            server_retire(sv, i, s, L.c->err.c_str());
+            ++finished;
+            continue;
+        }
+        if (L.run.finished) {
+            const dao_status f = plan_finish(L.run);
+            server_retire(sv, i, f, nullptr);
+            ++finished;
+            continue;
+        }
+        (L.c->dtype == DAO_F64 ? need64 : need32).push_back(&L.run);
+        ++i;
+    }
+    dao_status s = DAO_OK;
+    if (!need32.empty()) s = run_master_batch<float>(need32);
+    if (s == DAO_OK && !need64.empty()) s = run_master_batch<double>(need64);
+    if (s != DAO_OK) {
+        // a device error: every live solve ends with it
+        while (!sv->live.empty()) server_retire(sv, sv->live.size() - 1, s, "master launch failed");
+        if (n_live) *n_live = 0;
+        if (n_done) *n_done = finished;
+        return s;
+    }
+    for (auto& L : sv->live) plan_round_end(L->run);
+    if (n_live) *n_live = int32_t(sv->live.size());
+    if (n_done) *n_done = finished;
+    return DAO_OK;
+}
+
+dao_status dao_server_poll(dao_server* sv, int64_t ticket, int32_t* state, dao_plan* out) {
+    if (!sv || !state) return DAO_EINVAL;
+    auto it = sv->done.find(ticket);
+    if (it == sv->done.end()) {
+        if (sv->running.count(ticket)) {
+            *state = 1;
+            return DAO_OK;
+        }
+        for (const auto& q : sv->queue)
+            if (q.ticket == ticket) {
+                *state = 0;
+                return DAO_OK;
+            }
+        return DAO_EINVAL;   // unknown or already collected
+    }
+    *state = 2;
+    const dao_server::Result& r = it->second;
+    if (out) {
+        const int n = r.plan.rounds;
+        out->rounds = r.plan.rounds;
+        out->stop = r.plan.stop;
+        out->F = r.plan.F;
+        out->rc1 = r.plan.rc1;
+        out->total_steps = r.plan.total_steps;
+        out->total_ls_evals = r.plan.total_ls_evals;
+        out->price_s = r.plan.price_s;
+        out->master_s = r.plan.master_s;
+        if (out->round_beam) std::copy(r.beam.begin(), r.beam.begin() + n, out->round_beam);
+        if (out->round_steps) std::copy(r.steps.begin(), r.steps.begin() + n, out->round_steps);
+        if (out->round_rc) std::copy(r.rc.begin(), r.rc.begin() + n, out->round_rc);
+        if (out->round_gap) std::copy(r.gap.begin(), r.gap.begin() + n, out->round_gap);
+        if (out->round_kkt) std::copy(r.kkt.begin(), r.kkt.begin() + n, out->round_kkt);
+        if (out->round_F) std::copy(r.F.begin(), r.F.begin() + n, out->round_F);
+    }
+    const dao_status st = r.status;
+    sv->done.erase(it);
+    return st;
+}
+
+dao_status dao_server_info(const dao_server* sv, int32_t* queued, int32_t* live, int64_t* used_bytes) {
+    if (!sv) return DAO_EINVAL;
+    if (queued) *queued = int32_t(sv->queue.size());
+    if (live) *live = int32_t(sv->live.size());
+    if (used_bytes) *used_bytes = sv->used;
+    return DAO_OK;
+}
+
+}  // extern "C"
+

@@ -1,0 +1,83 @@
+"""The serving loop (dao_server_*): requests admitted as slots and memory
+free up, rounds of all live solves advanced together, each result the plan
+its solo dao_solve gives (same round beams and reduced costs; F within 1e-9
+in FP64, 1e-5 in FP32, as for dao_solve_batch)."""
+import numpy as np
+import pytest
+
+import paper_1003_5402_amd as dao
+from gpu_util import ctx_for, torch_cuda
+from phantom import make_phantom
+
+pytestmark = pytest.mark.gpu
+
+REQS = [("mini", 0, "f64", 5), ("tiny", 0, "f32", 6), ("tiny", 1, "f32", 4), ("mini", 1, "f32", 6),
+        ("tiny", 2, "f64", 5)]
+
+
+def _alone(ph, dtype, n_ap):
+    ctx = ctx_for(ph, dtype=dtype)
+    try:
+        return ctx.solve(n_ap), ctx.info()["device_bytes"]
+    finally:
+        ctx.close()
+
+
+def _run(server, reqs, phs):
+    tickets = [server.submit(ph, n, dtype=dt) for (_, _, dt, n), ph in zip(reqs, phs)]
+    results, max_live, max_used = {}, 0, 0
+    for _ in range(10000):
+        live, _done = server.step()
+        info = server.info()
+        max_live, max_used = max(max_live, live), max(max_used, info["used_bytes"])
+        for t in tickets:
+            if t not in results:
+                state, plan = server.poll(t)
+                if state == 2:
+                    results[t] = plan
+        if len(results) == len(tickets):
+            break
+    return [results[t] for t in tickets], max_live, max_used
+
+
+def test_serving_results_equal_solo_solves():
+    torch = torch_cuda()
+    phs = [make_phantom(n, s) for n, s, _, _ in REQS]
+    solo = [_alone(ph, dt, n) for ph, (_, _, dt, n) in zip(phs, REQS)]
+    server = dao.Server(max_live=3, stream=torch.cuda.current_stream().cuda_stream)
+    try:
+        res, max_live, _ = _run(server, REQS, phs)
+        assert max_live <= 3
+        for (name, seed, dt, n), r, (ref, _) in zip(REQS, res, solo):
+            tol = 1e-9 if dt == "f64" else 1e-5
+            print(f"[serve] {name}/{seed} {dt}: rounds {r['rounds']} F {r['F']:.10e} solo {ref['F']:.10e}", flush=True)
+            assert r["status"] == ref["status"] and r["rounds"] == ref["rounds"]
+            assert np.array_equal(r["round_beam"], ref["round_beam"])
+            assert abs(r["F"] - ref["F"]) <= tol * ref["F"]
+            np.testing.assert_allclose(r["round_rc"], ref["round_rc"], rtol=100 * tol)
+    finally:
+        server.close()
+
+
+def test_admission_respects_the_memory_cap():
+    torch = torch_cuda()
+    reqs = [("tiny", s, "f32", 3) for s in range(4)]
+    phs = [make_phantom(n, s) for n, s, _, _ in reqs]
+    sizes = [_alone(ph, "f32", 3)[1] for ph in phs]
+    cap = int(max(sizes) * 2.5)                      # room for two contexts at a time
+    server = dao.Server(max_live=8, hbm_cap_bytes=cap, stream=torch.cuda.current_stream().cuda_stream)
+    try:
+        res, max_live, max_used = _run(server, reqs, phs)
+        assert max_used <= cap and max_live <= 2
+        assert all(r["rounds"] == 3 for r in res)
+    finally:
+        server.close()
+    # a request that cannot fit even alone ends with DAO_ENOMEM, the others run
+    server = dao.Server(max_live=4, hbm_cap_bytes=min(sizes) // 4, stream=torch.cuda.current_stream().cuda_stream)
+    try:
+        t = server.submit(phs[0], 3, dtype="f32")
+        server.step()
+        state, plan = server.poll(t)
+        assert state == 2 and plan["status"] == dao.DAO_ENOMEM
+    finally:
+        server.close()
