@@ -123,6 +123,81 @@ def pmc_workload(ctx, n_ap, torch):
                       "copy_bytes": COPY_CALIB_BYTES}), flush=True)
 
 
+def serving_stream(n_req, rate, seed, log_fn):
+    """Seeded request stream shaped like the serving configuration: each
+    request is a re-planning solve on a phantom drawn from the tiny /
+    prostate / head-and-neck configurations (uniform), with a rigid shift of
+    0-5 mm, PTV scale 0.8-1.2 and a budget of 20-50 apertures; arrivals are
+    Poisson at `rate` per second.  Phantoms come from a pool of a few seeded
+    variants per configuration (generation takes seconds each), every
+    request still gets its own context and device copy of D."""
+    import numpy as np
+
+    from phantom import make_phantom
+    rng = np.random.default_rng(seed)
+    pool = {}
+    for cfg, nvar in (("tiny", 3), ("prostate", 3), ("headneck", 2)):
+        for v in range(nvar):
+            shift = rng.uniform(-1.0, 1.0, 3)
+            shift = shift / max(1e-9, np.linalg.norm(shift)) * rng.uniform(0.0, 5.0)
+            pool[(cfg, v)] = make_phantom(cfg, 100 + v, shift_mm=tuple(shift), ptv_scale=rng.uniform(0.8, 1.2),
+                                          dtype="f32")
+            log_fn(f"[serve] phantom {cfg}/{v}: {pool[(cfg, v)].n_blt} beamlets, nnz {pool[(cfg, v)].nnz}")
+    t = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    reqs = []
+    for i in range(n_req):
+        cfg = ("tiny", "prostate", "headneck")[rng.integers(3)]
+        nvar = 2 if cfg == "headneck" else 3
+        reqs.append(dict(arrival=float(t[i]), ph=pool[(cfg, int(rng.integers(nvar)))], cfg=cfg,
+                         budget=int(rng.integers(20, 51))))
+    return reqs
+
+
+def run_serving(reqs, stream, max_live, cap, sequential, **opts):
+    """Replay the stream in real time.  Batched: the library's serving loop;
+    sequential: one dao_solve at a time in arrival order.  Latency = finish -
+    arrival."""
+    import numpy as np
+    import torch
+
+    import paper_1003_5402_amd as dao
+    lat = [None] * len(reqs)
+    t0 = time.perf_counter()
+    now = lambda: time.perf_counter() - t0   # noqa: E731
+    if sequential:
+        for i, r in enumerate(reqs):
+            while now() < r["arrival"]:
+                time.sleep(min(0.005, r["arrival"] - now()))
+            ctx = dao.DaoContext.from_phantom(r["ph"], dtype="f32", stream=stream, **opts)
+            ctx.solve(r["budget"])
+            torch.cuda.synchronize()
+            ctx.close()
+            lat[i] = now() - r["arrival"]
+    else:
+        server = dao.Server(max_live=max_live, hbm_cap_bytes=cap, stream=stream)
+        nxt, open_t = 0, {}
+        while nxt < len(reqs) or open_t:
+            while nxt < len(reqs) and reqs[nxt]["arrival"] <= now():
+                open_t[server.submit(reqs[nxt]["ph"], reqs[nxt]["budget"], dtype="f32", **opts)] = nxt
+                nxt += 1
+            if not open_t:
+                time.sleep(min(0.005, max(0.0, reqs[nxt]["arrival"] - now())))
+                continue
+            server.step()
+            for t in list(open_t):
+                state, plan = server.poll(t)
+                if state == 2:
+                    i = open_t.pop(t)
+                    if plan["status"] < 0:
+                        raise RuntimeError(f"request {i} failed with status {plan['status']}")
+                    lat[i] = now() - reqs[i]["arrival"]
+        server.close()
+    wall = now()
+    lat = np.array(lat)
+    return dict(plans_s=len(reqs) / wall, wall_s=wall, p50_s=float(np.percentile(lat, 50)),
+                p99_s=float(np.percentile(lat, 99)), mean_s=float(lat.mean()))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +208,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--product-iters", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=32,
+                    help="requests of the serving replay (the serving configuration uses 256)")
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-max-live", type=int, default=8)
     ap.add_argument("--pmc-workload", action="store_true",
                     help="one plan plus a calibration copy, for rocprofv3 --pmc runs")
     args = ap.parse_args()
@@ -256,6 +335,24 @@ def main():
             rc.close()
     del scrub
 
+    # serving: the same seeded request stream replayed batched (FP32 D and
+    # FP16 D) and as sequential plain solves
+    serve = None
+    if args.serve_requests > 0:
+        reqs = serving_stream(args.serve_requests, args.serve_rate, args.seed, log)
+        cap = 64 << 30
+        serve = dict(requests=args.serve_requests, rate_per_s=args.serve_rate, max_live=args.serve_max_live,
+                     hbm_cap_bytes=cap,
+                     mix={c: sum(r["cfg"] == c for r in reqs) for c in ("tiny", "prostate", "headneck")})
+        serve["batched_f32"] = run_serving(reqs, stream, args.serve_max_live, cap, False)
+        log(f"[bench] serving batched FP32: {serve['batched_f32']}")
+        serve["batched_f16"] = run_serving(reqs, stream, args.serve_max_live, cap, False,
+                                           d_format=dao.DAO_DFMT_F16)
+        log(f"[bench] serving batched FP16 D: {serve['batched_f16']}")
+        serve["sequential_f32"] = run_serving(reqs, stream, 1, cap, True)
+        log(f"[bench] serving sequential FP32: {serve['sequential_f32']}")
+        serve["speedup_plans_s"] = serve["batched_f32"]["plans_s"] / serve["sequential_f32"]["plans_s"]
+
     steps_per_plan = int(outs[-1]["total_steps"])
     result = {
         "metric": METRIC,
@@ -297,6 +394,7 @@ def main():
         },
         "master_kernels": kernels,
         "d_16bit": reduced,
+        "serving": serve,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk_["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dk_["GBs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": dk_["total_bytes"] / max(1, dk_["launches"]),
