@@ -153,7 +153,7 @@ def serving_stream(n_req, rate, seed, log_fn):
     return reqs
 
 
-def run_serving(reqs, stream, max_live, cap, sequential, **opts):
+def run_serving(reqs, stream, max_live, cap, sequential, batch_masters=True, **opts):
     """Replay the stream in real time.  Batched: the library's serving loop;
     sequential: one dao_solve at a time in arrival order.  Latency = finish -
     arrival."""
@@ -174,7 +174,7 @@ def run_serving(reqs, stream, max_live, cap, sequential, **opts):
             ctx.close()
             lat[i] = now() - r["arrival"]
     else:
-        server = dao.Server(max_live=max_live, hbm_cap_bytes=cap, stream=stream)
+        server = dao.Server(max_live=max_live, hbm_cap_bytes=cap, stream=stream, batch_masters=batch_masters)
         nxt, open_t = 0, {}
         while nxt < len(reqs) or open_t:
             while nxt < len(reqs) and reqs[nxt]["arrival"] <= now():
@@ -183,7 +183,9 @@ def run_serving(reqs, stream, max_live, cap, sequential, **opts):
             if not open_t:
                 time.sleep(min(0.005, max(0.0, reqs[nxt]["arrival"] - now())))
                 continue
-            server.step()
+            live, _ = server.step()
+            if live == 0:
+                time.sleep(0.0005)   # the admission thread is building contexts
             for t in list(open_t):
                 state, plan = server.poll(t)
                 if state == 2:
@@ -346,12 +348,16 @@ def main():
                      mix={c: sum(r["cfg"] == c for r in reqs) for c in ("tiny", "prostate", "headneck")})
         serve["batched_f32"] = run_serving(reqs, stream, args.serve_max_live, cap, False)
         log(f"[bench] serving batched FP32: {serve['batched_f32']}")
+        serve["interleaved_f32"] = run_serving(reqs, stream, args.serve_max_live, cap, False, batch_masters=False)
+        log(f"[bench] serving interleaved FP32 (masters one after another): {serve['interleaved_f32']}")
         serve["batched_f16"] = run_serving(reqs, stream, args.serve_max_live, cap, False,
                                            d_format=dao.DAO_DFMT_F16)
         log(f"[bench] serving batched FP16 D: {serve['batched_f16']}")
         serve["sequential_f32"] = run_serving(reqs, stream, 1, cap, True)
         log(f"[bench] serving sequential FP32: {serve['sequential_f32']}")
         serve["speedup_plans_s"] = serve["batched_f32"]["plans_s"] / serve["sequential_f32"]["plans_s"]
+        serve["speedup_interleaved_plans_s"] = (serve["interleaved_f32"]["plans_s"] /
+                                                serve["sequential_f32"]["plans_s"])
 
     steps_per_plan = int(outs[-1]["total_steps"])
     result = {

@@ -307,23 +307,28 @@ dao_status dao_solve(dao_ctx* ctx, int32_t n_apertures, dao_plan* out);
  * solve i's log (may be NULL); the return is DAO_OK or the first error. */
 dao_status dao_solve_batch(dao_ctx* const* ctxs, int32_t n, const int32_t* n_apertures, dao_plan* plans);
 
-/* Serving loop (continuous batching).  Requests are queued in arrival order;
- * each dao_server_step admits queued requests while fewer than max_live
- * solves are live and their contexts fit under hbm_cap_bytes (0: no cap; a
- * context is created at admission with the remaining room as its
- * mem_cap_bytes, so the oldest request waits until enough memory is freed,
- * or fails with DAO_ENOMEM if it cannot fit even alone), then advances every
- * live solve by one column-generation round, their master solves sharing one
- * launch as in dao_solve_batch.  A solve that stops is retired at once: its
+/* Serving loop (continuous batching).  Requests are queued in arrival order.
+ * A worker thread of the server admits them while fewer than max_live solves
+ * are live or admitted and their contexts fit under hbm_cap_bytes (0: no
+ * cap; a context is created at admission, on a stream of the server's own,
+ * with the remaining room as its mem_cap_bytes, so the oldest request waits
+ * until enough memory is freed, or fails with DAO_ENOMEM if it cannot fit
+ * even alone); context creation thus overlaps the device work of the live
+ * solves.  Each dao_server_step takes the admitted contexts in and advances
+ * every live solve by one column-generation round, their master solves
+ * sharing one launch as in dao_solve_batch (batch_masters) or one after
+ * another.  A solve that stops is retired at once: its
  * context (dose matrix, dose, master state) is destroyed and its result is
  * kept for dao_server_poll.  Each result is the plan dao_solve gives for the
  * same request up to the order of floating-point sums.  The host arrays of
  * a request must stay valid until its ticket is admitted.  All work runs on
- * `stream`.  Not thread-safe. */
+ * `stream`; the server's calls are made from one thread. */
 typedef struct dao_server dao_server;
 typedef struct {
     int32_t max_live;        /* solves advanced together, 1..64 */
-    int64_t hbm_cap_bytes;   /* device bytes of the live contexts; 0 = no cap */
+    int32_t batch_masters;   /* 1: the round's master solves share one launch (dao_solve_batch);
+                                0: each runs with the whole grid, one after another */
+    int64_t hbm_cap_bytes;   /* device bytes of the admitted contexts; 0 = no cap */
 } dao_server_options;
 dao_status dao_server_create(const dao_server_options* opt, void* stream, dao_server** out);
 void dao_server_destroy(dao_server* srv);

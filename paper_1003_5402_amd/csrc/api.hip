@@ -4,8 +4,11 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <deque>
 #include <map>
+#include <mutex>
+#include <thread>
 #include <type_traits>
 #include <cmath>
 #include <cstring>
@@ -1355,11 +1358,17 @@ dao_status dao_solve(dao_ctx* c, int32_t n_apertures, dao_plan* out) {
 // ===========================================================================
 // Serving loop: continuous batching of solves under a device-memory cap
 // ===========================================================================
+// A worker thread admits queued requests (first come, first served): it
+// builds each context (host layout, uploads on its own stream) while the
+// device works on the live solves, as long as the live plus admitted
+// contexts stay within max_live and the memory cap.  dao_server_step takes
+// the admitted contexts in and advances every live solve by one round.
 struct dao_server {
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;   // solves
+    hipStream_t upload = nullptr;   // context creation (worker thread)
     int max_live = 8;
-    int64_t cap = 0;     // 0: no cap
-    int64_t used = 0;    // device bytes of the live contexts
+    int64_t cap = 0;                // 0: no cap
+    bool batch_masters = true;
     struct Req {
         const dao_matrix* D;
         const dao_beams* B;
@@ -1368,6 +1377,12 @@ struct dao_server {
         dao_options opt;
         int32_t n_ap;
         int64_t ticket;
+    };
+    struct Admitted {
+        Req q;
+        dao_ctx* c;
+        dao_status st;
+        std::string err;
     };
     struct Result {
         dao_status status = DAO_OK;
@@ -1382,15 +1397,62 @@ struct dao_server {
         int64_t ticket = 0;
         int64_t bytes = 0;
     };
+    // shared with the worker (under mu)
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stop = false;
     std::deque<Req> queue;
+    std::deque<Admitted> admitted;
+    int64_t used = 0;   // device bytes of admitted and live contexts
+    int n_live = 0;
+    // main thread only
     std::vector<std::unique_ptr<Live>> live;
     std::map<int64_t, Result> done;
     std::map<int64_t, Result> running;   // results being filled by live solves
     int64_t next_ticket = 0;
-    std::string error;
+    std::thread worker;
 };
 
 namespace {
+
+void server_worker(dao_server* sv) {
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+        sv->cv.wait(lk, [&] {
+            return sv->stop || (!sv->queue.empty() && sv->n_live + int(sv->admitted.size()) < sv->max_live &&
+                                (sv->cap == 0 || sv->used < sv->cap));
+        });
+        if (sv->stop) return;
+        dao_server::Req q = sv->queue.front();
+        dao_options o = q.opt;
+        const int64_t room = sv->cap > 0 ? sv->cap - sv->used : 0;
+        if (sv->cap > 0) o.mem_cap_bytes = o.mem_cap_bytes > 0 ? std::min(o.mem_cap_bytes, room) : room;
+        const bool others = sv->n_live + int(sv->admitted.size()) > 0;
+        lk.unlock();
+        dao_ctx* c = nullptr;
+        dao_status st = dao_create(q.D, q.B, q.S, q.P, &o, sv->upload, &c);
+        std::string err = st == DAO_OK ? std::string() : std::string(dao_create_error());
+        if (st == DAO_OK && hipStreamSynchronize(sv->upload) != hipSuccess) {
+            dao_destroy(c);
+            c = nullptr;
+            st = DAO_EDEVICE;
+            err = "upload failed";
+        }
+        lk.lock();
+        if (st == DAO_ENOMEM && others) {
+            // wait until a retirement frees memory, then try again
+            const int64_t before = sv->used;
+            sv->cv.wait(lk, [&] { return sv->stop || sv->used < before; });
+            continue;
+        }
+        sv->queue.pop_front();
+        if (st == DAO_OK) {
+            c->stream = sv->stream;   // the solve runs on the serving stream
+            sv->used += c->device_bytes;
+        }
+        sv->admitted.push_back(dao_server::Admitted{q, c, st, err});
+    }
+}
 
 void server_retire(dao_server* sv, size_t i, dao_status st, const char* why) {
     dao_server::Live& L = *sv->live[i];
@@ -1399,7 +1461,6 @@ void server_retire(dao_server* sv, size_t i, dao_status st, const char* why) {
     sv->running.erase(it);
     r.status = st == DAO_OK ? dao_status(L.run.stop) : st;
     if (why) r.error = why;
-    // the arrays moved with the result: point the summary at them again
     r.plan.round_beam = r.beam.data();
     r.plan.round_steps = r.steps.data();
     r.plan.round_rc = r.rc.data();
@@ -1407,41 +1468,45 @@ void server_retire(dao_server* sv, size_t i, dao_status st, const char* why) {
     r.plan.round_kkt = r.kkt.data();
     r.plan.round_F = r.F.data();
     sv->done[L.ticket] = std::move(r);
-    sv->used -= L.bytes;
     dao_destroy(L.c);
+    const int64_t bytes = L.bytes;
     sv->live.erase(sv->live.begin() + long(i));
+    {
+        std::lock_guard<std::mutex> g(sv->mu);
+        sv->used -= bytes;
+        sv->n_live = int(sv->live.size());
+    }
+    sv->cv.notify_all();
 }
 
-// Admit queued requests (first come, first served) while slots and memory allow.
-void server_admit(dao_server* sv) {
-    while (!sv->queue.empty() && int(sv->live.size()) < sv->max_live) {
-        dao_server::Req q = sv->queue.front();
-        dao_options o = q.opt;
-        if (sv->cap > 0) {
-            const int64_t room = sv->cap - sv->used;
-            if (room <= 0) break;
-            o.mem_cap_bytes = o.mem_cap_bytes > 0 ? std::min(o.mem_cap_bytes, room) : room;
-        }
-        dao_ctx* c = nullptr;
-        const dao_status st = dao_create(q.D, q.B, q.S, q.P, &o, sv->stream, &c);
-        if (st == DAO_ENOMEM && !sv->live.empty()) break;   // wait for memory to free up
-        sv->queue.pop_front();
+// Take the contexts the worker has admitted into the live set.
+void server_take_admitted(dao_server* sv) {
+    std::deque<dao_server::Admitted> got;
+    {
+        std::lock_guard<std::mutex> g(sv->mu);
+        got.swap(sv->admitted);
+        sv->n_live = int(sv->live.size() + got.size());
+    }
+    for (auto& a : got) {
         dao_server::Result r;
-        if (st != DAO_OK) {
-            r.status = st;
-            r.error = dao_create_error();
-            sv->done[q.ticket] = std::move(r);
+        if (a.st != DAO_OK) {
+            r.status = a.st;
+            r.error = a.err;
+            sv->done[a.q.ticket] = std::move(r);
+            std::lock_guard<std::mutex> g(sv->mu);
+            sv->n_live -= 1;
             continue;
         }
-        const int n = std::max(1, int(q.n_ap));
+        dao_ctx* c = a.c;
+        const int n = std::max(1, int(a.q.n_ap));
         r.beam.assign(n, 0);
         r.steps.assign(n, 0);
         r.rc.assign(n, 0.0);
         r.gap.assign(n, 0.0);
         r.kkt.assign(n, 0.0);
         r.F.assign(n, 0.0);
-        sv->running[q.ticket] = std::move(r);
-        dao_server::Result& rr = sv->running[q.ticket];
+        sv->running[a.q.ticket] = std::move(r);
+        dao_server::Result& rr = sv->running[a.q.ticket];
         rr.plan.round_beam = rr.beam.data();
         rr.plan.round_steps = rr.steps.data();
         rr.plan.round_rc = rr.rc.data();
@@ -1450,16 +1515,16 @@ void server_admit(dao_server* sv) {
         rr.plan.round_F = rr.F.data();
         auto L = std::make_unique<dao_server::Live>();
         L->c = c;
-        L->ticket = q.ticket;
+        L->ticket = a.q.ticket;
         L->bytes = c->device_bytes;
         L->run.c = c;
-        L->run.n_ap = std::min(q.n_ap, c->opt.max_apertures);
+        L->run.n_ap = std::min(a.q.n_ap, c->opt.max_apertures);
         L->run.out = &rr.plan;
         const dao_status s2 = c->dtype == DAO_F64 ? plan_start<double>(L->run) : plan_start<float>(L->run);
-        sv->used += L->bytes;
         sv->live.push_back(std::move(L));
         if (s2 != DAO_OK) server_retire(sv, sv->live.size() - 1, s2, c->err.c_str());
     }
+    sv->cv.notify_all();
 }
 
 }  // namespace
@@ -1467,18 +1532,36 @@ void server_admit(dao_server* sv) {
 extern "C" {
 
 dao_status dao_server_create(const dao_server_options* o, void* stream, dao_server** out) {
-    if (!out || !o || o->max_live < 1 || o->max_live > MAX_BATCH || o->hbm_cap_bytes < 0) return DAO_EINVAL;
+    if (!out || !o || o->max_live < 1 || o->max_live > MAX_BATCH || o->hbm_cap_bytes < 0 ||
+        (o->batch_masters != 0 && o->batch_masters != 1))
+        return DAO_EINVAL;
     auto* sv = new dao_server();
     sv->stream = static_cast<hipStream_t>(stream);
     sv->max_live = o->max_live;
     sv->cap = o->hbm_cap_bytes;
+    sv->batch_masters = o->batch_masters != 0;
+    if (hipStreamCreateWithFlags(&sv->upload, hipStreamNonBlocking) != hipSuccess) {
+        delete sv;
+        return DAO_EDEVICE;
+    }
+    sv->worker = std::thread(server_worker, sv);
     *out = sv;
     return DAO_OK;
 }
 
 void dao_server_destroy(dao_server* sv) {
     if (!sv) return;
+    {
+        std::lock_guard<std::mutex> g(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv.notify_all();
+    if (sv->worker.joinable()) sv->worker.join();
+    for (auto& a : sv->admitted)
+        if (a.c) dao_destroy(a.c);
+    sv->admitted.clear();
     while (!sv->live.empty()) server_retire(sv, sv->live.size() - 1, DAO_ESTATE, "server destroyed");
+    if (sv->upload) (void)hipStreamDestroy(sv->upload);
     delete sv;
 }
 
@@ -1486,21 +1569,25 @@ dao_status dao_server_submit(dao_server* sv, const dao_matrix* D, const dao_beam
                              const dao_prescription* presc, const dao_options* opt, int32_t n_apertures,
                              int64_t* ticket) {
     if (!sv || !D || !beams || !structs || !ticket || n_apertures < 0) return DAO_EINVAL;
-    dao_server::Req q{D, beams, structs, presc, {}, n_apertures, sv->next_ticket++};
+    dao_server::Req q{D, beams, structs, presc, {}, n_apertures, 0};
     if (opt)
         q.opt = *opt;
     else
         dao_default_options(&q.opt);
-    sv->queue.push_back(q);
+    {
+        std::lock_guard<std::mutex> g(sv->mu);
+        q.ticket = sv->next_ticket++;
+        sv->queue.push_back(q);
+    }
+    sv->cv.notify_all();
     *ticket = q.ticket;
     return DAO_OK;
 }
 
 dao_status dao_server_step(dao_server* sv, int32_t* n_live, int32_t* n_done) {
     if (!sv) return DAO_EINVAL;
-    server_admit(sv);
+    server_take_admitted(sv);
     int finished = 0;
-    // round begin for every live solve
     std::vector<PlanRun*> need32, need64;
     for (size_t i = 0; i < sv->live.size();) {
         dao_server::Live& L = *sv->live[i];
@@ -1520,11 +1607,19 @@ dao_status dao_server_step(dao_server* sv, int32_t* n_live, int32_t* n_done) {
         ++i;
     }
     dao_status s = DAO_OK;
-    if (!need32.empty()) s = run_master_batch<float>(need32);
-    if (s == DAO_OK && !need64.empty()) s = run_master_batch<double>(need64);
+    if (sv->batch_masters) {
+        if (!need32.empty()) s = run_master_batch<float>(need32);
+        if (s == DAO_OK && !need64.empty()) s = run_master_batch<double>(need64);
+    } else {
+        // each master with the whole grid, one after another
+        for (PlanRun* r : need32)
+            if (s == DAO_OK) s = run_master<float>(r->c, r->tol, r->c->opt.max_steps);
+        for (PlanRun* r : need64)
+            if (s == DAO_OK) s = run_master<double>(r->c, r->tol, r->c->opt.max_steps);
+    }
     if (s != DAO_OK) {
         // a device error: every live solve ends with it
-        while (!sv->live.empty()) server_retire(sv, sv->live.size() - 1, s, "master launch failed");
+        while (!sv->live.empty()) server_retire(sv, sv->live.size() - 1, s, "master solve failed");
         if (n_live) *n_live = 0;
         if (n_done) *n_done = finished;
         return s;
@@ -1543,6 +1638,12 @@ dao_status dao_server_poll(dao_server* sv, int64_t ticket, int32_t* state, dao_p
             *state = 1;
             return DAO_OK;
         }
+        std::lock_guard<std::mutex> g(sv->mu);
+        for (const auto& a : sv->admitted)
+            if (a.q.ticket == ticket) {
+                *state = 0;
+                return DAO_OK;
+            }
         for (const auto& q : sv->queue)
             if (q.ticket == ticket) {
                 *state = 0;
@@ -1574,13 +1675,14 @@ dao_status dao_server_poll(dao_server* sv, int64_t ticket, int32_t* state, dao_p
     return st;
 }
 
-dao_status dao_server_info(const dao_server* sv, int32_t* queued, int32_t* live, int64_t* used_bytes) {
-    if (!sv) return DAO_EINVAL;
-    if (queued) *queued = int32_t(sv->queue.size());
+dao_status dao_server_info(const dao_server* sv_c, int32_t* queued, int32_t* live, int64_t* used_bytes) {
+    if (!sv_c) return DAO_EINVAL;
+    auto* sv = const_cast<dao_server*>(sv_c);
+    std::lock_guard<std::mutex> g(sv->mu);
+    if (queued) *queued = int32_t(sv->queue.size() + sv->admitted.size());
     if (live) *live = int32_t(sv->live.size());
     if (used_bytes) *used_bytes = sv->used;
     return DAO_OK;
 }
 
 }  // extern "C"
-

@@ -2,6 +2,8 @@
 free up, rounds of all live solves advanced together, each result the plan
 its solo dao_solve gives (same round beams and reduced costs; F within 1e-9
 in FP64, 1e-5 in FP32, as for dao_solve_batch)."""
+import time
+
 import numpy as np
 import pytest
 
@@ -23,10 +25,13 @@ def _alone(ph, dtype, n_ap):
         ctx.close()
 
 
-def _run(server, reqs, phs):
-    tickets = [server.submit(ph, n, dtype=dt) for (_, _, dt, n), ph in zip(reqs, phs)]
+def _drain(server, tickets, limit_s=120.0):
+    """Step until every ticket is done (the admission thread may still be
+    building contexts when a step finds nothing live)."""
     results, max_live, max_used = {}, 0, 0
-    for _ in range(10000):
+    t0 = time.time()
+    while len(results) < len(tickets):
+        assert time.time() - t0 < limit_s, "serving loop made no progress"
         live, _done = server.step()
         info = server.info()
         max_live, max_used = max(max_live, live), max(max_used, info["used_bytes"])
@@ -35,16 +40,22 @@ def _run(server, reqs, phs):
                 state, plan = server.poll(t)
                 if state == 2:
                     results[t] = plan
-        if len(results) == len(tickets):
-            break
+        if live == 0:
+            time.sleep(0.001)
     return [results[t] for t in tickets], max_live, max_used
 
 
-def test_serving_results_equal_solo_solves():
+def _run(server, reqs, phs):
+    tickets = [server.submit(ph, n, dtype=dt) for (_, _, dt, n), ph in zip(reqs, phs)]
+    return _drain(server, tickets)
+
+
+@pytest.mark.parametrize("batch_masters", [True, False])
+def test_serving_results_equal_solo_solves(batch_masters):
     torch = torch_cuda()
     phs = [make_phantom(n, s) for n, s, _, _ in REQS]
     solo = [_alone(ph, dt, n) for ph, (_, _, dt, n) in zip(phs, REQS)]
-    server = dao.Server(max_live=3, stream=torch.cuda.current_stream().cuda_stream)
+    server = dao.Server(max_live=3, stream=torch.cuda.current_stream().cuda_stream, batch_masters=batch_masters)
     try:
         res, max_live, _ = _run(server, REQS, phs)
         assert max_live <= 3
@@ -76,8 +87,7 @@ def test_admission_respects_the_memory_cap():
     server = dao.Server(max_live=4, hbm_cap_bytes=min(sizes) // 4, stream=torch.cuda.current_stream().cuda_stream)
     try:
         t = server.submit(phs[0], 3, dtype="f32")
-        server.step()
-        state, plan = server.poll(t)
-        assert state == 2 and plan["status"] == dao.DAO_ENOMEM
+        (plan,), _, _ = _drain(server, [t])
+        assert plan["status"] == dao.DAO_ENOMEM
     finally:
         server.close()
