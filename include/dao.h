@@ -315,9 +315,10 @@ dao_status dao_solve_batch(dao_ctx* const* ctxs, int32_t n, const int32_t* n_ape
  * until enough memory is freed, or fails with DAO_ENOMEM if it cannot fit
  * even alone); context creation thus overlaps the device work of the live
  * solves.  Each dao_server_step takes the admitted contexts in and advances
- * every live solve by one column-generation round, their master solves
- * sharing one launch as in dao_solve_batch (batch_masters) or one after
- * another.  A solve that stops is retired at once: its
+ * every live solve by one column-generation round.  With batch_masters the
+ * master solves of the small solves (fewer than 4 row batches per workgroup
+ * of the whole grid) share one launch as in dao_solve_batch and each larger
+ * one keeps the whole grid; otherwise they all run one after another.  A solve that stops is retired at once: its
  * context (dose matrix, dose, master state) is destroyed and its result is
  * kept for dao_server_poll.  Each result is the plan dao_solve gives for the
  * same request up to the order of floating-point sums.  The host arrays of

@@ -1608,8 +1608,24 @@ dao_status dao_server_step(dao_server* sv, int32_t* n_live, int32_t* n_done) {
     }
     dao_status s = DAO_OK;
     if (sv->batch_masters) {
-        if (!need32.empty()) s = run_master_batch<float>(need32);
-        if (s == DAO_OK && !need64.empty()) s = run_master_batch<double>(need64);
+        // small solves (fewer rows than a few batches per workgroup of the
+        // whole grid) share one launch; a large solve keeps the whole grid
+        auto run_group = [&](std::vector<PlanRun*>& need, auto tag) -> dao_status {
+            using T = decltype(tag);
+            std::vector<PlanRun*> small;
+            for (PlanRun* r : need) {
+                const int64_t rows_per_wg = r->c->Vpad / std::max(1, r->c->coop_grid);
+                if (rows_per_wg < 4 * Batch<T>::ROWS)
+                    small.push_back(r);
+                else {
+                    const dao_status e = run_master<T>(r->c, r->tol, r->c->opt.max_steps);
+                    if (e != DAO_OK) return e;
+                }
+            }
+            return small.empty() ? DAO_OK : run_master_batch<T>(small);
+        };
+        if (!need32.empty()) s = run_group(need32, float{});
+        if (s == DAO_OK && !need64.empty()) s = run_group(need64, double{});
     } else {
         // each master with the whole grid, one after another
         for (PlanRun* r : need32)
