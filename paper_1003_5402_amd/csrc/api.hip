@@ -612,13 +612,7 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
             // workgroup beyond the kernel's static LDS, if one per CU still fits
             int lds_max = 0;
             HIPCHK(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-            // the rest of the per-workgroup limit after the kernel's static LDS
-            hipFuncAttributes fa{};
-            const int stat = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_master_coop<T, true>)) ==
-                                     hipSuccess
-                                 ? int(fa.sharedSizeBytes)
-                                 : 48 * 1024;
-            const int want = lds_max - ((stat + 1023) / 1024) * 1024;
+            const int want = lds_max - 24 * 1024;
             if (want > 0 &&
                 hipFuncSetAttribute(reinterpret_cast<const void*>(&k_master_coop<T, true>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, want) == hipSuccess) {

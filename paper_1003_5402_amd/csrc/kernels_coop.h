@@ -31,7 +31,7 @@
 namespace dao {
 
 constexpr int COOP_THREADS = 512;          // threads per workgroup: 8 wavefronts, 2 per SIMD
-constexpr int RECW = 2 * KS + 8;           // doubles per reduction record (the fused line-search record)
+constexpr int RECW = KS + 8;               // doubles per reduction record
 constexpr int MAX_COOP_GRID = 1024;        // workgroups of one persistent launch
 constexpr long SPIN_LIMIT = 4000000L;      // ~1 s of waiting before the grid aborts
 
@@ -157,35 +157,31 @@ template <bool LS, int FMAX>
 __device__ __forceinline__ void combine_fields(const double* buf, uint32_t nb, int W, double* out) {
     constexpr int L = 4;
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
-    // chunks of nw * FMAX fields (more than one only for the fused record)
-    for (int f0 = 0; f0 < W; f0 += nw * FMAX) {
-        const int Wc = min(W - f0, nw * FMAX);
-        const int nf = wave < Wc ? (Wc - wave + nw - 1) / nw : 0;
-        double acc[FMAX];
+    const int nf = wave < W ? (W - wave + nw - 1) / nw : 0;
+    double acc[FMAX];
 #pragma unroll
-        for (int i = 0; i < FMAX; ++i) acc[i] = rec_init<LS>(f0 + wave + nw * i);
-        for (uint32_t q0 = 0; q0 < nb; q0 += L * WAVE) {
-            double v[FMAX][L];
+    for (int i = 0; i < FMAX; ++i) acc[i] = rec_init<LS>(wave + nw * i);
+    for (uint32_t q0 = 0; q0 < nb; q0 += L * WAVE) {
+        double v[FMAX][L];
 #pragma unroll
-            for (int i = 0; i < FMAX; ++i)
+        for (int i = 0; i < FMAX; ++i)
 #pragma unroll
-                for (int u = 0; u < L; ++u) {
-                    const int f = f0 + wave + nw * i;
-                    const uint32_t rec = q0 + u * WAVE + lane;
-                    v[i][u] = (i < nf && rec < nb) ? aload(buf + size_t(f) * nb + rec) : rec_init<LS>(f);
-                }
-#pragma unroll
-            for (int i = 0; i < FMAX; ++i)
-#pragma unroll
-                for (int u = 0; u < L; ++u) acc[i] = rec_comb<LS>(f0 + wave + nw * i, acc[i], v[i][u]);
-        }
-#pragma unroll
-        for (int i = 0; i < FMAX; ++i) {
-            if (i < nf) {
-                const int f = f0 + wave + nw * i;
-                const double tot = field_reduce_dpp(LS, f, acc[i]);
-                if (lane == 0) out[f] = tot;
+            for (int u = 0; u < L; ++u) {
+                const int f = wave + nw * i;
+                const uint32_t rec = q0 + u * WAVE + lane;
+                v[i][u] = (i < nf && rec < nb) ? aload(buf + size_t(f) * nb + rec) : rec_init<LS>(f);
             }
+#pragma unroll
+        for (int i = 0; i < FMAX; ++i)
+#pragma unroll
+            for (int u = 0; u < L; ++u) acc[i] = rec_comb<LS>(wave + nw * i, acc[i], v[i][u]);
+    }
+#pragma unroll
+    for (int i = 0; i < FMAX; ++i) {
+        if (i < nf) {
+            const int f = wave + nw * i;
+            const double tot = field_reduce_dpp(LS, f, acc[i]);
+            if (lane == 0) out[f] = tot;
         }
     }
     __syncthreads();
@@ -228,31 +224,9 @@ __device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W
     }
     __syncthreads();
     if (!s_ok) return false;
-    if (LS && W <= 8)
-        combine_fields<LS, 1>(buf, nb, W, total);
-    else
-        combine_fields<LS, (KS + 1 + COOP_THREADS / WAVE - 1) / (COOP_THREADS / WAVE)>(buf, nb, W, total);
+    combine_fields<LS, LS ? (6 + COOP_THREADS / WAVE - 1) / (COOP_THREADS / WAVE)
+                             : (KS + 1 + COOP_THREADS / WAVE - 1) / (COOP_THREADS / WAVE)>(buf, nb, W, total);
     return true;
-}
-
-// Line-search evaluation of one voxel at t that also returns what the
-// update at a point of the same linear piece needs: dF/dz at t (u), its
-// slope along the step to the right of t times q (hq), the voxel objective
-// (f), and whether the slopes to the left and right of t differ (tie, the
-// voxel sits exactly on a threshold).
-__device__ __forceinline__ void fused_voxel(const ObjClass& c, double d, double q, double bu, double bo, double t,
-                                            Rec& r, double& u, double& hq, double& f, int& tie) {
-    ls_voxel_bp(c, d, q, bu, bo, t, r);
-    const double z = d + t * q;
-    u = grad_f(c, z);
-    f = obj_f(c, z);
-    const bool ua = c.a > 0.0, ob = c.b > 0.0;
-    const bool under_r = ua && ((z < c.t_under) || (z == c.t_under && q < 0.0));
-    const bool over_r = ob && ((z > c.t_over) || (z == c.t_over && q > 0.0));
-    const bool under_l = ua && ((z < c.t_under) || (z == c.t_under && q > 0.0));
-    const bool over_l = ob && ((z > c.t_over) || (z == c.t_over && q < 0.0));
-    hq = 2.0 * ((under_r ? c.a : 0.0) + (over_r ? c.b : 0.0)) * q;
-    tie = (under_r != under_l) || (over_r != over_l);
 }
 
 // Line-search state kept in registers by every thread (the fields
@@ -312,10 +286,8 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     __shared__ double s_y[KS], s_p[KS], s_g[KS];
     __shared__ double s_rec[RECW], s_tot[RECW];
     static_assert(NW == 8, "the wavefront combines assume 8 wavefronts");
-    __shared__ double s_acc[NW][RECW];   // per wavefront partials of the update / fused records
+    __shared__ double s_acc[NW][RECW];   // per wavefront: objective, then grad_y
     __shared__ double s_u[NW][ROWS];
-    __shared__ double s_h[NW][ROWS];     // fused evaluation: slope of dF/dz along the step, per row
-    __shared__ double s_fz[1 + KS];      // objective partial sum and grad_y extrapolated to the step
     __shared__ int s_go;
 
     ms_load(s_ms, A.ms);
@@ -377,15 +349,6 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     LsRegs ls{0.0, 0.0, 0.0, 0.0, 0, 0, s_ms.total_ls};
     int steps = s_ms.steps;
     const int refresh_every = s_ms.refresh_every;
-    // Fused steps: when a step's last line-search evaluation (at t_e) also
-    // returned dF/dz at t_e and its slope along the step summed through D_K^T,
-    // and the final step t lies in the same linear piece as t_e (no voxel
-    // crosses a threshold in between), the objective and grad_y at t follow
-    // exactly from the quadratic model of that piece, so the next update pass
-    // and its reduction are skipped (have_grad); d += t q is then applied to
-    // each row at its next use (pending_d).
-    bool have_grad = false, pending_d = false;
-    double pending_t = 0.0;
     // phase timing (workgroup 0, thread 0): 0 update pass, 1 its reduction,
     // 2 direction, 3 first line-search pass (q), 4 line-search reductions,
     // 5 final decision + step, 6 later line-search passes (with the decision
@@ -406,7 +369,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
 
     while (alive) {
         // ---------------- update pass: apply the step, dF/dz, F, grad_y partials
-        if (!have_grad) {
+        {
             const double t = ls.t;
             double yv[G::EPL], acc[G::EPL];
 #pragma unroll
@@ -497,13 +460,11 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             tick(1);
         }
         // ---------------- direction (identical in every workgroup)
-        const double* gsrc = have_grad ? s_fz : s_tot;   // [objective partial, grad_y]
-        have_grad = false;
         if (threadIdx.x < WAVE) {
             const int k = threadIdx.x;
             const bool in = k < K;
             const double yk = s_y[k];
-            const double gk = in ? gsrc[1 + k] : 0.0;
+            const double gk = in ? s_tot[1 + k] : 0.0;
             double pk = -gk;
             if (!in || (yk == 0.0 && gk >= 0.0)) pk = 0.0;
             const double kkt = wave_reduce_dpp<2>(in ? fabs(fmin(yk, gk)) : 0.0);
@@ -513,7 +474,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             s_p[k] = pk;
             s_g[k] = gk;
             if (k == 0) {
-                s_ms.F = s_ms.F_const + gsrc[0];
+                s_ms.F = s_ms.F_const + s_tot[0];
                 s_ms.kkt = kkt;
                 int go = 1;
                 if (!(kkt > s_ms.tol)) {
@@ -550,115 +511,22 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
         ls.hi_known = 0;
         ls.ls_iter = 0;
         // ---------------- line search: first evaluation computes q = D_K p
-        bool first = true, fused = false;
-        double t_e = 0.0;
+        bool first = true;
         for (;;) {
             const double t = ls.t;
-            // later evaluations are fused unless the next update is a refresh
-            fused = !first && ((steps + 1) % refresh_every) != 0;
-            t_e = t;
             Rec r = rec_identity();
             double pv[G::EPL];
 #pragma unroll
             for (int e = 0; e < G::EPL; ++e) pv[e] = s_p[c * G::EPL + e];
             double* sq = s_u[wave];
-            int W = 6;
-            if (fused) {
-                // evaluation at t plus, per row, dF/dz (u) and its slope along
-                // the step (hq), summed through D_K^T like the update pass
-                double a1[G::EPL], a2[G::EPL];
-#pragma unroll
-                for (int e = 0; e < G::EPL; ++e) {
-                    a1[e] = 0.0;
-                    a2[e] = 0.0;
-                }
-                double tiesd = 0.0;
-                double* su = s_u[wave];
-                double* sh = s_h[wave];
-                for (int64_t bt = bat0 + wave; bt < bat1; bt += NW) {
-                    const int64_t base = bt * ROWS;
-                    V v[IT];
-                    if (LDSRES) {
-                        uint32_t off = uint32_t(((base - r0 + rg) * nc + c) * 16);
-                        const uint32_t stride = uint32_t(G::RPW * nc * 16);
-#pragma unroll
-                        for (int it = 0; it < IT; ++it) {
-                            asm volatile("" : "+v"(off));
-                            v[it] = c < nc ? *reinterpret_cast<const V*>(dyn + off) : vzero<V>();
-                            off += stride;
-                        }
-                    } else {
-#pragma unroll
-                        for (int it = 0; it < IT; ++it) {
-                            v[it] = vzero<V>();
-                            if (c < nc) v[it] = dk_vec(base + it * G::RPW + rg);
-                        }
-                    }
-                    if (lane < ROWS) {
-                        const int64_t row = base + lane;
-                        const ObjClass cc = cl[cls_at(row)];
-                        const double dv = d_at(row), qv = double(q_at(row));
-                        double bu, bo;
-                        if (LDSRES) {
-                            bu = bul[row - r0];
-                            bo = bol[row - r0];
-                        } else {
-                            ls_breakpoints(cc, dv, qv, bu, bo);
-                        }
-                        double u, hq, f;
-                        int tie;
-                        fused_voxel(cc, dv, qv, bu, bo, t, r, u, hq, f, tie);
-                        r.s5 += f;
-                        tiesd += double(tie);
-                        su[lane] = u;
-                        sh[lane] = hq;
-                    }
-                    wave_sync();
-#pragma unroll
-                    for (int it = 0; it < IT; ++it) {
-                        const double uu = su[it * G::RPW + rg], hh = sh[it * G::RPW + rg];
-#pragma unroll
-                        for (int e = 0; e < G::EPL; ++e) {
-                            const double ve = vget(v[it], e);
-                            a1[e] += uu * ve;
-                            a2[e] += hh * ve;
-                        }
-                    }
-                    wave_sync();
-                }
-#pragma unroll
-                for (int off = G::LPR; off < WAVE; off <<= 1)
-#pragma unroll
-                    for (int e = 0; e < G::EPL; ++e) {
-                        a1[e] += __shfl_xor(a1[e], off, WAVE);
-                        a2[e] += __shfl_xor(a2[e], off, WAVE);
-                    }
-                if (rg == 0)
-#pragma unroll
-                    for (int e = 0; e < G::EPL; ++e) {
-                        const int k = c * G::EPL + e;
-                        if (k < K) {
-                            s_acc[wave][7 + k] = a1[e];
-                            s_acc[wave][7 + K + k] = a2[e];
-                        }
-                    }
-                tiesd = wave_reduce_dpp<0>(tiesd);
-                if (lane == 0) s_acc[wave][6] = tiesd;
-                __syncthreads();
-                combine_waves8(&s_acc[0][6], RECW, 1 + 2 * K, false, s_rec + 6);
-                W = 7 + 2 * K;
-            } else if (LDSRES) {
+            if (LDSRES) {
                 // one row per thread, straight from LDS; q's per-slot partials
                 // are combined in the order of the lane butterfly of the
                 // streaming form below, so q is the same up to the sign of an
                 // exact zero
                 for (int64_t rr = threadIdx.x; rr < nrows; rr += blockDim.x) {
                     const ObjClass cc = cl[cll[rr]];
-                    double dv = dl[rr];
-                    if (first && pending_d) {   // the previous fused step's d += t q
-                        dv = dv + pending_t * double(ql[rr]);
-                        dl[rr] = dv;
-                    }
+                    const double dv = dl[rr];
                     T qt;
                     if (first) {
                         const V* rp = dkl + rr * nc;
@@ -718,7 +586,6 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                         T qt;
                         if (first) {
                             qt = T(sq[lane]);   // the line search and the update use the stored value
-                            if (pending_d) d_at(row) = d_at(row) + pending_t * double(q_at(row));
                             q_at(row) = qt;
                         } else {
                             qt = q_at(row);
@@ -728,17 +595,15 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                     wave_sync();
                 }
             }
-            if (first) pending_d = false;   // every row has applied it
             block_rec_dpp(r, s_rec);
             if (gb == 0 && threadIdx.x == 0) {
                 const int kk = first ? 1 : 2;
                 cnt_bytes[kk] += (first ? (16.0 * nc + 8.0 + 1.0 + double(sizeof(T)))
-                                        : ((fused ? 16.0 * nc : 0.0) + 8.0 + double(sizeof(T)) + 1.0)) *
-                                 double(A.Vnz);
+                                          : (8.0 + double(sizeof(T)) + 1.0)) * double(A.Vnz);
                 cnt_real[kk] += 1;
             }
             tick(first ? 3 : 6);
-            if (!grid_reduce<true>(A.sync, A.recs, s_rec, W, s_tot, seq, gb, gn)) {
+            if (!grid_reduce<true>(A.sync, A.recs, s_rec, 6, s_tot, seq, gb, gn)) {
                 alive = false;
                 break;
             }
@@ -749,19 +614,6 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             if (fin) break;
         }
         if (!alive) break;
-        // a fused last evaluation whose piece contains the final step: the
-        // objective and grad_y at the step from the piece's quadratic model
-        if (fused) {
-            const double ts = ls.t, dt = ts - t_e;
-            const bool valid = dt >= 0.0 ? ts <= s_tot[3] : (ts >= s_tot[4] && s_tot[6] == 0.0);
-            if (valid) {
-                if (threadIdx.x == 0) s_fz[0] = s_tot[5] + dt * s_tot[0] + dt * dt * (dt >= 0.0 ? s_tot[1] : s_tot[2]);
-                if (threadIdx.x < K) s_fz[1 + threadIdx.x] = s_tot[7 + threadIdx.x] + dt * s_tot[7 + K + threadIdx.x];
-                have_grad = true;
-                pending_d = true;
-                pending_t = ts;
-            }
-        }
         // ---------------- step: y update, counters, next update mode
         {
             const double t = ls.t, tmax = ls.t_max;
@@ -790,14 +642,6 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             }
             __syncthreads();   // y visible to the next update pass
             tick(5);
-        }
-    }
-    if (pending_d) {   // the last fused step's d += t q
-        for (int64_t rr = threadIdx.x; rr < nrows; rr += blockDim.x) {
-            if (LDSRES)
-                dl[rr] = dl[rr] + pending_t * double(ql[rr]);
-            else
-                A.d[r0 + rr] = A.d[r0 + rr] + pending_t * double(A.q[r0 + rr]);
         }
     }
     if (LDSRES) {
