@@ -300,6 +300,17 @@ def main():
     cold_iters = max(1, args.product_iters // 10)
     us_dose_c = ctx.time_product_cold(0, cold_iters, scrub)
     us_grad_c = ctx.time_product_cold(1, cold_iters, scrub)
+    # every product variant, forced (the tuned choice above is one of them)
+    variants = {}
+    for dv, gd in ((0, 4), (1, 8), (2, 16)):
+        vc = dao.DaoContext.from_phantom(ph, dtype="f32", stream=stream, product_tune=0, dose_variant=dv,
+                                         gradient_depth=gd)
+        variants[f"dose{dv}_depth{gd}"] = {
+            "dose_us": vc.time_product(0, args.product_iters), "gradient_us": vc.time_product(1, args.product_iters),
+            "dose_cold_us": vc.time_product_cold(0, cold_iters, scrub),
+            "gradient_cold_us": vc.time_product_cold(1, cold_iters, scrub)}
+        vc.close()
+    log(f"[bench] product variants (tuned: dose {info['dose_variant']}, depth {info['gradient_depth']}): {variants}")
     del scrub
     gbs_dose_c = info["bytes_dose"] / (us_dose_c * 1e-6) / 1e9
     gbs_grad_c = info["bytes_gradient"] / (us_grad_c * 1e-6) / 1e9
@@ -395,6 +406,8 @@ def main():
             "dose_cold_us": us_dose_c, "dose_cold_GBs": gbs_dose_c,
             "gradient_cold_us": us_grad_c, "gradient_cold_GBs": gbs_grad_c,
             "dose_frac_cold": gbs_dose_c / HBM_PEAK_GBS, "gradient_frac_cold": gbs_grad_c / HBM_PEAK_GBS,
+            "tuned": {"dose_variant": info["dose_variant"], "gradient_depth": info["gradient_depth"]},
+            "variants": variants,
             "note": ("D x = k_dose, D^T u = k_gradT, timed standalone: warm back-to-back (D fits the 256 MB "
                      "last-level cache) and cold (1 GiB scrub write before each timed launch)"),
         },

@@ -118,6 +118,18 @@ typedef struct {
                                fit (else as 1); 1 is that launch streaming D_K from device
                                memory on every pass; 0 launches each phase of each step
                                separately */
+    int32_t product_tune;   /* 1 (default): dao_create times the variants of the two
+                               sparse products (how many loads each thread keeps in
+                               flight, and for native values whether x is staged on
+                               chip) and keeps the fastest; 0: the two fields below
+                               choose.  The variants add the same terms in the same
+                               order, so results do not depend on the choice */
+    int32_t dose_variant;   /* with product_tune 0: forward product variant, 0 (default)
+                               x staged on chip, 1 staged with 8 entries per lane in
+                               flight, 2 x read from device memory with 8 in flight
+                               (native d_format only) */
+    int32_t gradient_depth; /* with product_tune 0: transposed product entries per thread
+                               in flight, 4 (default), 8 or 16 */
 } dao_options;
 
 /* How the restricted master evaluates its two products per step.
@@ -169,6 +181,10 @@ typedef struct {
     int32_t d_residual;       /* 1 when the FP16 residual is stored and used */
     int64_t bytes_dose;       /* algorithmic HBM bytes of one forward product */
     int64_t bytes_gradient;   /* algorithmic HBM bytes of one transposed product */
+    int32_t dose_variant;     /* forward product variant in use: 0 x staged on chip, 1 staged
+                                 with 8 entries per lane in flight, 2 x read from device
+                                 memory with 8 in flight */
+    int32_t gradient_depth;   /* transposed product: entries per thread in flight (4, 8, 16) */
 } dao_info_t;
 dao_status dao_info(const dao_ctx* ctx, dao_info_t* out);
 

@@ -48,7 +48,8 @@ class dao_options(ctypes.Structure):
                 ("max_steps", c_int32), ("tau_rel", c_double), ("max_tighten", c_int32),
                 ("refresh_every", c_int32), ("ls_slots", c_int32), ("mem_cap_bytes", c_int64),
                 ("master", c_int32), ("d_format", c_int32), ("d_residual", c_int32),
-                ("persistent", c_int32)]
+                ("persistent", c_int32), ("product_tune", c_int32), ("dose_variant", c_int32),
+                ("gradient_depth", c_int32)]
 
 
 class dao_info_t(ctypes.Structure):
@@ -56,7 +57,8 @@ class dao_info_t(ctypes.Structure):
                 ("n_rows", c_int64), ("n_beams", c_int32), ("max_rows_per_beam", c_int32),
                 ("dtype", c_int32), ("n_slices", c_int32), ("sell_entries", c_int64),
                 ("device_bytes", c_int64), ("d_format", c_int32), ("d_residual", c_int32),
-                ("bytes_dose", c_int64), ("bytes_gradient", c_int64)]
+                ("bytes_dose", c_int64), ("bytes_gradient", c_int64),
+                ("dose_variant", c_int32), ("gradient_depth", c_int32)]
 
 
 class dao_server_options(ctypes.Structure):

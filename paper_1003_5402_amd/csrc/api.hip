@@ -96,6 +96,8 @@ struct dao_ctx {
     int prof_kernel = -1;              // aperture-master kernel timed with events (-1: none)
     double prof_phase_us[PROF_PHASES] = {};   // persistent master split of the last window
     int device = 0;                    // HIP device of the context
+    int dose_var = 0;                  // k_dose variant (0 staged, 1 staged + deep loads, 2 global x + deep)
+    int gradT_pf = 4;                  // k_gradT entries in flight per thread (4, 8 or 16)
     int last_steps = 0;                // steps of the previous master solve (chunk size guess)
     std::vector<hipEvent_t> prof_events;
     size_t prof_used = 0;
@@ -254,27 +256,108 @@ void with_values(const dao_ctx* c, F&& f) {
     f(ValueTag<T, false>{});
 }
 
-// d_out (T, caller order) = D x (x: T, caller order) through k_dose.
+// d_out (T, caller order) = D x (x: T, caller order) through k_dose, in
+// variant `var` (-1: the context's tuned one).  Every variant adds the same
+// products in the same order.  Variant 2 reads x from device memory and
+// exists for native values only (a 16-bit format folds its scale into the
+// staged copy).
 template <class T>
-void launch_dose(dao_ctx* c, const T* x, T* d_out) {
+void launch_dose(dao_ctx* c, const T* x, T* d_out, int var = -1) {
+    if (var < 0) var = c->dose_var;
     with_values<T>(c, [&](auto tag) {
         using VT = typename decltype(tag)::VT;
         constexpr bool LO = decltype(tag)::LO;
-        k_dose<T, VT, LO><<<c->slab_blocks(), SLAB_THREADS, c->stage_x() ? c->N * sizeof(T) : 0, c->stream>>>(
-            sell_view<VT>(c), c->perm, c->Vpad, x, int(c->N), c->stage_x(), c->col_scale, d_out);
+        const bool stage = c->stage_x() && !(var == 2 && c->opt.d_format == DAO_DFMT_NATIVE);
+        const size_t lds = stage ? c->N * sizeof(T) : 0;
+        if (var == 0)
+            k_dose<T, VT, LO, 0><<<c->slab_blocks(), SLAB_THREADS, lds, c->stream>>>(
+                sell_view<VT>(c), c->perm, c->Vpad, x, int(c->N), stage, c->col_scale, d_out);
+        else
+            k_dose<T, VT, LO, 8><<<c->slab_blocks(), SLAB_THREADS, lds, c->stream>>>(
+                sell_view<VT>(c), c->perm, c->Vpad, x, int(c->N), stage, c->col_scale, d_out);
     });
 }
 
-// g = D^T u (internal row order in, beamlet order out) through k_gradT.
+// g = D^T u (internal row order in, beamlet order out) through k_gradT with
+// pf entries per thread in flight (-1: the context's tuned depth); the sums
+// do not depend on pf.
 template <class T, class UT, class Acc, class GT>
-void launch_gradT(dao_ctx* c, const UT* u, GT* g) {
+void launch_gradT(dao_ctx* c, const UT* u, GT* g, int pf = -1) {
+    if (pf < 0) pf = c->gradT_pf;
     with_values<T>(c, [&](auto tag) {
         using VT = typename decltype(tag)::VT;
         constexpr bool LO = decltype(tag)::LO;
-        k_gradT<VT, UT, Acc, GT, false, LO><<<c->N, BLOCK, 0, c->stream>>>(
-            c->csc_ptr, c->csc_row, static_cast<const VT*>(c->csc_val), static_cast<const __half*>(c->csc_lo), u,
-            g, nullptr, c->col_scale);
+        const VT* cv = static_cast<const VT*>(c->csc_val);
+        const __half* cl = static_cast<const __half*>(c->csc_lo);
+        if (pf >= 16)
+            k_gradT<VT, UT, Acc, GT, false, LO, 16><<<c->N, BLOCK, 0, c->stream>>>(
+                c->csc_ptr, c->csc_row, cv, cl, u, g, nullptr, c->col_scale);
+        else if (pf >= 8)
+            k_gradT<VT, UT, Acc, GT, false, LO, 8><<<c->N, BLOCK, 0, c->stream>>>(
+                c->csc_ptr, c->csc_row, cv, cl, u, g, nullptr, c->col_scale);
+        else
+            k_gradT<VT, UT, Acc, GT, false, LO, 4><<<c->N, BLOCK, 0, c->stream>>>(
+                c->csc_ptr, c->csc_row, cv, cl, u, g, nullptr, c->col_scale);
     });
+}
+
+// Picks the fastest k_dose variant and k_gradT depth for this matrix by
+// timing each a few times on the context's stream (inputs are zeros; every
+// variant computes the same sums, so the choice changes time only).  The
+// forward product's output takes a transient buffer of n_vox values.
+template <class T>
+dao_status tune_products(dao_ctx* c) {
+    void* out = nullptr;
+    HIPCHK(c, hipMalloc(&out, std::max<int64_t>(1, c->V) * sizeof(T)));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    dao_status s = DAO_OK;
+    auto fail = [&](hipError_t e) {
+        s = c->fail(DAO_EDEVICE, std::string("product tuning: ") + hipGetErrorString(e));
+    };
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    if (he == hipSuccess) he = hipMemsetAsync(c->u, 0, c->Vpad * sizeof(T), c->stream);
+    const int nd = c->opt.d_format == DAO_DFMT_NATIVE ? 3 : 2;
+    const int pfs[3] = {4, 8, 16};
+    double best_d[3] = {1e30, 1e30, 1e30}, best_g[3] = {1e30, 1e30, 1e30};
+    constexpr int REPS = 3, LAUNCHES = 8;
+    auto time_one = [&](auto&& launch) -> double {
+        launch();
+        if (he == hipSuccess) he = hipEventRecord(e0, c->stream);
+        for (int i = 0; i < LAUNCHES; ++i) launch();
+        if (he == hipSuccess) he = hipEventRecord(e1, c->stream);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        return double(ms);
+    };
+    for (int r = 0; r < REPS && he == hipSuccess; ++r) {
+        for (int v = 0; v < nd; ++v)
+            best_d[v] = std::min(best_d[v], time_one([&] {
+                launch_dose<T>(c, static_cast<const T*>(c->dx), static_cast<T*>(out), v);
+            }));
+        for (int v = 0; v < 3; ++v)
+            best_g[v] = std::min(best_g[v], time_one([&] {
+                launch_gradT<T, T, T, T>(c, static_cast<const T*>(c->u), static_cast<T*>(c->g), pfs[v]);
+            }));
+    }
+    if (he == hipSuccess) he = hipGetLastError();
+    if (he != hipSuccess) fail(he);
+    if (s == DAO_OK) {
+        // a variant replaces the plain one only when clearly faster (2 %)
+        c->dose_var = 0;
+        for (int v = 1; v < nd; ++v)
+            if (best_d[v] < 0.98 * best_d[c->dose_var]) c->dose_var = v;
+        int bg = 0;
+        for (int v = 1; v < 3; ++v)
+            if (best_g[v] < 0.98 * best_g[bg]) bg = v;
+        c->gradT_pf = pfs[bg];
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(out);
+    return s;
 }
 
 PoolView pool_view(dao_ctx* c) {
@@ -670,6 +753,12 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     HIPCHK(c, hipMemsetAsync(c->p, 0, km * 8, c->stream));
     HIPCHK(c, hipMemsetAsync(c->q, 0, c->Vpad * ts, c->stream));
     HIPCHK(c, hipMemsetAsync(c->dx, 0, c->N * ts, c->stream));
+    c->dose_var = c->opt.dose_variant;
+    c->gradT_pf = c->opt.gradient_depth;
+    if (c->opt.product_tune) {
+        s = tune_products<T>(c);
+        if (s != DAO_OK) return s;
+    }
     s = reset_state<T>(c);
     if (s != DAO_OK) return s;
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1049,6 +1138,9 @@ void dao_default_options(dao_options* o) {
     o->d_format = DAO_DFMT_NATIVE;
     o->d_residual = 0;
     o->persistent = 2;
+    o->product_tune = 1;
+    o->dose_variant = 0;
+    o->gradient_depth = 4;
 }
 
 const char* dao_create_error(void) { return g_create_error.c_str(); }
@@ -1138,6 +1230,8 @@ dao_status dao_info(const dao_ctx* c, dao_info_t* o) {
     const int64_t ts = int64_t(c->tsize);
     o->d_format = c->opt.d_format;
     o->d_residual = c->opt.d_residual;
+    o->dose_variant = c->dose_var;
+    o->gradient_depth = c->gradT_pf;
     // stored bytes per value: the ctx type, or 16 bits (+ 16 for the residual)
     const bool narrow = c->opt.d_format != DAO_DFMT_NATIVE;
     const int64_t vs = narrow ? 2 + (c->opt.d_residual ? 2 : 0) : ts;

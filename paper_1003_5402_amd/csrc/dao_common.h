@@ -55,9 +55,8 @@ struct MasterState {
     double gphi0;          // <grad_y, p>
     double F;              // objective at the current dose
     double F_const;        // objective of voxels no beamlet reaches (dose 0)
-    double last_step;
-    int32_t pad0;
-    int32_t pad1;
+    double last_step;      // length of the last step
+    double prev_step;      // length of the step before it
 };
 
 // Work counters of the aperture master's kernels, kept by workgroup 0 of

@@ -277,11 +277,42 @@ __device__ __forceinline__ Acc sell_dot(const T* __restrict__ val, const __half*
     return acc;
 }
 
+// As sell_dot, with the loads of U entries (values, columns, then the U
+// gathers of x) in flight together before their products are added, in the
+// same order.
+template <class T, class XT, class Acc, bool LO, int U>
+__device__ __forceinline__ Acc sell_dot_deep(const T* __restrict__ val, const __half* __restrict__ lo,
+                                             const uint16_t* __restrict__ col, uint32_t base, int k0, int k1,
+                                             int lane, const XT* __restrict__ xs) {
+    const size_t o = base + uint32_t(k0) * SLICE + lane;
+    Acc acc = Acc(0);
+    for (int k = k0; k < k1; k += U) {
+        T v[U];
+        __half l[U];
+        uint16_t cc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool in = k + u < k1;
+            const size_t e = o + size_t(k - k0 + u) * SLICE;
+            v[u] = in ? val[e] : T(0);
+            cc[u] = in ? col[e] : uint16_t(0);
+            if (LO) l[u] = in ? lo[e] : __half(0.0f);
+        }
+        XT xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = k + u < k1 ? xs[cc[u]] : XT(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k + u < k1) acc += Acc(dval2<T, LO>(v[u], &l[u])) * Acc(xv[u]);
+    }
+    return acc;
+}
+
 // Row sums of this workgroup's slab (SLAB_THREADS threads).  Wavefront w
 // takes slice w / KSPLIT of the slab and the (w % KSPLIT)-th quarter of its
 // entries; partials meet in s_part and are added in k order.  Returns the
 // row sum in threads t < SLAB (row blockIdx.x * SLAB + t).
-template <class T, class XT, class Acc, bool LO = false>
+template <class T, class XT, class Acc, bool LO = false, int DEEP = 0>
 __device__ __forceinline__ Acc slab_rows(const SellView<T>& S, const XT* __restrict__ xs, Acc* s_part) {
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int j = wave / KSPLIT, kp = wave % KSPLIT;
@@ -291,7 +322,10 @@ __device__ __forceinline__ Acc slab_rows(const SellView<T>& S, const XT* __restr
         const int w = S.slice_w[s];
         const int kc = (w + KSPLIT - 1) / KSPLIT;
         const int k0 = min(w, kp * kc), k1 = min(w, k0 + kc);
-        acc = sell_dot<T, XT, Acc, LO>(S.val, S.lo, S.col, S.slice_ptr[s], k0, k1, lane, xs);
+        if constexpr (DEEP > 0)
+            acc = sell_dot_deep<T, XT, Acc, LO, DEEP>(S.val, S.lo, S.col, S.slice_ptr[s], k0, k1, lane, xs);
+        else
+            acc = sell_dot<T, XT, Acc, LO>(S.val, S.lo, S.col, S.slice_ptr[s], k0, k1, lane, xs);
     }
     s_part[kp * SLAB + j * SLICE + lane] = acc;
     __syncthreads();
@@ -323,8 +357,9 @@ __device__ __forceinline__ const XT* stage_vec(const ST* __restrict__ src, int n
 // ---------------------------------------------------------------------------
 
 // d_ext[perm[r]] = (D x)_r for every row of the slab; x staged in LDS
-// (times the per-beamlet scale of a 16-bit value format).
-template <class T, class VT = T, bool LO = false>
+// (times the per-beamlet scale of a 16-bit value format).  DEEP > 0 keeps
+// DEEP entries per lane in flight (the autotuned variants; same sums).
+template <class T, class VT = T, bool LO = false, int DEEP = 0>
 __global__ void __launch_bounds__(SLAB_THREADS) k_dose(SellView<VT> S, const int32_t* __restrict__ perm,
                                                        int64_t Vpad, const T* __restrict__ x, int N,
                                                        bool stage, const float* __restrict__ scale,
@@ -332,7 +367,7 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_dose(SellView<VT> S, const int
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ T s_part[KSPLIT * SLAB];
     const T* xs = stage_vec<T, T>(x, N, reinterpret_cast<T*>(smem), stage, scale);
-    const T sum = slab_rows<VT, T, T, LO>(S, xs, s_part);
+    const T sum = slab_rows<VT, T, T, LO, DEEP>(S, xs, s_part);
     const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
     if (threadIdx.x < SLAB && row < Vpad) {
         const int32_t j = perm[row];
@@ -411,7 +446,7 @@ __global__ void __launch_bounds__(BLOCK) k_objective_int(const double* __restric
 // GATED (the master's copy) runs only while a finished line search awaits
 // its update (phase PH_UPD of an unfinished master), like k_update.  With a
 // 16-bit value format the column sum is multiplied by the beamlet's scale.
-template <class T, class UT, class Acc, class GT, bool GATED, bool LO = false>
+template <class T, class UT, class Acc, class GT, bool GATED, bool LO = false, int PF = 4>
 __global__ void __launch_bounds__(BLOCK) k_gradT(const int32_t* __restrict__ cptr,
                                                  const int32_t* __restrict__ crow,
                                                  const T* __restrict__ cval, const __half* __restrict__ clo,
@@ -427,13 +462,32 @@ __global__ void __launch_bounds__(BLOCK) k_gradT(const int32_t* __restrict__ cpt
     const int e0 = cptr[i], e1 = cptr[i + 1];
     Acc acc = Acc(0);
     int e = e0 + threadIdx.x;
-    for (; e + 3 * BLOCK < e1; e += 4 * BLOCK) {
-        const int32_t r0 = crow[e], r1 = crow[e + BLOCK], r2 = crow[e + 2 * BLOCK], r3 = crow[e + 3 * BLOCK];
-        const T v0 = cval[e], v1 = cval[e + BLOCK], v2 = cval[e + 2 * BLOCK], v3 = cval[e + 3 * BLOCK];
-        acc += Acc(dval2<T, LO>(v0, clo + e)) * Acc(u[r0]);
-        acc += Acc(dval2<T, LO>(v1, clo + e + BLOCK)) * Acc(u[r1]);
-        acc += Acc(dval2<T, LO>(v2, clo + e + 2 * BLOCK)) * Acc(u[r2]);
-        acc += Acc(dval2<T, LO>(v3, clo + e + 3 * BLOCK)) * Acc(u[r3]);
+    if (PF <= 4) {
+        for (; e + 3 * BLOCK < e1; e += 4 * BLOCK) {
+            const int32_t r0 = crow[e], r1 = crow[e + BLOCK], r2 = crow[e + 2 * BLOCK], r3 = crow[e + 3 * BLOCK];
+            const T v0 = cval[e], v1 = cval[e + BLOCK], v2 = cval[e + 2 * BLOCK], v3 = cval[e + 3 * BLOCK];
+            acc += Acc(dval2<T, LO>(v0, clo + e)) * Acc(u[r0]);
+            acc += Acc(dval2<T, LO>(v1, clo + e + BLOCK)) * Acc(u[r1]);
+            acc += Acc(dval2<T, LO>(v2, clo + e + 2 * BLOCK)) * Acc(u[r2]);
+            acc += Acc(dval2<T, LO>(v3, clo + e + 3 * BLOCK)) * Acc(u[r3]);
+        }
+    } else {
+        // PF entries per thread in flight: rows and values, then the gathers
+        // of u, then the products in entry order (the same sums)
+        for (; e + (PF - 1) * BLOCK < e1; e += PF * BLOCK) {
+            int32_t r[PF];
+            T v[PF];
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                r[q] = crow[e + q * BLOCK];
+                v[q] = cval[e + q * BLOCK];
+            }
+            UT w[PF];
+#pragma unroll
+            for (int q = 0; q < PF; ++q) w[q] = u[r[q]];
+#pragma unroll
+            for (int q = 0; q < PF; ++q) acc += Acc(dval2<T, LO>(v[q], clo + e + q * BLOCK)) * Acc(w[q]);
+        }
     }
     for (; e < e1; e += BLOCK) acc += Acc(dval2<T, LO>(cval[e], clo + e)) * Acc(u[crow[e]]);
     acc = wave_sum(acc);
@@ -813,6 +867,7 @@ __device__ __forceinline__ void finish_step(const PoolView& P, MasterState& m, d
     if (threadIdx.x == 0) {
         m.steps += 1;
         m.total_steps += 1;
+        m.prev_step = m.last_step;
         m.last_step = t;
         m.refresh = (m.steps % m.refresh_every) == 0;
         s_refresh = m.refresh;

@@ -343,6 +343,7 @@ __device__ __forceinline__ void finish_step_ap(MasterState& m, double* y, const 
     if (threadIdx.x == 0) {
         m.steps += 1;
         m.total_steps += 1;
+        m.prev_step = m.last_step;
         m.last_step = t;
         m.refresh = (m.steps % m.refresh_every) == 0 ? 1 : 0;
         m.phase = PH_UPD;

@@ -155,3 +155,48 @@ def test_price_own_prices_at_zero_dose(contexts, name, dtype):
     ref = oracle.price(P, w)
     assert (got["beam"], got["leaves"]) == (ref["aperture"].beam, ref["aperture"].leaves)
     assert abs(got["rc"] - ref["rc"]) <= 1e-12 * abs(ref["rc"])
+
+
+# Every variant of the two products (loads in flight per thread, x staged on
+# chip or read from device memory) adds the same terms in the same order:
+# results agree bit for bit with the plain variant, in every value format.
+VARIANTS = [(0, 4), (1, 8), (2, 16)]
+
+
+@pytest.mark.parametrize("name,dtype,fmt", [("tiny", "f64", 0), ("prostate", "f32", 0), ("prostate", "f32", 1)])
+def test_product_variants_identical(name, dtype, fmt):
+    torch = torch_cuda()
+    ph = cached_phantom(name)
+    rng = np.random.default_rng(11)
+    x = dev(rng.uniform(0.0, 0.05, ph.n_blt), torch.float64 if dtype == "f64" else torch.float32)
+    outs = []
+    for dv, gd in VARIANTS:
+        if dv == 2 and fmt != 0:
+            continue
+        print(f"[variant] {name} {dtype} fmt={fmt} dose={dv} depth={gd}", flush=True)
+        ctx = ctx_for(ph, dtype=dtype, d_format=fmt, product_tune=0, dose_variant=dv, gradient_depth=gd)
+        try:
+            inf = ctx.info()
+            assert (inf["dose_variant"], inf["gradient_depth"]) == (dv, gd)
+            d = torch.full((ph.n_vox,), float("nan"), dtype=x.dtype, device="cuda:0")
+            ctx.dose(x, d)
+            g = torch.full((ph.n_blt,), float("nan"), dtype=x.dtype, device="cuda:0")
+            F = ctx.gradient(d, g)
+            torch.cuda.synchronize()
+            outs.append((d.cpu(), g.cpu(), F))
+        finally:
+            ctx.close()
+    d0, g0, F0 = outs[0]
+    assert torch.isfinite(d0).all() and torch.isfinite(g0).all()
+    for d, g, F in outs[1:]:
+        assert torch.equal(d, d0) and torch.equal(g, g0) and F == F0
+
+
+def test_tuned_variant_reported():
+    ph = cached_phantom("tiny")
+    ctx = ctx_for(ph, dtype="f32")
+    try:
+        inf = ctx.info()
+        assert inf["dose_variant"] in (0, 1, 2) and inf["gradient_depth"] in (4, 8, 16)
+    finally:
+        ctx.close()
