@@ -264,7 +264,7 @@ dao_status dao_time_product_cold(dao_ctx* ctx, int32_t kernel, int32_t iters, vo
  * HIP events on the context stream, and the kernel accumulates its
  * algorithmic bytes on the device (launches that find nothing to do add
  * none).  kernel: 0 update pass (apply step, grad F, F, grad_y partials),
- * 1 q pass (q = D_K p with the line-search evaluation at 0), 2 line-search
+ * 1 q pass (q = D_K p with the first line-search evaluation), 2 line-search
  * pass, 3 direction, 4 the persistent master (one launch per master solve;
  * its bytes are the sum over its update, q and line-search passes).  dao_profile_stop synchronises and returns the number
  * of launches, how many did work, their summed event time (us) and summed

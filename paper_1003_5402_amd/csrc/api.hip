@@ -566,6 +566,7 @@ dao_status reset_state(dao_ctx* c) {
     const int64_t eb = c->elem_blocks(c->Vpad);
     k_fill<double><<<eb, BLOCK, 0, c->stream>>>(c->d, c->Vpad, 0.0);
     k_fill<double><<<1, BLOCK, 0, c->stream>>>(c->y, c->opt.max_apertures, 0.0);
+    k_clear_steps<<<1, 1, 0, c->stream>>>(c->ms);
     LAUNCHCHK(c);
     c->K = 0;
     c->pool_beam.clear();

@@ -25,7 +25,7 @@ struct ObjClass {
 // sequence of launches; each launch runs only in its phase).
 enum Phase : int {
     PH_DIR = 0,   // gradient over the pool, projection, t_max, dx = A p
-    PH_Q = 1,     // q = D dx and the first line-search evaluation at t = 0
+    PH_Q = 1,     // q = D dx and the first line-search evaluation
     PH_LS = 2,    // further line-search evaluations
     PH_UPD = 3,   // d += t q (or d = D(A y) on refresh steps), grad F, F
     PH_TP = 4     // g = D^T grad F

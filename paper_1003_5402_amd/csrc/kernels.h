@@ -217,6 +217,18 @@ __device__ __forceinline__ void ls_voxel(const ObjClass& c, double d, double q, 
     ls_voxel_bp(c, d, q, bu, bo, t, r);
 }
 
+// First trial point of a line search: the length of the step before the
+// last, capped at t_max, when positive, else 0.  Gradient projection with
+// exact line searches tends to alternate between two step lengths, so that
+// point usually lies inside the linear piece of phi' that holds the
+// minimiser, where the Newton point from it is exact and one evaluation
+// ends the search.  The search needs no evaluation at 0: phi'(0) < 0 holds
+// for every direction that is not zero.
+__device__ __forceinline__ double ls_first_trial(double prev_step, double t_max) {
+    const double tb = fmin(prev_step, t_max);
+    return tb > 0.0 ? tb : 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // forward products over slabs
 // ---------------------------------------------------------------------------
@@ -772,7 +784,7 @@ __global__ void __launch_bounds__(1024) k_dir(PoolView P, const T* __restrict__ 
         } else {
             s_ms.t_max = tmax;
             s_ms.gphi0 = gp;
-            s_ms.t = 0.0;
+            s_ms.t = ls_first_trial(s_ms.prev_step, tmax);
             s_ms.lo = 0.0;
             s_ms.hi = tmax;
             s_ms.hi_known = 0;
@@ -880,7 +892,7 @@ __device__ __forceinline__ void finish_step(const PoolView& P, MasterState& m, d
     if (threadIdx.x == 0) m.phase = PH_UPD;
 }
 
-// q = D dx and the line-search evaluation at t = 0 (slab layout).
+// q = D dx and the first line-search evaluation (slab layout).
 template <class T>
 __global__ void __launch_bounds__(SLAB_THREADS) k_qstep(SellView<T> S, int64_t Vpad, const T* __restrict__ dx,
                                                         int N, bool stage, const double* __restrict__ d,

@@ -18,7 +18,7 @@
 //              objective partials and the partials of grad_y per workgroup.
 //   k_dir_ap   (PH_UPD) sums the partials in a fixed order, tests KKT and
 //              builds the projected direction (-> PH_Q).
-//   k_qstep_ap (PH_Q)   q = D_K p and the line-search evaluation at t = 0.
+//   k_qstep_ap (PH_Q)   q = D_K p and the first line-search evaluation.
 //   k_lseval   (PH_LS)  further evaluations (shared with the beamlet master).
 #pragma once
 
@@ -313,7 +313,7 @@ __global__ void __launch_bounds__(1024) k_dir_ap(const double* __restrict__ part
             } else {
                 s_ms.t_max = tmax;
                 s_ms.gphi0 = gp;
-                s_ms.t = 0.0;
+                s_ms.t = ls_first_trial(s_ms.prev_step, tmax);
                 s_ms.lo = 0.0;
                 s_ms.hi = tmax;
                 s_ms.hi_known = 0;
@@ -350,7 +350,7 @@ __device__ __forceinline__ void finish_step_ap(MasterState& m, double* y, const 
     }
 }
 
-// q = D_K p and the line-search evaluation at t = 0 (PH_Q).
+// q = D_K p and the first line-search evaluation (PH_Q).
 template <class T>
 __global__ void __launch_bounds__(BLOCK) k_qstep_ap(const T* __restrict__ dk, int64_t Vpad,
                                                     const double* __restrict__ d,
@@ -475,6 +475,15 @@ __global__ void __launch_bounds__(BLOCK) k_lseval_ap(const double* __restrict__ 
 
 // Reset for a solve of the aperture master: the first update pass keeps d
 // (mode 2) and only produces F and grad_y at the current point.
+// Forget the step-length history (a new plan starts from an empty pool, and
+// its line searches must not depend on what ran before).
+__global__ void k_clear_steps(MasterState* ms) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ms->last_step = 0.0;
+        ms->prev_step = 0.0;
+    }
+}
+
 __global__ void k_master_init_ap(MasterState* ms, int K, double tol, int max_steps) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         ms->phase = PH_UPD;

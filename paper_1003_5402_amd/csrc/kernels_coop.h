@@ -50,22 +50,19 @@ __device__ __forceinline__ uint32_t aload_u(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Combine of one record field: sums, except the line-search records'
-// nearest-breakpoint fields (3: minimum, 4: maximum of each NPART-field
-// record; a line-search reduction carries one or two records).
-__device__ __forceinline__ int ls_op(bool ls, int i) {
-    const int f = i % NPART;
-    return (ls && f == 3) ? 1 : (ls && f == 4) ? 2 : 0;
-}
+// Combine of one record field: sums, except the line-search record's
+// nearest-breakpoint fields (3: minimum, 4: maximum).
 template <bool LS>
 __device__ __forceinline__ double rec_comb(int i, double a, double b) {
-    const int op = ls_op(LS, i);
-    return op == 1 ? fmin(a, b) : op == 2 ? fmax(a, b) : a + b;
+    if (LS && i == 3) return fmin(a, b);
+    if (LS && i == 4) return fmax(a, b);
+    return a + b;
 }
 template <bool LS>
 __device__ __forceinline__ double rec_init(int i) {
-    const int op = ls_op(LS, i);
-    return op == 1 ? INFINITY : op == 2 ? -INFINITY : 0.0;
+    if (LS && i == 3) return INFINITY;
+    if (LS && i == 4) return -INFINITY;
+    return 0.0;
 }
 
 // Wavefront reductions through DPP lane moves (no LDS round trip).  The
@@ -101,9 +98,8 @@ __device__ __forceinline__ double wave_reduce_dpp(double v) {
     return lane63(v);
 }
 __device__ __forceinline__ double field_reduce_dpp(bool ls, int f, double v) {
-    const int op = ls_op(ls, f);
-    if (op == 1) return wave_reduce_dpp<1>(v);
-    if (op == 2) return wave_reduce_dpp<2>(v);
+    if (ls && f == 3) return wave_reduce_dpp<1>(v);
+    if (ls && f == 4) return wave_reduce_dpp<2>(v);
     return wave_reduce_dpp<0>(v);
 }
 
@@ -111,13 +107,12 @@ __device__ __forceinline__ double field_reduce_dpp(bool ls, int f, double v) {
 // (f < nf) into out[f] (LDS): lane group f of 8 lanes holds the 8 partials
 // of field f and combines them by three DPP moves inside the group (quad
 // swaps, then half-row mirror).  With ls, fields 3 and 4 are a minimum and
-// a maximum, the others sums (per NPART-field record).  Needs 8 wavefronts;
-// all threads call it.
+// a maximum, the others sums.  Needs 8 wavefronts; all threads call it.
 __device__ __forceinline__ void combine_waves8(const double* part, int stride, int nf, bool ls, double* out) {
     const int t = threadIdx.x, wave = t / WAVE;
     if (wave < (nf * 8 + WAVE - 1) / WAVE) {   // whole wavefronts take part in the moves
         const int f = t / 8, w = t % 8;
-        const int op = ls_op(ls, f);
+        const int op = (ls && f == 3) ? 1 : (ls && f == 4) ? 2 : 0;
         const double id = op == 0 ? 0.0 : op == 1 ? INFINITY : -INFINITY;
         double x = f < nf ? part[w * stride + f] : id;
         double m = dpp_move<0xB1, 0xF>(x, id);    // quad_perm [1,0,3,2]
@@ -131,11 +126,11 @@ __device__ __forceinline__ void combine_waves8(const double* part, int stride, i
     __syncthreads();
 }
 
-// Line-search record(s) of a workgroup (fields as Rec: s0, s1, s2, mn, mx,
-// s5) into out[0..6), and with two, the second record into out[6..12) (LDS);
-// waves combined in a fixed order.  Needs 8 wavefronts; all threads call it.
-__device__ __forceinline__ void block_rec_dpp(const Rec& r, const Rec& r2, bool two, double* out) {
-    __shared__ double s_w[1024 / WAVE][2 * NPART];
+// Line-search record of a workgroup (fields as Rec: s0, s1, s2, mn, mx, s5)
+// into out[0..6) (LDS), waves combined in a fixed order.  Needs 8
+// wavefronts; all threads call it.
+__device__ __forceinline__ void block_rec_dpp(const Rec& r, double* out) {
+    __shared__ double s_w[1024 / WAVE][6];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const double v0 = wave_reduce_dpp<0>(r.s0), v1 = wave_reduce_dpp<0>(r.s1), v2 = wave_reduce_dpp<0>(r.s2);
     const double v3 = wave_reduce_dpp<1>(r.mn), v4 = wave_reduce_dpp<2>(r.mx), v5 = wave_reduce_dpp<0>(r.s5);
@@ -147,22 +142,8 @@ __device__ __forceinline__ void block_rec_dpp(const Rec& r, const Rec& r2, bool 
         s_w[wave][4] = v4;
         s_w[wave][5] = v5;
     }
-    if (two) {
-        const double w0 = wave_reduce_dpp<0>(r2.s0), w1 = wave_reduce_dpp<0>(r2.s1),
-                     w2 = wave_reduce_dpp<0>(r2.s2);
-        const double w3 = wave_reduce_dpp<1>(r2.mn), w4 = wave_reduce_dpp<2>(r2.mx),
-                     w5 = wave_reduce_dpp<0>(r2.s5);
-        if (lane == 0) {
-            s_w[wave][6] = w0;
-            s_w[wave][7] = w1;
-            s_w[wave][8] = w2;
-            s_w[wave][9] = w3;
-            s_w[wave][10] = w4;
-            s_w[wave][11] = w5;
-        }
-    }
     __syncthreads();
-    combine_waves8(&s_w[0][0], 2 * NPART, two ? 2 * NPART : NPART, true, out);
+    combine_waves8(&s_w[0][0], 6, 6, true, out);
 }
 
 // Fixed-order combine of nb records of W doubles stored field-major (field i
@@ -243,30 +224,18 @@ __device__ bool grid_reduce(CoopSync* S, double* recs, const double* mine, int W
     }
     __syncthreads();
     if (!s_ok) return false;
-    combine_fields<LS, LS ? (2 * NPART + COOP_THREADS / WAVE - 1) / (COOP_THREADS / WAVE)
+    combine_fields<LS, LS ? (6 + COOP_THREADS / WAVE - 1) / (COOP_THREADS / WAVE)
                              : (KS + 1 + COOP_THREADS / WAVE - 1) / (COOP_THREADS / WAVE)>(buf, nb, W, total);
     return true;
 }
 
-
-// Decision after a first evaluation that took two trial points in one pass:
-// ea at m.t (= 0) and eb at tb (0 < tb <= t_max).  The first is decided as a
-// single evaluation; if that does not end the search, the second narrows the
-// bracket and ends it when the Newton point from tb stays inside tb's
-// linear piece (the same exact minimiser).  Otherwise the next trial is the
-// Newton point from 0 when it lies inside the narrowed bracket, else the
-// point the second evaluation proposes.  Counts as one evaluation.
-template <class S>
-__device__ __forceinline__ int ls_decide_pair(S& m, const Rec& ea, double tb, const Rec& eb) {
-    if (ls_decide(m, ea)) return 1;
-    const double next_a = m.t;
-    m.t = tb;
-    const int fin = ls_decide(m, eb);
-    m.ls_iter -= 1;
-    m.total_ls -= 1;
-    if (!fin && next_a > m.lo && next_a < m.hi) m.t = next_a;
-    return fin;
-}
+// Line-search state kept in registers by every thread (the fields
+// ls_decide uses).
+struct LsRegs {
+    double t, t_max, lo, hi;
+    int hi_known, ls_iter;
+    int64_t total_ls;
+};
 
 template <class T>
 struct CoopArgs {
@@ -375,10 +344,9 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
         cnt_bytes[threadIdx.x] = 0.0;
         cnt_real[threadIdx.x] = 0;
     }
-    // the line-search state lives in s_ms (LDS): thread 0 takes each
-    // decision from the broadcast totals, the others read the outcome after a
-    // barrier (keeps the state out of the registers of every thread)
-    __shared__ int s_fin;
+    // every thread takes the same line-search decisions and step counts from
+    // the same totals, in registers; thread 0 mirrors them into s_ms
+    LsRegs ls{0.0, 0.0, 0.0, 0.0, 0, 0, s_ms.total_ls};
     int steps = s_ms.steps;
     const int refresh_every = s_ms.refresh_every;
     // phase timing (workgroup 0, thread 0): 0 update pass, 1 its reduction,
@@ -402,7 +370,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     while (alive) {
         // ---------------- update pass: apply the step, dF/dz, F, grad_y partials
         {
-            const double t = s_ms.t;
+            const double t = ls.t;
             double yv[G::EPL], acc[G::EPL];
 #pragma unroll
             for (int e = 0; e < G::EPL; ++e) {
@@ -524,7 +492,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                 } else {
                     s_ms.t_max = tmax;
                     s_ms.gphi0 = gp;
-                    s_ms.t = 0.0;
+                    s_ms.t = ls_first_trial(s_ms.prev_step, tmax);
                     s_ms.lo = 0.0;
                     s_ms.hi = tmax;
                     s_ms.hi_known = 0;
@@ -536,18 +504,17 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
         __syncthreads();
         tick(2);
         if (!s_go) break;
+        ls.t_max = s_ms.t_max;
+        ls.t = ls_first_trial(s_ms.prev_step, ls.t_max);
+        ls.lo = 0.0;
+        ls.hi = ls.t_max;
+        ls.hi_known = 0;
+        ls.ls_iter = 0;
         // ---------------- line search: first evaluation computes q = D_K p
-        // and evaluates at 0 and at a second trial point tb, the length of
-        // the step before the last (gradient projection with exact line
-        // searches tends to alternate between two step lengths, and a trial
-        // point inside the minimiser's linear piece ends the search)
-        const double tb = fmin(s_ms.prev_step, s_ms.t_max);
-        const bool pair = tb > 0.0;   // false for 0 and NaN
         bool first = true;
         for (;;) {
-            const bool two = first && pair;
-            const double t = s_ms.t;
-            Rec r = rec_identity(), r2 = rec_identity();
+            const double t = ls.t;
+            Rec r = rec_identity();
             double pv[G::EPL];
 #pragma unroll
             for (int e = 0; e < G::EPL; ++e) pv[e] = s_p[c * G::EPL + e];
@@ -594,11 +561,6 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                     }
                     ls_voxel_bp(cc, dv, double(qt), bul[rr], bol[rr], t, r);
                 }
-                // the second trial point in a sweep of its own (fewer live
-                // registers than inside the q computation)
-                if (two)
-                    for (int64_t rr = threadIdx.x; rr < nrows; rr += blockDim.x)
-                        ls_voxel_bp(cl[cll[rr]], dl[rr], double(ql[rr]), bul[rr], bol[rr], tb, r2);
             } else {
                 for (int64_t bt = bat0 + wave; bt < bat1; bt += NW) {
                     const int64_t base = bt * ROWS;
@@ -629,12 +591,11 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                             qt = q_at(row);
                         }
                         ls_voxel(cl[cls_at(row)], d_at(row), double(qt), t, r);
-                        if (two) ls_voxel(cl[cls_at(row)], d_at(row), double(qt), tb, r2);
                     }
                     wave_sync();
                 }
             }
-            block_rec_dpp(r, r2, two, s_rec);
+            block_rec_dpp(r, s_rec);
             if (gb == 0 && threadIdx.x == 0) {
                 const int kk = first ? 1 : 2;
                 cnt_bytes[kk] += (first ? (16.0 * nc + 8.0 + 1.0 + double(sizeof(T)))
@@ -642,28 +603,20 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                 cnt_real[kk] += 1;
             }
             tick(first ? 3 : 6);
-            if (!grid_reduce<true>(A.sync, A.recs, s_rec, two ? 2 * NPART : NPART, s_tot, seq, gb, gn)) {
+            if (!grid_reduce<true>(A.sync, A.recs, s_rec, 6, s_tot, seq, gb, gn)) {
                 alive = false;
                 break;
             }
             tick(4);
-            if (threadIdx.x == 0) {
-                const Rec tot{s_tot[0], s_tot[1], s_tot[2], s_tot[3], s_tot[4], s_tot[5]};
-                if (two) {
-                    const Rec tot2{s_tot[6], s_tot[7], s_tot[8], s_tot[9], s_tot[10], s_tot[11]};
-                    s_fin = ls_decide_pair(s_ms, tot, tb, tot2);
-                } else {
-                    s_fin = ls_decide(s_ms, tot);
-                }
-            }
-            __syncthreads();
+            const Rec tot{s_tot[0], s_tot[1], s_tot[2], s_tot[3], s_tot[4], s_tot[5]};
+            const int fin = ls_decide(ls, tot);
             first = false;
-            if (s_fin) break;
+            if (fin) break;
         }
         if (!alive) break;
         // ---------------- step: y update, counters, next update mode
         {
-            const double t = s_ms.t, tmax = s_ms.t_max;
+            const double t = ls.t, tmax = ls.t_max;
             if (threadIdx.x < K) {
                 const int k = threadIdx.x;
                 const double pk = s_p[k];
@@ -680,6 +633,13 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                 s_ms.prev_step = s_ms.last_step;
                 s_ms.last_step = t;
                 s_ms.refresh = mode;
+                s_ms.t = t;
+                s_ms.t_max = tmax;
+                s_ms.lo = ls.lo;
+                s_ms.hi = ls.hi;
+                s_ms.hi_known = ls.hi_known;
+                s_ms.ls_iter = ls.ls_iter;
+                s_ms.total_ls = ls.total_ls;
             }
             __syncthreads();   // y visible to the next update pass
             tick(5);
