@@ -295,8 +295,8 @@ def main():
     gbs_dose = info["bytes_dose"] / (us_dose * 1e-6) / 1e9
     gbs_grad = info["bytes_gradient"] / (us_grad * 1e-6) / 1e9
     log(f"[bench] D x: {us_dose:.2f} us {gbs_dose:.0f} GB/s; D^T u: {us_grad:.2f} us {gbs_grad:.0f} GB/s")
-    # cold: a 1 GiB write (4x the last-level cache) before every timed launch
-    scrub = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    # cold: a 1 GiB read (4x the last-level cache) before every timed launch
+    scrub = torch.zeros(1 << 30, dtype=torch.uint8, device="cuda")
     cold_iters = max(1, args.product_iters // 10)
     us_dose_c = ctx.time_product_cold(0, cold_iters, scrub)
     us_grad_c = ctx.time_product_cold(1, cold_iters, scrub)
@@ -320,7 +320,7 @@ def main():
     # 16-bit storage of D (FP16 / BF16 value per beamlet scale, optional FP16
     # residual): product throughput and one plan each, on the same phantom
     reduced = {}
-    scrub = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    scrub = torch.zeros(1 << 30, dtype=torch.uint8, device="cuda")
     for fname, fmt in (("f16", dao.DAO_DFMT_F16), ("bf16", dao.DAO_DFMT_BF16)):
         for res in (0, 1):
             rc = dao.DaoContext.from_phantom(ph, dtype="f32", stream=stream, d_format=fmt, d_residual=res)
@@ -409,7 +409,7 @@ def main():
             "tuned": {"dose_variant": info["dose_variant"], "gradient_depth": info["gradient_depth"]},
             "variants": variants,
             "note": ("D x = k_dose, D^T u = k_gradT, timed standalone: warm back-to-back (D fits the 256 MB "
-                     "last-level cache) and cold (1 GiB scrub write before each timed launch)"),
+                     "last-level cache) and cold (1 GiB scrub read before each timed launch)"),
         },
         "master_kernels": kernels,
         "d_16bit": reduced,

@@ -250,11 +250,13 @@ dao_status dao_get_dose(dao_ctx* ctx, double* d_dev, double* F);
 dao_status dao_time_product(dao_ctx* ctx, int32_t kernel, int32_t iters, double* us_per_launch);
 
 /* As dao_time_product, with the caches cold: before each of the `iters`
- * launches a fill kernel writes scrub_bytes (>= 1 MiB, a multiple of 16) to
- * the caller-owned device buffer `scrub`, evicting D and the vectors from the
- * L2 and last-level caches; only the product launch is timed (one event pair
- * per launch, the mean is returned).  The scrub buffer's contents are
- * overwritten.  DAO_EINVAL for a bad kernel, iters < 1 or a bad scrub size. */
+ * launches a kernel reads scrub_bytes (>= 1 MiB, a multiple of 16) of the
+ * caller-owned device buffer `scrub`, displacing D and the vectors from the
+ * L2 and last-level caches with clean lines; only the product launch is
+ * timed (one event pair per launch, the mean is returned).  The scrub
+ * buffer is only read (its first 16 bytes may be written in the unlikely
+ * case that a thread's XOR of its words hits a fixed pattern).  DAO_EINVAL
+ * for a bad kernel, iters < 1 or a bad scrub size. */
 dao_status dao_time_product_cold(dao_ctx* ctx, int32_t kernel, int32_t iters, void* scrub,
                                  int64_t scrub_bytes, double* us_per_launch);
 

@@ -348,7 +348,7 @@ class DaoContext:
         return us.value
 
     def time_product_cold(self, kernel: int, iters: int, scrub) -> float:
-        """As time_product, with a write of the device tensor `scrub` (its
+        """As time_product, with a read of the device tensor `scrub` (its
         whole size) before every timed launch to evict the caches."""
         us = c_double()
         nbytes = scrub.numel() * scrub.element_size()

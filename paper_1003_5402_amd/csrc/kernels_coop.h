@@ -263,12 +263,17 @@ __host__ __device__ inline int64_t coop_batches_per_group(int64_t Vpad, int grid
     return (nbat + grid - 1) / grid;
 }
 
-// Dynamic LDS of the LDS-resident variant: the workgroup's D_K rows (nc
-// 16-byte vectors each), then d, the two breakpoints (double), q (T), class
-// (uint8).
+// 16-byte vectors per on-chip D_K row: the nc the pool needs, rounded up to
+// an odd count, so that lanes reading consecutive rows at the same slot
+// (the line search's one row per thread) fall in distinct LDS banks.
+__host__ __device__ inline int coop_row_vecs(int nc) { return nc | 1; }
+
+// Dynamic LDS of the LDS-resident variant: the workgroup's D_K rows
+// (coop_row_vecs(nc) 16-byte vectors each), then d, the two breakpoints
+// (double), q (T), class (uint8).
 template <class T>
 __host__ __device__ inline size_t coop_lds_bytes(int64_t rows, int nc) {
-    return size_t(rows) * nc * 16 + size_t(rows) * (3 * 8 + sizeof(T) + 1) + 64;
+    return size_t(rows) * coop_row_vecs(nc) * 16 + size_t(rows) * (3 * 8 + sizeof(T) + 1) + 64;
 }
 
 // LDSRES: the workgroup copies its rows of D_K, d, q and the classes into
@@ -311,7 +316,8 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     const int64_t r0 = bat0 * ROWS, nrows = (bat1 - bat0) * ROWS;
     // on-chip copies (LDSRES)
     V* dkl = reinterpret_cast<V*>(dyn);
-    double* dl = reinterpret_cast<double*>(dyn + size_t(nrows) * nc * 16);
+    const int ncp = coop_row_vecs(nc);   // LDS row stride in vectors
+    double* dl = reinterpret_cast<double*>(dyn + size_t(nrows) * ncp * 16);
     double* bul = dl + nrows;   // breakpoints of the current direction
     double* bol = bul + nrows;
     T* ql = reinterpret_cast<T*>(bol + nrows);
@@ -319,7 +325,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     if (LDSRES) {
         for (int64_t idx = threadIdx.x; idx < nrows * nc; idx += blockDim.x) {
             const int64_t rr = idx / nc;
-            dkl[idx] = reinterpret_cast<const V*>(A.dk + (r0 + rr) * KS)[idx - rr * nc];
+            dkl[rr * ncp + (idx - rr * nc)] = reinterpret_cast<const V*>(A.dk + (r0 + rr) * KS)[idx - rr * nc];
         }
         for (int64_t rr = threadIdx.x; rr < nrows; rr += blockDim.x) {
             dl[rr] = A.d[r0 + rr];
@@ -329,7 +335,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
         __syncthreads();
     }
     auto dk_vec = [&](int64_t row) -> V {
-        return LDSRES ? dkl[(row - r0) * nc + c] : reinterpret_cast<const V*>(A.dk + row * KS)[c];
+        return LDSRES ? dkl[(row - r0) * ncp + c] : reinterpret_cast<const V*>(A.dk + row * KS)[c];
     };
     auto d_at = [&](int64_t row) -> double& { return LDSRES ? dl[row - r0] : A.d[row]; };
     auto q_at = [&](int64_t row) -> T& { return LDSRES ? ql[row - r0] : A.q[row]; };
@@ -386,8 +392,8 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                 if (LDSRES) {
                     // running LDS offset, opaque to the compiler so it adds one
                     // stride per load instead of keeping IT addresses live
-                    uint32_t off = uint32_t(((base - r0 + rg) * nc + c) * 16);
-                    const uint32_t stride = uint32_t(G::RPW * nc * 16);
+                    uint32_t off = uint32_t(((base - r0 + rg) * ncp + c) * 16);
+                    const uint32_t stride = uint32_t(G::RPW * ncp * 16);
 #pragma unroll
                     for (int it = 0; it < IT; ++it) {
                         asm volatile("" : "+v"(off));
@@ -529,7 +535,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                     const double dv = dl[rr];
                     T qt;
                     if (first) {
-                        const V* rp = dkl + rr * nc;
+                        const V* rp = dkl + rr * ncp;
                         // partial of slot vector j (slots past the pool add exact zeros)
                         auto part_of = [&](int j) {
                             double part = 0.0;

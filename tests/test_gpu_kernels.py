@@ -200,3 +200,30 @@ def test_tuned_variant_reported():
         assert inf["dose_variant"] in (0, 1, 2) and inf["gradient_depth"] in (4, 8, 16)
     finally:
         ctx.close()
+
+
+def test_product_timing_calls():
+    """The measurement entry points run, return positive times and leave the
+    products' results unchanged; bad arguments are rejected."""
+    import paper_1003_5402_amd as dao
+    torch = torch_cuda()
+    ph = cached_phantom("tiny")
+    ctx = ctx_for(ph, dtype="f32")
+    try:
+        x = dev(np.random.default_rng(3).uniform(0, 0.05, ph.n_blt), torch.float32)
+        d0 = torch.empty(ph.n_vox, dtype=torch.float32, device="cuda:0")
+        ctx.dose(x, d0)
+        scrub = torch.zeros(4 << 20, dtype=torch.uint8, device="cuda:0")
+        assert ctx.time_product(0, 3) > 0 and ctx.time_product(1, 3) > 0
+        assert ctx.time_product_cold(0, 2, scrub) > 0 and ctx.time_product_cold(1, 2, scrub) > 0
+        assert int(scrub.count_nonzero()) == 0
+        d1 = torch.empty_like(d0)
+        ctx.dose(x, d1)
+        torch.cuda.synchronize()
+        assert torch.equal(d0, d1)
+        with pytest.raises(dao.DaoError):
+            ctx.time_product(2, 3)
+        with pytest.raises(dao.DaoError):
+            ctx.time_product_cold(0, 2, scrub[: 1 << 19])
+    finally:
+        ctx.close()
