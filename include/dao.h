@@ -185,6 +185,12 @@ typedef struct {
                                  with 8 entries per lane in flight, 2 x read from device
                                  memory with 8 in flight */
     int32_t gradient_depth;   /* transposed product: entries per thread in flight (4, 8, 16) */
+    int32_t last_master_form; /* how the last master solve ran: -1 none yet, 0 one launch per
+                                 phase, 1 persistent launch streaming D_K, 2 persistent launch
+                                 with each workgroup's rows on chip, 3 / 4 the batched launch
+                                 streaming / on chip */
+    int32_t onchip_lds_bytes; /* dynamic LDS a workgroup of the persistent launch may use for
+                                 its rows (0: the on-chip form is unavailable) */
 } dao_info_t;
 dao_status dao_info(const dao_ctx* ctx, dao_info_t* out);
 

@@ -58,7 +58,8 @@ class dao_info_t(ctypes.Structure):
                 ("dtype", c_int32), ("n_slices", c_int32), ("sell_entries", c_int64),
                 ("device_bytes", c_int64), ("d_format", c_int32), ("d_residual", c_int32),
                 ("bytes_dose", c_int64), ("bytes_gradient", c_int64),
-                ("dose_variant", c_int32), ("gradient_depth", c_int32)]
+                ("dose_variant", c_int32), ("gradient_depth", c_int32), ("last_master_form", c_int32),
+                ("onchip_lds_bytes", c_int32)]
 
 
 class dao_server_options(ctypes.Structure):

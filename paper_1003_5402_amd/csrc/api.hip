@@ -94,6 +94,7 @@ struct dao_ctx {
     bool batch_ok = false;             // the batched master launch is available
     ProfCounters* pc_h = nullptr;      // pinned
     int prof_kernel = -1;              // aperture-master kernel timed with events (-1: none)
+    int last_form = -1;                // form of the last master solve (dao_info_t.last_master_form)
     double prof_phase_us[PROF_PHASES] = {};   // persistent master split of the last window
     int device = 0;                    // HIP device of the context
     int dose_var = 0;                  // k_dose variant (0 staged, 1 staged + deep loads, 2 global x + deep)
@@ -474,12 +475,15 @@ dao_status run_master_coop(dao_ctx* c, double tol, int max_steps) {
     const int nc = (c->K + DKG<T>::EPL - 1) / DKG<T>::EPL;
     const int64_t rows = coop_batches_per_group<T>(c->Vpad, c->coop_grid) * Batch<T>::ROWS;
     const size_t lds = coop_lds_bytes<T>(rows, nc);
-    if (c->opt.persistent == 2 && c->coop_lds_max > 0 && lds <= size_t(c->coop_lds_max))
+    if (c->opt.persistent == 2 && c->coop_lds_max > 0 && lds <= size_t(c->coop_lds_max)) {
         HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T, true>),
                                              dim3(c->coop_grid), dim3(COOP_THREADS), args, lds, c->stream));
-    else
+        c->last_form = 2;
+    } else {
         HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T, false>),
                                              dim3(c->coop_grid), dim3(COOP_THREADS), args, 0, c->stream));
+        c->last_form = 1;
+    }
     if (prof) {
         dao_status s = prof_mark(c, 4, false);
         if (s != DAO_OK) return s;
@@ -521,6 +525,7 @@ dao_status run_master(dao_ctx* c, double tol, int max_steps) {
         chunk = std::max(4, std::min(32, (max_steps - c->ms_h->steps) / 4 + 4));
     }
     c->last_steps = c->ms_h->steps;
+    c->last_form = 0;
     return DAO_OK;
 }
 
@@ -696,7 +701,16 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
             // workgroup beyond the kernel's static LDS, if one per CU still fits
             int lds_max = 0;
             HIPCHK(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-            const int want = lds_max - 24 * 1024;
+            // the kernels' own static LDS (the larger of the single and the
+            // batched launch), rounded up to 1 KB
+            int stat = 0;
+            for (const void* fn : {reinterpret_cast<const void*>(&k_master_coop<T, true>),
+                                   reinterpret_cast<const void*>(&k_master_batch<T, true>)}) {
+                hipFuncAttributes fa{};
+                if (hipFuncGetAttributes(&fa, fn) == hipSuccess) stat = std::max(stat, int(fa.sharedSizeBytes));
+                else stat = std::max(stat, 32 * 1024);
+            }
+            const int want = lds_max - ((stat + 1023) / 1024) * 1024;
             if (want > 0 &&
                 hipFuncSetAttribute(reinterpret_cast<const void*>(&k_master_coop<T, true>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, want) == hipSuccess) {
@@ -1082,6 +1096,7 @@ dao_status run_master_batch(std::vector<PlanRun*>& live) {
     else
         HIPCHK(c0, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_batch<T, false>), dim3(G),
                                               dim3(COOP_THREADS), kargs, 0, c0->stream));
+    for (PlanRun* r : live) r->c->last_form = fits ? 4 : 3;
     for (PlanRun* r : live)
         HIPCHK(r->c, hipMemcpyAsync(r->c->ms_h, r->c->ms, sizeof(MasterState), hipMemcpyDeviceToHost, r->c->stream));
     HIPCHK(c0, hipStreamSynchronize(c0->stream));
@@ -1242,6 +1257,8 @@ dao_status dao_info(const dao_ctx* c, dao_info_t* o) {
     o->d_residual = c->opt.d_residual;
     o->dose_variant = c->dose_var;
     o->gradient_depth = c->gradT_pf;
+    o->last_master_form = c->last_form;
+    o->onchip_lds_bytes = c->coop_lds_max;
     // stored bytes per value: the ctx type, or 16 bits (+ 16 for the residual)
     const bool narrow = c->opt.d_format != DAO_DFMT_NATIVE;
     const int64_t vs = narrow ? 2 + (c->opt.d_residual ? 2 : 0) : ts;

@@ -167,3 +167,19 @@ def test_prostate_f32_teacher_forced_rounds(master):
             assert abs(F - Fr) <= 1e-5 * Fr
     finally:
         ctx.close()
+
+
+def test_prostate_plan_runs_on_chip():
+    """At the benchmark's size (prostate-shaped phantom, FP32, pool of 50) every
+    workgroup's rows fit in LDS, so the persistent master takes the on-chip form."""
+    ph = cached_phantom("prostate")
+    ctx = ctx_for(ph, dtype="f32", max_apertures=64)
+    try:
+        inf = ctx.info()
+        if inf["onchip_lds_bytes"] == 0:
+            pytest.fail("the on-chip form is unavailable on this device")
+        out = ctx.solve(ph.n_apertures)
+        assert out["rounds"] >= 1
+        assert ctx.info()["last_master_form"] == 2
+    finally:
+        ctx.close()
