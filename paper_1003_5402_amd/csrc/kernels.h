@@ -349,19 +349,22 @@ __device__ __forceinline__ Acc slab_rows(const SellView<T>& S, const XT* __restr
     return sum;
 }
 
-// Stage an n-vector into LDS (or return the global pointer when not staged),
-// multiplied by the per-beamlet scale when one is given (16-bit formats,
-// which are always staged).
-template <class XT, class ST>
-__device__ __forceinline__ const XT* stage_vec(const ST* __restrict__ src, int n, XT* lds, bool stage,
-                                               const float* __restrict__ scale = nullptr) {
-    if (!stage) return reinterpret_cast<const XT*>(src);
-    if (scale)
-        for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = XT(src[i]) * XT(scale[i]);
-    else
-        for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = XT(src[i]);
-    __syncthreads();
-    return lds;
+// Row sums of the slab against the n-vector src: staged into LDS (times the
+// per-beamlet scale when one is given) and gathered from there, or gathered
+// from device memory when not staged.  The two gathers are separate code
+// paths, so the staged one compiles to LDS reads rather than generic ones.
+template <class VT, class XT, class Acc, bool LO = false, int DEEP = 0, class ST>
+__device__ __forceinline__ Acc slab_rows_x(const SellView<VT>& S, const ST* __restrict__ src, int n, XT* lds,
+                                           bool stage, const float* __restrict__ scale, Acc* s_part) {
+    if (stage) {
+        if (scale)
+            for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = XT(src[i]) * XT(scale[i]);
+        else
+            for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = XT(src[i]);
+        __syncthreads();
+        return slab_rows<VT, XT, Acc, LO, DEEP>(S, lds, s_part);
+    }
+    return slab_rows<VT, XT, Acc, LO, DEEP>(S, reinterpret_cast<const XT*>(src), s_part);
 }
 
 // ---------------------------------------------------------------------------
@@ -378,8 +381,7 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_dose(SellView<VT> S, const int
                                                        T* __restrict__ d_ext) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ T s_part[KSPLIT * SLAB];
-    const T* xs = stage_vec<T, T>(x, N, reinterpret_cast<T*>(smem), stage, scale);
-    const T sum = slab_rows<VT, T, T, LO, DEEP>(S, xs, s_part);
+    const T sum = slab_rows_x<VT, T, T, LO, DEEP>(S, x, N, reinterpret_cast<T*>(smem), stage, scale, s_part);
     const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
     if (threadIdx.x < SLAB && row < Vpad) {
         const int32_t j = perm[row];
@@ -915,8 +917,7 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_qstep(SellView<T> S, int64_t V
     for (int i = threadIdx.x; i < ncls; i += blockDim.x) cl[i] = classes[i];
     T* xs_l = reinterpret_cast<T*>(smem + sizeof(ObjClass) * ncls);
     __syncthreads();
-    const T* xs = stage_vec<T, T>(dx, N, xs_l, stage);
-    const T sum = slab_rows<T, T, T>(S, xs, s_part);
+    const T sum = slab_rows_x<T, T, T>(S, dx, N, xs_l, stage, nullptr, s_part);
     Rec r = rec_identity();
     const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
     if (threadIdx.x < SLAB && row < Vpad) {
@@ -1005,8 +1006,7 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_update(SellView<T> S, int64_t 
     __syncthreads();
     double dn = 0.0;
     if (s_refresh) {
-        const double* xs = stage_vec<double, double>(x64, N, xs_l, stage);
-        dn = slab_rows<T, double, double>(S, xs, s_part);
+        dn = slab_rows_x<T, double, double>(S, x64, N, xs_l, stage, nullptr, s_part);
     }
     Rec r = rec_identity();
     const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;

@@ -103,8 +103,7 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_dk_column(SellView<VT> S, int6
                                                             T* __restrict__ dk) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double s_part[KSPLIT * SLAB];
-    const T* xs = stage_vec<T, T>(ind, N, reinterpret_cast<T*>(smem), stage, scale);
-    const double sum = slab_rows<VT, T, double, LO>(S, xs, s_part);
+    const double sum = slab_rows_x<VT, T, double, LO>(S, ind, N, reinterpret_cast<T*>(smem), stage, scale, s_part);
     const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
     if (threadIdx.x < SLAB && row < Vpad) dk[row * KS + k] = T(sum);
 }
