@@ -210,6 +210,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--product-iters", type=int, default=200)
+    ap.add_argument("--large-config", default="headneck",
+                    help="phantom whose products are also timed (D of ~120 MB); 'none' skips it")
     ap.add_argument("--serve-requests", type=int, default=32,
                     help="requests of the serving replay (the serving configuration uses 256)")
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -311,6 +313,29 @@ def main():
             "gradient_cold_us": vc.time_product_cold(1, cold_iters, scrub)}
         vc.close()
     log(f"[bench] product variants (tuned: dose {info['dose_variant']}, depth {info['gradient_depth']}): {variants}")
+    # the same products on the larger phantom (D several times the size, nearer
+    # the streaming regime the kernels are built for)
+    large = None
+    if args.large_config != "none" and args.large_config != args.config:
+        phl = make_phantom(args.large_config, args.seed)
+        large = {"phantom": args.large_config, "nnz": int(phl.row_ptr[-1]), "n_blt": int(phl.n_blt)}
+        for fname, fmt in (("f32", dao.DAO_DFMT_NATIVE), ("f16", dao.DAO_DFMT_F16)):
+            lc = dao.DaoContext.from_phantom(phl, dtype="f32", stream=stream, d_format=fmt)
+            li = lc.info()
+            ud, ug = lc.time_product(0, args.product_iters), lc.time_product(1, args.product_iters)
+            udc, ugc = lc.time_product_cold(0, cold_iters, scrub), lc.time_product_cold(1, cold_iters, scrub)
+            large[fname] = {
+                "dose_bytes": li["bytes_dose"], "gradient_bytes": li["bytes_gradient"],
+                "dose_us": ud, "gradient_us": ug, "dose_cold_us": udc, "gradient_cold_us": ugc,
+                "dose_GBs": li["bytes_dose"] / (ud * 1e-6) / 1e9, "gradient_GBs": li["bytes_gradient"] / (ug * 1e-6) / 1e9,
+                "dose_cold_GBs": li["bytes_dose"] / (udc * 1e-6) / 1e9,
+                "gradient_cold_GBs": li["bytes_gradient"] / (ugc * 1e-6) / 1e9,
+                "dose_frac_cold": li["bytes_dose"] / (udc * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                "gradient_frac_cold": li["bytes_gradient"] / (ugc * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                "tuned": {"dose_variant": li["dose_variant"], "gradient_depth": li["gradient_depth"]}}
+            lc.close()
+            log(f"[bench] {args.large_config} {fname} products: {large[fname]}")
+        del phl
     del scrub
     gbs_dose_c = info["bytes_dose"] / (us_dose_c * 1e-6) / 1e9
     gbs_grad_c = info["bytes_gradient"] / (us_grad_c * 1e-6) / 1e9
@@ -411,6 +436,7 @@ def main():
             "note": ("D x = k_dose, D^T u = k_gradT, timed standalone: warm back-to-back (D fits the 256 MB "
                      "last-level cache) and cold (1 GiB scrub read before each timed launch)"),
         },
+        "products_large": large,
         "master_kernels": kernels,
         "d_16bit": reduced,
         "serving": serve,

@@ -257,72 +257,52 @@ struct SellView {
     const __half* lo;   // FP16 residuals (same positions as val), or null
 };
 
-// Lane `lane` of a wavefront: entries k0..k1-1 of its row in the slice that
-// starts at entry `base`, visited in stored (ascending beamlet) order.
-template <class T, class XT, class Acc, bool LO = false>
+// Forward layout: in a slice of SLICE rows, entries come in groups of 4 of
+// one row (slice width padded to a multiple of 4): entry k of lane l sits at
+// base + (k / 4) * 4 * SLICE + 4 * l + k % 4, so one lane reads a group with
+// one 4-element load and a wavefront instruction reads 4 * SLICE entries.
+template <class T>
+struct alignas(4 * sizeof(T)) Quad {
+    T e[4];
+};
+
+// Lane `lane` of a wavefront: entries k0..k1-1 (multiples of 4) of its row in
+// the slice that starts at entry `base`, visited in stored (ascending
+// beamlet) order, with G groups of loads in flight per iteration.
+template <class T, class XT, class Acc, bool LO, int G>
 __device__ __forceinline__ Acc sell_dot(const T* __restrict__ val, const __half* __restrict__ lo,
                                         const uint16_t* __restrict__ col, uint32_t base, int k0, int k1,
                                         int lane, const XT* __restrict__ xs) {
-    const size_t o = base + uint32_t(k0) * SLICE + lane;
-    const T* v = val + o;
-    const __half* l = LO ? lo + o : nullptr;
-    const uint16_t* c = col + o;
+    const int g0 = k0 >> 2, g1 = k1 >> 2;
+    const size_t o = base + size_t(g0) * (4 * SLICE) + size_t(lane) * 4;
     Acc acc = Acc(0);
-    int k = k0;
-    for (; k + 4 <= k1; k += 4) {
-        const T v0 = v[0], v1 = v[SLICE], v2 = v[2 * SLICE], v3 = v[3 * SLICE];
-        const uint16_t c0 = c[0], c1 = c[SLICE], c2 = c[2 * SLICE], c3 = c[3 * SLICE];
-        acc += Acc(dval2<T, LO>(v0, l)) * Acc(xs[c0]);
-        acc += Acc(dval2<T, LO>(v1, l + SLICE)) * Acc(xs[c1]);
-        acc += Acc(dval2<T, LO>(v2, l + 2 * SLICE)) * Acc(xs[c2]);
-        acc += Acc(dval2<T, LO>(v3, l + 3 * SLICE)) * Acc(xs[c3]);
-        v += 4 * SLICE;
-        c += 4 * SLICE;
-        if (LO) l += 4 * SLICE;
-    }
-    for (; k < k1; ++k) {
-        acc += Acc(dval2<T, LO>(v[0], l)) * Acc(xs[c[0]]);
-        v += SLICE;
-        c += SLICE;
-        if (LO) l += SLICE;
-    }
-    return acc;
-}
-
-// As sell_dot, with the loads of U entries (values, columns, then the U
-// gathers of x) in flight together before their products are added, in the
-// same order.
-template <class T, class XT, class Acc, bool LO, int U>
-__device__ __forceinline__ Acc sell_dot_deep(const T* __restrict__ val, const __half* __restrict__ lo,
-                                             const uint16_t* __restrict__ col, uint32_t base, int k0, int k1,
-                                             int lane, const XT* __restrict__ xs) {
-    const size_t o = base + uint32_t(k0) * SLICE + lane;
-    Acc acc = Acc(0);
-    for (int k = k0; k < k1; k += U) {
-        T v[U];
-        __half l[U];
-        uint16_t cc[U];
+    for (int g = g0; g < g1; g += G) {
+        Quad<T> v[G];
+        Quad<uint16_t> c[G];
+        Quad<__half> l[G];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool in = k + u < k1;
-            const size_t e = o + size_t(k - k0 + u) * SLICE;
-            v[u] = in ? val[e] : T(0);
-            cc[u] = in ? col[e] : uint16_t(0);
-            if (LO) l[u] = in ? lo[e] : __half(0.0f);
+        for (int u = 0; u < G; ++u) {
+            const size_t e = o + size_t(g - g0 + u) * (4 * SLICE);
+            if (G == 1 || g + u < g1) {
+                v[u] = *reinterpret_cast<const Quad<T>*>(val + e);
+                c[u] = *reinterpret_cast<const Quad<uint16_t>*>(col + e);
+                if (LO) l[u] = *reinterpret_cast<const Quad<__half>*>(lo + e);
+            }
         }
-        XT xv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = k + u < k1 ? xs[cc[u]] : XT(0);
+        for (int u = 0; u < G; ++u) {
+            if (G == 1 || g + u < g1) {
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (k + u < k1) acc += Acc(dval2<T, LO>(v[u], &l[u])) * Acc(xv[u]);
+                for (int q = 0; q < 4; ++q) acc += Acc(dval2<T, LO>(v[u].e[q], &l[u].e[q])) * Acc(xs[c[u].e[q]]);
+            }
+        }
     }
     return acc;
 }
 
 // Row sums of this workgroup's slab (SLAB_THREADS threads).  Wavefront w
 // takes slice w / KSPLIT of the slab and the (w % KSPLIT)-th quarter of its
-// entries; partials meet in s_part and are added in k order.  Returns the
+// entry groups; partials meet in s_part and are added in k order.  Returns the
 // row sum in threads t < SLAB (row blockIdx.x * SLAB + t).
 template <class T, class XT, class Acc, bool LO = false, int DEEP = 0>
 __device__ __forceinline__ Acc slab_rows(const SellView<T>& S, const XT* __restrict__ xs, Acc* s_part) {
@@ -331,13 +311,11 @@ __device__ __forceinline__ Acc slab_rows(const SellView<T>& S, const XT* __restr
     const int64_t s = int64_t(blockIdx.x) * SPB + j;
     Acc acc = Acc(0);
     if (s < S.nslices) {
-        const int w = S.slice_w[s];
-        const int kc = (w + KSPLIT - 1) / KSPLIT;
+        const int w = S.slice_w[s];   // a multiple of 4
+        const int kc = ((w >> 2) + KSPLIT - 1) / KSPLIT * 4;
         const int k0 = min(w, kp * kc), k1 = min(w, k0 + kc);
-        if constexpr (DEEP > 0)
-            acc = sell_dot_deep<T, XT, Acc, LO, DEEP>(S.val, S.lo, S.col, S.slice_ptr[s], k0, k1, lane, xs);
-        else
-            acc = sell_dot<T, XT, Acc, LO>(S.val, S.lo, S.col, S.slice_ptr[s], k0, k1, lane, xs);
+        constexpr int G = DEEP > 0 ? DEEP / 4 : 1;   // groups of loads in flight
+        acc = sell_dot<T, XT, Acc, LO, G>(S.val, S.lo, S.col, S.slice_ptr[s], k0, k1, lane, xs);
     }
     s_part[kp * SLAB + j * SLICE + lane] = acc;
     __syncthreads();

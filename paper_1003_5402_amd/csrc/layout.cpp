@@ -246,6 +246,7 @@ void build_layout(const dao_matrix* D, const dao_beams* beams, const dao_structu
             int32_t j = L->perm[s * SLICE + l];
             if (j >= 0) w = std::max<int64_t>(w, rp[j + 1] - rp[j]);
         }
+        w = (w + 3) / 4 * 4;   // groups of 4 entries per row
         L->slice_w[s] = int32_t(w);
         L->slice_ptr[s + 1] = L->slice_ptr[s] + uint32_t(w * SLICE);
     }
@@ -258,7 +259,7 @@ void build_layout(const dao_matrix* D, const dao_beams* beams, const dao_structu
             if (j < 0) continue;
             int64_t len = rp[j + 1] - rp[j];
             for (int64_t k = 0; k < len; ++k) {
-                uint32_t e = L->slice_ptr[s] + uint32_t(k * SLICE + l);
+                uint32_t e = L->slice_ptr[s] + uint32_t((k / 4) * 4 * SLICE + 4 * l + k % 4);
                 L->sell_col[e] = uint16_t(D->col[rp[j] + k]);
                 L->sell_val[e] = D->val[rp[j] + k];
             }

@@ -20,7 +20,9 @@ struct HostLayout {
     int64_t Vpad = 0;           // nslices * SLICE
     int32_t B = 0, R = 0, max_rows_per_beam = 0, n_struct = 0;
 
-    // forward layout: sliced ELL, 64 rows per slice, column-major in a slice
+    // forward layout: sliced ELL, 64 rows per slice, each row's entries in
+    // groups of 4 (slice width padded to a multiple of 4): entry k of row l
+    // of a slice at (k / 4) * 256 + 4 * l + k % 4 from the slice's start
     std::vector<int32_t> perm;        // [Vpad] internal row -> caller voxel (-1: padding)
     std::vector<uint32_t> slice_ptr;  // [nslices + 1] first entry of each slice
     std::vector<int32_t> slice_w;     // [nslices] entries per row in the slice
