@@ -304,7 +304,7 @@ def main():
     us_grad_c = ctx.time_product_cold(1, cold_iters, scrub)
     # every product variant, forced (the tuned choice above is one of them)
     variants = {}
-    for dv, gd in ((0, 4), (1, 8), (2, 16)):
+    for dv, gd in ((0, 4), (1, 8), (2, 16), (3, 4)):
         vc = dao.DaoContext.from_phantom(ph, dtype="f32", stream=stream, product_tune=0, dose_variant=dv,
                                          gradient_depth=gd)
         variants[f"dose{dv}_depth{gd}"] = {

@@ -125,9 +125,10 @@ typedef struct {
                                choose.  The variants add the same terms in the same
                                order, so results do not depend on the choice */
     int32_t dose_variant;   /* with product_tune 0: forward product variant, 0 (default)
-                               x staged on chip, 1 staged with 8 entries per lane in
-                               flight, 2 x read from device memory with 8 in flight
-                               (native d_format only) */
+                               x staged on chip, 4 slices of 64 rows per workgroup;
+                               1 as 0 with 8 entries per lane in flight; 2 x read from
+                               device memory with 8 in flight (native d_format only);
+                               3 as 0 with 8 slices per workgroup */
     int32_t gradient_depth; /* with product_tune 0: transposed product entries per thread
                                in flight, 4 (default), 8 or 16 */
 } dao_options;
@@ -181,9 +182,7 @@ typedef struct {
     int32_t d_residual;       /* 1 when the FP16 residual is stored and used */
     int64_t bytes_dose;       /* algorithmic HBM bytes of one forward product */
     int64_t bytes_gradient;   /* algorithmic HBM bytes of one transposed product */
-    int32_t dose_variant;     /* forward product variant in use: 0 x staged on chip, 1 staged
-                                 with 8 entries per lane in flight, 2 x read from device
-                                 memory with 8 in flight */
+    int32_t dose_variant;     /* forward product variant in use (as dao_options.dose_variant) */
     int32_t gradient_depth;   /* transposed product: entries per thread in flight (4, 8, 16) */
     int32_t last_master_form; /* how the last master solve ran: -1 none yet, 0 one launch per
                                  phase, 1 persistent launch streaming D_K, 2 persistent launch

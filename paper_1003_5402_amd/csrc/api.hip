@@ -261,7 +261,8 @@ void with_values(const dao_ctx* c, F&& f) {
 // variant `var` (-1: the context's tuned one).  Every variant adds the same
 // products in the same order.  Variant 2 reads x from device memory and
 // exists for native values only (a 16-bit format folds its scale into the
-// staged copy).
+// staged copy); variant 3 gives each workgroup twice the slices (each
+// wavefront two chunks of its row).
 template <class T>
 void launch_dose(dao_ctx* c, const T* x, T* d_out, int var = -1) {
     if (var < 0) var = c->dose_var;
@@ -272,6 +273,9 @@ void launch_dose(dao_ctx* c, const T* x, T* d_out, int var = -1) {
         const size_t lds = stage ? c->N * sizeof(T) : 0;
         if (var == 0)
             k_dose<T, VT, LO, 0><<<c->slab_blocks(), SLAB_THREADS, lds, c->stream>>>(
+                sell_view<VT>(c), c->perm, c->Vpad, x, int(c->N), stage, c->col_scale, d_out);
+        else if (var == 3)
+            k_dose<T, VT, LO, 0, 2 * SPB><<<(c->nslices + 2 * SPB - 1) / (2 * SPB), SLAB_THREADS, lds, c->stream>>>(
                 sell_view<VT>(c), c->perm, c->Vpad, x, int(c->N), stage, c->col_scale, d_out);
         else
             k_dose<T, VT, LO, 8><<<c->slab_blocks(), SLAB_THREADS, lds, c->stream>>>(
@@ -318,9 +322,9 @@ dao_status tune_products(dao_ctx* c) {
     hipError_t he = hipEventCreate(&e0);
     if (he == hipSuccess) he = hipEventCreate(&e1);
     if (he == hipSuccess) he = hipMemsetAsync(c->u, 0, c->Vpad * sizeof(T), c->stream);
-    const int nd = c->opt.d_format == DAO_DFMT_NATIVE ? 3 : 2;
+    const bool native = c->opt.d_format == DAO_DFMT_NATIVE;
     const int pfs[3] = {4, 8, 16};
-    double best_d[3] = {1e30, 1e30, 1e30}, best_g[3] = {1e30, 1e30, 1e30};
+    double best_d[4] = {1e30, 1e30, 1e30, 1e30}, best_g[3] = {1e30, 1e30, 1e30};
     constexpr int REPS = 3, LAUNCHES = 8;
     auto time_one = [&](auto&& launch) -> double {
         launch();
@@ -333,8 +337,9 @@ dao_status tune_products(dao_ctx* c) {
         return double(ms);
     };
     for (int r = 0; r < REPS && he == hipSuccess; ++r) {
-        for (int v = 0; v < nd; ++v)
-            best_d[v] = std::min(best_d[v], time_one([&] {
+        for (int v = 0; v < 4; ++v)
+            if (native || v != 2)
+                best_d[v] = std::min(best_d[v], time_one([&] {
                 launch_dose<T>(c, static_cast<const T*>(c->dx), static_cast<T*>(out), v);
             }));
         for (int v = 0; v < 3; ++v)
@@ -347,7 +352,7 @@ dao_status tune_products(dao_ctx* c) {
     if (s == DAO_OK) {
         // a variant replaces the plain one only when clearly faster (2 %)
         c->dose_var = 0;
-        for (int v = 1; v < nd; ++v)
+        for (int v = 1; v < 4; ++v)
             if (best_d[v] < 0.98 * best_d[c->dose_var]) c->dose_var = v;
         int bg = 0;
         for (int v = 1; v < 3; ++v)

@@ -300,29 +300,87 @@ __device__ __forceinline__ Acc sell_dot(const T* __restrict__ val, const __half*
     return acc;
 }
 
-// Row sums of this workgroup's slab (SLAB_THREADS threads).  Wavefront w
-// takes slice w / KSPLIT of the slab and the (w % KSPLIT)-th quarter of its
-// entry groups; partials meet in s_part and are added in k order.  Returns the
-// row sum in threads t < SLAB (row blockIdx.x * SLAB + t).
-template <class T, class XT, class Acc, bool LO = false, int DEEP = 0>
+// As sell_dot for C chunks of the same row at once (chunk c: entries
+// k0[c]..k1[c]-1), one group of each chunk per iteration, each chunk summed
+// in its own accumulator in stored order (the same sums as C sell_dot calls).
+template <class T, class XT, class Acc, bool LO, int C>
+__device__ __forceinline__ void sell_dot_multi(const T* __restrict__ val, const __half* __restrict__ lo,
+                                               const uint16_t* __restrict__ col, uint32_t base, const int* k0,
+                                               const int* k1, int lane, const XT* __restrict__ xs, Acc* acc) {
+    int n = 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        acc[c] = Acc(0);
+        n = max(n, (k1[c] - k0[c]) >> 2);
+    }
+    for (int g = 0; g < n; ++g) {
+        Quad<T> v[C];
+        Quad<uint16_t> cq[C];
+        Quad<__half> l[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if (g < ((k1[c] - k0[c]) >> 2)) {
+                const size_t e = base + size_t((k0[c] >> 2) + g) * (4 * SLICE) + size_t(lane) * 4;
+                v[c] = *reinterpret_cast<const Quad<T>*>(val + e);
+                cq[c] = *reinterpret_cast<const Quad<uint16_t>*>(col + e);
+                if (LO) l[c] = *reinterpret_cast<const Quad<__half>*>(lo + e);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if (g < ((k1[c] - k0[c]) >> 2)) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    acc[c] += Acc(dval2<T, LO>(v[c].e[q], &l[c].e[q])) * Acc(xs[cq[c].e[q]]);
+            }
+        }
+    }
+}
+
+// Row sums of this workgroup's slab of SPBt slices (SLAB_THREADS threads).
+// Every slice's entry groups are split into KSPLIT chunks whose partials
+// meet in s_part (KSPLIT * SPBt * SLICE values) and are added in chunk
+// order, whatever the geometry: with SPBt = SPB each wavefront sums one
+// chunk; with more slices per slab each wavefront sums several chunks of
+// its slice together (fewer workgroups, each staging x once for more rows;
+// the same sums).  Returns the row sum in threads t < SPBt * SLICE (row
+// blockIdx.x * SPBt * SLICE + t).
+template <class T, class XT, class Acc, bool LO = false, int DEEP = 0, int SPBt = SPB>
 __device__ __forceinline__ Acc slab_rows(const SellView<T>& S, const XT* __restrict__ xs, Acc* s_part) {
+    constexpr int KSP = SPB * KSPLIT / SPBt;   // wavefronts per slice
+    constexpr int CPW = KSPLIT / KSP;          // chunks per wavefront
+    constexpr int SLABt = SPBt * SLICE;
+    static_assert(KSP * CPW == KSPLIT && SPBt * KSP * WAVE == SLAB_THREADS, "slab geometry");
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int j = wave / KSPLIT, kp = wave % KSPLIT;
-    const int64_t s = int64_t(blockIdx.x) * SPB + j;
-    Acc acc = Acc(0);
+    const int j = wave / KSP, kp = wave % KSP;
+    const int64_t s = int64_t(blockIdx.x) * SPBt + j;
+    Acc acc[CPW];
+#pragma unroll
+    for (int i = 0; i < CPW; ++i) acc[i] = Acc(0);
     if (s < S.nslices) {
         const int w = S.slice_w[s];   // a multiple of 4
         const int kc = ((w >> 2) + KSPLIT - 1) / KSPLIT * 4;
-        const int k0 = min(w, kp * kc), k1 = min(w, k0 + kc);
-        constexpr int G = DEEP > 0 ? DEEP / 4 : 1;   // groups of loads in flight
-        acc = sell_dot<T, XT, Acc, LO, G>(S.val, S.lo, S.col, S.slice_ptr[s], k0, k1, lane, xs);
+        if constexpr (CPW == 1) {
+            const int k0 = min(w, kp * kc), k1 = min(w, k0 + kc);
+            constexpr int G = DEEP > 0 ? DEEP / 4 : 1;   // groups of loads in flight
+            acc[0] = sell_dot<T, XT, Acc, LO, G>(S.val, S.lo, S.col, S.slice_ptr[s], k0, k1, lane, xs);
+        } else {
+            int k0[CPW], k1[CPW];
+#pragma unroll
+            for (int i = 0; i < CPW; ++i) {
+                k0[i] = min(w, (kp * CPW + i) * kc);
+                k1[i] = min(w, k0[i] + kc);
+            }
+            sell_dot_multi<T, XT, Acc, LO, CPW>(S.val, S.lo, S.col, S.slice_ptr[s], k0, k1, lane, xs, acc);
+        }
     }
-    s_part[kp * SLAB + j * SLICE + lane] = acc;
+#pragma unroll
+    for (int i = 0; i < CPW; ++i) s_part[(kp * CPW + i) * SLABt + j * SLICE + lane] = acc[i];
     __syncthreads();
     Acc sum = Acc(0);
-    if (threadIdx.x < SLAB) {
+    if (threadIdx.x < SLABt) {
 #pragma unroll
-        for (int q = 0; q < KSPLIT; ++q) sum += s_part[q * SLAB + threadIdx.x];
+        for (int q = 0; q < KSPLIT; ++q) sum += s_part[q * SLABt + threadIdx.x];
     }
     return sum;
 }
@@ -331,7 +389,7 @@ __device__ __forceinline__ Acc slab_rows(const SellView<T>& S, const XT* __restr
 // per-beamlet scale when one is given) and gathered from there, or gathered
 // from device memory when not staged.  The two gathers are separate code
 // paths, so the staged one compiles to LDS reads rather than generic ones.
-template <class VT, class XT, class Acc, bool LO = false, int DEEP = 0, class ST>
+template <class VT, class XT, class Acc, bool LO = false, int DEEP = 0, int SPBt = SPB, class ST>
 __device__ __forceinline__ Acc slab_rows_x(const SellView<VT>& S, const ST* __restrict__ src, int n, XT* lds,
                                            bool stage, const float* __restrict__ scale, Acc* s_part) {
     if (stage) {
@@ -340,9 +398,9 @@ __device__ __forceinline__ Acc slab_rows_x(const SellView<VT>& S, const ST* __re
         else
             for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = XT(src[i]);
         __syncthreads();
-        return slab_rows<VT, XT, Acc, LO, DEEP>(S, lds, s_part);
+        return slab_rows<VT, XT, Acc, LO, DEEP, SPBt>(S, lds, s_part);
     }
-    return slab_rows<VT, XT, Acc, LO, DEEP>(S, reinterpret_cast<const XT*>(src), s_part);
+    return slab_rows<VT, XT, Acc, LO, DEEP, SPBt>(S, reinterpret_cast<const XT*>(src), s_part);
 }
 
 // ---------------------------------------------------------------------------
@@ -351,17 +409,19 @@ __device__ __forceinline__ Acc slab_rows_x(const SellView<VT>& S, const ST* __re
 
 // d_ext[perm[r]] = (D x)_r for every row of the slab; x staged in LDS
 // (times the per-beamlet scale of a 16-bit value format).  DEEP > 0 keeps
-// DEEP entries per lane in flight (the autotuned variants; same sums).
-template <class T, class VT = T, bool LO = false, int DEEP = 0>
+// DEEP entries per lane in flight, SPBt slices per workgroup (the autotuned
+// variants; the same sums).
+template <class T, class VT = T, bool LO = false, int DEEP = 0, int SPBt = SPB>
 __global__ void __launch_bounds__(SLAB_THREADS) k_dose(SellView<VT> S, const int32_t* __restrict__ perm,
                                                        int64_t Vpad, const T* __restrict__ x, int N,
                                                        bool stage, const float* __restrict__ scale,
                                                        T* __restrict__ d_ext) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ T s_part[KSPLIT * SLAB];
-    const T sum = slab_rows_x<VT, T, T, LO, DEEP>(S, x, N, reinterpret_cast<T*>(smem), stage, scale, s_part);
-    const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
-    if (threadIdx.x < SLAB && row < Vpad) {
+    __shared__ T s_part[KSPLIT * SPBt * SLICE];
+    const T sum =
+        slab_rows_x<VT, T, T, LO, DEEP, SPBt>(S, x, N, reinterpret_cast<T*>(smem), stage, scale, s_part);
+    const int64_t row = int64_t(blockIdx.x) * (SPBt * SLICE) + threadIdx.x;
+    if (threadIdx.x < SPBt * SLICE && row < Vpad) {
         const int32_t j = perm[row];
         if (j >= 0) d_ext[j] = sum;
     }

@@ -101,7 +101,7 @@ dao_status validate_inputs(const dao_matrix* D, const dao_beams* beams,
         return fail("master must be DAO_MASTER_APERTURE or DAO_MASTER_BEAMLET");
     if (opt->persistent < 0 || opt->persistent > 2) return fail("persistent must be 0, 1 or 2");
     if (opt->product_tune < 0 || opt->product_tune > 1) return fail("product_tune must be 0 or 1");
-    if (opt->dose_variant < 0 || opt->dose_variant > 2) return fail("dose_variant must be 0, 1 or 2");
+    if (opt->dose_variant < 0 || opt->dose_variant > 3) return fail("dose_variant must be 0, 1, 2 or 3");
     if (opt->dose_variant == 2 && opt->d_format != DAO_DFMT_NATIVE)
         return fail("dose_variant 2 reads x unscaled: native d_format only");
     if (opt->gradient_depth != 4 && opt->gradient_depth != 8 && opt->gradient_depth != 16)

@@ -81,7 +81,7 @@ def test_create_rejects_malformed_inputs():
     for opts, needle in [(dict(d_format=3), "d_format"), (dict(d_residual=1), "d_residual"),
                          (dict(d_format=1, d_residual=2), "d_residual"),
                          (dict(d_format=1, dtype="f64"), "DAO_F32"), (dict(d_format=2, master=1), "aperture"),
-                         (dict(product_tune=2), "product_tune"), (dict(dose_variant=3), "dose_variant"),
+                         (dict(product_tune=2), "product_tune"), (dict(dose_variant=4), "dose_variant"),
                          (dict(dose_variant=2, d_format=1), "native"), (dict(gradient_depth=6), "gradient_depth")]:
         msg = _expect(dao.DAO_EINVAL, _a=_args(ph), _opts=opts)
         assert needle in msg, (opts, msg)

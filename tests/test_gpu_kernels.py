@@ -158,12 +158,14 @@ def test_price_own_prices_at_zero_dose(contexts, name, dtype):
 
 
 # Every variant of the two products (loads in flight per thread, x staged on
-# chip or read from device memory) adds the same terms in the same order:
-# results agree bit for bit with the plain variant, in every value format.
-VARIANTS = [(0, 4), (1, 8), (2, 16)]
+# chip or read from device memory, slices per workgroup) adds the same terms
+# in the same order: results agree bit for bit with the plain variant, in
+# every value format.
+VARIANTS = [(0, 4), (1, 8), (2, 16), (3, 4)]
 
 
-@pytest.mark.parametrize("name,dtype,fmt", [("tiny", "f64", 0), ("prostate", "f32", 0), ("prostate", "f32", 1)])
+@pytest.mark.parametrize("name,dtype,fmt", [("tiny", "f64", 0), ("prostate", "f32", 0), ("prostate", "f32", 1),
+                                            ("headneck", "f32", 0)])
 def test_product_variants_identical(name, dtype, fmt):
     torch = torch_cuda()
     ph = cached_phantom(name)
@@ -197,7 +199,7 @@ def test_tuned_variant_reported():
     ctx = ctx_for(ph, dtype="f32")
     try:
         inf = ctx.info()
-        assert inf["dose_variant"] in (0, 1, 2) and inf["gradient_depth"] in (4, 8, 16)
+        assert inf["dose_variant"] in (0, 1, 2, 3) and inf["gradient_depth"] in (4, 8, 16)
     finally:
         ctx.close()
 
