@@ -269,14 +269,29 @@ struct alignas(4 * sizeof(T)) Quad {
 // Lane `lane` of a wavefront: entries k0..k1-1 (multiples of 4) of its row in
 // the slice that starts at entry `base`, visited in stored (ascending
 // beamlet) order, with G groups of loads in flight per iteration.
+// The first group of a lane's chunk, loaded ahead (before x is staged).
+template <class T>
+struct FirstGroup {
+    Quad<T> v;
+    Quad<uint16_t> c;
+    Quad<__half> l;
+};
+
 template <class T, class XT, class Acc, bool LO, int G>
 __device__ __forceinline__ Acc sell_dot(const T* __restrict__ val, const __half* __restrict__ lo,
                                         const uint16_t* __restrict__ col, uint32_t base, int k0, int k1,
-                                        int lane, const XT* __restrict__ xs) {
+                                        int lane, const XT* __restrict__ xs,
+                                        const FirstGroup<T>* first = nullptr) {
     const int g0 = k0 >> 2, g1 = k1 >> 2;
     const size_t o = base + size_t(g0) * (4 * SLICE) + size_t(lane) * 4;
     Acc acc = Acc(0);
-    for (int g = g0; g < g1; g += G) {
+    int gs = g0;
+    if (first && g0 < g1) {   // group g0 already loaded
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc += Acc(dval2<T, LO>(first->v.e[q], &first->l.e[q])) * Acc(xs[first->c.e[q]]);
+        gs = g0 + 1;
+    }
+    for (int g = gs; g < g1; g += G) {
         Quad<T> v[G];
         Quad<uint16_t> c[G];
         Quad<__half> l[G];
@@ -345,8 +360,18 @@ __device__ __forceinline__ void sell_dot_multi(const T* __restrict__ val, const 
 // its slice together (fewer workgroups, each staging x once for more rows;
 // the same sums).  Returns the row sum in threads t < SPBt * SLICE (row
 // blockIdx.x * SPBt * SLICE + t).
+// Entry range [k0, k1) of chunk q of slice s (KSPLIT chunks of whole groups).
+template <class T>
+__device__ __forceinline__ void chunk_range(const SellView<T>& S, int64_t s, int q, int& k0, int& k1) {
+    const int w = S.slice_w[s];   // a multiple of 4
+    const int kc = ((w >> 2) + KSPLIT - 1) / KSPLIT * 4;
+    k0 = min(w, q * kc);
+    k1 = min(w, k0 + kc);
+}
+
 template <class T, class XT, class Acc, bool LO = false, int DEEP = 0, int SPBt = SPB>
-__device__ __forceinline__ Acc slab_rows(const SellView<T>& S, const XT* __restrict__ xs, Acc* s_part) {
+__device__ __forceinline__ Acc slab_rows(const SellView<T>& S, const XT* __restrict__ xs, Acc* s_part,
+                                         const FirstGroup<T>* first = nullptr) {
     constexpr int KSP = SPB * KSPLIT / SPBt;   // wavefronts per slice
     constexpr int CPW = KSPLIT / KSP;          // chunks per wavefront
     constexpr int SLABt = SPBt * SLICE;
@@ -361,9 +386,10 @@ __device__ __forceinline__ Acc slab_rows(const SellView<T>& S, const XT* __restr
         const int w = S.slice_w[s];   // a multiple of 4
         const int kc = ((w >> 2) + KSPLIT - 1) / KSPLIT * 4;
         if constexpr (CPW == 1) {
-            const int k0 = min(w, kp * kc), k1 = min(w, k0 + kc);
+            int k0, k1;
+            chunk_range(S, s, kp, k0, k1);
             constexpr int G = DEEP > 0 ? DEEP / 4 : 1;   // groups of loads in flight
-            acc[0] = sell_dot<T, XT, Acc, LO, G>(S.val, S.lo, S.col, S.slice_ptr[s], k0, k1, lane, xs);
+            acc[0] = sell_dot<T, XT, Acc, LO, G>(S.val, S.lo, S.col, S.slice_ptr[s], k0, k1, lane, xs, first);
         } else {
             int k0[CPW], k1[CPW];
 #pragma unroll
@@ -393,12 +419,30 @@ template <class VT, class XT, class Acc, bool LO = false, int DEEP = 0, int SPBt
 __device__ __forceinline__ Acc slab_rows_x(const SellView<VT>& S, const ST* __restrict__ src, int n, XT* lds,
                                            bool stage, const float* __restrict__ scale, Acc* s_part) {
     if (stage) {
+        // one wavefront per chunk: load the chunk's first group before x is
+        // staged, so that the two memory round trips overlap
+        FirstGroup<VT> fg;
+        constexpr bool PRE = SPBt == SPB;
+        if (PRE) {
+            const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+            const int64_t s = int64_t(blockIdx.x) * SPB + wave / KSPLIT;
+            if (s < S.nslices) {
+                int k0, k1;
+                chunk_range(S, s, wave % KSPLIT, k0, k1);
+                if (k0 < k1) {
+                    const size_t e = S.slice_ptr[s] + size_t(k0 >> 2) * (4 * SLICE) + size_t(lane) * 4;
+                    fg.v = *reinterpret_cast<const Quad<VT>*>(S.val + e);
+                    fg.c = *reinterpret_cast<const Quad<uint16_t>*>(S.col + e);
+                    if (LO) fg.l = *reinterpret_cast<const Quad<__half>*>(S.lo + e);
+                }
+            }
+        }
         if (scale)
             for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = XT(src[i]) * XT(scale[i]);
         else
             for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = XT(src[i]);
         __syncthreads();
-        return slab_rows<VT, XT, Acc, LO, DEEP, SPBt>(S, lds, s_part);
+        return slab_rows<VT, XT, Acc, LO, DEEP, SPBt>(S, lds, s_part, PRE ? &fg : nullptr);
     }
     return slab_rows<VT, XT, Acc, LO, DEEP, SPBt>(S, reinterpret_cast<const XT*>(src), s_part);
 }
