@@ -569,20 +569,28 @@ __global__ void __launch_bounds__(BLOCK) k_gradT(const int32_t* __restrict__ cpt
         }
     } else {
         // PF entries per thread in flight: rows and values, then the gathers
-        // of u, then the products in entry order (the same sums)
-        for (; e + (PF - 1) * BLOCK < e1; e += PF * BLOCK) {
+        // of u, then the products in entry order (the same sums).  Entries
+        // past the column's end read its last entry (a valid address, no
+        // branch around the load) and are left out of the sum, so the whole
+        // batch is in flight at once
+        for (; e < e1; e += PF * BLOCK) {
             int32_t r[PF];
             T v[PF];
 #pragma unroll
             for (int q = 0; q < PF; ++q) {
-                r[q] = crow[e + q * BLOCK];
-                v[q] = cval[e + q * BLOCK];
+                const int ee = min(e + q * BLOCK, e1 - 1);
+                r[q] = crow[ee];
+                v[q] = cval[ee];
             }
             UT w[PF];
 #pragma unroll
             for (int q = 0; q < PF; ++q) w[q] = u[r[q]];
 #pragma unroll
-            for (int q = 0; q < PF; ++q) acc += Acc(dval2<T, LO>(v[q], clo + e + q * BLOCK)) * Acc(w[q]);
+            for (int q = 0; q < PF; ++q) {
+                const int ee = min(e + q * BLOCK, e1 - 1);
+                const Acc term = Acc(dval2<T, LO>(v[q], clo + ee)) * Acc(w[q]);
+                if (e + q * BLOCK < e1) acc += term;
+            }
         }
     }
     for (; e < e1; e += BLOCK) acc += Acc(dval2<T, LO>(cval[e], clo + e)) * Acc(u[crow[e]]);
