@@ -558,16 +558,7 @@ __global__ void __launch_bounds__(BLOCK) k_gradT(const int32_t* __restrict__ cpt
     const int e0 = cptr[i], e1 = cptr[i + 1];
     Acc acc = Acc(0);
     int e = e0 + threadIdx.x;
-    if (PF <= 4) {
-        for (; e + 3 * BLOCK < e1; e += 4 * BLOCK) {
-            const int32_t r0 = crow[e], r1 = crow[e + BLOCK], r2 = crow[e + 2 * BLOCK], r3 = crow[e + 3 * BLOCK];
-            const T v0 = cval[e], v1 = cval[e + BLOCK], v2 = cval[e + 2 * BLOCK], v3 = cval[e + 3 * BLOCK];
-            acc += Acc(dval2<T, LO>(v0, clo + e)) * Acc(u[r0]);
-            acc += Acc(dval2<T, LO>(v1, clo + e + BLOCK)) * Acc(u[r1]);
-            acc += Acc(dval2<T, LO>(v2, clo + e + 2 * BLOCK)) * Acc(u[r2]);
-            acc += Acc(dval2<T, LO>(v3, clo + e + 3 * BLOCK)) * Acc(u[r3]);
-        }
-    } else {
+    {
         // PF entries per thread in flight: rows and values, then the gathers
         // of u, then the products in entry order (the same sums).  Entries
         // past the column's end read its last entry (a valid address, no
