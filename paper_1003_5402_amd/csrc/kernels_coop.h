@@ -626,9 +626,11 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             if (threadIdx.x < K) {
                 const int k = threadIdx.x;
                 const double pk = s_p[k];
-                const double ratio = pk < 0.0 ? s_y[k] / (-pk) : INFINITY;
                 double yn = s_y[k] + t * pk;
-                if (t == tmax && ratio == t) yn = 0.0;
+                if (t == tmax) {   // an aperture that blocks the step ends at exactly 0
+                    const double ratio = pk < 0.0 ? s_y[k] / (-pk) : INFINITY;
+                    if (ratio == t) yn = 0.0;
+                }
                 s_y[k] = fmax(yn, 0.0);
             }
             steps += 1;
@@ -647,7 +649,10 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                 s_ms.ls_iter = ls.ls_iter;
                 s_ms.total_ls = ls.total_ls;
             }
-            __syncthreads();   // y visible to the next update pass
+            // y must be visible before a refresh update pass reads it; every
+            // other reader of y and of s_ms comes after the update pass's
+            // own barriers
+            if (mode == 1) __syncthreads();
             tick(5);
         }
     }
