@@ -1,10 +1,9 @@
 """Pins for the pricing oracle (eq. 8 and the row scan of Section 2.3).
 
-* The single left-to-right scan of Section 2.3 (running sum, running
-  maximum prefix, best value; Bates & Constable / Bentley), written here from
-  its description, must give the same leaves and value as the oracle's
-  enumeration on random rows, on integer rows with constructed exact ties and
-  on all-non-negative rows.
+* A prefix-sum formulation of the row minimum (interval sum = difference of
+  two prefix sums; exact rational arithmetic) must give the same leaves and
+  value as the oracle's enumeration on random rows, on integer rows with
+  constructed exact ties and on all-non-negative rows.
 * Brute force over every deliverable aperture of small beams
   ((n(n+1)/2 + 1)^rows apertures) must reach the same beam value, and the
   same aperture when the minimum is unique.
@@ -23,28 +22,24 @@ from conftest import cached_phantom, oracle_problem
 from oracle.aperture import Aperture
 
 
-def paper_row_scan(w):
-    """The row scan of Section 2.3 in its own 1-based notation.
-
-    v: running sum, vbar: best prefix so far, vstar: best value so far,
-    l/r: current leaf positions, lstar/rstar: best leaf positions.
-    The open beamlets are those strictly between lstar and rstar (1-based),
-    i.e. 0-based [lstar, rstar - 1).
-    """
-    n = len(w)
-    v = vbar = vstar = 0.0
-    l = lstar = 0
-    rstar = 1
-    for r in range(1, n + 1):
-        v = v + w[r - 1]
-        if v > vbar:
-            vbar = v
-            l = r
-        if v - vbar < vstar:
-            vstar = v - vbar
-            lstar = l
-            rstar = r + 1
-    return lstar, rstar - 1, vstar
+def prefix_row_min(w):
+    """Minimum-sum interval of a row from prefix sums, in exact rational
+    arithmetic.  With P[0] = 0 and P[k] = w_0 + ... + w_{k-1}, the interval
+    [l, r) sums to P[r] - P[l]; for each right end r the best interval ends
+    there and starts at the earliest l < r with the largest P[l]; over right
+    ends in increasing order only a strictly smaller value replaces the best,
+    which starts at 0 with the row closed.  Independent of the oracle's
+    enumeration (no interval sums are formed one by one)."""
+    from fractions import Fraction
+    P = [Fraction(0)]
+    for v in w:
+        P.append(P[-1] + Fraction(float(v)))
+    best, L, R = Fraction(0), 0, 0
+    for r in range(1, len(w) + 1):
+        lmax = max(range(r), key=lambda l: (P[l], -l))
+        if P[r] - P[lmax] < best:
+            best, L, R = P[r] - P[lmax], lmax, r
+    return L, R, float(best)
 
 
 def _rows(rng):
@@ -60,7 +55,7 @@ def test_scan_equals_enumeration():
     rng = np.random.default_rng(0)
     for w in _rows(rng):
         L, R, best, second = oracle.price_row(w)
-        l2, r2, v2 = paper_row_scan(list(w))
+        l2, r2, v2 = prefix_row_min(list(w))
         if R == L:
             assert (l2, r2) in [(0, 0)] and v2 == 0.0
         else:
