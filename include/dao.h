@@ -49,6 +49,8 @@ typedef enum {
     DAO_OK = 0,
     DAO_EOPTIMAL = 1,   /* dao_solve stopped: no aperture prices below -tau */
     DAO_ESTALLED = 2,   /* dao_solve stopped: pricing kept returning a pool member */
+    DAO_ENOTCONV = 3,   /* dao_master_solve stopped at max_steps with the KKT residual still
+                           above tol; the state is valid (not an error) */
     DAO_EINVAL = -1,    /* malformed argument; nothing was changed */
     DAO_ENOMEM = -2,    /* device allocation failed or exceeded mem_cap_bytes */
     DAO_EDEVICE = -3,   /* a HIP call failed */
@@ -226,12 +228,17 @@ dao_status dao_add_aperture(dao_ctx* ctx, int32_t beam, const int16_t* leaves);
  * step (*kkt) and the step length (*step, 0 if already at a KKT point). */
 dao_status dao_master_step(dao_ctx* ctx, double* F, double* kkt, double* step);
 
-/* Gradient projection until KKT residual <= tol or max_steps steps. */
+/* Gradient projection until KKT residual <= tol or max_steps steps.
+ * Returns DAO_OK when the residual reached tol (or the projected direction
+ * vanished) and DAO_ENOTCONV when the step cap ended the solve first. */
 dao_status dao_master_solve(dao_ctx* ctx, double tol, int32_t max_steps,
                             int32_t* steps, double* kkt, double* F);
 
-/* Prices at the current master point in FP64 and returns the entering
- * aperture (same outputs as dao_price). */
+/* Prices at the current intensities in FP64 and returns the entering
+ * aperture (same outputs as dao_price).  The master dose is first
+ * recomputed as D (A y) with FP64 products and sums (eq. 7, eq. 1), so the
+ * prices (eq. 8 with pi = grad F) are those of the current y, not of the
+ * master's incrementally updated dose; the master continues from that dose. */
 dao_status dao_price_current(dao_ctx* ctx, int32_t* beam, int16_t* leaves,
                              double* rc, double* gap);
 
@@ -308,6 +315,9 @@ typedef struct {
     double* round_F;
     double price_s;           /* host wall-clock seconds in pricing (incl. the gradient refresh) */
     double master_s;          /* host wall-clock seconds in column building and master solves */
+    int32_t* round_stop;      /* why each round's master stopped: 1 KKT residual <= tol,
+                                 2 step cap (max_steps) reached first, 3 zero projected direction */
+    int32_t capped_rounds;    /* rounds whose master stopped at the step cap */
 } dao_plan;
 
 /* Column generation (Section 2.2, Section 2.3) from an empty pool: round 1
@@ -317,6 +327,42 @@ typedef struct {
  * otherwise adds the aperture and solves the master to
  * eps * |rc_1| or max_steps.  Stops after n_apertures apertures. */
 dao_status dao_solve(dao_ctx* ctx, int32_t n_apertures, dao_plan* out);
+
+/* Checkpoint and resume of a plan (also used to restore an arbitrary pool and
+ * intensities, e.g. a reference solve's state, before pricing or a master
+ * solve).  The state is the pool in entry order, y, and the column-generation
+ * loop's scalars below; the dose is not part of it: dao_set_state recomputes
+ * it as D (A y) in FP64, which is also the dose every round's pricing uses,
+ * so a plan resumed from a checkpoint taken between rounds repeats the
+ * uninterrupted plan. */
+typedef struct {
+    int32_t n;          /* pool size */
+    int32_t tighten;    /* master tolerance tightenings so far */
+    double rc1;         /* reduced cost of round 1 (NaN: no round priced yet) */
+    double eps;         /* current master tolerance factor (tolerance = eps * |rc1|) */
+    double last_step;   /* length of the last master step (0 if none) */
+    double prev_step;   /* length of the step before it (the next line search starts there) */
+} dao_state_info;
+
+/* Copy the state out: beams[cap], leaves[cap * 2 * max_rows_per_beam]
+ * (layout of dao_get_pool), y[cap] and *info.  DAO_EINVAL if cap is smaller
+ * than the pool. */
+dao_status dao_get_state(dao_ctx* ctx, int32_t cap, int32_t* beams, int16_t* leaves, double* y,
+                         dao_state_info* info);
+
+/* Replace the pool and intensities by info->n apertures (arrays laid out as
+ * dao_get_state's) and y[info->n] (finite, >= 0), and set the loop scalars.
+ * Rebuilds the aperture dose matrix, the dose D (A y) (FP64), the objective
+ * and the prices.  DAO_EINVAL for a malformed aperture or value (nothing is
+ * changed then). */
+dao_status dao_set_state(dao_ctx* ctx, const dao_state_info* info, const int32_t* beams,
+                         const int16_t* leaves, const double* y);
+
+/* Column generation continued from the current pool (dao_set_state or an
+ * earlier solve) under dao_solve's rules, with the loop's rc1, eps and
+ * tightenings carried over, until the pool holds n_apertures.  The plan's
+ * round arrays cover the rounds of this call. */
+dao_status dao_solve_resume(dao_ctx* ctx, int32_t n_apertures, dao_plan* out);
 
 /* Several independent solves advanced together (the serving form): each
  * round prices every live solve and adds its column, then one cooperative

@@ -10,12 +10,13 @@ import numpy as np
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdao.so")
 
-DAO_OK, DAO_EOPTIMAL, DAO_ESTALLED = 0, 1, 2
+DAO_OK, DAO_EOPTIMAL, DAO_ESTALLED, DAO_ENOTCONV = 0, 1, 2, 3
 DAO_EINVAL, DAO_ENOMEM, DAO_EDEVICE, DAO_ESTATE = -1, -2, -3, -4
 DAO_F64, DAO_F32 = 0, 1
 DAO_MASTER_APERTURE, DAO_MASTER_BEAMLET = 0, 1
 DAO_DFMT_NATIVE, DAO_DFMT_F16, DAO_DFMT_BF16 = 0, 1, 2
-_NAMES = {0: "DAO_OK", 1: "DAO_EOPTIMAL", 2: "DAO_ESTALLED", -1: "DAO_EINVAL", -2: "DAO_ENOMEM",
+_NAMES = {0: "DAO_OK", 1: "DAO_EOPTIMAL", 2: "DAO_ESTALLED", 3: "DAO_ENOTCONV", -1: "DAO_EINVAL",
+          -2: "DAO_ENOMEM",
           -3: "DAO_EDEVICE", -4: "DAO_ESTATE"}
 
 
@@ -72,7 +73,13 @@ class dao_plan(ctypes.Structure):
                 ("round_beam", POINTER(c_int32)), ("round_rc", POINTER(c_double)),
                 ("round_gap", POINTER(c_double)), ("round_steps", POINTER(c_int32)),
                 ("round_kkt", POINTER(c_double)), ("round_F", POINTER(c_double)),
-                ("price_s", c_double), ("master_s", c_double)]
+                ("price_s", c_double), ("master_s", c_double),
+                ("round_stop", POINTER(c_int32)), ("capped_rounds", c_int32)]
+
+
+class dao_state_info(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("tighten", c_int32), ("rc1", c_double), ("eps", c_double),
+                ("last_step", c_double), ("prev_step", c_double)]
 
 
 # name -> (restype, argtypes); every symbol include/dao.h declares
@@ -99,6 +106,11 @@ _SIGS = {
                                POINTER(c_double)]),
     "dao_get_dose": (c_int32, [c_void_p, c_void_p, POINTER(c_double)]),
     "dao_solve": (c_int32, [c_void_p, c_int32, POINTER(dao_plan)]),
+    "dao_solve_resume": (c_int32, [c_void_p, c_int32, POINTER(dao_plan)]),
+    "dao_get_state": (c_int32, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int16), POINTER(c_double),
+                                POINTER(dao_state_info)]),
+    "dao_set_state": (c_int32, [c_void_p, POINTER(dao_state_info), POINTER(c_int32), POINTER(c_int16),
+                                POINTER(c_double)]),
     "dao_solve_batch": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_int32), POINTER(dao_plan)]),
     "dao_server_create": (c_int32, [c_void_p, c_void_p, POINTER(c_void_p)]),
     "dao_server_destroy": (None, [c_void_p]),
@@ -168,7 +180,8 @@ def _addr(v) -> int:
 def _plan_arrays(n):
     n = max(1, int(n))
     arr = dict(round_beam=np.zeros(n, np.int32), round_rc=np.zeros(n), round_gap=np.zeros(n),
-               round_steps=np.zeros(n, np.int32), round_kkt=np.zeros(n), round_F=np.zeros(n))
+               round_steps=np.zeros(n, np.int32), round_kkt=np.zeros(n), round_F=np.zeros(n),
+               round_stop=np.zeros(n, np.int32))
     P = dao_plan()
     for k, a in arr.items():
         setattr(P, k, _ptr(a, c_int32 if a.dtype == np.int32 else c_double))
@@ -179,7 +192,7 @@ def _plan_dict(P, arr, st):
     r = P.rounds
     return dict(status=st, rounds=r, stop=P.stop, F=P.F, rc1=P.rc1, total_steps=P.total_steps,
                 total_ls_evals=P.total_ls_evals, price_s=P.price_s, master_s=P.master_s,
-                **{k: v[:r].copy() for k, v in arr.items()})
+                capped_rounds=P.capped_rounds, **{k: v[:r].copy() for k, v in arr.items()})
 
 
 def solve_batch(ctxs, n_apertures) -> list:
@@ -316,10 +329,46 @@ class DaoContext:
         return F.value, kkt.value, step.value
 
     def master_solve(self, tol: float, max_steps: int):
+        """(steps, kkt, F); ``self.last_master_capped`` tells whether the step
+        cap ended the solve (DAO_ENOTCONV)."""
         steps, kkt, F = c_int32(), c_double(), c_double()
-        self._check(self._lib.dao_master_solve(self._h, float(tol), int(max_steps), byref(steps),
-                                               byref(kkt), byref(F)))
+        st = self._check(self._lib.dao_master_solve(self._h, float(tol), int(max_steps), byref(steps),
+                                                    byref(kkt), byref(F)))
+        self.last_master_capped = st == DAO_ENOTCONV
         return steps.value, kkt.value, F.value
+
+    def get_state(self, cap: int = 256) -> Dict:
+        """Pool, intensities and loop scalars (dao_get_state)."""
+        beams = np.zeros(cap, dtype=np.int32)
+        lv = np.zeros(cap * 2 * self.max_rows_per_beam, dtype=np.int16)
+        y = np.zeros(cap, dtype=np.float64)
+        info = dao_state_info()
+        self._check(self._lib.dao_get_state(self._h, cap, _ptr(beams, c_int32), _ptr(lv, c_int16),
+                                            _ptr(y, c_double), byref(info)))
+        n = info.n
+        lv = lv.reshape(cap, self.max_rows_per_beam, 2)
+        pool = [(int(beams[i]), tuple((int(a), int(b)) for a, b in lv[i, :int(self.rows_per_beam[beams[i]])]))
+                for i in range(n)]
+        return dict(pool=pool, y=y[:n].copy(), rc1=info.rc1, eps=info.eps, tighten=info.tighten,
+                    last_step=info.last_step, prev_step=info.prev_step)
+
+    def set_state(self, pool, y, rc1: float = float("nan"), eps: Optional[float] = None, tighten: int = 0,
+                  last_step: float = 0.0, prev_step: float = 0.0) -> None:
+        """Restore a pool [(beam, ((L, R), ...)), ...] and intensities (dao_set_state)."""
+        n = len(pool)
+        m = max(1, n)
+        beams = np.zeros(m, dtype=np.int32)
+        lv = np.zeros((m, self.max_rows_per_beam, 2), dtype=np.int16)
+        for i, (b, leaves) in enumerate(pool):
+            beams[i] = int(b)
+            fl = np.asarray(leaves, dtype=np.int16).reshape(-1, 2)
+            lv[i, :fl.shape[0]] = fl
+        yv = np.zeros(m, dtype=np.float64)
+        yv[:n] = np.asarray(y, dtype=np.float64)[:n]
+        info = dao_state_info(n, int(tighten), float(rc1), float(eps if eps is not None else self.opts.eps),
+                              float(last_step), float(prev_step))
+        self._check(self._lib.dao_set_state(self._h, byref(info), _ptr(beams, c_int32),
+                                            _ptr(lv.reshape(-1), c_int16), _ptr(yv, c_double)))
 
     def get_pool(self, cap: int = 256):
         n = c_int32()
@@ -374,17 +423,15 @@ class DaoContext:
         return dict(launches=n.value, working_launches=w.value, total_us=us.value, total_bytes=b.value)
 
     def solve(self, n_apertures: int) -> Dict:
-        n = max(1, int(n_apertures))
-        arr = dict(round_beam=np.zeros(n, np.int32), round_rc=np.zeros(n), round_gap=np.zeros(n),
-                   round_steps=np.zeros(n, np.int32), round_kkt=np.zeros(n), round_F=np.zeros(n))
-        P = dao_plan()
-        for k, a in arr.items():
-            setattr(P, k, _ptr(a, c_int32 if a.dtype == np.int32 else c_double))
+        P, arr = _plan_arrays(n_apertures)
         st = self._check(self._lib.dao_solve(self._h, int(n_apertures), byref(P)))
-        r = P.rounds
-        return dict(status=st, rounds=r, stop=P.stop, F=P.F, rc1=P.rc1, total_steps=P.total_steps,
-                    total_ls_evals=P.total_ls_evals, price_s=P.price_s, master_s=P.master_s,
-                    **{k: v[:r].copy() for k, v in arr.items()})
+        return _plan_dict(P, arr, st)
+
+    def solve_resume(self, n_apertures: int) -> Dict:
+        """Column generation continued from the current pool (dao_solve_resume)."""
+        P, arr = _plan_arrays(n_apertures)
+        st = self._check(self._lib.dao_solve_resume(self._h, int(n_apertures), byref(P)))
+        return _plan_dict(P, arr, st)
 
 
 class Server:

@@ -100,6 +100,11 @@ struct dao_ctx {
     int dose_var = 0;                  // k_dose variant (0 staged, 1 staged + deep loads, 2 global x + deep)
     int gradT_pf = 4;                  // k_gradT entries in flight per thread (4, 8 or 16)
     int last_steps = 0;                // steps of the previous master solve (chunk size guess)
+    // column-generation loop state of the last (or restored) solve, for resume
+    double loop_rc1 = NAN;             // reduced cost of round 1 (NaN: none yet)
+    double loop_eps = 0.0;             // current master tolerance factor
+    int loop_tighten = 0;              // tightenings so far
+    int last_stop = 0;                 // stop reason of the last master solve (MasterState.stop_reason)
     std::vector<hipEvent_t> prof_events;
     size_t prof_used = 0;
     void* g = nullptr;         // [N] ctx type
@@ -498,6 +503,7 @@ dao_status run_master_coop(dao_ctx* c, double tol, int max_steps) {
     if (c->ms_h->stop_reason == 4 || !c->ms_h->done)
         return c->fail(DAO_EDEVICE, "persistent master: grid reduction timed out");
     c->last_steps = c->ms_h->steps;
+    c->last_stop = c->ms_h->stop_reason;
     return DAO_OK;
 }
 
@@ -530,6 +536,7 @@ dao_status run_master(dao_ctx* c, double tol, int max_steps) {
         chunk = std::max(4, std::min(32, (max_steps - c->ms_h->steps) / 4 + 4));
     }
     c->last_steps = c->ms_h->steps;
+    c->last_stop = c->ms_h->stop_reason;
     c->last_form = 0;
     return DAO_OK;
 }
@@ -561,11 +568,41 @@ dao_status price_on(dao_ctx* c, const double* g, int32_t* beam, int16_t* leaves,
     return DAO_OK;
 }
 
-// FP64 prices at the master's current dose (g64 = D^T grad F(d), FP64 sums).
+// The master dose recomputed from the intensities in FP64 (x = A y, then
+// d = D x with FP64 products and sums), replacing the master's incremental
+// dose.
 template <class T>
-dao_status price_current(dao_ctx* c, int32_t* beam, int16_t* leaves, double* rc, double* gap) {
+dao_status refresh_dose_exact(dao_ctx* c) {
+    k_pool_x<<<(c->N + BLOCK - 1) / BLOCK, BLOCK, 0, c->stream>>>(pool_view(c), c->K, c->y, c->x64);
+    with_values<T>(c, [&](auto tag) {
+        using VT = typename decltype(tag)::VT;
+        constexpr bool LO = decltype(tag)::LO;
+        k_dose_exact<VT, LO><<<c->slab_blocks(), SLAB_THREADS, c->stage_x64() ? c->N * 8 : 0, c->stream>>>(
+            sell_view<VT>(c), c->Vpad, c->x64, int(c->N), c->stage_x64(), c->col_scale, c->d);
+    });
+    LAUNCHCHK(c);
+    return DAO_OK;
+}
+
+// u, u64, F and g (ctx type) after the master dose changed outside a master
+// solve.
+template <class T>
+dao_status refresh_objective(dao_ctx* c) {
     k_objective_int<T><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
         c->d, c->cls_int, c->Vpad, c->classes, static_cast<T*>(c->u), c->u64, c->parts, c->arr, c->ms);
+    if (!c->ap_master()) launch_gradT<T, T, T, T>(c, static_cast<const T*>(c->u), static_cast<T*>(c->g));
+    LAUNCHCHK(c);
+    return DAO_OK;
+}
+
+// FP64 prices at the current intensities: the dose is first recomputed as
+// D (A y) in FP64, then g64 = D^T grad F(d) with FP64 sums.
+template <class T>
+dao_status price_current(dao_ctx* c, int32_t* beam, int16_t* leaves, double* rc, double* gap) {
+    dao_status s = refresh_dose_exact<T>(c);
+    if (s != DAO_OK) return s;
+    s = refresh_objective<T>(c);
+    if (s != DAO_OK) return s;
     launch_gradT<T, double, double, double>(c, c->u64, c->g64);
     LAUNCHCHK(c);
     return price_on(c, c->g64, beam, leaves, rc, gap);
@@ -880,6 +917,46 @@ dao_status master_solve_typed(dao_ctx* c, double tol, int max_steps, int32_t* st
     if (steps) *steps = c->ms_h->steps;
     if (kkt) *kkt = c->ms_h->kkt;
     if (F) *F = c->ms_h->F;
+    return c->ms_h->stop_reason == 2 ? DAO_ENOTCONV : DAO_OK;
+}
+
+// Restore a pool, its intensities and the loop state: the columns of D_K are
+// rebuilt, the dose is D (A y) in FP64 and the objective, grad F and prices
+// follow from it.
+template <class T>
+dao_status set_state_typed(dao_ctx* c, const dao_state_info* info, const int32_t* beams, const int16_t* leaves,
+                           const double* y) {
+    dao_status s = reset_state<T>(c);
+    if (s != DAO_OK) return s;
+    const int n = info->n;
+    for (int k = 0; k < n; ++k) {
+        const int16_t* lv = leaves + size_t(k) * 2 * c->maxRB;
+        const int nr = c->rows_per_beam[beams[k]];
+        for (int i = 0; i < c->maxRB; ++i) {
+            c->lv_stage_h[2 * i] = i < nr ? lv[2 * i] : int16_t(0);
+            c->lv_stage_h[2 * i + 1] = i < nr ? lv[2 * i + 1] : int16_t(0);
+        }
+        HIPCHK(c, hipMemcpyAsync(c->ap_lv + size_t(k) * c->maxRB * 2, c->lv_stage_h, size_t(c->maxRB) * 4,
+                                 hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->ap_beam + k, beams + k, 4, hipMemcpyHostToDevice, c->stream));
+        // the staging buffer is reused by the next aperture
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        s = build_dk_column<T>(c, k);
+        if (s != DAO_OK) return s;
+        mirror_add(c, beams[k], lv);
+        c->K = k + 1;
+    }
+    if (n > 0) HIPCHK(c, hipMemcpyAsync(c->y, y, size_t(n) * 8, hipMemcpyHostToDevice, c->stream));
+    k_set_history<<<1, 1, 0, c->stream>>>(c->ms, info->last_step, info->prev_step);
+    LAUNCHCHK(c);
+    s = refresh_dose_exact<T>(c);
+    if (s != DAO_OK) return s;
+    s = refresh_objective<T>(c);
+    if (s != DAO_OK) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->loop_rc1 = info->rc1;
+    c->loop_eps = info->eps;
+    c->loop_tighten = info->tighten;
     return DAO_OK;
 }
 
@@ -893,7 +970,7 @@ struct PlanRun {
     int32_t n_ap = 0;
     dao_plan* out = nullptr;
     double eps = 0.0, rc1 = NAN, tol = 0.0;
-    int tighten = 0, rounds = 0;
+    int tighten = 0, rounds = 0, capped = 0;
     int32_t stop = DAO_OK;
     int64_t steps0 = 0, ls0 = 0;
     double t_price = 0.0, t_master = 0.0;
@@ -904,12 +981,23 @@ struct PlanRun {
     clk::time_point tm;
 };
 
+// A fresh solve starts from an empty pool; a resumed one from the context's
+// current pool, intensities and loop state (dao_set_state or an earlier
+// solve), numbering its rounds on from the pool size.
 template <class T>
-dao_status plan_start(PlanRun& r) {
+dao_status plan_start(PlanRun& r, bool resume = false) {
     dao_ctx* c = r.c;
-    dao_status s = reset_state<T>(c);
-    if (s != DAO_OK) return s;
-    r.eps = c->opt.eps;
+    if (resume) {
+        r.eps = c->loop_eps > 0.0 ? c->loop_eps : c->opt.eps;
+        r.rc1 = c->loop_rc1;
+        r.tighten = c->loop_tighten;
+    } else {
+        dao_status s = reset_state<T>(c);
+        if (s != DAO_OK) return s;
+        r.eps = c->opt.eps;
+        r.rc1 = NAN;
+        r.tighten = 0;
+    }
     HIPCHK(c, hipMemcpyAsync(c->ms_h, c->ms, sizeof(MasterState), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     r.steps0 = c->ms_h->total_steps;
@@ -982,7 +1070,9 @@ void plan_round_end(PlanRun& r) {
         if (out->round_steps) out->round_steps[r.rounds] = c->ms_h->steps;
         if (out->round_kkt) out->round_kkt[r.rounds] = c->ms_h->kkt;
         if (out->round_F) out->round_F[r.rounds] = c->ms_h->F;
+        if (out->round_stop) out->round_stop[r.rounds] = c->ms_h->stop_reason;
     }
+    if (c->ms_h->stop_reason == 2) ++r.capped;
     ++r.rounds;
 }
 
@@ -999,17 +1089,21 @@ dao_status plan_finish(PlanRun& r) {
         out->total_ls_evals = c->ms_h->total_ls - r.ls0;
         out->price_s = r.t_price;
         out->master_s = r.t_master;
+        out->capped_rounds = r.capped;
     }
+    c->loop_rc1 = r.rc1;
+    c->loop_eps = r.eps;
+    c->loop_tighten = r.tighten;
     return DAO_OK;
 }
 
 template <class T>
-dao_status solve_typed(dao_ctx* c, int32_t n_ap, dao_plan* out) {
+dao_status solve_typed(dao_ctx* c, int32_t n_ap, dao_plan* out, bool resume = false) {
     PlanRun r;
     r.c = c;
     r.n_ap = n_ap;
     r.out = out;
-    dao_status s = plan_start<T>(r);
+    dao_status s = plan_start<T>(r, resume);
     if (s != DAO_OK) return s;
     for (;;) {
         s = plan_round_begin<T>(r);
@@ -1109,6 +1203,7 @@ dao_status run_master_batch(std::vector<PlanRun*>& live) {
         if (r->c->ms_h->stop_reason == 4 || !r->c->ms_h->done)
             return r->c->fail(DAO_EDEVICE, "batched persistent master: grid reduction timed out");
         r->c->last_steps = r->c->ms_h->steps;
+        r->c->last_stop = r->c->ms_h->stop_reason;
     }
     return DAO_OK;
 }
@@ -1467,6 +1562,58 @@ dao_status dao_solve_batch(dao_ctx* const* ctxs, int32_t n, const int32_t* n_ape
     }
     return ctxs[0]->dtype == DAO_F64 ? solve_batch_typed<double>(ctxs, n, n_apertures, plans)
                                      : solve_batch_typed<float>(ctxs, n, n_apertures, plans);
+}
+
+dao_status dao_get_state(dao_ctx* c, int32_t cap, int32_t* beams, int16_t* leaves, double* y,
+                         dao_state_info* info) {
+    if (!c) return DAO_EINVAL;
+    if (!info) return c->fail(DAO_EINVAL, "null state info");
+    const int m = std::min<int>(std::max(cap, 0), c->K);
+    if (m > 0 && (!beams || !leaves || !y)) return c->fail(DAO_EINVAL, "null state arrays");
+    if (m < c->K) return c->fail(DAO_EINVAL, "cap is smaller than the pool");
+    dao_status s = dao_get_pool(c, cap, nullptr, beams, leaves, y);
+    if (s != DAO_OK) return s;
+    HIPCHK(c, hipMemcpyAsync(c->ms_h, c->ms, sizeof(MasterState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    info->n = c->K;
+    info->tighten = c->loop_tighten;
+    info->rc1 = c->loop_rc1;
+    info->eps = c->loop_eps > 0.0 ? c->loop_eps : c->opt.eps;
+    info->last_step = c->ms_h->last_step;
+    info->prev_step = c->ms_h->prev_step;
+    return DAO_OK;
+}
+
+dao_status dao_set_state(dao_ctx* c, const dao_state_info* info, const int32_t* beams, const int16_t* leaves,
+                         const double* y) {
+    if (!c) return DAO_EINVAL;
+    if (!info) return c->fail(DAO_EINVAL, "null state info");
+    const int n = info->n;
+    if (n < 0 || n > c->opt.max_apertures) return c->fail(DAO_EINVAL, "pool size out of range");
+    if (n > 0 && (!beams || !leaves || !y)) return c->fail(DAO_EINVAL, "null state arrays");
+    if (!(info->eps > 0.0) || !std::isfinite(info->eps)) return c->fail(DAO_EINVAL, "eps must be finite and > 0");
+    if (info->tighten < 0) return c->fail(DAO_EINVAL, "negative tighten count");
+    if (!(info->last_step >= 0.0) || !(info->prev_step >= 0.0) || !std::isfinite(info->last_step) ||
+        !std::isfinite(info->prev_step))
+        return c->fail(DAO_EINVAL, "step history must be finite and >= 0");
+    if (!std::isnan(info->rc1) && !std::isfinite(info->rc1)) return c->fail(DAO_EINVAL, "rc1 must be finite or NaN");
+    for (int k = 0; k < n; ++k) {
+        dao_status s = check_aperture(c, beams[k], leaves + size_t(k) * 2 * c->maxRB);
+        if (s != DAO_OK) return s;
+        if (!(y[k] >= 0.0) || !std::isfinite(y[k])) return c->fail(DAO_EINVAL, "intensities must be finite and >= 0");
+    }
+    return c->dtype == DAO_F64 ? set_state_typed<double>(c, info, beams, leaves, y)
+                               : set_state_typed<float>(c, info, beams, leaves, y);
+}
+
+dao_status dao_solve_resume(dao_ctx* c, int32_t n_apertures, dao_plan* out) {
+    if (!c) return DAO_EINVAL;
+    if (n_apertures < 0 || n_apertures > c->opt.max_apertures)
+        return c->fail(DAO_EINVAL, "n_apertures must be in [0, max_apertures]");
+    dao_status s = c->dtype == DAO_F64 ? solve_typed<double>(c, n_apertures, out, true)
+                                       : solve_typed<float>(c, n_apertures, out, true);
+    if (s != DAO_OK) return s;
+    return out ? dao_status(out->stop) : DAO_OK;
 }
 
 dao_status dao_solve(dao_ctx* c, int32_t n_apertures, dao_plan* out) {

@@ -471,6 +471,25 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_dose(SellView<VT> S, const int
     }
 }
 
+// The master dose from its intensities, in FP64 throughout: d[row] =
+// (D x64)_row over internal rows, every product D_ij x_i and every sum in
+// double (the stored D values are exact in double; a 16-bit format's scale
+// multiplies x first).  Used at every round end, so that the prices of the
+// sub-problem (eq. 8) see the dose of the current intensities rather than
+// the master's incremental one, and on a state restore.
+template <class VT, bool LO = false>
+__global__ void __launch_bounds__(SLAB_THREADS) k_dose_exact(SellView<VT> S, int64_t Vpad,
+                                                             const double* __restrict__ x64, int N, bool stage,
+                                                             const float* __restrict__ scale,
+                                                             double* __restrict__ d) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double s_part[KSPLIT * SLAB];
+    const double sum =
+        slab_rows_x<VT, double, double, LO>(S, x64, N, reinterpret_cast<double*>(smem), stage, scale, s_part);
+    const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
+    if (threadIdx.x < SLAB && row < Vpad) d[row] = sum;
+}
+
 template <class T>
 __global__ void k_fill(T* __restrict__ p, int64_t n, T v) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
@@ -761,6 +780,22 @@ __device__ __forceinline__ double pool_at_beamlet(const PoolView& P, int K, cons
         if (pos >= l[0] && pos < l[1]) acc += v[k];
     }
     return acc;
+}
+
+// x64[i] = sum over the pool of y_k for the apertures that open beamlet i
+// (eq. 7), added in pool order.
+__global__ void k_pool_x(PoolView P, int K, const double* __restrict__ y, double* __restrict__ x64) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P.N; i += gridDim.x * blockDim.x)
+        x64[i] = pool_at_beamlet(P, K, P.ap_beam, P.ap_lv, y, i);
+}
+
+// Line-search history of a restored state (the first trial point of the
+// next search is the step before the last).
+__global__ void k_set_history(MasterState* ms, double last_step, double prev_step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ms->last_step = last_step;
+        ms->prev_step = prev_step;
+    }
 }
 
 // Direction step (single block of 1024 threads): objective of the last
