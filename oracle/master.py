@@ -4,12 +4,23 @@ Section 2.3 solves the master -- the objective over the current pool of
 apertures with y >= 0 -- by the gradient projection method: move along the
 negative gradient, projected so that the intensities stay non-negative.  The
 paper takes the method from its earlier fluence-map work and gives no step
-rule, tolerance or iteration cap; this module fixes one reading of those
-details, and the HIP path follows the same reading:
+rule, tolerance or iteration cap; Section 2.2 and Section 2.3 only require
+that the master find the optimal intensities of the pool.  This module fixes
+one reading of those details, and the HIP path follows the same reading:
 
 * gradient over the pool:   grad_k = sum_{i in A_k} g_i,  g = D^T grad F(d)
-* projected direction:      p_k = -grad_k, except p_k = 0 where y_k = 0 and
-                            grad_k >= 0 (moving would leave the feasible set)
+* projected negative gradient r: r_k = -grad_k, except r_k = 0 where y_k = 0
+  and grad_k >= 0 (moving would leave the feasible set); the apertures with
+  r_k allowed to be non-zero form the free set
+* direction p (``conjugate=True``, the default): p = r + beta p_prev with
+  beta = max(0, r.(r - r_prev) / r_prev.r_prev) (Polak-Ribiere, truncated at
+  0), taken only when the previous step of this pool exists, did not block
+  (t < t_max) and had the same free set, and only if it is a descent
+  direction (grad.p < 0); otherwise p = r.  This is Polyak's conjugate
+  gradient projection: on a fixed face of the constraints and a fixed piece
+  of F it is the conjugate gradient method, which reaches the face's minimum
+  in at most |free set| steps, while the plain projected steepest descent
+  (``conjugate=False``: always p = r) zig-zags and may need thousands.
 * longest feasible step:    t_max = min over p_k < 0 of y_k / (-p_k)
 * exact line search of the convex piecewise quadratic phi(t) = F(d + t q),
   q = D (A p), on [0, t_max]   (see :func:`line_search`)
@@ -17,6 +28,11 @@ details, and the HIP path follows the same reading:
   and d += t q; every 50 steps d is recomputed as D (A y)
 * stop when the KKT residual max_k |min(y_k, grad_k)| <= tol, or after
   ``max_steps`` steps.
+
+The memory of the conjugate direction (previous p, r and free set) belongs
+to the master state: it is cleared when an aperture enters the pool and after
+a step that blocks, and kept across the 50-step dose recomputation and
+across consecutive solves of the same pool.
 """
 from __future__ import annotations
 
@@ -117,6 +133,14 @@ class MasterState:
     d: np.ndarray
     u: np.ndarray
     g: np.ndarray
+    # conjugate-direction memory: direction, projected gradient and free set
+    # of the last step (None: the next step starts from r)
+    p_prev: Optional[np.ndarray] = None
+    r_prev: Optional[np.ndarray] = None
+    free_prev: Optional[np.ndarray] = None
+
+    def forget_direction(self) -> None:
+        self.p_prev = self.r_prev = self.free_prev = None
 
     @classmethod
     def empty(cls, P: Problem) -> "MasterState":
@@ -133,6 +157,7 @@ class MasterState:
     def add(self, ap: Aperture) -> None:
         self.pool.append(ap)
         self.y = np.append(self.y, 0.0)
+        self.forget_direction()
 
 
 def kkt_residual(y: np.ndarray, grad: np.ndarray) -> float:
@@ -163,13 +188,27 @@ def take_step(y: np.ndarray, p: np.ndarray, t: float) -> np.ndarray:
     return np.maximum(out, 0.0)
 
 
-def master_step(P: Problem, st: MasterState) -> Optional[dict]:
+def direction(st: MasterState, grad: np.ndarray, conjugate: bool = True):
+    """Search direction p and the projected negative gradient r and free set
+    it came from (see the module docstring)."""
+    free = ~((st.y == 0.0) & (grad >= 0.0))
+    r = np.where(free, -grad, 0.0)
+    p = r
+    if (conjugate and st.r_prev is not None and st.r_prev.shape == r.shape
+            and np.array_equal(free, st.free_prev)):
+        beta = max(0.0, float(np.dot(r, r - st.r_prev)) / float(np.dot(st.r_prev, st.r_prev)))
+        cand = r + beta * st.p_prev
+        if float(np.dot(grad, cand)) < 0.0:
+            p = cand
+    return p, r, free
+
+
+def master_step(P: Problem, st: MasterState, conjugate: bool = True) -> Optional[dict]:
     """One gradient-projection iteration in place.  Returns its record, or
-    None when the projected direction is zero (an exact KKT point)."""
+    None when the projected negative gradient is zero (an exact KKT point)."""
     grad = aperture_gradient(P, st.pool, st.g)
-    p = -grad
-    p[(st.y == 0.0) & (grad >= 0.0)] = 0.0
-    if not np.any(p != 0.0):
+    p, r, free = direction(st, grad, conjugate)
+    if not np.any(r != 0.0):
         return None
     t_max = max_step(st.y, p)
     q = dose(P, beamlet_intensity(P, st.pool, p))
@@ -178,18 +217,22 @@ def master_step(P: Problem, st: MasterState) -> Optional[dict]:
     st.d = st.d + t * q
     st.u = grad_objective(P, st.d)
     st.g = prices(P, st.u)
+    if t == t_max:
+        st.forget_direction()
+    else:
+        st.p_prev, st.r_prev, st.free_prev = p, r, free
     return dict(t=t, t_max=t_max, ls_evals=evals, gphi0=float(np.dot(grad, p)))
 
 
 def solve_master(P: Problem, st: MasterState, tol: float, max_steps: int = 500,
-                 track_F: bool = False):
+                 track_F: bool = False, conjugate: bool = True):
     """Iterate :func:`master_step` until the KKT residual is at most ``tol``
     or ``max_steps`` steps were taken.  Returns a log dict."""
     Fs = [objective(P, st.d)] if track_F else []
     steps, evals = 0, 0
     kkt = kkt_residual(st.y, aperture_gradient(P, st.pool, st.g))
     while kkt > tol and steps < max_steps:
-        rec = master_step(P, st)
+        rec = master_step(P, st, conjugate)
         if rec is None:
             break
         steps += 1

@@ -16,7 +16,8 @@ used:
   ``max_tighten`` times over the solve), the master is re-solved and the
   round is priced again; after that the loop stops;
 * otherwise the aperture enters and the master runs to KKT residual
-  <= eps * |rc_1| (or ``max_steps`` steps);
+  <= eps * |rc_1| (or ``max_steps`` steps), by conjugate gradient projection
+  unless ``conjugate=False`` (see :mod:`oracle.master`);
 * the loop ends when the pool holds ``n_apertures`` apertures.
 """
 from __future__ import annotations
@@ -32,7 +33,7 @@ from .pricing import price
 
 def solve(P: Problem, n_apertures: int, eps: float = 1e-6, max_steps: int = 500,
           tau_rel: float = 1e-10, max_tighten: int = 3, track_F: bool = False,
-          on_round: Optional[Callable[[int, Dict, MasterState], None]] = None) -> Dict:
+          conjugate: bool = True, on_round: Optional[Callable[[int, Dict, MasterState], None]] = None) -> Dict:
     st = MasterState.empty(P)
     log: List[Dict] = []
     rc1 = None
@@ -55,10 +56,10 @@ def solve(P: Problem, n_apertures: int, eps: float = 1e-6, max_steps: int = 500,
                 break
             tighten += 1
             eps /= 10.0
-            solve_master(P, st, eps * scale, max_steps)
+            solve_master(P, st, eps * scale, max_steps, conjugate=conjugate)
             continue
         st.add(pr["aperture"])
-        mlog = solve_master(P, st, eps * scale, max_steps, track_F=track_F)
+        mlog = solve_master(P, st, eps * scale, max_steps, track_F=track_F, conjugate=conjugate)
         rec = dict(round=len(st.pool), beam=pr["aperture"].beam, rc=pr["rc"], gap=pr["gap"],
                    steps=mlog["steps"], ls_evals=mlog["ls_evals"], kkt=mlog["kkt"],
                    F=objective(P, st.d), F_trace=mlog["F_trace"])

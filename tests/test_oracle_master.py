@@ -10,6 +10,13 @@
 * General master against scipy's L-BFGS-B with bounds y >= 0.
 * Invariants: F never increases from one step to the next, and the KKT
   conditions hold at exit.
+* Conjugate gradient projection: on the NNLS special case (F one quadratic)
+  started on the optimum's face, the conjugate direction must reach the
+  NNLS optimum in K steps (the finite termination of conjugate gradients
+  with exact line searches), which plain projected steepest descent does
+  not; after a blocking step the next direction is the projected negative
+  gradient again.
+The pins on the converged master run in both direction modes.
 """
 import math
 
@@ -111,14 +118,15 @@ def _dk(P, pool):
     return np.stack(cols, axis=1)
 
 
-def test_master_matches_nnls_special_case():
+@pytest.mark.parametrize("conjugate", [True, False])
+def test_master_matches_nnls_special_case(conjugate):
     ph = cached_phantom("mini")
     P, reached = _single_target_problem(ph)
     pool = _pool(P, 5, 0)
     st = MasterState.empty(P)
     for ap in pool:
         st.add(ap)
-    log = solve_master(P, st, tol=1e-13, max_steps=20000)
+    log = solve_master(P, st, tol=1e-13, max_steps=20000, conjugate=conjugate)
     assert log["kkt"] <= 1e-13
     DK = _dk(P, pool)[reached]
     y_ref, _ = so.nnls(DK, np.full(DK.shape[0], 0.3), maxiter=10000)
@@ -128,15 +136,16 @@ def test_master_matches_nnls_special_case():
     np.testing.assert_allclose(st.y, y_ref, rtol=1e-5, atol=1e-7)
 
 
+@pytest.mark.parametrize("conjugate", [True, False])
 @pytest.mark.parametrize("seed", [1, 2])
-def test_master_matches_lbfgsb(seed):
+def test_master_matches_lbfgsb(seed, conjugate):
     ph = cached_phantom("mini")
     P = oracle_problem(ph)
     pool = _pool(P, 6, seed)
     st = MasterState.empty(P)
     for ap in pool:
         st.add(ap)
-    log = solve_master(P, st, tol=1e-12, max_steps=50000, track_F=True)
+    log = solve_master(P, st, tol=1e-12, max_steps=50000, track_F=True, conjugate=conjugate)
     assert log["kkt"] <= 1e-12
     DK = sp.csr_matrix(_dk(P, pool))
 
@@ -181,7 +190,8 @@ def test_line_search_pure_quadratic_clamps_to_t_max():
     assert t == 0.3 * t_free
 
 
-def test_blocking_apertures_land_exactly_on_zero():
+@pytest.mark.parametrize("conjugate", [True, False])
+def test_blocking_apertures_land_exactly_on_zero(conjugate):
     from oracle.master import master_step
     ph = cached_phantom("mini")
     P = oracle_problem(ph)
@@ -194,12 +204,14 @@ def test_blocking_apertures_land_exactly_on_zero():
         st.refresh(P)
         for _ in range(40):
             y_before = st.y.copy()
-            rec = master_step(P, st)
+            rec = master_step(P, st, conjugate)
             if rec is None:
                 break
             if rec["t"] == rec["t_max"]:
                 was_pos = y_before > 0
                 assert np.any(st.y[was_pos] == 0.0)
+                # a block ends the conjugate sequence
+                assert st.p_prev is None and st.r_prev is None
                 blocked += 1
     assert blocked >= 3
 
@@ -242,3 +254,70 @@ def test_line_search_returns_t_max_inside_first_piece():
     assert ev == 1 and abs(t_free - 50.0) < 1e-12
     t, ev = oracle.line_search(P, d, q, 12.5)
     assert t == 12.5 and ev == 1
+
+
+@pytest.mark.parametrize("seed", [0, 3, 5, 7, 10])
+def test_conjugate_projection_terminates_on_a_face(seed):
+    # F = c ||D_K y - T||^2 exactly (one target, T- = T+, alpha = beta) and a
+    # pool whose NNLS optimum is strictly positive; started inside the
+    # positive orthant near it, no step blocks, so the face never changes and
+    # conjugate gradients with exact line searches reach the minimiser in K
+    # steps.  Projected steepest descent from the same point does not.
+    from oracle.master import master_step
+    ph = cached_phantom("mini")
+    P, reached = _single_target_problem(ph)
+    K = 5
+    pool = _pool(P, K, seed)
+    DK = _dk(P, pool)[reached]
+    y_ref, _ = so.nnls(DK, np.full(DK.shape[0], 0.3))
+    assert np.min(y_ref) > 0
+    res = {}
+    for conjugate in (True, False):
+        st = MasterState.empty(P)
+        for ap in pool:
+            st.add(ap)
+        st.y = y_ref * np.random.default_rng(seed).uniform(0.5, 1.5, K)
+        st.refresh(P)
+        g0 = np.max(np.abs(oracle.aperture_gradient(P, pool, st.g)))
+        for _ in range(K):
+            rec = master_step(P, st, conjugate)
+            assert rec is not None and rec["t"] < rec["t_max"]
+        grad = oracle.aperture_gradient(P, pool, st.g)
+        res[conjugate] = (kkt_residual(st.y, grad) / g0, np.max(np.abs(st.y - y_ref) / y_ref))
+    assert res[True][0] <= 1e-10 and res[True][1] <= 1e-9, res
+    assert res[False][0] >= 1e-4, res
+
+
+def test_conjugate_direction_first_step_and_restart_rule():
+    # the first step of a pool, and any step whose free set differs from the
+    # last one's, move along the projected negative gradient r
+    from oracle.master import direction
+    ph = cached_phantom("mini")
+    P = oracle_problem(ph)
+    st = MasterState.empty(P)
+    for ap in _pool(P, 4, 7):
+        st.add(ap)
+    st.y = np.array([0.0, 0.02, 0.01, 0.0])
+    st.refresh(P)
+    grad = np.array([1.0, -2.0, 0.5, -1.0])
+    p, r, free = direction(st, grad)
+    np.testing.assert_array_equal(free, [False, True, True, True])
+    np.testing.assert_array_equal(p, [0.0, 2.0, -0.5, 1.0])
+    np.testing.assert_array_equal(p, r)
+    # same free set: r + beta p_prev with the truncated Polak-Ribiere beta
+    st.p_prev, st.r_prev, st.free_prev = np.array([0.0, 1.0, 1.0, 1.0]), np.array([0.0, 1.0, -1.0, 1.0]), free
+    p2, r2, _ = direction(st, grad)
+    beta = (2 * (2 - 1) + (-0.5) * (-0.5 + 1) + 1 * (1 - 1)) / 3.0
+    np.testing.assert_allclose(p2, r2 + beta * st.p_prev, rtol=0, atol=1e-15)
+    # negative beta is truncated to 0
+    st.r_prev = np.array([0.0, 4.0, 0.0, 0.0])
+    p3, r3, _ = direction(st, grad)
+    np.testing.assert_array_equal(p3, r3)
+    # different free set: restart
+    st.r_prev, st.free_prev = np.array([0.0, 1.0, -1.0, 1.0]), np.array([True, True, True, True])
+    p4, r4, _ = direction(st, grad)
+    np.testing.assert_array_equal(p4, r4)
+    # plain projected steepest descent ignores the memory
+    st.free_prev = free
+    p5, r5, _ = direction(st, grad, conjugate=False)
+    np.testing.assert_array_equal(p5, r5)
