@@ -133,7 +133,20 @@ typedef struct {
                                3 as 0 with 8 slices per workgroup */
     int32_t gradient_depth; /* with product_tune 0: transposed product entries per thread
                                in flight, 4 (default), 8 or 16 */
+    int32_t direction;      /* master search direction (Section 2.3, gradient projection):
+                               DAO_DIR_CONJUGATE (default) or DAO_DIR_STEEPEST, see below */
 } dao_options;
+
+/* Search direction of the master's gradient projection.  r is the projected
+ * negative gradient over the pool: r_k = -dF/dy_k, except 0 where y_k = 0 and
+ * dF/dy_k >= 0.  DAO_DIR_STEEPEST moves along r.  DAO_DIR_CONJUGATE moves along
+ * r + beta p_prev, with beta = max(0, r.(r - r_prev) / r_prev.r_prev), when the
+ * pool's previous step did not block and had the same free set (where r may
+ * be non-zero) and the result is a descent direction; otherwise along r.  The
+ * memory is cleared when an aperture enters the pool, on dao_reset and
+ * dao_set_state, and after a blocking step.  It is kept across consecutive
+ * dao_master_step / dao_master_solve calls on the same pool. */
+enum { DAO_DIR_STEEPEST = 0, DAO_DIR_CONJUGATE = 1 };
 
 /* How the restricted master evaluates its two products per step.
  * DAO_MASTER_APERTURE keeps the aperture dose matrix D_K (eq. 1 and eq. 2:
@@ -214,6 +227,7 @@ dao_status dao_gradient(dao_ctx* ctx, const void* d_dev, void* g_dev, double* F)
  * to the runner-up interval of any chosen row, whichever is smaller). */
 dao_status dao_price(dao_ctx* ctx, const double* g_dev, int32_t* beam, int16_t* leaves,
                      double* rc, double* gap);
+
 
 /* Master state.  dao_reset empties the pool (y = 0, dose 0).
  * dao_add_aperture appends an aperture with y = 0 (leaves as in dao_price;

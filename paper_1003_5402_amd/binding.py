@@ -15,6 +15,7 @@ DAO_EINVAL, DAO_ENOMEM, DAO_EDEVICE, DAO_ESTATE = -1, -2, -3, -4
 DAO_F64, DAO_F32 = 0, 1
 DAO_MASTER_APERTURE, DAO_MASTER_BEAMLET = 0, 1
 DAO_DFMT_NATIVE, DAO_DFMT_F16, DAO_DFMT_BF16 = 0, 1, 2
+DAO_DIR_STEEPEST, DAO_DIR_CONJUGATE = 0, 1
 _NAMES = {0: "DAO_OK", 1: "DAO_EOPTIMAL", 2: "DAO_ESTALLED", 3: "DAO_ENOTCONV", -1: "DAO_EINVAL",
           -2: "DAO_ENOMEM",
           -3: "DAO_EDEVICE", -4: "DAO_ESTATE"}
@@ -50,7 +51,7 @@ class dao_options(ctypes.Structure):
                 ("refresh_every", c_int32), ("ls_slots", c_int32), ("mem_cap_bytes", c_int64),
                 ("master", c_int32), ("d_format", c_int32), ("d_residual", c_int32),
                 ("persistent", c_int32), ("product_tune", c_int32), ("dose_variant", c_int32),
-                ("gradient_depth", c_int32)]
+                ("gradient_depth", c_int32), ("direction", c_int32)]
 
 
 class dao_info_t(ctypes.Structure):

@@ -117,6 +117,7 @@ struct dao_ctx {
     int16_t* ap_lv = nullptr;
     double* y = nullptr;
     double* p = nullptr;
+    CgMem* cgm = nullptr;             // conjugate-direction memory of the master
     double* gradk = nullptr;
     std::vector<int32_t> pool_beam;
     std::vector<int16_t> pool_lv;
@@ -383,7 +384,7 @@ dao_status enqueue_cycle(dao_ctx* c) {
     const size_t cls_b = sizeof(ObjClass) * c->ncls;
     const int nupd = int(c->slab_blocks());
     k_dir<T><<<1, 1024, c->stage_dir() ? c->dir_lds() : 0, c->stream>>>(
-        P, static_cast<const T*>(c->g), c->y, c->p, c->gradk, static_cast<T*>(c->dx), c->ms, c->upd_parts,
+        P, static_cast<const T*>(c->g), c->y, c->p, c->gradk, static_cast<T*>(c->dx), c->ms, c->cgm, c->upd_parts,
         nupd, c->stage_dir());
     k_qstep<T><<<c->slab_blocks(), SLAB_THREADS, cls_b + (c->stage_x() ? c->N * sizeof(T) : 0), c->stream>>>(
         S, c->Vpad, static_cast<const T*>(c->dx), int(c->N), c->stage_x(), c->d, c->cls_int, c->classes,
@@ -431,7 +432,7 @@ dao_status enqueue_cycle_ap(dao_ctx* c) {
                                               c->classes, c->ncls, c->y, c->parts2, c->ms, c->pc, c->Vnz);
     MARK(0, false);
     MARK(3, true);
-    k_dir_ap<<<1, 1024, 0, c->stream>>>(c->parts2, nb, c->y, c->p, c->gradk, c->ms, c->pc);
+    k_dir_ap<<<1, 1024, 0, c->stream>>>(c->parts2, nb, c->y, c->p, c->gradk, c->ms, c->cgm, c->pc);
     MARK(3, false);
     MARK(1, true);
     k_qstep_ap<T><<<nb, BLOCK, 0, c->stream>>>(dk, c->Vpad, c->d, c->cls_int, c->classes, c->ncls,
@@ -473,7 +474,7 @@ dao_status run_master_coop(dao_ctx* c, double tol, int max_steps) {
     LAUNCHCHK(c);
     HIPCHK(c, hipMemsetAsync(c->coop, 0, sizeof(CoopSync), c->stream));
     CoopArgs<T> A{static_cast<const T*>(c->dk), c->Vpad, c->Vnz, c->d, static_cast<T*>(c->q), c->cls_int,
-                  c->classes, c->ncls, c->y, c->p, c->gradk, c->ms, c->coop_recs, c->coop, c->pc,
+                  c->classes, c->ncls, c->y, c->p, c->gradk, c->cgm, c->ms, c->coop_recs, c->coop, c->pc,
                   c->prof_kernel == 4 ? 1 : 0};
     void* args[] = {&A};
     const bool prof = c->prof_kernel == 4;
@@ -720,6 +721,7 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     TRY(dev_alloc(c, &c->ap_lv, size_t(km) * c->maxRB * 2 * 2));
     TRY(dev_alloc(c, &c->y, km * 8));
     TRY(dev_alloc(c, &c->p, km * 8));
+    TRY(dev_alloc(c, &c->cgm, sizeof(CgMem)));
     TRY(dev_alloc(c, &c->gradk, km * 8));
     TRY(dev_alloc(c, &c->ms, sizeof(MasterState)));
     TRY(dev_alloc(c, &c->pr, sizeof(PriceResult)));
@@ -799,6 +801,7 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     std::memset(c->ms_h, 0, sizeof(MasterState));
     c->ms_h->done = 1;
     c->ms_h->refresh_every = c->opt.refresh_every;
+    c->ms_h->conj = c->opt.direction == DAO_DIR_CONJUGATE ? 1 : 0;
     c->ms_h->F_const = c->F_const;
     HIPCHK(c, hipMemcpyAsync(c->ms, c->ms_h, sizeof(MasterState), hipMemcpyHostToDevice, c->stream));
     std::memset(c->pr_h, 0, sizeof(PriceResult));
@@ -1174,7 +1177,8 @@ dao_status run_master_batch(std::vector<PlanRun*>& live) {
         LAUNCHCHK(c);
         HIPCHK(c, hipMemsetAsync(c->coop, 0, sizeof(CoopSync), c->stream));
         hargs[i] = CoopArgs<T>{static_cast<const T*>(c->dk), c->Vpad, c->Vnz, c->d, static_cast<T*>(c->q), c->cls_int,
-                               c->classes, c->ncls, c->y, c->p, c->gradk, c->ms, c->coop_recs, c->coop, c->pc, 0};
+                               c->classes, c->ncls, c->y, c->p, c->gradk, c->cgm, c->ms, c->coop_recs, c->coop,
+                               c->pc, 0};
         hstart[i + 1] = hstart[i] + g[i];
         const int nc = (c->K + DKG<T>::EPL - 1) / DKG<T>::EPL;
         const size_t li = coop_lds_bytes<T>(coop_batches_per_group<T>(c->Vpad, g[i]) * Batch<T>::ROWS, nc);
@@ -1266,6 +1270,7 @@ void dao_default_options(dao_options* o) {
     o->product_tune = 1;
     o->dose_variant = 0;
     o->gradient_depth = 4;
+    o->direction = DAO_DIR_CONJUGATE;
 }
 
 const char* dao_create_error(void) { return g_create_error.c_str(); }

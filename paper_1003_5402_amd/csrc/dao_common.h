@@ -57,6 +57,17 @@ struct MasterState {
     double F_const;        // objective of voxels no beamlet reaches (dose 0)
     double last_step;      // length of the last step
     double prev_step;      // length of the step before it
+    int32_t conj;          // 1: conjugate gradient projection, 0: projected steepest descent
+    int32_t cg_valid;      // the conjugate memory (CgMem, p) holds the last step of this pool
+    int32_t cg_K;          // pool size when the memory was recorded
+    int32_t cg_pad;
+};
+
+// Memory of the conjugate direction: projected negative gradient r and free
+// set of the last step (its direction stays in the master's p array).
+struct CgMem {
+    double r[MAX_APERTURES];
+    int32_t free[MAX_APERTURES];
 };
 
 // Work counters of the aperture master's kernels, kept by workgroup 0 of

@@ -229,6 +229,29 @@ __device__ __forceinline__ double ls_first_trial(double prev_step, double t_max)
     return tb > 0.0 ? tb : 0.0;
 }
 
+// Search direction of gradient projection for one wavefront, lane k holding
+// pool aperture k (K <= 64; every lane of the wavefront calls it).  The
+// projected negative gradient r is -grad_k except 0 where y_k = 0 and
+// grad_k >= 0 (the free set is where it may be non-zero).  With mem (the
+// last step of this pool did not block and the conjugate direction is on)
+// and an unchanged free set, p = r + beta p_prev with the Polak-Ribiere
+// beta truncated at 0, kept only if it is a descent direction; else p = r.
+__device__ __forceinline__ double cg_dir_wave(bool in, double yk, double gk, bool mem, double pprev,
+                                              double rprev, bool fprev, double& r, bool& fr) {
+    fr = in && !(yk == 0.0 && gk >= 0.0);
+    r = fr ? -gk : 0.0;
+    double p = r;
+    if (mem && __all(fr == (in && fprev))) {
+        const double rp = in ? rprev : 0.0;
+        const double num = wave_sum(r * (r - rp));
+        const double den = wave_sum(rp * rp);
+        const double beta = den > 0.0 ? fmax(0.0, num / den) : 0.0;
+        const double cand = r + beta * (in ? pprev : 0.0);
+        if (wave_sum(in ? gk * cand : 0.0) < 0.0) p = cand;
+    }
+    return p;
+}
+
 // ---------------------------------------------------------------------------
 // forward products over slabs
 // ---------------------------------------------------------------------------
@@ -795,6 +818,7 @@ __global__ void k_set_history(MasterState* ms, double last_step, double prev_ste
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         ms->last_step = last_step;
         ms->prev_step = prev_step;
+        ms->cg_valid = 0;
     }
 }
 
@@ -805,13 +829,15 @@ template <class T>
 __global__ void __launch_bounds__(1024) k_dir(PoolView P, const T* __restrict__ g,
                                               double* __restrict__ y, double* __restrict__ p,
                                               double* __restrict__ grad, T* __restrict__ dx,
-                                              MasterState* ms, const Rec* __restrict__ upd_parts,
-                                              int n_upd, bool stage) {
+                                              MasterState* ms, CgMem* __restrict__ cgm,
+                                              const Rec* __restrict__ upd_parts, int n_upd, bool stage) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_skip, s_go, s_upd, s_K;
     __shared__ double s_grad[MAX_APERTURES];
     __shared__ double s_p[MAX_APERTURES];
     __shared__ double s_y[MAX_APERTURES];
+    __shared__ double s_r[MAX_APERTURES];
+    __shared__ int32_t s_fr[MAX_APERTURES];
     __shared__ int32_t s_beam[MAX_APERTURES];
     __shared__ MasterState s_ms;
     ms_load(s_ms, ms);
@@ -881,19 +907,43 @@ __global__ void __launch_bounds__(1024) k_dir(PoolView P, const T* __restrict__ 
         double tmax = INFINITY, gp = 0.0;
         int any = 0;
         if (go) {
+            // projected negative gradient r and free set; the conjugate
+            // direction r + beta p_prev needs the last step's free set
+            bool same = s_ms.conj && s_ms.cg_valid;
             for (int k = 0; k < K; ++k) {
-                double pk = -s_grad[k];
-                if (s_y[k] == 0.0 && s_grad[k] >= 0.0) pk = 0.0;
-                p[k] = pk;
-                s_p[k] = pk;
-                grad[k] = s_grad[k];
-                if (pk != 0.0) any = 1;
+                const bool fr = !(s_y[k] == 0.0 && s_grad[k] >= 0.0);
+                s_r[k] = fr ? -s_grad[k] : 0.0;
+                s_fr[k] = fr;
+                if (fr != (cgm->free[k] != 0)) same = false;
+                if (s_r[k] != 0.0) any = 1;
+            }
+            double beta = 0.0;
+            if (same) {
+                double num = 0.0, den = 0.0, gc = 0.0;
+                for (int k = 0; k < K; ++k) {
+                    num += s_r[k] * (s_r[k] - cgm->r[k]);
+                    den += cgm->r[k] * cgm->r[k];
+                }
+                beta = den > 0.0 ? fmax(0.0, num / den) : 0.0;
+                for (int k = 0; k < K; ++k) gc += s_grad[k] * (s_r[k] + beta * p[k]);
+                if (!(gc < 0.0)) same = false;
+            }
+            for (int k = 0; k < K; ++k) s_p[k] = same ? s_r[k] + beta * p[k] : s_r[k];
+            for (int k = 0; k < K; ++k) {
+                const double pk = s_p[k];
                 if (pk < 0.0) tmax = fmin(tmax, s_y[k] / (-pk));
                 gp += s_grad[k] * pk;
             }
             if (!any) {
                 s_ms.stop_reason = 3;
                 go = 0;
+            } else {
+                for (int k = 0; k < K; ++k) {
+                    p[k] = s_p[k];
+                    grad[k] = s_grad[k];
+                    cgm->r[k] = s_r[k];
+                    cgm->free[k] = s_fr[k];
+                }
             }
         }
         if (!go) {
@@ -1000,6 +1050,9 @@ __device__ __forceinline__ void finish_step(const PoolView& P, MasterState& m, d
         m.prev_step = m.last_step;
         m.last_step = t;
         m.refresh = (m.steps % m.refresh_every) == 0;
+        // a step that blocks ends the conjugate sequence
+        m.cg_valid = m.conj && !(t == tmax);
+        m.cg_K = K;
         s_refresh = m.refresh;
     }
     __syncthreads();
@@ -1149,6 +1202,7 @@ __global__ void k_master_init(MasterState* ms, int K, double tol, int max_steps)
         ms->stop_reason = 0;
         ms->ls_iter = 0;
         ms->refresh = 0;
+        if (ms->cg_K != K) ms->cg_valid = 0;   // the pool changed since the last step
     }
 }
 

@@ -246,7 +246,8 @@ __global__ void __launch_bounds__(BLOCK) k_upd_ap(const T* __restrict__ dk, int6
 // longest feasible step.  One wavefront handles the (at most 64) apertures.
 __global__ void __launch_bounds__(1024) k_dir_ap(const double* __restrict__ parts2, int nblk,
                                                  const double* __restrict__ y, double* __restrict__ p,
-                                                 double* __restrict__ grad, MasterState* ms, ProfCounters* pc) {
+                                                 double* __restrict__ grad, MasterState* ms,
+                                                 CgMem* __restrict__ cgm, ProfCounters* pc) {
     constexpr int SPLIT = 16;   // threads per record column
     __shared__ MasterState s_ms;
     __shared__ int s_skip;
@@ -283,15 +284,24 @@ __global__ void __launch_bounds__(1024) k_dir_ap(const double* __restrict__ part
         const bool in = k < K;
         const double yk = in ? y[k] : 0.0;
         const double gk = in ? s_red[1 + k] : 0.0;
-        double pk = -gk;
-        if (!in || (yk == 0.0 && gk >= 0.0)) pk = 0.0;
+        const bool mem = s_ms.conj && s_ms.cg_valid;
+        double rk;
+        bool fk;
+        const double pk = cg_dir_wave(in, yk, gk, mem, in && mem ? p[k] : 0.0, in && mem ? cgm->r[k] : 0.0,
+                                      in && mem && cgm->free[k] != 0, rk, fk);
         const double kkt = wave_max(in ? fabs(fmin(yk, gk)) : 0.0);
         const double tmax = wave_min(pk < 0.0 ? yk / (-pk) : INFINITY);
         const double gp = wave_sum(gk * pk);
-        const bool any = __any(pk != 0.0);
+        const bool any = __any(rk != 0.0);
+        // the memory and p change only when a step is taken
+        const bool take = kkt > s_ms.tol && s_ms.steps < s_ms.max_steps && any;
         if (in) {
-            p[k] = pk;
             grad[k] = gk;
+            if (take) {
+                p[k] = pk;
+                cgm->r[k] = rk;
+                cgm->free[k] = fk;
+            }
         }
         if (k == 0) {
             s_ms.F = s_ms.F_const + s_red[0];
@@ -345,6 +355,9 @@ __device__ __forceinline__ void finish_step_ap(MasterState& m, double* y, const 
         m.prev_step = m.last_step;
         m.last_step = t;
         m.refresh = (m.steps % m.refresh_every) == 0 ? 1 : 0;
+        // a step that blocks ends the conjugate sequence
+        m.cg_valid = m.conj && !(t == tmax);
+        m.cg_K = K;
         m.phase = PH_UPD;
     }
 }
@@ -480,6 +493,7 @@ __global__ void k_clear_steps(MasterState* ms) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         ms->last_step = 0.0;
         ms->prev_step = 0.0;
+        ms->cg_valid = 0;
     }
 }
 
@@ -495,6 +509,7 @@ __global__ void k_master_init_ap(MasterState* ms, int K, double tol, int max_ste
         ms->tol = tol;
         ms->stop_reason = 0;
         ms->ls_iter = 0;
+        if (ms->cg_K != K) ms->cg_valid = 0;   // the pool changed since the last step
     }
 }
 

@@ -249,6 +249,7 @@ struct CoopArgs {
     double* y;          // in: current intensities; out: final intensities (workgroup 0)
     double* p;          // out: last direction (workgroup 0)
     double* grad;       // out: last grad_y (workgroup 0)
+    CgMem* cgm;         // in/out: conjugate-direction memory (with p: the last step's direction)
     MasterState* ms;    // in: state set by k_master_init_ap; out: final state (workgroup 0)
     double* recs;       // [2][workgroups of the solve][RECW]
     CoopSync* sync;
@@ -288,7 +289,8 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ MasterState s_ms;
     __shared__ ObjClass cl[256];
-    __shared__ double s_y[KS], s_p[KS], s_g[KS];
+    __shared__ double s_y[KS], s_p[KS], s_g[KS], s_r[KS];
+    __shared__ int s_fr[KS];
     __shared__ double s_rec[RECW], s_tot[RECW];
     static_assert(NW == 8, "the wavefront combines assume 8 wavefronts");
     __shared__ double s_acc[NW][RECW];   // per wavefront: objective, then grad_y
@@ -298,9 +300,14 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     ms_load(s_ms, A.ms);
     for (int i = threadIdx.x; i < A.ncls; i += blockDim.x) cl[i] = A.classes[i];
     const int K = s_ms.K;
+    // the conjugate memory of the pool's last step, if any
+    const bool mem0 = s_ms.conj && s_ms.cg_valid;
     for (int k = threadIdx.x; k < KS; k += blockDim.x) {
-        s_y[k] = k < K ? A.y[k] : 0.0;
-        s_p[k] = 0.0;
+        const bool in = k < K;
+        s_y[k] = in ? A.y[k] : 0.0;
+        s_p[k] = in && mem0 ? A.p[k] : 0.0;
+        s_r[k] = in && mem0 ? A.cgm->r[k] : 0.0;
+        s_fr[k] = in && mem0 ? A.cgm->free[k] : 0;
         s_g[k] = 0.0;
     }
     __syncthreads();
@@ -471,13 +478,20 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             const bool in = k < K;
             const double yk = s_y[k];
             const double gk = in ? s_tot[1 + k] : 0.0;
-            double pk = -gk;
-            if (!in || (yk == 0.0 && gk >= 0.0)) pk = 0.0;
+            double rk;
+            bool fk;
+            const double pk = cg_dir_wave(in, yk, gk, s_ms.conj && s_ms.cg_valid, s_p[k], s_r[k], s_fr[k] != 0,
+                                          rk, fk);
             const double kkt = wave_reduce_dpp<2>(in ? fabs(fmin(yk, gk)) : 0.0);
             const double tmax = wave_reduce_dpp<1>(pk < 0.0 ? yk / (-pk) : INFINITY);
             const double gp = wave_reduce_dpp<0>(gk * pk);
-            const bool any = __any(pk != 0.0);
-            s_p[k] = pk;
+            const bool any = __any(rk != 0.0);
+            // the direction and its memory change only when a step is taken
+            if (kkt > s_ms.tol && steps < s_ms.max_steps && any) {
+                s_p[k] = pk;
+                s_r[k] = rk;
+                s_fr[k] = fk;
+            }
             s_g[k] = gk;
             if (k == 0) {
                 s_ms.F = s_ms.F_const + s_tot[0];
@@ -636,6 +650,9 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             steps += 1;
             mode = (steps % refresh_every) == 0 ? 1 : 0;
             if (threadIdx.x == 0) {
+                // a step that blocks ends the conjugate sequence
+                s_ms.cg_valid = s_ms.conj && !(t == tmax);
+                s_ms.cg_K = K;
                 s_ms.steps = steps;
                 s_ms.total_steps += 1;
                 s_ms.prev_step = s_ms.last_step;
@@ -673,6 +690,8 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             A.y[threadIdx.x] = s_y[threadIdx.x];
             A.p[threadIdx.x] = s_p[threadIdx.x];
             A.grad[threadIdx.x] = s_g[threadIdx.x];
+            A.cgm->r[threadIdx.x] = s_r[threadIdx.x];
+            A.cgm->free[threadIdx.x] = s_fr[threadIdx.x];
         }
         if (threadIdx.x == 0 && !alive) s_ms.stop_reason = 4;
         ms_store(A.ms, s_ms);

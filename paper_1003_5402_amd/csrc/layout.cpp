@@ -106,6 +106,8 @@ dao_status validate_inputs(const dao_matrix* D, const dao_beams* beams,
         return fail("dose_variant 2 reads x unscaled: native d_format only");
     if (opt->gradient_depth != 4 && opt->gradient_depth != 8 && opt->gradient_depth != 16)
         return fail("gradient_depth must be 4, 8 or 16");
+    if (opt->direction != DAO_DIR_STEEPEST && opt->direction != DAO_DIR_CONJUGATE)
+        return fail("direction must be DAO_DIR_STEEPEST or DAO_DIR_CONJUGATE");
     if (opt->d_format < DAO_DFMT_NATIVE || opt->d_format > DAO_DFMT_BF16)
         return fail("d_format must be DAO_DFMT_NATIVE, DAO_DFMT_F16 or DAO_DFMT_BF16");
     if (opt->d_residual != 0 && opt->d_residual != 1) return fail("d_residual must be 0 or 1");
