@@ -1,7 +1,9 @@
 """Writes the oracle's column-generation trajectories used as parity fixtures.
 
 Calls only ``oracle/`` (and the seeded phantom generator for its inputs), so
-every stored value is the FP64 oracle's.  For each phantom it records, per
+every stored value is the FP64 oracle's.  For phantoms whose dose matrix is
+stored in FP32 the oracle solves the problem with D rounded to FP32 (exact in
+FP64), which is the problem an FP32 context holds.  For each phantom it records, per
 round: the entering aperture (beam, leaves), its reduced cost, the decision
 gap, the master's step count, line-search evaluations, KKT residual at exit,
 whether the master stopped at the step cap, the objective after the master
@@ -15,7 +17,8 @@ Usage::
     python tests/golden/make_golden.py headneck 10      # first 10 rounds
 
 The solve parameters are the library defaults (KKT tolerance 1e-6 |rc_1|,
-500 master steps per round, entry threshold 1e-10 |rc_1|, three tightenings).
+500 master steps per round, entry threshold 1e-10 |rc_1|, three tightenings,
+conjugate gradient projection).
 """
 from __future__ import annotations
 
@@ -44,7 +47,13 @@ def golden_path(name: str, seed: int, rounds: int) -> str:
 
 def main(name: str, rounds: int, seed: int = 0) -> str:
     ph = make_phantom(name, seed)
-    P = oracle.make_problem(ph.csr(), ph.rows_per_beam, ph.row_len, ph.vox_struct, ph.prescriptions)
+    D = ph.csr()
+    if ph.dtype == "f32":
+        # an FP32 context stores D rounded to FP32; the oracle solves that
+        # same problem (the rounded values are exact in FP64)
+        D = D.copy()
+        D.data = D.data.astype(np.float32).astype(np.float64)
+    P = oracle.make_problem(D, ph.rows_per_beam, ph.row_len, ph.vox_struct, ph.prescriptions)
     recs = []
     t0 = time.perf_counter()
 
@@ -67,7 +76,7 @@ def main(name: str, rounds: int, seed: int = 0) -> str:
         if s > 0:
             metrics[f"dmax_{nm}"] = oracle.dmax(res["d"], ph.vox_struct == s)
     doc = dict(phantom=name, seed=seed, n_vox=ph.n_vox, n_blt=ph.n_blt, nnz=ph.nnz,
-               d_dtype=ph.dtype, eps=EPS, max_steps=MAX_STEPS, tau_rel=TAU_REL,
+               d_dtype=ph.dtype, direction="conjugate", eps=EPS, max_steps=MAX_STEPS, tau_rel=TAU_REL,
                max_tighten=MAX_TIGHTEN, rounds_requested=rounds, status=res["status"],
                rc1=res["rc1"], F=res["F"], final_eps=res["eps"], metrics=metrics,
                dose_sum=math.fsum(res["d"].tolist()), dose_max=float(np.max(res["d"])),
