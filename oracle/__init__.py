@@ -33,7 +33,8 @@ trajectory of a full multi-round solve beyond those invariants is
 "parity unpinned": the paper prints no apertures, objective values or
 iteration counts to compare against.
 """
-from .model import Problem, make_problem, voxel_coefficients, dose, objective, grad_objective, prices  # noqa: F401
+from .model import (Problem, make_problem, voxel_coefficients, structure_sizes, reoptimization_structures,  # noqa: F401
+                    dose, objective, grad_objective, prices)
 from .aperture import Aperture, beamlet_intensity, aperture_gradient  # noqa: F401
 from .pricing import price_row, price  # noqa: F401
 from .master import line_search, MasterState, master_step, solve_master  # noqa: F401

@@ -51,24 +51,28 @@ LS_MAX_ITER = 60
 
 def _slopes(P: Problem, z: np.ndarray, q: np.ndarray):
     """phi''(t) just right and just left of t: sum_j q_j^2 times the active curvature."""
-    ua = P.a > 0
-    ob = P.b > 0
-    under_r = ua & ((z < P.t_under) | ((z == P.t_under) & (q < 0)))
-    over_r = ob & ((z > P.t_over) | ((z == P.t_over) & (q > 0)))
-    under_l = ua & ((z < P.t_under) | ((z == P.t_under) & (q > 0)))
-    over_l = ob & ((z > P.t_over) | ((z == P.t_over) & (q < 0)))
     q2 = q * q
-    s_r = 2.0 * float(np.sum(q2 * (P.a * under_r + P.b * over_r)))
-    s_l = 2.0 * float(np.sum(q2 * (P.a * under_l + P.b * over_l)))
+    s_r = s_l = 0.0
+    for a, tu, b, to in P.terms():
+        ua = a > 0
+        ob = b > 0
+        under_r = ua & ((z < tu) | ((z == tu) & (q < 0)))
+        over_r = ob & ((z > to) | ((z == to) & (q > 0)))
+        under_l = ua & ((z < tu) | ((z == tu) & (q > 0)))
+        over_l = ob & ((z > to) | ((z == to) & (q < 0)))
+        s_r += 2.0 * float(np.sum(q2 * (a * under_r + b * over_r)))
+        s_l += 2.0 * float(np.sum(q2 * (a * under_l + b * over_l)))
     return s_r, s_l
 
 
 def _breakpoints(P: Problem, d: np.ndarray, q: np.ndarray) -> np.ndarray:
     """Values of t at which some voxel's dose d_j + t q_j meets one of its thresholds."""
     nz = q != 0
-    bu = (P.t_under - d)[nz & (P.a > 0)] / q[nz & (P.a > 0)]
-    bo = (P.t_over - d)[nz & (P.b > 0)] / q[nz & (P.b > 0)]
-    return np.concatenate([bu, bo])
+    out = []
+    for a, tu, b, to in P.terms():
+        out.append((tu - d)[nz & (a > 0)] / q[nz & (a > 0)])
+        out.append((to - d)[nz & (b > 0)] / q[nz & (b > 0)])
+    return np.concatenate(out)
 
 
 def line_search(P: Problem, d: np.ndarray, q: np.ndarray, t_max: float,

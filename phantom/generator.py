@@ -35,7 +35,10 @@ point where beamlet i's central ray enters the body.
 
 Structures carry one label per voxel (PTV first, then organs at risk in the
 listed order, then normal tissue = rest of the body); ``-1`` marks voxels
-outside the body.  Prescriptions follow the per-structure objective of the
+outside the body.  With ``nested_targets`` the target is split as in the
+paper's head-and-neck cases: a boost target PTV1 inside a larger PTV2; PTV1
+voxels carry PTV1 as first label and PTV2 as second label
+(``vox_struct2``), the rest of PTV2 carries PTV2.  Prescriptions follow the per-structure objective of the
 Discussion (eq. 9 and eq. 10): targets have under- and over-dose thresholds
 and weights, other structures over-dose only.
 """
@@ -128,6 +131,7 @@ class Phantom:
     struct_names: List[str]
     prescriptions: List[Dict]  # per structure: is_target, t_under, t_over, w_under, w_over
     n_apertures: int
+    vox_struct2: Optional[np.ndarray] = None   # (V,) int16 second label (nested targets), -1 = none
 
     @property
     def n_vox(self) -> int:
@@ -230,16 +234,34 @@ def _presc(is_target, t_under, t_over, w_under, w_over):
                 w_under=float(w_under), w_over=float(w_over))
 
 
+# nested targets: PTV1 (boost) prescription 1.0, PTV2 54/73.8 of it
+# (Section 3's head-and-neck prescriptions, normalised to PTV1); PTV2 also
+# contains PTV1, so its over-dose threshold is PTV1's
+PTV2_T_UNDER = 54.0 / 73.8
+PTV1_SCALE = 0.6
+
+
+def _nest(out):
+    """Split the first (target) entry into PTV1 (a shrunk copy of its first
+    component, passed as out[0][3]) and PTV2 (the whole target)."""
+    name, ptv, pr, ptv1 = out[0]
+    return [("PTV1", ptv1 & ptv, _presc(1, 1.0, 1.0, 1.0, 1.0)),
+            ("PTV2", ptv, _presc(1, PTV2_T_UNDER, 1.0, 1.0, 1.0))] + [o[:3] for o in out[1:]]
+
+
 def _anatomy(kind, cfg, P, iso, rng, shift, ptv_scale):
-    """Return (list of (name, mask, prescription)) in priority order."""
+    """Return (list of (name, mask, prescription, boost mask)) in priority
+    order; the boost mask (a shrunk copy of the target's first component) is
+    used only for nested targets."""
     out = []
     c = iso + shift
     if kind == "sphere_cyl":
         ptv = _ellipsoid(P, c, [cfg["ptv_r"] * ptv_scale] * 3)
+        boost = _ellipsoid(P, c, [cfg["ptv_r"] * ptv_scale * PTV1_SCALE] * 3)
         # organ-at-risk cylinder along z, posterior (+y) of the isocentre
         oar = _cylinder_z(P, (iso[0], iso[1] + cfg["oar_off"]), cfg["oar_r"])
-        out.append(("PTV", ptv, _presc(1, 1.0, 1.0, 1.0, 1.0)))
-        out.append(("OAR", oar, _presc(0, 0.0, 0.5, 0.0, 0.5)))
+        out.append(("PTV", ptv, _presc(1, 1.0, 1.0, 1.0, 1.0), boost))
+        out.append(("OAR", oar, _presc(0, 0.0, 0.5, 0.0, 0.5), None))
     elif kind == "prostate":
         semi = np.array([35.0, 25.0, 25.0]) * ptv_scale
         ptv = _ellipsoid(P, c, semi)
@@ -248,11 +270,12 @@ def _anatomy(kind, cfg, P, iso, rng, shift, ptv_scale):
         re_semi = np.array([15.0, 15.0, 30.0])
         bladder = _ellipsoid(P, c + np.array([0.0, -(semi[1] + bl_semi[1]), 0.0]), bl_semi)
         rectum = _ellipsoid(P, c + np.array([0.0, semi[1] + re_semi[1], 0.0]), re_semi)
-        out.append(("PTV", ptv, _presc(1, 1.0, 1.0, 1.0, 1.0)))
-        out.append(("bladder", bladder, _presc(0, 0.0, 0.5, 0.0, 0.5)))
-        out.append(("rectum", rectum, _presc(0, 0.0, 0.5, 0.0, 0.5)))
+        out.append(("PTV", ptv, _presc(1, 1.0, 1.0, 1.0, 1.0), _ellipsoid(P, c, semi * PTV1_SCALE)))
+        out.append(("bladder", bladder, _presc(0, 0.0, 0.5, 0.0, 0.5), None))
+        out.append(("rectum", rectum, _presc(0, 0.0, 0.5, 0.0, 0.5), None))
     elif kind == "headneck":
         ptv = np.zeros(P.shape[0], dtype=bool)
+        boost = None
         for _ in range(3):
             # lateral semi-axes U[20, 40] mm; elongated along z (nodal chains run
             # superior-inferior) with a z semi-axis U[40, 75] mm; centres within
@@ -263,7 +286,9 @@ def _anatomy(kind, cfg, P, iso, rng, shift, ptv_scale):
             d2 *= rng.uniform(0.0, 20.0) / max(np.linalg.norm(d2), 1e-12)
             d = np.array([d2[0], d2[1], rng.uniform(-40.0, 40.0)])
             ptv |= _ellipsoid(P, c + d, semi)
-        out.append(("PTV", ptv, _presc(1, 1.0, 1.0, 1.0, 1.0)))
+            if boost is None:
+                boost = _ellipsoid(P, c + d, semi * PTV1_SCALE)
+        out.append(("PTV", ptv, _presc(1, 1.0, 1.0, 1.0, 1.0), boost))
         thr = rng.uniform(0.4, 0.7, size=6)
         cord = _cylinder_z(P, (iso[0], iso[1] + 60.0), 6.0)
         stem = _ellipsoid(P, iso + np.array([0.0, 45.0, 70.0]), [12.0, 12.0, 20.0])
@@ -280,7 +305,7 @@ def _anatomy(kind, cfg, P, iso, rng, shift, ptv_scale):
                     break
             oars.append((f"sphere{k}", m))
         for (name, m), t in zip(oars, thr):
-            out.append((name, m, _presc(0, 0.0, t, 0.0, 0.5)))
+            out.append((name, m, _presc(0, 0.0, t, 0.0, 0.5), None))
     else:
         raise ValueError(kind)
     return out
@@ -289,13 +314,14 @@ def _anatomy(kind, cfg, P, iso, rng, shift, ptv_scale):
 def make_phantom(name: str = "tiny", seed: int = 0, *, shift_mm=(0.0, 0.0, 0.0),
                  ptv_scale: float = 1.0, n_apertures: Optional[int] = None,
                  dtype: Optional[str] = None, body_half: Optional[Sequence[float]] = None,
-                 normal_tissue: bool = True) -> Phantom:
+                 normal_tissue: bool = True, nested_targets: bool = False) -> Phantom:
     """Build a seeded phantom.
 
     ``name`` picks an entry of :data:`CONFIGS`.  ``shift_mm`` rigidly moves the
     target (not the beams), ``ptv_scale`` scales it; both serve re-planning
     variants.  ``normal_tissue`` adds the over-dose term on the body outside
-    all listed structures.
+    all listed structures.  ``nested_targets`` splits the target into PTV1
+    inside PTV2 (see the module docstring).
     """
     cfg = CONFIGS[name]
     rng = np.random.default_rng(seed)
@@ -321,6 +347,7 @@ def make_phantom(name: str = "tiny", seed: int = 0, *, shift_mm=(0.0, 0.0, 0.0),
     inside = body.contains(P[:, 0], P[:, 1])
     structs = _anatomy(cfg["anatomy"], cfg, P, iso, rng,
                        np.asarray(shift_mm, dtype=np.float64), float(ptv_scale))
+    structs = _nest(structs) if nested_targets else [o[:3] for o in structs]
     vox_struct = np.full(V, -1, dtype=np.int16)
     names, prescs = [], []
     for k, (nm, m, pr) in enumerate(structs):
@@ -328,12 +355,18 @@ def make_phantom(name: str = "tiny", seed: int = 0, *, shift_mm=(0.0, 0.0, 0.0),
         vox_struct[sel] = k
         names.append(nm)
         prescs.append(pr)
+    vox_struct2 = None
+    if nested_targets:
+        # PTV1 voxels also belong to PTV2 (structure 1)
+        vox_struct2 = np.full(V, -1, dtype=np.int16)
+        vox_struct2[(vox_struct == 0) & structs[1][1]] = 1
     if normal_tissue:
         k = len(names)
         vox_struct[inside & (vox_struct < 0)] = k
         names.append("NT")
         prescs.append(_presc(0, 0.0, NT_T_OVER, 0.0, NT_W_OVER))
-    ptv_idx = np.flatnonzero(vox_struct == 0)
+    targets = [k for k, pr in enumerate(prescs) if pr["is_target"]]
+    ptv_idx = np.flatnonzero(np.isin(vox_struct, targets))
 
     # ---- beams and active beamlets -------------------------------------
     B = int(cfg["n_beams"])
@@ -433,4 +466,5 @@ def make_phantom(name: str = "tiny", seed: int = 0, *, shift_mm=(0.0, 0.0, 0.0),
         row_ptr=A.indptr.astype(np.int64), col=A.indices.astype(np.int32),
         val=A.data.astype(np.float64), dtype=dtype, vox_struct=vox_struct,
         struct_names=names, prescriptions=prescs,
-        n_apertures=int(n_apertures if n_apertures is not None else cfg["n_apertures"]))
+        n_apertures=int(n_apertures if n_apertures is not None else cfg["n_apertures"]),
+        vox_struct2=vox_struct2)

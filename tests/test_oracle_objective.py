@@ -89,7 +89,8 @@ def test_adjoint_identity():
 
 def test_structure_size_normalisation():
     ph = cached_phantom("tiny")
-    a, tu, b, to = oracle.voxel_coefficients(ph.vox_struct, ph.prescriptions)
+    (a, tu, b, to), second = oracle.voxel_coefficients(ph.vox_struct, ph.prescriptions)
+    assert second is None
     for s, pr in enumerate(ph.prescriptions):
         m = ph.vox_struct == s
         assert abs(math.fsum(b[m].tolist()) - pr["w_over"]) < 1e-12
