@@ -36,7 +36,7 @@ iteration counts to compare against.
 from .model import (Problem, make_problem, voxel_coefficients, structure_sizes, reoptimization_structures,  # noqa: F401
                     dose, objective, grad_objective, prices)
 from .aperture import Aperture, beamlet_intensity, aperture_gradient  # noqa: F401
-from .pricing import price_row, price  # noqa: F401
+from .pricing import price_row, price, ranked_apertures  # noqa: F401
 from .master import line_search, MasterState, master_step, solve_master  # noqa: F401
 from .solve import solve  # noqa: F401
 from .metrics import d95, dmax  # noqa: F401

@@ -18,6 +18,10 @@ several equal intervals is chosen:
 * the best value starts at 0 with the row closed, so a row without a negative
   interval stays closed.
 Beams with equal values go to the lowest beam index.
+
+Several apertures per round (a variant of the loop): the beams ranked by
+value (ties to the lowest index) each supply their own best aperture, so the
+m best beams give m apertures, the first being the usual entering one.
 """
 from __future__ import annotations
 
@@ -81,3 +85,15 @@ def price(P: Problem, g: np.ndarray) -> Dict:
     return dict(aperture=Aperture(best_b, leaves), rc=beam_vals[best_b],
                 beam_values=beam_vals, gap=min(beam_gap, row_gap),
                 rows=row_res)
+
+
+def ranked_apertures(P: Problem, pr: Dict) -> List[Tuple[float, Aperture]]:
+    """Every beam's best aperture with its value, from a :func:`price`
+    result, ordered by value and then beam index."""
+    out = []
+    for b in range(P.rows_per_beam.shape[0]):
+        r0, r1 = P.beam_row_range(b)
+        leaves = tuple((pr["rows"][r][0], pr["rows"][r][1]) for r in range(r0, r1))
+        out.append((pr["beam_values"][b], b, Aperture(b, leaves)))
+    out.sort(key=lambda t: (t[0], t[1]))
+    return [(v, ap) for v, _, ap in out]

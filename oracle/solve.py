@@ -19,6 +19,12 @@ used:
   <= eps * |rc_1| (or ``max_steps`` steps), by conjugate gradient projection
   unless ``conjugate=False`` (see :mod:`oracle.master`);
 * the loop ends when the pool holds ``n_apertures`` apertures.
+
+With ``per_round = m > 1`` (a variant: several apertures per round), after
+the entering aperture the beams ranked 2..m by value (ties to the lowest
+index) add their own best apertures too, each only if its value is below
+-tau, it is not already pooled and the budget allows; then the master runs
+once over the enlarged pool.
 """
 from __future__ import annotations
 
@@ -28,12 +34,12 @@ import numpy as np
 
 from .master import MasterState, solve_master
 from .model import Problem, objective
-from .pricing import price
+from .pricing import price, ranked_apertures
 
 
 def solve(P: Problem, n_apertures: int, eps: float = 1e-6, max_steps: int = 500,
           tau_rel: float = 1e-10, max_tighten: int = 3, track_F: bool = False,
-          conjugate: bool = True, on_round: Optional[Callable[[int, Dict, MasterState], None]] = None) -> Dict:
+          conjugate: bool = True, per_round: int = 1, on_round: Optional[Callable[[int, Dict, MasterState], None]] = None) -> Dict:
     st = MasterState.empty(P)
     log: List[Dict] = []
     rc1 = None
@@ -59,8 +65,17 @@ def solve(P: Problem, n_apertures: int, eps: float = 1e-6, max_steps: int = 500,
             solve_master(P, st, eps * scale, max_steps, conjugate=conjugate)
             continue
         st.add(pr["aperture"])
+        extra = []
+        if per_round > 1:
+            for v, ap in ranked_apertures(P, pr)[1:per_round]:
+                if len(st.pool) >= n_apertures or not v < -tau_rel * scale:
+                    break
+                if ap in st.pool:
+                    continue
+                st.add(ap)
+                extra.append(ap)
         mlog = solve_master(P, st, eps * scale, max_steps, track_F=track_F, conjugate=conjugate)
-        rec = dict(round=len(st.pool), beam=pr["aperture"].beam, rc=pr["rc"], gap=pr["gap"],
+        rec = dict(round=len(st.pool), beam=pr["aperture"].beam, rc=pr["rc"], gap=pr["gap"], extra=extra,
                    steps=mlog["steps"], ls_evals=mlog["ls_evals"], kkt=mlog["kkt"],
                    F=objective(P, st.d), F_trace=mlog["F_trace"])
         log.append(rec)

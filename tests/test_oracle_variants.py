@@ -15,6 +15,13 @@ and T_j the deformed dose of the original plan):
 * when T is the dose of a pool at known intensities y0, the master over that
   pool reaches F = 0 and y = y0 (D_K of full column rank);
 * the column-generation loop never increases F.
+
+Several apertures per round:
+* the beam ranking's values equal each beam's optimum found by enumerating
+  every interval of every row (brute force), in value order with ties to the
+  lowest beam, and each ranked aperture attains its value;
+* the loop fills the budget with distinct apertures in fewer rounds and never
+  increases F.
 """
 import math
 
@@ -177,3 +184,51 @@ def test_reoptimization_loop_decreases_objective():
     Fs = [oracle.objective(P, np.zeros(ph.n_vox))] + [r["F"] for r in res["log"]]
     assert res["log"][0]["rc"] < 0
     assert all(b <= a * (1 + 1e-12) for a, b in zip(Fs[:-1], Fs[1:]))
+
+
+# --- several apertures per round --------------------------------------------
+
+def _beam_optimum_brute(P, g, b):
+    """Smallest sum over every deliverable aperture of beam b (each row: closed
+    or any contiguous run), by enumeration of each row's intervals."""
+    r0, r1 = P.beam_row_range(b)
+    starts = P.row_start()
+    total = 0.0
+    for r in range(r0, r1):
+        w = g[starts[r]:starts[r] + P.row_len[r]]
+        n = len(w)
+        best = min([0.0] + [math.fsum(w[l:q].tolist()) for q in range(1, n + 1) for l in range(q)])
+        total += best
+    return total
+
+
+def test_ranked_apertures_order_and_values():
+    ph = cached_phantom("mini")
+    P = oracle.make_problem(ph.csr(), ph.rows_per_beam, ph.row_len, ph.vox_struct, ph.prescriptions)
+    rng = np.random.default_rng(8)
+    for k in range(3):
+        d = oracle.dose(P, rng.uniform(0.0, 0.06, ph.n_blt))
+        g = oracle.prices(P, oracle.grad_objective(P, d))
+        pr = oracle.price(P, g)
+        ranked = oracle.ranked_apertures(P, pr)
+        assert ranked[0][1] == pr["aperture"] and ranked[0][0] == pr["rc"]
+        brute = sorted((_beam_optimum_brute(P, g, b), b) for b in range(len(ph.rows_per_beam)))
+        assert [ap.beam for _, ap in ranked] == [b for _, b in brute]
+        for (v, ap), (vb, _) in zip(ranked, brute):
+            assert abs(v - vb) <= 1e-14 * max(1.0, abs(vb))
+            # each beam's aperture attains its value
+            assert abs(math.fsum(g[ap.open_beamlets(P)].tolist()) - v) <= 1e-14 * max(1.0, abs(v))
+
+
+def test_several_apertures_per_round_loop():
+    ph = cached_phantom("mini")
+    P = oracle.make_problem(ph.csr(), ph.rows_per_beam, ph.row_len, ph.vox_struct, ph.prescriptions)
+    res = oracle.solve(P, 7, eps=1e-8, max_steps=3000, per_round=3)
+    assert len(res["pool"]) == 7 and len(set(res["pool"])) == 7
+    assert len(res["log"]) < 7          # some round added more than one
+    assert any(r["extra"] for r in res["log"])
+    Fs = [oracle.objective(P, np.zeros(ph.n_vox))] + [r["F"] for r in res["log"]]
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(Fs[:-1], Fs[1:]))
+    # the same budget one aperture at a time ends at a comparable objective
+    one = oracle.solve(P, 7, eps=1e-8, max_steps=3000)
+    assert res["F"] < 3.0 * one["F"] and one["F"] < 3.0 * res["F"]
