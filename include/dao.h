@@ -81,10 +81,24 @@ typedef struct {
 } dao_beams;
 
 /* Structure label of every voxel (eq. 9 and eq. 10's v_s): vox_struct[n_vox]
- * in [-1, n_struct), -1 = in no structure.  n_struct <= 255. */
+ * in [-1, n_struct), -1 = in no structure.  n_struct <= 255.
+ * vox_struct2 (optional, NULL = none): a second label per voxel for
+ * overlapping structures, whose terms add to the first label's (eq. 10 sums
+ * over every structure containing the voxel; nested targets such as PTV1
+ * inside PTV2, Section 3).  -1, or a structure other than the voxel's first
+ * label, which must then be set.  |v_s| counts both labels.  At most 255
+ * distinct (first, second) pairs plus single labels.
+ * vox_shift (optional, NULL = none): per-voxel threshold shift tau_j (finite):
+ * every threshold of voxel j is T_s + tau_j (eq. 3 and eq. 4's per-voxel
+ * T_j).  The re-optimization mode of the Discussion (alpha_j = beta_j = 1,
+ * T_j = the deformed dose of the original plan) is one target structure and
+ * one structure for all other voxels, thresholds 0, weights equal to the
+ * structure sizes, and tau = T. */
 typedef struct {
     int32_t n_struct;
     const int16_t* vox_struct;
+    const int16_t* vox_struct2;
+    const double* vox_shift;
 } dao_structures;
 
 /* One prescription per structure (eq. 9 and eq. 10): targets (is_target != 0)
@@ -113,7 +127,12 @@ typedef struct {
                                dtype) or, for DAO_F32 with the aperture master,
                                DAO_DFMT_F16 / DAO_DFMT_BF16, see below */
     int32_t d_residual;     /* with a 16-bit d_format: 1 also stores the FP16 residual and
-                               uses it in every product; 0 (default) the 16-bit values only */
+                               uses it in every product; 0 (default) the 16-bit values only;
+                               2 stores it and uses it selectively: in the plan's last
+                               residual_rounds rounds (where D_K is also rebuilt in FP32 when
+                               dk_format is DAO_DFMT_F16), and to price again any earlier
+                               decision whose gap is within the 16-bit values' rounding bound
+                               (4 u sum_{i in A} (D^T |grad F|)_i, u = 2^-11 FP16, 2^-8 BF16) */
     int32_t persistent;     /* aperture master: 2 (default) runs each master solve as one
                                cooperative launch when the device supports it, each
                                workgroup holding its rows of D_K, d and q in LDS when they
@@ -135,6 +154,19 @@ typedef struct {
                                in flight, 4 (default), 8 or 16 */
     int32_t direction;      /* master search direction (Section 2.3, gradient projection):
                                DAO_DIR_CONJUGATE (default) or DAO_DIR_STEEPEST, see below */
+    int32_t apertures_per_round; /* 1 (default): one aperture enters per round (Section 2.3).
+                               m in [2, 16]: after it, the beams ranked 2..m by their best
+                               aperture's value (ties to the lowest beam) add their
+                               apertures too, each if its value is below -tau, it is not
+                               pooled and the budget allows; one master solve follows */
+    int32_t dk_format;      /* storage of the aperture dose matrix D_K (eq. 1 and eq. 2) the
+                               aperture master streams: DAO_DFMT_NATIVE (default: the ctx
+                               dtype) or, for DAO_F32, DAO_DFMT_F16: FP16 values of D_K over
+                               the largest entry of D (half the bytes per master pass, about
+                               2.4e-4 relative rounding per entry); products accumulate in
+                               FP32 / FP64 as before */
+    int32_t residual_rounds; /* with d_residual 2: the plan's last this many rounds (5) run in
+                               the accurate form, see d_residual */
 } dao_options;
 
 /* Search direction of the master's gradient projection.  r is the projected
@@ -205,6 +237,9 @@ typedef struct {
                                  streaming / on chip */
     int32_t onchip_lds_bytes; /* dynamic LDS a workgroup of the persistent launch may use for
                                  its rows (0: the on-chip form is unavailable) */
+    int32_t dk_format;        /* storage of D_K now (DAO_DFMT_NATIVE or DAO_DFMT_F16) */
+    int32_t residual_reprices; /* d_residual 2: decisions priced again with the residual in the
+                                 last plan (or since the last reset) */
 } dao_info_t;
 dao_status dao_info(const dao_ctx* ctx, dao_info_t* out);
 

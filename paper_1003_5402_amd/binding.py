@@ -37,7 +37,8 @@ class dao_beams(ctypes.Structure):
 
 
 class dao_structures(ctypes.Structure):
-    _fields_ = [("n_struct", c_int32), ("vox_struct", POINTER(c_int16))]
+    _fields_ = [("n_struct", c_int32), ("vox_struct", POINTER(c_int16)), ("vox_struct2", POINTER(c_int16)),
+                ("vox_shift", POINTER(c_double))]
 
 
 class dao_prescription(ctypes.Structure):
@@ -51,7 +52,8 @@ class dao_options(ctypes.Structure):
                 ("refresh_every", c_int32), ("ls_slots", c_int32), ("mem_cap_bytes", c_int64),
                 ("master", c_int32), ("d_format", c_int32), ("d_residual", c_int32),
                 ("persistent", c_int32), ("product_tune", c_int32), ("dose_variant", c_int32),
-                ("gradient_depth", c_int32), ("direction", c_int32)]
+                ("gradient_depth", c_int32), ("direction", c_int32), ("apertures_per_round", c_int32),
+                ("dk_format", c_int32), ("residual_rounds", c_int32)]
 
 
 class dao_info_t(ctypes.Structure):
@@ -61,7 +63,7 @@ class dao_info_t(ctypes.Structure):
                 ("device_bytes", c_int64), ("d_format", c_int32), ("d_residual", c_int32),
                 ("bytes_dose", c_int64), ("bytes_gradient", c_int64),
                 ("dose_variant", c_int32), ("gradient_depth", c_int32), ("last_master_form", c_int32),
-                ("onchip_lds_bytes", c_int32)]
+                ("onchip_lds_bytes", c_int32), ("dk_format", c_int32), ("residual_reprices", c_int32)]
 
 
 class dao_server_options(ctypes.Structure):
@@ -214,11 +216,29 @@ def solve_batch(ctxs, n_apertures) -> list:
     return [_plan_dict(plans[i], keep[i], int(plans[i].stop)) for i in range(n)]
 
 
+def _structures(n_struct, vs, vox_struct2, vox_shift, keep):
+    """dao_structures with the optional second labels and threshold shifts
+    (NULL when absent); the arrays are appended to ``keep``."""
+    S = dao_structures()
+    S.n_struct = int(n_struct)
+    S.vox_struct = _ptr(vs, c_int16)
+    if vox_struct2 is not None:
+        v2 = np.ascontiguousarray(vox_struct2, dtype=np.int16)
+        keep.append(v2)
+        S.vox_struct2 = _ptr(v2, c_int16)
+    if vox_shift is not None:
+        sh = np.ascontiguousarray(vox_shift, dtype=np.float64)
+        keep.append(sh)
+        S.vox_shift = _ptr(sh, c_double)
+    return S
+
+
 class DaoContext:
     """One plan's device state: dose matrix, structures, pool and master."""
 
     def __init__(self, row_ptr, col, val, n_blt: int, rows_per_beam, row_len, vox_struct,
-                 prescriptions: Sequence[Dict], dtype: str = "f32", stream: int = 0, **opts):
+                 prescriptions: Sequence[Dict], dtype: str = "f32", stream: int = 0, vox_struct2=None,
+                 vox_shift=None, **opts):
         lib = load_library()
         self._lib = lib
         self._keep = []
@@ -232,7 +252,7 @@ class DaoContext:
         M = dao_matrix(rp.shape[0] - 1, int(n_blt), cl.shape[0], _ptr(rp, c_int64), _ptr(cl, c_int32),
                        _ptr(vl, c_double))
         Bm = dao_beams(rpb.shape[0], _ptr(rpb, c_int32), _ptr(rl, c_int32))
-        S = dao_structures(len(prescriptions), _ptr(vs, c_int16))
+        S = _structures(len(prescriptions), vs, vox_struct2, vox_shift, self._keep)
         PA = (dao_prescription * max(1, len(prescriptions)))()
         for i, p in enumerate(prescriptions):
             PA[i] = dao_prescription(int(p["is_target"]), p["t_under"], p["t_over"], p["w_under"], p["w_over"])
@@ -259,7 +279,8 @@ class DaoContext:
     @classmethod
     def from_phantom(cls, ph, dtype: Optional[str] = None, stream: int = 0, **opts) -> "DaoContext":
         return cls(ph.row_ptr, ph.col, ph.val, ph.n_blt, ph.rows_per_beam, ph.row_len, ph.vox_struct,
-                   ph.prescriptions, dtype=dtype or ph.dtype, stream=stream, **opts)
+                   ph.prescriptions, dtype=dtype or ph.dtype, stream=stream,
+                   vox_struct2=getattr(ph, "vox_struct2", None), **opts)
 
     # -- helpers -------------------------------------------------------------
     def _check(self, st):
@@ -460,7 +481,8 @@ class Server:
         M = dao_matrix(rp.shape[0] - 1, int(ph.n_blt), cl.shape[0], _ptr(rp, c_int64), _ptr(cl, c_int32),
                        _ptr(vl, c_double))
         Bm = dao_beams(rpb.shape[0], _ptr(rpb, c_int32), _ptr(rl, c_int32))
-        S = dao_structures(len(ph.prescriptions), _ptr(vs, c_int16))
+        extra = []
+        S = _structures(len(ph.prescriptions), vs, getattr(ph, "vox_struct2", None), None, extra)
         PA = (dao_prescription * max(1, len(ph.prescriptions)))()
         for i, p in enumerate(ph.prescriptions):
             PA[i] = dao_prescription(int(p["is_target"]), p["t_under"], p["t_over"], p["w_under"], p["w_over"])
@@ -477,7 +499,7 @@ class Server:
                                          byref(t))
         if st != DAO_OK:
             raise DaoError(st, "dao_server_submit rejected the request")
-        self._keep[t.value] = (rp, cl, vl, rpb, rl, vs, M, Bm, S, PA, O)
+        self._keep[t.value] = (rp, cl, vl, rpb, rl, vs, M, Bm, S, PA, O, extra)
         self._n_ap[t.value] = int(n_apertures)
         return t.value
 

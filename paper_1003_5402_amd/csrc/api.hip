@@ -118,6 +118,15 @@ struct dao_ctx {
     double* y = nullptr;
     double* p = nullptr;
     CgMem* cgm = nullptr;             // conjugate-direction memory of the master
+    bool dk16 = false;                // D_K stored in FP16 (values over dk_scale)
+    bool lo_now = false;              // selective residual: products use the FP16 residual now
+    bool final_phase = false;         // selective residual: the plan's final rounds have begun
+    int32_t reprices = 0;             // selective residual: near-tie decisions priced again with it
+    double* gabs64 = nullptr;         // [N] D^T |grad F| (rounding bound of the prices)
+    double* uabs64 = nullptr;         // [Vpad] |grad F|
+    double dk_scale = 1.0;            // D_K = dk_scale * stored value
+    double* tau_int = nullptr;        // per-voxel threshold shifts, internal rows (null: none)
+    double* tau_ext = nullptr;        // the same in caller order
     double* gradk = nullptr;
     std::vector<int32_t> pool_beam;
     std::vector<int16_t> pool_lv;
@@ -216,11 +225,12 @@ int64_t predicted_bytes(const HostLayout& L, size_t ts, int kmax, const dao_opti
     int64_t b = 0;
     b += (L.nslices + 1) * 4 + L.nslices * 4 + int64_t(L.slice_ptr.back()) * (vs + 2) + L.Vpad * 4;
     b += (L.N + 1) * 4 + L.nnz * (4 + vs) + (opt.d_format != DAO_DFMT_NATIVE ? L.N * 4 : 0);
-    b += L.Vpad + L.V + (L.n_struct + 1) * sizeof(ObjClass);
+    b += L.Vpad + L.V + int64_t(L.classes.size()) * sizeof(ObjClass) + int64_t(L.tau_int.size() + L.tau_ext.size()) * 8;
     b += int64_t(L.R) * 8 + (L.B + 1) * 4 + L.N * 12;
     b += L.Vpad * (8 + 3 * ts + 8) + L.N * (ts + 8 + ts + 8);
     b += int64_t(kmax) * (4 + 2 * 2 * L.max_rows_per_beam + 24);
-    b += int64_t(L.Vpad) * KS * ts + L.N * ts + 512 * (KS + 1) * 8;
+    const int64_t dkb = (opt.dk_format == DAO_DFMT_F16 && ts == 4) ? 2 : int64_t(ts);
+    b += int64_t(L.Vpad) * KS * dkb + L.N * ts + 512 * (KS + 1) * 8;
     b += sizeof(MasterState) + sizeof(PriceResult) + L.R * sizeof(RowRec) + 2 * ELEM_BLOCKS_MAX * sizeof(Rec) +
          sizeof(Arrival);
     return b;
@@ -245,15 +255,18 @@ struct ValueTag {
 template <class T, class F>
 void with_values(const dao_ctx* c, F&& f) {
     if constexpr (std::is_same<T, float>::value) {
+        // the FP16 residual: always (d_residual 1) or while the selective
+        // policy asks for it (d_residual 2)
+        const bool lo = c->opt.d_residual == 1 || (c->opt.d_residual == 2 && c->lo_now);
         if (c->opt.d_format == DAO_DFMT_F16) {
-            if (c->opt.d_residual)
+            if (lo)
                 f(ValueTag<__half, true>{});
             else
                 f(ValueTag<__half, false>{});
             return;
         }
         if (c->opt.d_format == DAO_DFMT_BF16) {
-            if (c->opt.d_residual)
+            if (lo)
                 f(ValueTag<__hip_bfloat16, true>{});
             else
                 f(ValueTag<__hip_bfloat16, false>{});
@@ -395,7 +408,7 @@ dao_status enqueue_cycle(dao_ctx* c) {
             c->y, c->p, c->x64);
     k_update<T><<<c->slab_blocks(), SLAB_THREADS, cls_b + (c->stage_x64() ? c->N * 8 : 0), c->stream>>>(
         S, c->Vpad, c->x64, int(c->N), c->stage_x64(), c->d, static_cast<const T*>(c->q), c->cls_int,
-        c->classes, c->ncls, static_cast<T*>(c->u), c->upd_parts, c->ms);
+        c->classes, c->ncls, c->tau_int, static_cast<T*>(c->u), c->upd_parts, c->ms);
     k_gradT<T, T, T, T, true><<<c->N, BLOCK, 0, c->stream>>>(c->csc_ptr, c->csc_row,
                                                              static_cast<const T*>(c->csc_val), nullptr,
                                                              static_cast<const T*>(c->u),
@@ -417,10 +430,12 @@ dao_status prof_mark(dao_ctx* c, int kernel, bool before) {
     return DAO_OK;
 }
 
-template <class T>
-dao_status enqueue_cycle_ap(dao_ctx* c) {
+template <class T, class DT>
+dao_status enqueue_cycle_ap_dt(dao_ctx* c) {
+    if (c->Vpad % Batch<DT>::ROWS != 0) return c->fail(DAO_ESTATE, "padded rows not a multiple of the D_K batch");
     const int nb = int(c->ap_blocks());
-    const T* dk = static_cast<const T*>(c->dk);
+    const DT* dk = static_cast<const DT*>(c->dk);
+    const double dks = c->dk_scale;
     dao_status s;
 #define MARK(k, b)                      \
     do {                                \
@@ -428,14 +443,15 @@ dao_status enqueue_cycle_ap(dao_ctx* c) {
         if (s != DAO_OK) return s;      \
     } while (0)
     MARK(0, true);
-    k_upd_ap<T><<<nb, BLOCK, 0, c->stream>>>(dk, c->Vpad, c->d, static_cast<const T*>(c->q), c->cls_int,
-                                              c->classes, c->ncls, c->y, c->parts2, c->ms, c->pc, c->Vnz);
+    k_upd_ap<T, DT><<<nb, BLOCK, 0, c->stream>>>(dk, dks, c->Vpad, c->d, static_cast<const T*>(c->q), c->cls_int,
+                                              c->classes, c->ncls, c->y, c->parts2, c->ms, c->pc, c->Vnz,
+                                              c->tau_int);
     MARK(0, false);
     MARK(3, true);
     k_dir_ap<<<1, 1024, 0, c->stream>>>(c->parts2, nb, c->y, c->p, c->gradk, c->ms, c->cgm, c->pc);
     MARK(3, false);
     MARK(1, true);
-    k_qstep_ap<T><<<nb, BLOCK, 0, c->stream>>>(dk, c->Vpad, c->d, c->cls_int, c->classes, c->ncls,
+    k_qstep_ap<T, DT><<<nb, BLOCK, 0, c->stream>>>(dk, dks, c->Vpad, c->d, c->cls_int, c->classes, c->ncls,
                                                 static_cast<T*>(c->q), c->parts, c->arr, c->ms, c->y, c->p,
                                                 c->pc, c->Vnz);
     MARK(1, false);
@@ -451,6 +467,13 @@ dao_status enqueue_cycle_ap(dao_ctx* c) {
     return DAO_OK;
 }
 
+template <class T>
+dao_status enqueue_cycle_ap(dao_ctx* c) {
+    if constexpr (std::is_same<T, float>::value)
+        if (c->dk16) return enqueue_cycle_ap_dt<T, __half>(c);
+    return enqueue_cycle_ap_dt<T, T>(c);
+}
+
 // Column k of the aperture dose matrix: D times the 0/1 indicator of aperture k.
 template <class T>
 dao_status build_dk_column(dao_ctx* c, int k) {
@@ -459,23 +482,33 @@ dao_status build_dk_column(dao_ctx* c, int k) {
     with_values<T>(c, [&](auto tag) {
         using VT = typename decltype(tag)::VT;
         constexpr bool LO = decltype(tag)::LO;
-        k_dk_column<T, VT, LO><<<c->slab_blocks(), SLAB_THREADS, c->stage_x() ? c->N * sizeof(T) : 0, c->stream>>>(
+        const size_t lds = c->stage_x() ? c->N * sizeof(T) : 0;
+        if constexpr (std::is_same<T, float>::value) {
+            if (c->dk16) {
+                k_dk_column<T, VT, LO, __half><<<c->slab_blocks(), SLAB_THREADS, lds, c->stream>>>(
+                    sell_view<VT>(c), c->Vpad, static_cast<const T*>(c->ind), int(c->N), c->stage_x(),
+                    c->col_scale, k, static_cast<__half*>(c->dk), 1.0 / c->dk_scale);
+                return;
+            }
+        }
+        k_dk_column<T, VT, LO, T><<<c->slab_blocks(), SLAB_THREADS, lds, c->stream>>>(
             sell_view<VT>(c), c->Vpad, static_cast<const T*>(c->ind), int(c->N), c->stage_x(), c->col_scale, k,
-            static_cast<T*>(c->dk));
+            static_cast<T*>(c->dk), 1.0);
     });
     LAUNCHCHK(c);
     return DAO_OK;
 }
 
 // One cooperative launch runs the whole master solve.
-template <class T>
-dao_status run_master_coop(dao_ctx* c, double tol, int max_steps) {
+template <class T, class DT>
+dao_status run_master_coop_dt(dao_ctx* c, double tol, int max_steps) {
+    if (c->Vpad % Batch<DT>::ROWS != 0) return c->fail(DAO_ESTATE, "padded rows not a multiple of the D_K batch");
     k_master_init_ap<<<1, 1, 0, c->stream>>>(c->ms, c->K, tol, max_steps);
     LAUNCHCHK(c);
     HIPCHK(c, hipMemsetAsync(c->coop, 0, sizeof(CoopSync), c->stream));
-    CoopArgs<T> A{static_cast<const T*>(c->dk), c->Vpad, c->Vnz, c->d, static_cast<T*>(c->q), c->cls_int,
-                  c->classes, c->ncls, c->y, c->p, c->gradk, c->cgm, c->ms, c->coop_recs, c->coop, c->pc,
-                  c->prof_kernel == 4 ? 1 : 0};
+    CoopArgs<T> A{c->dk, c->dk_scale, c->Vpad, c->Vnz, c->d, static_cast<T*>(c->q), c->cls_int,
+                  c->classes, c->ncls, c->y, c->p, c->gradk, c->cgm, c->tau_int, c->ms, c->coop_recs, c->coop,
+                  c->pc, c->prof_kernel == 4 ? 1 : 0};
     void* args[] = {&A};
     const bool prof = c->prof_kernel == 4;
     if (prof) {
@@ -483,15 +516,15 @@ dao_status run_master_coop(dao_ctx* c, double tol, int max_steps) {
         if (s != DAO_OK) return s;
     }
     // LDS-resident variant when the workgroup's slice fits on chip
-    const int nc = (c->K + DKG<T>::EPL - 1) / DKG<T>::EPL;
-    const int64_t rows = coop_batches_per_group<T>(c->Vpad, c->coop_grid) * Batch<T>::ROWS;
+    const int nc = (c->K + DKG<DT>::EPL - 1) / DKG<DT>::EPL;
+    const int64_t rows = coop_batches_per_group<DT>(c->Vpad, c->coop_grid) * Batch<DT>::ROWS;
     const size_t lds = coop_lds_bytes<T>(rows, nc);
     if (c->opt.persistent == 2 && c->coop_lds_max > 0 && lds <= size_t(c->coop_lds_max)) {
-        HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T, true>),
+        HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T, DT, true>),
                                              dim3(c->coop_grid), dim3(COOP_THREADS), args, lds, c->stream));
         c->last_form = 2;
     } else {
-        HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T, false>),
+        HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T, DT, false>),
                                              dim3(c->coop_grid), dim3(COOP_THREADS), args, 0, c->stream));
         c->last_form = 1;
     }
@@ -506,6 +539,13 @@ dao_status run_master_coop(dao_ctx* c, double tol, int max_steps) {
     c->last_steps = c->ms_h->steps;
     c->last_stop = c->ms_h->stop_reason;
     return DAO_OK;
+}
+
+template <class T>
+dao_status run_master_coop(dao_ctx* c, double tol, int max_steps) {
+    if constexpr (std::is_same<T, float>::value)
+        if (c->dk16) return run_master_coop_dt<T, __half>(c, tol, max_steps);
+    return run_master_coop_dt<T, T>(c, tol, max_steps);
 }
 
 template <class T>
@@ -556,17 +596,24 @@ PriceGeom price_geom(dao_ctx* c) {
     return PriceGeom{c->row_start_d, c->row_len_d, c->beam_row0_d, c->R, c->B};
 }
 
-dao_status price_on(dao_ctx* c, const double* g, int32_t* beam, int16_t* leaves, double* rc,
-                    double* gap) {
-    k_price<<<c->price_blocks(), BLOCK, 0, c->stream>>>(price_geom(c), g, c->rowrec, c->pr, c->arr);
+// One pricing launch with the given scratch (row records, result, arrival
+// counters), then the result to the host.
+dao_status price_with(dao_ctx* c, const double* g, RowRec* rows, PriceResult* pr, Arrival* arr, int32_t* beam,
+                      int16_t* leaves, double* rc, double* gap) {
+    k_price<<<c->price_blocks(), BLOCK, 0, c->stream>>>(price_geom(c), g, rows, pr, arr);
     LAUNCHCHK(c);
-    HIPCHK(c, hipMemcpyAsync(c->pr_h, c->pr, sizeof(PriceResult), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->pr_h, pr, sizeof(PriceResult), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (beam) *beam = c->pr_h->beam;
     if (leaves) std::memcpy(leaves, c->pr_h->leaves, sizeof(int16_t) * 2 * c->pr_h->n_rows);
     if (rc) *rc = c->pr_h->rc;
     if (gap) *gap = c->pr_h->gap;
     return DAO_OK;
+}
+
+dao_status price_on(dao_ctx* c, const double* g, int32_t* beam, int16_t* leaves, double* rc,
+                    double* gap) {
+    return price_with(c, g, c->rowrec, c->pr, c->arr, beam, leaves, rc, gap);
 }
 
 // The master dose recomputed from the intensities in FP64 (x = A y, then
@@ -579,7 +626,7 @@ dao_status refresh_dose_exact(dao_ctx* c) {
         using VT = typename decltype(tag)::VT;
         constexpr bool LO = decltype(tag)::LO;
         k_dose_exact<VT, LO><<<c->slab_blocks(), SLAB_THREADS, c->stage_x64() ? c->N * 8 : 0, c->stream>>>(
-            sell_view<VT>(c), c->Vpad, c->x64, int(c->N), c->stage_x64(), c->col_scale, c->d);
+            sell_view<VT>(c), c->Vpad, c->x64, int(c->N), c->stage_x64(), c->col_scale, c->tau_int, c->d);
     });
     LAUNCHCHK(c);
     return DAO_OK;
@@ -612,7 +659,13 @@ dao_status price_current(dao_ctx* c, int32_t* beam, int16_t* leaves, double* rc,
 template <class T>
 dao_status reset_state(dao_ctx* c) {
     const int64_t eb = c->elem_blocks(c->Vpad);
-    k_fill<double><<<eb, BLOCK, 0, c->stream>>>(c->d, c->Vpad, 0.0);
+    // a new pool starts in the fast form of the selective residual
+    c->lo_now = false;
+    c->final_phase = false;
+    c->reprices = 0;
+    c->dk16 = std::is_same<T, float>::value && c->ap_master() && c->opt.dk_format == DAO_DFMT_F16;
+    // zero dose; the master keeps d - tau
+    k_neg_or_zero<<<eb, BLOCK, 0, c->stream>>>(c->tau_int, c->Vpad, c->d);
     k_fill<double><<<1, BLOCK, 0, c->stream>>>(c->y, c->opt.max_apertures, 0.0);
     k_clear_steps<<<1, 1, 0, c->stream>>>(c->ms);
     LAUNCHCHK(c);
@@ -651,6 +704,64 @@ bool in_pool(dao_ctx* c, int32_t beam, const int16_t* leaves) {
         if (std::equal(lv, lv + 2 * nr, leaves)) return true;
     }
     return false;
+}
+
+// Grid and on-chip LDS budget of the persistent master for D_K storage DT
+// (one co-resident workgroup per compute unit).  Sets coop_grid (0: the
+// device cannot run it), coop_lds_max and batch_ok.
+template <class T, class DT>
+hipError_t setup_coop(dao_ctx* c, int dev, int coop, int ncu) {
+    int occ = 0;
+    c->coop_lds_max = 0;
+    c->batch_ok = false;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &occ, reinterpret_cast<const void*>(&k_master_coop<T, DT, false>), COOP_THREADS, 0);
+    if (e != hipSuccess) return e;
+    if (coop && occ > 0 && ncu > 0) {
+        c->coop_grid = std::min(ncu, MAX_COOP_GRID);   // one co-resident workgroup per compute unit
+        // on-chip variant: as much dynamic LDS as the device grants one
+        // workgroup beyond the kernel's static LDS, if one per CU still fits
+        int lds_max = 0;
+        e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess) return e;
+        // the kernels' own static LDS (the larger of the single and the
+        // batched launch), rounded up to 1 KB
+        int stat = 0;
+        for (const void* fn : {reinterpret_cast<const void*>(&k_master_coop<T, DT, true>),
+                               reinterpret_cast<const void*>(&k_master_batch<T, DT, true>)}) {
+            hipFuncAttributes fa{};
+            if (hipFuncGetAttributes(&fa, fn) == hipSuccess) stat = std::max(stat, int(fa.sharedSizeBytes));
+            else stat = std::max(stat, 32 * 1024);
+        }
+        const int want = lds_max - ((stat + 1023) / 1024) * 1024;
+        if (want > 0 &&
+            hipFuncSetAttribute(reinterpret_cast<const void*>(&k_master_coop<T, DT, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, want) == hipSuccess) {
+            int occ2 = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &occ2, reinterpret_cast<const void*>(&k_master_coop<T, DT, true>), COOP_THREADS, want) ==
+                    hipSuccess &&
+                occ2 >= 1)
+                c->coop_lds_max = want;
+        }
+        (void)hipGetLastError();
+        // the batched launch: same resources, both variants
+        int occ3 = 0, occ4 = 0;
+        c->batch_ok =
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &occ3, reinterpret_cast<const void*>(&k_master_batch<T, DT, false>), COOP_THREADS, 0) == hipSuccess &&
+            occ3 >= 1;
+        if (c->batch_ok && c->coop_lds_max > 0 &&
+            !(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_master_batch<T, DT, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, c->coop_lds_max) == hipSuccess &&
+              hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &occ4, reinterpret_cast<const void*>(&k_master_batch<T, DT, true>), COOP_THREADS,
+                  c->coop_lds_max) == hipSuccess &&
+              occ4 >= 1))
+            c->batch_ok = false;
+        (void)hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 template <class T>
@@ -701,6 +812,10 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     TRY(upload(c, &c->cls_int, L.cls_int.data(), L.cls_int.size()));
     TRY(upload(c, &c->cls_ext, L.cls_ext.data(), L.cls_ext.size()));
     TRY(upload(c, &c->classes, L.classes.data(), L.classes.size() * sizeof(ObjClass)));
+    if (!L.tau_int.empty()) {
+        TRY(upload(c, &c->tau_int, L.tau_int.data(), L.tau_int.size() * 8));
+        TRY(upload(c, &c->tau_ext, L.tau_ext.data(), L.tau_ext.size() * 8));
+    }
     TRY(upload(c, &c->row_start_d, L.row_start.data(), L.row_start.size() * 4));
     TRY(upload(c, &c->row_len_d, L.row_len.data(), L.row_len.size() * 4));
     TRY(upload(c, &c->beam_row0_d, L.beam_row0.data(), L.beam_row0.size() * 4));
@@ -711,6 +826,10 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     TRY(dev_alloc(c, &c->q, c->Vpad * ts));
     TRY(dev_alloc(c, &c->u, c->Vpad * ts));
     TRY(dev_alloc(c, &c->u64, c->Vpad * 8));
+    if (c->opt.d_residual == 2) {
+        TRY(dev_alloc(c, &c->gabs64, c->N * 8));
+        TRY(dev_alloc(c, &c->uabs64, c->Vpad * 8));
+    }
     TRY(dev_alloc(c, &c->ug, c->Vpad * ts));
     TRY(dev_alloc(c, &c->g, c->N * ts));
     TRY(dev_alloc(c, &c->g64, c->N * 8));
@@ -731,62 +850,50 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     TRY(dev_alloc(c, &c->upd_parts, c->slab_blocks() * sizeof(Rec)));
     TRY(dev_alloc(c, &c->arr, sizeof(Arrival)));
     TRY(dev_alloc(c, &c->pc, sizeof(ProfCounters)));
+    // FP16 storage of D_K: values over the largest entry of D (every D_K
+    // entry is a sum of D entries, so the stored values stay well inside
+    // FP16's range)
+    c->dk16 = std::is_same<T, float>::value && c->ap_master() && c->opt.dk_format == DAO_DFMT_F16;
+    c->dk_scale = 1.0;
+    if (c->dk16) {
+        float mx = 0.0f;
+        for (float v : L.col_scale) mx = std::max(mx, v);
+        c->dk_scale = mx > 0.0f ? double(mx) : 1.0;
+    }
+    // bytes per stored D_K value; the selective residual switches D_K to FP32
+    // for the final rounds, so its buffer holds FP32 values
+    const size_t dkb = (c->dk16 && c->opt.d_residual != 2) ? sizeof(__half) : ts;
     if (c->ap_master() && c->opt.persistent) {
-        int dev = 0, coop = 0, ncu = 0, occ = 0;
+        int dev = 0, coop = 0, ncu = 0;
         HIPCHK(c, hipGetDevice(&dev));
         c->device = dev;
         HIPCHK(c, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
         HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-        HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                      &occ, reinterpret_cast<const void*>(&k_master_coop<T, false>), COOP_THREADS, 0));
-        if (coop && occ > 0 && ncu > 0) {
-            c->coop_grid = std::min(ncu, MAX_COOP_GRID);   // one co-resident workgroup per compute unit
-            // on-chip variant: as much dynamic LDS as the device grants one
-            // workgroup beyond the kernel's static LDS, if one per CU still fits
-            int lds_max = 0;
-            HIPCHK(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-            // the kernels' own static LDS (the larger of the single and the
-            // batched launch), rounded up to 1 KB
-            int stat = 0;
-            for (const void* fn : {reinterpret_cast<const void*>(&k_master_coop<T, true>),
-                                   reinterpret_cast<const void*>(&k_master_batch<T, true>)}) {
-                hipFuncAttributes fa{};
-                if (hipFuncGetAttributes(&fa, fn) == hipSuccess) stat = std::max(stat, int(fa.sharedSizeBytes));
-                else stat = std::max(stat, 32 * 1024);
+        if constexpr (std::is_same<T, float>::value) {
+            if (c->dk16 && c->opt.d_residual == 2) {
+                // both storages run: keep the smaller on-chip budget
+                HIPCHK(c, (setup_coop<T, T>(c, dev, coop, ncu)));
+                const int lds_f = c->coop_lds_max;
+                const bool ok_f = c->batch_ok;
+                HIPCHK(c, (setup_coop<T, __half>(c, dev, coop, ncu)));
+                c->coop_lds_max = std::min(c->coop_lds_max, lds_f);
+                c->batch_ok = c->batch_ok && ok_f;
+            } else if (c->dk16) {
+                HIPCHK(c, (setup_coop<T, __half>(c, dev, coop, ncu)));
+            } else {
+                HIPCHK(c, (setup_coop<T, T>(c, dev, coop, ncu)));
             }
-            const int want = lds_max - ((stat + 1023) / 1024) * 1024;
-            if (want > 0 &&
-                hipFuncSetAttribute(reinterpret_cast<const void*>(&k_master_coop<T, true>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, want) == hipSuccess) {
-                int occ2 = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                        &occ2, reinterpret_cast<const void*>(&k_master_coop<T, true>), COOP_THREADS, want) ==
-                        hipSuccess &&
-                    occ2 >= 1)
-                    c->coop_lds_max = want;
-            }
-            (void)hipGetLastError();
-            // the batched launch: same resources, both variants
-            int occ3 = 0, occ4 = 0;
-            c->batch_ok =
-                hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &occ3, reinterpret_cast<const void*>(&k_master_batch<T, false>), COOP_THREADS, 0) == hipSuccess &&
-                occ3 >= 1;
-            if (c->batch_ok && c->coop_lds_max > 0 &&
-                !(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_master_batch<T, true>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, c->coop_lds_max) == hipSuccess &&
-                  hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                      &occ4, reinterpret_cast<const void*>(&k_master_batch<T, true>), COOP_THREADS,
-                      c->coop_lds_max) == hipSuccess &&
-                  occ4 >= 1))
-                c->batch_ok = false;
+        } else {
+            HIPCHK(c, (setup_coop<T, T>(c, dev, coop, ncu)));
+        }
+        if (c->coop_grid > 0) {
             (void)hipGetLastError();
             TRY(dev_alloc(c, &c->coop, sizeof(CoopSync)));
             TRY(dev_alloc(c, &c->coop_recs, 2 * size_t(c->coop_grid) * RECW * sizeof(double)));
         }
     }
     if (c->ap_master()) {
-        TRY(dev_alloc(c, &c->dk, size_t(c->Vpad) * KS * ts));
+        TRY(dev_alloc(c, &c->dk, size_t(c->Vpad) * KS * dkb));
         TRY(dev_alloc(c, &c->ind, c->N * ts));
         TRY(dev_alloc(c, &c->parts2, c->ap_blocks() * (KS + 1) * sizeof(double)));
     }
@@ -807,7 +914,7 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     std::memset(c->pr_h, 0, sizeof(PriceResult));
     HIPCHK(c, hipMemcpyAsync(c->pr, c->pr_h, sizeof(PriceResult), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemsetAsync(c->arr, 0, sizeof(Arrival), c->stream));
-    if (c->ap_master()) HIPCHK(c, hipMemsetAsync(c->dk, 0, size_t(c->Vpad) * KS * ts, c->stream));
+    if (c->ap_master()) HIPCHK(c, hipMemsetAsync(c->dk, 0, size_t(c->Vpad) * KS * dkb, c->stream));
     HIPCHK(c, hipMemsetAsync(c->ap_lv, 0, size_t(km) * c->maxRB * 4, c->stream));
     HIPCHK(c, hipMemsetAsync(c->ap_beam, 0, km * 4, c->stream));
     HIPCHK(c, hipMemsetAsync(c->p, 0, km * 8, c->stream));
@@ -837,9 +944,10 @@ template <class T>
 dao_status gradient_typed(dao_ctx* c, const void* d, void* g, double* F) {
     const T* dd = static_cast<const T*>(d);
     k_objective_ext<T><<<c->elem_blocks(c->V), BLOCK, 0, c->stream>>>(dd, c->cls_ext, c->V, c->classes,
-                                                                       c->parts, c->arr, c->scalar);
+                                                                       c->tau_ext, c->parts, c->arr, c->scalar);
     k_gather_grad<T><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(dd, c->perm, c->cls_int, c->Vpad,
-                                                                        c->classes, static_cast<T*>(c->ug));
+                                                                        c->classes, c->tau_int,
+                                                                        static_cast<T*>(c->ug));
     launch_gradT<T, T, T, T>(c, static_cast<const T*>(c->ug), static_cast<T*>(g));
     LAUNCHCHK(c);
     HIPCHK(c, hipMemcpyAsync(c->scalar_h, c->scalar, 8, hipMemcpyDeviceToHost, c->stream));
@@ -963,6 +1071,119 @@ dao_status set_state_typed(dao_ctx* c, const dao_state_info* info, const int32_t
     return DAO_OK;
 }
 
+// Append an aperture given on the host (leaves of its beam's rows) with y = 0.
+// Selective residual (d_residual 2).  The final rounds of a plan run with
+// the FP16 residual in every product and with D_K in FP32: the columns built
+// so far are rebuilt that way once, when the final phase begins.
+template <class T>
+dao_status enter_final_phase(dao_ctx* c) {
+    c->final_phase = true;
+    c->lo_now = true;
+    if (c->dk16) {
+        c->dk16 = false;
+        HIPCHK(c, hipMemsetAsync(c->dk, 0, size_t(c->Vpad) * KS * sizeof(T), c->stream));
+        for (int k = 0; k < c->K; ++k) {
+            const dao_status s = build_dk_column<T>(c, k);
+            if (s != DAO_OK) return s;
+        }
+    }
+    return DAO_OK;
+}
+
+// Before the final phase, pricing runs on the 16-bit values alone.  Each of
+// its prices w_i = sum_j D_ij pi_j is then off by at most u sum_j D_ij |pi_j|
+// (u = 2^-11 for FP16, 2^-8 for BF16: the relative rounding of a stored
+// value), so a reduced cost is off by at most u sum_{i in A} (D^T |pi|)_i,
+// doubled for the rounding the dose carries into pi.  A decision whose gap
+// is below twice that bound is priced again with the residual.
+template <class T>
+dao_status price_selective(dao_ctx* c, int32_t* beam, int16_t* leaves, double* rc, double* gap) {
+    dao_status s = price_current<T>(c, beam, leaves, rc, gap);
+    if (s != DAO_OK || c->opt.d_residual != 2 || c->lo_now) return s;
+    k_abs_copy<<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(c->u64, c->Vpad, c->uabs64);
+    launch_gradT<T, double, double, double>(c, c->uabs64, c->gabs64);
+    LAUNCHCHK(c);
+    std::vector<double> ga(size_t(c->N));
+    HIPCHK(c, hipMemcpyAsync(ga.data(), c->gabs64, size_t(c->N) * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int start = 0;
+    for (int r = 0; r < c->beam_row0[*beam]; ++r) start += c->row_len[r];
+    double sum = 0.0;
+    for (int r = c->beam_row0[*beam]; r < c->beam_row0[*beam + 1]; ++r) {
+        const int lr = r - c->beam_row0[*beam];
+        for (int pos = leaves[2 * lr]; pos < leaves[2 * lr + 1]; ++pos) sum += ga[size_t(start + pos)];
+        start += c->row_len[r];
+    }
+    const double u = c->opt.d_format == DAO_DFMT_BF16 ? 0x1p-8 : 0x1p-11;
+    if (!(*gap > 4.0 * u * sum)) {
+        c->lo_now = true;
+        s = price_current<T>(c, beam, leaves, rc, gap);
+        c->lo_now = false;
+        ++c->reprices;
+    }
+    return s;
+}
+
+dao_status add_aperture_host(dao_ctx* c, int32_t beam, const int16_t* leaves) {
+    dao_status s;
+    if (c->K >= c->opt.max_apertures) return c->fail(DAO_ESTATE, "pool capacity reached");
+    const int nr = c->rows_per_beam[beam];
+    for (int i = 0; i < c->maxRB; ++i) {
+        c->lv_stage_h[2 * i] = i < nr ? leaves[2 * i] : int16_t(0);
+        c->lv_stage_h[2 * i + 1] = i < nr ? leaves[2 * i + 1] : int16_t(0);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->ap_lv + size_t(c->K) * c->maxRB * 2, c->lv_stage_h,
+                             size_t(c->maxRB) * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->ap_beam + c->K, &beam, 4, hipMemcpyHostToDevice, c->stream));
+    k_fill<double><<<1, 64, 0, c->stream>>>(c->y + c->K, 1, 0.0);
+    LAUNCHCHK(c);
+    s = c->dtype == DAO_F64 ? build_dk_column<double>(c, c->K) : build_dk_column<float>(c, c->K);
+    if (s != DAO_OK) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    mirror_add(c, beam, leaves);
+    c->K += 1;
+    return DAO_OK;
+}
+
+
+// Several apertures per round: after the entering aperture, the beams ranked
+// 2..m by value (ties to the lowest beam) add their own best apertures, each
+// if its value is below -tau, it is not pooled yet and the budget allows.
+// The beam values are summed from the pricing launch's row records in the
+// kernel's own order, so the ranking sees the same values as the argmin.
+template <class T>
+dao_status add_ranked_apertures(dao_ctx* c, int m, int n_ap, double tau, int* added) {
+    *added = 0;
+    std::vector<RowRec> rows(size_t(c->R));
+    HIPCHK(c, hipMemcpyAsync(rows.data(), c->rowrec, size_t(c->R) * sizeof(RowRec), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<std::pair<double, int>> order;
+    for (int b = 0; b < c->B; ++b) {
+        double sb = 0.0;
+        for (int rr = c->beam_row0[b]; rr < c->beam_row0[b + 1]; ++rr) sb += rows[size_t(rr)].v;
+        order.push_back({sb, b});
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<double, int>& x, const std::pair<double, int>& y) {
+                         return x.first < y.first || (x.first == y.first && x.second < y.second);
+                     });
+    std::vector<int16_t> lv(size_t(2 * c->maxRB), 0);
+    for (int i = 1; i < std::min(m, int(order.size())); ++i) {
+        if (c->K >= n_ap || !(order[size_t(i)].first < -tau)) break;
+        const int b = order[size_t(i)].second;
+        for (int rr = c->beam_row0[b]; rr < c->beam_row0[b + 1]; ++rr) {
+            lv[size_t(2 * (rr - c->beam_row0[b]))] = int16_t(rows[size_t(rr)].L);
+            lv[size_t(2 * (rr - c->beam_row0[b]) + 1)] = int16_t(rows[size_t(rr)].R);
+        }
+        if (in_pool(c, b, lv.data())) continue;
+        const dao_status s = add_aperture_host(c, b, lv.data());
+        if (s != DAO_OK) return s;
+        ++*added;
+    }
+    return DAO_OK;
+}
+
 // One column-generation solve, split into the steps around its master
 // solves so that several solves can share one master launch per round.
 using clk = std::chrono::steady_clock;
@@ -1020,7 +1241,11 @@ dao_status plan_round_begin(PlanRun& r) {
         return DAO_OK;
     }
     const auto tp = clk::now();
-    dao_status s = price_current<T>(c, &r.beam, r.lv.data(), &r.rc, &r.gap);
+    if (c->opt.d_residual == 2 && !c->final_phase && c->K >= r.n_ap - c->opt.residual_rounds) {
+        const dao_status f = enter_final_phase<T>(c);
+        if (f != DAO_OK) return f;
+    }
+    dao_status s = price_selective<T>(c, &r.beam, r.lv.data(), &r.rc, &r.gap);
     if (s != DAO_OK) return s;
     r.t_price += since(tp);
     r.tm = clk::now();
@@ -1058,6 +1283,11 @@ dao_status plan_round_begin(PlanRun& r) {
     c->K += 1;
     r.added = true;
     r.tol = r.eps * scale;
+    if (c->opt.apertures_per_round > 1) {
+        int more = 0;
+        s = add_ranked_apertures<T>(c, c->opt.apertures_per_round, r.n_ap, c->opt.tau_rel * scale, &more);
+        if (s != DAO_OK) return s;
+    }
     return DAO_OK;
 }
 
@@ -1123,8 +1353,11 @@ dao_status solve_typed(dao_ctx* c, int32_t n_ap, dao_plan* out, bool resume = fa
 // k_master_batch (when all use the persistent master on one stream; else one
 // after another).  Workgroups are shared out in proportion to the solves'
 // voxel rows, at least one each.
-template <class T>
-dao_status run_master_batch(std::vector<PlanRun*>& live) {
+template <class T, class DT>
+dao_status run_master_batch_dt(std::vector<PlanRun*>& live) {
+    for (PlanRun* r : live)
+        if (r->c->Vpad % Batch<DT>::ROWS != 0)
+            return r->c->fail(DAO_ESTATE, "padded rows not a multiple of the D_K batch");
     dao_ctx* c0 = live[0]->c;
     bool together = live.size() > 1 && int(live.size()) <= std::min(MAX_BATCH, c0->coop_grid);
     for (PlanRun* r : live)
@@ -1176,12 +1409,12 @@ dao_status run_master_batch(std::vector<PlanRun*>& live) {
         k_master_init_ap<<<1, 1, 0, c->stream>>>(c->ms, c->K, live[i]->tol, c->opt.max_steps);
         LAUNCHCHK(c);
         HIPCHK(c, hipMemsetAsync(c->coop, 0, sizeof(CoopSync), c->stream));
-        hargs[i] = CoopArgs<T>{static_cast<const T*>(c->dk), c->Vpad, c->Vnz, c->d, static_cast<T*>(c->q), c->cls_int,
-                               c->classes, c->ncls, c->y, c->p, c->gradk, c->cgm, c->ms, c->coop_recs, c->coop,
-                               c->pc, 0};
+        hargs[i] = CoopArgs<T>{c->dk, c->dk_scale, c->Vpad, c->Vnz, c->d, static_cast<T*>(c->q), c->cls_int,
+                               c->classes, c->ncls, c->y, c->p, c->gradk, c->cgm, c->tau_int, c->ms,
+                               c->coop_recs, c->coop, c->pc, 0};
         hstart[i + 1] = hstart[i] + g[i];
-        const int nc = (c->K + DKG<T>::EPL - 1) / DKG<T>::EPL;
-        const size_t li = coop_lds_bytes<T>(coop_batches_per_group<T>(c->Vpad, g[i]) * Batch<T>::ROWS, nc);
+        const int nc = (c->K + DKG<DT>::EPL - 1) / DKG<DT>::EPL;
+        const size_t li = coop_lds_bytes<T>(coop_batches_per_group<DT>(c->Vpad, g[i]) * Batch<DT>::ROWS, nc);
         lds = std::max(lds, li);
         fits = fits && c->opt.persistent == 2 && li <= size_t(c0->coop_lds_max);
     }
@@ -1194,10 +1427,10 @@ dao_status run_master_batch(std::vector<PlanRun*>& live) {
     int nn = n;
     void* kargs[] = {&dargs, &dstart, &nn};
     if (fits)
-        HIPCHK(c0, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_batch<T, true>), dim3(G),
+        HIPCHK(c0, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_batch<T, DT, true>), dim3(G),
                                               dim3(COOP_THREADS), kargs, lds, c0->stream));
     else
-        HIPCHK(c0, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_batch<T, false>), dim3(G),
+        HIPCHK(c0, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_batch<T, DT, false>), dim3(G),
                                               dim3(COOP_THREADS), kargs, 0, c0->stream));
     for (PlanRun* r : live) r->c->last_form = fits ? 4 : 3;
     for (PlanRun* r : live)
@@ -1210,6 +1443,21 @@ dao_status run_master_batch(std::vector<PlanRun*>& live) {
         r->c->last_stop = r->c->ms_h->stop_reason;
     }
     return DAO_OK;
+}
+
+// Solves whose D_K storage differs run in separate batched launches.
+template <class T>
+dao_status run_master_batch(std::vector<PlanRun*>& live) {
+    if constexpr (std::is_same<T, float>::value) {
+        std::vector<PlanRun*> h, n;
+        for (PlanRun* r : live) (r->c->dk16 ? h : n).push_back(r);
+        if (!h.empty()) {
+            const dao_status s = run_master_batch_dt<T, __half>(h);
+            if (s != DAO_OK) return s;
+        }
+        return n.empty() ? DAO_OK : run_master_batch_dt<T, T>(n);
+    }
+    return run_master_batch_dt<T, T>(live);
 }
 
 // Several solves advanced round by round together: each round prices every
@@ -1271,6 +1519,9 @@ void dao_default_options(dao_options* o) {
     o->dose_variant = 0;
     o->gradient_depth = 4;
     o->direction = DAO_DIR_CONJUGATE;
+    o->apertures_per_round = 1;
+    o->dk_format = DAO_DFMT_NATIVE;
+    o->residual_rounds = 5;
 }
 
 const char* dao_create_error(void) { return g_create_error.c_str(); }
@@ -1315,19 +1566,25 @@ dao_status dao_create(const dao_matrix* D, const dao_beams* beams, const dao_str
     c->nnz = L->nnz;
     c->Vnz = L->Vnz;
     c->Vpad = std::max<int64_t>(L->Vpad, SLICE);
+    // the master passes walk rows in batches of Batch<DT>::ROWS: 128 with an
+    // FP16 D_K, so its padded row count is a multiple of 128 (the extra
+    // rows belong to no structure and carry no dose)
+    if (opt.dtype == DAO_F32 && opt.master == DAO_MASTER_APERTURE && opt.dk_format == DAO_DFMT_F16)
+        c->Vpad = (c->Vpad + 127) / 128 * 128;
     c->nslices = L->nslices;
     c->B = L->B;
     c->R = L->R;
     c->maxRB = L->max_rows_per_beam;
-    c->ncls = L->n_struct + 1;
+    c->ncls = int32_t(L->classes.size());
     c->sell_entries = L->slice_ptr.back();
     c->F_const = L->F_const;
     c->rows_per_beam.assign(beams->rows_per_beam, beams->rows_per_beam + beams->n_beams);
     c->row_len = L->row_len;
     c->beam_row0 = L->beam_row0;
-    if (L->Vpad < c->Vpad) {   // no non-empty row at all: keep one padding slice
+    if (L->Vpad < c->Vpad) {   // padding rows past the layout's (no non-empty row, or FP16 D_K batches)
         L->perm.resize(c->Vpad, -1);
         L->cls_int.resize(c->Vpad, uint8_t(L->n_struct));
+        if (!L->tau_int.empty()) L->tau_int.resize(c->Vpad, 0.0);
     }
     s = (c->dtype == DAO_F64) ? create_typed<double>(c.get(), *L) : create_typed<float>(c.get(), *L);
     if (s != DAO_OK) {
@@ -1364,6 +1621,8 @@ dao_status dao_info(const dao_ctx* c, dao_info_t* o) {
     o->gradient_depth = c->gradT_pf;
     o->last_master_form = c->last_form;
     o->onchip_lds_bytes = c->coop_lds_max;
+    o->dk_format = c->dk16 ? DAO_DFMT_F16 : DAO_DFMT_NATIVE;
+    o->residual_reprices = c->reprices;
     // stored bytes per value: the ctx type, or 16 bits (+ 16 for the residual)
     const bool narrow = c->opt.d_format != DAO_DFMT_NATIVE;
     const int64_t vs = narrow ? 2 + (c->opt.d_residual ? 2 : 0) : ts;
@@ -1408,23 +1667,7 @@ dao_status dao_add_aperture(dao_ctx* c, int32_t beam, const int16_t* leaves) {
     if (!c) return DAO_EINVAL;
     dao_status s = check_aperture(c, beam, leaves);
     if (s != DAO_OK) return s;
-    if (c->K >= c->opt.max_apertures) return c->fail(DAO_ESTATE, "pool capacity reached");
-    const int nr = c->rows_per_beam[beam];
-    for (int i = 0; i < c->maxRB; ++i) {
-        c->lv_stage_h[2 * i] = i < nr ? leaves[2 * i] : int16_t(0);
-        c->lv_stage_h[2 * i + 1] = i < nr ? leaves[2 * i + 1] : int16_t(0);
-    }
-    HIPCHK(c, hipMemcpyAsync(c->ap_lv + size_t(c->K) * c->maxRB * 2, c->lv_stage_h,
-                             size_t(c->maxRB) * 4, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->ap_beam + c->K, &beam, 4, hipMemcpyHostToDevice, c->stream));
-    k_fill<double><<<1, 64, 0, c->stream>>>(c->y + c->K, 1, 0.0);
-    LAUNCHCHK(c);
-    s = c->dtype == DAO_F64 ? build_dk_column<double>(c, c->K) : build_dk_column<float>(c, c->K);
-    if (s != DAO_OK) return s;
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    mirror_add(c, beam, leaves);
-    c->K += 1;
-    return DAO_OK;
+    return add_aperture_host(c, beam, leaves);
 }
 
 dao_status dao_master_step(dao_ctx* c, double* F, double* kkt, double* step) {
@@ -1468,7 +1711,9 @@ dao_status dao_get_dose(dao_ctx* c, double* d_dev, double* F) {
     if (!c) return DAO_EINVAL;
     if (d_dev) {
         k_fill<double><<<c->elem_blocks(c->V), BLOCK, 0, c->stream>>>(d_dev, c->V, 0.0);
-        k_scatter<double, double><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(c->d, c->perm, c->Vpad, d_dev);
+        // the master keeps d - tau: add the shifts back
+        k_scatter_shift<<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(c->d, c->tau_int, c->perm, c->Vpad,
+                                                                          d_dev);
         LAUNCHCHK(c);
     }
     HIPCHK(c, hipMemcpyAsync(c->ms_h, c->ms, sizeof(MasterState), hipMemcpyDeviceToHost, c->stream));

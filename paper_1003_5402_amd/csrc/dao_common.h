@@ -14,12 +14,17 @@ constexpr int LS_MAX_ITER = 60;       // line-search evaluations per master step
 constexpr int BLOCK = 256;            // threads per block of the streaming kernels
 constexpr int NPART = 6;              // doubles per block in a reduction record
 
-// Per-structure objective coefficients (eq. 9 and eq. 10).  a and b are the
-// structure weights already divided by the structure size; the class index
-// n_struct (one past the last structure) is "no structure": all zero.
+// Objective coefficients of a voxel class (eq. 9 and eq. 10): the terms of
+// its first structure and, for a voxel in two overlapping structures, of its
+// second (zero weights when there is none).  a and b are the structure
+// weights already divided by the structure size.  Classes 0 .. n_struct - 1
+// are the single structures, class n_struct is "no structure" (all zero),
+// later classes are pairs of structures.
 struct ObjClass {
     double a, t_under, b, t_over;
+    double a2, t_under2, b2, t_over2;
 };
+constexpr int MAX_CLASSES = 256;
 
 // Phases of one gradient-projection step (the master loop is a fixed
 // sequence of launches; each launch runs only in its phase).

@@ -50,15 +50,21 @@ struct Arrival {
 // small helpers
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double grad_f(const ObjClass& c, double z) {
-    // dF/dz of eq. 9 + eq. 10 for one voxel
-    return -2.0 * c.a * fmax(0.0, c.t_under - z) + 2.0 * c.b * fmax(0.0, z - c.t_over);
+    // dF/dz of eq. 9 + eq. 10 for one voxel (both structures' terms)
+    return -2.0 * c.a * fmax(0.0, c.t_under - z) + 2.0 * c.b * fmax(0.0, z - c.t_over) -
+           2.0 * c.a2 * fmax(0.0, c.t_under2 - z) + 2.0 * c.b2 * fmax(0.0, z - c.t_over2);
 }
 
 __device__ __forceinline__ double obj_f(const ObjClass& c, double z) {
     const double un = fmax(0.0, c.t_under - z);
     const double ov = fmax(0.0, z - c.t_over);
-    return c.a * un * un + c.b * ov * ov;
+    const double un2 = fmax(0.0, c.t_under2 - z);
+    const double ov2 = fmax(0.0, z - c.t_over2);
+    return c.a * un * un + c.b * ov * ov + c.a2 * un2 * un2 + c.b2 * ov2 * ov2;
 }
+
+// Per-voxel threshold shift of internal row r (0 without shifts).
+__device__ __forceinline__ double tau_at(const double* tau, int64_t r) { return tau ? tau[r] : 0.0; }
 
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -191,24 +197,36 @@ __device__ __forceinline__ void ls_breakpoints(const ObjClass& c, double d, doub
     bo = (c.b > 0.0 && q != 0.0) ? (c.t_over - d) / q : NAN;
 }
 
-// Line-search sums of one voxel at t, with its breakpoints given.
-__device__ __forceinline__ void ls_voxel_bp(const ObjClass& c, double d, double q, double bu, double bo, double t,
-                                            Rec& r) {
-    const double z = d + t * q;
-    r.s0 += q * grad_f(c, z);
-    const bool ua = c.a > 0.0, ob = c.b > 0.0;
-    const bool under_r = ua && ((z < c.t_under) || (z == c.t_under && q < 0.0));
-    const bool over_r = ob && ((z > c.t_over) || (z == c.t_over && q > 0.0));
-    const bool under_l = ua && ((z < c.t_under) || (z == c.t_under && q > 0.0));
-    const bool over_l = ob && ((z > c.t_over) || (z == c.t_over && q < 0.0));
-    const double q2 = q * q;
-    r.s1 += q2 * ((under_r ? c.a : 0.0) + (over_r ? c.b : 0.0));
-    r.s2 += q2 * ((under_l ? c.a : 0.0) + (over_l ? c.b : 0.0));
+// Curvature flags and breakpoints of one (a, T-, b, T+) term at z = d + t q.
+__device__ __forceinline__ void ls_term(double a, double tu, double b, double to, double z, double q,
+                                        double q2, double bu, double bo, double t, Rec& r) {
+    const bool ua = a > 0.0, ob = b > 0.0;
+    const bool under_r = ua && ((z < tu) || (z == tu && q < 0.0));
+    const bool over_r = ob && ((z > to) || (z == to && q > 0.0));
+    const bool under_l = ua && ((z < tu) || (z == tu && q > 0.0));
+    const bool over_l = ob && ((z > to) || (z == to && q < 0.0));
+    r.s1 += q2 * ((under_r ? a : 0.0) + (over_r ? b : 0.0));
+    r.s2 += q2 * ((under_l ? a : 0.0) + (over_l ? b : 0.0));
     // comparisons with NaN are false: absent breakpoints never count
     if (bu > t) r.mn = fmin(r.mn, bu);
     if (bu < t) r.mx = fmax(r.mx, bu);
     if (bo > t) r.mn = fmin(r.mn, bo);
     if (bo < t) r.mx = fmax(r.mx, bo);
+}
+
+// Line-search sums of one voxel at t, with the first structure's
+// breakpoints given (a second structure's are computed here).
+__device__ __forceinline__ void ls_voxel_bp(const ObjClass& c, double d, double q, double bu, double bo, double t,
+                                            Rec& r) {
+    const double z = d + t * q;
+    r.s0 += q * grad_f(c, z);
+    const double q2 = q * q;
+    ls_term(c.a, c.t_under, c.b, c.t_over, z, q, q2, bu, bo, t, r);
+    if (c.a2 > 0.0 || c.b2 > 0.0) {
+        const double bu2 = (c.a2 > 0.0 && q != 0.0) ? (c.t_under2 - d) / q : NAN;
+        const double bo2 = (c.b2 > 0.0 && q != 0.0) ? (c.t_over2 - d) / q : NAN;
+        ls_term(c.a2, c.t_under2, c.b2, c.t_over2, z, q, q2, bu2, bo2, t, r);
+    }
 }
 
 __device__ __forceinline__ void ls_voxel(const ObjClass& c, double d, double q, double t, Rec& r) {
@@ -504,13 +522,15 @@ template <class VT, bool LO = false>
 __global__ void __launch_bounds__(SLAB_THREADS) k_dose_exact(SellView<VT> S, int64_t Vpad,
                                                              const double* __restrict__ x64, int N, bool stage,
                                                              const float* __restrict__ scale,
+                                                             const double* __restrict__ tau,
                                                              double* __restrict__ d) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double s_part[KSPLIT * SLAB];
     const double sum =
         slab_rows_x<VT, double, double, LO>(S, x64, N, reinterpret_cast<double*>(smem), stage, scale, s_part);
     const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
-    if (threadIdx.x < SLAB && row < Vpad) d[row] = sum;
+    // the master keeps the dose minus the per-voxel threshold shift
+    if (threadIdx.x < SLAB && row < Vpad) d[row] = sum - tau_at(tau, row);
 }
 
 template <class T>
@@ -518,6 +538,28 @@ __global__ void k_fill(T* __restrict__ p, int64_t n, T v) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * blockDim.x)
         p[i] = v;
+}
+
+// out[i] = |in[i]|.
+__global__ void k_abs_copy(const double* __restrict__ in, int64_t n, double* __restrict__ out) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        out[i] = fabs(in[i]);
+}
+
+// d[r] = -tau[r] (0 without shifts): the master's shifted form of zero dose.
+__global__ void k_neg_or_zero(const double* __restrict__ tau, int64_t n, double* __restrict__ d) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        d[i] = -tau_at(tau, i);
+}
+
+// out[perm[r]] = in[r] + tau[r] for internal rows (caller order): the dose
+// from the master's shifted dose, after a fill of out.
+__global__ void k_scatter_shift(const double* __restrict__ in, const double* __restrict__ tau,
+                                const int32_t* __restrict__ perm, int64_t n, double* __restrict__ out) {
+    for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < n; r += int64_t(gridDim.x) * blockDim.x) {
+        const int32_t j = perm[r];
+        if (j >= 0) out[j] = in[r] + tau_at(tau, r);
+    }
 }
 
 // out[perm[r]] = in[r] for internal rows (caller order), after a fill of out.
@@ -532,14 +574,16 @@ __global__ void k_scatter(const TI* __restrict__ in, const int32_t* __restrict__
 }
 
 // F over every caller voxel (eq. 9 + eq. 10); the last block writes *F_out.
+// tau_ext: per-voxel threshold shifts in caller order (null: none).
 template <class T>
 __global__ void __launch_bounds__(BLOCK) k_objective_ext(const T* __restrict__ d_ext,
                                                          const uint8_t* __restrict__ cls, int64_t V,
                                                          const ObjClass* __restrict__ classes,
+                                                         const double* __restrict__ tau_ext,
                                                          Rec* parts, Arrival* arr, double* F_out) {
     Rec r = rec_identity();
     for (int64_t j = int64_t(blockIdx.x) * BLOCK + threadIdx.x; j < V; j += int64_t(gridDim.x) * BLOCK)
-        r.s5 += obj_f(classes[cls[j]], double(d_ext[j]));
+        r.s5 += obj_f(classes[cls[j]], double(d_ext[j]) - tau_at(tau_ext, j));
     Rec tot;
     const Rec mine = block_reduce(r);
     if (arrive_and_reduce(mine, parts, arr, &tot) && threadIdx.x == 0) *F_out = tot.s5;
@@ -549,11 +593,12 @@ __global__ void __launch_bounds__(BLOCK) k_objective_ext(const T* __restrict__ d
 template <class T>
 __global__ void k_gather_grad(const T* __restrict__ d_ext, const int32_t* __restrict__ perm,
                               const uint8_t* __restrict__ cls, int64_t Vpad,
-                              const ObjClass* __restrict__ classes, T* __restrict__ u) {
+                              const ObjClass* __restrict__ classes, const double* __restrict__ tau_int,
+                              T* __restrict__ u) {
     for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < Vpad;
          r += int64_t(gridDim.x) * blockDim.x) {
         const int32_t j = perm[r];
-        u[r] = j >= 0 ? T(grad_f(classes[cls[r]], double(d_ext[j]))) : T(0);
+        u[r] = j >= 0 ? T(grad_f(classes[cls[r]], double(d_ext[j]) - tau_at(tau_int, r))) : T(0);
     }
 }
 
@@ -1156,6 +1201,7 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_update(SellView<T> S, int64_t 
                                                          double* __restrict__ d, const T* __restrict__ q,
                                                          const uint8_t* __restrict__ cls,
                                                          const ObjClass* __restrict__ classes, int ncls,
+                                                         const double* __restrict__ tau,
                                                          T* __restrict__ u, Rec* upd_parts,
                                                          const MasterState* ms) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1180,7 +1226,7 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_update(SellView<T> S, int64_t 
     Rec r = rec_identity();
     const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
     if (threadIdx.x < SLAB && row < Vpad) {
-        if (!s_refresh) dn = d[row] + s_t * double(q[row]);
+        dn = s_refresh ? dn - tau_at(tau, row) : d[row] + s_t * double(q[row]);
         d[row] = dn;
         const ObjClass c = cl[cls[row]];
         u[row] = T(grad_f(c, dn));

@@ -38,6 +38,15 @@ struct Vec16<double> {
     using type = double2;
     static constexpr int n = 2;
 };
+// FP16 storage of D_K (values over one global scale): 8 slots per vector
+struct alignas(16) half8 {
+    __half2 h[4];
+};
+template <>
+struct Vec16<__half> {
+    using type = half8;
+    static constexpr int n = 8;
+};
 
 template <class T>
 struct DKG {
@@ -50,6 +59,10 @@ __device__ __forceinline__ double vget(const float4& v, int e) {
     return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
 }
 __device__ __forceinline__ double vget(const double2& v, int e) { return e == 0 ? v.x : v.y; }
+__device__ __forceinline__ double vget(const half8& v, int e) {
+    const __half2 p = v.h[e >> 1];
+    return double((e & 1) ? __high2float(p) : __low2float(p));
+}
 
 template <class V>
 __device__ __forceinline__ V vzero();
@@ -60,6 +73,13 @@ __device__ __forceinline__ float4 vzero<float4>() {
 template <>
 __device__ __forceinline__ double2 vzero<double2>() {
     return make_double2(0.0, 0.0);
+}
+template <>
+__device__ __forceinline__ half8 vzero<half8>() {
+    half8 z;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) z.h[i] = __float2half2_rn(0.0f);
+    return z;
 }
 
 // Order LDS traffic between lanes of one wavefront (used inside loops whose
@@ -95,17 +115,22 @@ __global__ void k_ap_indicator(PoolView P, int k, T* __restrict__ ind) {
     }
 }
 
-// Column k of D_K: dk[row * KS + k] = (D ind)_row, FP64 sums rounded to T.
-template <class T, class VT = T, bool LO = false>
+// Column k of D_K: dk[row * KS + k] = (D ind)_row, FP64 sums rounded to the
+// storage type DT (T, or FP16 of the sum times inv_scale).
+__device__ __forceinline__ void dk_store(float* p, double v, double) { *p = float(v); }
+__device__ __forceinline__ void dk_store(double* p, double v, double) { *p = v; }
+__device__ __forceinline__ void dk_store(__half* p, double v, double inv) { *p = __float2half_rn(float(v * inv)); }
+
+template <class T, class VT = T, bool LO = false, class DT = T>
 __global__ void __launch_bounds__(SLAB_THREADS) k_dk_column(SellView<VT> S, int64_t Vpad,
                                                             const T* __restrict__ ind, int N, bool stage,
                                                             const float* __restrict__ scale, int k,
-                                                            T* __restrict__ dk) {
+                                                            DT* __restrict__ dk, double inv_dk_scale) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double s_part[KSPLIT * SLAB];
     const double sum = slab_rows_x<VT, T, double, LO>(S, ind, N, reinterpret_cast<T*>(smem), stage, scale, s_part);
     const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
-    if (threadIdx.x < SLAB && row < Vpad) dk[row * KS + k] = T(sum);
+    if (threadIdx.x < SLAB && row < Vpad) dk_store(dk + row * KS + k, sum, inv_dk_scale);
 }
 
 // Rows are processed in batches of BATCH = ITERS * RPW consecutive rows per
@@ -117,21 +142,24 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_dk_column(SellView<VT> S, int6
 template <class T>
 struct Batch {
     static constexpr int ITERS = 16;
-    static constexpr int ROWS = ITERS * DKG<T>::RPW;   // 64 (FP32) or 32 (FP64)
+    static constexpr int ROWS = ITERS * DKG<T>::RPW;   // 64 (FP32), 32 (FP64) or 128 (FP16 storage)
 };
 
 // Update pass (PH_UPD).  Record of workgroup b in parts2[b * (KS + 1)]:
 // [objective partial, grad_y partial for apertures 0..KS-1].
-template <class T>
-__global__ void __launch_bounds__(BLOCK) k_upd_ap(const T* __restrict__ dk, int64_t Vpad,
+// DT: D_K storage (T, or FP16 of D_K / dk_scale); the products multiply back
+// by dk_scale (exactly 1 for T storage).
+template <class T, class DT = T>
+__global__ void __launch_bounds__(BLOCK) k_upd_ap(const DT* __restrict__ dk, double dk_scale, int64_t Vpad,
                                                   double* __restrict__ d, const T* __restrict__ q,
                                                   const uint8_t* __restrict__ cls,
                                                   const ObjClass* __restrict__ classes, int ncls,
                                                   const double* __restrict__ y, double* __restrict__ parts2,
-                                                  const MasterState* ms, ProfCounters* pc, int64_t Vnz) {
-    using G = DKG<T>;
-    using V = typename Vec16<T>::type;
-    constexpr int IT = Batch<T>::ITERS, ROWS = Batch<T>::ROWS;
+                                                  const MasterState* ms, ProfCounters* pc, int64_t Vnz,
+                                                  const double* __restrict__ tau) {
+    using G = DKG<DT>;
+    using V = typename Vec16<DT>::type;
+    constexpr int IT = Batch<DT>::ITERS, ROWS = Batch<DT>::ROWS;
     constexpr int NW = BLOCK / WAVE;
     __shared__ int s_skip, s_mode, s_K;
     __shared__ double s_t;
@@ -165,7 +193,7 @@ __global__ void __launch_bounds__(BLOCK) k_upd_ap(const T* __restrict__ dk, int6
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
         const int k = c * G::EPL + e;
-        yv[e] = (mode == 1 && k < K) ? y[k] : 0.0;
+        yv[e] = (mode == 1 && k < K) ? y[k] * dk_scale : 0.0;
     }
     double acc[G::EPL];
 #pragma unroll
@@ -198,7 +226,7 @@ __global__ void __launch_bounds__(BLOCK) k_upd_ap(const T* __restrict__ dk, int6
             const int64_t row = base + lane;
             double dn;
             if (mode == 1) {
-                dn = su[lane];
+                dn = su[lane] - tau_at(tau, row);   // the master keeps d - tau
             } else {
                 dn = d[row];
                 if (mode == 0) dn = dn + t * double(q[row]);
@@ -225,7 +253,7 @@ __global__ void __launch_bounds__(BLOCK) k_upd_ap(const T* __restrict__ dk, int6
         for (int e = 0; e < G::EPL; ++e) acc[e] += __shfl_xor(acc[e], off, WAVE);
     if (rg == 0)
 #pragma unroll
-        for (int e = 0; e < G::EPL; ++e) s_acc[wave][c * G::EPL + e] = acc[e];
+        for (int e = 0; e < G::EPL; ++e) s_acc[wave][c * G::EPL + e] = acc[e] * dk_scale;
     Fp = wave_sum(Fp);
     if (lane == 0) s_F[wave] = Fp;
     __syncthreads();
@@ -363,17 +391,17 @@ __device__ __forceinline__ void finish_step_ap(MasterState& m, double* y, const 
 }
 
 // q = D_K p and the first line-search evaluation (PH_Q).
-template <class T>
-__global__ void __launch_bounds__(BLOCK) k_qstep_ap(const T* __restrict__ dk, int64_t Vpad,
+template <class T, class DT = T>
+__global__ void __launch_bounds__(BLOCK) k_qstep_ap(const DT* __restrict__ dk, double dk_scale, int64_t Vpad,
                                                     const double* __restrict__ d,
                                                     const uint8_t* __restrict__ cls,
                                                     const ObjClass* __restrict__ classes, int ncls,
                                                     T* __restrict__ q, Rec* parts, Arrival* arr,
                                                     MasterState* ms, double* y, const double* p,
                                                     ProfCounters* pc, int64_t Vnz) {
-    using G = DKG<T>;
-    using V = typename Vec16<T>::type;
-    constexpr int IT = Batch<T>::ITERS, ROWS = Batch<T>::ROWS;
+    using G = DKG<DT>;
+    using V = typename Vec16<DT>::type;
+    constexpr int IT = Batch<DT>::ITERS, ROWS = Batch<DT>::ROWS;
     constexpr int NW = BLOCK / WAVE;
     __shared__ int s_skip, s_K;
     __shared__ double s_t;
@@ -402,7 +430,7 @@ __global__ void __launch_bounds__(BLOCK) k_qstep_ap(const T* __restrict__ dk, in
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
         const int k = c * G::EPL + e;
-        pv[e] = k < K ? p[k] : 0.0;
+        pv[e] = k < K ? p[k] * dk_scale : 0.0;
     }
     Rec r = rec_identity();
     double* sq = s_q[wave];

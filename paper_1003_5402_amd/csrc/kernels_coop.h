@@ -239,7 +239,8 @@ struct LsRegs {
 
 template <class T>
 struct CoopArgs {
-    const T* dk;
+    const void* dk;     // D_K rows of KS slots, storage type DT of the kernel
+    double dk_scale;    // D_K = dk_scale * stored value (1 unless stored in FP16)
     int64_t Vpad, Vnz;
     double* d;
     T* q;
@@ -250,6 +251,7 @@ struct CoopArgs {
     double* p;          // out: last direction (workgroup 0)
     double* grad;       // out: last grad_y (workgroup 0)
     CgMem* cgm;         // in/out: conjugate-direction memory (with p: the last step's direction)
+    const double* tau;  // per-voxel threshold shifts by internal row (null: none)
     MasterState* ms;    // in: state set by k_master_init_ap; out: final state (workgroup 0)
     double* recs;       // [2][workgroups of the solve][RECW]
     CoopSync* sync;
@@ -280,11 +282,13 @@ __host__ __device__ inline size_t coop_lds_bytes(int64_t rows, int nc) {
 // LDSRES: the workgroup copies its rows of D_K, d, q and the classes into
 // LDS once per solve and every pass reads on-chip memory; d is written back
 // at the end.  Otherwise the passes stream them from global memory.
-template <class T, bool LDSRES>
+template <class T, class DT, bool LDSRES>
 __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t gb, const uint32_t gn) {
-    using G = DKG<T>;
-    using V = typename Vec16<T>::type;
-    constexpr int IT = Batch<T>::ITERS, ROWS = Batch<T>::ROWS;
+    using G = DKG<DT>;
+    using V = typename Vec16<DT>::type;
+    constexpr int IT = Batch<DT>::ITERS, ROWS = Batch<DT>::ROWS;
+    const DT* dk = static_cast<const DT*>(A.dk);
+    const double dks = A.dk_scale;
     constexpr int NW = COOP_THREADS / WAVE;
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ MasterState s_ms;
@@ -318,7 +322,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     const int nc = (K + G::EPL - 1) / G::EPL;
     // this workgroup's batches of ROWS rows
     const int64_t nbat = A.Vpad / ROWS;
-    const int64_t per = coop_batches_per_group<T>(A.Vpad, gn);
+    const int64_t per = coop_batches_per_group<DT>(A.Vpad, gn);
     const int64_t bat0 = min(nbat, int64_t(gb) * per), bat1 = min(nbat, bat0 + per);
     const int64_t r0 = bat0 * ROWS, nrows = (bat1 - bat0) * ROWS;
     // on-chip copies (LDSRES)
@@ -332,7 +336,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     if (LDSRES) {
         for (int64_t idx = threadIdx.x; idx < nrows * nc; idx += blockDim.x) {
             const int64_t rr = idx / nc;
-            dkl[rr * ncp + (idx - rr * nc)] = reinterpret_cast<const V*>(A.dk + (r0 + rr) * KS)[idx - rr * nc];
+            dkl[rr * ncp + (idx - rr * nc)] = reinterpret_cast<const V*>(dk + (r0 + rr) * KS)[idx - rr * nc];
         }
         for (int64_t rr = threadIdx.x; rr < nrows; rr += blockDim.x) {
             dl[rr] = A.d[r0 + rr];
@@ -342,7 +346,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
         __syncthreads();
     }
     auto dk_vec = [&](int64_t row) -> V {
-        return LDSRES ? dkl[(row - r0) * ncp + c] : reinterpret_cast<const V*>(A.dk + row * KS)[c];
+        return LDSRES ? dkl[(row - r0) * ncp + c] : reinterpret_cast<const V*>(dk + row * KS)[c];
     };
     auto d_at = [&](int64_t row) -> double& { return LDSRES ? dl[row - r0] : A.d[row]; };
     auto q_at = [&](int64_t row) -> T& { return LDSRES ? ql[row - r0] : A.q[row]; };
@@ -388,7 +392,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
 #pragma unroll
             for (int e = 0; e < G::EPL; ++e) {
                 const int k = c * G::EPL + e;
-                yv[e] = (mode == 1 && k < K) ? s_y[k] : 0.0;
+                yv[e] = (mode == 1 && k < K) ? s_y[k] * dks : 0.0;
                 acc[e] = 0.0;
             }
             double Fp = 0.0;
@@ -429,7 +433,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                     const int64_t row = base + lane;
                     double dn;
                     if (mode == 1) {
-                        dn = su[lane];
+                        dn = su[lane] - tau_at(A.tau, row);   // the master keeps d - tau
                     } else {
                         dn = d_at(row);
                         if (mode == 0) dn = dn + t * double(q_at(row));
@@ -454,7 +458,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                 for (int e = 0; e < G::EPL; ++e) acc[e] += __shfl_xor(acc[e], off, WAVE);
             if (rg == 0)
 #pragma unroll
-                for (int e = 0; e < G::EPL; ++e) s_acc[wave][1 + c * G::EPL + e] = acc[e];
+                for (int e = 0; e < G::EPL; ++e) s_acc[wave][1 + c * G::EPL + e] = acc[e] * dks;
             Fp = wave_reduce_dpp<0>(Fp);
             if (lane == 0) s_acc[wave][0] = Fp;
             __syncthreads();
@@ -537,7 +541,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             Rec r = rec_identity();
             double pv[G::EPL];
 #pragma unroll
-            for (int e = 0; e < G::EPL; ++e) pv[e] = s_p[c * G::EPL + e];
+            for (int e = 0; e < G::EPL; ++e) pv[e] = s_p[c * G::EPL + e] * dks;
             double* sq = s_u[wave];
             if (LDSRES) {
                 // one row per thread, straight from LDS; q's per-slot partials
@@ -556,7 +560,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                             if (j < nc) {
                                 const V v = rp[j];
 #pragma unroll
-                                for (int e = 0; e < G::EPL; ++e) part += vget(v, e) * s_p[j * G::EPL + e];
+                                for (int e = 0; e < G::EPL; ++e) part += vget(v, e) * (s_p[j * G::EPL + e] * dks);
                             }
                             return part;
                         };
@@ -699,16 +703,16 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
 }
 
 // One master solve per launch: every workgroup of the grid works on it.
-template <class T, bool LDSRES>
+template <class T, class DT, bool LDSRES>
 __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
-    master_body<T, LDSRES>(A, blockIdx.x, gridDim.x);
+    master_body<T, DT, LDSRES>(A, blockIdx.x, gridDim.x);
 }
 
 // Several master solves in one cooperative launch: solve i gets workgroups
 // [gstart[i], gstart[i + 1]) and runs exactly as k_master_coop would on a grid
 // of that size; solves never wait for each other, and the launch ends when
 // the last one has converged.
-template <class T, bool LDSRES>
+template <class T, class DT, bool LDSRES>
 __global__ void __launch_bounds__(COOP_THREADS) k_master_batch(const CoopArgs<T>* __restrict__ args,
                                                                const int32_t* __restrict__ gstart, int nsolves) {
     __shared__ int s_i;
@@ -722,7 +726,7 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_batch(const CoopArgs<T>
     const uint32_t g0 = uint32_t(gstart[i]), g1 = uint32_t(gstart[i + 1]);
     if (blockIdx.x >= g1) return;   // workgroups past the last solve (none when the host fills the grid)
     const CoopArgs<T> A = args[i];
-    master_body<T, LDSRES>(A, blockIdx.x - g0, g1 - g0);
+    master_body<T, DT, LDSRES>(A, blockIdx.x - g0, g1 - g0);
 }
 
 }  // namespace dao

@@ -3,7 +3,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <numeric>
+#include <set>
 #include <sstream>
 
 namespace dao {
@@ -108,9 +110,16 @@ dao_status validate_inputs(const dao_matrix* D, const dao_beams* beams,
         return fail("gradient_depth must be 4, 8 or 16");
     if (opt->direction != DAO_DIR_STEEPEST && opt->direction != DAO_DIR_CONJUGATE)
         return fail("direction must be DAO_DIR_STEEPEST or DAO_DIR_CONJUGATE");
+    if (opt->apertures_per_round < 1 || opt->apertures_per_round > 16)
+        return fail("apertures_per_round must be in [1, 16]");
+    if (opt->dk_format != DAO_DFMT_NATIVE && opt->dk_format != DAO_DFMT_F16)
+        return fail("dk_format must be DAO_DFMT_NATIVE or DAO_DFMT_F16");
+    if (opt->dk_format == DAO_DFMT_F16 && (opt->dtype != DAO_F32 || opt->master != DAO_MASTER_APERTURE))
+        return fail("an FP16 aperture dose matrix needs dtype DAO_F32 and the aperture-matrix master");
     if (opt->d_format < DAO_DFMT_NATIVE || opt->d_format > DAO_DFMT_BF16)
         return fail("d_format must be DAO_DFMT_NATIVE, DAO_DFMT_F16 or DAO_DFMT_BF16");
-    if (opt->d_residual != 0 && opt->d_residual != 1) return fail("d_residual must be 0 or 1");
+    if (opt->d_residual < 0 || opt->d_residual > 2) return fail("d_residual must be 0, 1 or 2");
+    if (opt->residual_rounds < 0) return fail("residual_rounds must be >= 0");
     if (opt->d_format != DAO_DFMT_NATIVE) {
         if (opt->dtype != DAO_F32) return fail("a 16-bit d_format needs dtype DAO_F32");
         if (opt->master != DAO_MASTER_APERTURE) return fail("a 16-bit d_format needs the aperture-matrix master");
@@ -161,6 +170,24 @@ dao_status validate_inputs(const dao_matrix* D, const dao_beams* beams,
         int s = structs->vox_struct[j];
         if (s < -1 || s >= structs->n_struct) return fail(cat("structure id out of range at voxel ", j));
     }
+    if (structs->vox_struct2) {
+        std::set<std::pair<int, int>> pairs;
+        for (int64_t j = 0; j < D->n_vox; ++j) {
+            const int s2 = structs->vox_struct2[j];
+            if (s2 < -1 || s2 >= structs->n_struct) return fail(cat("second structure id out of range at voxel ", j));
+            if (s2 < 0) continue;
+            const int s1 = structs->vox_struct[j];
+            if (s1 < 0) return fail(cat("voxel ", j, " has a second structure but no first"));
+            if (s1 == s2) return fail(cat("voxel ", j, " lists the same structure twice"));
+            pairs.insert({s1, s2});
+        }
+        if (int64_t(structs->n_struct) + 1 + int64_t(pairs.size()) > MAX_CLASSES)
+            return fail("more than 255 distinct structures and structure pairs");
+    }
+    if (structs->vox_shift) {
+        for (int64_t j = 0; j < D->n_vox; ++j)
+            if (!std::isfinite(structs->vox_shift[j])) return fail(cat("non-finite threshold shift at voxel ", j));
+    }
     for (int s = 0; s < structs->n_struct; ++s) {
         const dao_prescription& p = presc[s];
         if (!std::isfinite(p.t_under) || !std::isfinite(p.t_over) || !std::isfinite(p.w_under) ||
@@ -182,26 +209,53 @@ void build_layout(const dao_matrix* D, const dao_beams* beams, const dao_structu
     L->n_struct = structs->n_struct;
 
     // --- objective classes (eq. 9 and eq. 10) ------------------------------
-    std::vector<int64_t> size(structs->n_struct, 0);
-    for (int64_t j = 0; j < V; ++j)
-        if (structs->vox_struct[j] >= 0) size[structs->vox_struct[j]]++;
-    L->classes.assign(structs->n_struct + 1, ObjClass{0, 0, 0, 0});
-    for (int s = 0; s < structs->n_struct; ++s) {
-        if (size[s] == 0) continue;
-        const dao_prescription& p = presc[s];
-        ObjClass c{0, 0, 0, 0};
-        if (p.is_target) {
-            c.a = p.w_under / double(size[s]);
-            c.t_under = p.t_under;
-        }
-        c.b = p.w_over / double(size[s]);
-        c.t_over = p.t_over;
-        L->classes[s] = c;
+    // |v_s| counts the voxels carrying s as first or second label; pairs of
+    // overlapping structures get classes of their own after "none"
+    const int ns = structs->n_struct;
+    const int16_t* l1 = structs->vox_struct;
+    const int16_t* l2 = structs->vox_struct2;
+    std::vector<int64_t> size(ns, 0);
+    for (int64_t j = 0; j < V; ++j) {
+        if (l1[j] >= 0) size[l1[j]]++;
+        if (l2 && l2[j] >= 0) size[l2[j]]++;
     }
-    const uint8_t none = uint8_t(structs->n_struct);
+    // the terms of structure s: (a, T-, b, T+), zero weights when empty
+    auto terms = [&](int st, double* a, double* tu, double* b, double* to) {
+        *a = *tu = *b = *to = 0.0;
+        if (st < 0 || size[st] == 0) return;
+        const dao_prescription& p = presc[st];
+        if (p.is_target) {
+            *a = p.w_under / double(size[st]);
+            *tu = p.t_under;
+        }
+        *b = p.w_over / double(size[st]);
+        *to = p.t_over;
+    };
+    const ObjClass zero{0, 0, 0, 0, 0, 0, 0, 0};
+    L->classes.assign(ns + 1, zero);
+    for (int st = 0; st < ns; ++st) {
+        ObjClass& c = L->classes[st];
+        terms(st, &c.a, &c.t_under, &c.b, &c.t_over);
+    }
+    const uint8_t none = uint8_t(ns);
     L->cls_ext.resize(V);
-    for (int64_t j = 0; j < V; ++j)
-        L->cls_ext[j] = structs->vox_struct[j] < 0 ? none : uint8_t(structs->vox_struct[j]);
+    std::map<std::pair<int, int>, int> pair_class;
+    for (int64_t j = 0; j < V; ++j) {
+        int cl = l1[j] < 0 ? int(none) : int(l1[j]);
+        if (l2 && l2[j] >= 0) {
+            const auto key = std::make_pair(int(l1[j]), int(l2[j]));
+            auto it = pair_class.find(key);
+            if (it == pair_class.end()) {
+                ObjClass c = zero;
+                terms(key.first, &c.a, &c.t_under, &c.b, &c.t_over);
+                terms(key.second, &c.a2, &c.t_under2, &c.b2, &c.t_over2);
+                it = pair_class.emplace(key, int(L->classes.size())).first;
+                L->classes.push_back(c);
+            }
+            cl = it->second;
+        }
+        L->cls_ext[j] = uint8_t(cl);
+    }
 
     // --- internal row order: non-empty rows, sorted by length (descending)
     //     inside windows so that slices carry little padding ---------------
@@ -226,15 +280,25 @@ void build_layout(const dao_matrix* D, const dao_beams* beams, const dao_structu
     L->cls_int.assign(L->Vpad, none);
     for (int64_t r = 0; r < L->Vnz; ++r) L->cls_int[r] = L->cls_ext[L->perm[r]];
 
-    // objective of voxels that no beamlet reaches (their dose is always 0)
+    // per-voxel threshold shifts: caller order and internal row order
+    // (padding rows 0)
+    if (structs->vox_shift) {
+        L->tau_ext.assign(structs->vox_shift, structs->vox_shift + V);
+        L->tau_int.assign(L->Vpad, 0.0);
+        for (int64_t r = 0; r < L->Vnz; ++r) L->tau_int[r] = structs->vox_shift[L->perm[r]];
+    }
+
+    // objective of voxels that no beamlet reaches (their dose is always 0;
+    // with shifted thresholds the terms see 0 - tau_j against unshifted ones)
     {
         double acc = 0.0;
         for (int64_t j = 0; j < V; ++j) {
             if (rp[j + 1] > rp[j]) continue;
             const ObjClass& c = L->classes[L->cls_ext[j]];
-            double un = std::max(0.0, c.t_under);
-            double ov = std::max(0.0, -c.t_over);
-            acc += c.a * un * un + c.b * ov * ov;
+            const double z = structs->vox_shift ? -structs->vox_shift[j] : 0.0;
+            const double un = std::max(0.0, c.t_under - z), ov = std::max(0.0, z - c.t_over);
+            const double un2 = std::max(0.0, c.t_under2 - z), ov2 = std::max(0.0, z - c.t_over2);
+            acc += c.a * un * un + c.b * ov * ov + c.a2 * un2 * un2 + c.b2 * ov2 * ov2;
         }
         L->F_const = acc;
     }

@@ -38,8 +38,12 @@ struct HostLayout {
     // objective classes
     std::vector<uint8_t> cls_int;     // [Vpad] class of each internal row
     std::vector<uint8_t> cls_ext;     // [V] class of each caller voxel
-    std::vector<ObjClass> classes;    // [n_struct + 1]
+    std::vector<ObjClass> classes;    // [n_struct + 1 + structure pairs]
     double F_const = 0.0;             // objective of unreachable voxels at dose 0
+    // per-voxel threshold shifts (empty when none): the master keeps the
+    // shifted dose d - tau in internal row order
+    std::vector<double> tau_ext;      // [V] caller order
+    std::vector<double> tau_int;      // [Vpad] internal row order (padding 0)
 
     // MLC geometry
     std::vector<int32_t> row_start;   // [R] first beamlet of each row

@@ -115,6 +115,9 @@ int main(int argc, char** argv) {
     o.product_tune = 1;
     o.gradient_depth = 4;
     o.direction = DAO_DIR_CONJUGATE;
+    o.apertures_per_round = 1;
+    o.dk_format = DAO_DFMT_NATIVE;
+    o.residual_rounds = 5;
     expect(validate(p, o) == DAO_OK, "valid problem accepted");
 
     // ---- the layouts

@@ -79,12 +79,34 @@ def test_create_rejects_malformed_inputs():
     msg = _expect(dao.DAO_EINVAL, _a=_args(ph), _opts=dict(persistent=3))
     assert "persistent" in msg
     for opts, needle in [(dict(d_format=3), "d_format"), (dict(d_residual=1), "d_residual"),
-                         (dict(d_format=1, d_residual=2), "d_residual"),
+                         (dict(d_format=1, d_residual=3), "d_residual"),
+                         (dict(d_format=1, d_residual=2, residual_rounds=-1), "residual_rounds"),
+                         (dict(direction=2), "direction"), (dict(apertures_per_round=0), "apertures_per_round"),
+                         (dict(apertures_per_round=17), "apertures_per_round"), (dict(dk_format=2), "dk_format"),
+                         (dict(dk_format=1, dtype="f64"), "DAO_F32"), (dict(dk_format=1, master=1), "aperture"),
                          (dict(d_format=1, dtype="f64"), "DAO_F32"), (dict(d_format=2, master=1), "aperture"),
                          (dict(product_tune=2), "product_tune"), (dict(dose_variant=4), "dose_variant"),
                          (dict(dose_variant=2, d_format=1), "native"), (dict(gradient_depth=6), "gradient_depth")]:
         msg = _expect(dao.DAO_EINVAL, _a=_args(ph), _opts=opts)
         assert needle in msg, (opts, msg)
+
+
+def test_create_rejects_malformed_structure_extras():
+    ph = cached_phantom("mini", nested_targets=True)
+    v2 = ph.vox_struct2.copy()
+    j = int(np.flatnonzero(v2 >= 0)[0])
+    bad = v2.copy(); bad[j] = ph.vox_struct[j]
+    msg = _expect(dao.DAO_EINVAL, _a=_args(ph), _opts=dict(vox_struct2=bad))
+    assert "same structure twice" in msg
+    bad = v2.copy(); bad[j] = len(ph.prescriptions)
+    msg = _expect(dao.DAO_EINVAL, _a=_args(ph), _opts=dict(vox_struct2=bad))
+    assert "second structure id" in msg
+    a = _args(ph); a["vox_struct"][j] = -1
+    msg = _expect(dao.DAO_EINVAL, _a=a, _opts=dict(vox_struct2=v2))
+    assert "no first" in msg
+    shift = np.zeros(ph.n_vox); shift[3] = np.inf
+    msg = _expect(dao.DAO_EINVAL, _a=_args(ph), _opts=dict(vox_shift=shift))
+    assert "threshold shift" in msg
 
 
 def test_create_enforces_memory_cap():

@@ -12,7 +12,10 @@ Two FP64 oracle references:
   at most that bound.  The bars below are those bounds rounded up.
 The converged master on the same pool is compared the same two ways, plus
 the plan metrics PTV D95 and OAR Dmax against the FP64 master on the
-original D.
+original D.  The precision form of the head-and-neck-shaped plan (16-bit D
+and an FP16 aperture dose matrix) is checked teacher-forced against the
+oracle's stored trajectory: objective after every round, final dose, PTV D95
+and organ Dmax within 1e-3.
 """
 import numpy as np
 import pytest
@@ -112,5 +115,105 @@ def test_converged_master_with_16bit_storage(fmt, res):
         print(f"[precision] {fmt} residual={res} errors vs FP64 on the original D: {errs}", flush=True)
         for k, v in errs.items():
             assert v <= 10 * bound, (k, v)
+    finally:
+        ctx.close()
+
+
+def _golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"{name}_seed0_r50.json")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored trajectory {path}")
+    with open(path) as f:
+        return json.load(f)
+
+
+# the precision form of the head-and-neck-shaped plan: 16-bit D (with and
+# without the FP16 residual) and an FP16 aperture dose matrix
+PLAN_FORMATS = [("f16", 0, 1), ("f16", 1, 1), ("bf16", 1, 1), ("f16", 0, 0)]
+
+
+@pytest.mark.parametrize("fmt,res,dk16", PLAN_FORMATS)
+def test_precision_plan_teacher_forced(fmt, res, dk16):
+    """Teacher-forced against the FP64 oracle's stored 50-aperture trajectory
+    (the oracle on the FP32 matrix): every round starts from the oracle's
+    pool and intensities; the objective after the round's master and, at the
+    end, the dose, PTV D95 and organ Dmax agree with the oracle's to 1e-3.
+    Pricing decisions are compared where the gap exceeds the reduced-cost
+    error of the format (1e-3 |rc|); closer ones are counted."""
+    torch = torch_cuda()
+    doc = _golden("headneck")
+    ph = cached_phantom("headneck")
+    rc1 = doc["rc1"]
+    tol = doc["eps"] * abs(rc1)
+    ctx = ctx_for(ph, dtype="f32", d_format=FMT[fmt], d_residual=res, dk_format=FMT["f16"] if dk16 else 0)
+    worst_F, near = 0.0, 0
+    try:
+        for k, rec in enumerate(doc["rounds"]):
+            pool = [(r["beam"], tuple(tuple(p) for p in r["leaves"])) for r in doc["rounds"][:k]]
+            ctx.set_state(pool, doc["rounds"][k - 1]["y"] if k else [], rc1=rc1 if k else float("nan"),
+                          eps=doc["eps"])
+            got = ctx.price_current()
+            if rec["gap"] > 1e-3 * abs(rec["rc"]):
+                assert (got["beam"], got["leaves"]) == (rec["beam"], tuple(tuple(p) for p in rec["leaves"])), k
+            else:
+                near += 1
+            ctx.add_aperture(rec["beam"], rec["leaves"])
+            steps, kkt, F = ctx.master_solve(tol, doc["max_steps"])
+            worst_F = max(worst_F, abs(F - rec["F"]) / rec["F"])
+            assert abs(F - rec["F"]) <= 1e-3 * rec["F"], (k, F, rec["F"])
+        # the last round's plan against the oracle's
+        P = oracle_problem(ph, "f32")
+        ap = [oracle.Aperture(r["beam"], tuple(tuple(p) for p in r["leaves"])) for r in doc["rounds"]]
+        z0 = oracle.dose(P, oracle.beamlet_intensity(P, ap, doc["rounds"][-1]["y"]))
+        d = torch.empty(ph.n_vox, dtype=torch.float64, device="cuda:0")
+        ctx.get_dose(d)
+        z = d.cpu().numpy()
+        ptv = np.asarray(ph.vox_struct) == 0
+        errs = dict(F=worst_F, dose=relerr(z, z0), D95=abs(d95(z, ptv) - d95(z0, ptv)) / d95(z0, ptv))
+        for s, nm in enumerate(ph.struct_names):
+            if s > 0:
+                m = np.asarray(ph.vox_struct) == s
+                errs[f"Dmax_{nm}"] = abs(dmax(z, m) - dmax(z0, m)) / dmax(z0, m)
+        print(f"[precision] headneck {fmt} residual={res} dk16={dk16}: {errs}, near decisions {near}", flush=True)
+        for key, v in errs.items():
+            assert v <= 1e-3, (key, v)
+    finally:
+        ctx.close()
+
+
+def test_selective_residual_plan():
+    """d_residual 2 on the head-and-neck-shaped plan (FP16 D and D_K): the
+    early rounds run on the 16-bit values, near-tie decisions are priced
+    again with the residual, and the last rounds run with the residual and an
+    FP32 D_K.  The final plan is then accurate to the FP32 bar: the GPU's
+    dose and objective equal the FP64 oracle's dose D (A y) and F at the
+    GPU's own final pool and intensities to 1e-5, and the objective is within
+    1e-3 of the oracle's stored plan."""
+    torch = torch_cuda()
+    doc = _golden("headneck")
+    ph = cached_phantom("headneck")
+    P = oracle_problem(ph, "f32")
+    ctx = ctx_for(ph, dtype="f32", d_format=FMT["f16"], d_residual=2, dk_format=FMT["f16"], residual_rounds=5)
+    try:
+        assert ctx.info()["dk_format"] == FMT["f16"]
+        out = ctx.solve(len(doc["rounds"]))
+        info = ctx.info()
+        assert out["rounds"] == len(doc["rounds"])
+        assert info["dk_format"] == 0          # the final rounds switched D_K to FP32
+        pool, y = ctx.get_pool()
+        ap = [oracle.Aperture(b, lv) for b, lv in pool]
+        z0 = oracle.dose(P, oracle.beamlet_intensity(P, ap, y))
+        d = torch.empty(ph.n_vox, dtype=torch.float64, device="cuda:0")
+        F = ctx.get_dose(d)
+        z = d.cpu().numpy()
+        F0 = oracle.objective(P, z0)
+        print(f"[precision] selective residual: reprices {info['residual_reprices']}, F {F:.10e} "
+              f"oracle at the same y {F0:.10e}, stored plan {doc['F']:.10e}, dose err {relerr(z, z0):.2e}",
+              flush=True)
+        assert relerr(z, z0) <= 1e-5
+        assert abs(F - F0) <= 1e-5 * F0
+        assert abs(F - doc["F"]) <= 1e-3 * doc["F"]
     finally:
         ctx.close()
