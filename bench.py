@@ -1,10 +1,12 @@
-"""Benchmark: time-to-50-aperture plan on the prostate-shaped phantom (1 GPU).
+"""Benchmark: time-to-50-aperture plan on one GPU.
 
 One "step" is one whole plan: dao_solve from an empty pool to 50 apertures
 (pricing, master, column generation) with the dose matrix resident on the
-device.  Prints one JSON line.
+device.  The headline workload is the head-and-neck-shaped phantom (the
+largest configuration); the prostate-shaped plan is timed beside it.  Prints
+one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--config prostate] [--cpu-seconds S]
+    python bench.py [--steps K] [--warmup W] [--config headneck] [--cpu-seconds S]
 """
 import argparse
 import json
@@ -34,8 +36,8 @@ def cpu_baseline(ph, gpu_steps_per_plan, rounds_per_plan, seconds):
 
     Sample: the oracle's own column generation on the same phantom, run
     round by round until `seconds` of CPU time are spent.  Its mean time per
-    master step and per pricing round are scaled to one whole plan with the
-    master step count the plan takes (the GPU runs the same algorithm).
+    master step and per pricing round are extrapolated to one whole plan with
+    the master step count the plan takes (the GPU runs the same algorithm).
     """
     import numpy as np
     from threadpoolctl import threadpool_limits
@@ -44,7 +46,11 @@ def cpu_baseline(ph, gpu_steps_per_plan, rounds_per_plan, seconds):
     from oracle.master import MasterState, solve_master
 
     with threadpool_limits(limits=1):
-        P = oracle.make_problem(ph.csr(), ph.rows_per_beam, ph.row_len, ph.vox_struct, ph.prescriptions)
+        D = ph.csr()
+        if ph.dtype == "f32":   # the problem the FP32 context holds
+            D = D.copy()
+            D.data = D.data.astype(np.float32).astype(np.float64)
+        P = oracle.make_problem(D, ph.rows_per_beam, ph.row_len, ph.vox_struct, ph.prescriptions)
         st = MasterState.empty(P)
         t_price = t_master = 0.0
         steps = rounds = 0
@@ -68,9 +74,9 @@ def cpu_baseline(ph, gpu_steps_per_plan, rounds_per_plan, seconds):
     s_round = t_price / max(1, rounds)
     plan_s = s_step * gpu_steps_per_plan + s_round * rounds_per_plan
     return dict(value=1.0 / plan_s, unit="plans/s", cores=1, kind="oracle",
-                sample=(f"FP64 oracle column generation on the same phantom for {rounds} rounds "
+                sample=(f"FP64 oracle column generation on the same phantom for its first {rounds} rounds "
                         f"({steps} master steps, {t_master + t_price:.1f} s); {s_step * 1e3:.1f} ms per "
-                        f"master step and {s_round * 1e3:.1f} ms per pricing round scaled to the "
+                        f"master step and {s_round * 1e3:.1f} ms per pricing round extrapolated to the "
                         f"{gpu_steps_per_plan} master steps and {rounds_per_plan} rounds of one plan"),
                 plan_seconds=plan_s)
 
@@ -200,19 +206,120 @@ def run_serving(reqs, stream, max_live, cap, sequential, batch_masters=True, **o
                 p99_s=float(np.percentile(lat, 99)), mean_s=float(lat.mean()))
 
 
+def time_plans(dao, ph, stream, steps, warmup, **opts):
+    """K timed plans (after W warm-ups) on one context; returns the context
+    and the figures."""
+    import numpy as np
+    import torch
+    ctx = dao.DaoContext.from_phantom(ph, stream=stream, **opts)
+    n_ap = ph.n_apertures
+    for w in range(warmup):
+        out = ctx.solve(n_ap)
+        log(f"[bench] {ph.name} warmup {w}: rounds {out['rounds']} steps {out['total_steps']} F {out['F']:.6e}")
+    torch.cuda.synchronize()
+    lat, outs = [], []
+    t_start = time.perf_counter()
+    for k in range(steps):
+        t0 = time.perf_counter()
+        out = ctx.solve(n_ap)
+        lat.append(time.perf_counter() - t0)
+        outs.append(out)
+        log(f"[bench] {ph.name} plan {k}: {lat[-1]:.4f} s rounds {out['rounds']} steps {out['total_steps']} "
+            f"ls {out['total_ls_evals']} F {out['F']:.8e}")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    lat = np.array(lat)
+    o = outs[-1]
+    fig = {
+        "plans_s": steps / total, "total_s": total,
+        "plan_s_p50": float(np.percentile(lat, 50)), "plan_s_p99": float(np.percentile(lat, 99)),
+        "plan_s_mean": float(lat.mean()),
+        "plan_split_s": {"pricing": float(np.mean([x["price_s"] for x in outs])),
+                         "columns_and_master": float(np.mean([x["master_s"] for x in outs]))},
+        "rounds": int(o["rounds"]), "master_steps_per_plan": int(o["total_steps"]),
+        "ls_evals_per_plan": int(o["total_ls_evals"]),
+        "round_steps": [int(v) for v in o["round_steps"]], "capped_rounds": int(o["capped_rounds"]),
+        "final_F": o["F"], "master_form": ctx.info()["last_master_form"],
+    }
+    return ctx, fig
+
+
+def profile_master(dao, ctx, n_ap, algo_step_bytes, ls_pass_bytes):
+    """One instrumented plan: every launch of the master kernel bracketed by
+    HIP events on the context stream.  Plans are deterministic, so it repeats
+    the launches of a timed plan.  Algorithmic bytes per launch follow the
+    per-step count: two beamlet products plus the line-search passes."""
+    try:
+        ctx.profile_start(4)
+        ctx.profile_stop()
+        plist = [(4, "k_master_coop")]
+    except dao.DaoError:
+        plist = [(0, "k_upd_ap"), (1, "k_qstep_ap"), (2, "k_lseval_ap"), (3, "k_dir_ap")]
+    kernels = {}
+    for kid, kname in plist:
+        ctx.profile_start(kid)
+        out = ctx.solve(n_ap)
+        r = ctx.profile_stop()
+        r["avg_us"] = r["total_us"] / max(1, r["launches"])
+        r["steps_per_plan"] = int(out["total_steps"])
+        r["ls_evals_per_plan"] = int(out["total_ls_evals"])
+        r["algo_bytes_per_plan"] = out["total_steps"] * algo_step_bytes + out["total_ls_evals"] * ls_pass_bytes
+        r["algo_GBs"] = r["algo_bytes_per_plan"] / max(r["total_us"], 1e-9) / 1e3
+        if kid == 4:
+            r["phases_us"] = ctx.profile_phases()
+            log(f"[bench] {kname} phases (us per plan): {r['phases_us']}")
+        kernels[kname] = r
+        log(f"[bench] {kname}: {r['launches']} launches ({r['working_launches']} working), "
+            f"{r['total_us'] / 1e3:.2f} ms, avg {r['avg_us']:.2f} us, {r['algo_GBs']:.0f} GB/s algorithmic")
+    return kernels
+
+
+def time_products(ctx, info, iters, scrub):
+    """k_dose / k_gradT (the kernels behind dao_dose / dao_gradient): warm
+    back to back, and cold after a 1 GiB scrub read before every launch."""
+    cold_iters = max(1, iters // 10)
+    ud, ug = ctx.time_product(0, iters), ctx.time_product(1, iters)
+    udc, ugc = ctx.time_product_cold(0, cold_iters, scrub), ctx.time_product_cold(1, cold_iters, scrub)
+    bd, bg = info["bytes_dose"], info["bytes_gradient"]
+    return {"dose_bytes": bd, "gradient_bytes": bg, "dose_us": ud, "gradient_us": ug,
+            "dose_cold_us": udc, "gradient_cold_us": ugc,
+            "dose_GBs": bd / (ud * 1e-6) / 1e9, "gradient_GBs": bg / (ug * 1e-6) / 1e9,
+            "dose_cold_GBs": bd / (udc * 1e-6) / 1e9, "gradient_cold_GBs": bg / (ugc * 1e-6) / 1e9,
+            "dose_frac_cold": bd / (udc * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "gradient_frac_cold": bg / (ugc * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "tuned": {"dose_variant": info["dose_variant"], "gradient_depth": info["gradient_depth"]}}
+
+
+def copy_ceiling(torch):
+    """Achievable HBM bandwidth: a 1 GiB device copy (read + write bytes over
+    the time of the copy), best of 5."""
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    best = 0.0
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, 2.0 * n * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del src, dst
+    return best
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="prostate")
+    ap.add_argument("--config", default="headneck")
+    ap.add_argument("--also", default="prostate", help="second phantom whose plan is timed beside; 'none' skips")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--product-iters", type=int, default=200)
-    ap.add_argument("--large-config", default="headneck",
-                    help="phantom whose products are also timed (D of ~120 MB); 'none' skips it")
-    ap.add_argument("--serve-requests", type=int, default=32,
+    ap.add_argument("--serve-requests", type=int, default=256,
                     help="requests of the serving replay (the serving configuration uses 256)")
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-max-live", type=int, default=8)
@@ -235,142 +342,77 @@ def main():
     log(f"[bench] phantom {args.config} seed {args.seed}")
     ph = make_phantom(args.config, args.seed)
     stream = torch.cuda.current_stream().cuda_stream
-    t0 = time.perf_counter()
-    ctx = dao.DaoContext.from_phantom(ph, stream=stream)
-    create_s = time.perf_counter() - t0
-    info = ctx.info()
     n_ap = ph.n_apertures
-    log(f"[bench] ctx ready in {create_s:.2f} s: {info}")
     if args.pmc_workload:
+        ctx = dao.DaoContext.from_phantom(ph, stream=stream)
         pmc_workload(ctx, n_ap, torch)
         ctx.close()
         return
 
-    for w in range(args.warmup):
-        out = ctx.solve(n_ap)
-        log(f"[bench] warmup {w}: rounds {out['rounds']} steps {out['total_steps']} F {out['F']:.6e}")
-    torch.cuda.synchronize()
-    lat = []
-    outs = []
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        t0 = time.perf_counter()
-        out = ctx.solve(n_ap)
-        lat.append(time.perf_counter() - t0)
-        outs.append(out)
-        log(f"[bench] plan {k}: {lat[-1]:.4f} s rounds {out['rounds']} steps {out['total_steps']} "
-            f"ls {out['total_ls_evals']} F {out['F']:.8e}")
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-    lat = np.array(lat)
+    t0 = time.perf_counter()
+    ctx, plan = time_plans(dao, ph, stream, args.steps, args.warmup)
+    info = ctx.info()
+    create_s = time.perf_counter() - t0
+    log(f"[bench] {args.config}: {plan['plans_s']:.3f} plans/s, {plan['master_steps_per_plan']} steps, "
+        f"capped rounds {plan['capped_rounds']}, form {plan['master_form']}")
 
-    # master kernels: one instrumented plan per kernel, every launch bracketed
-    # by HIP events on the context stream; algorithmic bytes counted on the
-    # device.  Plans are deterministic, so each instrumented plan repeats
-    # exactly the launches of a timed plan.
-    kernels = {}
-    try:
-        ctx.profile_start(4)
-        ctx.profile_stop()
-        plist = [(4, "k_master_coop")]
-    except dao.DaoError:
-        plist = [(0, "k_upd_ap"), (1, "k_qstep_ap"), (2, "k_lseval_ap"), (3, "k_dir_ap")]
-    for kid, kname in plist:
-        ctx.profile_start(kid)
-        ctx.solve(n_ap)
-        r = ctx.profile_stop()
-        r["avg_us"] = r["total_us"] / max(1, r["launches"])
-        r["GBs"] = r["total_bytes"] / max(r["total_us"], 1e-9) / 1e3
-        if kid == 4:
-            r["phases_us"] = ctx.profile_phases()
-            log(f"[bench] {kname} phases (us per plan): {r['phases_us']}")
-        kernels[kname] = r
-        log(f"[bench] {kname}: {r['launches']} launches ({r['working_launches']} working), "
-            f"{r['total_us'] / 1e3:.1f} ms, avg {r['avg_us']:.2f} us, {r['GBs']:.0f} GB/s")
+    # the master kernel, with the algorithmic bytes of a master step: one
+    # forward and one transposed beamlet product, and per line-search
+    # evaluation one pass over d (8 B), q (4 B) and the structure class (1 B)
+    step_bytes = info["bytes_dose"] + info["bytes_gradient"]
+    ls_bytes = info["n_vox_nonempty"] * (8 + 4 + 1)
+    kernels = profile_master(dao, ctx, n_ap, step_bytes, ls_bytes)
     dom = max(kernels, key=lambda k: kernels[k]["total_us"])
     dk_ = kernels[dom]
     traffic = measured_traffic(dom, args.config)
+    hbm_copy = copy_ceiling(torch)
+    log(f"[bench] device copy: {hbm_copy:.0f} GB/s")
 
-    # the plain products (the kernels behind dao_dose / dao_gradient)
-    us_dose = ctx.time_product(0, args.product_iters)
-    us_grad = ctx.time_product(1, args.product_iters)
-    gbs_dose = info["bytes_dose"] / (us_dose * 1e-6) / 1e9
-    gbs_grad = info["bytes_gradient"] / (us_grad * 1e-6) / 1e9
-    log(f"[bench] D x: {us_dose:.2f} us {gbs_dose:.0f} GB/s; D^T u: {us_grad:.2f} us {gbs_grad:.0f} GB/s")
-    # cold: a 1 GiB read (4x the last-level cache) before every timed launch
     scrub = torch.zeros(1 << 30, dtype=torch.uint8, device="cuda")
-    cold_iters = max(1, args.product_iters // 10)
-    us_dose_c = ctx.time_product_cold(0, cold_iters, scrub)
-    us_grad_c = ctx.time_product_cold(1, cold_iters, scrub)
-    # every product variant, forced (the tuned choice above is one of them)
-    variants = {}
-    for dv, gd in ((0, 4), (1, 8), (2, 16), (3, 4)):
-        vc = dao.DaoContext.from_phantom(ph, dtype="f32", stream=stream, product_tune=0, dose_variant=dv,
-                                         gradient_depth=gd)
-        variants[f"dose{dv}_depth{gd}"] = {
-            "dose_us": vc.time_product(0, args.product_iters), "gradient_us": vc.time_product(1, args.product_iters),
-            "dose_cold_us": vc.time_product_cold(0, cold_iters, scrub),
-            "gradient_cold_us": vc.time_product_cold(1, cold_iters, scrub)}
-        vc.close()
-    log(f"[bench] product variants (tuned: dose {info['dose_variant']}, depth {info['gradient_depth']}): {variants}")
-    # the same products on the larger phantom (D several times the size, nearer
-    # the streaming regime the kernels are built for)
-    large = None
-    if args.large_config != "none" and args.large_config != args.config:
-        phl = make_phantom(args.large_config, args.seed)
-        large = {"phantom": args.large_config, "nnz": int(phl.row_ptr[-1]), "n_blt": int(phl.n_blt)}
-        for fname, fmt in (("f32", dao.DAO_DFMT_NATIVE), ("f16", dao.DAO_DFMT_F16)):
-            lc = dao.DaoContext.from_phantom(phl, dtype="f32", stream=stream, d_format=fmt)
-            li = lc.info()
-            ud, ug = lc.time_product(0, args.product_iters), lc.time_product(1, args.product_iters)
-            udc, ugc = lc.time_product_cold(0, cold_iters, scrub), lc.time_product_cold(1, cold_iters, scrub)
-            large[fname] = {
-                "dose_bytes": li["bytes_dose"], "gradient_bytes": li["bytes_gradient"],
-                "dose_us": ud, "gradient_us": ug, "dose_cold_us": udc, "gradient_cold_us": ugc,
-                "dose_GBs": li["bytes_dose"] / (ud * 1e-6) / 1e9, "gradient_GBs": li["bytes_gradient"] / (ug * 1e-6) / 1e9,
-                "dose_cold_GBs": li["bytes_dose"] / (udc * 1e-6) / 1e9,
-                "gradient_cold_GBs": li["bytes_gradient"] / (ugc * 1e-6) / 1e9,
-                "dose_frac_cold": li["bytes_dose"] / (udc * 1e-6) / 1e9 / HBM_PEAK_GBS,
-                "gradient_frac_cold": li["bytes_gradient"] / (ugc * 1e-6) / 1e9 / HBM_PEAK_GBS,
-                "tuned": {"dose_variant": li["dose_variant"], "gradient_depth": li["gradient_depth"]}}
-            lc.close()
-            log(f"[bench] {args.large_config} {fname} products: {large[fname]}")
-        del phl
-    del scrub
-    gbs_dose_c = info["bytes_dose"] / (us_dose_c * 1e-6) / 1e9
-    gbs_grad_c = info["bytes_gradient"] / (us_grad_c * 1e-6) / 1e9
-    log(f"[bench] cold D x: {us_dose_c:.2f} us {gbs_dose_c:.0f} GB/s; "
-        f"cold D^T u: {us_grad_c:.2f} us {gbs_grad_c:.0f} GB/s")
+    products = time_products(ctx, info, args.product_iters, scrub)
+    log(f"[bench] {args.config} products: {products}")
 
-    # 16-bit storage of D (FP16 / BF16 value per beamlet scale, optional FP16
-    # residual): product throughput and one plan each, on the same phantom
+    # the precision form: D stored in 16 bits (FP16 / BF16 values over a
+    # per-beamlet FP32 scale, optional FP16 residual) and the aperture dose
+    # matrix in FP16 (or FP32): products and timed plans, same phantom
     reduced = {}
-    scrub = torch.zeros(1 << 30, dtype=torch.uint8, device="cuda")
-    for fname, fmt in (("f16", dao.DAO_DFMT_F16), ("bf16", dao.DAO_DFMT_BF16)):
-        for res in (0, 1):
-            rc = dao.DaoContext.from_phantom(ph, dtype="f32", stream=stream, d_format=fmt, d_residual=res)
+    combos = [("f16", dao.DAO_DFMT_F16, 0, 1), ("f16", dao.DAO_DFMT_F16, 1, 1), ("bf16", dao.DAO_DFMT_BF16, 0, 1),
+              ("bf16", dao.DAO_DFMT_BF16, 1, 1), ("f16", dao.DAO_DFMT_F16, 0, 0), ("f32", dao.DAO_DFMT_NATIVE, 0, 1)]
+    for fname, fmt, res, dk16 in combos:
+        if True:
+            rc = dao.DaoContext.from_phantom(ph, dtype="f32", stream=stream, d_format=fmt, d_residual=res,
+                                             dk_format=dao.DAO_DFMT_F16 if dk16 else dao.DAO_DFMT_NATIVE)
             ri = rc.info()
-            ud, ug = rc.time_product(0, args.product_iters), rc.time_product(1, args.product_iters)
-            udc, ugc = rc.time_product_cold(0, cold_iters, scrub), rc.time_product_cold(1, cold_iters, scrub)
+            key = f"{fname}{'+lo' if res else ''}{'_dk16' if dk16 else '_dk32'}"
+            reduced[key] = time_products(rc, ri, args.product_iters, scrub)
             rc.solve(n_ap)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            ro = rc.solve(n_ap)
+            nrep = 5
+            for _ in range(nrep):
+                ro = rc.solve(n_ap)
             torch.cuda.synchronize()
-            pt = time.perf_counter() - t0
-            key = f"{fname}{'+lo' if res else ''}"
-            reduced[key] = {
-                "dose_us": ud, "dose_bytes": ri["bytes_dose"], "dose_GBs": ri["bytes_dose"] / (ud * 1e-6) / 1e9,
-                "gradient_us": ug, "gradient_bytes": ri["bytes_gradient"],
-                "gradient_GBs": ri["bytes_gradient"] / (ug * 1e-6) / 1e9,
-                "dose_cold_us": udc, "gradient_cold_us": ugc,
-                "dose_speedup_vs_f32": us_dose / ud, "gradient_speedup_vs_f32": us_grad / ug,
-                "plan_s": pt, "plan_F": ro["F"], "plan_F_rel_vs_f32": (ro["F"] - outs[-1]["F"]) / outs[-1]["F"],
-                "device_bytes": ri["device_bytes"],
-            }
-            log(f"[bench] D {key}: D x {ud:.2f} us ({reduced[key]['dose_GBs']:.0f} GB/s), D^T u {ug:.2f} us "
-                f"({reduced[key]['gradient_GBs']:.0f} GB/s), plan {pt:.4f} s F {ro['F']:.8e}")
+            pt = (time.perf_counter() - t0) / nrep
+            reduced[key].update(plan_s=pt, plan_F=ro["F"], plan_F_rel_vs_f32=(ro["F"] - plan["final_F"]) / plan["final_F"],
+                                plan_steps=int(ro["total_steps"]), device_bytes=ri["device_bytes"])
+            log(f"[bench] D {key}: {reduced[key]}")
             rc.close()
+
+    # the second phantom's plan and products
+    also = None
+    if args.also != "none" and args.also != args.config:
+        pha = make_phantom(args.also, args.seed)
+        actx, also = time_plans(dao, pha, stream, args.steps, args.warmup)
+        ainfo = actx.info()
+        also["config"] = {"phantom": args.also, "n_vox_nonempty": ainfo["n_vox_nonempty"], "nnz": ainfo["nnz"],
+                          "n_blt": ainfo["n_blt"], "apertures": pha.n_apertures}
+        akern = profile_master(dao, actx, pha.n_apertures, ainfo["bytes_dose"] + ainfo["bytes_gradient"],
+                               ainfo["n_vox_nonempty"] * 13)
+        also["master_kernels"] = akern
+        also["products"] = time_products(actx, ainfo, args.product_iters, scrub)
+        actx.close()
+        log(f"[bench] {args.also}: {also['plans_s']:.3f} plans/s")
+        del pha
     del scrub
 
     # serving: the same seeded request stream replayed batched (FP32 D and
@@ -384,70 +426,55 @@ def main():
                      mix={c: sum(r["cfg"] == c for r in reqs) for c in ("tiny", "prostate", "headneck")})
         serve["batched_f32"] = run_serving(reqs, stream, args.serve_max_live, cap, False)
         log(f"[bench] serving batched FP32: {serve['batched_f32']}")
-        serve["interleaved_f32"] = run_serving(reqs, stream, args.serve_max_live, cap, False, batch_masters=False)
-        log(f"[bench] serving interleaved FP32 (masters one after another): {serve['interleaved_f32']}")
         serve["batched_f16"] = run_serving(reqs, stream, args.serve_max_live, cap, False,
                                            d_format=dao.DAO_DFMT_F16)
         log(f"[bench] serving batched FP16 D: {serve['batched_f16']}")
         serve["sequential_f32"] = run_serving(reqs, stream, 1, cap, True)
         log(f"[bench] serving sequential FP32: {serve['sequential_f32']}")
         serve["speedup_plans_s"] = serve["batched_f32"]["plans_s"] / serve["sequential_f32"]["plans_s"]
-        serve["speedup_interleaved_plans_s"] = (serve["interleaved_f32"]["plans_s"] /
-                                                serve["sequential_f32"]["plans_s"])
+        serve["speedup_f16_plans_s"] = serve["batched_f16"]["plans_s"] / serve["sequential_f32"]["plans_s"]
 
-    steps_per_plan = int(outs[-1]["total_steps"])
+    algo_per_launch = dk_["algo_bytes_per_plan"] / max(1, dk_["launches"])
     result = {
         "metric": METRIC,
-        "value": args.steps / total,
+        "value": plan["plans_s"],
         "unit": "plans/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * total / args.steps,
+        "ms_per_step": 1e3 * plan["total_s"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": (f"prostate-shaped phantom {ph.shape[0]}x{ph.shape[1]}x{ph.shape[2]} voxels at 2.5 mm, "
+            "workload": (f"{args.config} phantom {ph.shape[0]}x{ph.shape[1]}x{ph.shape[2]} voxels at 2.5 mm, "
                          f"{ph.n_beams} beams, {ph.n_blt} beamlets, nnz {ph.nnz}, {n_ap}-aperture plan, "
                          f"FP32 dose matrix"),
             "phantom": args.config, "seed": args.seed, "apertures": n_ap,
             "n_vox_nonempty": info["n_vox_nonempty"], "nnz": info["nnz"], "n_blt": info["n_blt"],
         },
-        "plan_s_p50": float(np.percentile(lat, 50)),
-        "plan_s_p99": float(np.percentile(lat, 99)),
-        "plan_s_mean": float(lat.mean()),
-        "plan_split_s": {"pricing": float(np.mean([o["price_s"] for o in outs])),
-                         "columns_and_master": float(np.mean([o["master_s"] for o in outs]))},
-        "master_steps_per_plan": steps_per_plan,
-        "ls_evals_per_plan": int(outs[-1]["total_ls_evals"]),
-        "final_F": outs[-1]["F"],
         "create_s": create_s,
-        "products": {
-            "dose_us": us_dose, "dose_bytes": info["bytes_dose"], "dose_GBs": gbs_dose,
-            "gradient_us": us_grad, "gradient_bytes": info["bytes_gradient"], "gradient_GBs": gbs_grad,
-            "dose_cold_us": us_dose_c, "dose_cold_GBs": gbs_dose_c,
-            "gradient_cold_us": us_grad_c, "gradient_cold_GBs": gbs_grad_c,
-            "dose_frac_cold": gbs_dose_c / HBM_PEAK_GBS, "gradient_frac_cold": gbs_grad_c / HBM_PEAK_GBS,
-            "tuned": {"dose_variant": info["dose_variant"], "gradient_depth": info["gradient_depth"]},
-            "variants": variants,
-            "note": ("D x = k_dose, D^T u = k_gradT, timed standalone: warm back-to-back (D fits the 256 MB "
-                     "last-level cache) and cold (1 GiB scrub read before each timed launch)"),
-        },
-        "products_large": large,
+        "plan": {k: v for k, v in plan.items() if k not in ("plans_s", "total_s")},
+        "products": products,
+        "hbm_copy_GBs": hbm_copy,
         "master_kernels": kernels,
         "d_16bit": reduced,
+        args.also: also,
         "serving": serve,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk_["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dk_["GBs"] / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": dk_["total_bytes"] / max(1, dk_["launches"]),
-                     "us_per_launch": dk_["avg_us"], "launches_per_plan": dk_["launches"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": algo_per_launch / (dk_["avg_us"] * 1e-6) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": algo_per_launch / (dk_["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": traffic, "algo_bytes_per_launch": algo_per_launch,
+                     "us_per_launch": dk_["avg_us"], "launches_per_plan": dk_["launches"],
+                     "copy_GBs": hbm_copy,
+                     "note": ("algorithmic bytes of a master step: one forward and one transposed beamlet "
+                              "product plus 13 B per non-empty voxel row per line-search evaluation")},
     }
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
-        result["cpu_baseline"] = cpu_baseline(ph, steps_per_plan, int(outs[-1]["rounds"]), args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(ph, plan["master_steps_per_plan"], plan["rounds"], args.cpu_seconds)
     ctx.close()
     print(json.dumps(result), flush=True)
 
