@@ -111,12 +111,20 @@ def measured_traffic(kernel, config):
         return None
 
 
-def pmc_workload(ctx, n_ap, torch):
-    """Short run for counter collection: one plan, then a plain device copy
-    of COPY_CALIB_BYTES (read and write) that calibrates FETCH_SIZE and
-    WRITE_SIZE against a known byte count."""
-    out = ctx.solve(n_ap)
-    log(f"[bench] pmc plan: rounds {out['rounds']} steps {out['total_steps']}")
+def pmc_workload(ctx, n_ap, torch, what="plan"):
+    """Short run for counter collection: one plan (or, with what="products",
+    8 cold launches of each sparse product after a cache scrub), then a plain
+    device copy of COPY_CALIB_BYTES (read and write) that calibrates
+    FETCH_SIZE and WRITE_SIZE against a known byte count."""
+    if what == "products":
+        scrub = torch.zeros(1 << 30, dtype=torch.uint8, device="cuda")
+        for kernel in (0, 1):
+            us = ctx.time_product_cold(kernel, 8, scrub)
+            log(f"[bench] pmc product {kernel}: 8 cold launches, {us:.2f} us each")
+        del scrub
+    else:
+        out = ctx.solve(n_ap)
+        log(f"[bench] pmc plan: rounds {out['rounds']} steps {out['total_steps']}")
     n = COPY_CALIB_BYTES // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -323,8 +331,8 @@ def main():
                     help="requests of the serving replay (the serving configuration uses 256)")
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-max-live", type=int, default=8)
-    ap.add_argument("--pmc-workload", action="store_true",
-                    help="one plan plus a calibration copy, for rocprofv3 --pmc runs")
+    ap.add_argument("--pmc-workload", nargs="?", const="plan", default=None, choices=["plan", "products"],
+                    help="one plan (or cold product launches) plus a calibration copy, for rocprofv3 --pmc runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the plan is a single-GPU workload "
@@ -345,7 +353,7 @@ def main():
     n_ap = ph.n_apertures
     if args.pmc_workload:
         ctx = dao.DaoContext.from_phantom(ph, stream=stream)
-        pmc_workload(ctx, n_ap, torch)
+        pmc_workload(ctx, n_ap, torch, args.pmc_workload)
         ctx.close()
         return
 

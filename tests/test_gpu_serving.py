@@ -1,7 +1,8 @@
 """The serving loop (dao_server_*): requests admitted as slots and memory
 free up, rounds of all live solves advanced together, each result the plan
 its solo dao_solve gives (same round beams and reduced costs; F within 1e-9
-in FP64, 1e-5 in FP32, as for dao_solve_batch)."""
+in FP64, 1e-5 in FP32, as for dao_solve_batch), and served plans against
+the oracle directly (its solve in FP64, its stored trajectory in FP32)."""
 import time
 
 import numpy as np
@@ -91,3 +92,52 @@ def test_admission_respects_the_memory_cap():
         assert plan["status"] == dao.DAO_ENOMEM
     finally:
         server.close()
+
+
+def test_served_plans_against_the_oracle():
+    """Plans served in a mix (the prostate-shaped 50-aperture plan in FP32 next
+    to 32^3 plans in FP64 and FP32) against the oracle directly: the FP64
+    plan takes the oracle's aperture wherever the decision gap exceeds 1e-9
+    (objective after every round within 1e-9); the prostate-shaped plan
+    matches the oracle's stored trajectory round by round up to its first
+    decision within the master's tolerance (objective within 1e-5)."""
+    import json
+    import os
+
+    import oracle
+    from conftest import oracle_problem
+    torch = torch_cuda()
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "prostate_seed0_r50.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored trajectory")
+    with open(path) as f:
+        doc = json.load(f)
+    reqs = [("prostate", 0, "f32", 50), ("tiny", 0, "f64", 10), ("tiny", 1, "f32", 6)]
+    phs = [make_phantom(n, s) for n, s, _, _ in reqs]
+    server = dao.Server(max_live=3, stream=torch.cuda.current_stream().cuda_stream)
+    try:
+        res, _, _ = _run(server, reqs, phs)
+    finally:
+        server.close()
+    # the FP64 32^3 plan against the oracle's solve
+    P = oracle_problem(phs[1])
+    ref = oracle.solve(P, 10, eps=1e-6)
+    r = res[1]
+    assert r["rounds"] == len(ref["log"])
+    for k, rec in enumerate(ref["log"]):
+        if rec["gap"] > 1e-9:
+            assert r["round_beam"][k] == rec["beam"], k
+        assert abs(r["round_F"][k] - rec["F"]) <= 1e-9 * rec["F"], k
+    # the prostate-shaped plan against the stored trajectory
+    r = res[0]
+    assert r["rounds"] == 50
+    rc1 = doc["rc1"]
+    matched = 0
+    for k, rec in enumerate(doc["rounds"]):
+        if r["round_beam"][k] != rec["beam"] or abs(r["round_rc"][k] - rec["rc"]) > 1e-6 * abs(rc1):
+            assert rec["gap"] <= 1e-6 * abs(rc1), (k, rec["gap"])
+            break
+        assert abs(r["round_F"][k] - rec["F"]) <= 1e-5 * rec["F"], k
+        matched += 1
+    print(f"[serve] prostate served plan: {matched} of 50 rounds match the oracle's, F {r['F']:.10e} "
+          f"oracle {doc['F']:.10e}", flush=True)
