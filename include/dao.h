@@ -263,6 +263,19 @@ dao_status dao_gradient(dao_ctx* ctx, const void* d_dev, void* g_dev, double* F)
 dao_status dao_price(dao_ctx* ctx, const double* g_dev, int32_t* beam, int16_t* leaves,
                      double* rc, double* gap);
 
+/* For callers that cannot allocate device memory or call allocating library
+ * routines during the call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid it): dao_price with the same arguments,
+ * outputs and errors, whose pricing launch keeps its scratch (per-row
+ * records, the result and the arrival counters) in a static device array of
+ * the library instead of the context's buffers.  The call allocates nothing;
+ * the array's address is looked up once per device when the first context on
+ * that device is created.  Limit: at most 4096 MLC rows (DAO_EINVAL above).
+ * Every call on one device uses the same array and leaves its contents
+ * behind (the counters are cleared at the start of each call): calls that
+ * overlap on one device, from any thread or stream, race. */
+dao_status dao_price_noalloc(dao_ctx* ctx, const double* g_dev, int32_t* beam, int16_t* leaves,
+                             double* rc, double* gap);
 
 /* Master state.  dao_reset empties the pool (y = 0, dose 0).
  * dao_add_aperture appends an aperture with y = 0 (leaves as in dao_price;

@@ -98,6 +98,8 @@ _SIGS = {
     "dao_gradient": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(c_double)]),
     "dao_price": (c_int32, [c_void_p, c_void_p, POINTER(c_int32), POINTER(c_int16),
                             POINTER(c_double), POINTER(c_double)]),
+    "dao_price_noalloc": (c_int32, [c_void_p, c_void_p, POINTER(c_int32), POINTER(c_int16),
+                                    POINTER(c_double), POINTER(c_double)]),
     "dao_reset": (c_int32, [c_void_p]),
     "dao_add_aperture": (c_int32, [c_void_p, c_int32, POINTER(c_int16)]),
     "dao_master_step": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
@@ -328,6 +330,13 @@ class DaoContext:
         beam, lv, rc, gap = self._price_out()
         self._check(self._lib.dao_price(self._h, c_void_p(_addr(g64)), byref(beam), _ptr(lv, c_int16),
                                         byref(rc), byref(gap)))
+        return self._price_result(beam, lv, rc, gap)
+
+    def price_noalloc(self, g64) -> Dict:
+        """dao_price_noalloc: dao_price with the library's static scratch."""
+        beam, lv, rc, gap = self._price_out()
+        self._check(self._lib.dao_price_noalloc(self._h, c_void_p(_addr(g64)), byref(beam), _ptr(lv, c_int16),
+                                                byref(rc), byref(gap)))
         return self._price_result(beam, lv, rc, gap)
 
     def price_current(self) -> Dict:

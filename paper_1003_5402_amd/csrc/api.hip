@@ -127,6 +127,7 @@ struct dao_ctx {
     double dk_scale = 1.0;            // D_K = dk_scale * stored value
     double* tau_int = nullptr;        // per-voxel threshold shifts, internal rows (null: none)
     double* tau_ext = nullptr;        // the same in caller order
+    unsigned char* scratch_dev = nullptr;   // this device's copy of the static pricing scratch
     double* gradk = nullptr;
     std::vector<int32_t> pool_beam;
     std::vector<int16_t> pool_lv;
@@ -383,6 +384,45 @@ dao_status tune_products(dao_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     (void)hipFree(out);
     return s;
+}
+
+// Scratch of dao_price_noalloc: the per-row records, the result and the
+// arrival counters of one pricing launch, for up to NOALLOC_MAX_ROWS MLC
+// rows.  One copy per device (static device memory, held until the process
+// ends); every call on a device shares it.  Host code never passes the
+// array's name to a kernel: its device address is looked up once per device
+// (hipGetSymbolAddress) and kept in g_scratch_addr.
+constexpr size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+constexpr int NOALLOC_MAX_ROWS = 4096;
+constexpr size_t NOALLOC_ROWS_OFF = 0;
+constexpr size_t NOALLOC_PR_OFF = align256(size_t(NOALLOC_MAX_ROWS) * sizeof(RowRec));
+constexpr size_t NOALLOC_ARR_OFF = align256(NOALLOC_PR_OFF + sizeof(PriceResult));
+constexpr size_t NOALLOC_BYTES = align256(NOALLOC_ARR_OFF + sizeof(Arrival));
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch_addr;   // device -> address of its scratch copy
+
+// Device address of the current device's scratch copy (looked up on first use).
+dao_status scratch_address(unsigned char** out, std::string* err) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        *err = "hipGetDevice failed";
+        return DAO_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it == g_scratch_addr.end()) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            *err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return DAO_EDEVICE;
+        }
+        it = g_scratch_addr.emplace(dev, static_cast<unsigned char*>(ptr)).first;
+    }
+    *out = it->second;
+    return DAO_OK;
 }
 
 PoolView pool_view(dao_ctx* c) {
@@ -845,6 +885,11 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     TRY(dev_alloc(c, &c->ms, sizeof(MasterState)));
     TRY(dev_alloc(c, &c->pr, sizeof(PriceResult)));
     TRY(dev_alloc(c, &c->rowrec, std::max<int64_t>(1, c->R) * sizeof(RowRec)));
+    {
+        // this device's copy of the static scratch of dao_price_noalloc
+        std::string e;
+        if (scratch_address(&c->scratch_dev, &e) != DAO_OK) return c->fail(DAO_EDEVICE, e);
+    }
     c->nparts = std::max<int64_t>({c->slab_blocks(), c->elem_blocks(c->Vpad), c->elem_blocks(c->V)});
     TRY(dev_alloc(c, &c->parts, c->nparts * sizeof(Rec)));
     TRY(dev_alloc(c, &c->upd_parts, c->slab_blocks() * sizeof(Rec)));
@@ -1653,6 +1698,26 @@ dao_status dao_price(dao_ctx* c, const double* g, int32_t* beam, int16_t* leaves
     if (!c) return DAO_EINVAL;
     if (!g) return c->fail(DAO_EINVAL, "null prices");
     return price_on(c, g, beam, leaves, rc, gap);
+}
+
+dao_status dao_price_noalloc(dao_ctx* c, const double* g, int32_t* beam, int16_t* leaves, double* rc,
+                             double* gap) {
+    if (!c) return DAO_EINVAL;
+    if (!g) return c->fail(DAO_EINVAL, "null prices");
+    if (c->R > NOALLOC_MAX_ROWS)
+        return c->fail(DAO_EINVAL, std::to_string(c->R) + " MLC rows exceed the " +
+                                       std::to_string(NOALLOC_MAX_ROWS) + " rows of the static pricing scratch");
+    if (!c->scratch_dev) return c->fail(DAO_ESTATE, "static pricing scratch unavailable");
+    RowRec* rows = reinterpret_cast<RowRec*>(c->scratch_dev + NOALLOC_ROWS_OFF);
+    PriceResult* pr = reinterpret_cast<PriceResult*>(c->scratch_dev + NOALLOC_PR_OFF);
+    Arrival* arr = reinterpret_cast<Arrival*>(c->scratch_dev + NOALLOC_ARR_OFF);
+    // the arrival counters must start at zero whatever the last call left
+    // (a fill kernel: no memset node if the caller captures the stream)
+    constexpr int64_t narr = int64_t(sizeof(Arrival) / sizeof(uint32_t));
+    k_fill<uint32_t><<<(narr + BLOCK - 1) / BLOCK, BLOCK, 0, c->stream>>>(reinterpret_cast<uint32_t*>(arr), narr,
+                                                                         0u);
+    LAUNCHCHK(c);
+    return price_with(c, g, rows, pr, arr, beam, leaves, rc, gap);
 }
 
 dao_status dao_reset(dao_ctx* c) {
