@@ -282,14 +282,41 @@ def profile_master(dao, ctx, n_ap, algo_step_bytes, ls_pass_bytes):
     return kernels
 
 
-def time_products(ctx, info, iters, scrub):
+def read_at_size(torch, nbytes, scrub, iters=10):
+    """A plain streaming read of `nbytes` (torch.sum over FP32), cold: the
+    1 GiB scrub buffer is read before every timed launch.  The practical
+    ceiling for a kernel that reads that many bytes once, launch ramp and
+    drain included.  Returns GB/s (best of `iters`)."""
+    x = torch.ones(max(1, int(nbytes) // 4), dtype=torch.float32, device="cuda")
+    best = 0.0
+    for _ in range(iters):
+        scrub.sum()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        x.sum()
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, x.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del x
+    return best
+
+
+def time_products(ctx, info, iters, scrub, torch=None):
     """k_dose / k_gradT (the kernels behind dao_dose / dao_gradient): warm
-    back to back, and cold after a 1 GiB scrub read before every launch."""
+    back to back, and cold after a 1 GiB scrub read before every launch;
+    with `torch`, also the cold streaming-read rate at each product's byte
+    count."""
     cold_iters = max(1, iters // 10)
     ud, ug = ctx.time_product(0, iters), ctx.time_product(1, iters)
     udc, ugc = ctx.time_product_cold(0, cold_iters, scrub), ctx.time_product_cold(1, cold_iters, scrub)
     bd, bg = info["bytes_dose"], info["bytes_gradient"]
-    return {"dose_bytes": bd, "gradient_bytes": bg, "dose_us": ud, "gradient_us": ug,
+    extra = {}
+    if torch is not None:
+        rd, rg = read_at_size(torch, bd, scrub), read_at_size(torch, bg, scrub)
+        extra = {"read_cold_GBs_at_dose_bytes": rd, "read_cold_GBs_at_gradient_bytes": rg,
+                 "dose_cold_vs_read": bd / (udc * 1e-6) / 1e9 / rd,
+                 "gradient_cold_vs_read": bg / (ugc * 1e-6) / 1e9 / rg}
+    return {**extra, "dose_bytes": bd, "gradient_bytes": bg, "dose_us": ud, "gradient_us": ug,
             "dose_cold_us": udc, "gradient_cold_us": ugc,
             "dose_GBs": bd / (ud * 1e-6) / 1e9, "gradient_GBs": bg / (ug * 1e-6) / 1e9,
             "dose_cold_GBs": bd / (udc * 1e-6) / 1e9, "gradient_cold_GBs": bg / (ugc * 1e-6) / 1e9,
@@ -333,6 +360,8 @@ def main():
     ap.add_argument("--serve-max-live", type=int, default=8)
     ap.add_argument("--pmc-workload", nargs="?", const="plan", default=None, choices=["plan", "products"],
                     help="one plan (or cold product launches) plus a calibration copy, for rocprofv3 --pmc runs")
+    ap.add_argument("--round-log", default=None,
+                    help="append the per-round records of one untimed headline plan to this JSON-lines file")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the plan is a single-GPU workload "
@@ -363,6 +392,8 @@ def main():
     create_s = time.perf_counter() - t0
     log(f"[bench] {args.config}: {plan['plans_s']:.3f} plans/s, {plan['master_steps_per_plan']} steps, "
         f"capped rounds {plan['capped_rounds']}, form {plan['master_form']}")
+    if args.round_log:
+        ctx.solve(n_ap, round_log=args.round_log)   # untimed: the timed plans are deterministic
 
     # the master kernel, with the algorithmic bytes of a master step: one
     # forward and one transposed beamlet product, and per line-search
@@ -377,7 +408,7 @@ def main():
     log(f"[bench] device copy: {hbm_copy:.0f} GB/s")
 
     scrub = torch.zeros(1 << 30, dtype=torch.uint8, device="cuda")
-    products = time_products(ctx, info, args.product_iters, scrub)
+    products = time_products(ctx, info, args.product_iters, scrub, torch)
     log(f"[bench] {args.config} products: {products}")
 
     # the precision form: D stored in 16 bits (FP16 / BF16 values over a
@@ -417,7 +448,7 @@ def main():
         akern = profile_master(dao, actx, pha.n_apertures, ainfo["bytes_dose"] + ainfo["bytes_gradient"],
                                ainfo["n_vox_nonempty"] * 13)
         also["master_kernels"] = akern
-        also["products"] = time_products(actx, ainfo, args.product_iters, scrub)
+        also["products"] = time_products(actx, ainfo, args.product_iters, scrub, torch)
         actx.close()
         log(f"[bench] {args.also}: {also['plans_s']:.3f} plans/s")
         del pha

@@ -149,7 +149,11 @@ typedef struct {
                                x staged on chip, 4 slices of 64 rows per workgroup;
                                1 as 0 with 8 entries per lane in flight; 2 x read from
                                device memory with 8 in flight (native d_format only);
-                               3 as 0 with 8 slices per workgroup */
+                               3 as 0 with 8 slices per workgroup; 4, 5, 6 whole rows
+                               per lane (every entry group of a row in flight, x staged
+                               once per workgroup) on a grid of 1, 2 or 4 workgroups of
+                               256 threads per compute unit, each walking slices with
+                               the grid's stride */
     int32_t gradient_depth; /* with product_tune 0: transposed product entries per thread
                                in flight, 4 (default), 8 or 16 */
     int32_t direction;      /* master search direction (Section 2.3, gradient projection):
@@ -167,6 +171,12 @@ typedef struct {
                                FP32 / FP64 as before */
     int32_t residual_rounds; /* with d_residual 2: the plan's last this many rounds (5) run in
                                the accurate form, see d_residual */
+    int32_t graphs;         /* 1: the pricing sequence of every round (exact FP64 dose,
+                               objective, FP64 prices, pricing scan, result copy) replays,
+                               on the context stream, a HIP graph captured at its first use
+                               (one per residual setting) on a stream the context creates
+                               for that; 0 (default): the same launches one by one.  Same
+                               results */
 } dao_options;
 
 /* Search direction of the master's gradient projection.  r is the projected

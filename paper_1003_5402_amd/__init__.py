@@ -12,4 +12,4 @@ from __future__ import annotations
 from .binding import (DAO_DFMT_BF16, DAO_DFMT_F16, DAO_DFMT_NATIVE, DAO_EDEVICE, DAO_EINVAL, DAO_ENOMEM,
                       DAO_EOPTIMAL, DAO_ESTALLED, DAO_ESTATE, DAO_F32, DAO_F64, DAO_MASTER_APERTURE,
                       DAO_MASTER_BEAMLET, DAO_OK, DaoError, DaoContext, Server, encode_values,
-                      load_library, solve_batch, symbols)  # noqa: F401
+                      load_library, solve_batch, symbols, write_round_log)  # noqa: F401

@@ -53,7 +53,8 @@ class dao_options(ctypes.Structure):
                 ("master", c_int32), ("d_format", c_int32), ("d_residual", c_int32),
                 ("persistent", c_int32), ("product_tune", c_int32), ("dose_variant", c_int32),
                 ("gradient_depth", c_int32), ("direction", c_int32), ("apertures_per_round", c_int32),
-                ("dk_format", c_int32), ("residual_rounds", c_int32)]
+                ("dk_format", c_int32), ("residual_rounds", c_int32),
+                ("graphs", c_int32)]
 
 
 class dao_info_t(ctypes.Structure):
@@ -198,6 +199,33 @@ def _plan_dict(P, arr, st):
     return dict(status=st, rounds=r, stop=P.stop, F=P.F, rc1=P.rc1, total_steps=P.total_steps,
                 total_ls_evals=P.total_ls_evals, price_s=P.price_s, master_s=P.master_s,
                 capped_rounds=P.capped_rounds, **{k: v[:r].copy() for k, v in arr.items()})
+
+
+STOP_NAMES = {1: "kkt", 2: "step_cap", 3: "zero_direction"}
+
+
+def write_round_log(plan: Dict, out, **meta) -> int:
+    """One JSON line per round of a plan dict (from solve / solve_batch /
+    the server): round, entering beam, reduced cost, decision gap, objective
+    after the master, master steps, KKT residual and the master's stop
+    reason.  `out` is a path (appended to) or a text file; `meta` is copied
+    into every line.  Returns the number of lines written."""
+    import json
+    lines = []
+    for k in range(int(plan["rounds"])):
+        rec = dict(meta)
+        rec.update(round=k, beam=int(plan["round_beam"][k]), rc=float(plan["round_rc"][k]),
+                   gap=float(plan["round_gap"][k]), F=float(plan["round_F"][k]),
+                   steps=int(plan["round_steps"][k]), kkt=float(plan["round_kkt"][k]),
+                   stop=STOP_NAMES.get(int(plan["round_stop"][k]), int(plan["round_stop"][k])))
+        lines.append(json.dumps(rec))
+    text = "".join(line + "\n" for line in lines)
+    if isinstance(out, (str, os.PathLike)):
+        with open(out, "a") as f:
+            f.write(text)
+    else:
+        out.write(text)
+    return len(lines)
 
 
 def solve_batch(ctxs, n_apertures) -> list:
@@ -453,10 +481,15 @@ class DaoContext:
         self._check(self._lib.dao_profile_stop(self._h, byref(n), byref(w), byref(us), byref(b)))
         return dict(launches=n.value, working_launches=w.value, total_us=us.value, total_bytes=b.value)
 
-    def solve(self, n_apertures: int) -> Dict:
+    def solve(self, n_apertures: int, round_log=None) -> Dict:
+        """dao_solve; with `round_log` (a path or text file) the per-round
+        records are appended to it as JSON lines (write_round_log)."""
         P, arr = _plan_arrays(n_apertures)
         st = self._check(self._lib.dao_solve(self._h, int(n_apertures), byref(P)))
-        return _plan_dict(P, arr, st)
+        plan = _plan_dict(P, arr, st)
+        if round_log is not None:
+            write_round_log(plan, round_log)
+        return plan
 
     def solve_resume(self, n_apertures: int) -> Dict:
         """Column generation continued from the current pool (dao_solve_resume)."""

@@ -87,6 +87,7 @@ struct dao_ctx {
     CoopSync* coop = nullptr;          // grid-reduction scratch of the persistent master
     double* coop_recs = nullptr;       // [2][coop_grid][RECW]
     int coop_grid = 0;                 // co-resident workgroups (0: persistent master unavailable)
+    int ncu = 0;                       // compute units of the device
     int coop_lds_max = 0;              // dynamic LDS the on-chip variant may use (0: never)
     void* batch_args = nullptr;        // [MAX_BATCH] CoopArgs of a batched master launch
     int32_t* batch_gstart = nullptr;   // [MAX_BATCH + 1] first workgroup of each solve
@@ -106,6 +107,8 @@ struct dao_ctx {
     int loop_tighten = 0;              // tightenings so far
     int last_stop = 0;                 // stop reason of the last master solve (MasterState.stop_reason)
     std::vector<hipEvent_t> prof_events;
+    hipGraphExec_t price_exec[2] = {nullptr, nullptr};   // captured pricing sequence (without / with residual)
+    hipStream_t cap_stream = nullptr;  // capture only (the null stream cannot be captured); replays use `stream`
     size_t prof_used = 0;
     void* g = nullptr;         // [N] ctx type
     double* g64 = nullptr;     // [N]
@@ -125,6 +128,7 @@ struct dao_ctx {
     double* gabs64 = nullptr;         // [N] D^T |grad F| (rounding bound of the prices)
     double* uabs64 = nullptr;         // [Vpad] |grad F|
     double dk_scale = 1.0;            // D_K = dk_scale * stored value
+    double dk16_scale = 1.0;          // dk_scale while D_K is stored in FP16
     double* tau_int = nullptr;        // per-voxel threshold shifts, internal rows (null: none)
     double* tau_ext = nullptr;        // the same in caller order
     unsigned char* scratch_dev = nullptr;   // this device's copy of the static pricing scratch
@@ -154,6 +158,9 @@ struct dao_ctx {
         if (pc_h) (void)hipHostFree(pc_h);
         if (batch_host) (void)hipHostFree(batch_host);
         for (auto e : prof_events) (void)hipEventDestroy(e);
+        for (auto g : price_exec)
+            if (g) (void)hipGraphExecDestroy(g);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
 
     dao_status fail(dao_status s, std::string m) {
@@ -297,6 +304,14 @@ void launch_dose(dao_ctx* c, const T* x, T* d_out, int var = -1) {
         else if (var == 3)
             k_dose<T, VT, LO, 0, 2 * SPB><<<(c->nslices + 2 * SPB - 1) / (2 * SPB), SLAB_THREADS, lds, c->stream>>>(
                 sell_view<VT>(c), c->perm, c->Vpad, x, int(c->N), stage, c->col_scale, d_out);
+        else if (var >= 4 && stage) {
+            // whole rows per lane on a grid of 1, 2 or 4 workgroups per CU
+            const int per_cu = var == 4 ? 1 : var == 5 ? 2 : 4;
+            const int64_t need = (c->nslices + ROWS_THREADS / WAVE - 1) / (ROWS_THREADS / WAVE);
+            const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(need, int64_t(std::max(1, c->ncu)) * per_cu));
+            k_dose_rows<T, VT, LO><<<grid, ROWS_THREADS, lds, c->stream>>>(sell_view<VT>(c), c->perm, c->Vpad, x,
+                                                                         int(c->N), c->col_scale, d_out);
+        }
         else
             k_dose<T, VT, LO, 8><<<c->slab_blocks(), SLAB_THREADS, lds, c->stream>>>(
                 sell_view<VT>(c), c->perm, c->Vpad, x, int(c->N), stage, c->col_scale, d_out);
@@ -344,7 +359,9 @@ dao_status tune_products(dao_ctx* c) {
     if (he == hipSuccess) he = hipMemsetAsync(c->u, 0, c->Vpad * sizeof(T), c->stream);
     const bool native = c->opt.d_format == DAO_DFMT_NATIVE;
     const int pfs[3] = {4, 8, 16};
-    double best_d[4] = {1e30, 1e30, 1e30, 1e30}, best_g[3] = {1e30, 1e30, 1e30};
+    constexpr int NDV = 7;   // forward variants: 0-3 slab forms, 4-6 whole rows per lane
+    double best_d[NDV], best_g[3] = {1e30, 1e30, 1e30};
+    for (double& b : best_d) b = 1e30;
     constexpr int REPS = 3, LAUNCHES = 8;
     auto time_one = [&](auto&& launch) -> double {
         launch();
@@ -357,8 +374,8 @@ dao_status tune_products(dao_ctx* c) {
         return double(ms);
     };
     for (int r = 0; r < REPS && he == hipSuccess; ++r) {
-        for (int v = 0; v < 4; ++v)
-            if (native || v != 2)
+        for (int v = 0; v < NDV; ++v)
+            if ((native || v != 2) && (v < 4 || c->stage_x()))
                 best_d[v] = std::min(best_d[v], time_one([&] {
                 launch_dose<T>(c, static_cast<const T*>(c->dx), static_cast<T*>(out), v);
             }));
@@ -372,7 +389,7 @@ dao_status tune_products(dao_ctx* c) {
     if (s == DAO_OK) {
         // a variant replaces the plain one only when clearly faster (2 %)
         c->dose_var = 0;
-        for (int v = 1; v < 4; ++v)
+        for (int v = 1; v < NDV; ++v)
             if (best_d[v] < 0.98 * best_d[c->dose_var]) c->dose_var = v;
         int bg = 0;
         for (int v = 1; v < 3; ++v)
@@ -683,27 +700,86 @@ dao_status refresh_objective(dao_ctx* c) {
     return DAO_OK;
 }
 
-// FP64 prices at the current intensities: the dose is first recomputed as
-// D (A y) in FP64, then g64 = D^T grad F(d) with FP64 sums.
+// The pricing launches after x = A y: d = D x in FP64, grad F and F, the
+// FP64 prices, the pricing scan and the result's copy to the host.  Every
+// argument is fixed per context (and per residual setting), so the sequence
+// can be captured once as a graph.
 template <class T>
-dao_status price_current(dao_ctx* c, int32_t* beam, int16_t* leaves, double* rc, double* gap) {
-    dao_status s = refresh_dose_exact<T>(c);
-    if (s != DAO_OK) return s;
-    s = refresh_objective<T>(c);
+dao_status enqueue_price_tail(dao_ctx* c) {
+    with_values<T>(c, [&](auto tag) {
+        using VT = typename decltype(tag)::VT;
+        constexpr bool LO = decltype(tag)::LO;
+        k_dose_exact<VT, LO><<<c->slab_blocks(), SLAB_THREADS, c->stage_x64() ? c->N * 8 : 0, c->stream>>>(
+            sell_view<VT>(c), c->Vpad, c->x64, int(c->N), c->stage_x64(), c->col_scale, c->tau_int, c->d);
+    });
+    dao_status s = refresh_objective<T>(c);
     if (s != DAO_OK) return s;
     launch_gradT<T, double, double, double>(c, c->u64, c->g64);
+    k_price<<<c->price_blocks(), BLOCK, 0, c->stream>>>(price_geom(c), c->g64, c->rowrec, c->pr, c->arr);
     LAUNCHCHK(c);
-    return price_on(c, c->g64, beam, leaves, rc, gap);
+    HIPCHK(c, hipMemcpyAsync(c->pr_h, c->pr, sizeof(PriceResult), hipMemcpyDeviceToHost, c->stream));
+    return DAO_OK;
+}
+
+// FP64 prices at the current intensities: the dose is first recomputed as
+// D (A y) in FP64, then g64 = D^T grad F(d) with FP64 sums.  With
+// dao_options.graphs the launches after x = A y replay a graph captured on
+// the context stream at first use (one per residual setting).
+template <class T>
+dao_status price_current(dao_ctx* c, int32_t* beam, int16_t* leaves, double* rc, double* gap) {
+    k_pool_x<<<(c->N + BLOCK - 1) / BLOCK, BLOCK, 0, c->stream>>>(pool_view(c), c->K, c->y, c->x64);
+    LAUNCHCHK(c);
+    dao_status s = DAO_OK;
+    if (c->opt.graphs) {
+        const int gi = (c->opt.d_residual == 1 || (c->opt.d_residual == 2 && c->lo_now)) ? 1 : 0;
+        if (!c->price_exec[gi]) {
+            // recorded on a stream of the context's own: nothing runs during
+            // the capture, and the caller's stream may be the null stream
+            if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+            HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            const hipStream_t run_stream = c->stream;
+            c->stream = c->cap_stream;
+            s = enqueue_price_tail<T>(c);
+            c->stream = run_stream;
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+            if (s != DAO_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return s;
+            }
+            HIPCHK(c, e);
+            const hipError_t ei = hipGraphInstantiate(&c->price_exec[gi], graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIPCHK(c, ei);
+        }
+        HIPCHK(c, hipGraphLaunch(c->price_exec[gi], c->stream));
+    } else {
+        s = enqueue_price_tail<T>(c);
+        if (s != DAO_OK) return s;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (beam) *beam = c->pr_h->beam;
+    if (leaves) std::memcpy(leaves, c->pr_h->leaves, sizeof(int16_t) * 2 * c->pr_h->n_rows);
+    if (rc) *rc = c->pr_h->rc;
+    if (gap) *gap = c->pr_h->gap;
+    return DAO_OK;
 }
 
 template <class T>
 dao_status reset_state(dao_ctx* c) {
     const int64_t eb = c->elem_blocks(c->Vpad);
     // a new pool starts in the fast form of the selective residual
+    const bool dk_was_f32 = c->final_phase && !c->dk16;
     c->lo_now = false;
     c->final_phase = false;
     c->reprices = 0;
     c->dk16 = std::is_same<T, float>::value && c->ap_master() && c->opt.dk_format == DAO_DFMT_F16;
+    c->dk_scale = c->dk16 ? c->dk16_scale : 1.0;
+    // FP16 columns are written over the FP32 ones of the last final phase:
+    // clear the buffer, so that no slot beyond the pool holds a stale value
+    // (the products multiply every slot of a row's last group by 0)
+    if (c->dk16 && dk_was_f32)
+        HIPCHK(c, hipMemsetAsync(c->dk, 0, size_t(c->Vpad) * KS * sizeof(T), c->stream));
     // zero dose; the master keeps d - tau
     k_neg_or_zero<<<eb, BLOCK, 0, c->stream>>>(c->tau_int, c->Vpad, c->d);
     k_fill<double><<<1, BLOCK, 0, c->stream>>>(c->y, c->opt.max_apertures, 0.0);
@@ -899,12 +975,12 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     // entry is a sum of D entries, so the stored values stay well inside
     // FP16's range)
     c->dk16 = std::is_same<T, float>::value && c->ap_master() && c->opt.dk_format == DAO_DFMT_F16;
-    c->dk_scale = 1.0;
     if (c->dk16) {
         float mx = 0.0f;
         for (float v : L.col_scale) mx = std::max(mx, v);
-        c->dk_scale = mx > 0.0f ? double(mx) : 1.0;
+        c->dk16_scale = mx > 0.0f ? double(mx) : 1.0;
     }
+    c->dk_scale = c->dk16 ? c->dk16_scale : 1.0;
     // bytes per stored D_K value; the selective residual switches D_K to FP32
     // for the final rounds, so its buffer holds FP32 values
     const size_t dkb = (c->dk16 && c->opt.d_residual != 2) ? sizeof(__half) : ts;
@@ -965,7 +1041,13 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     HIPCHK(c, hipMemsetAsync(c->p, 0, km * 8, c->stream));
     HIPCHK(c, hipMemsetAsync(c->q, 0, c->Vpad * ts, c->stream));
     HIPCHK(c, hipMemsetAsync(c->dx, 0, c->N * ts, c->stream));
+    {
+        int dev = 0;
+        HIPCHK(c, hipGetDevice(&dev));
+        HIPCHK(c, hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    }
     c->dose_var = c->opt.dose_variant;
+    if (c->dose_var >= 4 && !c->stage_x()) c->dose_var = 0;   // the row form stages x
     c->gradT_pf = c->opt.gradient_depth;
     if (c->opt.product_tune) {
         s = tune_products<T>(c);
@@ -1126,6 +1208,7 @@ dao_status enter_final_phase(dao_ctx* c) {
     c->lo_now = true;
     if (c->dk16) {
         c->dk16 = false;
+        c->dk_scale = 1.0;   // FP32 columns hold D_K itself
         HIPCHK(c, hipMemsetAsync(c->dk, 0, size_t(c->Vpad) * KS * sizeof(T), c->stream));
         for (int k = 0; k < c->K; ++k) {
             const dao_status s = build_dk_column<T>(c, k);
@@ -1567,6 +1650,7 @@ void dao_default_options(dao_options* o) {
     o->apertures_per_round = 1;
     o->dk_format = DAO_DFMT_NATIVE;
     o->residual_rounds = 5;
+    o->graphs = 0;
 }
 
 const char* dao_create_error(void) { return g_create_error.c_str(); }
@@ -1611,11 +1695,6 @@ dao_status dao_create(const dao_matrix* D, const dao_beams* beams, const dao_str
     c->nnz = L->nnz;
     c->Vnz = L->Vnz;
     c->Vpad = std::max<int64_t>(L->Vpad, SLICE);
-    // the master passes walk rows in batches of Batch<DT>::ROWS: 128 with an
-    // FP16 D_K, so its padded row count is a multiple of 128 (the extra
-    // rows belong to no structure and carry no dose)
-    if (opt.dtype == DAO_F32 && opt.master == DAO_MASTER_APERTURE && opt.dk_format == DAO_DFMT_F16)
-        c->Vpad = (c->Vpad + 127) / 128 * 128;
     c->nslices = L->nslices;
     c->B = L->B;
     c->R = L->R;
@@ -1626,7 +1705,7 @@ dao_status dao_create(const dao_matrix* D, const dao_beams* beams, const dao_str
     c->rows_per_beam.assign(beams->rows_per_beam, beams->rows_per_beam + beams->n_beams);
     c->row_len = L->row_len;
     c->beam_row0 = L->beam_row0;
-    if (L->Vpad < c->Vpad) {   // padding rows past the layout's (no non-empty row, or FP16 D_K batches)
+    if (L->Vpad < c->Vpad) {   // no non-empty row at all: keep one padding slice
         L->perm.resize(c->Vpad, -1);
         L->cls_int.resize(c->Vpad, uint8_t(L->n_struct));
         if (!L->tau_int.empty()) L->tau_int.resize(c->Vpad, 0.0);

@@ -512,6 +512,87 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_dose(SellView<VT> S, const int
     }
 }
 
+// d_ext[perm[r]] = (D x)_r, whole rows per lane: a grid of a few
+// workgroups per compute unit, each staging x (times the per-beamlet scale
+// of a 16-bit format) in LDS once and then walking slices with the grid's
+// stride (wavefront w of workgroup b: slices b * 4 + w, then every
+// gridDim.x * 4 further).  The next slice's header is loaded while the
+// current one is summed, and each lane issues GB groups of its row before
+// adding them, so a whole row of the head-and-neck matrix is in flight at
+// once.  The terms are added chunk by chunk exactly as the slab form adds
+// them (the KSPLIT chunks of whole groups, each from 0 in stored order, then
+// the chunk sums in order, empty chunks included), so the result is the
+// same bit for bit.
+constexpr int ROWS_THREADS = 256;
+template <class T, class VT = T, bool LO = false, int GB = 8>
+__global__ void __launch_bounds__(ROWS_THREADS) k_dose_rows(SellView<VT> S, const int32_t* __restrict__ perm,
+                                                            int64_t Vpad, const T* __restrict__ x, int N,
+                                                            const float* __restrict__ scale, T* __restrict__ d_ext) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* xs = reinterpret_cast<T*>(smem);
+    constexpr int NW = ROWS_THREADS / WAVE;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int64_t stride = int64_t(gridDim.x) * NW;
+    int64_t s = int64_t(blockIdx.x) * NW + wave;
+    uint32_t nbase = 0;
+    int nwid = 0;
+    if (s < S.nslices) {
+        nbase = S.slice_ptr[s];
+        nwid = S.slice_w[s];
+    }
+    if (scale)
+        for (int i = threadIdx.x; i < N; i += blockDim.x) xs[i] = T(x[i]) * T(scale[i]);
+    else
+        for (int i = threadIdx.x; i < N; i += blockDim.x) xs[i] = T(x[i]);
+    __syncthreads();
+    for (; s < S.nslices; s += stride) {
+        const uint32_t base = nbase;
+        const int w = nwid;   // a multiple of 4
+        if (s + stride < S.nslices) {
+            nbase = S.slice_ptr[s + stride];
+            nwid = S.slice_w[s + stride];
+        }
+        const int ng = w >> 2;
+        const int gpc = (ng + KSPLIT - 1) / KSPLIT;   // groups per chunk, as chunk_range
+        const size_t o = size_t(base) + size_t(lane) * 4;
+        T sum = T(0), cur = T(0);
+        int q = 0;
+        for (int g0 = 0; g0 < ng; g0 += GB) {
+            Quad<VT> v[GB];
+            Quad<uint16_t> c[GB];
+            Quad<__half> l[GB];
+#pragma unroll
+            for (int u = 0; u < GB; ++u) {
+                if (g0 + u < ng) {
+                    const size_t e = o + size_t(g0 + u) * (4 * SLICE);
+                    v[u] = *reinterpret_cast<const Quad<VT>*>(S.val + e);
+                    c[u] = *reinterpret_cast<const Quad<uint16_t>*>(S.col + e);
+                    if (LO) l[u] = *reinterpret_cast<const Quad<__half>*>(S.lo + e);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < GB; ++u) {
+                if (g0 + u < ng) {
+                    if ((g0 + u) / gpc != q) {   // the next chunk begins
+                        sum += cur;
+                        cur = T(0);
+                        ++q;
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) cur += T(dval2<VT, LO>(v[u].e[e], &l[u].e[e])) * xs[c[u].e[e]];
+                }
+            }
+        }
+        sum += cur;
+        for (++q; q < KSPLIT; ++q) sum += T(0);   // the empty chunks
+        const int64_t row = s * SLICE + lane;
+        if (row < Vpad) {
+            const int32_t j = perm[row];
+            if (j >= 0) d_ext[j] = sum;
+        }
+    }
+}
+
 // The master dose from its intensities, in FP64 throughout: d[row] =
 // (D x64)_row over internal rows, every product D_ij x_i and every sum in
 // double (the stored D values are exact in double; a 16-bit format's scale

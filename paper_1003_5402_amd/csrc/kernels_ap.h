@@ -139,10 +139,14 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_dk_column(SellView<VT> S, int6
 // holds aperture slots c*EPL .. c*EPL+EPL-1), then the batch is handled one
 // row per lane for the per-voxel work (coalesced d, q and class access, all
 // lanes active), with row results exchanged through LDS.
+// The per-voxel stage of a batch gives each lane one row, so a batch holds at
+// most WAVE rows: 16 loads per lane for FP32 and FP64 storage (64 and 32
+// rows), 8 for FP16 storage (8 rows per instruction, 64 rows).
 template <class T>
 struct Batch {
-    static constexpr int ITERS = 16;
-    static constexpr int ROWS = ITERS * DKG<T>::RPW;   // 64 (FP32), 32 (FP64) or 128 (FP16 storage)
+    static constexpr int ITERS = 16 * DKG<T>::RPW > WAVE ? WAVE / DKG<T>::RPW : 16;
+    static constexpr int ROWS = ITERS * DKG<T>::RPW;
+    static_assert(ROWS <= WAVE, "one row per lane in the per-voxel stage");
 };
 
 // Update pass (PH_UPD).  Record of workgroup b in parts2[b * (KS + 1)]:

@@ -399,6 +399,17 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             double* su = s_u[wave];
             for (int64_t bt = bat0 + wave; bt < bat1; bt += NW) {
                 const int64_t base = bt * ROWS;
+                // this lane's row of the per-voxel stage: its d, q and class
+                // are loaded together with the batch's D_K rows, so the two
+                // memory round trips overlap
+                double d_pre = 0.0, q_pre = 0.0;
+                uint8_t c_pre = 0;
+                if (lane < ROWS) {
+                    const int64_t row = base + lane;
+                    if (mode != 1) d_pre = d_at(row);
+                    if (mode == 0) q_pre = double(q_at(row));
+                    c_pre = cls_at(row);
+                }
                 V v[IT];
                 if (LDSRES) {
                     // running LDS offset, opaque to the compiler so it adds one
@@ -435,10 +446,10 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                     if (mode == 1) {
                         dn = su[lane] - tau_at(A.tau, row);   // the master keeps d - tau
                     } else {
-                        dn = d_at(row);
-                        if (mode == 0) dn = dn + t * double(q_at(row));
+                        dn = d_pre;
+                        if (mode == 0) dn = dn + t * q_pre;
                     }
-                    const ObjClass cc = cl[cls_at(row)];
+                    const ObjClass cc = cl[c_pre];
                     if (mode != 2) d_at(row) = dn;
                     Fp += obj_f(cc, dn);
                     su[lane] = grad_f(cc, dn);
@@ -588,6 +599,15 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             } else {
                 for (int64_t bt = bat0 + wave; bt < bat1; bt += NW) {
                     const int64_t base = bt * ROWS;
+                    // this lane's row: d and class loaded with the D_K rows
+                    double d_pre = 0.0;
+                    uint8_t c_pre = 0;
+                    T q_pre = T(0);
+                    if (lane < ROWS) {
+                        d_pre = d_at(base + lane);
+                        c_pre = cls_at(base + lane);
+                        if (!first) q_pre = q_at(base + lane);
+                    }
                     if (first) {
                         V v[IT];
 #pragma unroll
@@ -612,9 +632,9 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                             qt = T(sq[lane]);   // the line search and the update use the stored value
                             q_at(row) = qt;
                         } else {
-                            qt = q_at(row);
+                            qt = q_pre;
                         }
-                        ls_voxel(cl[cls_at(row)], d_at(row), double(qt), t, r);
+                        ls_voxel(cl[c_pre], d_pre, double(qt), t, r);
                     }
                     wave_sync();
                 }

@@ -103,7 +103,7 @@ dao_status validate_inputs(const dao_matrix* D, const dao_beams* beams,
         return fail("master must be DAO_MASTER_APERTURE or DAO_MASTER_BEAMLET");
     if (opt->persistent < 0 || opt->persistent > 2) return fail("persistent must be 0, 1 or 2");
     if (opt->product_tune < 0 || opt->product_tune > 1) return fail("product_tune must be 0 or 1");
-    if (opt->dose_variant < 0 || opt->dose_variant > 3) return fail("dose_variant must be 0, 1, 2 or 3");
+    if (opt->dose_variant < 0 || opt->dose_variant > 6) return fail("dose_variant must be in [0, 6]");
     if (opt->dose_variant == 2 && opt->d_format != DAO_DFMT_NATIVE)
         return fail("dose_variant 2 reads x unscaled: native d_format only");
     if (opt->gradient_depth != 4 && opt->gradient_depth != 8 && opt->gradient_depth != 16)
@@ -120,6 +120,7 @@ dao_status validate_inputs(const dao_matrix* D, const dao_beams* beams,
         return fail("d_format must be DAO_DFMT_NATIVE, DAO_DFMT_F16 or DAO_DFMT_BF16");
     if (opt->d_residual < 0 || opt->d_residual > 2) return fail("d_residual must be 0, 1 or 2");
     if (opt->residual_rounds < 0) return fail("residual_rounds must be >= 0");
+    if (opt->graphs < 0 || opt->graphs > 1) return fail("graphs must be 0 or 1");
     if (opt->d_format != DAO_DFMT_NATIVE) {
         if (opt->dtype != DAO_F32) return fail("a 16-bit d_format needs dtype DAO_F32");
         if (opt->master != DAO_MASTER_APERTURE) return fail("a 16-bit d_format needs the aperture-matrix master");

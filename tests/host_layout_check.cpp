@@ -118,6 +118,7 @@ int main(int argc, char** argv) {
     o.apertures_per_round = 1;
     o.dk_format = DAO_DFMT_NATIVE;
     o.residual_rounds = 5;
+    o.graphs = 0;
     expect(validate(p, o) == DAO_OK, "valid problem accepted");
 
     // ---- the layouts

@@ -134,3 +134,30 @@ def test_persistent_and_per_phase_masters_agree(name, dtype, persistent):
     finally:
         a.close()
         b.close()
+
+
+@pytest.mark.parametrize("name,dtype,opts", [("tiny", "f64", {}), ("prostate", "f32", {}),
+                                             ("prostate", "f32", dict(d_format=1, d_residual=2, dk_format=1))])
+def test_graph_replayed_pricing_equals_launches(name, dtype, opts):
+    """dao_options.graphs: the per-round pricing sequence replays a captured
+    HIP graph (once per residual setting), with the master's eager launches
+    between the replays.  Every replay must give what the launches one by
+    one give: the same plan, bit for bit, twice in a row on one context."""
+    ph = cached_phantom(name)
+    n = min(ph.n_apertures, 12)
+    ref_ctx = ctx_for(ph, dtype=dtype, graphs=0, **opts)
+    try:
+        ref = ref_ctx.solve(n)
+    finally:
+        ref_ctx.close()
+    ctx = ctx_for(ph, dtype=dtype, graphs=1, **opts)
+    try:
+        for rep in range(2):
+            out = ctx.solve(n)
+            print(f"[graphs] {name} {opts} replay {rep}: F {out['F']:.12e} ref {ref['F']:.12e}", flush=True)
+            assert out["rounds"] == ref["rounds"]
+            assert list(out["round_beam"]) == list(ref["round_beam"])
+            assert list(out["round_rc"]) == list(ref["round_rc"])
+            assert out["F"] == ref["F"]
+    finally:
+        ctx.close()

@@ -15,7 +15,8 @@ the plan metrics PTV D95 and OAR Dmax against the FP64 master on the
 original D.  The precision form of the head-and-neck-shaped plan (16-bit D
 and an FP16 aperture dose matrix) is checked teacher-forced against the
 oracle's stored trajectory: objective after every round, final dose, PTV D95
-and organ Dmax within 1e-3.
+and organ Dmax within 1e-3.  The prostate-shaped plan, whose master keeps D_K
+on chip, is checked the same way with an FP16 aperture dose matrix.
 """
 import numpy as np
 import pytest
@@ -30,7 +31,7 @@ from quant import quantized
 
 pytestmark = pytest.mark.gpu
 
-FMT = {"f16": dao.DAO_DFMT_F16, "bf16": dao.DAO_DFMT_BF16}
+FMT = {"native": dao.DAO_DFMT_NATIVE, "f16": dao.DAO_DFMT_F16, "bf16": dao.DAO_DFMT_BF16}
 FORMATS = [("f16", 0), ("f16", 1), ("bf16", 0), ("bf16", 1)]
 # max-norm relative error against the original D
 BOUND = {("f16", 0): 3e-4, ("bf16", 0): 2e-3, ("f16", 1): 1e-5, ("bf16", 1): 1e-5}
@@ -129,13 +130,15 @@ def _golden(name):
         return json.load(f)
 
 
-# the precision form of the head-and-neck-shaped plan: 16-bit D (with and
-# without the FP16 residual) and an FP16 aperture dose matrix
-PLAN_FORMATS = [("f16", 0, 1), ("f16", 1, 1), ("bf16", 1, 1), ("f16", 0, 0)]
+# the precision form of the head-and-neck-shaped plan (streaming master):
+# 16-bit D (with and without the FP16 residual) and an FP16 aperture dose
+# matrix; the prostate-shaped plan's master keeps D_K on chip
+PLAN_FORMATS = [("headneck", "f16", 0, 1), ("headneck", "f16", 1, 1), ("headneck", "bf16", 1, 1),
+                ("headneck", "f16", 0, 0), ("prostate", "native", 0, 1), ("prostate", "f16", 0, 1)]
 
 
-@pytest.mark.parametrize("fmt,res,dk16", PLAN_FORMATS)
-def test_precision_plan_teacher_forced(fmt, res, dk16):
+@pytest.mark.parametrize("name,fmt,res,dk16", PLAN_FORMATS)
+def test_precision_plan_teacher_forced(name, fmt, res, dk16):
     """Teacher-forced against the FP64 oracle's stored 50-aperture trajectory
     (the oracle on the FP32 matrix): every round starts from the oracle's
     pool and intensities; the objective after the round's master and, at the
@@ -143,8 +146,8 @@ def test_precision_plan_teacher_forced(fmt, res, dk16):
     Pricing decisions are compared where the gap exceeds the reduced-cost
     error of the format (1e-3 |rc|); closer ones are counted."""
     torch = torch_cuda()
-    doc = _golden("headneck")
-    ph = cached_phantom("headneck")
+    doc = _golden(name)
+    ph = cached_phantom(name)
     rc1 = doc["rc1"]
     tol = doc["eps"] * abs(rc1)
     ctx = ctx_for(ph, dtype="f32", d_format=FMT[fmt], d_residual=res, dk_format=FMT["f16"] if dk16 else 0)
@@ -176,7 +179,7 @@ def test_precision_plan_teacher_forced(fmt, res, dk16):
             if s > 0:
                 m = np.asarray(ph.vox_struct) == s
                 errs[f"Dmax_{nm}"] = abs(dmax(z, m) - dmax(z0, m)) / dmax(z0, m)
-        print(f"[precision] headneck {fmt} residual={res} dk16={dk16}: {errs}, near decisions {near}", flush=True)
+        print(f"[precision] {name} {fmt} residual={res} dk16={dk16}: {errs}, near decisions {near}", flush=True)
         for key, v in errs.items():
             assert v <= 1e-3, (key, v)
     finally:
@@ -190,7 +193,8 @@ def test_selective_residual_plan():
     FP32 D_K.  The final plan is then accurate to the FP32 bar: the GPU's
     dose and objective equal the FP64 oracle's dose D (A y) and F at the
     GPU's own final pool and intensities to 1e-5, and the objective is within
-    1e-3 of the oracle's stored plan."""
+    1e-3 of the oracle's stored plan.  A second plan on the same context
+    (which goes back to the FP16 D_K) repeats the first bit for bit."""
     torch = torch_cuda()
     doc = _golden("headneck")
     ph = cached_phantom("headneck")
@@ -215,5 +219,11 @@ def test_selective_residual_plan():
         assert relerr(z, z0) <= 1e-5
         assert abs(F - F0) <= 1e-5 * F0
         assert abs(F - doc["F"]) <= 1e-3 * doc["F"]
+        again = ctx.solve(len(doc["rounds"]))
+        print(f"[precision] selective residual, second plan: F {again['F']:.10e}", flush=True)
+        assert again["rounds"] == out["rounds"] and again["F"] == out["F"]
+        assert list(again["round_beam"]) == list(out["round_beam"])
+        pool2, y2 = ctx.get_pool()
+        assert pool2 == pool and np.array_equal(np.asarray(y2), np.asarray(y))
     finally:
         ctx.close()
