@@ -880,6 +880,25 @@ hipError_t setup_coop(dao_ctx* c, int dev, int coop, int ncu) {
     return hipSuccess;
 }
 
+// f(a, b) over [0, n) split into contiguous ranges of at least `grain`
+// items, on up to 16 host threads (the 16-bit encode of a large matrix).
+template <class F>
+void parallel_ranges(int64_t n, int64_t grain, F&& f) {
+    const int64_t hc = std::max<int64_t>(1, int64_t(std::thread::hardware_concurrency()));
+    const int64_t nt = std::min<int64_t>({16, hc, std::max<int64_t>(1, n / std::max<int64_t>(1, grain))});
+    if (nt <= 1) {
+        f(int64_t(0), n);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t per = (n + nt - 1) / nt;
+    for (int64_t a = 0; a < n; a += per) {
+        const int64_t b = std::min(n, a + per);
+        th.emplace_back([&f, a, b] { f(a, b); });
+    }
+    for (auto& t : th) t.join();
+}
+
 template <class T>
 dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     dao_status s;
@@ -900,8 +919,10 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
         // 16-bit value / per-beamlet scale (+ FP16 residual)
         const bool res = c->opt.d_residual != 0;
         std::vector<uint16_t> hi(L.sell_val.size()), lo(res ? L.sell_val.size() : 0);
-        for (size_t e = 0; e < hi.size(); ++e)
-            encode_value(fmt, L.sell_val[e] / double(L.col_scale[L.sell_col[e]]), &hi[e], res ? &lo[e] : nullptr);
+        parallel_ranges(int64_t(hi.size()), int64_t(1) << 18, [&](int64_t a, int64_t b) {
+            for (int64_t e = a; e < b; ++e)
+                encode_value(fmt, L.sell_val[e] / double(L.col_scale[L.sell_col[e]]), &hi[e], res ? &lo[e] : nullptr);
+        });
         TRY(upload(c, &c->sell_val, hi.data(), hi.size() * 2));
         if (res) TRY(upload(c, &c->sell_lo, lo.data(), lo.size() * 2));
         TRY(upload(c, &c->col_scale, L.col_scale.data(), L.col_scale.size() * 4));
@@ -918,9 +939,11 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     } else {
         const bool res = c->opt.d_residual != 0;
         std::vector<uint16_t> hi(L.csc_val.size()), lo(res ? L.csc_val.size() : 0);
-        for (int64_t i = 0; i < L.N; ++i)
-            for (int32_t e = L.csc_ptr[i]; e < L.csc_ptr[i + 1]; ++e)
-                encode_value(fmt, L.csc_val[e] / double(L.col_scale[i]), &hi[e], res ? &lo[e] : nullptr);
+        parallel_ranges(L.N, 32, [&](int64_t a, int64_t b) {
+            for (int64_t i = a; i < b; ++i)
+                for (int32_t e = L.csc_ptr[i]; e < L.csc_ptr[i + 1]; ++e)
+                    encode_value(fmt, L.csc_val[e] / double(L.col_scale[i]), &hi[e], res ? &lo[e] : nullptr);
+        });
         TRY(upload(c, &c->csc_val, hi.data(), hi.size() * 2));
         if (res) TRY(upload(c, &c->csc_lo, lo.data(), lo.size() * 2));
         HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -91,12 +91,43 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Sum over the LPR lanes of one row (aligned lane groups); all get the sum.
+// v of the lane OFF places further along its row of 16 lanes, cyclically:
+// lane c gets lane (c + OFF) mod 16.  DPP row_ror:N moves data N lanes up
+// the row (lane c receives lane c - N mod 16), so the move is row_ror by
+// 16 - OFF (a VALU move; every lane of the wavefront must be active).
+template <int OFF>
+__device__ __forceinline__ double dpp_row_from(double v) {
+    static_assert(OFF >= 1 && OFF <= 15, "offsets 1..15 inside a row");
+    constexpr int CTRL = 0x120 + (16 - OFF);   // row_ror:(16 - OFF)
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(b), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+template <int OFF>
+__device__ __forceinline__ double ror_tree(double v) {
+    if constexpr (OFF == 0)
+        return v;
+    else
+        return ror_tree<OFF / 2>(v + dpp_row_from<OFF>(v));
+}
+
+// Sum over the LPR lanes of one row (aligned lane groups); lane 0 of the
+// group gets the sum, as the butterfly adds it: lane c with lane c + LPR/2
+// first, then halves.  Groups inside one row of 16 lanes take their
+// operands by DPP rotations of the row (for c below the offset, lane
+// (c + off) mod 16 is lane c + off of the same group, so lane 0 adds
+// exactly the butterfly's operands); wider groups go through lane permutes.
+// Call with every lane of the wavefront active.
 template <int LPR>
 __device__ __forceinline__ double group_sum(double v) {
+    if constexpr (LPR <= 16) {
+        return ror_tree<LPR / 2>(v);
+    } else {
 #pragma unroll
-    for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-    return v;
+        for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+        return v;
+    }
 }
 
 // ind[i] = 1 if beamlet i is open in pool aperture k, else 0.

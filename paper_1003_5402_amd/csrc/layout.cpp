@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <numeric>
 #include <set>
@@ -24,31 +25,35 @@ std::string cat(A&&... a) {
 }  // namespace
 
 namespace {
-// r = a * 2^E with a in [1, 2): E of |r| > 0
-int exp2_of(double a) {
-    int e = 0;
-    std::frexp(a, &e);   // a = m 2^e, m in [0.5, 1)
-    return e - 1;
-}
 // RNE of |r| to a binary format with `mant` stored mantissa bits, exponent
-// bias `bias` and `ebits` exponent bits; returns the magnitude bits.
+// bias `bias` and `ebits` exponent bits; returns the magnitude bits.  Works
+// on the IEEE bits of the double: the significand m (53 bits with the
+// implicit one) is shifted right to the target's units, 2^(E - mant) for a
+// normal result and 2^(1 - bias - mant) below the normal range, and the
+// dropped bits round it to nearest, ties to an even result.
 uint16_t enc_mag(double a, int mant, int bias, int ebits) {
     const int emax_field = (1 << ebits) - 1;   // all ones: infinity
     if (a == 0.0) return 0;
     if (std::isinf(a)) return uint16_t(emax_field << mant);
-    int E = exp2_of(a);
-    if (E >= 1 - bias) {   // normal range
-        double q = std::nearbyint(std::ldexp(a, mant - E));
-        if (q >= std::ldexp(1.0, mant + 1)) {   // rounded up to the next binade
-            E += 1;
-            q = double(1 << mant);
-        }
-        if (E + bias >= emax_field) return uint16_t(emax_field << mant);
-        return uint16_t(((E + bias) << mant) | (int(q) - (1 << mant)));
+    uint64_t bits;
+    std::memcpy(&bits, &a, sizeof bits);
+    const int ef = int((bits >> 52) & 0x7FF);
+    if (ef == 0) return 0;   // a subnormal double is far below half the smallest 16-bit unit
+    const uint64_t m = (bits & ((uint64_t(1) << 52) - 1)) | (uint64_t(1) << 52);
+    int E = ef - 1023;   // a = m 2^(E - 52)
+    const bool normal = E >= 1 - bias;
+    const int shift = (52 - mant) + (normal ? 0 : (1 - bias - E));
+    if (shift >= 54) return 0;   // a < half a unit (m < 2^53)
+    uint64_t q = m >> shift;
+    const uint64_t rem = m & ((uint64_t(1) << shift) - 1), half = uint64_t(1) << (shift - 1);
+    if (rem > half || (rem == half && (q & 1))) ++q;
+    if (!normal) return uint16_t(q);   // 2^mant units is the smallest normal, encoded the same way
+    if (q == (uint64_t(1) << (mant + 1))) {   // rounded up to the next binade
+        E += 1;
+        q = uint64_t(1) << mant;
     }
-    // subnormal: units of 2^(1 - bias - mant); 2^mant units is the smallest normal
-    const double q = std::nearbyint(std::ldexp(a, bias - 1 + mant));
-    return uint16_t(q);
+    if (E + bias >= emax_field) return uint16_t(emax_field << mant);
+    return uint16_t(((E + bias) << mant) | int(q - (uint64_t(1) << mant)));
 }
 double dec_mag(uint16_t h, int mant, int bias, int ebits) {
     const int ef = (h >> mant) & ((1 << ebits) - 1), m = h & ((1 << mant) - 1);
