@@ -1037,6 +1037,11 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
         }
     }
     if (c->ap_master()) {
+        // D_K is stored in blocks of one batch of rows; the padded row count
+        // (whole slices) is a whole number of blocks in every storage type
+        static_assert(SLICE % Batch<float>::ROWS == 0 && SLICE % Batch<double>::ROWS == 0 &&
+                          SLICE % Batch<__half>::ROWS == 0,
+                      "D_K blocks tile the padded rows");
         TRY(dev_alloc(c, &c->dk, size_t(c->Vpad) * KS * dkb));
         TRY(dev_alloc(c, &c->ind, c->N * ts));
         TRY(dev_alloc(c, &c->parts2, c->ap_blocks() * (KS + 1) * sizeof(double)));

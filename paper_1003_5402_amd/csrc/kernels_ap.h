@@ -2,15 +2,15 @@
 //
 // Section 2.1, eq. 1 and eq. 2 give the voxel dose of the pool as
 // z = D_K y with D_kj = sum_{i in A_k} D_ij.  Here D_K is kept on the device
-// as a dense row-major block dk[row * KS + k] (KS = 64 aperture slots per
-// voxel row, internal row order).  A round appends one column (one forward
+// as a dense block of KS = 64 aperture slots per voxel row (internal row
+// order), stored by batch: see dk_vec_index.  A round appends one column (one forward
 // product of D with the aperture's 0/1 beamlet indicator); nothing is ever
 // rebuilt or transposed.  Both master products then stream D_K row by row:
 //   q = D_K p              (direction of the dose, k_qstep_ap)
 //   grad_y = D_K^T dF/dz    (gradient over the pool, fused into k_upd_ap)
-// A row of KS values is 256 B (FP32) or 512 B (FP64); LPR lanes each load
-// one 16-byte vector of it, so one wavefront instruction reads RPW whole
-// consecutive rows (1 KB, fully coalesced).
+// LPR lanes each load one 16-byte vector of a row, so one wavefront
+// instruction reads slot vector c of RPW consecutive rows (RPW runs of
+// 16 B per c, contiguous across the batch's instructions).
 //
 // Step sequence: k_upd_ap -> k_dir_ap -> k_qstep_ap -> k_lseval x slots.
 //   k_upd_ap   (PH_UPD) applies the last step to d (mode 0: d += t q,
@@ -53,7 +53,43 @@ struct DKG {
     static constexpr int EPL = Vec16<T>::n;   // aperture slots per lane
     static constexpr int LPR = KS / EPL;      // lanes per row
     static constexpr int RPW = WAVE / LPR;    // rows per wavefront instruction
+    static constexpr int VPR = KS / EPL;      // 16-byte slot vectors per row
 };
+
+// Rows are processed in batches of BATCH = ITERS * RPW consecutive rows per
+// wavefront.  Each lane first issues all ITERS of its 16-byte D_K loads for
+// the batch (lane group rg holds rows rg, rg + RPW, ...; lane c of the group
+// holds aperture slots c*EPL .. c*EPL+EPL-1), then the batch is handled one
+// row per lane for the per-voxel work (coalesced d, q and class access, all
+// lanes active), with row results exchanged through LDS.
+// The per-voxel stage of a batch gives each lane one row, so a batch holds at
+// most WAVE rows: 16 loads per lane for FP32 and FP64 storage (64 and 32
+// rows), 8 for FP16 storage (8 rows per instruction, 64 rows).
+template <class T>
+struct Batch {
+    static constexpr int ITERS = 16 * DKG<T>::RPW > WAVE ? WAVE / DKG<T>::RPW : 16;
+    static constexpr int ROWS = ITERS * DKG<T>::RPW;
+    static_assert(ROWS <= WAVE, "one row per lane in the per-voxel stage");
+};
+
+// Layout of D_K in device memory: the rows in blocks of one batch; inside a
+// block, slot vector c of every row of the block is stored contiguously.
+// Vector (row, c) is element ((row / ROWS) * VPR + c) * ROWS + row % ROWS of
+// the 16-byte vectors.  A pass that needs the first nc vectors of each row
+// (the pool's K slots) then reads nc contiguous runs of ROWS * 16 bytes per
+// batch and nothing else, whatever K is; with whole rows of KS slots the
+// tail of the row's last cache line would be fetched too.
+template <class DT>
+__host__ __device__ __forceinline__ int64_t dk_vec_index(int64_t row, int c) {
+    constexpr int ROWS = Batch<DT>::ROWS;
+    const int64_t blk = row / ROWS;
+    return (blk * DKG<DT>::VPR + c) * ROWS + (row - blk * ROWS);
+}
+// element index of aperture slot k of a row
+template <class DT>
+__host__ __device__ __forceinline__ int64_t dk_index(int64_t row, int k) {
+    return dk_vec_index<DT>(row, k / DKG<DT>::EPL) * DKG<DT>::EPL + k % DKG<DT>::EPL;
+}
 
 __device__ __forceinline__ double vget(const float4& v, int e) {
     return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
@@ -80,6 +116,24 @@ __device__ __forceinline__ half8 vzero<half8>() {
 #pragma unroll
     for (int i = 0; i < 4; ++i) z.h[i] = __float2half2_rn(0.0f);
     return z;
+}
+
+// This lane's D_K vectors of the batch that starts at row `base` (a
+// multiple of the batch size, so the batch is one storage block): vector c
+// of rows base + it * RPW + rg, zero where c >= nc.  All IT loads sit in one
+// predicated region, so all are issued before the first is waited for (a
+// branch per load lets the compiler wait on each load in turn).
+template <class DT, int IT, class V>
+__device__ __forceinline__ void load_batch(const DT* dk, int64_t base, int rg, int c, int nc, V (&v)[IT]) {
+    static_assert(IT * DKG<DT>::RPW == Batch<DT>::ROWS, "one batch per block");
+    if (c < nc) {
+        const V* p = reinterpret_cast<const V*>(dk) + dk_vec_index<DT>(base + rg, c);
+#pragma unroll
+        for (int it = 0; it < IT; ++it) v[it] = p[it * DKG<DT>::RPW];
+    } else {
+#pragma unroll
+        for (int it = 0; it < IT; ++it) v[it] = vzero<V>();
+    }
 }
 
 // Order LDS traffic between lanes of one wavefront (used inside loops whose
@@ -146,8 +200,8 @@ __global__ void k_ap_indicator(PoolView P, int k, T* __restrict__ ind) {
     }
 }
 
-// Column k of D_K: dk[row * KS + k] = (D ind)_row, FP64 sums rounded to the
-// storage type DT (T, or FP16 of the sum times inv_scale).
+// Column k of D_K: slot k of every row = (D ind)_row, FP64 sums rounded to
+// the storage type DT (T, or FP16 of the sum times inv_scale).
 __device__ __forceinline__ void dk_store(float* p, double v, double) { *p = float(v); }
 __device__ __forceinline__ void dk_store(double* p, double v, double) { *p = v; }
 __device__ __forceinline__ void dk_store(__half* p, double v, double inv) { *p = __float2half_rn(float(v * inv)); }
@@ -161,24 +215,9 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_dk_column(SellView<VT> S, int6
     __shared__ double s_part[KSPLIT * SLAB];
     const double sum = slab_rows_x<VT, T, double, LO>(S, ind, N, reinterpret_cast<T*>(smem), stage, scale, s_part);
     const int64_t row = int64_t(blockIdx.x) * SLAB + threadIdx.x;
-    if (threadIdx.x < SLAB && row < Vpad) dk_store(dk + row * KS + k, sum, inv_dk_scale);
+    if (threadIdx.x < SLAB && row < Vpad) dk_store(dk + dk_index<DT>(row, k), sum, inv_dk_scale);
 }
 
-// Rows are processed in batches of BATCH = ITERS * RPW consecutive rows per
-// wavefront.  Each lane first issues all ITERS of its 16-byte D_K loads for
-// the batch (lane group rg holds rows rg, rg + RPW, ...; lane c of the group
-// holds aperture slots c*EPL .. c*EPL+EPL-1), then the batch is handled one
-// row per lane for the per-voxel work (coalesced d, q and class access, all
-// lanes active), with row results exchanged through LDS.
-// The per-voxel stage of a batch gives each lane one row, so a batch holds at
-// most WAVE rows: 16 loads per lane for FP32 and FP64 storage (64 and 32
-// rows), 8 for FP16 storage (8 rows per instruction, 64 rows).
-template <class T>
-struct Batch {
-    static constexpr int ITERS = 16 * DKG<T>::RPW > WAVE ? WAVE / DKG<T>::RPW : 16;
-    static constexpr int ROWS = ITERS * DKG<T>::RPW;
-    static_assert(ROWS <= WAVE, "one row per lane in the per-voxel stage");
-};
 
 // Update pass (PH_UPD).  Record of workgroup b in parts2[b * (KS + 1)]:
 // [objective partial, grad_y partial for apertures 0..KS-1].
@@ -239,11 +278,7 @@ __global__ void __launch_bounds__(BLOCK) k_upd_ap(const DT* __restrict__ dk, dou
     for (int64_t base = (int64_t(blockIdx.x) * NW + wave) * ROWS; base < Vpad; base += nw * ROWS) {
         // 1. all D_K loads of the batch
         V v[IT];
-#pragma unroll
-        for (int it = 0; it < IT; ++it) {
-            v[it] = vzero<V>();
-            if (c < nc) v[it] = reinterpret_cast<const V*>(dk + (base + it * G::RPW + rg) * KS)[c];
-        }
+        load_batch<DT>(dk, base, rg, c, nc, v);
         // 2. refresh: d = D_K y for the batch's rows
         if (mode == 1) {
 #pragma unroll
@@ -472,11 +507,7 @@ __global__ void __launch_bounds__(BLOCK) k_qstep_ap(const DT* __restrict__ dk, d
     const int64_t nw = int64_t(gridDim.x) * NW;
     for (int64_t base = (int64_t(blockIdx.x) * NW + wave) * ROWS; base < Vpad; base += nw * ROWS) {
         V v[IT];
-#pragma unroll
-        for (int it = 0; it < IT; ++it) {
-            v[it] = vzero<V>();
-            if (c < nc) v[it] = reinterpret_cast<const V*>(dk + (base + it * G::RPW + rg) * KS)[c];
-        }
+        load_batch<DT>(dk, base, rg, c, nc, v);
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             double part = 0.0;

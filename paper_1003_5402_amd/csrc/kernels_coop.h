@@ -239,7 +239,7 @@ struct LsRegs {
 
 template <class T>
 struct CoopArgs {
-    const void* dk;     // D_K rows of KS slots, storage type DT of the kernel
+    const void* dk;     // D_K (KS slots per row, blocked by batch), storage type DT of the kernel
     double dk_scale;    // D_K = dk_scale * stored value (1 unless stored in FP16)
     int64_t Vpad, Vnz;
     double* d;
@@ -334,9 +334,13 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     T* ql = reinterpret_cast<T*>(bol + nrows);
     uint8_t* cll = reinterpret_cast<uint8_t*>(ql + nrows);
     if (LDSRES) {
+        // in storage order: per batch, vector c of its ROWS rows, contiguous
         for (int64_t idx = threadIdx.x; idx < nrows * nc; idx += blockDim.x) {
-            const int64_t rr = idx / nc;
-            dkl[rr * ncp + (idx - rr * nc)] = reinterpret_cast<const V*>(dk + (r0 + rr) * KS)[idx - rr * nc];
+            const int64_t bb = idx / (int64_t(nc) * ROWS);
+            const int64_t rem = idx - bb * (int64_t(nc) * ROWS);
+            const int cc = int(rem / ROWS);
+            const int64_t rr = bb * ROWS + (rem - int64_t(cc) * ROWS);
+            dkl[rr * ncp + cc] = reinterpret_cast<const V*>(dk)[dk_vec_index<DT>(r0 + rr, cc)];
         }
         for (int64_t rr = threadIdx.x; rr < nrows; rr += blockDim.x) {
             dl[rr] = A.d[r0 + rr];
@@ -345,9 +349,6 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
         }
         __syncthreads();
     }
-    auto dk_vec = [&](int64_t row) -> V {
-        return LDSRES ? dkl[(row - r0) * ncp + c] : reinterpret_cast<const V*>(dk + row * KS)[c];
-    };
     auto d_at = [&](int64_t row) -> double& { return LDSRES ? dl[row - r0] : A.d[row]; };
     auto q_at = [&](int64_t row) -> T& { return LDSRES ? ql[row - r0] : A.q[row]; };
     auto cls_at = [&](int64_t row) -> uint8_t { return LDSRES ? cll[row - r0] : A.cls[row]; };
@@ -416,18 +417,20 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                     // stride per load instead of keeping IT addresses live
                     uint32_t off = uint32_t(((base - r0 + rg) * ncp + c) * 16);
                     const uint32_t stride = uint32_t(G::RPW * ncp * 16);
+                    // one predicated region for all the loads (see load_batch)
+                    if (c < nc) {
 #pragma unroll
-                    for (int it = 0; it < IT; ++it) {
-                        asm volatile("" : "+v"(off));
-                        v[it] = c < nc ? *reinterpret_cast<const V*>(dyn + off) : vzero<V>();
-                        off += stride;
+                        for (int it = 0; it < IT; ++it) {
+                            asm volatile("" : "+v"(off));
+                            v[it] = *reinterpret_cast<const V*>(dyn + off);
+                            off += stride;
+                        }
+                    } else {
+#pragma unroll
+                        for (int it = 0; it < IT; ++it) v[it] = vzero<V>();
                     }
                 } else {
-#pragma unroll
-                    for (int it = 0; it < IT; ++it) {
-                        v[it] = vzero<V>();
-                        if (c < nc) v[it] = dk_vec(base + it * G::RPW + rg);
-                    }
+                    load_batch<DT>(dk, base, rg, c, nc, v);
                 }
                 if (mode == 1) {
 #pragma unroll
@@ -610,11 +613,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                     }
                     if (first) {
                         V v[IT];
-#pragma unroll
-                        for (int it = 0; it < IT; ++it) {
-                            v[it] = vzero<V>();
-                            if (c < nc) v[it] = dk_vec(base + it * G::RPW + rg);
-                        }
+                        load_batch<DT>(dk, base, rg, c, nc, v);
 #pragma unroll
                         for (int it = 0; it < IT; ++it) {
                             double part = 0.0;
