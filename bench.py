@@ -482,8 +482,16 @@ def main():
         log(f"[bench] serving batched FP16 D + FP16 D_K (selective residual): {serve['batched_f16']}")
         serve["sequential_f32"] = run_serving(reqs, stream, 1, cap, True)
         log(f"[bench] serving sequential FP32: {serve['sequential_f32']}")
+        # capacity: the same requests all queued at once, so that plans/s is
+        # set by the server rather than by the arrival rate
+        sat = [dict(r, arrival=0.0) for r in reqs]
+        serve["saturated_f32"] = run_serving(sat, stream, args.serve_max_live, cap, False)
+        log(f"[bench] serving saturated FP32: {serve['saturated_f32']}")
+        serve["saturated_f16"] = run_serving(sat, stream, args.serve_max_live, cap, False, **f16_opts)
+        log(f"[bench] serving saturated FP16 D + FP16 D_K (selective residual): {serve['saturated_f16']}")
         serve["speedup_plans_s"] = serve["batched_f32"]["plans_s"] / serve["sequential_f32"]["plans_s"]
         serve["speedup_f16_plans_s"] = serve["batched_f16"]["plans_s"] / serve["sequential_f32"]["plans_s"]
+        serve["saturated_f16_vs_f32"] = serve["saturated_f16"]["plans_s"] / serve["saturated_f32"]["plans_s"]
 
     algo_per_launch = dk_["algo_bytes_per_plan"] / max(1, dk_["launches"])
     result = {

@@ -449,12 +449,15 @@ dao_status dao_solve_resume(dao_ctx* ctx, int32_t n_apertures, dao_plan* out);
 dao_status dao_solve_batch(dao_ctx* const* ctxs, int32_t n, const int32_t* n_apertures, dao_plan* plans);
 
 /* Serving loop (continuous batching).  Requests are queued in arrival order.
- * A worker thread of the server admits them while fewer than max_live solves
- * are live or admitted and their contexts fit under hbm_cap_bytes (0: no
- * cap; a context is created at admission, on a stream of the server's own,
- * with the remaining room as its mem_cap_bytes, so the oldest request waits
- * until enough memory is freed, or fails with DAO_ENOMEM if it cannot fit
- * even alone); context creation thus overlaps the device work of the live
+ * The server's admission threads (`workers`) take them in that order while
+ * fewer than max_live solves are live, admitted or being built.  Each lays
+ * out the request's inputs on the host, reserves the context's predicted
+ * device footprint under hbm_cap_bytes (0: no cap; a request whose
+ * footprint does not fit waits until retirements free enough memory, and
+ * fails with DAO_ENOMEM if it exceeds the cap alone), then allocates and
+ * uploads on a stream of its own; a request is admitted when its context is
+ * ready, so requests built at the same time may be admitted out of arrival
+ * order.  Context creation thus overlaps the device work of the live
  * solves.  Each dao_server_step takes the admitted contexts in and advances
  * every live solve by one column-generation round.  With batch_masters the
  * master solves of the small solves (fewer than 4 row batches per workgroup
@@ -471,6 +474,7 @@ typedef struct {
     int32_t batch_masters;   /* 1: the round's master solves share one launch (dao_solve_batch);
                                 0: each runs with the whole grid, one after another */
     int64_t hbm_cap_bytes;   /* device bytes of the admitted contexts; 0 = no cap */
+    int32_t workers;         /* admission threads building contexts at once, 0..16 (0: 4) */
 } dao_server_options;
 dao_status dao_server_create(const dao_server_options* opt, void* stream, dao_server** out);
 void dao_server_destroy(dao_server* srv);

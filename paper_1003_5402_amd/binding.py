@@ -68,7 +68,8 @@ class dao_info_t(ctypes.Structure):
 
 
 class dao_server_options(ctypes.Structure):
-    _fields_ = [("max_live", c_int32), ("batch_masters", c_int32), ("hbm_cap_bytes", c_int64)]
+    _fields_ = [("max_live", c_int32), ("batch_masters", c_int32), ("hbm_cap_bytes", c_int64),
+                ("workers", c_int32)]
 
 
 class dao_plan(ctypes.Structure):
@@ -502,9 +503,10 @@ class Server:
     """The library's serving loop (dao_server_*): queue requests, step rounds,
     poll results.  Keeps each request's host arrays alive until it is done."""
 
-    def __init__(self, max_live: int = 8, hbm_cap_bytes: int = 0, stream: int = 0, batch_masters: bool = True):
+    def __init__(self, max_live: int = 8, hbm_cap_bytes: int = 0, stream: int = 0, batch_masters: bool = True,
+                 workers: int = 0):
         self._lib = load_library()
-        o = dao_server_options(int(max_live), int(bool(batch_masters)), int(hbm_cap_bytes))
+        o = dao_server_options(int(max_live), int(bool(batch_masters)), int(hbm_cap_bytes), int(workers))
         h = c_void_p()
         st = self._lib.dao_server_create(byref(o), c_void_p(stream), byref(h))
         if st != DAO_OK:

@@ -8,6 +8,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <set>
 #include <thread>
 #include <type_traits>
 #include <cmath>
@@ -32,6 +33,7 @@ thread_local std::string g_create_error;
 constexpr size_t STAGE_LIMIT = 48 * 1024;   // largest vector staged in LDS per block
 constexpr int MAX_BATCH = 64;                // solves of one batched master launch
 constexpr int ELEM_BLOCKS_MAX = 2048;
+constexpr int REDUCE_BLOCKS_MAX = 512;
 
 struct DevBuf {
     void* p = nullptr;
@@ -170,6 +172,12 @@ struct dao_ctx {
 
     int64_t elem_blocks(int64_t n) const {
         return std::max<int64_t>(1, std::min<int64_t>(ELEM_BLOCKS_MAX, (n + BLOCK - 1) / BLOCK));
+    }
+    // kernels that end in arrive_and_reduce: every workgroup's arrival takes
+    // an agent-scope fence, whose cost grows with the workgroup count, so
+    // these take at most REDUCE_BLOCKS_MAX workgroups of 4+ rows per thread
+    int64_t reduce_blocks(int64_t n) const {
+        return std::max<int64_t>(1, std::min<int64_t>(REDUCE_BLOCKS_MAX, (n + 4 * BLOCK - 1) / (4 * BLOCK)));
     }
     int64_t slab_blocks() const { return std::max<int64_t>(1, (nslices + SPB - 1) / SPB); }
     int64_t ap_blocks() const { return std::max<int64_t>(1, std::min<int64_t>(512, (Vpad + 255) / 256)); }
@@ -460,7 +468,7 @@ dao_status enqueue_cycle(dao_ctx* c) {
         S, c->Vpad, static_cast<const T*>(c->dx), int(c->N), c->stage_x(), c->d, c->cls_int, c->classes,
         c->ncls, static_cast<T*>(c->q), c->parts, c->arr, c->ms, P, c->y, c->p, c->x64);
     for (int i = 0; i < c->opt.ls_slots; ++i)
-        k_lseval<<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
+        k_lseval<<<c->reduce_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
             c->d, c->q, sizeof(T) == 8, c->cls_int, c->Vpad, c->classes, c->ncls, c->parts, c->arr, c->ms, P,
             c->y, c->p, c->x64);
     k_update<T><<<c->slab_blocks(), SLAB_THREADS, cls_b + (c->stage_x64() ? c->N * 8 : 0), c->stream>>>(
@@ -514,7 +522,7 @@ dao_status enqueue_cycle_ap_dt(dao_ctx* c) {
     MARK(1, false);
     for (int i = 0; i < c->opt.ls_slots; ++i) {
         MARK(2, true);
-        k_lseval_ap<T><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
+        k_lseval_ap<T><<<c->reduce_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
             c->d, static_cast<const T*>(c->q), c->cls_int, c->Vpad, c->classes, c->ncls, c->parts, c->arr,
             c->ms, c->y, c->p, c->pc, c->Vnz);
         MARK(2, false);
@@ -642,8 +650,8 @@ dao_status run_master(dao_ctx* c, double tol, int max_steps) {
 // u, u64 and F from the master dose; g (ctx type) from u.
 template <class T>
 dao_status refresh_gradient(dao_ctx* c) {
-    k_objective_int<T><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
-        c->d, c->cls_int, c->Vpad, c->classes, static_cast<T*>(c->u), c->u64, c->parts, c->arr, c->ms);
+    k_objective_int<T><<<c->reduce_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
+        c->d, c->cls_int, c->Vpad, c->classes, c->ncls, static_cast<T*>(c->u), c->u64, c->parts, c->arr, c->ms);
     launch_gradT<T, T, T, T>(c, static_cast<const T*>(c->u), static_cast<T*>(c->g));
     LAUNCHCHK(c);
     return DAO_OK;
@@ -693,8 +701,8 @@ dao_status refresh_dose_exact(dao_ctx* c) {
 // solve.
 template <class T>
 dao_status refresh_objective(dao_ctx* c) {
-    k_objective_int<T><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
-        c->d, c->cls_int, c->Vpad, c->classes, static_cast<T*>(c->u), c->u64, c->parts, c->arr, c->ms);
+    k_objective_int<T><<<c->reduce_blocks(c->Vpad), BLOCK, 0, c->stream>>>(
+        c->d, c->cls_int, c->Vpad, c->classes, c->ncls, static_cast<T*>(c->u), c->u64, c->parts, c->arr, c->ms);
     if (!c->ap_master()) launch_gradT<T, T, T, T>(c, static_cast<const T*>(c->u), static_cast<T*>(c->g));
     LAUNCHCHK(c);
     return DAO_OK;
@@ -1098,8 +1106,8 @@ dao_status dose_typed(dao_ctx* c, const void* x, void* d) {
 template <class T>
 dao_status gradient_typed(dao_ctx* c, const void* d, void* g, double* F) {
     const T* dd = static_cast<const T*>(d);
-    k_objective_ext<T><<<c->elem_blocks(c->V), BLOCK, 0, c->stream>>>(dd, c->cls_ext, c->V, c->classes,
-                                                                       c->tau_ext, c->parts, c->arr, c->scalar);
+    k_objective_ext<T><<<c->reduce_blocks(c->V), BLOCK, 0, c->stream>>>(dd, c->cls_ext, c->V, c->classes, c->ncls,
+                                                                         c->tau_ext, c->parts, c->arr, c->scalar);
     k_gather_grad<T><<<c->elem_blocks(c->Vpad), BLOCK, 0, c->stream>>>(dd, c->perm, c->cls_int, c->Vpad,
                                                                         c->classes, c->tau_int,
                                                                         static_cast<T*>(c->ug));
@@ -1685,34 +1693,35 @@ const char* dao_create_error(void) { return g_create_error.c_str(); }
 
 const char* dao_last_error(const dao_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-dao_status dao_create(const dao_matrix* D, const dao_beams* beams, const dao_structures* structs,
-                      const dao_prescription* presc, const dao_options* opt_in, void* stream,
-                      dao_ctx** out) {
-    g_create_error.clear();
-    if (!out) {
-        g_create_error = "null output pointer";
-        return DAO_EINVAL;
-    }
-    *out = nullptr;
-    dao_options opt;
-    if (opt_in)
-        opt = *opt_in;
-    else
-        dao_default_options(&opt);
+}  // extern "C"
+
+namespace {
+
+// The host half of dao_create: validate the inputs and lay them out; *need is
+// the predicted device footprint.  Sets g_create_error on failure.
+dao_status prepare_layout(const dao_matrix* D, const dao_beams* beams, const dao_structures* structs,
+                          const dao_prescription* presc, dao_options* opt, std::unique_ptr<HostLayout>* L,
+                          int64_t* need) {
     std::string err;
-    dao_status s = validate_inputs(D, beams, structs, presc, &opt, &err);
+    const dao_status s = validate_inputs(D, beams, structs, presc, opt, &err);
     if (s != DAO_OK) {
         g_create_error = err;
         return s;
     }
-    auto L = std::make_unique<HostLayout>();
-    build_layout(D, beams, structs, presc, L.get());
-    const size_t ts = opt.dtype == DAO_F64 ? 8 : 4;
-    const int64_t need = predicted_bytes(*L, ts, opt.max_apertures, opt);
-    if (opt.mem_cap_bytes > 0 && need > opt.mem_cap_bytes) {
-        g_create_error = "device footprint " + std::to_string(need) + " B exceeds mem_cap_bytes";
+    *L = std::make_unique<HostLayout>();
+    build_layout(D, beams, structs, presc, L->get());
+    *need = predicted_bytes(**L, opt->dtype == DAO_F64 ? 8 : 4, opt->max_apertures, *opt);
+    if (opt->mem_cap_bytes > 0 && *need > opt->mem_cap_bytes) {
+        g_create_error = "device footprint " + std::to_string(*need) + " B exceeds mem_cap_bytes";
         return DAO_ENOMEM;
     }
+    return DAO_OK;
+}
+
+// The device half: allocate, upload, tune.  Sets g_create_error on failure.
+dao_status create_on_device(std::unique_ptr<HostLayout> L, const dao_beams* beams, const dao_options& opt,
+                            void* stream, dao_ctx** out) {
+    const size_t ts = opt.dtype == DAO_F64 ? 8 : 4;
     auto c = std::make_unique<dao_ctx>();
     c->opt = opt;
     c->dtype = opt.dtype;
@@ -1738,13 +1747,38 @@ dao_status dao_create(const dao_matrix* D, const dao_beams* beams, const dao_str
         L->cls_int.resize(c->Vpad, uint8_t(L->n_struct));
         if (!L->tau_int.empty()) L->tau_int.resize(c->Vpad, 0.0);
     }
-    s = (c->dtype == DAO_F64) ? create_typed<double>(c.get(), *L) : create_typed<float>(c.get(), *L);
+    const dao_status s = (c->dtype == DAO_F64) ? create_typed<double>(c.get(), *L) : create_typed<float>(c.get(), *L);
     if (s != DAO_OK) {
         g_create_error = c->err;
         return s;
     }
     *out = c.release();
     return DAO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dao_status dao_create(const dao_matrix* D, const dao_beams* beams, const dao_structures* structs,
+                      const dao_prescription* presc, const dao_options* opt_in, void* stream,
+                      dao_ctx** out) {
+    g_create_error.clear();
+    if (!out) {
+        g_create_error = "null output pointer";
+        return DAO_EINVAL;
+    }
+    *out = nullptr;
+    dao_options opt;
+    if (opt_in)
+        opt = *opt_in;
+    else
+        dao_default_options(&opt);
+    std::unique_ptr<HostLayout> L;
+    int64_t need = 0;
+    const dao_status s = prepare_layout(D, beams, structs, presc, &opt, &L, &need);
+    if (s != DAO_OK) return s;
+    return create_on_device(std::move(L), beams, opt, stream, out);
 }
 
 void dao_destroy(dao_ctx* c) {
@@ -2060,7 +2094,7 @@ dao_status dao_solve(dao_ctx* c, int32_t n_apertures, dao_plan* out) {
 // the admitted contexts in and advances every live solve by one round.
 struct dao_server {
     hipStream_t stream = nullptr;   // solves
-    hipStream_t upload = nullptr;   // context creation (worker thread)
+    std::vector<hipStream_t> uploads;   // context creation, one per admission thread
     int max_live = 8;
     int64_t cap = 0;                // 0: no cap
     bool batch_masters = true;
@@ -2098,54 +2132,79 @@ struct dao_server {
     bool stop = false;
     std::deque<Req> queue;
     std::deque<Admitted> admitted;
-    int64_t used = 0;   // device bytes of admitted and live contexts
+    int64_t used = 0;   // device bytes of admitted and live contexts, and reserved by creations
     int n_live = 0;
+    std::set<int64_t> building;   // tickets taken off the queue whose contexts are being built
     // main thread only
     std::vector<std::unique_ptr<Live>> live;
     std::map<int64_t, Result> done;
     std::map<int64_t, Result> running;   // results being filled by live solves
     int64_t next_ticket = 0;
-    std::thread worker;
+    std::vector<std::thread> workers;
 };
 
 namespace {
 
-void server_worker(dao_server* sv) {
+// An admission thread: takes the oldest queued request while fewer than
+// max_live solves are live, admitted or being built, lays out its inputs
+// (host only), reserves its predicted device footprint under the cap
+// (waiting for retirements while it does not fit), then allocates and
+// uploads on its own stream.  Several threads build contexts at once; each
+// request is admitted when its context is ready.
+void server_worker(dao_server* sv, int w) {
     std::unique_lock<std::mutex> lk(sv->mu);
     for (;;) {
         sv->cv.wait(lk, [&] {
-            return sv->stop || (!sv->queue.empty() && sv->n_live + int(sv->admitted.size()) < sv->max_live &&
-                                (sv->cap == 0 || sv->used < sv->cap));
+            return sv->stop ||
+                   (!sv->queue.empty() &&
+                    sv->n_live + int(sv->admitted.size()) + int(sv->building.size()) < sv->max_live);
         });
         if (sv->stop) return;
         dao_server::Req q = sv->queue.front();
+        sv->queue.pop_front();
+        sv->building.insert(q.ticket);
+        lk.unlock();
         dao_options o = q.opt;
-        const int64_t room = sv->cap > 0 ? sv->cap - sv->used : 0;
-        if (sv->cap > 0) o.mem_cap_bytes = o.mem_cap_bytes > 0 ? std::min(o.mem_cap_bytes, room) : room;
-        const bool others = sv->n_live + int(sv->admitted.size()) > 0;
+        std::unique_ptr<HostLayout> L;
+        int64_t need = 0;
+        dao_status st = prepare_layout(q.D, q.B, q.S, q.P, &o, &L, &need);
+        std::string err = st == DAO_OK ? std::string() : std::string(dao_create_error());
+        lk.lock();
+        bool reserved = false;
+        if (st == DAO_OK && sv->cap > 0 && need > sv->cap) {
+            st = DAO_ENOMEM;
+            err = "device footprint " + std::to_string(need) + " B exceeds the server's hbm_cap_bytes";
+        }
+        if (st == DAO_OK) {
+            if (sv->cap > 0) sv->cv.wait(lk, [&] { return sv->stop || sv->used + need <= sv->cap; });
+            if (sv->stop) {
+                sv->building.erase(q.ticket);
+                return;
+            }
+            sv->used += need;
+            reserved = true;
+        }
         lk.unlock();
         dao_ctx* c = nullptr;
-        dao_status st = dao_create(q.D, q.B, q.S, q.P, &o, sv->upload, &c);
-        std::string err = st == DAO_OK ? std::string() : std::string(dao_create_error());
-        if (st == DAO_OK && hipStreamSynchronize(sv->upload) != hipSuccess) {
-            dao_destroy(c);
-            c = nullptr;
-            st = DAO_EDEVICE;
-            err = "upload failed";
+        if (st == DAO_OK) {
+            st = create_on_device(std::move(L), q.B, o, sv->uploads[size_t(w)], &c);
+            if (st != DAO_OK) err = dao_create_error();
+            if (st == DAO_OK && hipStreamSynchronize(sv->uploads[size_t(w)]) != hipSuccess) {
+                dao_destroy(c);
+                c = nullptr;
+                st = DAO_EDEVICE;
+                err = "upload failed";
+            }
         }
         lk.lock();
-        if (st == DAO_ENOMEM && others) {
-            // wait until a retirement frees memory, then try again
-            const int64_t before = sv->used;
-            sv->cv.wait(lk, [&] { return sv->stop || sv->used < before; });
-            continue;
-        }
-        sv->queue.pop_front();
+        if (reserved) sv->used -= need;
         if (st == DAO_OK) {
             c->stream = sv->stream;   // the solve runs on the serving stream
             sv->used += c->device_bytes;
         }
+        sv->building.erase(q.ticket);
         sv->admitted.push_back(dao_server::Admitted{q, c, st, err});
+        sv->cv.notify_all();
     }
 }
 
@@ -2228,18 +2287,24 @@ extern "C" {
 
 dao_status dao_server_create(const dao_server_options* o, void* stream, dao_server** out) {
     if (!out || !o || o->max_live < 1 || o->max_live > MAX_BATCH || o->hbm_cap_bytes < 0 ||
-        (o->batch_masters != 0 && o->batch_masters != 1))
+        (o->batch_masters != 0 && o->batch_masters != 1) || o->workers < 0 || o->workers > 16)
         return DAO_EINVAL;
     auto* sv = new dao_server();
     sv->stream = static_cast<hipStream_t>(stream);
     sv->max_live = o->max_live;
     sv->cap = o->hbm_cap_bytes;
     sv->batch_masters = o->batch_masters != 0;
-    if (hipStreamCreateWithFlags(&sv->upload, hipStreamNonBlocking) != hipSuccess) {
-        delete sv;
-        return DAO_EDEVICE;
+    const int nw = o->workers > 0 ? o->workers : 4;
+    for (int w = 0; w < nw; ++w) {
+        hipStream_t u = nullptr;
+        if (hipStreamCreateWithFlags(&u, hipStreamNonBlocking) != hipSuccess) {
+            for (auto x : sv->uploads) (void)hipStreamDestroy(x);
+            delete sv;
+            return DAO_EDEVICE;
+        }
+        sv->uploads.push_back(u);
     }
-    sv->worker = std::thread(server_worker, sv);
+    for (int w = 0; w < nw; ++w) sv->workers.emplace_back(server_worker, sv, w);
     *out = sv;
     return DAO_OK;
 }
@@ -2251,12 +2316,13 @@ void dao_server_destroy(dao_server* sv) {
         sv->stop = true;
     }
     sv->cv.notify_all();
-    if (sv->worker.joinable()) sv->worker.join();
+    for (auto& t : sv->workers)
+        if (t.joinable()) t.join();
     for (auto& a : sv->admitted)
         if (a.c) dao_destroy(a.c);
     sv->admitted.clear();
     while (!sv->live.empty()) server_retire(sv, sv->live.size() - 1, DAO_ESTATE, "server destroyed");
-    if (sv->upload) (void)hipStreamDestroy(sv->upload);
+    for (auto u : sv->uploads) (void)hipStreamDestroy(u);
     delete sv;
 }
 
@@ -2360,6 +2426,10 @@ dao_status dao_server_poll(dao_server* sv, int64_t ticket, int32_t* state, dao_p
                 *state = 0;
                 return DAO_OK;
             }
+        if (sv->building.count(ticket)) {
+            *state = 0;
+            return DAO_OK;
+        }
         return DAO_EINVAL;   // unknown or already collected
     }
     *state = 2;
@@ -2390,7 +2460,7 @@ dao_status dao_server_info(const dao_server* sv_c, int32_t* queued, int32_t* liv
     if (!sv_c) return DAO_EINVAL;
     auto* sv = const_cast<dao_server*>(sv_c);
     std::lock_guard<std::mutex> g(sv->mu);
-    if (queued) *queued = int32_t(sv->queue.size() + sv->admitted.size());
+    if (queued) *queued = int32_t(sv->queue.size() + sv->admitted.size() + sv->building.size());
     if (live) *live = int32_t(sv->live.size());
     if (used_bytes) *used_bytes = sv->used;
     return DAO_OK;

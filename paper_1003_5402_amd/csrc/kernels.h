@@ -656,15 +656,24 @@ __global__ void k_scatter(const TI* __restrict__ in, const int32_t* __restrict__
 
 // F over every caller voxel (eq. 9 + eq. 10); the last block writes *F_out.
 // tau_ext: per-voxel threshold shifts in caller order (null: none).
+// The class table (at most 256 records of 64 B) is copied to LDS first, so
+// a voxel costs one round of independent loads (class index, dose, shift).
+__device__ __forceinline__ void stage_classes(ObjClass* s_cl, const ObjClass* __restrict__ classes, int ncls) {
+    for (int i = threadIdx.x; i < ncls; i += blockDim.x) s_cl[i] = classes[i];
+    __syncthreads();
+}
+
 template <class T>
 __global__ void __launch_bounds__(BLOCK) k_objective_ext(const T* __restrict__ d_ext,
                                                          const uint8_t* __restrict__ cls, int64_t V,
-                                                         const ObjClass* __restrict__ classes,
+                                                         const ObjClass* __restrict__ classes, int ncls,
                                                          const double* __restrict__ tau_ext,
                                                          Rec* parts, Arrival* arr, double* F_out) {
+    __shared__ ObjClass s_cl[MAX_CLASSES];
+    stage_classes(s_cl, classes, ncls);
     Rec r = rec_identity();
     for (int64_t j = int64_t(blockIdx.x) * BLOCK + threadIdx.x; j < V; j += int64_t(gridDim.x) * BLOCK)
-        r.s5 += obj_f(classes[cls[j]], double(d_ext[j]) - tau_at(tau_ext, j));
+        r.s5 += obj_f(s_cl[cls[j]], double(d_ext[j]) - tau_at(tau_ext, j));
     Rec tot;
     const Rec mine = block_reduce(r);
     if (arrive_and_reduce(mine, parts, arr, &tot) && threadIdx.x == 0) *F_out = tot.s5;
@@ -688,13 +697,15 @@ __global__ void k_gather_grad(const T* __restrict__ d_ext, const int32_t* __rest
 template <class T>
 __global__ void __launch_bounds__(BLOCK) k_objective_int(const double* __restrict__ d,
                                                          const uint8_t* __restrict__ cls, int64_t Vpad,
-                                                         const ObjClass* __restrict__ classes,
+                                                         const ObjClass* __restrict__ classes, int ncls,
                                                          T* __restrict__ u, double* __restrict__ u64,
                                                          Rec* parts, Arrival* arr, MasterState* ms) {
+    __shared__ ObjClass s_cl[MAX_CLASSES];
+    stage_classes(s_cl, classes, ncls);
     Rec r = rec_identity();
     for (int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x; i < Vpad;
          i += int64_t(gridDim.x) * BLOCK) {
-        const ObjClass c = classes[cls[i]];
+        const ObjClass c = s_cl[cls[i]];
         const double z = d[i];
         const double gz = grad_f(c, z);
         u[i] = T(gz);
@@ -706,7 +717,21 @@ __global__ void __launch_bounds__(BLOCK) k_objective_int(const double* __restric
     if (arrive_and_reduce(mine, parts, arr, &tot) && threadIdx.x == 0) ms->F = ms->F_const + tot.s5;
 }
 
+// Workgroups are handed to the 8 XCDs round-robin (workgroup b runs on XCD
+// b mod 8), each XCD with its own L2.  xcd_block gives the workgroups of one
+// XCD a contiguous range of [0, n): XCD x takes the x-th eighth.  A bijection
+// of [0, n) for any n.
+__device__ __forceinline__ int xcd_block(int b, int n) {
+    constexpr int NX = 8;
+    const int x = b % NX, k = b / NX;
+    const int per = n / NX, rem = n % NX;   // XCD x runs per + (x < rem) workgroups
+    return x * per + min(x, rem) + k;
+}
+
 // g_i = sum over beamlet i's entries of val * u[row]; one block per beamlet.
+// Beamlets of one beam are adjacent and reach overlapping voxel rows, so
+// each XCD takes a contiguous range of beamlets (xcd_block): its L2 then
+// holds the u rows of a few beams instead of every XCD gathering all of u.
 // GATED (the master's copy) runs only while a finished line search awaits
 // its update (phase PH_UPD of an unfinished master), like k_update.  With a
 // 16-bit value format the column sum is multiplied by the beamlet's scale.
@@ -722,7 +747,7 @@ __global__ void __launch_bounds__(BLOCK) k_gradT(const int32_t* __restrict__ cpt
         __syncthreads();
         if (s_skip) return;
     }
-    const int i = blockIdx.x;
+    const int i = xcd_block(blockIdx.x, gridDim.x);
     const int e0 = cptr[i], e1 = cptr[i + 1];
     Acc acc = Acc(0);
     int e = e0 + threadIdx.x;
@@ -773,6 +798,11 @@ struct RowRec {
     int32_t L, R;
 };
 
+// the last block of k_price stages the row values and beam sums in LDS
+// when they fit (otherwise it reads them from device memory)
+constexpr int PRICE_ROWS_LDS = 4096;
+constexpr int PRICE_BEAMS_LDS = 1024;
+
 struct PriceGeom {
     const int32_t* row_start;
     const int32_t* row_len;
@@ -792,12 +822,15 @@ __global__ void __launch_bounds__(BLOCK) k_price(PriceGeom G, const double* __re
     const bool have = r < G.R;
     const int n = have ? G.row_len[r] : 0;
     double* S = s_S[wave];
+    // every lane loads its price (all loads in flight at once), then lane 0
+    // forms the prefix sums in order from LDS
+    S[lane + 1] = (have && lane < n) ? g[G.row_start[r] + lane] : 0.0;
+    __syncthreads();
     if (lane == 0) {
-        const double* w = have ? g + G.row_start[r] : g;
         double acc = 0.0;
         S[0] = 0.0;
         for (int i = 0; i < WAVE; ++i) {
-            if (i < n) acc += w[i];
+            if (i < n) acc += S[i + 1];
             S[i + 1] = acc;
         }
     }
@@ -856,38 +889,74 @@ __global__ void __launch_bounds__(BLOCK) k_price(PriceGeom G, const double* __re
             rows[r] = rr;
         }
     }
-    // last block: per-beam sums, argmin, gap
+    // last block: per-beam sums (each beam's rows in order), the first
+    // beam of smallest value, the smallest value among the other beams, and
+    // the gap and leaves of the chosen beam's rows
     __shared__ int s_last;
     __syncthreads();
     if (threadIdx.x == 0) s_last = arrive_last(arr);
     __syncthreads();
     if (!s_last) return;
     __threadfence();
+    __shared__ double s_rv[PRICE_ROWS_LDS];    // row values
+    __shared__ double s_bs[PRICE_BEAMS_LDS];   // beam sums
+    __shared__ int s_best;
+    __shared__ double s_bv, s_sv;
+    const bool staged = G.R <= PRICE_ROWS_LDS && G.B <= PRICE_BEAMS_LDS;
+    if (staged) {
+        for (int rr = threadIdx.x; rr < G.R; rr += blockDim.x) s_rv[rr] = rows[rr].v;
+        __syncthreads();
+        for (int b = threadIdx.x; b < G.B; b += blockDim.x) {
+            double sb = 0.0;
+            for (int rr = G.beam_row0[b]; rr < G.beam_row0[b + 1]; ++rr) sb += s_rv[rr];
+            s_bs[b] = sb;
+        }
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
         int best = -1;
         double bv = INFINITY, sv = INFINITY;
         for (int b = 0; b < G.B; ++b) {
-            double s = 0.0;
-            for (int rr = G.beam_row0[b]; rr < G.beam_row0[b + 1]; ++rr) s += rows[rr].v;
-            if (best < 0 || s < bv) {
+            double sb;
+            if (staged) {
+                sb = s_bs[b];
+            } else {
+                sb = 0.0;
+                for (int rr = G.beam_row0[b]; rr < G.beam_row0[b + 1]; ++rr) sb += rows[rr].v;
+            }
+            if (best < 0 || sb < bv) {
                 sv = bv;
-                bv = s;
+                bv = sb;
                 best = b;
-            } else if (s < sv) {
-                sv = s;
+            } else if (sb < sv) {
+                sv = sb;
             }
         }
-        double gap = sv - bv;
-        const int r0 = G.beam_row0[best], r1 = G.beam_row0[best + 1];
-        for (int rr = r0; rr < r1; ++rr) {
-            const RowRec x = rows[rr];
-            gap = fmin(gap, x.second - x.v);
-            res->leaves[2 * (rr - r0)] = int16_t(x.L);
-            res->leaves[2 * (rr - r0) + 1] = int16_t(x.R);
-        }
+        s_best = best;
+        s_bv = bv;
+        s_sv = sv;
+    }
+    __syncthreads();
+    // the chosen beam's rows, one per thread: leaves and the smallest row gap
+    const int best = s_best;
+    const int r0 = G.beam_row0[best], r1 = G.beam_row0[best + 1];
+    double gap_t = INFINITY;
+    for (int rr = r0 + int(threadIdx.x); rr < r1; rr += blockDim.x) {
+        const RowRec x = rows[rr];
+        gap_t = fmin(gap_t, x.second - x.v);
+        res->leaves[2 * (rr - r0)] = int16_t(x.L);
+        res->leaves[2 * (rr - r0) + 1] = int16_t(x.R);
+    }
+    __shared__ double s_gap[BLOCK / WAVE];
+    gap_t = wave_min(gap_t);
+    if (lane == 0) s_gap[wave] = gap_t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double gap = s_sv - s_bv;
+        for (int w = 0; w < BLOCK / WAVE; ++w) gap = fmin(gap, s_gap[w]);
         res->beam = best;
         res->n_rows = r1 - r0;
-        res->rc = bv;
+        res->rc = s_bv;
         res->gap = gap;
     }
 }

@@ -113,3 +113,10 @@ def test_create_enforces_memory_cap():
     ph = cached_phantom("mini")
     msg = _expect(dao.DAO_ENOMEM, _a=_args(ph), _opts=dict(mem_cap_bytes=10000))
     assert "exceeds mem_cap_bytes" in msg
+
+
+def test_server_rejects_bad_options():
+    """dao_server_create checks its options before touching the device."""
+    for kw in (dict(max_live=0), dict(max_live=65), dict(hbm_cap_bytes=-1), dict(workers=-1), dict(workers=17)):
+        with pytest.raises(dao.DaoError):
+            dao.Server(**kw)

@@ -51,12 +51,15 @@ def _run(server, reqs, phs):
     return _drain(server, tickets)
 
 
-@pytest.mark.parametrize("batch_masters", [True, False])
-def test_serving_results_equal_solo_solves(batch_masters):
+@pytest.mark.parametrize("batch_masters,workers", [(True, 4), (False, 1)])
+def test_serving_results_equal_solo_solves(batch_masters, workers):
+    """With one admission thread, and with four building contexts at once
+    (requests may then be admitted out of arrival order)."""
     torch = torch_cuda()
     phs = [make_phantom(n, s) for n, s, _, _ in REQS]
     solo = [_alone(ph, dt, n) for ph, (_, _, dt, n) in zip(phs, REQS)]
-    server = dao.Server(max_live=3, stream=torch.cuda.current_stream().cuda_stream, batch_masters=batch_masters)
+    server = dao.Server(max_live=3, stream=torch.cuda.current_stream().cuda_stream, batch_masters=batch_masters,
+                        workers=workers)
     try:
         res, max_live, _ = _run(server, REQS, phs)
         assert max_live <= 3
