@@ -475,11 +475,12 @@ def main():
         serve["batched_f32"] = run_serving(reqs, stream, args.serve_max_live, cap, False)
         log(f"[bench] serving batched FP32: {serve['batched_f32']}")
         # the precision form: FP16 D with the selective residual (final rounds
-        # and near-tie pricing with the FP16 residual) and an FP16 D_K
-        f16_opts = dict(d_format=dao.DAO_DFMT_F16, d_residual=2, dk_format=dao.DAO_DFMT_F16)
-        serve["f16_options"] = {"d_format": "f16", "d_residual": "selective", "dk_format": "f16"}
+        # and near-tie pricing with the FP16 residual) and D_K in FP16 where
+        # the master streams it (automatic storage)
+        f16_opts = dict(d_format=dao.DAO_DFMT_F16, d_residual=2, dk_format=dao.DAO_DFMT_AUTO)
+        serve["f16_options"] = {"d_format": "f16", "d_residual": "selective", "dk_format": "auto"}
         serve["batched_f16"] = run_serving(reqs, stream, args.serve_max_live, cap, False, **f16_opts)
-        log(f"[bench] serving batched FP16 D + FP16 D_K (selective residual): {serve['batched_f16']}")
+        log(f"[bench] serving batched FP16 D + automatic D_K (selective residual): {serve['batched_f16']}")
         serve["sequential_f32"] = run_serving(reqs, stream, 1, cap, True)
         log(f"[bench] serving sequential FP32: {serve['sequential_f32']}")
         # capacity: the same requests all queued at once, so that plans/s is
@@ -488,10 +489,14 @@ def main():
         serve["saturated_f32"] = run_serving(sat, stream, args.serve_max_live, cap, False)
         log(f"[bench] serving saturated FP32: {serve['saturated_f32']}")
         serve["saturated_f16"] = run_serving(sat, stream, args.serve_max_live, cap, False, **f16_opts)
-        log(f"[bench] serving saturated FP16 D + FP16 D_K (selective residual): {serve['saturated_f16']}")
+        log(f"[bench] serving saturated FP16 D + automatic D_K (selective residual): {serve['saturated_f16']}")
+        serve["saturated_dk_auto"] = run_serving(sat, stream, args.serve_max_live, cap, False,
+                                                 dk_format=dao.DAO_DFMT_AUTO)
+        log(f"[bench] serving saturated FP32 D + automatic D_K: {serve['saturated_dk_auto']}")
         serve["speedup_plans_s"] = serve["batched_f32"]["plans_s"] / serve["sequential_f32"]["plans_s"]
         serve["speedup_f16_plans_s"] = serve["batched_f16"]["plans_s"] / serve["sequential_f32"]["plans_s"]
         serve["saturated_f16_vs_f32"] = serve["saturated_f16"]["plans_s"] / serve["saturated_f32"]["plans_s"]
+        serve["saturated_dk_auto_vs_f32"] = serve["saturated_dk_auto"]["plans_s"] / serve["saturated_f32"]["plans_s"]
 
     algo_per_launch = dk_["algo_bytes_per_plan"] / max(1, dk_["launches"])
     result = {

@@ -168,7 +168,12 @@ typedef struct {
                                dtype) or, for DAO_F32, DAO_DFMT_F16: FP16 values of D_K over
                                the largest entry of D (half the bytes per master pass, about
                                2.4e-4 relative rounding per entry); products accumulate in
-                               FP32 / FP64 as before */
+                               FP32 / FP64 as before; or, for DAO_F32, DAO_DFMT_AUTO: a plan
+                               starts with D_K in FP32 and moves it to FP16 (its columns
+                               rebuilt once) before the first column that would make the pool
+                               too large for the persistent master's on-chip form (from the
+                               start when that form is off: persistent 0 or 1); the buffer is
+                               FP32-sized.  dao_info_t.dk_format reports the storage now */
     int32_t residual_rounds; /* with d_residual 2: the plan's last this many rounds (5) run in
                                the accurate form, see d_residual */
     int32_t graphs;         /* 1: the pricing sequence of every round (exact FP64 dose,
@@ -207,7 +212,7 @@ enum { DAO_MASTER_APERTURE = 0, DAO_MASTER_BEAMLET = 1 };
  * D_ij ~= s_i (hi + lo).  The scale is applied to x before the forward
  * product and to each column sum of the transposed product.  Needs
  * n_blt * 4 bytes of x to fit the on-chip staging (n_blt <= 12288). */
-enum { DAO_DFMT_NATIVE = 0, DAO_DFMT_F16 = 1, DAO_DFMT_BF16 = 2 };
+enum { DAO_DFMT_NATIVE = 0, DAO_DFMT_F16 = 1, DAO_DFMT_BF16 = 2, DAO_DFMT_AUTO = 3 /* dk_format only */ };
 
 /* The host encoder of that storage, for inspection and tests: for each of
  * n ratios r[i] (finite, >= 0) writes hi[i] (the 16-bit pattern of

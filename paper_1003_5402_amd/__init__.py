@@ -9,7 +9,7 @@ the stream is a raw ``hipStream_t`` (``torch.cuda.current_stream().cuda_stream``
 """
 from __future__ import annotations
 
-from .binding import (DAO_DFMT_BF16, DAO_DFMT_F16, DAO_DFMT_NATIVE, DAO_EDEVICE, DAO_EINVAL, DAO_ENOMEM,
+from .binding import (DAO_DFMT_AUTO, DAO_DFMT_BF16, DAO_DFMT_F16, DAO_DFMT_NATIVE, DAO_EDEVICE, DAO_EINVAL, DAO_ENOMEM,
                       DAO_EOPTIMAL, DAO_ESTALLED, DAO_ESTATE, DAO_F32, DAO_F64, DAO_MASTER_APERTURE,
                       DAO_MASTER_BEAMLET, DAO_OK, DaoError, DaoContext, Server, encode_values,
                       load_library, solve_batch, symbols, write_round_log)  # noqa: F401

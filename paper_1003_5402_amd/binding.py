@@ -14,7 +14,7 @@ DAO_OK, DAO_EOPTIMAL, DAO_ESTALLED, DAO_ENOTCONV = 0, 1, 2, 3
 DAO_EINVAL, DAO_ENOMEM, DAO_EDEVICE, DAO_ESTATE = -1, -2, -3, -4
 DAO_F64, DAO_F32 = 0, 1
 DAO_MASTER_APERTURE, DAO_MASTER_BEAMLET = 0, 1
-DAO_DFMT_NATIVE, DAO_DFMT_F16, DAO_DFMT_BF16 = 0, 1, 2
+DAO_DFMT_NATIVE, DAO_DFMT_F16, DAO_DFMT_BF16, DAO_DFMT_AUTO = 0, 1, 2, 3
 DAO_DIR_STEEPEST, DAO_DIR_CONJUGATE = 0, 1
 _NAMES = {0: "DAO_OK", 1: "DAO_EOPTIMAL", 2: "DAO_ESTALLED", 3: "DAO_ENOTCONV", -1: "DAO_EINVAL",
           -2: "DAO_ENOMEM",

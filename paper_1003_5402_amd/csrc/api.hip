@@ -131,6 +131,7 @@ struct dao_ctx {
     double* uabs64 = nullptr;         // [Vpad] |grad F|
     double dk_scale = 1.0;            // D_K = dk_scale * stored value
     double dk16_scale = 1.0;          // dk_scale while D_K is stored in FP16
+    bool dk16_base = false;           // the storage a plan starts with (dk_format, resolved at creation)
     double* tau_int = nullptr;        // per-voxel threshold shifts, internal rows (null: none)
     double* tau_ext = nullptr;        // the same in caller order
     unsigned char* scratch_dev = nullptr;   // this device's copy of the static pricing scratch
@@ -245,7 +246,9 @@ int64_t predicted_bytes(const HostLayout& L, size_t ts, int kmax, const dao_opti
     b += int64_t(L.R) * 8 + (L.B + 1) * 4 + L.N * 12;
     b += L.Vpad * (8 + 3 * ts + 8) + L.N * (ts + 8 + ts + 8);
     b += int64_t(kmax) * (4 + 2 * 2 * L.max_rows_per_beam + 24);
-    const int64_t dkb = (opt.dk_format == DAO_DFMT_F16 && ts == 4) ? 2 : int64_t(ts);
+    // FP16 D_K: 2 bytes, unless the selective residual keeps an FP32-sized
+    // buffer; the automatic choice is counted at the native size (a bound)
+    const int64_t dkb = (opt.dk_format == DAO_DFMT_F16 && ts == 4 && opt.d_residual != 2) ? 2 : int64_t(ts);
     b += int64_t(L.Vpad) * KS * dkb + L.N * ts + 512 * (KS + 1) * 8;
     b += sizeof(MasterState) + sizeof(PriceResult) + L.R * sizeof(RowRec) + 2 * ELEM_BLOCKS_MAX * sizeof(Rec) +
          sizeof(Arrival);
@@ -539,10 +542,34 @@ dao_status enqueue_cycle_ap(dao_ctx* c) {
     return enqueue_cycle_ap_dt<T, T>(c);
 }
 
+// Whether the persistent master keeps D_K on chip in the context type for a
+// pool of K apertures (the same test its launch makes).
+template <class T>
+bool dk_on_chip(const dao_ctx* c, int K) {
+    if (c->opt.persistent != 2 || c->coop_grid <= 0) return false;
+    const int nc = (K + DKG<T>::EPL - 1) / DKG<T>::EPL;
+    const int64_t rows = coop_batches_per_group<T>(c->Vpad, c->coop_grid) * Batch<T>::ROWS;
+    return coop_lds_bytes<T>(rows, nc) <= size_t(c->coop_lds_max);
+}
+
 // Column k of the aperture dose matrix: D times the 0/1 indicator of aperture k.
+// With dk_format DAO_DFMT_AUTO a plan starts with D_K in FP32 and moves it to
+// FP16 (its columns rebuilt once) before the first column that would make the
+// pool too large for the on-chip master form.
 template <class T>
 dao_status build_dk_column(dao_ctx* c, int k) {
     if (!c->ap_master()) return DAO_OK;
+    if constexpr (std::is_same<T, float>::value) {
+        if (c->opt.dk_format == DAO_DFMT_AUTO && !c->dk16 && !c->final_phase && !dk_on_chip<T>(c, k + 1)) {
+            c->dk16 = true;
+            c->dk_scale = c->dk16_scale;
+            HIPCHK(c, hipMemsetAsync(c->dk, 0, size_t(c->Vpad) * KS * sizeof(T), c->stream));
+            for (int j = 0; j < k; ++j) {
+                const dao_status s = build_dk_column<T>(c, j);
+                if (s != DAO_OK) return s;
+            }
+        }
+    }
     k_ap_indicator<T><<<(c->N + BLOCK - 1) / BLOCK, BLOCK, 0, c->stream>>>(pool_view(c), k, static_cast<T*>(c->ind));
     with_values<T>(c, [&](auto tag) {
         using VT = typename decltype(tag)::VT;
@@ -776,17 +803,20 @@ dao_status price_current(dao_ctx* c, int32_t* beam, int16_t* leaves, double* rc,
 template <class T>
 dao_status reset_state(dao_ctx* c) {
     const int64_t eb = c->elem_blocks(c->Vpad);
-    // a new pool starts in the fast form of the selective residual
-    const bool dk_was_f32 = c->final_phase && !c->dk16;
+    // a new pool starts in the fast form of the selective residual and in
+    // the starting storage of D_K
+    const bool dk_prev = c->dk16;
     c->lo_now = false;
     c->final_phase = false;
     c->reprices = 0;
-    c->dk16 = std::is_same<T, float>::value && c->ap_master() && c->opt.dk_format == DAO_DFMT_F16;
+    c->dk16 = c->dk16_base;
     c->dk_scale = c->dk16 ? c->dk16_scale : 1.0;
-    // FP16 columns are written over the FP32 ones of the last final phase:
-    // clear the buffer, so that no slot beyond the pool holds a stale value
-    // (the products multiply every slot of a row's last group by 0)
-    if (c->dk16 && dk_was_f32)
+    // columns of one storage are about to be written over those of the
+    // other (the selective residual's final phase, the automatic storage's
+    // switch; both keep an FP32-sized buffer): clear it, so that no slot
+    // beyond the pool holds a stale value (the products multiply every slot
+    // of a row's last vector by 0)
+    if (c->ap_master() && c->dk16 != dk_prev)
         HIPCHK(c, hipMemsetAsync(c->dk, 0, size_t(c->Vpad) * KS * sizeof(T), c->stream));
     // zero dose; the master keeps d - tau
     k_neg_or_zero<<<eb, BLOCK, 0, c->stream>>>(c->tau_int, c->Vpad, c->d);
@@ -1002,27 +1032,23 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
     TRY(dev_alloc(c, &c->upd_parts, c->slab_blocks() * sizeof(Rec)));
     TRY(dev_alloc(c, &c->arr, sizeof(Arrival)));
     TRY(dev_alloc(c, &c->pc, sizeof(ProfCounters)));
-    // FP16 storage of D_K: values over the largest entry of D (every D_K
-    // entry is a sum of D entries, so the stored values stay well inside
-    // FP16's range)
-    c->dk16 = std::is_same<T, float>::value && c->ap_master() && c->opt.dk_format == DAO_DFMT_F16;
-    if (c->dk16) {
-        float mx = 0.0f;
-        for (float v : L.col_scale) mx = std::max(mx, v);
-        c->dk16_scale = mx > 0.0f ? double(mx) : 1.0;
-    }
-    c->dk_scale = c->dk16 ? c->dk16_scale : 1.0;
-    // bytes per stored D_K value; the selective residual switches D_K to FP32
-    // for the final rounds, so its buffer holds FP32 values
-    const size_t dkb = (c->dk16 && c->opt.d_residual != 2) ? sizeof(__half) : ts;
+    // storage of D_K: FP16 on request, or (DAO_DFMT_AUTO) where the master
+    // cannot keep it on chip
+    constexpr bool f32 = std::is_same<T, float>::value;
+    c->dk16 = f32 && c->ap_master() && c->opt.dk_format == DAO_DFMT_F16;
+    // DAO_DFMT_AUTO: without the persistent launch the per-phase kernels
+    // always stream D_K, so FP16 from the start; otherwise a plan starts in
+    // FP32 and moves to FP16 when the pool outgrows the on-chip form
+    const bool dk_auto = f32 && c->ap_master() && c->opt.dk_format == DAO_DFMT_AUTO;
+    if (dk_auto && !c->opt.persistent) c->dk16 = true;
     if (c->ap_master() && c->opt.persistent) {
         int dev = 0, coop = 0, ncu = 0;
         HIPCHK(c, hipGetDevice(&dev));
         c->device = dev;
         HIPCHK(c, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
         HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-        if constexpr (std::is_same<T, float>::value) {
-            if (c->dk16 && c->opt.d_residual == 2) {
+        if constexpr (f32) {
+            if ((c->dk16 && c->opt.d_residual == 2) || dk_auto) {
                 // both storages run: keep the smaller on-chip budget
                 HIPCHK(c, (setup_coop<T, T>(c, dev, coop, ncu)));
                 const int lds_f = c->coop_lds_max;
@@ -1044,6 +1070,19 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
             TRY(dev_alloc(c, &c->coop_recs, 2 * size_t(c->coop_grid) * RECW * sizeof(double)));
         }
     }
+    // FP16 storage of D_K: values over the largest entry of D (every D_K
+    // entry is a sum of D entries, so the stored values stay well inside
+    // FP16's range)
+    c->dk16_base = c->dk16;
+    if (c->dk16 || dk_auto) {
+        float mx = 0.0f;
+        for (float v : L.col_scale) mx = std::max(mx, v);
+        c->dk16_scale = mx > 0.0f ? double(mx) : 1.0;
+    }
+    c->dk_scale = c->dk16 ? c->dk16_scale : 1.0;
+    // bytes per stored D_K value; the selective residual switches D_K to FP32
+    // for the final rounds, so its buffer holds FP32 values
+    const size_t dkb = (c->dk16 && c->opt.d_residual != 2 && !(dk_auto && c->opt.persistent)) ? sizeof(__half) : ts;
     if (c->ap_master()) {
         // D_K is stored in blocks of one batch of rows; the padded row count
         // (whole slices) is a whole number of blocks in every storage type

@@ -117,8 +117,8 @@ dao_status validate_inputs(const dao_matrix* D, const dao_beams* beams,
         return fail("direction must be DAO_DIR_STEEPEST or DAO_DIR_CONJUGATE");
     if (opt->apertures_per_round < 1 || opt->apertures_per_round > 16)
         return fail("apertures_per_round must be in [1, 16]");
-    if (opt->dk_format != DAO_DFMT_NATIVE && opt->dk_format != DAO_DFMT_F16)
-        return fail("dk_format must be DAO_DFMT_NATIVE or DAO_DFMT_F16");
+    if (opt->dk_format != DAO_DFMT_NATIVE && opt->dk_format != DAO_DFMT_F16 && opt->dk_format != DAO_DFMT_AUTO)
+        return fail("dk_format must be DAO_DFMT_NATIVE, DAO_DFMT_F16 or DAO_DFMT_AUTO");
     if (opt->dk_format == DAO_DFMT_F16 && (opt->dtype != DAO_F32 || opt->master != DAO_MASTER_APERTURE))
         return fail("an FP16 aperture dose matrix needs dtype DAO_F32 and the aperture-matrix master");
     if (opt->d_format < DAO_DFMT_NATIVE || opt->d_format > DAO_DFMT_BF16)

@@ -82,7 +82,7 @@ def test_create_rejects_malformed_inputs():
                          (dict(d_format=1, d_residual=3), "d_residual"),
                          (dict(d_format=1, d_residual=2, residual_rounds=-1), "residual_rounds"),
                          (dict(direction=2), "direction"), (dict(apertures_per_round=0), "apertures_per_round"),
-                         (dict(apertures_per_round=17), "apertures_per_round"), (dict(dk_format=2), "dk_format"),
+                         (dict(apertures_per_round=17), "apertures_per_round"), (dict(dk_format=2), "dk_format"), (dict(dk_format=4), "dk_format"),
                          (dict(dk_format=1, dtype="f64"), "DAO_F32"), (dict(dk_format=1, master=1), "aperture"),
                          (dict(d_format=1, dtype="f64"), "DAO_F32"), (dict(d_format=2, master=1), "aperture"),
                          (dict(product_tune=2), "product_tune"), (dict(dose_variant=7), "dose_variant"),

@@ -227,3 +227,34 @@ def test_selective_residual_plan():
         assert pool2 == pool and np.array_equal(np.asarray(y2), np.asarray(y))
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("name,expect", [("headneck", "f16"), ("prostate", "native")])
+def test_automatic_dk_storage(name, expect):
+    """dk_format = DAO_DFMT_AUTO: a plan starts with D_K in FP32 and moves it
+    to FP16 once the pool outgrows the master's on-chip form.  The
+    head-and-neck-shaped matrix does so after a few apertures, and its plan
+    stays within the FP16 bar (1e-3) of the FP32 plan; the prostate-shaped
+    one stays on chip in FP32, so its plan equals the FP32 plan bit for bit.
+    A second plan on the same context (back to FP32 storage, the buffer
+    cleared) repeats the first bit for bit."""
+    ph = cached_phantom(name)
+    n = 12
+    auto = ctx_for(ph, dtype="f32", dk_format=dao.DAO_DFMT_AUTO)
+    ref = ctx_for(ph, dtype="f32")
+    try:
+        assert auto.info()["dk_format"] == FMT["native"]
+        a, b = auto.solve(n), ref.solve(n)
+        got = auto.info()["dk_format"]
+        print(f"[precision] {name} auto D_K: {got}, F {a['F']:.12e} FP32 {b['F']:.12e}", flush=True)
+        assert got == FMT[expect] and a["rounds"] == b["rounds"] == n
+        if expect == "native":
+            assert a["F"] == b["F"] and list(a["round_beam"]) == list(b["round_beam"])
+            assert list(a["round_steps"]) == list(b["round_steps"])
+        else:
+            assert abs(a["F"] - b["F"]) <= 1e-3 * b["F"]
+        again = auto.solve(n)
+        assert again["F"] == a["F"] and list(again["round_beam"]) == list(a["round_beam"])
+    finally:
+        auto.close()
+        ref.close()
