@@ -387,9 +387,9 @@ __global__ void __launch_bounds__(1024) k_dir_ap(const double* __restrict__ part
         bool fk;
         const double pk = cg_dir_wave(in, yk, gk, mem, in && mem ? p[k] : 0.0, in && mem ? cgm->r[k] : 0.0,
                                       in && mem && cgm->free[k] != 0, rk, fk);
-        const double kkt = wave_max(in ? fabs(fmin(yk, gk)) : 0.0);
-        const double tmax = wave_min(pk < 0.0 ? yk / (-pk) : INFINITY);
-        const double gp = wave_sum(gk * pk);
+        const double kkt = wave_reduce_dpp<2>(in ? fabs(fmin(yk, gk)) : 0.0);
+        const double tmax = wave_reduce_dpp<1>(pk < 0.0 ? yk / (-pk) : INFINITY);
+        const double gp = wave_reduce_dpp<0>(gk * pk);   // as the persistent master sums it
         const bool any = __any(rk != 0.0);
         // the memory and p change only when a step is taken
         const bool take = kkt > s_ms.tol && s_ms.steps < s_ms.max_steps && any;

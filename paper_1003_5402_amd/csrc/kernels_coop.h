@@ -65,38 +65,6 @@ __device__ __forceinline__ double rec_init(int i) {
     return 0.0;
 }
 
-// Wavefront reductions through DPP lane moves (no LDS round trip).  The
-// order is fixed: xor 1, xor 2 inside quads, half-row mirror, row mirror,
-// then the row broadcasts; lane 63 ends with the total, which is then read
-// into every lane.  Call with all 64 lanes active.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_move(double v, double ident) {
-    const long long b = __double_as_longlong(v), id = __double_as_longlong(ident);
-    const int lo = __builtin_amdgcn_update_dpp(int(id), int(b), CTRL, ROW_MASK, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(int(id >> 32), int(b >> 32), CTRL, ROW_MASK, 0xf, false);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-__device__ __forceinline__ double lane63(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane(int(b), 63), hi = __builtin_amdgcn_readlane(int(b >> 32), 63);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-// op: 0 sum, 1 min, 2 max
-template <int OP>
-__device__ __forceinline__ double dpp_comb(double a, double b) {
-    return OP == 0 ? a + b : OP == 1 ? fmin(a, b) : fmax(a, b);
-}
-template <int OP>
-__device__ __forceinline__ double wave_reduce_dpp(double v) {
-    const double id = OP == 0 ? 0.0 : OP == 1 ? INFINITY : -INFINITY;
-    v = dpp_comb<OP>(v, dpp_move<0xB1, 0xF>(v, id));    // quad_perm [1,0,3,2]
-    v = dpp_comb<OP>(v, dpp_move<0x4E, 0xF>(v, id));    // quad_perm [2,3,0,1]
-    v = dpp_comb<OP>(v, dpp_move<0x141, 0xF>(v, id));   // row_half_mirror
-    v = dpp_comb<OP>(v, dpp_move<0x140, 0xF>(v, id));   // row_mirror
-    v = dpp_comb<OP>(v, dpp_move<0x142, 0xA>(v, id));   // row_bcast15 into rows 1, 3
-    v = dpp_comb<OP>(v, dpp_move<0x143, 0xC>(v, id));   // row_bcast31 into rows 2, 3
-    return lane63(v);
-}
 __device__ __forceinline__ double field_reduce_dpp(bool ls, int f, double v) {
     if (ls && f == 3) return wave_reduce_dpp<1>(v);
     if (ls && f == 4) return wave_reduce_dpp<2>(v);
