@@ -617,7 +617,8 @@ dao_status run_master_coop_dt(dao_ctx* c, double tol, int max_steps) {
         c->last_form = 2;
     } else {
         HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T, DT, false>),
-                                             dim3(c->coop_grid), dim3(COOP_THREADS), args, 0, c->stream));
+                                             dim3(c->coop_grid), dim3(COOP_THREADS), args, coop_stream_lds<DT>(),
+                                             c->stream));
         c->last_form = 1;
     }
     if (prof) {
@@ -868,8 +869,19 @@ hipError_t setup_coop(dao_ctx* c, int dev, int coop, int ncu) {
     int occ = 0;
     c->coop_lds_max = 0;
     c->batch_ok = false;
+    c->coop_grid = 0;
+    // the streaming form's dynamic LDS (the q pass's row partials)
+    constexpr int slds = int(coop_stream_lds<DT>());
+    for (const void* fn : {reinterpret_cast<const void*>(&k_master_coop<T, DT, false>),
+                           reinterpret_cast<const void*>(&k_master_batch<T, DT, false>)}) {
+        const hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, slds);
+        if (ea != hipSuccess) {
+            (void)hipGetLastError();
+            return hipSuccess;   // no persistent master on this device
+        }
+    }
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &occ, reinterpret_cast<const void*>(&k_master_coop<T, DT, false>), COOP_THREADS, 0);
+        &occ, reinterpret_cast<const void*>(&k_master_coop<T, DT, false>), COOP_THREADS, slds);
     if (e != hipSuccess) return e;
     if (coop && occ > 0 && ncu > 0) {
         c->coop_grid = std::min(ncu, MAX_COOP_GRID);   // one co-resident workgroup per compute unit
@@ -903,7 +915,8 @@ hipError_t setup_coop(dao_ctx* c, int dev, int coop, int ncu) {
         int occ3 = 0, occ4 = 0;
         c->batch_ok =
             hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &occ3, reinterpret_cast<const void*>(&k_master_batch<T, DT, false>), COOP_THREADS, 0) == hipSuccess &&
+                &occ3, reinterpret_cast<const void*>(&k_master_batch<T, DT, false>), COOP_THREADS,
+                coop_stream_lds<DT>()) == hipSuccess &&
             occ3 >= 1;
         if (c->batch_ok && c->coop_lds_max > 0 &&
             !(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_master_batch<T, DT, true>),
@@ -1634,7 +1647,7 @@ dao_status run_master_batch_dt(std::vector<PlanRun*>& live) {
                                               dim3(COOP_THREADS), kargs, lds, c0->stream));
     else
         HIPCHK(c0, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_batch<T, DT, false>), dim3(G),
-                                              dim3(COOP_THREADS), kargs, 0, c0->stream));
+                                              dim3(COOP_THREADS), kargs, coop_stream_lds<DT>(), c0->stream));
     for (PlanRun* r : live) r->c->last_form = fits ? 4 : 3;
     for (PlanRun* r : live)
         HIPCHK(r->c, hipMemcpyAsync(r->c->ms_h, r->c->ms, sizeof(MasterState), hipMemcpyDeviceToHost, r->c->stream));

@@ -184,6 +184,21 @@ __device__ __forceinline__ double group_sum(double v) {
     }
 }
 
+// The same sum for one row whose LPR per-slot partials sit in memory (x[c]
+// the partial of lane c): the butterfly's pairs, in the butterfly's order.
+template <int LPR>
+__device__ __forceinline__ double row_tree(const double* x) {
+    constexpr int H = LPR / 2;
+    double pc[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) pc[j] = x[j] + x[j + H];
+#pragma unroll
+    for (int off = H / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int j = 0; j < off; ++j) pc[j] = pc[j] + pc[j + off];
+    return pc[0];
+}
+
 // ind[i] = 1 if beamlet i is open in pool aperture k, else 0.
 template <class T>
 __global__ void k_ap_indicator(PoolView P, int k, T* __restrict__ ind) {

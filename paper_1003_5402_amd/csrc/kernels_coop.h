@@ -234,6 +234,14 @@ __host__ __device__ inline int64_t coop_batches_per_group(int64_t Vpad, int grid
     return (nbat + grid - 1) / grid;
 }
 
+// Dynamic LDS of the streaming form: per wavefront, the per-slot partials of
+// one batch's rows in the q pass (ROWS rows of LPR + 1 doubles; the pad
+// spreads a lane's row reads over the banks).
+template <class DT>
+__host__ __device__ constexpr size_t coop_stream_lds() {
+    return size_t(COOP_THREADS / WAVE) * Batch<DT>::ROWS * (DKG<DT>::LPR + 1) * sizeof(double);
+}
+
 // 16-byte vectors per on-chip D_K row: the nc the pool needs, rounded up to
 // an odd count, so that lanes reading consecutive rows at the same slot
 // (the line search's one row per thread) fall in distinct LDS banks.
@@ -524,7 +532,6 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             double pv[G::EPL];
 #pragma unroll
             for (int e = 0; e < G::EPL; ++e) pv[e] = s_p[c * G::EPL + e] * dks;
-            double* sq = s_u[wave];
             if (LDSRES) {
                 // one row per thread, straight from LDS; q's per-slot partials
                 // are combined in the order of the lane butterfly of the
@@ -579,24 +586,30 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                         c_pre = cls_at(base + lane);
                         if (!first) q_pre = q_at(base + lane);
                     }
+                    double qsum = 0.0;
                     if (first) {
                         V v[IT];
                         load_batch<DT>(dk, base, rg, c, nc, v);
+                        // each lane's per-slot partials go to LDS, then every
+                        // row is summed by its own lane in the order of the lane
+                        // butterfly (row_tree): the q of the on-chip form
+                        constexpr int TPS = G::LPR + 1;
+                        double* tp = reinterpret_cast<double*>(dyn) + size_t(wave) * ROWS * TPS;
 #pragma unroll
                         for (int it = 0; it < IT; ++it) {
                             double part = 0.0;
 #pragma unroll
                             for (int e = 0; e < G::EPL; ++e) part += vget(v[it], e) * pv[e];
-                            part = group_sum<G::LPR>(part);
-                            if (c == 0) sq[it * G::RPW + rg] = part;
+                            tp[(it * G::RPW + rg) * TPS + c] = part;
                         }
                         wave_sync();
+                        if (lane < ROWS) qsum = row_tree<G::LPR>(tp + lane * TPS);
                     }
                     if (lane < ROWS) {
                         const int64_t row = base + lane;
                         T qt;
                         if (first) {
-                            qt = T(sq[lane]);   // the line search and the update use the stored value
+                            qt = T(qsum);   // the line search and the update use the stored value
                             q_at(row) = qt;
                         } else {
                             qt = q_pre;
