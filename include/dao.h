@@ -136,9 +136,9 @@ typedef struct {
     int32_t persistent;     /* aperture master: 2 (default) runs each master solve as one
                                cooperative launch when the device supports it, each
                                workgroup holding its rows of D_K, d and q in LDS when they
-                               fit (else as 1); 1 is that launch streaming D_K from device
-                               memory on every pass; 0 launches each phase of each step
-                               separately */
+                               fit, else only its d, q and classes (D_K streamed), else as 1;
+                               1 is that launch streaming D_K, d and q from device memory on
+                               every pass; 0 launches each phase of each step separately */
     int32_t product_tune;   /* 1 (default): dao_create times the variants of the two
                                sparse products (how many loads each thread keeps in
                                flight, and for native values whether x is staged on
@@ -247,9 +247,10 @@ typedef struct {
     int32_t dose_variant;     /* forward product variant in use (as dao_options.dose_variant) */
     int32_t gradient_depth;   /* transposed product: entries per thread in flight (4, 8, 16) */
     int32_t last_master_form; /* how the last master solve ran: -1 none yet, 0 one launch per
-                                 phase, 1 persistent launch streaming D_K, 2 persistent launch
-                                 with each workgroup's rows on chip, 3 / 4 the batched launch
-                                 streaming / on chip */
+                                 phase, 1 persistent launch streaming D_K, d and q, 2 persistent
+                                 launch with each workgroup's rows (D_K, d, q) on chip, 5
+                                 persistent launch streaming D_K with each workgroup's d and q
+                                 on chip, 3 / 4 / 6 the batched launch in forms 1 / 2 / 5 */
     int32_t onchip_lds_bytes; /* dynamic LDS a workgroup of the persistent launch may use for
                                  its rows (0: the on-chip form is unavailable) */
     int32_t dk_format;        /* storage of D_K now (DAO_DFMT_NATIVE or DAO_DFMT_F16) */

@@ -607,16 +607,23 @@ dao_status run_master_coop_dt(dao_ctx* c, double tol, int max_steps) {
         dao_status s = prof_mark(c, 4, true);
         if (s != DAO_OK) return s;
     }
-    // LDS-resident variant when the workgroup's slice fits on chip
+    // the form: the workgroup's rows on chip when they fit, else d, q and
+    // the classes on chip with D_K streamed, else everything streamed
+    // (persistent 1 always streams everything)
     const int nc = (c->K + DKG<DT>::EPL - 1) / DKG<DT>::EPL;
     const int64_t rows = coop_batches_per_group<DT>(c->Vpad, c->coop_grid) * Batch<DT>::ROWS;
-    const size_t lds = coop_lds_bytes<T>(rows, nc);
-    if (c->opt.persistent == 2 && c->coop_lds_max > 0 && lds <= size_t(c->coop_lds_max)) {
-        HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T, DT, true>),
+    const size_t lds = coop_lds_bytes<T>(rows, nc), lds_h = coop_hybrid_lds<T, DT>(rows);
+    const bool chip_ok = c->opt.persistent == 2 && c->coop_lds_max > 0;
+    if (chip_ok && lds <= size_t(c->coop_lds_max)) {
+        HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T, DT, COOP_CHIP>),
                                              dim3(c->coop_grid), dim3(COOP_THREADS), args, lds, c->stream));
         c->last_form = 2;
+    } else if (chip_ok && lds_h <= size_t(c->coop_lds_max)) {
+        HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T, DT, COOP_HYBRID>),
+                                             dim3(c->coop_grid), dim3(COOP_THREADS), args, lds_h, c->stream));
+        c->last_form = 5;
     } else {
-        HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T, DT, false>),
+        HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_coop<T, DT, COOP_STREAM>),
                                              dim3(c->coop_grid), dim3(COOP_THREADS), args, coop_stream_lds<DT>(),
                                              c->stream));
         c->last_form = 1;
@@ -872,8 +879,8 @@ hipError_t setup_coop(dao_ctx* c, int dev, int coop, int ncu) {
     c->coop_grid = 0;
     // the streaming form's dynamic LDS (the q pass's row partials)
     constexpr int slds = int(coop_stream_lds<DT>());
-    for (const void* fn : {reinterpret_cast<const void*>(&k_master_coop<T, DT, false>),
-                           reinterpret_cast<const void*>(&k_master_batch<T, DT, false>)}) {
+    for (const void* fn : {reinterpret_cast<const void*>(&k_master_coop<T, DT, COOP_STREAM>),
+                           reinterpret_cast<const void*>(&k_master_batch<T, DT, COOP_STREAM>)}) {
         const hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, slds);
         if (ea != hipSuccess) {
             (void)hipGetLastError();
@@ -881,7 +888,7 @@ hipError_t setup_coop(dao_ctx* c, int dev, int coop, int ncu) {
         }
     }
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &occ, reinterpret_cast<const void*>(&k_master_coop<T, DT, false>), COOP_THREADS, slds);
+        &occ, reinterpret_cast<const void*>(&k_master_coop<T, DT, COOP_STREAM>), COOP_THREADS, slds);
     if (e != hipSuccess) return e;
     if (coop && occ > 0 && ncu > 0) {
         c->coop_grid = std::min(ncu, MAX_COOP_GRID);   // one co-resident workgroup per compute unit
@@ -890,24 +897,32 @@ hipError_t setup_coop(dao_ctx* c, int dev, int coop, int ncu) {
         int lds_max = 0;
         e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         if (e != hipSuccess) return e;
-        // the kernels' own static LDS (the larger of the single and the
-        // batched launch), rounded up to 1 KB
+        // the kernels' own static LDS (the largest of the single and the
+        // batched launch in the two forms with rows on chip), rounded up to 1 KB
         int stat = 0;
-        for (const void* fn : {reinterpret_cast<const void*>(&k_master_coop<T, DT, true>),
-                               reinterpret_cast<const void*>(&k_master_batch<T, DT, true>)}) {
+        for (const void* fn : {reinterpret_cast<const void*>(&k_master_coop<T, DT, COOP_CHIP>),
+                               reinterpret_cast<const void*>(&k_master_batch<T, DT, COOP_CHIP>),
+                               reinterpret_cast<const void*>(&k_master_coop<T, DT, COOP_HYBRID>),
+                               reinterpret_cast<const void*>(&k_master_batch<T, DT, COOP_HYBRID>)}) {
             hipFuncAttributes fa{};
             if (hipFuncGetAttributes(&fa, fn) == hipSuccess) stat = std::max(stat, int(fa.sharedSizeBytes));
             else stat = std::max(stat, 32 * 1024);
         }
         const int want = lds_max - ((stat + 1023) / 1024) * 1024;
         if (want > 0 &&
-            hipFuncSetAttribute(reinterpret_cast<const void*>(&k_master_coop<T, DT, true>),
+            hipFuncSetAttribute(reinterpret_cast<const void*>(&k_master_coop<T, DT, COOP_CHIP>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, want) == hipSuccess &&
+            hipFuncSetAttribute(reinterpret_cast<const void*>(&k_master_coop<T, DT, COOP_HYBRID>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, want) == hipSuccess) {
-            int occ2 = 0;
+            int occ2 = 0, occ5 = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &occ2, reinterpret_cast<const void*>(&k_master_coop<T, DT, true>), COOP_THREADS, want) ==
+                    &occ2, reinterpret_cast<const void*>(&k_master_coop<T, DT, COOP_CHIP>), COOP_THREADS, want) ==
                     hipSuccess &&
-                occ2 >= 1)
+                occ2 >= 1 &&
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &occ5, reinterpret_cast<const void*>(&k_master_coop<T, DT, COOP_HYBRID>), COOP_THREADS, want) ==
+                    hipSuccess &&
+                occ5 >= 1)
                 c->coop_lds_max = want;
         }
         (void)hipGetLastError();
@@ -915,16 +930,23 @@ hipError_t setup_coop(dao_ctx* c, int dev, int coop, int ncu) {
         int occ3 = 0, occ4 = 0;
         c->batch_ok =
             hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &occ3, reinterpret_cast<const void*>(&k_master_batch<T, DT, false>), COOP_THREADS,
+                &occ3, reinterpret_cast<const void*>(&k_master_batch<T, DT, COOP_STREAM>), COOP_THREADS,
                 coop_stream_lds<DT>()) == hipSuccess &&
             occ3 >= 1;
+        int occ6 = 0;
         if (c->batch_ok && c->coop_lds_max > 0 &&
-            !(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_master_batch<T, DT, true>),
+            !(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_master_batch<T, DT, COOP_CHIP>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, c->coop_lds_max) == hipSuccess &&
               hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                  &occ4, reinterpret_cast<const void*>(&k_master_batch<T, DT, true>), COOP_THREADS,
+                  &occ4, reinterpret_cast<const void*>(&k_master_batch<T, DT, COOP_CHIP>), COOP_THREADS,
                   c->coop_lds_max) == hipSuccess &&
-              occ4 >= 1))
+              occ4 >= 1 &&
+              hipFuncSetAttribute(reinterpret_cast<const void*>(&k_master_batch<T, DT, COOP_HYBRID>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, c->coop_lds_max) == hipSuccess &&
+              hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &occ6, reinterpret_cast<const void*>(&k_master_batch<T, DT, COOP_HYBRID>), COOP_THREADS,
+                  c->coop_lds_max) == hipSuccess &&
+              occ6 >= 1))
             c->batch_ok = false;
         (void)hipGetLastError();
     }
@@ -1617,8 +1639,9 @@ dao_status run_master_batch_dt(std::vector<PlanRun*>& live) {
     auto* hargs = reinterpret_cast<CoopArgs<T>*>(c0->batch_host);
     auto* hstart = reinterpret_cast<int32_t*>(static_cast<char*>(c0->batch_host) +
                                               size_t(MAX_BATCH) * sizeof(CoopArgs<double>));
-    size_t lds = 0;
+    size_t lds = 0, lds_h = 0;
     bool fits = c0->opt.persistent == 2 && c0->coop_lds_max > 0;
+    bool fits_h = fits;
     hstart[0] = 0;
     for (int i = 0; i < n; ++i) {
         dao_ctx* c = live[i]->c;
@@ -1630,9 +1653,12 @@ dao_status run_master_batch_dt(std::vector<PlanRun*>& live) {
                                c->coop_recs, c->coop, c->pc, 0};
         hstart[i + 1] = hstart[i] + g[i];
         const int nc = (c->K + DKG<DT>::EPL - 1) / DKG<DT>::EPL;
-        const size_t li = coop_lds_bytes<T>(coop_batches_per_group<DT>(c->Vpad, g[i]) * Batch<DT>::ROWS, nc);
+        const int64_t rows_i = coop_batches_per_group<DT>(c->Vpad, g[i]) * Batch<DT>::ROWS;
+        const size_t li = coop_lds_bytes<T>(rows_i, nc), lh = coop_hybrid_lds<T, DT>(rows_i);
         lds = std::max(lds, li);
+        lds_h = std::max(lds_h, lh);
         fits = fits && c->opt.persistent == 2 && li <= size_t(c0->coop_lds_max);
+        fits_h = fits_h && c->opt.persistent == 2 && lh <= size_t(c0->coop_lds_max);
     }
     HIPCHK(c0, hipMemcpyAsync(c0->batch_args, hargs, size_t(n) * sizeof(CoopArgs<T>), hipMemcpyHostToDevice,
                               c0->stream));
@@ -1642,13 +1668,18 @@ dao_status run_master_batch_dt(std::vector<PlanRun*>& live) {
     const int32_t* dstart = c0->batch_gstart;
     int nn = n;
     void* kargs[] = {&dargs, &dstart, &nn};
+    // the form every solve of the launch can take (as for one solve)
     if (fits)
-        HIPCHK(c0, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_batch<T, DT, true>), dim3(G),
-                                              dim3(COOP_THREADS), kargs, lds, c0->stream));
+        HIPCHK(c0, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_batch<T, DT, COOP_CHIP>),
+                                              dim3(G), dim3(COOP_THREADS), kargs, lds, c0->stream));
+    else if (fits_h)
+        HIPCHK(c0, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_batch<T, DT, COOP_HYBRID>),
+                                              dim3(G), dim3(COOP_THREADS), kargs, lds_h, c0->stream));
     else
-        HIPCHK(c0, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_batch<T, DT, false>), dim3(G),
-                                              dim3(COOP_THREADS), kargs, coop_stream_lds<DT>(), c0->stream));
-    for (PlanRun* r : live) r->c->last_form = fits ? 4 : 3;
+        HIPCHK(c0, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_master_batch<T, DT, COOP_STREAM>),
+                                              dim3(G), dim3(COOP_THREADS), kargs, coop_stream_lds<DT>(),
+                                              c0->stream));
+    for (PlanRun* r : live) r->c->last_form = fits ? 4 : fits_h ? 6 : 3;
     for (PlanRun* r : live)
         HIPCHK(r->c, hipMemcpyAsync(r->c->ms_h, r->c->ms, sizeof(MasterState), hipMemcpyDeviceToHost, r->c->stream));
     HIPCHK(c0, hipStreamSynchronize(c0->stream));

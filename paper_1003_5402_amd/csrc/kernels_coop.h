@@ -254,12 +254,24 @@ template <class T>
 __host__ __device__ inline size_t coop_lds_bytes(int64_t rows, int nc) {
     return size_t(rows) * coop_row_vecs(nc) * 16 + size_t(rows) * (3 * 8 + sizeof(T) + 1) + 64;
 }
+// Dynamic LDS of the hybrid form: the streaming form's q-pass partials, then
+// the workgroup's d (double), q (T) and class (uint8).
+template <class T, class DT>
+__host__ __device__ inline size_t coop_hybrid_lds(int64_t rows) {
+    return coop_stream_lds<DT>() + size_t(rows) * (8 + sizeof(T) + 1) + 64;
+}
 
-// LDSRES: the workgroup copies its rows of D_K, d, q and the classes into
-// LDS once per solve and every pass reads on-chip memory; d is written back
-// at the end.  Otherwise the passes stream them from global memory.
-template <class T, class DT, bool LDSRES>
+// The three forms of the persistent master (FORM):
+//   COOP_STREAM  every pass streams D_K, d, q and the classes from device memory;
+//   COOP_HYBRID  D_K streamed; the workgroup keeps its rows of d, q and the
+//                classes in LDS for the whole solve (d written back at the end);
+//   COOP_CHIP    D_K too: the workgroup copies its rows of D_K into LDS once per
+//                solve and keeps the breakpoints of each direction there.
+constexpr int COOP_STREAM = 0, COOP_HYBRID = 1, COOP_CHIP = 2;
+template <class T, class DT, int FORM>
 __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t gb, const uint32_t gn) {
+    constexpr bool LDSRES = FORM == COOP_CHIP;      // D_K on chip
+    constexpr bool VEC_LDS = FORM != COOP_STREAM;   // d, q and the classes on chip
     using G = DKG<DT>;
     using V = typename Vec16<DT>::type;
     constexpr int IT = Batch<DT>::ITERS, ROWS = Batch<DT>::ROWS;
@@ -301,13 +313,14 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     const int64_t per = coop_batches_per_group<DT>(A.Vpad, gn);
     const int64_t bat0 = min(nbat, int64_t(gb) * per), bat1 = min(nbat, bat0 + per);
     const int64_t r0 = bat0 * ROWS, nrows = (bat1 - bat0) * ROWS;
-    // on-chip copies (LDSRES)
+    // on-chip copies: D_K rows (COOP_CHIP) or the q-pass partials
+    // (COOP_HYBRID), then d, the breakpoints (COOP_CHIP), q and the classes
     V* dkl = reinterpret_cast<V*>(dyn);
     const int ncp = coop_row_vecs(nc);   // LDS row stride in vectors
-    double* dl = reinterpret_cast<double*>(dyn + size_t(nrows) * ncp * 16);
+    double* dl = reinterpret_cast<double*>(dyn + (LDSRES ? size_t(nrows) * ncp * 16 : coop_stream_lds<DT>()));
     double* bul = dl + nrows;   // breakpoints of the current direction
     double* bol = bul + nrows;
-    T* ql = reinterpret_cast<T*>(bol + nrows);
+    T* ql = reinterpret_cast<T*>(LDSRES ? bol + nrows : dl + nrows);
     uint8_t* cll = reinterpret_cast<uint8_t*>(ql + nrows);
     if (LDSRES) {
         // in storage order: per batch, vector c of its ROWS rows, contiguous
@@ -318,6 +331,8 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             const int64_t rr = bb * ROWS + (rem - int64_t(cc) * ROWS);
             dkl[rr * ncp + cc] = reinterpret_cast<const V*>(dk)[dk_vec_index<DT>(r0 + rr, cc)];
         }
+    }
+    if (VEC_LDS) {
         for (int64_t rr = threadIdx.x; rr < nrows; rr += blockDim.x) {
             dl[rr] = A.d[r0 + rr];
             ql[rr] = T(0);
@@ -325,9 +340,9 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
         }
         __syncthreads();
     }
-    auto d_at = [&](int64_t row) -> double& { return LDSRES ? dl[row - r0] : A.d[row]; };
-    auto q_at = [&](int64_t row) -> T& { return LDSRES ? ql[row - r0] : A.q[row]; };
-    auto cls_at = [&](int64_t row) -> uint8_t { return LDSRES ? cll[row - r0] : A.cls[row]; };
+    auto d_at = [&](int64_t row) -> double& { return VEC_LDS ? dl[row - r0] : A.d[row]; };
+    auto q_at = [&](int64_t row) -> T& { return VEC_LDS ? ql[row - r0] : A.q[row]; };
+    auto cls_at = [&](int64_t row) -> uint8_t { return VEC_LDS ? cll[row - r0] : A.cls[row]; };
     bool alive = true;
     int mode = s_ms.refresh;   // first update keeps d (2) unless told otherwise
     // work counters of workgroup 0 (update, q and line-search passes), kept in
@@ -677,7 +692,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             tick(5);
         }
     }
-    if (LDSRES) {
+    if (VEC_LDS) {
         __syncthreads();
         for (int64_t rr = threadIdx.x; rr < nrows; rr += blockDim.x) A.d[r0 + rr] = dl[rr];
     }
@@ -703,16 +718,16 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
 }
 
 // One master solve per launch: every workgroup of the grid works on it.
-template <class T, class DT, bool LDSRES>
+template <class T, class DT, int FORM>
 __global__ void __launch_bounds__(COOP_THREADS) k_master_coop(CoopArgs<T> A) {
-    master_body<T, DT, LDSRES>(A, blockIdx.x, gridDim.x);
+    master_body<T, DT, FORM>(A, blockIdx.x, gridDim.x);
 }
 
 // Several master solves in one cooperative launch: solve i gets workgroups
 // [gstart[i], gstart[i + 1]) and runs exactly as k_master_coop would on a grid
 // of that size; solves never wait for each other, and the launch ends when
 // the last one has converged.
-template <class T, class DT, bool LDSRES>
+template <class T, class DT, int FORM>
 __global__ void __launch_bounds__(COOP_THREADS) k_master_batch(const CoopArgs<T>* __restrict__ args,
                                                                const int32_t* __restrict__ gstart, int nsolves) {
     __shared__ int s_i;
@@ -726,7 +741,7 @@ __global__ void __launch_bounds__(COOP_THREADS) k_master_batch(const CoopArgs<T>
     const uint32_t g0 = uint32_t(gstart[i]), g1 = uint32_t(gstart[i + 1]);
     if (blockIdx.x >= g1) return;   // workgroups past the last solve (none when the host fills the grid)
     const CoopArgs<T> A = args[i];
-    master_body<T, DT, LDSRES>(A, blockIdx.x - g0, g1 - g0);
+    master_body<T, DT, FORM>(A, blockIdx.x - g0, g1 - g0);
 }
 
 }  // namespace dao
