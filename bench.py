@@ -290,23 +290,16 @@ def profile_master(dao, ctx, n_ap, algo_step_bytes, ls_pass_bytes):
     return kernels
 
 
-def read_at_size(torch, nbytes, scrub, iters=10):
-    """A plain streaming read of `nbytes` (torch.sum over FP32), cold: the
-    1 GiB scrub buffer is read before every timed launch.  The practical
-    ceiling for a kernel that reads that many bytes once, launch ramp and
-    drain included.  Returns GB/s (best of `iters`)."""
-    x = torch.ones(max(1, int(nbytes) // 4), dtype=torch.float32, device="cuda")
-    best = 0.0
-    for _ in range(iters):
-        scrub.sum()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        x.sum()
-        e1.record()
-        torch.cuda.synchronize()
-        best = max(best, x.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+def read_at_size(ctx, torch, nbytes, scrub, iters=10):
+    """A plain streaming read of `nbytes` (the library's 16-byte grid-stride
+    read kernel, dao_time_read_cold), cold exactly as the products are timed:
+    the practical ceiling for a kernel that reads that many bytes once,
+    launch ramp and drain included.  Returns GB/s."""
+    n = (int(nbytes) + 15) // 16 * 16
+    x = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    us = ctx.time_read_cold(x, n, iters, scrub)
     del x
-    return best
+    return n / (us * 1e-6) / 1e9
 
 
 def time_products(ctx, info, iters, scrub, torch=None):
@@ -320,7 +313,7 @@ def time_products(ctx, info, iters, scrub, torch=None):
     bd, bg = info["bytes_dose"], info["bytes_gradient"]
     extra = {}
     if torch is not None:
-        rd, rg = read_at_size(torch, bd, scrub), read_at_size(torch, bg, scrub)
+        rd, rg = read_at_size(ctx, torch, bd, scrub), read_at_size(ctx, torch, bg, scrub)
         extra = {"read_cold_GBs_at_dose_bytes": rd, "read_cold_GBs_at_gradient_bytes": rg,
                  "dose_cold_vs_read": bd / (udc * 1e-6) / 1e9 / rd,
                  "gradient_cold_vs_read": bg / (ugc * 1e-6) / 1e9 / rg}

@@ -350,6 +350,16 @@ dao_status dao_time_product(dao_ctx* ctx, int32_t kernel, int32_t iters, double*
 dao_status dao_time_product_cold(dao_ctx* ctx, int32_t kernel, int32_t iters, void* scrub,
                                  int64_t scrub_bytes, double* us_per_launch);
 
+/* The reference for those figures: a plain streaming read (16-byte loads,
+ * grid-stride, 2048 workgroups of 256 threads, the kernel that scrubs) of
+ * the first `bytes` bytes of the caller-owned device buffer `buf`, timed as
+ * dao_time_product_cold times a product (scrub read first, one event pair
+ * per launch); *us_per_launch is the mean.  buf is only read (its first 16
+ * bytes may be written as for the scrub buffer).  bytes >= 16, a multiple
+ * of 16; DAO_EINVAL otherwise or for a bad scrub size or iters < 1. */
+dao_status dao_time_read_cold(dao_ctx* ctx, void* buf, int64_t bytes, int32_t iters, void* scrub,
+                              int64_t scrub_bytes, double* us_per_launch);
+
 /* Launch-level measurement of one kernel of the aperture-matrix master
  * (Section 2.3's master, evaluated as in DAO_MASTER_APERTURE): after
  * dao_profile_start(ctx, kernel) every launch of that kernel is bracketed by

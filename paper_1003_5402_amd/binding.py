@@ -131,6 +131,7 @@ _SIGS = {
     "dao_encode_values": (c_int32, [c_int32, c_int64, POINTER(c_double), POINTER(ctypes.c_uint16),
                                     POINTER(ctypes.c_uint16)]),
     "dao_time_product_cold": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_int64, POINTER(c_double)]),
+    "dao_time_read_cold": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_int64, POINTER(c_double)]),
     "dao_profile_start": (c_int32, [c_void_p, c_int32]),
     "dao_profile_stop": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_double),
                                    POINTER(c_double)]),
@@ -464,6 +465,15 @@ class DaoContext:
         nbytes = scrub.numel() * scrub.element_size()
         self._check(self._lib.dao_time_product_cold(self._h, int(kernel), int(iters), c_void_p(_addr(scrub)),
                                                     c_int64(nbytes), byref(us)))
+        return us.value
+
+    def time_read_cold(self, buf, nbytes: int, iters: int, scrub) -> float:
+        """dao_time_read_cold: a plain streaming read of the first `nbytes`
+        bytes of device tensor `buf`, timed cold as time_product_cold."""
+        us = c_double()
+        sbytes = scrub.numel() * scrub.element_size()
+        self._check(self._lib.dao_time_read_cold(self._h, c_void_p(_addr(buf)), c_int64(nbytes), int(iters),
+                                                 c_void_p(_addr(scrub)), c_int64(sbytes), byref(us)))
         return us.value
 
     def profile_phases(self) -> Dict:

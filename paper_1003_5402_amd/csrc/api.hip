@@ -2039,6 +2039,43 @@ dao_status dao_time_product_cold(dao_ctx* c, int32_t kernel, int32_t iters, void
                                : time_product_cold_typed<float>(c, kernel, iters, scrub, scrub_bytes, us_per_launch);
 }
 
+dao_status dao_time_read_cold(dao_ctx* c, void* buf, int64_t bytes, int32_t iters, void* scrub,
+                              int64_t scrub_bytes, double* us_per_launch) {
+    if (!c) return DAO_EINVAL;
+    if (!buf || bytes < 16 || bytes % 16 != 0 || iters < 1 || !us_per_launch)
+        return c->fail(DAO_EINVAL, "buf must be a device buffer of >= 16 bytes, a multiple of 16; iters >= 1");
+    if (!scrub || scrub_bytes < (int64_t(1) << 20) || scrub_bytes % 16 != 0)
+        return c->fail(DAO_EINVAL, "scrub must be a device buffer of >= 1 MiB, a multiple of 16 bytes");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(c, hipEventCreate(&e0));
+    const hipError_t ec = hipEventCreate(&e1);
+    if (ec != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return c->fail(DAO_EDEVICE, "hipEventCreate failed");
+    }
+    double tot = 0.0;
+    hipError_t he = hipSuccess;
+    for (int i = 0; i < iters && he == hipSuccess; ++i) {
+        k_scrub<<<2048, BLOCK, 0, c->stream>>>(static_cast<uint4*>(scrub), scrub_bytes / 16, 0x9E3779B9u + uint32_t(i));
+        he = hipGetLastError();
+        if (he == hipSuccess) he = hipEventRecord(e0, c->stream);
+        if (he == hipSuccess) {
+            k_scrub<<<2048, BLOCK, 0, c->stream>>>(static_cast<uint4*>(buf), bytes / 16, 0x85EBCA6Bu + uint32_t(i));
+            he = hipGetLastError();
+        }
+        if (he == hipSuccess) he = hipEventRecord(e1, c->stream);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        tot += double(ms) * 1e3;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (he != hipSuccess) return c->fail(DAO_EDEVICE, std::string("read timing: ") + hipGetErrorString(he));
+    *us_per_launch = tot / iters;
+    return DAO_OK;
+}
+
 dao_status dao_profile_phases(dao_ctx* c, double* us) {
     if (!c || !us) return DAO_EINVAL;
     for (int i = 0; i < PROF_PHASES; ++i) us[i] = c->prof_phase_us[i];

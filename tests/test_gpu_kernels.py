@@ -228,5 +228,12 @@ def test_product_timing_calls():
             ctx.time_product(2, 3)
         with pytest.raises(dao.DaoError):
             ctx.time_product_cold(0, 2, scrub[: 1 << 19])
+        # the streaming-read reference: positive, buffers untouched, sizes checked
+        buf = torch.zeros(1 << 20, dtype=torch.uint8, device="cuda:0")
+        assert ctx.time_read_cold(buf, 1 << 20, 2, scrub) > 0
+        assert int(buf.count_nonzero()) == 0 and int(scrub.count_nonzero()) == 0
+        for nbytes in (8, 1000):
+            with pytest.raises(dao.DaoError):
+                ctx.time_read_cold(buf, nbytes, 2, scrub)
     finally:
         ctx.close()
