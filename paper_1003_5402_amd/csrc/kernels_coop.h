@@ -227,7 +227,9 @@ struct CoopArgs {
     int timing;         // workgroup 0 accumulates per-phase wall-clock ticks in pc->ticks
 };
 
-// Rows of workgroup b: batches [bat0, bat1) of ROWS rows (contiguous).
+// Rows of a workgroup: a contiguous range of batches of ROWS rows, `per` of
+// them (the last workgroups may own fewer); local batch lb of workgroup b is
+// batch b * per + lb.
 template <class T>
 __host__ __device__ inline int64_t coop_batches_per_group(int64_t Vpad, int grid) {
     const int64_t nbat = Vpad / Batch<T>::ROWS;
@@ -308,11 +310,12 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int rg = lane / G::LPR, c = lane % G::LPR;
     const int nc = (K + G::EPL - 1) / G::EPL;
-    // this workgroup's batches of ROWS rows
+    // this workgroup's batches of ROWS rows: local batch lb (local rows
+    // lb * ROWS ...) is batch bat0 + lb
     const int64_t nbat = A.Vpad / ROWS;
     const int64_t per = coop_batches_per_group<DT>(A.Vpad, gn);
-    const int64_t bat0 = min(nbat, int64_t(gb) * per), bat1 = min(nbat, bat0 + per);
-    const int64_t r0 = bat0 * ROWS, nrows = (bat1 - bat0) * ROWS;
+    const int64_t bat0 = min(nbat, int64_t(gb) * per), nlb = min(nbat, bat0 + per) - bat0, nrows = nlb * ROWS;
+    auto batch_base = [&](int64_t lb) -> int64_t { return (bat0 + lb) * ROWS; };
     // on-chip copies: D_K rows (COOP_CHIP) or the q-pass partials
     // (COOP_HYBRID), then d, the breakpoints (COOP_CHIP), q and the classes
     V* dkl = reinterpret_cast<V*>(dyn);
@@ -325,24 +328,27 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     if (LDSRES) {
         // in storage order: per batch, vector c of its ROWS rows, contiguous
         for (int64_t idx = threadIdx.x; idx < nrows * nc; idx += blockDim.x) {
-            const int64_t bb = idx / (int64_t(nc) * ROWS);
-            const int64_t rem = idx - bb * (int64_t(nc) * ROWS);
+            const int64_t lb = idx / (int64_t(nc) * ROWS);
+            const int64_t rem = idx - lb * (int64_t(nc) * ROWS);
             const int cc = int(rem / ROWS);
-            const int64_t rr = bb * ROWS + (rem - int64_t(cc) * ROWS);
-            dkl[rr * ncp + cc] = reinterpret_cast<const V*>(dk)[dk_vec_index<DT>(r0 + rr, cc)];
+            const int64_t lr = rem - int64_t(cc) * ROWS;
+            dkl[(lb * ROWS + lr) * ncp + cc] =
+                reinterpret_cast<const V*>(dk)[dk_vec_index<DT>(batch_base(lb) + lr, cc)];
         }
     }
     if (VEC_LDS) {
         for (int64_t rr = threadIdx.x; rr < nrows; rr += blockDim.x) {
-            dl[rr] = A.d[r0 + rr];
+            const int64_t row = batch_base(rr / ROWS) + rr % ROWS;
+            dl[rr] = A.d[row];
             ql[rr] = T(0);
-            cll[rr] = A.cls[r0 + rr];
+            cll[rr] = A.cls[row];
         }
         __syncthreads();
     }
-    auto d_at = [&](int64_t row) -> double& { return VEC_LDS ? dl[row - r0] : A.d[row]; };
-    auto q_at = [&](int64_t row) -> T& { return VEC_LDS ? ql[row - r0] : A.q[row]; };
-    auto cls_at = [&](int64_t row) -> uint8_t { return VEC_LDS ? cll[row - r0] : A.cls[row]; };
+    // per-voxel vectors by (global row, local row)
+    auto d_at = [&](int64_t row, int64_t lrow) -> double& { return VEC_LDS ? dl[lrow] : A.d[row]; };
+    auto q_at = [&](int64_t row, int64_t lrow) -> T& { return VEC_LDS ? ql[lrow] : A.q[row]; };
+    auto cls_at = [&](int64_t row, int64_t lrow) -> uint8_t { return VEC_LDS ? cll[lrow] : A.cls[row]; };
     bool alive = true;
     int mode = s_ms.refresh;   // first update keeps d (2) unless told otherwise
     // work counters of workgroup 0 (update, q and line-search passes), kept in
@@ -389,24 +395,12 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             }
             double Fp = 0.0;
             double* su = s_u[wave];
-            for (int64_t bt = bat0 + wave; bt < bat1; bt += NW) {
-                const int64_t base = bt * ROWS;
-                // this lane's row of the per-voxel stage: its d, q and class
-                // are loaded together with the batch's D_K rows, so the two
-                // memory round trips overlap
-                double d_pre = 0.0, q_pre = 0.0;
-                uint8_t c_pre = 0;
-                if (lane < ROWS) {
-                    const int64_t row = base + lane;
-                    if (mode != 1) d_pre = d_at(row);
-                    if (mode == 0) q_pre = double(q_at(row));
-                    c_pre = cls_at(row);
-                }
-                V v[IT];
+            // the batch's D_K rows, from LDS (COOP_CHIP) or device memory
+            auto load_rows = [&](int64_t base, int64_t lbase, V (&v)[IT]) {
                 if (LDSRES) {
                     // running LDS offset, opaque to the compiler so it adds one
                     // stride per load instead of keeping IT addresses live
-                    uint32_t off = uint32_t(((base - r0 + rg) * ncp + c) * 16);
+                    uint32_t off = uint32_t(((lbase + rg) * ncp + c) * 16);
                     const uint32_t stride = uint32_t(G::RPW * ncp * 16);
                     // one predicated region for all the loads (see load_batch)
                     if (c < nc) {
@@ -423,6 +417,54 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                 } else {
                     load_batch<DT>(dk, base, rg, c, nc, v);
                 }
+            };
+            for (int64_t lb = wave; lb < nlb; lb += NW) {
+                const int64_t base = batch_base(lb), lbase = lb * ROWS;
+                if (VEC_LDS && mode != 1) {
+                    // the per-voxel stage first (d, q and the class are in
+                    // LDS).  A row inside its dose window has dF/dz = 0 and
+                    // adds exact zeros to grad_y (the partial sums start at +0
+                    // and never become -0), so a batch with no other row
+                    // leaves them bit for bit as they are and its D_K rows
+                    // are not read.
+                    double u = 0.0;
+                    if (lane < ROWS) {
+                        const int64_t lrow = lbase + lane;
+                        double dn = dl[lrow];
+                        if (mode == 0) dn = dn + t * double(ql[lrow]);
+                        const ObjClass cc = cl[cll[lrow]];
+                        if (mode != 2) dl[lrow] = dn;
+                        Fp += obj_f(cc, dn);
+                        u = grad_f(cc, dn);
+                        su[lane] = u;
+                    }
+                    if (__any(u != 0.0)) {
+                        V v[IT];
+                        load_rows(base, lbase, v);
+                        wave_sync();
+#pragma unroll
+                        for (int it = 0; it < IT; ++it) {
+                            const double uu = su[it * G::RPW + rg];
+#pragma unroll
+                            for (int e = 0; e < G::EPL; ++e) acc[e] += uu * vget(v[it], e);
+                        }
+                    }
+                    wave_sync();
+                    continue;
+                }
+                // this lane's row of the per-voxel stage: its d, q and class
+                // are loaded together with the batch's D_K rows, so the two
+                // memory round trips overlap
+                double d_pre = 0.0, q_pre = 0.0;
+                uint8_t c_pre = 0;
+                if (lane < ROWS) {
+                    const int64_t row = base + lane, lrow = lbase + lane;
+                    if (mode != 1) d_pre = d_at(row, lrow);
+                    if (mode == 0) q_pre = double(q_at(row, lrow));
+                    c_pre = cls_at(row, lrow);
+                }
+                V v[IT];
+                load_rows(base, lbase, v);
                 if (mode == 1) {
 #pragma unroll
                     for (int it = 0; it < IT; ++it) {
@@ -444,7 +486,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                         if (mode == 0) dn = dn + t * q_pre;
                     }
                     const ObjClass cc = cl[c_pre];
-                    if (mode != 2) d_at(row) = dn;
+                    if (mode != 2) d_at(row, lbase + lane) = dn;
                     Fp += obj_f(cc, dn);
                     su[lane] = grad_f(cc, dn);
                 }
@@ -590,16 +632,16 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                     ls_voxel_bp(cc, dv, double(qt), bul[rr], bol[rr], t, r);
                 }
             } else {
-                for (int64_t bt = bat0 + wave; bt < bat1; bt += NW) {
-                    const int64_t base = bt * ROWS;
+                for (int64_t lb = wave; lb < nlb; lb += NW) {
+                    const int64_t base = batch_base(lb), lbase = lb * ROWS;
                     // this lane's row: d and class loaded with the D_K rows
                     double d_pre = 0.0;
                     uint8_t c_pre = 0;
                     T q_pre = T(0);
                     if (lane < ROWS) {
-                        d_pre = d_at(base + lane);
-                        c_pre = cls_at(base + lane);
-                        if (!first) q_pre = q_at(base + lane);
+                        d_pre = d_at(base + lane, lbase + lane);
+                        c_pre = cls_at(base + lane, lbase + lane);
+                        if (!first) q_pre = q_at(base + lane, lbase + lane);
                     }
                     double qsum = 0.0;
                     if (first) {
@@ -625,7 +667,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                         T qt;
                         if (first) {
                             qt = T(qsum);   // the line search and the update use the stored value
-                            q_at(row) = qt;
+                            q_at(row, lbase + lane) = qt;
                         } else {
                             qt = q_pre;
                         }
@@ -694,7 +736,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     }
     if (VEC_LDS) {
         __syncthreads();
-        for (int64_t rr = threadIdx.x; rr < nrows; rr += blockDim.x) A.d[r0 + rr] = dl[rr];
+        for (int64_t rr = threadIdx.x; rr < nrows; rr += blockDim.x) A.d[batch_base(rr / ROWS) + rr % ROWS] = dl[rr];
     }
     if (timer)
         for (int i = 0; i < PROF_PHASES; ++i) A.pc->ticks[i] += s_tk[i];
