@@ -88,6 +88,7 @@ struct dao_ctx {
     ProfCounters* pc = nullptr;
     CoopSync* coop = nullptr;          // grid-reduction scratch of the persistent master
     double* coop_recs = nullptr;       // [2][coop_grid][RECW]
+    double* coop_bpart = nullptr;      // streaming form's per-batch grad_y partials (Vpad / 32 * KS)
     int coop_grid = 0;                 // co-resident workgroups (0: persistent master unavailable)
     int ncu = 0;                       // compute units of the device
     int coop_lds_max = 0;              // dynamic LDS the on-chip variant may use (0: never)
@@ -250,6 +251,7 @@ int64_t predicted_bytes(const HostLayout& L, size_t ts, int kmax, const dao_opti
     // buffer; the automatic choice is counted at the native size (a bound)
     const int64_t dkb = (opt.dk_format == DAO_DFMT_F16 && ts == 4 && opt.d_residual != 2) ? 2 : int64_t(ts);
     b += int64_t(L.Vpad) * KS * dkb + L.N * ts + 512 * (KS + 1) * 8;
+    b += int64_t(L.Vpad) / 32 * KS * 8;   // the persistent master's per-batch partials
     b += sizeof(MasterState) + sizeof(PriceResult) + L.R * sizeof(RowRec) + 2 * ELEM_BLOCKS_MAX * sizeof(Rec) +
          sizeof(Arrival);
     return b;
@@ -599,8 +601,8 @@ dao_status run_master_coop_dt(dao_ctx* c, double tol, int max_steps) {
     LAUNCHCHK(c);
     HIPCHK(c, hipMemsetAsync(c->coop, 0, sizeof(CoopSync), c->stream));
     CoopArgs<T> A{c->dk, c->dk_scale, c->Vpad, c->Vnz, c->d, static_cast<T*>(c->q), c->cls_int,
-                  c->classes, c->ncls, c->y, c->p, c->gradk, c->cgm, c->tau_int, c->ms, c->coop_recs, c->coop,
-                  c->pc, c->prof_kernel == 4 ? 1 : 0};
+                  c->classes, c->ncls, c->y, c->p, c->gradk, c->cgm, c->tau_int, c->ms, c->coop_recs,
+                  c->coop_bpart, c->coop, c->pc, c->prof_kernel == 4 ? 1 : 0};
     void* args[] = {&A};
     const bool prof = c->prof_kernel == 4;
     if (prof) {
@@ -1103,6 +1105,8 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
             (void)hipGetLastError();
             TRY(dev_alloc(c, &c->coop, sizeof(CoopSync)));
             TRY(dev_alloc(c, &c->coop_recs, 2 * size_t(c->coop_grid) * RECW * sizeof(double)));
+            // batches of at least 32 rows
+            TRY(dev_alloc(c, &c->coop_bpart, size_t(c->Vpad / 32) * KS * sizeof(double)));
         }
     }
     // FP16 storage of D_K: values over the largest entry of D (every D_K
@@ -1650,7 +1654,7 @@ dao_status run_master_batch_dt(std::vector<PlanRun*>& live) {
         HIPCHK(c, hipMemsetAsync(c->coop, 0, sizeof(CoopSync), c->stream));
         hargs[i] = CoopArgs<T>{c->dk, c->dk_scale, c->Vpad, c->Vnz, c->d, static_cast<T*>(c->q), c->cls_int,
                                c->classes, c->ncls, c->y, c->p, c->gradk, c->cgm, c->tau_int, c->ms,
-                               c->coop_recs, c->coop, c->pc, 0};
+                               c->coop_recs, c->coop_bpart, c->coop, c->pc, 0};
         hstart[i + 1] = hstart[i] + g[i];
         const int nc = (c->K + DKG<DT>::EPL - 1) / DKG<DT>::EPL;
         const int64_t rows_i = coop_batches_per_group<DT>(c->Vpad, g[i]) * Batch<DT>::ROWS;

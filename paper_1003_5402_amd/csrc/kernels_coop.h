@@ -222,18 +222,45 @@ struct CoopArgs {
     const double* tau;  // per-voxel threshold shifts by internal row (null: none)
     MasterState* ms;    // in: state set by k_master_init_ap; out: final state (workgroup 0)
     double* recs;       // [2][workgroups of the solve][RECW]
+    double* bpart;      // streaming form: grad_y partial of every batch (KS doubles each)
     CoopSync* sync;
     ProfCounters* pc;
     int timing;         // workgroup 0 accumulates per-phase wall-clock ticks in pc->ticks
 };
 
-// Rows of a workgroup: a contiguous range of batches of ROWS rows, `per` of
-// them (the last workgroups may own fewer); local batch lb of workgroup b is
-// batch b * per + lb.
+// Rows of a workgroup (forms that stream D_K): the batches of ROWS rows are
+// dealt in rounds of one batch per workgroup; in round lb, workgroup b of a
+// solve on gn workgroups owns batch lb * gn + (b + COOP_SKEW * lb) % gn.  The rows whose D_K rows
+// the update pass reads (voxels outside their dose window) cluster in space
+// and, after the length sort, at the start of each sort window; dealing the
+// batches spreads them over the workgroups, and the skew keeps a pattern
+// that repeats with the round length from landing on the same workgroups
+// every round.
+constexpr int64_t COOP_SKEW = 101;
+__host__ __device__ inline int64_t coop_batch(int64_t lb, uint32_t b, uint32_t gn) {
+    return lb * gn + (int64_t(b) + COOP_SKEW * lb) % gn;
+}
+// Batches of workgroup b: one per full round, and the last partial round's
+// when its slot falls inside it.
+__host__ __device__ inline int64_t coop_nbatches(int64_t nbat, uint32_t b, uint32_t gn) {
+    const int64_t full = nbat / gn, rem = nbat % gn;
+    return full + ((rem > 0 && (int64_t(b) + COOP_SKEW * full) % gn < rem) ? 1 : 0);
+}
+// The most batches a workgroup owns (LDS sizing).  With D_K on chip a
+// workgroup owns a contiguous range of that many batches (the last ones
+// fewer): the update pass's skipped batches cost little there, D_K being read
+// from LDS, so its rows need no dealing.
 template <class T>
 __host__ __device__ inline int64_t coop_batches_per_group(int64_t Vpad, int grid) {
     const int64_t nbat = Vpad / Batch<T>::ROWS;
     return (nbat + grid - 1) / grid;
+}
+// The update pass's LDS (rows on chip): dF/dz of every row (double), then
+// each batch's grad_y partial (KS doubles) and its flag (a byte).
+template <class DT>
+__host__ __device__ inline size_t coop_upd_lds(int64_t rows) {
+    const int64_t nb = rows / Batch<DT>::ROWS;
+    return size_t(rows) * 8 + size_t(nb) * KS * 8 + ((size_t(nb) + 15) / 16) * 16;
 }
 
 // Dynamic LDS of the streaming form: per wavefront, the per-slot partials of
@@ -256,11 +283,17 @@ template <class T>
 __host__ __device__ inline size_t coop_lds_bytes(int64_t rows, int nc) {
     return size_t(rows) * coop_row_vecs(nc) * 16 + size_t(rows) * (3 * 8 + sizeof(T) + 1) + 64;
 }
-// Dynamic LDS of the hybrid form: the streaming form's q-pass partials, then
-// the workgroup's d (double), q (T) and class (uint8).
+// Dynamic LDS of the hybrid form: the larger of the q pass's row partials
+// and the update pass's area (coop_upd_lds), then the workgroup's d
+// (double), q (T) and class (uint8).
+template <class DT>
+__host__ __device__ inline size_t coop_hybrid_front(int64_t rows) {
+    const size_t a = coop_stream_lds<DT>(), b = coop_upd_lds<DT>(rows);
+    return a > b ? a : b;
+}
 template <class T, class DT>
 __host__ __device__ inline size_t coop_hybrid_lds(int64_t rows) {
-    return coop_stream_lds<DT>() + size_t(rows) * (8 + sizeof(T) + 1) + 64;
+    return coop_hybrid_front<DT>(rows) + size_t(rows) * (8 + sizeof(T) + 1) + 64;
 }
 
 // The three forms of the persistent master (FORM):
@@ -311,20 +344,31 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     const int rg = lane / G::LPR, c = lane % G::LPR;
     const int nc = (K + G::EPL - 1) / G::EPL;
     // this workgroup's batches of ROWS rows: local batch lb (local rows
-    // lb * ROWS ...) is batch bat0 + lb
+    // lb * ROWS ...) is batch bat0 + lb (D_K on chip) or coop_batch(lb, gb, gn)
     const int64_t nbat = A.Vpad / ROWS;
     const int64_t per = coop_batches_per_group<DT>(A.Vpad, gn);
-    const int64_t bat0 = min(nbat, int64_t(gb) * per), nlb = min(nbat, bat0 + per) - bat0, nrows = nlb * ROWS;
-    auto batch_base = [&](int64_t lb) -> int64_t { return (bat0 + lb) * ROWS; };
+    const int64_t bat0 = LDSRES ? min(nbat, int64_t(gb) * per) : 0;
+    const int64_t nlb = LDSRES ? min(nbat, bat0 + per) - bat0 : coop_nbatches(nbat, gb, gn);
+    const int64_t nrows = nlb * ROWS, rows_max = per * ROWS;   // rows_max: the LDS layout's row count
+    auto batch_base = [&](int64_t lb) -> int64_t {
+        return LDSRES ? (bat0 + lb) * ROWS : coop_batch(lb, gb, gn) * ROWS;
+    };
     // on-chip copies: D_K rows (COOP_CHIP) or the q-pass partials
     // (COOP_HYBRID), then d, the breakpoints (COOP_CHIP), q and the classes
     V* dkl = reinterpret_cast<V*>(dyn);
     const int ncp = coop_row_vecs(nc);   // LDS row stride in vectors
-    double* dl = reinterpret_cast<double*>(dyn + (LDSRES ? size_t(nrows) * ncp * 16 : coop_stream_lds<DT>()));
-    double* bul = dl + nrows;   // breakpoints of the current direction
-    double* bol = bul + nrows;
-    T* ql = reinterpret_cast<T*>(LDSRES ? bol + nrows : dl + nrows);
-    uint8_t* cll = reinterpret_cast<uint8_t*>(ql + nrows);
+    double* dl = reinterpret_cast<double*>(dyn + (LDSRES ? size_t(rows_max) * ncp * 16
+                                                         : coop_hybrid_front<DT>(rows_max)));
+    double* bul = dl + rows_max;   // breakpoints of the current direction
+    double* bol = bul + rows_max;
+    T* ql = reinterpret_cast<T*>(LDSRES ? bol + rows_max : dl + rows_max);
+    uint8_t* cll = reinterpret_cast<uint8_t*>(ql + rows_max);
+    // update pass of the hybrid form (at the front, where the q pass keeps
+    // its row partials): dF/dz per row, then per batch its grad_y partial
+    // and a flag (the batch has a row with dF/dz != 0)
+    double* ul = reinterpret_cast<double*>(dyn);
+    double* bpl = ul + rows_max;
+    uint8_t* flg = reinterpret_cast<uint8_t*>(bpl + (rows_max / ROWS) * KS);
     if (LDSRES) {
         // in storage order: per batch, vector c of its ROWS rows, contiguous
         for (int64_t idx = threadIdx.x; idx < nrows * nc; idx += blockDim.x) {
@@ -385,131 +429,311 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     while (alive) {
         // ---------------- update pass: apply the step, dF/dz, F, grad_y partials
         {
-            const double t = ls.t;
-            double yv[G::EPL], acc[G::EPL];
+            if constexpr (LDSRES) {
+                // D_K on chip: each wavefront sums grad_y over its batches
+                // (lb = wave, wave + NW, ...) in registers
+                const double t = ls.t;
+                double yv[G::EPL], acc[G::EPL];
 #pragma unroll
-            for (int e = 0; e < G::EPL; ++e) {
-                const int k = c * G::EPL + e;
-                yv[e] = (mode == 1 && k < K) ? s_y[k] * dks : 0.0;
-                acc[e] = 0.0;
-            }
-            double Fp = 0.0;
-            double* su = s_u[wave];
-            // the batch's D_K rows, from LDS (COOP_CHIP) or device memory
-            auto load_rows = [&](int64_t base, int64_t lbase, V (&v)[IT]) {
-                if (LDSRES) {
-                    // running LDS offset, opaque to the compiler so it adds one
-                    // stride per load instead of keeping IT addresses live
-                    uint32_t off = uint32_t(((lbase + rg) * ncp + c) * 16);
-                    const uint32_t stride = uint32_t(G::RPW * ncp * 16);
-                    // one predicated region for all the loads (see load_batch)
-                    if (c < nc) {
+                for (int e = 0; e < G::EPL; ++e) {
+                    const int k = c * G::EPL + e;
+                    yv[e] = (mode == 1 && k < K) ? s_y[k] * dks : 0.0;
+                    acc[e] = 0.0;
+                }
+                double Fp = 0.0;
+                double* su = s_u[wave];
+                // the batch's D_K rows, from LDS (COOP_CHIP) or device memory
+                auto load_rows = [&](int64_t base, int64_t lbase, V (&v)[IT]) {
+                    if (LDSRES) {
+                        // running LDS offset, opaque to the compiler so it adds one
+                        // stride per load instead of keeping IT addresses live
+                        uint32_t off = uint32_t(((lbase + rg) * ncp + c) * 16);
+                        const uint32_t stride = uint32_t(G::RPW * ncp * 16);
+                        // one predicated region for all the loads (see load_batch)
+                        if (c < nc) {
 #pragma unroll
-                        for (int it = 0; it < IT; ++it) {
-                            asm volatile("" : "+v"(off));
-                            v[it] = *reinterpret_cast<const V*>(dyn + off);
-                            off += stride;
+                            for (int it = 0; it < IT; ++it) {
+                                asm volatile("" : "+v"(off));
+                                v[it] = *reinterpret_cast<const V*>(dyn + off);
+                                off += stride;
+                            }
+                        } else {
+#pragma unroll
+                            for (int it = 0; it < IT; ++it) v[it] = vzero<V>();
                         }
                     } else {
-#pragma unroll
-                        for (int it = 0; it < IT; ++it) v[it] = vzero<V>();
+                        load_batch<DT>(dk, base, rg, c, nc, v);
                     }
-                } else {
-                    load_batch<DT>(dk, base, rg, c, nc, v);
-                }
-            };
-            for (int64_t lb = wave; lb < nlb; lb += NW) {
-                const int64_t base = batch_base(lb), lbase = lb * ROWS;
-                if (VEC_LDS && mode != 1) {
-                    // the per-voxel stage first (d, q and the class are in
-                    // LDS).  A row inside its dose window has dF/dz = 0 and
-                    // adds exact zeros to grad_y (the partial sums start at +0
-                    // and never become -0), so a batch with no other row
-                    // leaves them bit for bit as they are and its D_K rows
-                    // are not read.
-                    double u = 0.0;
+                };
+                for (int64_t lb = wave; lb < nlb; lb += NW) {
+                    const int64_t base = batch_base(lb), lbase = lb * ROWS;
+                    if (VEC_LDS && mode != 1) {
+                        // the per-voxel stage first (d, q and the class are in
+                        // LDS).  A row inside its dose window has dF/dz = 0 and
+                        // adds exact zeros to grad_y (the partial sums start at +0
+                        // and never become -0), so a batch with no other row
+                        // leaves them bit for bit as they are and its D_K rows
+                        // are not read.
+                        double u = 0.0;
+                        if (lane < ROWS) {
+                            const int64_t lrow = lbase + lane;
+                            double dn = dl[lrow];
+                            if (mode == 0) dn = dn + t * double(ql[lrow]);
+                            const ObjClass cc = cl[cll[lrow]];
+                            if (mode != 2) dl[lrow] = dn;
+                            Fp += obj_f(cc, dn);
+                            u = grad_f(cc, dn);
+                            su[lane] = u;
+                        }
+                        if (__any(u != 0.0)) {
+                            V v[IT];
+                            load_rows(base, lbase, v);
+                            wave_sync();
+#pragma unroll
+                            for (int it = 0; it < IT; ++it) {
+                                const double uu = su[it * G::RPW + rg];
+#pragma unroll
+                                for (int e = 0; e < G::EPL; ++e) acc[e] += uu * vget(v[it], e);
+                            }
+                        }
+                        wave_sync();
+                        continue;
+                    }
+                    // this lane's row of the per-voxel stage: its d, q and class
+                    // are loaded together with the batch's D_K rows, so the two
+                    // memory round trips overlap
+                    double d_pre = 0.0, q_pre = 0.0;
+                    uint8_t c_pre = 0;
                     if (lane < ROWS) {
-                        const int64_t lrow = lbase + lane;
+                        const int64_t row = base + lane, lrow = lbase + lane;
+                        if (mode != 1) d_pre = d_at(row, lrow);
+                        if (mode == 0) q_pre = double(q_at(row, lrow));
+                        c_pre = cls_at(row, lrow);
+                    }
+                    V v[IT];
+                    load_rows(base, lbase, v);
+                    if (mode == 1) {
+#pragma unroll
+                        for (int it = 0; it < IT; ++it) {
+                            double part = 0.0;
+#pragma unroll
+                            for (int e = 0; e < G::EPL; ++e) part += vget(v[it], e) * yv[e];
+                            part = group_sum<G::LPR>(part);
+                            if (c == 0) su[it * G::RPW + rg] = part;
+                        }
+                    }
+                    wave_sync();
+                    if (lane < ROWS) {
+                        const int64_t row = base + lane;
+                        double dn;
+                        if (mode == 1) {
+                            dn = su[lane] - tau_at(A.tau, row);   // the master keeps d - tau
+                        } else {
+                            dn = d_pre;
+                            if (mode == 0) dn = dn + t * q_pre;
+                        }
+                        const ObjClass cc = cl[c_pre];
+                        if (mode != 2) d_at(row, lbase + lane) = dn;
+                        Fp += obj_f(cc, dn);
+                        su[lane] = grad_f(cc, dn);
+                    }
+                    wave_sync();
+#pragma unroll
+                    for (int it = 0; it < IT; ++it) {
+                        const double u = su[it * G::RPW + rg];
+#pragma unroll
+                        for (int e = 0; e < G::EPL; ++e) acc[e] += u * vget(v[it], e);
+                    }
+                    wave_sync();
+                }
+#pragma unroll
+                for (int off = G::LPR; off < WAVE; off <<= 1)
+#pragma unroll
+                    for (int e = 0; e < G::EPL; ++e) acc[e] += __shfl_xor(acc[e], off, WAVE);
+                if (rg == 0)
+#pragma unroll
+                    for (int e = 0; e < G::EPL; ++e) s_acc[wave][1 + c * G::EPL + e] = acc[e] * dks;
+                Fp = wave_reduce_dpp<0>(Fp);
+                if (lane == 0) s_acc[wave][0] = Fp;
+                __syncthreads();
+                combine_waves8(&s_acc[0][0], RECW, K + 1, false, s_rec);
+            } else {
+                //
+                // grad_y is summed per batch (each lane over the batch's rows in
+                // order, then across the lane groups), then over the workgroup's
+                // batches in a fixed order, so the sum does not depend on which
+                // wavefront handles a batch.  With the rows on chip (and outside
+                // refresh steps) every row's new dose and dF/dz come first; a row
+                // inside its dose window has dF/dz = +0 exactly and adds exact zeros,
+                // so only batches with another row read their D_K rows (the sums
+                // start at +0 and never become -0, so skipping a batch leaves the
+                // bits as they are), and those batches are dealt to the wavefronts
+                // round-robin.
+                const double t = ls.t;
+                double yv[G::EPL];
+#pragma unroll
+                for (int e = 0; e < G::EPL; ++e) {
+                    const int k = c * G::EPL + e;
+                    yv[e] = (mode == 1 && k < K) ? s_y[k] * dks : 0.0;
+                }
+                double Fp = 0.0;
+                double* su = s_u[wave];
+                // the batch's D_K rows, from LDS (COOP_CHIP) or device memory
+                auto load_rows = [&](int64_t base, int64_t lbase, V (&v)[IT]) {
+                    if (LDSRES) {
+                        // running LDS offset, opaque to the compiler so it adds one
+                        // stride per load instead of keeping IT addresses live
+                        uint32_t off = uint32_t(((lbase + rg) * ncp + c) * 16);
+                        const uint32_t stride = uint32_t(G::RPW * ncp * 16);
+                        // one predicated region for all the loads (see load_batch)
+                        if (c < nc) {
+#pragma unroll
+                            for (int it = 0; it < IT; ++it) {
+                                asm volatile("" : "+v"(off));
+                                v[it] = *reinterpret_cast<const V*>(dyn + off);
+                                off += stride;
+                            }
+                        } else {
+#pragma unroll
+                            for (int it = 0; it < IT; ++it) v[it] = vzero<V>();
+                        }
+                    } else {
+                        load_batch<DT>(dk, base, rg, c, nc, v);
+                    }
+                };
+                // grad_y partial of one batch from its D_K rows and the rows'
+                // dF/dz (u(r): row r of the batch), stored for the combine
+                auto batch_partial = [&](int64_t lb, const V (&v)[IT], auto&& u) {
+                    double a[G::EPL];
+#pragma unroll
+                    for (int e = 0; e < G::EPL; ++e) a[e] = 0.0;
+#pragma unroll
+                    for (int it = 0; it < IT; ++it) {
+                        const double uu = u(it * G::RPW + rg);
+#pragma unroll
+                        for (int e = 0; e < G::EPL; ++e) a[e] += uu * vget(v[it], e);
+                    }
+#pragma unroll
+                    for (int off = G::LPR; off < WAVE; off <<= 1)
+#pragma unroll
+                        for (int e = 0; e < G::EPL; ++e) a[e] += __shfl_xor(a[e], off, WAVE);
+                    if (rg == 0) {
+                        if (VEC_LDS) {
+#pragma unroll
+                            for (int e = 0; e < G::EPL; ++e) bpl[lb * KS + c * G::EPL + e] = a[e];
+                        } else {
+                            double* bp = A.bpart + (batch_base(lb) / ROWS) * KS + c * G::EPL;
+#pragma unroll
+                            for (int e = 0; e < G::EPL; ++e) astore(bp + e, a[e]);
+                        }
+                    }
+                };
+                if (VEC_LDS && mode != 1) {
+                    // rows on chip: new dose, F and dF/dz of every row, one row per thread
+                    for (int64_t i = threadIdx.x; i < nlb; i += blockDim.x) flg[i] = 0;
+                    __syncthreads();
+                    for (int64_t lrow = threadIdx.x; lrow < nrows; lrow += blockDim.x) {
                         double dn = dl[lrow];
                         if (mode == 0) dn = dn + t * double(ql[lrow]);
                         const ObjClass cc = cl[cll[lrow]];
                         if (mode != 2) dl[lrow] = dn;
                         Fp += obj_f(cc, dn);
-                        u = grad_f(cc, dn);
-                        su[lane] = u;
+                        const double u = grad_f(cc, dn);
+                        ul[lrow] = u;
+                        if (u != 0.0) flg[lrow / ROWS] = 1;
                     }
-                    if (__any(u != 0.0)) {
-                        V v[IT];
-                        load_rows(base, lbase, v);
-                        wave_sync();
-#pragma unroll
-                        for (int it = 0; it < IT; ++it) {
-                            const double uu = su[it * G::RPW + rg];
-#pragma unroll
-                            for (int e = 0; e < G::EPL; ++e) acc[e] += uu * vget(v[it], e);
+                    __syncthreads();
+                    // the flagged batches, dealt to the wavefronts in batch order
+                    int done = 0;
+                    for (int64_t c0 = 0; c0 < nlb; c0 += WAVE) {
+                        const bool on = c0 + lane < nlb && flg[c0 + lane] != 0;
+                        const uint64_t m = __ballot(on);
+                        const int rank = done + __popcll(m & ((uint64_t(1) << lane) - 1));
+                        uint64_t mine = __ballot(on && rank % NW == wave);
+                        done += __popcll(m);
+                        while (mine) {
+                            const int64_t lb = c0 + __builtin_ctzll(mine);
+                            mine &= mine - 1;
+                            V v[IT];
+                            load_rows(batch_base(lb), lb * ROWS, v);
+                            const double* ub = ul + lb * ROWS;
+                            batch_partial(lb, v, [&](int r) { return ub[r]; });
                         }
                     }
-                    wave_sync();
-                    continue;
-                }
-                // this lane's row of the per-voxel stage: its d, q and class
-                // are loaded together with the batch's D_K rows, so the two
-                // memory round trips overlap
-                double d_pre = 0.0, q_pre = 0.0;
-                uint8_t c_pre = 0;
-                if (lane < ROWS) {
-                    const int64_t row = base + lane, lrow = lbase + lane;
-                    if (mode != 1) d_pre = d_at(row, lrow);
-                    if (mode == 0) q_pre = double(q_at(row, lrow));
-                    c_pre = cls_at(row, lrow);
-                }
-                V v[IT];
-                load_rows(base, lbase, v);
-                if (mode == 1) {
+                } else {
+                    // refresh steps (d = D_K y needs every D_K row) and the
+                    // streaming form: each batch in one go, d and the class
+                    // loaded together with the D_K rows so that the two memory
+                    // round trips overlap
+                    for (int64_t lb = wave; lb < nlb; lb += NW) {
+                        const int64_t base = batch_base(lb), lbase = lb * ROWS;
+                        double d_pre = 0.0, q_pre = 0.0;
+                        uint8_t c_pre = 0;
+                        if (lane < ROWS) {
+                            const int64_t row = base + lane, lrow = lbase + lane;
+                            if (mode != 1) d_pre = d_at(row, lrow);
+                            if (mode == 0) q_pre = double(q_at(row, lrow));
+                            c_pre = cls_at(row, lrow);
+                        }
+                        V v[IT];
+                        load_rows(base, lbase, v);
+                        if (mode == 1) {
 #pragma unroll
-                    for (int it = 0; it < IT; ++it) {
-                        double part = 0.0;
+                            for (int it = 0; it < IT; ++it) {
+                                double part = 0.0;
 #pragma unroll
-                        for (int e = 0; e < G::EPL; ++e) part += vget(v[it], e) * yv[e];
-                        part = group_sum<G::LPR>(part);
-                        if (c == 0) su[it * G::RPW + rg] = part;
+                                for (int e = 0; e < G::EPL; ++e) part += vget(v[it], e) * yv[e];
+                                part = group_sum<G::LPR>(part);
+                                if (c == 0) su[it * G::RPW + rg] = part;
+                            }
+                        }
+                        wave_sync();
+                        if (lane < ROWS) {
+                            const int64_t row = base + lane;
+                            double dn;
+                            if (mode == 1) {
+                                dn = su[lane] - tau_at(A.tau, row);   // the master keeps d - tau
+                            } else {
+                                dn = d_pre;
+                                if (mode == 0) dn = dn + t * q_pre;
+                            }
+                            const ObjClass cc = cl[c_pre];
+                            if (mode != 2) d_at(row, lbase + lane) = dn;
+                            Fp += obj_f(cc, dn);
+                            su[lane] = grad_f(cc, dn);
+                        }
+                        wave_sync();
+                        batch_partial(lb, v, [&](int r) { return su[r]; });
+                        if (VEC_LDS && lane == 0) flg[lb] = 1;
+                        wave_sync();
                     }
                 }
-                wave_sync();
-                if (lane < ROWS) {
-                    const int64_t row = base + lane;
-                    double dn;
-                    if (mode == 1) {
-                        dn = su[lane] - tau_at(A.tau, row);   // the master keeps d - tau
-                    } else {
-                        dn = d_pre;
-                        if (mode == 0) dn = dn + t * q_pre;
+                if (!VEC_LDS) __threadfence();   // the partials stored in device memory, before the barrier
+                // F per wavefront; grad_y: thread (k, j) sums the partials of
+                // batches j, j + 8, ... (flagged ones; the others are +0), then
+                // the 8 sums of each slot and the F of the 8 wavefronts are
+                // combined in a fixed order
+                Fp = wave_reduce_dpp<0>(Fp);
+                if (lane == 0) s_acc[wave][0] = Fp;
+                __syncthreads();
+                {
+                    const int k = threadIdx.x / NW, j = threadIdx.x % NW;
+                    if (k < K) {
+                        double sacc = 0.0;
+                        for (int64_t lb = j; lb < nlb; lb += NW) {
+                            if (VEC_LDS) {
+                                const double x = bpl[lb * KS + k];
+                                sacc += flg[lb] ? x : 0.0;
+                            } else {
+                                sacc += aload(A.bpart + (batch_base(lb) / ROWS) * KS + k);
+                            }
+                        }
+                        s_acc[j][1 + k] = sacc * dks;
                     }
-                    const ObjClass cc = cl[c_pre];
-                    if (mode != 2) d_at(row, lbase + lane) = dn;
-                    Fp += obj_f(cc, dn);
-                    su[lane] = grad_f(cc, dn);
                 }
-                wave_sync();
-#pragma unroll
-                for (int it = 0; it < IT; ++it) {
-                    const double u = su[it * G::RPW + rg];
-#pragma unroll
-                    for (int e = 0; e < G::EPL; ++e) acc[e] += u * vget(v[it], e);
-                }
-                wave_sync();
+                __syncthreads();
+                combine_waves8(&s_acc[0][0], RECW, K + 1, false, s_rec);
             }
-#pragma unroll
-            for (int off = G::LPR; off < WAVE; off <<= 1)
-#pragma unroll
-                for (int e = 0; e < G::EPL; ++e) acc[e] += __shfl_xor(acc[e], off, WAVE);
-            if (rg == 0)
-#pragma unroll
-                for (int e = 0; e < G::EPL; ++e) s_acc[wave][1 + c * G::EPL + e] = acc[e] * dks;
-            Fp = wave_reduce_dpp<0>(Fp);
-            if (lane == 0) s_acc[wave][0] = Fp;
-            __syncthreads();
-            combine_waves8(&s_acc[0][0], RECW, K + 1, false, s_rec);
             if (gb == 0 && threadIdx.x == 0) {
                 const double per_row = 16.0 * nc + 1.0 + (mode != 1 ? 8.0 : 0.0) +
                                        (mode == 0 ? double(sizeof(T)) : 0.0) + (mode != 2 ? 8.0 : 0.0);

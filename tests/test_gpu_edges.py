@@ -165,23 +165,35 @@ def test_graph_replayed_pricing_equals_launches(name, dtype, opts):
 
 @pytest.mark.parametrize("dk_format", [0, 1])
 def test_hybrid_form_equals_streaming(dk_format):
-    """On the head-and-neck-shaped matrix D_K does not fit on chip, but each
-    workgroup's d, q and classes do: the default persistent launch keeps
-    those in LDS and streams D_K (form 5).  It runs the streaming form's
-    arithmetic, so its plan equals the all-streaming launch's (persistent 1,
-    form 1) bit for bit, in FP32 and with an FP16 D_K."""
+    """On the head-and-neck-shaped matrix D_K does not fit on chip past a few
+    apertures (8 with FP16 storage), but each workgroup's d, q and classes
+    do: the default persistent launch then keeps those in LDS and streams
+    D_K (form 5).  It runs the streaming form's arithmetic (the same rows per
+    workgroup, the same order of every sum), so from the same state (the
+    default context's after 9 rounds, restored into both) its rounds equal
+    the all-streaming launch's (persistent 1, form 1) bit for bit, in FP32
+    and with an FP16 D_K.  (The on-chip form of the first rounds keeps its
+    own row split and order of sums.)"""
     ph = cached_phantom("headneck")
-    n = 12   # past 8 apertures an FP16 D_K no longer fits on chip either
     a = ctx_for(ph, dtype="f32", dk_format=dk_format)
     b = ctx_for(ph, dtype="f32", dk_format=dk_format, persistent=1)
     try:
-        ra, rb = a.solve(n), b.solve(n)
+        a.solve(9)
+        st = a.get_state()
+        for c in (a, b):
+            c.set_state(st["pool"], st["y"], rc1=st["rc1"], eps=st["eps"], tighten=st["tighten"],
+                        last_step=st["last_step"], prev_step=st["prev_step"])
+        ra, rb = a.solve_resume(12), b.solve_resume(12)
         fa, fb = a.info()["last_master_form"], b.info()["last_master_form"]
         print(f"[forms] headneck dk_format={dk_format}: forms {fa} / {fb}, F {ra['F']:.12e} / {rb['F']:.12e}",
               flush=True)
         assert fa == 5 and fb == 1
+        assert ra["rounds"] == rb["rounds"] and ra["rounds"] >= 1
         assert ra["F"] == rb["F"] and list(ra["round_beam"]) == list(rb["round_beam"])
         assert list(ra["round_steps"]) == list(rb["round_steps"])
+        pa, ya = a.get_pool()
+        pb, yb = b.get_pool()
+        assert pa == pb and np.array_equal(np.asarray(ya), np.asarray(yb))
     finally:
         a.close()
         b.close()
