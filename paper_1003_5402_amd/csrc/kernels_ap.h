@@ -136,6 +136,36 @@ __device__ __forceinline__ void load_batch(const DT* dk, int64_t base, int rg, i
     }
 }
 
+// load_batch restricted to some rows: `rows` has bit r set for each row
+// base + r that is needed; a load whose RPW rows are all unneeded reads
+// nothing and gives zeros.  The loads are buffer loads through a descriptor
+// of the batch's storage block, and an unneeded one gets an offset past the
+// block's end (out of range: no memory access, zero data), so all of them
+// still issue back to back with no branch.
+template <class DT, int IT, class V>
+__device__ __forceinline__ void load_batch_rows(const DT* dk, int64_t base, int rg, int c, int nc, uint64_t rows,
+                                                V (&v)[IT]) {
+    static_assert(IT * DKG<DT>::RPW == Batch<DT>::ROWS, "one batch per block");
+    static_assert(sizeof(V) == 16, "16-byte vectors");
+    constexpr int ROWS = Batch<DT>::ROWS, RPW = DKG<DT>::RPW;
+    constexpr uint32_t BLOCK_BYTES = uint32_t(DKG<DT>::VPR) * ROWS * 16;
+    const unsigned char* blk = reinterpret_cast<const unsigned char*>(dk) +
+                               size_t(base / ROWS) * BLOCK_BYTES;   // base: a multiple of ROWS
+    // word 3 of a GFX9 buffer descriptor: 32-bit data format, no swizzle
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char*>(blk), short(0), int(BLOCK_BYTES), 0x00020000);
+    // out of range: at or past 2^31, also after adding a row offset (< 2^11)
+    constexpr uint32_t OUT = 0x80000000u;
+    const uint32_t lane_off = c < nc ? uint32_t((c * ROWS + rg) * 16) : OUT;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        // the same for every lane: a scalar select, no branch
+        const bool grp = ((rows >> (it * RPW)) & ((uint64_t(1) << RPW) - 1)) != 0;
+        const uint32_t off = grp ? lane_off + uint32_t(it * RPW * 16) : OUT;
+        v[it] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rsrc, int(off), 0, 0));
+    }
+}
+
 // Order LDS traffic between lanes of one wavefront (used inside loops whose
 // trip count differs between the wavefronts of a workgroup, where a
 // workgroup barrier would be wrong).

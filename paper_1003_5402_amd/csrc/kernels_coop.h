@@ -255,12 +255,13 @@ __host__ __device__ inline int64_t coop_batches_per_group(int64_t Vpad, int grid
     const int64_t nbat = Vpad / Batch<T>::ROWS;
     return (nbat + grid - 1) / grid;
 }
-// The update pass's LDS (rows on chip): dF/dz of every row (double), then
-// each batch's grad_y partial (KS doubles) and its flag (a byte).
+// The update pass's LDS (hybrid form): dF/dz of every row (double), then
+// each batch's grad_y partial (KS doubles), then each batch's mask of rows
+// with dF/dz != 0 (64 bits).
 template <class DT>
 __host__ __device__ inline size_t coop_upd_lds(int64_t rows) {
     const int64_t nb = rows / Batch<DT>::ROWS;
-    return size_t(rows) * 8 + size_t(nb) * KS * 8 + ((size_t(nb) + 15) / 16) * 16;
+    return size_t(rows) * 8 + size_t(nb) * KS * 8 + size_t(nb) * 8;
 }
 
 // Dynamic LDS of the streaming form: per wavefront, the per-slot partials of
@@ -365,10 +366,10 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     uint8_t* cll = reinterpret_cast<uint8_t*>(ql + rows_max);
     // update pass of the hybrid form (at the front, where the q pass keeps
     // its row partials): dF/dz per row, then per batch its grad_y partial
-    // and a flag (the batch has a row with dF/dz != 0)
+    // and its mask of rows with dF/dz != 0
     double* ul = reinterpret_cast<double*>(dyn);
     double* bpl = ul + rows_max;
-    uint8_t* flg = reinterpret_cast<uint8_t*>(bpl + (rows_max / ROWS) * KS);
+    uint64_t* msk = reinterpret_cast<uint64_t*>(bpl + (rows_max / ROWS) * KS);
     if (LDSRES) {
         // in storage order: per batch, vector c of its ROWS rows, contiguous
         for (int64_t idx = threadIdx.x; idx < nrows * nc; idx += blockDim.x) {
@@ -629,24 +630,39 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                     }
                 };
                 if (VEC_LDS && mode != 1) {
-                    // rows on chip: new dose, F and dF/dz of every row, one row per thread
-                    for (int64_t i = threadIdx.x; i < nlb; i += blockDim.x) flg[i] = 0;
-                    __syncthreads();
-                    for (int64_t lrow = threadIdx.x; lrow < nrows; lrow += blockDim.x) {
-                        double dn = dl[lrow];
-                        if (mode == 0) dn = dn + t * double(ql[lrow]);
-                        const ObjClass cc = cl[cll[lrow]];
-                        if (mode != 2) dl[lrow] = dn;
-                        Fp += obj_f(cc, dn);
-                        const double u = grad_f(cc, dn);
-                        ul[lrow] = u;
-                        if (u != 0.0) flg[lrow / ROWS] = 1;
+                    // rows on chip: new dose, F and dF/dz of every row, one
+                    // row per thread (wavefront w: rows w * 64 + lane, then
+                    // every 512 further), and each batch's mask of rows with
+                    // dF/dz != 0
+                    static_assert(ROWS == WAVE || ROWS == WAVE / 2, "one or two batches per wavefront of rows");
+                    for (int64_t r0 = int64_t(wave) * WAVE; r0 < nrows; r0 += int64_t(NW) * WAVE) {
+                        const int64_t lrow = r0 + lane;
+                        double u = 0.0;
+                        if (lrow < nrows) {
+                            double dn = dl[lrow];
+                            if (mode == 0) dn = dn + t * double(ql[lrow]);
+                            const ObjClass cc = cl[cll[lrow]];
+                            if (mode != 2) dl[lrow] = dn;
+                            Fp += obj_f(cc, dn);
+                            u = grad_f(cc, dn);
+                            ul[lrow] = u;
+                        }
+                        const uint64_t m = __ballot(u != 0.0);
+                        if (lane == 0) {
+                            if (ROWS == WAVE) {
+                                msk[r0 / ROWS] = m;
+                            } else {
+                                msk[r0 / ROWS] = m & 0xFFFFFFFFull;
+                                if (r0 + ROWS < nrows) msk[r0 / ROWS + 1] = m >> 32;
+                            }
+                        }
                     }
                     __syncthreads();
-                    // the flagged batches, dealt to the wavefronts in batch order
+                    // the batches with a row to read, dealt to the wavefronts
+                    // in batch order
                     int done = 0;
                     for (int64_t c0 = 0; c0 < nlb; c0 += WAVE) {
-                        const bool on = c0 + lane < nlb && flg[c0 + lane] != 0;
+                        const bool on = c0 + lane < nlb && msk[c0 + lane] != 0;
                         const uint64_t m = __ballot(on);
                         const int rank = done + __popcll(m & ((uint64_t(1) << lane) - 1));
                         uint64_t mine = __ballot(on && rank % NW == wave);
@@ -655,7 +671,8 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                             const int64_t lb = c0 + __builtin_ctzll(mine);
                             mine &= mine - 1;
                             V v[IT];
-                            load_rows(batch_base(lb), lb * ROWS, v);
+                            // only the groups of RPW rows that hold a row with dF/dz != 0
+                            load_batch_rows<DT>(dk, batch_base(lb), rg, c, nc, msk[lb], v);
                             const double* ub = ul + lb * ROWS;
                             batch_partial(lb, v, [&](int r) { return ub[r]; });
                         }
@@ -704,7 +721,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                         }
                         wave_sync();
                         batch_partial(lb, v, [&](int r) { return su[r]; });
-                        if (VEC_LDS && lane == 0) flg[lb] = 1;
+                        if (VEC_LDS && lane == 0) msk[lb] = ~uint64_t(0);
                         wave_sync();
                     }
                 }
@@ -723,7 +740,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                         for (int64_t lb = j; lb < nlb; lb += NW) {
                             if (VEC_LDS) {
                                 const double x = bpl[lb * KS + k];
-                                sacc += flg[lb] ? x : 0.0;
+                                sacc += msk[lb] != 0 ? x : 0.0;
                             } else {
                                 sacc += aload(A.bpart + (batch_base(lb) / ROWS) * KS + k);
                             }
