@@ -725,7 +725,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                         wave_sync();
                     }
                 }
-                if (!VEC_LDS) __threadfence();   // the partials stored in device memory, before the barrier
+                    if (!VEC_LDS) __threadfence();   // the partials stored in device memory, before the barrier
                 // F per wavefront; grad_y: thread (k, j) sums the partials of
                 // batches j, j + 8, ... (flagged ones; the others are +0), then
                 // the 8 sums of each slot and the F of the 8 wavefronts are
