@@ -14,6 +14,25 @@ constexpr int LS_MAX_ITER = 60;       // line-search evaluations per master step
 constexpr int BLOCK = 256;            // threads per block of the streaming kernels
 constexpr int NPART = 6;              // doubles per block in a reduction record
 
+// Rows of the persistent master's workgroups (forms that stream the aperture
+// dose matrix): the batches of voxel rows are dealt in rounds of one batch
+// per workgroup; in round lb, workgroup b of a solve on gn workgroups owns
+// batch lb * gn + (b + COOP_SKEW * lb) % gn.  The rows the update pass has to
+// read (voxels outside their dose window) cluster in space and, after the
+// length sort, at the start of each sort window; dealing the batches spreads
+// them over the workgroups, and the skew keeps a pattern that repeats with
+// the round length from landing on the same workgroups every round.
+// (constexpr: usable on the host and, in HIP, on the device.)
+constexpr int64_t COOP_SKEW = 101;
+constexpr int64_t coop_batch(int64_t lb, uint32_t b, uint32_t gn) {
+    return lb * gn + (int64_t(b) + COOP_SKEW * lb) % gn;
+}
+// Batches of workgroup b: one per full round, and the last partial round's
+// when its slot falls inside it.
+constexpr int64_t coop_nbatches(int64_t nbat, uint32_t b, uint32_t gn) {
+    return nbat / gn + ((nbat % gn > 0 && (int64_t(b) + COOP_SKEW * (nbat / gn)) % gn < nbat % gn) ? 1 : 0);
+}
+
 // Objective coefficients of a voxel class (eq. 9 and eq. 10): the terms of
 // its first structure and, for a voxel in two overlapping structures, of its
 // second (zero weights when there is none).  a and b are the structure

@@ -228,24 +228,8 @@ struct CoopArgs {
     int timing;         // workgroup 0 accumulates per-phase wall-clock ticks in pc->ticks
 };
 
-// Rows of a workgroup (forms that stream D_K): the batches of ROWS rows are
-// dealt in rounds of one batch per workgroup; in round lb, workgroup b of a
-// solve on gn workgroups owns batch lb * gn + (b + COOP_SKEW * lb) % gn.  The rows whose D_K rows
-// the update pass reads (voxels outside their dose window) cluster in space
-// and, after the length sort, at the start of each sort window; dealing the
-// batches spreads them over the workgroups, and the skew keeps a pattern
-// that repeats with the round length from landing on the same workgroups
-// every round.
-constexpr int64_t COOP_SKEW = 101;
-__host__ __device__ inline int64_t coop_batch(int64_t lb, uint32_t b, uint32_t gn) {
-    return lb * gn + (int64_t(b) + COOP_SKEW * lb) % gn;
-}
-// Batches of workgroup b: one per full round, and the last partial round's
-// when its slot falls inside it.
-__host__ __device__ inline int64_t coop_nbatches(int64_t nbat, uint32_t b, uint32_t gn) {
-    const int64_t full = nbat / gn, rem = nbat % gn;
-    return full + ((rem > 0 && (int64_t(b) + COOP_SKEW * full) % gn < rem) ? 1 : 0);
-}
+// Rows of a workgroup: in the forms that stream D_K the batches of ROWS rows
+// are dealt to the workgroups (coop_batch and coop_nbatches, dao_common.h).
 // The most batches a workgroup owns (LDS sizing).  With D_K on chip a
 // workgroup owns a contiguous range of that many batches (the last ones
 // fewer): the update pass's skipped batches cost little there, D_K being read

@@ -121,6 +121,30 @@ int main(int argc, char** argv) {
     o.graphs = 0;
     expect(validate(p, o) == DAO_OK, "valid problem accepted");
 
+    // ---- the persistent master's dealt row batches: every batch owned by
+    // exactly one workgroup, each workgroup's count as coop_nbatches says,
+    // never more than the LDS sizing's ceil(batches / workgroups), and a
+    // workgroup's local batches in increasing order
+    for (int64_t nbat : {int64_t(1), int64_t(7), int64_t(255), int64_t(256), int64_t(257), int64_t(1651),
+                         int64_t(11236), int64_t(20000)}) {
+        for (uint32_t gn : {1u, 3u, 64u, 255u, 256u}) {
+            std::vector<int> owner(size_t(nbat), 0);
+            const int64_t most = (nbat + gn - 1) / gn;
+            for (uint32_t b = 0; b < gn; ++b) {
+                const int64_t n = coop_nbatches(nbat, b, gn);
+                expect(n <= most, "no workgroup owns more batches than the LDS holds");
+                int64_t prev = -1;
+                for (int64_t lb = 0; lb < n; ++lb) {
+                    const int64_t bt = coop_batch(lb, b, gn);
+                    expect(bt >= 0 && bt < nbat && bt > prev, "dealt batch in range and in order");
+                    if (bt >= 0 && bt < nbat) ++owner[size_t(bt)];
+                    prev = bt;
+                }
+            }
+            for (int64_t bt = 0; bt < nbat; ++bt) expect(owner[size_t(bt)] == 1, "every batch dealt once");
+        }
+    }
+
     // ---- the layouts
     const dao_matrix M = p.m();
     const dao_beams Bm = p.b();

@@ -5,8 +5,10 @@ UndefinedBehaviorSanitizer by g++ and run on phantom inputs (no GPU).
 tests/host_layout_check.cpp reads every array the layout builder writes and
 checks it against the CSR input (forward sliced-ELL entries in order with
 zero padding, transposed entries, row permutation, objective classes, MLC
-geometry), feeds malformed inputs to the validator, and checks the encoders'
-rounding.  A sanitizer report or a failed check ends the run non-zero.
+geometry), feeds malformed inputs to the validator, checks the encoders'
+rounding, and checks that the persistent master's dealing of row batches to
+workgroups (dao_common.h) is a bijection within the LDS sizing.  A sanitizer
+report or a failed check ends the run non-zero.
 """
 import os
 import shutil
