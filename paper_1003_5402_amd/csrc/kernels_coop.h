@@ -412,7 +412,8 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     };
 
     while (alive) {
-        // ---------------- update pass: apply the step, dF/dz, F, grad_y partials
+        // ---------------- update pass: apply the step, dF/dz, grad_y partials
+        // (the objective is summed once, at the final point of the solve)
         {
             if constexpr (LDSRES) {
                 // D_K on chip: each wavefront sums grad_y over its batches
@@ -425,7 +426,6 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                     yv[e] = (mode == 1 && k < K) ? s_y[k] * dks : 0.0;
                     acc[e] = 0.0;
                 }
-                double Fp = 0.0;
                 double* su = s_u[wave];
                 // the batch's D_K rows, from LDS (COOP_CHIP) or device memory
                 auto load_rows = [&](int64_t base, int64_t lbase, V (&v)[IT]) {
@@ -466,7 +466,6 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                             if (mode == 0) dn = dn + t * double(ql[lrow]);
                             const ObjClass cc = cl[cll[lrow]];
                             if (mode != 2) dl[lrow] = dn;
-                            Fp += obj_f(cc, dn);
                             u = grad_f(cc, dn);
                             su[lane] = u;
                         }
@@ -519,7 +518,6 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                         }
                         const ObjClass cc = cl[c_pre];
                         if (mode != 2) d_at(row, lbase + lane) = dn;
-                        Fp += obj_f(cc, dn);
                         su[lane] = grad_f(cc, dn);
                     }
                     wave_sync();
@@ -537,11 +535,9 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                     for (int e = 0; e < G::EPL; ++e) acc[e] += __shfl_xor(acc[e], off, WAVE);
                 if (rg == 0)
 #pragma unroll
-                    for (int e = 0; e < G::EPL; ++e) s_acc[wave][1 + c * G::EPL + e] = acc[e] * dks;
-                Fp = wave_reduce_dpp<0>(Fp);
-                if (lane == 0) s_acc[wave][0] = Fp;
+                    for (int e = 0; e < G::EPL; ++e) s_acc[wave][c * G::EPL + e] = acc[e] * dks;
                 __syncthreads();
-                combine_waves8(&s_acc[0][0], RECW, K + 1, false, s_rec);
+                combine_waves8(&s_acc[0][0], RECW, K, false, s_rec);
             } else {
                 //
                 // grad_y is summed per batch (each lane over the batch's rows in
@@ -561,7 +557,6 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                     const int k = c * G::EPL + e;
                     yv[e] = (mode == 1 && k < K) ? s_y[k] * dks : 0.0;
                 }
-                double Fp = 0.0;
                 double* su = s_u[wave];
                 // the batch's D_K rows, from LDS (COOP_CHIP) or device memory
                 auto load_rows = [&](int64_t base, int64_t lbase, V (&v)[IT]) {
@@ -627,7 +622,6 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                             if (mode == 0) dn = dn + t * double(ql[lrow]);
                             const ObjClass cc = cl[cll[lrow]];
                             if (mode != 2) dl[lrow] = dn;
-                            Fp += obj_f(cc, dn);
                             u = grad_f(cc, dn);
                             ul[lrow] = u;
                         }
@@ -700,7 +694,6 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                             }
                             const ObjClass cc = cl[c_pre];
                             if (mode != 2) d_at(row, lbase + lane) = dn;
-                            Fp += obj_f(cc, dn);
                             su[lane] = grad_f(cc, dn);
                         }
                         wave_sync();
@@ -710,12 +703,9 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                     }
                 }
                     if (!VEC_LDS) __threadfence();   // the partials stored in device memory, before the barrier
-                // F per wavefront; grad_y: thread (k, j) sums the partials of
-                // batches j, j + 8, ... (flagged ones; the others are +0), then
-                // the 8 sums of each slot and the F of the 8 wavefronts are
-                // combined in a fixed order
-                Fp = wave_reduce_dpp<0>(Fp);
-                if (lane == 0) s_acc[wave][0] = Fp;
+                // grad_y: thread (k, j) sums the partials of batches j, j + 8,
+                // ... (those with a row to read; the others are +0), then the
+                // 8 sums of each slot are combined in a fixed order
                 __syncthreads();
                 {
                     const int k = threadIdx.x / NW, j = threadIdx.x % NW;
@@ -729,11 +719,11 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                                 sacc += aload(A.bpart + (batch_base(lb) / ROWS) * KS + k);
                             }
                         }
-                        s_acc[j][1 + k] = sacc * dks;
+                        s_acc[j][k] = sacc * dks;
                     }
                 }
                 __syncthreads();
-                combine_waves8(&s_acc[0][0], RECW, K + 1, false, s_rec);
+                combine_waves8(&s_acc[0][0], RECW, K, false, s_rec);
             }
             if (gb == 0 && threadIdx.x == 0) {
                 const double per_row = 16.0 * nc + 1.0 + (mode != 1 ? 8.0 : 0.0) +
@@ -742,7 +732,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                 cnt_real[0] += 1;
             }
             tick(0);
-            if (!grid_reduce<false>(A.sync, A.recs, s_rec, K + 1, s_tot, seq, gb, gn)) {
+            if (!grid_reduce<false>(A.sync, A.recs, s_rec, K, s_tot, seq, gb, gn)) {
                 alive = false;
                 break;
             }
@@ -753,7 +743,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             const int k = threadIdx.x;
             const bool in = k < K;
             const double yk = s_y[k];
-            const double gk = in ? s_tot[1 + k] : 0.0;
+            const double gk = in ? s_tot[k] : 0.0;
             double rk;
             bool fk;
             const double pk = cg_dir_wave(in, yk, gk, s_ms.conj && s_ms.cg_valid, s_p[k], s_r[k], s_fr[k] != 0,
@@ -770,7 +760,6 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             }
             s_g[k] = gk;
             if (k == 0) {
-                s_ms.F = s_ms.F_const + s_tot[0];
                 s_ms.kkt = kkt;
                 int go = 1;
                 if (!(kkt > s_ms.tol)) {
@@ -957,6 +946,25 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
             // own barriers
             if (mode == 1) __syncthreads();
             tick(5);
+        }
+    }
+    // the objective at the final point: one row per thread (the same split
+    // and order in every form), a fixed-order workgroup sum, one grid
+    // reduction
+    if (alive) {
+        double Fp = 0.0;
+        for (int64_t lrow = threadIdx.x; lrow < nrows; lrow += blockDim.x) {
+            const int64_t row = batch_base(lrow / ROWS) + lrow % ROWS;
+            Fp += obj_f(cl[cls_at(row, lrow)], d_at(row, lrow));
+        }
+        Fp = wave_reduce_dpp<0>(Fp);
+        if (lane == 0) s_acc[wave][0] = Fp;
+        __syncthreads();
+        combine_waves8(&s_acc[0][0], RECW, 1, false, s_rec);
+        if (grid_reduce<false>(A.sync, A.recs, s_rec, 1, s_tot, seq, gb, gn)) {
+            if (threadIdx.x == 0) s_ms.F = s_ms.F_const + s_tot[0];
+        } else {
+            alive = false;
         }
     }
     if (VEC_LDS) {
