@@ -305,7 +305,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
     __shared__ int s_fr[KS];
     __shared__ double s_rec[RECW], s_tot[RECW];
     static_assert(NW == 8, "the wavefront combines assume 8 wavefronts");
-    __shared__ double s_acc[NW][RECW];   // per wavefront: objective, then grad_y
+    __shared__ double s_acc[NW][RECW];   // per wavefront: grad_y (the final objective in field 0)
     __shared__ double s_u[NW][ROWS];
     __shared__ int s_go;
 
@@ -609,7 +609,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                     }
                 };
                 if (VEC_LDS && mode != 1) {
-                    // rows on chip: new dose, F and dF/dz of every row, one
+                    // rows on chip: new dose and dF/dz of every row, one
                     // row per thread (wavefront w: rows w * 64 + lane, then
                     // every 512 further), and each batch's mask of rows with
                     // dF/dz != 0
