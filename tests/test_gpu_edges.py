@@ -163,20 +163,21 @@ def test_graph_replayed_pricing_equals_launches(name, dtype, opts):
         ctx.close()
 
 
-@pytest.mark.parametrize("dk_format", [0, 1])
-def test_hybrid_form_equals_streaming(dk_format):
+@pytest.mark.parametrize("dtype,dk_format", [("f32", 0), ("f32", 1), ("f64", 0)])
+def test_hybrid_form_equals_streaming(dtype, dk_format):
     """On the head-and-neck-shaped matrix D_K does not fit on chip past a few
     apertures (8 with FP16 storage), but each workgroup's d, q and classes
     do: the default persistent launch then keeps those in LDS and streams
     D_K (form 5).  It runs the streaming form's arithmetic (the same rows per
     workgroup, the same order of every sum), so from the same state (the
     default context's after 9 rounds, restored into both) its rounds equal
-    the all-streaming launch's (persistent 1, form 1) bit for bit, in FP32
-    and with an FP16 D_K.  (The on-chip form of the first rounds keeps its
-    own row split and order of sums.)"""
+    the all-streaming launch's (persistent 1, form 1) bit for bit, in FP32,
+    with an FP16 D_K and in FP64 (batches of 32 rows, two per wavefront).
+    (The on-chip form of the first rounds keeps its own row split and order
+    of sums.)"""
     ph = cached_phantom("headneck")
-    a = ctx_for(ph, dtype="f32", dk_format=dk_format)
-    b = ctx_for(ph, dtype="f32", dk_format=dk_format, persistent=1)
+    a = ctx_for(ph, dtype=dtype, dk_format=dk_format)
+    b = ctx_for(ph, dtype=dtype, dk_format=dk_format, persistent=1)
     try:
         a.solve(9)
         st = a.get_state()
@@ -185,7 +186,7 @@ def test_hybrid_form_equals_streaming(dk_format):
                         last_step=st["last_step"], prev_step=st["prev_step"])
         ra, rb = a.solve_resume(12), b.solve_resume(12)
         fa, fb = a.info()["last_master_form"], b.info()["last_master_form"]
-        print(f"[forms] headneck dk_format={dk_format}: forms {fa} / {fb}, F {ra['F']:.12e} / {rb['F']:.12e}",
+        print(f"[forms] headneck {dtype} dk_format={dk_format}: forms {fa} / {fb}, F {ra['F']:.12e} / {rb['F']:.12e}",
               flush=True)
         assert fa == 5 and fb == 1
         assert ra["rounds"] == rb["rounds"] and ra["rounds"] >= 1
