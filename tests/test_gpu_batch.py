@@ -76,6 +76,34 @@ def test_batch_of_different_sizes_and_budgets_fp32():
             c.close()
 
 
+def test_batch_with_streamed_aperture_matrix_fp32():
+    """A head-and-neck-shaped solve beside a prostate-shaped one: past a few
+    apertures the head-and-neck D_K no longer fits on chip, so the batched
+    launch takes the hybrid form (D_K streamed, each workgroup's rows of d,
+    q and classes on chip, row batches dealt over its share of the grid);
+    every plan as alone."""
+    torch_cuda()
+    specs = [("headneck", 0), ("prostate", 0)]
+    budgets = [9, 9]   # equal budgets: every round, both solves share the launch
+    phs = _phantoms(specs)
+    alone = [_alone(ph, "f32", n) for ph, n in zip(phs, budgets)]
+    ctxs = [ctx_for(ph, dtype="f32") for ph in phs]
+    try:
+        outs = dao.solve_batch(ctxs, budgets)
+        forms = [c.info()["last_master_form"] for c in ctxs]
+        print(f"[batch] head-and-neck + prostate: last forms {forms}", flush=True)
+        assert forms == [6, 6]
+        for i, (out, ctx) in enumerate(zip(outs, ctxs)):
+            ref, pool_ref, _ = alone[i]
+            pool, _ = ctx.get_pool()
+            print(f"[batch] {specs[i]} F {out['F']:.12e} alone {ref['F']:.12e}", flush=True)
+            assert pool == pool_ref, i
+            assert abs(out["F"] - ref["F"]) <= 1e-5 * ref["F"], (i, out["F"], ref["F"])
+    finally:
+        for c in ctxs:
+            c.close()
+
+
 def test_batch_rejects_bad_arguments():
     torch_cuda()
     ph = make_phantom("mini", 0)
