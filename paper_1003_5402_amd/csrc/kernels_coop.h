@@ -558,29 +558,6 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                     yv[e] = (mode == 1 && k < K) ? s_y[k] * dks : 0.0;
                 }
                 double* su = s_u[wave];
-                // the batch's D_K rows, from LDS (COOP_CHIP) or device memory
-                auto load_rows = [&](int64_t base, int64_t lbase, V (&v)[IT]) {
-                    if (LDSRES) {
-                        // running LDS offset, opaque to the compiler so it adds one
-                        // stride per load instead of keeping IT addresses live
-                        uint32_t off = uint32_t(((lbase + rg) * ncp + c) * 16);
-                        const uint32_t stride = uint32_t(G::RPW * ncp * 16);
-                        // one predicated region for all the loads (see load_batch)
-                        if (c < nc) {
-#pragma unroll
-                            for (int it = 0; it < IT; ++it) {
-                                asm volatile("" : "+v"(off));
-                                v[it] = *reinterpret_cast<const V*>(dyn + off);
-                                off += stride;
-                            }
-                        } else {
-#pragma unroll
-                            for (int it = 0; it < IT; ++it) v[it] = vzero<V>();
-                        }
-                    } else {
-                        load_batch<DT>(dk, base, rg, c, nc, v);
-                    }
-                };
                 // grad_y partial of one batch from its D_K rows and the rows'
                 // dF/dz (u(r): row r of the batch), stored for the combine
                 auto batch_partial = [&](int64_t lb, const V (&v)[IT], auto&& u) {
@@ -671,7 +648,7 @@ __device__ __forceinline__ void master_body(const CoopArgs<T>& A, const uint32_t
                             c_pre = cls_at(row, lrow);
                         }
                         V v[IT];
-                        load_rows(base, lbase, v);
+                        load_batch<DT>(dk, base, rg, c, nc, v);
                         if (mode == 1) {
 #pragma unroll
                             for (int it = 0; it < IT; ++it) {
