@@ -365,8 +365,8 @@ def main():
                     help="append the per-round records of one untimed headline plan to this JSON-lines file")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the plan is a single-GPU workload "
-              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: one plan's dose matrix, aperture dose matrix and master "
+              "state fit one GPU, and this build measures a single GPU", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
