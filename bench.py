@@ -366,7 +366,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: one plan's dose matrix, aperture dose matrix and master "
-              "state fit one GPU, and this build measures a single GPU", file=sys.stderr)
+              "state fit one GPU, and several GPUs are not measured", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
