@@ -153,7 +153,9 @@ typedef struct {
                                per lane (every entry group of a row in flight, x staged
                                once per workgroup) on a grid of 1, 2 or 4 workgroups of
                                256 threads per compute unit, each walking slices with
-                               the grid's stride */
+                               the grid's stride; 7, 8 as 5, 6 with each wavefront's
+                               slices from a list balanced by slice width at creation
+                               (widest first, to the least-loaded wavefront) */
     int32_t gradient_depth; /* with product_tune 0: transposed product entries per thread
                                in flight, 4 (default), 8 or 16 */
     int32_t direction;      /* master search direction (Section 2.3, gradient projection):

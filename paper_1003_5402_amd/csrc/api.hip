@@ -102,6 +102,8 @@ struct dao_ctx {
     double prof_phase_us[PROF_PHASES] = {};   // persistent master split of the last window
     int device = 0;                    // HIP device of the context
     int dose_var = 0;                  // k_dose variant (0 staged, 1 staged + deep loads, 2 global x + deep)
+    int32_t* slice_order[2] = {nullptr, nullptr};   // dose variants 7 / 8: balanced slice lists
+    int slice_rounds[2] = {0, 0};
     int gradT_pf = 4;                  // k_gradT entries in flight per thread (4, 8 or 16)
     int last_steps = 0;                // steps of the previous master solve (chunk size guess)
     // column-generation loop state of the last (or restored) solve, for resume
@@ -252,6 +254,7 @@ int64_t predicted_bytes(const HostLayout& L, size_t ts, int kmax, const dao_opti
     const int64_t dkb = (opt.dk_format == DAO_DFMT_F16 && ts == 4 && opt.d_residual != 2) ? 2 : int64_t(ts);
     b += int64_t(L.Vpad) * KS * dkb + L.N * ts + 512 * (KS + 1) * 8;
     b += int64_t(L.Vpad) / 32 * KS * 8;   // the persistent master's per-batch partials
+    b += 2 * 8 * (L.nslices + 4096) * 4;   // the forward product's slice lists (a generous bound)
     b += sizeof(MasterState) + sizeof(PriceResult) + L.R * sizeof(RowRec) + 2 * ELEM_BLOCKS_MAX * sizeof(Rec) +
          sizeof(Arrival);
     return b;
@@ -303,6 +306,12 @@ void with_values(const dao_ctx* c, F&& f) {
 // exists for native values only (a 16-bit format folds its scale into the
 // staged copy); variant 3 gives each workgroup twice the slices (each
 // wavefront two chunks of its row).
+// Grid of the whole-rows forward product with per_cu workgroups per compute unit.
+inline int64_t rows_grid(const dao_ctx* c, int per_cu) {
+    const int64_t need = (c->nslices + ROWS_THREADS / WAVE - 1) / (ROWS_THREADS / WAVE);
+    return std::max<int64_t>(1, std::min<int64_t>(need, int64_t(std::max(1, c->ncu)) * per_cu));
+}
+
 template <class T>
 void launch_dose(dao_ctx* c, const T* x, T* d_out, int var = -1) {
     if (var < 0) var = c->dose_var;
@@ -317,13 +326,18 @@ void launch_dose(dao_ctx* c, const T* x, T* d_out, int var = -1) {
         else if (var == 3)
             k_dose<T, VT, LO, 0, 2 * SPB><<<(c->nslices + 2 * SPB - 1) / (2 * SPB), SLAB_THREADS, lds, c->stream>>>(
                 sell_view<VT>(c), c->perm, c->Vpad, x, int(c->N), stage, c->col_scale, d_out);
-        else if (var >= 4 && stage) {
+        else if (var >= 7 && stage && c->slice_order[var - 7]) {
+            // whole rows per lane, 2 or 4 workgroups per CU, balanced slice lists
+            const int i = var - 7;
+            k_dose_rows<T, VT, LO, 8, true><<<rows_grid(c, i == 0 ? 2 : 4), ROWS_THREADS, lds, c->stream>>>(
+                sell_view<VT>(c), c->perm, c->Vpad, x, int(c->N), c->col_scale, d_out, c->slice_order[i],
+                c->slice_rounds[i]);
+        }
+        else if (var >= 4 && var <= 6 && stage) {
             // whole rows per lane on a grid of 1, 2 or 4 workgroups per CU
             const int per_cu = var == 4 ? 1 : var == 5 ? 2 : 4;
-            const int64_t need = (c->nslices + ROWS_THREADS / WAVE - 1) / (ROWS_THREADS / WAVE);
-            const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(need, int64_t(std::max(1, c->ncu)) * per_cu));
-            k_dose_rows<T, VT, LO><<<grid, ROWS_THREADS, lds, c->stream>>>(sell_view<VT>(c), c->perm, c->Vpad, x,
-                                                                         int(c->N), c->col_scale, d_out);
+            k_dose_rows<T, VT, LO><<<rows_grid(c, per_cu), ROWS_THREADS, lds, c->stream>>>(
+                sell_view<VT>(c), c->perm, c->Vpad, x, int(c->N), c->col_scale, d_out);
         }
         else
             k_dose<T, VT, LO, 8><<<c->slab_blocks(), SLAB_THREADS, lds, c->stream>>>(
@@ -372,7 +386,7 @@ dao_status tune_products(dao_ctx* c) {
     if (he == hipSuccess) he = hipMemsetAsync(c->u, 0, c->Vpad * sizeof(T), c->stream);
     const bool native = c->opt.d_format == DAO_DFMT_NATIVE;
     const int pfs[3] = {4, 8, 16};
-    constexpr int NDV = 7;   // forward variants: 0-3 slab forms, 4-6 whole rows per lane
+    constexpr int NDV = 9;   // forward variants: 0-3 slab forms, 4-8 whole rows per lane
     double best_d[NDV], best_g[3] = {1e30, 1e30, 1e30};
     for (double& b : best_d) b = 1e30;
     constexpr int REPS = 3, LAUNCHES = 8;
@@ -1159,6 +1173,18 @@ dao_status create_typed(dao_ctx* c, const HostLayout& L) {
         int dev = 0;
         HIPCHK(c, hipGetDevice(&dev));
         HIPCHK(c, hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    }
+    // balanced slice lists of the whole-rows forward product (variants 7 and 8:
+    // 2 and 4 workgroups per CU), for this device's compute units
+    if (c->stage_x() && c->nslices > 0) {
+        for (int i = 0; i < 2; ++i) {
+            std::vector<int32_t> order;
+            int rounds = 0;
+            balanced_slice_order(L.slice_w, rows_grid(c, i == 0 ? 2 : 4) * (ROWS_THREADS / WAVE), order, rounds);
+            const dao_status su = upload(c, &c->slice_order[i], order.data(), order.size() * 4);
+            if (su != DAO_OK) return su;
+            c->slice_rounds[i] = rounds;
+        }
     }
     c->dose_var = c->opt.dose_variant;
     if (c->dose_var >= 4 && !c->stage_x()) c->dose_var = 0;   // the row form stages x

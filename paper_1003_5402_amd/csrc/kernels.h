@@ -556,20 +556,38 @@ __global__ void __launch_bounds__(SLAB_THREADS) k_dose(SellView<VT> S, const int
 // them (the KSPLIT chunks of whole groups, each from 0 in stored order, then
 // the chunk sums in order, empty chunks included), so the result is the
 // same bit for bit.
+//
+// ORDERED: the slices of wavefront gw (of nw = gridDim.x * 4 in the grid) are
+// order[k * nw + gw] for k = 0, 1, ... up to the first -1 (at most rounds),
+// a list the host balances by slice width (the widest slices first, each to
+// the wavefront with the least work so far): the length sort puts the widest
+// slices at the start of every sort window, and a plain grid stride would
+// give some wavefronts several of them.  Every row's sum is the same either
+// way; only which wavefront computes it changes.
 constexpr int ROWS_THREADS = 256;
-template <class T, class VT = T, bool LO = false, int GB = 8>
+template <class T, class VT = T, bool LO = false, int GB = 8, bool ORDERED = false>
 __global__ void __launch_bounds__(ROWS_THREADS) k_dose_rows(SellView<VT> S, const int32_t* __restrict__ perm,
                                                             int64_t Vpad, const T* __restrict__ x, int N,
-                                                            const float* __restrict__ scale, T* __restrict__ d_ext) {
+                                                            const float* __restrict__ scale, T* __restrict__ d_ext,
+                                                            const int32_t* __restrict__ order = nullptr,
+                                                            int rounds = 0) {
     extern __shared__ __align__(16) unsigned char smem[];
     T* xs = reinterpret_cast<T*>(smem);
     constexpr int NW = ROWS_THREADS / WAVE;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int64_t stride = int64_t(gridDim.x) * NW;
-    int64_t s = int64_t(blockIdx.x) * NW + wave;
+    const int64_t gw = int64_t(blockIdx.x) * NW + wave;
+    // slice of this wavefront's k-th turn (-1: none)
+    auto slice_at = [&](int64_t k) -> int64_t {
+        if (ORDERED) return k < rounds ? int64_t(order[k * stride + gw]) : -1;
+        const int64_t sl = gw + k * stride;
+        return sl < S.nslices ? sl : -1;
+    };
+    int64_t k = 0;
+    int64_t s = slice_at(0);
     uint32_t nbase = 0;
     int nwid = 0;
-    if (s < S.nslices) {
+    if (s >= 0) {
         nbase = S.slice_ptr[s];
         nwid = S.slice_w[s];
     }
@@ -578,12 +596,13 @@ __global__ void __launch_bounds__(ROWS_THREADS) k_dose_rows(SellView<VT> S, cons
     else
         for (int i = threadIdx.x; i < N; i += blockDim.x) xs[i] = T(x[i]);
     __syncthreads();
-    for (; s < S.nslices; s += stride) {
+    while (s >= 0) {
         const uint32_t base = nbase;
         const int w = nwid;   // a multiple of 4
-        if (s + stride < S.nslices) {
-            nbase = S.slice_ptr[s + stride];
-            nwid = S.slice_w[s + stride];
+        const int64_t s_next = slice_at(++k);
+        if (s_next >= 0) {
+            nbase = S.slice_ptr[s_next];
+            nwid = S.slice_w[s_next];
         }
         const int ng = w >> 2;
         const int gpc = (ng + KSPLIT - 1) / KSPLIT;   // groups per chunk, as chunk_range
@@ -623,6 +642,7 @@ __global__ void __launch_bounds__(ROWS_THREADS) k_dose_rows(SellView<VT> S, cons
             const int32_t j = perm[row];
             if (j >= 0) d_ext[j] = sum;
         }
+        s = s_next;
     }
 }
 

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <map>
 #include <numeric>
+#include <queue>
 #include <set>
 #include <sstream>
 
@@ -108,7 +109,7 @@ dao_status validate_inputs(const dao_matrix* D, const dao_beams* beams,
         return fail("master must be DAO_MASTER_APERTURE or DAO_MASTER_BEAMLET");
     if (opt->persistent < 0 || opt->persistent > 2) return fail("persistent must be 0, 1 or 2");
     if (opt->product_tune < 0 || opt->product_tune > 1) return fail("product_tune must be 0 or 1");
-    if (opt->dose_variant < 0 || opt->dose_variant > 6) return fail("dose_variant must be in [0, 6]");
+    if (opt->dose_variant < 0 || opt->dose_variant > 8) return fail("dose_variant must be in [0, 8]");
     if (opt->dose_variant == 2 && opt->d_format != DAO_DFMT_NATIVE)
         return fail("dose_variant 2 reads x unscaled: native d_format only");
     if (opt->gradient_depth != 4 && opt->gradient_depth != 8 && opt->gradient_depth != 16)
@@ -389,6 +390,33 @@ void build_layout(const dao_matrix* D, const dao_beams* beams, const dao_structu
             }
         }
     }
+}
+
+void balanced_slice_order(const std::vector<int32_t>& slice_w, int64_t nwaves, std::vector<int32_t>& order,
+                          int& rounds) {
+    const int64_t ns = int64_t(slice_w.size());
+    std::vector<int32_t> idx(static_cast<size_t>(ns));
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return slice_w[a] > slice_w[b]; });
+    using Item = std::pair<int64_t, int64_t>;   // (work so far, wavefront)
+    std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+    for (int64_t g = 0; g < nwaves; ++g) heap.push({0, g});
+    std::vector<std::vector<int32_t>> lists(size_t(nwaves > 0 ? nwaves : 0));
+    for (int32_t sl : idx) {
+        Item it = heap.top();
+        heap.pop();
+        lists[size_t(it.second)].push_back(sl);
+        it.first += int64_t(slice_w[size_t(sl)]) + 4;
+        heap.push(it);
+    }
+    rounds = 0;
+    for (auto& l : lists) {
+        std::sort(l.begin(), l.end());
+        rounds = std::max(rounds, int(l.size()));
+    }
+    order.assign(size_t(rounds) * size_t(nwaves > 0 ? nwaves : 0), -1);
+    for (int64_t g = 0; g < nwaves; ++g)
+        for (size_t k = 0; k < lists[size_t(g)].size(); ++k) order[k * size_t(nwaves) + size_t(g)] = lists[size_t(g)][k];
 }
 
 }  // namespace dao

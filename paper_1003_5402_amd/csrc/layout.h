@@ -72,4 +72,12 @@ dao_status validate_inputs(const dao_matrix* D, const dao_beams* beams,
 void build_layout(const dao_matrix* D, const dao_beams* beams, const dao_structures* structs,
                   const dao_prescription* presc, HostLayout* L);
 
+// Slice lists of the whole-rows forward product for nwaves wavefronts: the
+// widest slices first, each to the wavefront with the least work so far
+// (ties: the lowest wavefront), work = slice width + 4; each list ascending.
+// order[k * nwaves + g] is the k-th slice of wavefront g, -1 past its list;
+// rounds = the longest list.
+void balanced_slice_order(const std::vector<int32_t>& slice_w, int64_t nwaves, std::vector<int32_t>& order,
+                          int& rounds);
+
 }  // namespace dao

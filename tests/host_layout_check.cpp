@@ -145,6 +145,38 @@ int main(int argc, char** argv) {
         }
     }
 
+    // ---- balanced slice lists: every slice once, -1 only past a list's end,
+    // each list ascending, and no wavefront's work above the average plus the
+    // widest slice (the greedy bound)
+    {
+        std::mt19937 g(7);
+        for (int64_t nw : {int64_t(1), int64_t(5), int64_t(64), int64_t(2048)}) {
+            std::vector<int32_t> w(size_t(3000));
+            for (auto& x : w) x = 4 * int32_t(1 + g() % 18);
+            std::vector<int32_t> order;
+            int rounds = 0;
+            balanced_slice_order(w, nw, order, rounds);
+            expect(int64_t(order.size()) == int64_t(rounds) * nw, "slice lists size");
+            std::vector<int> seen(w.size(), 0);
+            int64_t total = 0, widest = 0, worst = 0;
+            for (auto x : w) { total += x + 4; widest = std::max<int64_t>(widest, x + 4); }
+            for (int64_t gw = 0; gw < nw; ++gw) {
+                int64_t work = 0, prev = -1;
+                bool ended = false;
+                for (int k = 0; k < rounds; ++k) {
+                    const int32_t sl = order[size_t(k) * size_t(nw) + size_t(gw)];
+                    if (sl < 0) { ended = true; continue; }
+                    expect(!ended && sl < int32_t(w.size()) && sl > prev, "list entry in range, ascending, unbroken");
+                    if (sl >= 0 && sl < int32_t(w.size())) { ++seen[size_t(sl)]; work += w[size_t(sl)] + 4; }
+                    prev = sl;
+                }
+                worst = std::max(worst, work);
+            }
+            for (int v : seen) expect(v == 1, "every slice in one list");
+            expect(worst <= total / nw + widest, "greedy balance bound");
+        }
+    }
+
     // ---- the layouts
     const dao_matrix M = p.m();
     const dao_beams Bm = p.b();

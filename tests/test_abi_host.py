@@ -85,7 +85,7 @@ def test_create_rejects_malformed_inputs():
                          (dict(apertures_per_round=17), "apertures_per_round"), (dict(dk_format=2), "dk_format"), (dict(dk_format=4), "dk_format"),
                          (dict(dk_format=1, dtype="f64"), "DAO_F32"), (dict(dk_format=1, master=1), "aperture"),
                          (dict(d_format=1, dtype="f64"), "DAO_F32"), (dict(d_format=2, master=1), "aperture"),
-                         (dict(product_tune=2), "product_tune"), (dict(dose_variant=7), "dose_variant"),
+                         (dict(product_tune=2), "product_tune"), (dict(dose_variant=9), "dose_variant"),
                          (dict(dose_variant=2, d_format=1), "native"), (dict(gradient_depth=6), "gradient_depth")]:
         msg = _expect(dao.DAO_EINVAL, _a=_args(ph), _opts=opts)
         assert needle in msg, (opts, msg)

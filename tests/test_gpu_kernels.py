@@ -162,7 +162,7 @@ def test_price_own_prices_at_zero_dose(contexts, name, dtype):
 # on a grid of 1, 2 or 4 workgroups per compute unit) adds the same terms in
 # the same order: results agree bit for bit with the plain variant, in every
 # value format.
-VARIANTS = [(0, 4), (1, 8), (2, 16), (3, 4), (4, 8), (5, 4), (6, 16)]
+VARIANTS = [(0, 4), (1, 8), (2, 16), (3, 4), (4, 8), (5, 4), (6, 16), (7, 8), (8, 16)]
 
 
 @pytest.mark.parametrize("name,dtype,fmt", [("tiny", "f64", 0), ("prostate", "f32", 0), ("prostate", "f32", 1),
@@ -200,7 +200,7 @@ def test_tuned_variant_reported():
     ctx = ctx_for(ph, dtype="f32")
     try:
         inf = ctx.info()
-        assert 0 <= inf["dose_variant"] <= 6 and inf["gradient_depth"] in (4, 8, 16)
+        assert 0 <= inf["dose_variant"] <= 8 and inf["gradient_depth"] in (4, 8, 16)
     finally:
         ctx.close()
 

@@ -7,7 +7,8 @@ checks it against the CSR input (forward sliced-ELL entries in order with
 zero padding, transposed entries, row permutation, objective classes, MLC
 geometry), feeds malformed inputs to the validator, checks the encoders'
 rounding, and checks that the persistent master's dealing of row batches to
-workgroups (dao_common.h) is a bijection within the LDS sizing.  A sanitizer
+workgroups (dao_common.h) is a bijection within the LDS sizing, and that the
+forward product's balanced slice lists hold every slice once.  A sanitizer
 report or a failed check ends the run non-zero.
 """
 import os
