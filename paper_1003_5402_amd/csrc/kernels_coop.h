@@ -3,7 +3,8 @@
 // One cooperative launch runs a whole master solve (Section 2.3's gradient
 // projection, same step rule and line search as the per-phase kernels of
 // kernels_ap.h).  The grid is co-resident (cooperative launch), each
-// workgroup owns a fixed contiguous range of voxel rows for the whole solve,
+// workgroup owns a fixed set of voxel-row batches for the whole solve (a
+// contiguous range with D_K on chip, batches dealt with a skew otherwise),
 // so the per-voxel vectors d and q are only ever touched by their owner and
 // need no cross-workgroup coherence.  The only data that crosses
 // workgroups are the small reduction records (objective, grad_y, line-search
